@@ -1,0 +1,207 @@
+"""Benchmark: ORAS-preconditioned GMRES solves of the 3D Helmholtz equation on
+one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config mid|tiny]
+
+A step is one full solve (right-preconditioned GMRES to 1e-6 true relative
+residual, complex128) of the workload's point-source right-hand side, with
+the operator, the factored two-level preconditioner and the right-hand side
+already resident in HBM.  Setup (assembly, analysis, factorisation) happens
+before the timed region and is reported separately.  Prints one JSON line.
+
+Workload "mid": 8 x 8 x 2 km synthetic thrust-layered model (12 layers,
+folded and faulted, seed 0), 80 x 80 x 20 hexes cut into 768,000 Kuhn tets,
+P2 (1,062,761 dofs), f = 5 Hz, source at (4000, 4000, 10) m, 8 x 8 x 1 box
+subdomains with 2 overlap layers, two-level ORAS with the nested 40 x 40 x 10
+P1 coarse mesh, GMRES(50).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, iters_per_solve):
+    """Times the CPU oracle (single thread) on a bounded sample of the same
+    workload and scales it to GMRES iterations per second: one of the
+    subdomain factorisations and local solves (scaled by the number of
+    subdomains), the full-size SpMV, the coarse correction and MGS at the
+    mean Krylov dimension of the measured solves."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import coarse as ocoarse
+    from oracle import dd as odd
+    from oracle import fem
+    import scipy.sparse.linalg as spla
+
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        P = fem.Problem(w.xyz, w.tets, w.order, w.c_tet, w.omega)
+        subs = odd.decompose(P, w.part, w.n_sub, w.overlap)
+        mid = w.n_sub // 2 + int(np.sqrt(w.n_sub)) // 2  # an interior subdomain
+        s = subs[mid]
+        lu = spla.splu(odd.local_matrix(P, s).tocsc())
+        rng = np.random.default_rng(0)
+        r = rng.standard_normal(P.n) + 1j * rng.standard_normal(P.n)
+        reps = 3
+        t = time.perf_counter()
+        for _ in range(reps):
+            z = np.zeros(P.n, dtype=np.complex128)
+            z[s.dofs] += s.D * lu.solve(r[s.dofs])
+        t_loc = (time.perf_counter() - t) / reps
+        t = time.perf_counter()
+        for _ in range(reps):
+            y = P.A @ r
+        t_spmv = (time.perf_counter() - t) / reps
+        t_coarse = 0.0
+        if w.coarse_xyz is not None:
+            Z, _ = ocoarse.interpolation(P, w.coarse_xyz, w.coarse_tets)
+            Elu = spla.splu(ocoarse.galerkin(P.A, Z))
+            t = time.perf_counter()
+            for _ in range(reps):
+                q = Z @ Elu.solve(Z.T @ r)
+            t_coarse = (time.perf_counter() - t) / reps + t_spmv  # plus r - A q
+        jbar = max(1, int(round(iters_per_solve / 2)))
+        V = rng.standard_normal((P.n, jbar)) + 0j
+        t = time.perf_counter()
+        wv = y.copy()
+        for i in range(jbar):
+            h = np.vdot(V[:, i], wv)
+            wv = wv - h * V[:, i]
+        t_gs = time.perf_counter() - t
+        per_it = w.n_sub * t_loc + t_spmv + t_coarse + t_gs
+        total = time.perf_counter() - t0
+    return {
+        "value": 1.0 / per_it,
+        "unit": "GMRES iterations/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"oracle single-threaded: 1 of {w.n_sub} subdomain LU solves (x{w.n_sub}), full SpMV, "
+                   f"coarse correction, MGS at j={jbar}; {total:.1f} s of CPU work"),
+        "seconds_per_iteration": per_it,
+        "solves_per_s": 1.0 / (per_it * iters_per_solve),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="mid", choices=["mid", "tiny"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2004_06309_amd import helm
+    from paper_2004_06309_amd import workloads as wl
+
+    w = wl.mid() if args.config == "mid" else wl.tiny()
+    log(f"[bench] workload {w.name}: {w.tets.shape[0]} tets, P{w.order}")
+    t0 = time.perf_counter()
+    h = helm.Helm(0)
+    h.assemble(w.xyz, w.tets, w.order, w.c_tet, w.omega)
+    t_asm = time.perf_counter() - t0
+    h.precond_setup(w.part, w.n_sub, w.overlap, w.coarse_xyz, w.coarse_tets)
+    st = h.stats()
+    log(f"[bench] setup {time.perf_counter() - t0:.1f} s, stats {st}")
+    b = helm.load_vector(h, w)
+    B = torch.from_numpy(b).to("cuda")
+    U = torch.zeros_like(B)
+    stream = torch.cuda.current_stream()
+
+    def one_solve():
+        U.zero_()
+        rc, info = h.solve(B, U, tol=w.tol, restart=w.restart, stream=stream)
+        if rc != helm.HELM_OK:
+            raise RuntimeError(f"solve did not converge: {info}")
+        return info[0]
+
+    for i in range(args.warmup):
+        inf = one_solve()
+        log(f"[bench] warmup {i}: {inf}")
+    torch.cuda.synchronize()
+    h.profile(True)
+    times, its = [], []
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        inf = one_solve()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+        its.append(inf["iterations"])
+        log(f"[bench] step {i}: {inf['iterations']} its, {times[-1] * 1e3:.1f} ms, relres {inf['relres']:.2e}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    prof = h.profile_read()
+    h.profile(False)
+    total_t = float(np.sum(times))
+    total_its = int(np.sum(its))
+    its_per_s = total_its / total_t
+    solves_per_s = len(times) / total_t
+    # dominant kernel by summed time
+    dom = max(("trsv_fwd", "trsv_bwd", "spmv", "gs"), key=lambda k: prof[k]["ms"])
+    pk = prof[dom]
+    avg_ms = pk["ms"] / max(pk["launches"], 1)
+    avg_bytes = pk["bytes"] / max(pk["launches"], 1)
+    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
+    kernels = {k: {"launches": v["launches"], "avg_us": 1e3 * v["ms"] / max(v["launches"], 1),
+                   "share_of_solve": v["ms"] / 1e3 / total_t,
+                   "GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None}
+               for k, v in prof.items()}
+    out = {
+        "metric": "GMRES iterations/s and solves/s at 1e-6 rel. residual (fp32 vs fp64 precond); p50/p99",
+        "value": its_per_s,
+        "unit": "GMRES iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * total_t / len(times),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: 8x8x2 km thrust model, 80x80x20 hex -> Kuhn tets, P2, "
+                               f"{h.n} dofs, f=5 Hz, 64 subdomains overlap 2, two-level ORAS (P1 coarse "
+                               f"{st['n_coarse']} unknowns), GMRES(50), tol 1e-6, 1 RHS"
+                   if w.name == "mid" else f"{w.name}: {h.n} P1 dofs, 8 subdomains, one-level ORAS",
+                   "precond_precision": "fp64 (complex128 factors)", "nrhs": 1},
+        "solves_per_s": solves_per_s,
+        "iterations_per_solve": float(np.mean(its)),
+        "p50_ms": 1e3 * float(np.percentile(times, 50)),
+        "p99_ms": 1e3 * float(np.percentile(times, 99)),
+        "setup_s": st["setup_seconds"] + t_asm,
+        "factor_GB": st["factor_entries"] * 16 / 1e9,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": 1e3 * avg_ms, "avg_bytes_per_launch": avg_bytes},
+        "kernels": kernels,
+        "wall_s_timed": wall,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(w, float(np.mean(its)))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,220 @@
+/*
+ * helm.h -- C-ABI of libhelm: ORAS-preconditioned GMRES for the 3D Helmholtz
+ * equation on one MI355X (gfx950).
+ *
+ * Method (Dolean, Jolivet, Tournier, Operto, "Iterative frequency-domain
+ * seismic wave solvers based on multi-level domain-decomposition
+ * preconditioners"):
+ *   - (Delta + k(x)^2) u = b, k = omega / c(x), c complex in attenuating media,
+ *     homogeneous Dirichlet on the top face (z = min z; z is depth) and
+ *     first-order absorbing conditions on the other boundary faces (eq. eqh);
+ *   - P1/P2 Lagrange finite elements on tetrahedra, A u = b (eq. eq1);
+ *   - right-preconditioned GMRES stopped at ||A x - b|| / ||b|| <= tol
+ *     (Section "Numerical experiments");
+ *   - one-level ORAS  M1^{-1} = sum_i R_i^T D_i A_i^{-1} R_i (eq. oras) with
+ *     impedance local matrices, and the two-level preconditioner
+ *     M^{-1} = M1^{-1}(I - A Q) + Q, Q = Z E^{-1} Z^T, E = Z^T A Z (eq. 2lvl).
+ *
+ * Conventions
+ *   - complex arrays are interleaved (re, im) doubles;
+ *   - time dependence exp(-i omega t): absorbing condition d_n u = i k u and
+ *     the weak form A = -K + M_{k^2} + i B_k;
+ *   - dof numbering: P1 = vertices in input order; P2 = vertices, then edges
+ *     sorted by (min vertex id, max vertex id), the edge dof at its midpoint;
+ *   - Dirichlet dofs are kept as unknowns with identity rows and columns;
+ *   - every call returns an int status, 0 = HELM_OK, negative = error; the
+ *     message of the last error is returned by helm_last_error;
+ *   - the caller owns every buffer it passes; the library keeps no caller
+ *     pointer after a call returns; the library owns all memory it allocates;
+ *   - a context is not thread-safe; distinct contexts may be used from
+ *     distinct threads.
+ */
+#ifndef HELM_H
+#define HELM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HELM_OK = 0,
+  HELM_EINVAL = -1,     /* bad argument, bad mesh, zero-volume tet          */
+  HELM_ESINGULAR = -2,  /* zero pivot in a frontal matrix                   */
+  HELM_ENOCONV = -3,    /* maxit reached; U holds the last iterates         */
+  HELM_ENUMERIC = -4,   /* NaN/Inf met in the iteration                     */
+  HELM_ENOMEM = -5,     /* host or device allocation failed                 */
+  HELM_ESTATE = -6,     /* call made in the wrong order or on a host-only
+                           context                                          */
+  HELM_EDEVICE = -7     /* HIP runtime error                                */
+};
+
+typedef struct helm_ctx helm_ctx;
+
+/* Tetrahedral mesh, host arrays (read during the call only). */
+typedef struct helm_mesh {
+  int64_t n_nodes;
+  const double* xyz;       /* [n_nodes][3], metres, z = depth             */
+  int64_t n_tets;
+  const int64_t* tets;     /* [n_tets][4] vertex ids; any orientation      */
+  int32_t order;           /* 1 (P1) or 2 (P2)                             */
+} helm_mesh;
+
+typedef struct helm_precond_opts {
+  int32_t leaf_size;       /* nested-dissection leaf size, 0 = default     */
+  int32_t reserved[7];
+} helm_precond_opts;
+
+enum {
+  HELM_SOLVE_X0 = 1        /* read U as the initial guess                  */
+};
+
+typedef struct helm_solve_opts {
+  int32_t restart;         /* GMRES(m) restart length, 0 = 50              */
+  int32_t maxit;           /* total Arnoldi steps per RHS, 0 = 1000        */
+  int32_t flags;           /* HELM_SOLVE_*                                 */
+  int32_t reserved;
+} helm_solve_opts;
+
+typedef struct helm_solve_info {
+  int32_t iterations;      /* Arnoldi steps over all restarts              */
+  int32_t converged;       /* 1 if the true relative residual <= tol       */
+  double relres;           /* true ||b - A u|| / ||b|| at exit            */
+  double seconds;          /* wall time of this RHS (device-synchronised)  */
+} helm_solve_info;
+
+typedef struct helm_precond_stats {
+  int32_t n_sub;           /* subdomains                                   */
+  int32_t n_coarse;        /* coarse unknowns (0 = one-level)              */
+  int64_t n_local_total;   /* sum of local sizes n_i                       */
+  int64_t factor_entries;  /* stored fine-level factor entries (L + U)     */
+  int64_t coarse_entries;  /* stored coarse factor entries                 */
+  int32_t levels_fwd;      /* batched forward-solve launches               */
+  int32_t levels_bwd;      /* batched backward-solve launches              */
+  int32_t max_front;       /* largest frontal matrix order                 */
+  int32_t n_supernodes;    /* fine-level supernodes                        */
+  double setup_seconds;    /* wall time of the last helm_precond_setup     */
+  double factor_flops;     /* complex multiply-adds x 8 in the factorisation */
+} helm_precond_stats;
+
+/* Create a context on HIP device `device_ordinal`; -1 creates a host-only
+ * context that can assemble and analyse but not solve (used to inspect the
+ * setup without a GPU).  *out is NULL on failure. */
+int helm_create(helm_ctx** out, int device_ordinal);
+
+/* Free every host and device resource of the context; NULL is accepted. */
+void helm_destroy(helm_ctx* ctx);
+
+/* Message of the last failing call on ctx (or of helm_create when ctx is
+ * NULL); never NULL, owned by the library. */
+const char* helm_last_error(const helm_ctx* ctx);
+
+/* Assemble A of eq. eq1 for mesh, complex velocity c_tet (interleaved
+ * c128[n_tets], constant per tet) and angular frequency omega (rad/s).
+ * Tets are re-oriented if needed; a degenerate tet gives HELM_EINVAL.
+ * Invalidates any earlier preconditioner. */
+int helm_assemble(helm_ctx* ctx, const helm_mesh* mesh, const double* c_tet, double omega);
+
+/* Number of global dofs n (after helm_assemble). */
+int helm_ndof(const helm_ctx* ctx, int64_t* n);
+
+/* Dof coordinates, caller-allocated host f64[n][3]. */
+int helm_dof_coords(const helm_ctx* ctx, double* xyz);
+
+/* Load of a point source b = delta(x - xs): F_i = phi_i(xs), zero on
+ * Dirichlet dofs.  b is a caller-allocated host c128[n]. */
+int helm_point_source(const helm_ctx* ctx, const double* xs, double* b);
+
+/* Number of stored entries of A (CSR, after Dirichlet elimination). */
+int helm_matrix_nnz(const helm_ctx* ctx, int64_t* nnz);
+
+/* Copy A to caller-allocated host CSR arrays: rowptr i64[n+1],
+ * col i32[nnz] (ascending per row), val c128[nnz]. */
+int helm_matrix_csr(const helm_ctx* ctx, int64_t* rowptr, int32_t* col, double* val);
+
+/* Build the preconditioner (eqs. oras and 2lvl): tet_part[n_tets] holds the
+ * non-overlapping subdomain id (0..n_sub-1) of every tet, overlap the number
+ * of element layers added by vertex adjacency, coarse the P1 coarse mesh
+ * (NULL = one-level ORAS; its order field is ignored).  Local matrices carry
+ * the impedance condition on artificial faces, the partition of unity is
+ * chi_i = max(0, 1 - l/overlap) normalised, local solves are LU factors
+ * (nested-dissection multifrontal, partial pivoting inside each front) and
+ * the coarse matrix E = Z^T A Z is factored the same way.  On a host-only
+ * context the numeric factorisation is skipped. */
+int helm_precond_setup(helm_ctx* ctx, const int32_t* tet_part, int32_t n_sub, int32_t overlap,
+                       const helm_mesh* coarse, const helm_precond_opts* opts);
+
+int helm_precond_stats_get(const helm_ctx* ctx, helm_precond_stats* stats);
+
+/* Subdomain i after setup: local size, then (when the pointers are not
+ * NULL) its global dofs (i64[n_i], ascending), partition-of-unity weights
+ * (f64[n_i]) and local matrix in CSR over local indices
+ * (rowptr i64[n_i+1], col i32[nnz_i], val c128[nnz_i]).  Pass col == NULL
+ * to read only nnz_i from rowptr[n_i]. */
+int helm_subdomain_size(const helm_ctx* ctx, int32_t i, int64_t* n_i, int64_t* nnz_i);
+int helm_subdomain_get(const helm_ctx* ctx, int32_t i, int64_t* dofs, double* D,
+                       int64_t* rowptr, int32_t* col, double* val);
+
+/* Coarse interpolation Z (real CSR n x n_c: rowptr i64[n+1], col i32, val f64)
+ * after a two-level setup. */
+int helm_coarse_nnz(const helm_ctx* ctx, int64_t* n_c, int64_t* nnz);
+int helm_coarse_get(const helm_ctx* ctx, int64_t* rowptr, int32_t* col, double* val);
+
+/* --- Device operations (device pointers to c128[n]; stream = hipStream_t or
+ *     NULL for the null stream).  Asynchronous with respect to the host. --- */
+
+/* y = A x  (complex CSR SpMV). */
+int helm_apply_A(helm_ctx* ctx, const void* x, void* y, void* stream);
+
+/* z = M^{-1} r (two-level when a coarse mesh was given, else one-level). */
+int helm_apply_precond(helm_ctx* ctx, const void* r, void* z, void* stream);
+
+/* z = M1^{-1} r, the one-level ORAS part only. */
+int helm_apply_oras(helm_ctx* ctx, const void* r, void* z, void* stream);
+
+/* q = Z E^{-1} Z^T r (two-level setup only). */
+int helm_apply_coarse(helm_ctx* ctx, const void* r, void* q, void* stream);
+
+/* Solve A U = B for nrhs right-hand sides with right-preconditioned GMRES.
+ * B and U are device arrays c128, column-major n x nrhs; U is read as the
+ * initial guess iff opts->flags has HELM_SOLVE_X0.  info (host, nrhs
+ * entries, may be NULL) receives per-RHS results.  Returns HELM_OK when
+ * every RHS reached the true relative residual tol, HELM_ENOCONV when some
+ * did not (U then holds the last iterates).  ||b|| = 0 gives U = 0 in 0
+ * iterations.  The call returns after the work on `stream` is complete. */
+int helm_solve(helm_ctx* ctx, int32_t nrhs, const void* B, double tol, const helm_solve_opts* opts,
+               void* U, void* stream, helm_solve_info* info);
+
+/* --- Kernel timing (HIP events around every launch of the per-iteration
+ *     kernels, on the stream they run on).  Algorithmic bytes count each
+ *     stored factor entry (16 B), matrix entry (20 B) and vector entry the
+ *     kernel must touch once. --- */
+
+enum {
+  HELM_K_TRSV_FWD = 0,    /* batched forward level solves, fine subdomains  */
+  HELM_K_TRSV_BWD = 1,    /* batched backward level solves, fine subdomains */
+  HELM_K_SPMV = 2,        /* A x and r - A x                               */
+  HELM_K_COARSE = 3,      /* Z^T r, coarse solves, Z y                      */
+  HELM_K_PROLONG = 4,     /* partition-of-unity prolongation                */
+  HELM_K_GS = 5,          /* CGS2 dots, updates, norm, scaling              */
+  HELM_K_COUNT = 6
+};
+
+typedef struct helm_kernel_profile {
+  int64_t launches;       /* timed launches since the last reset           */
+  double milliseconds;    /* summed event-to-event time                    */
+  double bytes;           /* summed algorithmic bytes                      */
+} helm_kernel_profile;
+
+/* Turn per-launch timing on (1) or off (0); both reset the counters. */
+int helm_profile_enable(helm_ctx* ctx, int on);
+
+/* Copy the HELM_K_COUNT counters (completed work only: call after
+ * helm_solve returned or after synchronising the stream). */
+int helm_profile_read(helm_ctx* ctx, helm_kernel_profile* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HELM_H */

@@ -1,0 +1,149 @@
+// Context of the C-ABI: host setup data and device-resident operators.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <string>
+#include <vector>
+
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace helm {
+
+#define HELM_HIP(call)                                                                              \
+  do {                                                                                              \
+    hipError_t e_ = (call);                                                                         \
+    if (e_ != hipSuccess)                                                                           \
+      ::helm::fail(e_ == hipErrorOutOfMemory ? HELM_ENOMEM : HELM_EDEVICE,                          \
+                   std::string(#call) + ": " + hipGetErrorString(e_));                              \
+  } while (0)
+
+// Owning device array.
+template <class T>
+struct DVec {
+  T* p = nullptr;
+  size_t n = 0;
+  DVec() = default;
+  DVec(const DVec&) = delete;
+  DVec& operator=(const DVec&) = delete;
+  ~DVec() { reset(); }
+  void reset() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    reset();
+    if (count == 0) return;
+    HELM_HIP(hipMalloc((void**)&p, count * sizeof(T)));
+    n = count;
+  }
+  void upload(const T* src, size_t count) {
+    alloc(count);
+    if (count) HELM_HIP(hipMemcpy(p, src, count * sizeof(T), hipMemcpyHostToDevice));
+  }
+  void upload(const std::vector<T>& v) { upload(v.data(), v.size()); }
+};
+
+// Host description of a batch of factored matrices (solve layout).
+struct BatchHost {
+  int64_t npos = 0;                  // total positions (sum of matrix orders)
+  std::vector<int32_t> c0, w, uoff, frow0;
+  std::vector<int64_t> roff;
+  std::vector<int32_t> rows, bidx, fcon_ptr, fcon_idx;
+  std::vector<dev::Tile> tf, tb;
+  std::vector<int64_t> lev_f, lev_b;  // tile ranges per level
+  int64_t nf = 0, nb = 0, nu = 0;     // panel entries (fwd, bwd), update entries
+  int32_t max_front = 0;
+  double flops = 0;
+};
+
+// Device copy of a batch.
+struct BatchDev {
+  DVec<dev::Tile> tf, tb;
+  DVec<int32_t> c0, w, uoff, frow0, rows, bidx, fcon_ptr, fcon_idx;
+  DVec<int64_t> roff;
+  DVec<double> pf, pb, ubuf, y, x;
+  std::vector<int64_t> lev_f, lev_b;
+  int64_t npos = 0;
+  std::vector<double> bytes_f, bytes_b;  // algorithmic bytes per level
+  dev::Batch view() const;
+  void reset() {
+    for (auto* v : {&c0, &w, &uoff, &frow0, &rows, &bidx, &fcon_ptr, &fcon_idx}) v->reset();
+    for (auto* v : {&pf, &pb, &ubuf, &y, &x}) v->reset();
+    tf.reset();
+    tb.reset();
+    roff.reset();
+    lev_f.clear();
+    lev_b.clear();
+    bytes_f.clear();
+    bytes_b.clear();
+    npos = 0;
+  }
+};
+
+// Event pairs around kernel launches; harvested at synchronisation points.
+struct Profiler {
+  bool on = false;
+  helm_kernel_profile acc[HELM_K_COUNT] = {};
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<std::pair<int, double>> pending;  // kernel id, bytes
+  void begin(hipStream_t s);
+  void end(int kid, double bytes, hipStream_t s);
+  void harvest();  // stream must be synchronised
+  void reset();
+  ~Profiler();
+};
+
+struct Ctx {
+  int device = -1;
+  std::string err;
+  bool assembled = false, precond_ready = false;
+  Discretization D;
+  // preconditioner (host)
+  int32_t n_sub = 0, overlap = 0;
+  std::vector<SubdomainHost> subs;
+  std::vector<Symbolic> sym;
+  bool two_level = false;
+  CsrReal Z, ZT;
+  Csr E;
+  Symbolic Esym;
+  helm_precond_stats stats{};
+  // device operators
+  DVec<int64_t> A_ptr;
+  DVec<int32_t> A_col;
+  DVec<double> A_val;
+  BatchDev fine, coarse;
+  DVec<int64_t> pro_ptr;   // prolongation: global dof -> (position, weight)
+  DVec<int32_t> pro_idx;
+  DVec<double> pro_w;
+  DVec<int64_t> Zp_ptr, ZT_ptr;
+  DVec<int32_t> Zp_col, ZT_col;
+  DVec<double> Zp_val, ZT_val;
+  // work vectors
+  DVec<double> t, q, cvec;
+  // GMRES work
+  int gm_m = 0;
+  DVec<double> V, Zk, w, partial, hcol, htmp, nrm, ydev;
+  double* h_host = nullptr;  // pinned
+  Profiler prof;
+  ~Ctx();
+  void free_precond();
+};
+
+// solver.cpp
+void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<const std::vector<int64_t>*>& in_idx,
+                  const std::vector<NumericOut>& num, BatchHost& B);
+void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overlap, const helm_mesh* coarse,
+                   const helm_precond_opts* opts);
+void upload_matrix(Ctx& c);
+void apply_A(Ctx& c, const double* x, double* y, hipStream_t s);
+void apply_oras(Ctx& c, const double* r, double* z, const double* q, hipStream_t s);
+void apply_coarse(Ctx& c, const double* r, double* q, hipStream_t s);
+void apply_precond(Ctx& c, const double* r, double* z, hipStream_t s);
+int solve(Ctx& c, int32_t nrhs, const double* B, double tol, const helm_solve_opts* opts, double* U, hipStream_t s,
+          helm_solve_info* info);
+
+}  // namespace helm

@@ -1,0 +1,467 @@
+// HIP kernels of the per-iteration path (gfx950, 64-wide wavefronts).
+//
+//  - fwd_level / bwd_level: one level of the batched supernodal forward and
+//    backward solves of all subdomains at once (local solves of eq. oras).
+//    One workgroup (4 waves) per tile of <= 64 panel rows; each lane owns a
+//    row, the four waves split the input columns, the input vector (gathered
+//    through index lists, restriction fused in) sits in LDS, and the panel is
+//    streamed column by column (64 rows x 16 B = 1 KiB coalesced per wave).
+//  - spmv / spmv_real: CSR products, a group of lanes per row.
+//  - prolong: partition-of-unity weighted sum of the local solutions.
+//  - Gram-Schmidt reductions: per-block partial sums reduced in a fixed order
+//    (no atomics), so every result is bitwise repeatable.
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+
+namespace helm {
+namespace dev {
+
+namespace {
+
+constexpr int kWG = 256;
+constexpr int kChunk = 2048;  // input columns staged in LDS per pass
+
+__device__ __forceinline__ void cfma(double& ar, double& ai, double2 a, double2 v) {
+  ar = fma(a.x, v.x, ar);
+  ar = fma(-a.y, v.y, ar);
+  ai = fma(a.x, v.y, ai);
+  ai = fma(a.y, v.x, ai);
+}
+
+// Streams columns [k0, k1) of a tile (column-major, ld = nr) against vin.
+__device__ __forceinline__ void tile_dot(const double2* __restrict__ p, int nr, const double2* vin, int k0, int k1,
+                                        double& ar, double& ai) {
+  int k = k0;
+  double br = 0, bi = 0;
+  for (; k + 4 <= k1; k += 4) {
+    double2 a0 = p[(int64_t)(k + 0) * nr];
+    double2 a1 = p[(int64_t)(k + 1) * nr];
+    double2 a2 = p[(int64_t)(k + 2) * nr];
+    double2 a3 = p[(int64_t)(k + 3) * nr];
+    cfma(ar, ai, a0, vin[k + 0]);
+    cfma(br, bi, a1, vin[k + 1]);
+    cfma(ar, ai, a2, vin[k + 2]);
+    cfma(br, bi, a3, vin[k + 3]);
+  }
+  for (; k < k1; ++k) cfma(ar, ai, p[(int64_t)k * nr], vin[k]);
+  ar += br;
+  ai += bi;
+}
+
+__global__ __launch_bounds__(kWG) void fwd_level_kernel(const Tile* __restrict__ tiles, Batch b,
+                                                        const double2* __restrict__ bin) {
+  __shared__ double2 vin[kChunk];
+  __shared__ double2 red[4][64];
+  const Tile t = tiles[blockIdx.x];
+  const int s = t.sn;
+  const int c0 = b.sn_c0[s], w = b.sn_w[s], frow0 = b.sn_frow0[s];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double2* __restrict__ P = reinterpret_cast<const double2*>(b.pf) + t.off + lane;
+  const double2* __restrict__ ub = reinterpret_cast<const double2*>(b.ubuf);
+  double ar = 0, ai = 0;
+  for (int cb = 0; cb < t.ncols; cb += kChunk) {
+    const int cn = min(kChunk, t.ncols - cb);
+    for (int k = threadIdx.x; k < cn; k += kWG) {
+      const int kk = cb + k;
+      double2 v = bin[b.bidx[c0 + kk]];
+      const int fr = frow0 + kk;
+      for (int e = b.fcon_ptr[fr]; e < b.fcon_ptr[fr + 1]; ++e) {
+        double2 u = ub[b.fcon_idx[e]];
+        v.x -= u.x;
+        v.y -= u.y;
+      }
+      vin[k] = v;
+    }
+    __syncthreads();
+    const int per = (cn + 3) >> 2;
+    const int k0 = wv * per, k1 = min(cn, k0 + per);
+    if (lane < t.nrows) tile_dot(P + (int64_t)cb * t.nrows, t.nrows, vin, k0, k1, ar, ai);
+    __syncthreads();
+  }
+  red[wv][lane] = make_double2(ar, ai);
+  __syncthreads();
+  if (wv == 0 && lane < t.nrows) {
+    double rr = red[0][lane].x + red[1][lane].x + red[2][lane].x + red[3][lane].x;
+    double ii = red[0][lane].y + red[1][lane].y + red[2][lane].y + red[3][lane].y;
+    const int row = t.row0 + lane;
+    if (row < w) {
+      reinterpret_cast<double2*>(b.y)[c0 + row] = make_double2(rr, ii);
+    } else {
+      const int fr = frow0 + row;
+      for (int e = b.fcon_ptr[fr]; e < b.fcon_ptr[fr + 1]; ++e) {
+        double2 u = ub[b.fcon_idx[e]];
+        rr += u.x;
+        ii += u.y;
+      }
+      reinterpret_cast<double2*>(b.ubuf)[b.sn_uoff[s] + row - w] = make_double2(rr, ii);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kWG) void bwd_level_kernel(const Tile* __restrict__ tiles, Batch b) {
+  __shared__ double2 vin[kChunk];
+  __shared__ double2 red[4][64];
+  const Tile t = tiles[blockIdx.x];
+  const int s = t.sn;
+  const int c0 = b.sn_c0[s], w = b.sn_w[s];
+  const int64_t roff = b.sn_roff[s];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double2* __restrict__ P = reinterpret_cast<const double2*>(b.pb) + t.off + lane;
+  const double2* __restrict__ yv = reinterpret_cast<const double2*>(b.y);
+  const double2* xv = reinterpret_cast<const double2*>(b.x);
+  double ar = 0, ai = 0;
+  for (int cb = 0; cb < t.ncols; cb += kChunk) {
+    const int cn = min(kChunk, t.ncols - cb);
+    for (int k = threadIdx.x; k < cn; k += kWG) {
+      const int c = t.col0 + cb + k;
+      vin[k] = c < w ? yv[c0 + c] : xv[b.rows[roff + (c - w)]];
+    }
+    __syncthreads();
+    const int per = (cn + 3) >> 2;
+    const int k0 = wv * per, k1 = min(cn, k0 + per);
+    if (lane < t.nrows) tile_dot(P + (int64_t)cb * t.nrows, t.nrows, vin, k0, k1, ar, ai);
+    __syncthreads();
+  }
+  red[wv][lane] = make_double2(ar, ai);
+  __syncthreads();
+  if (wv == 0 && lane < t.nrows) {
+    double rr = red[0][lane].x + red[1][lane].x + red[2][lane].x + red[3][lane].x;
+    double ii = red[0][lane].y + red[1][lane].y + red[2][lane].y + red[3][lane].y;
+    reinterpret_cast<double2*>(b.x)[c0 + t.row0 + lane] = make_double2(rr, ii);
+  }
+}
+
+template <int G>
+__global__ __launch_bounds__(kWG) void spmv_kernel(int64_t n, const int64_t* __restrict__ ptr,
+                                                   const int32_t* __restrict__ col, const double2* __restrict__ val,
+                                                   const double2* __restrict__ x, const double2* __restrict__ bvec,
+                                                   double2* __restrict__ y) {
+  const int64_t row = ((int64_t)blockIdx.x * kWG + threadIdx.x) / G;
+  const int l = threadIdx.x % G;
+  double ar = 0, ai = 0;
+  if (row < n) {
+    const int64_t p1 = ptr[row + 1];
+    for (int64_t p = ptr[row] + l; p < p1; p += G) cfma(ar, ai, val[p], x[col[p]]);
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    ar += __shfl_xor(ar, o, G);
+    ai += __shfl_xor(ai, o, G);
+  }
+  if (row < n && l == 0) {
+    if (bvec) {
+      double2 bb = bvec[row];
+      y[row] = make_double2(bb.x - ar, bb.y - ai);
+    } else {
+      y[row] = make_double2(ar, ai);
+    }
+  }
+}
+
+template <int G>
+__global__ __launch_bounds__(kWG) void spmv_real_kernel(int64_t n, const int64_t* __restrict__ ptr,
+                                                        const int32_t* __restrict__ col,
+                                                        const double* __restrict__ val,
+                                                        const double2* __restrict__ x, double2* __restrict__ y) {
+  const int64_t row = ((int64_t)blockIdx.x * kWG + threadIdx.x) / G;
+  const int l = threadIdx.x % G;
+  double ar = 0, ai = 0;
+  if (row < n) {
+    const int64_t p1 = ptr[row + 1];
+    for (int64_t p = ptr[row] + l; p < p1; p += G) {
+      double a = val[p];
+      double2 v = x[col[p]];
+      ar = fma(a, v.x, ar);
+      ai = fma(a, v.y, ai);
+    }
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    ar += __shfl_xor(ar, o, G);
+    ai += __shfl_xor(ai, o, G);
+  }
+  if (row < n && l == 0) y[row] = make_double2(ar, ai);
+}
+
+__global__ __launch_bounds__(kWG) void prolong_kernel(int64_t n, const int64_t* __restrict__ ptr,
+                                                      const int32_t* __restrict__ idx, const double* __restrict__ w,
+                                                      const double2* __restrict__ xl, const double2* __restrict__ q,
+                                                      double2* __restrict__ z) {
+  const int64_t g = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (g >= n) return;
+  double ar = 0, ai = 0;
+  if (q) {
+    ar = q[g].x;
+    ai = q[g].y;
+  }
+  for (int64_t p = ptr[g]; p < ptr[g + 1]; ++p) {
+    double2 v = xl[idx[p]];
+    double c = w[p];
+    ar = fma(c, v.x, ar);
+    ai = fma(c, v.y, ai);
+  }
+  z[g] = make_double2(ar, ai);
+}
+
+// ---- Gram-Schmidt ----------------------------------------------------------
+
+constexpr int kGsCols = 8;
+
+__global__ __launch_bounds__(kWG) void gs_dots_partial_kernel(int64_t n, const double2* __restrict__ V, int64_t ld,
+                                                              int ncol, const double2* __restrict__ w,
+                                                              double2* __restrict__ partial) {
+  __shared__ double2 sm[kGsCols][kWG];
+  const int tid = threadIdx.x;
+  for (int k0 = 0; k0 < ncol; k0 += kGsCols) {
+    const int kc = min(kGsCols, ncol - k0);
+    double ar[kGsCols], ai[kGsCols];
+#pragma unroll
+    for (int c = 0; c < kGsCols; ++c) ar[c] = ai[c] = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kWG + tid; i < n; i += (int64_t)gridDim.x * kWG) {
+      const double2 wi = w[i];
+#pragma unroll
+      for (int c = 0; c < kGsCols; ++c)
+        if (c < kc) {
+          const double2 v = V[(int64_t)(k0 + c) * ld + i];
+          // conj(v) * wi
+          ar[c] = fma(v.x, wi.x, ar[c]);
+          ar[c] = fma(v.y, wi.y, ar[c]);
+          ai[c] = fma(v.x, wi.y, ai[c]);
+          ai[c] = fma(-v.y, wi.x, ai[c]);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kGsCols; ++c) sm[c][tid] = make_double2(ar[c], ai[c]);
+    __syncthreads();
+    for (int st = kWG / 2; st > 0; st >>= 1) {
+      if (tid < st)
+        for (int c = 0; c < kc; ++c) {
+          sm[c][tid].x += sm[c][tid + st].x;
+          sm[c][tid].y += sm[c][tid + st].y;
+        }
+      __syncthreads();
+    }
+    if (tid < kc) partial[(int64_t)blockIdx.x * ncol + k0 + tid] = sm[tid][0];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kWG) void gs_dots_final_kernel(const double2* __restrict__ partial, int nblk, int ncol,
+                                                            double2* __restrict__ h, double2* __restrict__ hacc,
+                                                            int accumulate) {
+  __shared__ double2 sm[kWG];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  double ar = 0, ai = 0;
+  for (int b = tid; b < nblk; b += kWG) {
+    double2 v = partial[(int64_t)b * ncol + k];
+    ar += v.x;
+    ai += v.y;
+  }
+  sm[tid] = make_double2(ar, ai);
+  __syncthreads();
+  for (int st = kWG / 2; st > 0; st >>= 1) {
+    if (tid < st) {
+      sm[tid].x += sm[tid + st].x;
+      sm[tid].y += sm[tid + st].y;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    h[k] = sm[0];
+    if (hacc) {
+      if (accumulate)
+        hacc[k] = make_double2(hacc[k].x + sm[0].x, hacc[k].y + sm[0].y);
+      else
+        hacc[k] = sm[0];
+    }
+  }
+}
+
+__global__ __launch_bounds__(kWG) void gs_update_kernel(int64_t n, const double2* __restrict__ V, int64_t ld, int ncol,
+                                                        const double2* __restrict__ h, double2* __restrict__ w) {
+  __shared__ double2 hs[1024];
+  for (int k = threadIdx.x; k < ncol; k += kWG) hs[k] = h[k];
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG) {
+    double ar = 0, ai = 0;
+    for (int k = 0; k < ncol; ++k) cfma(ar, ai, V[(int64_t)k * ld + i], hs[k]);
+    double2 wi = w[i];
+    w[i] = make_double2(wi.x - ar, wi.y - ai);
+  }
+}
+
+__global__ __launch_bounds__(kWG) void norm_partial_kernel(int64_t n, const double2* __restrict__ w,
+                                                           double* __restrict__ partial) {
+  __shared__ double sm[kWG];
+  double s = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG) {
+    double2 v = w[i];
+    s = fma(v.x, v.x, s);
+    s = fma(v.y, v.y, s);
+  }
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = kWG / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sm[threadIdx.x] += sm[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sm[0];
+}
+
+__global__ __launch_bounds__(kWG) void norm_final_kernel(const double* __restrict__ partial, int nblk,
+                                                         double2* __restrict__ out) {
+  __shared__ double sm[kWG];
+  double s = 0;
+  for (int b = threadIdx.x; b < nblk; b += kWG) s += partial[b];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = kWG / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sm[threadIdx.x] += sm[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = make_double2(sqrt(sm[0]), 0.0);
+}
+
+__global__ __launch_bounds__(kWG) void scale_by_inv_kernel(int64_t n, const double2* __restrict__ w,
+                                                           const double2* __restrict__ nrm, double2* __restrict__ v) {
+  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (i >= n) return;
+  const double d = nrm[0].x;
+  const double inv = d != 0.0 ? 1.0 / d : 0.0;
+  const double2 a = w[i];
+  v[i] = make_double2(a.x * inv, a.y * inv);
+}
+
+__global__ __launch_bounds__(kWG) void scale_kernel(int64_t n, const double2* __restrict__ w, double alpha,
+                                                    double2* __restrict__ v) {
+  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (i >= n) return;
+  const double2 a = w[i];
+  v[i] = make_double2(a.x * alpha, a.y * alpha);
+}
+
+__global__ __launch_bounds__(kWG) void gemv_acc_kernel(int64_t n, const double2* __restrict__ Z, int64_t ld, int k,
+                                                       const double2* __restrict__ y, double2* __restrict__ x) {
+  __shared__ double2 ys[1024];
+  for (int j = threadIdx.x; j < k; j += kWG) ys[j] = y[j];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (i >= n) return;
+  double ar = 0, ai = 0;
+  for (int j = 0; j < k; ++j) cfma(ar, ai, Z[(int64_t)j * ld + i], ys[j]);
+  double2 xi = x[i];
+  x[i] = make_double2(xi.x + ar, xi.y + ai);
+}
+
+__global__ __launch_bounds__(kWG) void fill_zero_kernel(int64_t n, double* __restrict__ p) {
+  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+__global__ __launch_bounds__(kWG) void copy_kernel(int64_t n, const double* __restrict__ a, double* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+inline unsigned blocks_for(int64_t n, int per = kWG) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+void fwd_level(const Batch& b, int64_t tile0, int64_t ntiles, const double* bin, hipStream_t s) {
+  if (ntiles <= 0) return;
+  fwd_level_kernel<<<(unsigned)ntiles, kWG, 0, s>>>(b.tf + tile0, b, reinterpret_cast<const double2*>(bin));
+}
+
+void bwd_level(const Batch& b, int64_t tile0, int64_t ntiles, hipStream_t s) {
+  if (ntiles <= 0) return;
+  bwd_level_kernel<<<(unsigned)ntiles, kWG, 0, s>>>(b.tb + tile0, b);
+}
+
+void spmv(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const double* x, const double* b,
+          double* y, hipStream_t s) {
+  if (n <= 0) return;
+  constexpr int G = 8;
+  spmv_kernel<G><<<blocks_for(n * G), kWG, 0, s>>>(n, ptr, col, reinterpret_cast<const double2*>(val),
+                                                    reinterpret_cast<const double2*>(x),
+                                                    reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(y));
+}
+
+void spmv_real(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const double* x, double* y,
+               hipStream_t s) {
+  if (n <= 0) return;
+  constexpr int G = 4;
+  spmv_real_kernel<G><<<blocks_for(n * G), kWG, 0, s>>>(n, ptr, col, val, reinterpret_cast<const double2*>(x),
+                                                         reinterpret_cast<double2*>(y));
+}
+
+void prolong(int64_t n, const int64_t* ptr, const int32_t* idx, const double* w, const double* xl, const double* q,
+             double* z, hipStream_t s) {
+  if (n <= 0) return;
+  prolong_kernel<<<blocks_for(n), kWG, 0, s>>>(n, ptr, idx, w, reinterpret_cast<const double2*>(xl),
+                                               reinterpret_cast<const double2*>(q), reinterpret_cast<double2*>(z));
+}
+
+int gs_blocks(int64_t n) {
+  int64_t b = (n + kWG * 4 - 1) / (kWG * 4);
+  if (b < 1) b = 1;
+  if (b > 2048) b = 2048;
+  return (int)b;
+}
+
+void gs_dots_partial(int64_t n, const double* V, int64_t ld, int ncol, const double* w, double* partial, int nblk,
+                     hipStream_t s) {
+  gs_dots_partial_kernel<<<(unsigned)nblk, kWG, 0, s>>>(n, reinterpret_cast<const double2*>(V), ld, ncol,
+                                                         reinterpret_cast<const double2*>(w),
+                                                         reinterpret_cast<double2*>(partial));
+}
+
+void gs_dots_final(const double* partial, int nblk, int ncol, double* h, double* hacc, int accumulate,
+                   hipStream_t s) {
+  gs_dots_final_kernel<<<(unsigned)ncol, kWG, 0, s>>>(reinterpret_cast<const double2*>(partial), nblk, ncol,
+                                                       reinterpret_cast<double2*>(h),
+                                                       reinterpret_cast<double2*>(hacc), accumulate);
+}
+
+void gs_update(int64_t n, const double* V, int64_t ld, int ncol, const double* h, double* w, hipStream_t s) {
+  gs_update_kernel<<<(unsigned)gs_blocks(n), kWG, 0, s>>>(n, reinterpret_cast<const double2*>(V), ld, ncol,
+                                                           reinterpret_cast<const double2*>(h),
+                                                           reinterpret_cast<double2*>(w));
+}
+
+void norm2(int64_t n, const double* w, double* partial, int nblk, double* out, hipStream_t s) {
+  norm_partial_kernel<<<(unsigned)nblk, kWG, 0, s>>>(n, reinterpret_cast<const double2*>(w), partial);
+  norm_final_kernel<<<1, kWG, 0, s>>>(partial, nblk, reinterpret_cast<double2*>(out));
+}
+
+void scale_by_inv(int64_t n, const double* w, const double* nrm, double* v, hipStream_t s) {
+  if (n <= 0) return;
+  scale_by_inv_kernel<<<blocks_for(n), kWG, 0, s>>>(n, reinterpret_cast<const double2*>(w),
+                                                    reinterpret_cast<const double2*>(nrm),
+                                                    reinterpret_cast<double2*>(v));
+}
+
+void scale(int64_t n, const double* w, double alpha, double* v, hipStream_t s) {
+  if (n <= 0) return;
+  scale_kernel<<<blocks_for(n), kWG, 0, s>>>(n, reinterpret_cast<const double2*>(w), alpha,
+                                             reinterpret_cast<double2*>(v));
+}
+
+void gemv_acc(int64_t n, const double* Z, int64_t ld, int k, const double* y, double* x, hipStream_t s) {
+  if (n <= 0 || k <= 0) return;
+  gemv_acc_kernel<<<blocks_for(n), kWG, 0, s>>>(n, reinterpret_cast<const double2*>(Z), ld, k,
+                                                reinterpret_cast<const double2*>(y), reinterpret_cast<double2*>(x));
+}
+
+void fill_zero(int64_t n, double* p, hipStream_t s) {
+  if (n <= 0) return;
+  fill_zero_kernel<<<blocks_for(n), kWG, 0, s>>>(n, p);
+}
+
+void copy(int64_t n, const double* src, double* dst, hipStream_t s) {
+  if (n <= 0) return;
+  copy_kernel<<<blocks_for(n), kWG, 0, s>>>(n, src, dst);
+}
+
+}  // namespace dev
+}  // namespace helm

@@ -1,0 +1,74 @@
+// Launchers of the HIP kernels (device.hip).  Complex vectors are interleaved
+// (re, im) doubles; every launch is asynchronous on the given stream.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+namespace helm {
+namespace dev {
+
+// Mirrors helm::TileDesc.
+struct Tile {
+  int64_t off;
+  int32_t sn, row0, nrows, col0, ncols, pad;
+};
+
+// Device arrays of one batch of factored matrices (all fine subdomains, or
+// the coarse matrix), see factor.cpp for the panel layout.
+struct Batch {
+  const Tile* tf = nullptr;        // forward tiles, grouped by level
+  const Tile* tb = nullptr;        // backward tiles, grouped by level
+  const int32_t* sn_c0 = nullptr;  // first position of the supernode
+  const int32_t* sn_w = nullptr;   // columns
+  const int32_t* sn_uoff = nullptr;  // offset of its update vector in ubuf
+  const int32_t* sn_frow0 = nullptr; // first front row in the fcon index
+  const int64_t* sn_roff = nullptr;  // offset of R_s in rows
+  const int32_t* rows = nullptr;   // R lists (batch positions)
+  const int32_t* bidx = nullptr;   // pivot position -> input-vector index
+  const int32_t* fcon_ptr = nullptr; // front row -> child update entries
+  const int32_t* fcon_idx = nullptr;
+  const double* pf = nullptr;      // forward panels
+  const double* pb = nullptr;      // backward panels
+  double* ubuf = nullptr;          // update vectors
+  double* y = nullptr;             // forward result (pivot order)
+  double* x = nullptr;             // backward result (column order)
+};
+
+void fwd_level(const Batch& b, int64_t tile0, int64_t ntiles, const double* bin, hipStream_t s);
+void bwd_level(const Batch& b, int64_t tile0, int64_t ntiles, hipStream_t s);
+
+// y = A x, or y = b - A x when b != nullptr (complex CSR).
+void spmv(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const double* x, const double* b,
+          double* y, hipStream_t s);
+// y = A x with a real CSR matrix and complex vectors.
+void spmv_real(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const double* x, double* y,
+               hipStream_t s);
+// z[g] = sum_p w[p] xl[idx[p]] over p in [ptr[g], ptr[g+1]) (+ q[g] if q).
+void prolong(int64_t n, const int64_t* ptr, const int32_t* idx, const double* w, const double* xl, const double* q,
+             double* z, hipStream_t s);
+
+// Gram-Schmidt pieces over V (n x ncol, column-major, leading dim ld).
+int gs_blocks(int64_t n);
+// partial[b*ncol + k] = sum over block b's rows of conj(V[i,k]) w[i]
+void gs_dots_partial(int64_t n, const double* V, int64_t ld, int ncol, const double* w, double* partial, int nblk,
+                     hipStream_t s);
+// h[k] = sum_b partial[b*ncol + k]; hacc[k] (+)= h[k] (accumulate != 0 adds)
+void gs_dots_final(const double* partial, int nblk, int ncol, double* h, double* hacc, int accumulate,
+                   hipStream_t s);
+// w -= V h
+void gs_update(int64_t n, const double* V, int64_t ld, int ncol, const double* h, double* w, hipStream_t s);
+// out[0] = ||w||_2 (real, stored as complex with zero imaginary part)
+void norm2(int64_t n, const double* w, double* partial, int nblk, double* out, hipStream_t s);
+// v = w / out[0]  (zeros when out[0] == 0)
+void scale_by_inv(int64_t n, const double* w, const double* nrm, double* v, hipStream_t s);
+// v = alpha * w
+void scale(int64_t n, const double* w, double alpha, double* v, hipStream_t s);
+// x += Z y  (Z n x k column-major, y device)
+void gemv_acc(int64_t n, const double* Z, int64_t ld, int k, const double* y, double* x, hipStream_t s);
+void fill_zero(int64_t n_doubles, double* p, hipStream_t s);
+void copy(int64_t n_doubles, const double* src, double* dst, hipStream_t s);
+
+}  // namespace dev
+}  // namespace helm

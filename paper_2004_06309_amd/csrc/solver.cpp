@@ -1,0 +1,673 @@
+// Preconditioner setup (host analysis + factorisation, device upload), the
+// device applications of A, M1^{-1} (eq. oras) and M^{-1} (eq. 2lvl), and the
+// right-preconditioned restarted GMRES driver (stop at ||b - A x|| <= tol ||b||,
+// Section "Numerical experiments").
+//
+// GMRES keeps the preconditioned vectors z_j = M^{-1} v_j (flexible storage,
+// x = x0 + Z_m y), orthogonalises with classical Gram-Schmidt applied twice
+// (CGS2, Hermitian inner product) and solves the small least-squares problem
+// on the host in double precision with complex Givens rotations
+//   r = sqrt(|a|^2 + |b|^2), c = |a| / r, s = (a / |a|) conj(b) / r.
+// The only host/device transfer per iteration is the new Hessenberg column.
+#include <omp.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "ctx.hpp"
+
+namespace helm {
+
+Ctx::~Ctx() {
+  if (h_host) (void)hipHostFree(h_host);
+}
+
+void Ctx::free_precond() {
+  precond_ready = false;
+  subs.clear();
+  sym.clear();
+  two_level = false;
+  Z = CsrReal();
+  ZT = CsrReal();
+  E = Csr();
+  Esym = Symbolic();
+  stats = helm_precond_stats{};
+  fine.reset();
+  coarse.reset();
+  pro_ptr.reset();
+  pro_idx.reset();
+  pro_w.reset();
+  Zp_ptr.reset();
+  Zp_col.reset();
+  Zp_val.reset();
+  ZT_ptr.reset();
+  ZT_col.reset();
+  ZT_val.reset();
+}
+
+dev::Batch BatchDev::view() const {
+  dev::Batch b;
+  b.tf = tf.p;
+  b.tb = tb.p;
+  b.sn_c0 = c0.p;
+  b.sn_w = w.p;
+  b.sn_uoff = uoff.p;
+  b.sn_frow0 = frow0.p;
+  b.sn_roff = roff.p;
+  b.rows = rows.p;
+  b.bidx = bidx.p;
+  b.fcon_ptr = fcon_ptr.p;
+  b.fcon_idx = fcon_idx.p;
+  b.pf = pf.p;
+  b.pb = pb.p;
+  b.ubuf = ubuf.p;
+  b.y = y.p;
+  b.x = x.p;
+  return b;
+}
+
+void Profiler::begin(hipStream_t s) {
+  if (used + 2 > pool.size()) {
+    size_t old = pool.size();
+    pool.resize(std::max<size_t>(64, 2 * pool.size()));
+    for (size_t i = old; i < pool.size(); ++i) HELM_HIP(hipEventCreate(&pool[i]));
+  }
+  HELM_HIP(hipEventRecord(pool[used], s));
+}
+
+void Profiler::end(int kid, double bytes, hipStream_t s) {
+  HELM_HIP(hipEventRecord(pool[used + 1], s));
+  pending.push_back({kid, bytes});
+  used += 2;
+}
+
+void Profiler::harvest() {
+  for (size_t k = 0; k < pending.size(); ++k) {
+    float ms = 0;
+    HELM_HIP(hipEventSynchronize(pool[2 * k + 1]));
+    HELM_HIP(hipEventElapsedTime(&ms, pool[2 * k], pool[2 * k + 1]));
+    helm_kernel_profile& a = acc[pending[k].first];
+    a.launches += 1;
+    a.milliseconds += ms;
+    a.bytes += pending[k].second;
+  }
+  pending.clear();
+  used = 0;
+}
+
+void Profiler::reset() {
+  pending.clear();
+  used = 0;
+  for (auto& a : acc) a = helm_kernel_profile{};
+}
+
+Profiler::~Profiler() {
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+// Solve layout of a batch of analysed and factored matrices: positions,
+// per-supernode data, input gather (with the pivot order folded in), routing
+// of children's update vectors to the parents' front rows, and the tiles of
+// every forward (by height) and backward (by depth) level.  in_idx[i][l] is
+// the index in the solve's input vector of row l (original order) of matrix i.
+void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<const std::vector<int64_t>*>& in_idx,
+                  const std::vector<NumericOut>& num, BatchHost& B) {
+  const int nm = (int)Ss.size();
+  B = BatchHost();
+  std::vector<int64_t> pos0(nm + 1, 0), sn0(nm + 1, 0), pf0(nm + 1, 0), pb0(nm + 1, 0), u0(nm + 1, 0),
+      fr0(nm + 1, 0);
+  int32_t maxlev_f = 0, maxlev_b = 0;
+  for (int i = 0; i < nm; ++i) {
+    const Symbolic& S = *Ss[i];
+    pos0[i + 1] = pos0[i] + S.n;
+    sn0[i + 1] = sn0[i] + S.nsn;
+    pf0[i + 1] = pf0[i] + S.fwd_entries;
+    pb0[i + 1] = pb0[i] + S.bwd_entries;
+    u0[i + 1] = u0[i] + (int64_t)S.rows.size();
+    int64_t fr = 0;
+    for (int32_t s = 0; s < S.nsn; ++s) fr += S.sn_w[s] + (S.sn_rptr[s + 1] - S.sn_rptr[s]);
+    fr0[i + 1] = fr0[i] + fr;
+    for (int32_t s = 0; s < S.nsn; ++s) {
+      maxlev_f = std::max(maxlev_f, S.height[s]);
+      maxlev_b = std::max(maxlev_b, S.depth[s]);
+    }
+    B.max_front = std::max(B.max_front, S.max_front);
+    B.flops += S.flops;
+  }
+  if (pos0[nm] >= (int64_t)INT32_MAX || u0[nm] >= (int64_t)INT32_MAX || fr0[nm] >= (int64_t)INT32_MAX)
+    fail(HELM_EINVAL, "batch too large for 32-bit solve indices");
+  B.npos = pos0[nm];
+  B.nf = pf0[nm];
+  B.nb = pb0[nm];
+  B.nu = u0[nm];
+  const int64_t nsn = sn0[nm];
+  B.c0.resize(nsn);
+  B.w.resize(nsn);
+  B.uoff.resize(nsn);
+  B.frow0.resize(nsn);
+  B.roff.resize(nsn);
+  B.rows.resize(B.nu);
+  B.bidx.assign(B.npos, 0);
+  std::vector<std::vector<dev::Tile>> lf(maxlev_f + 1), lb(maxlev_b + 1);
+  std::vector<int32_t> fcon_cnt(fr0[nm] + 1, 0);
+  std::vector<std::vector<std::pair<int64_t, int32_t>>> fcon_m(nm);
+  std::vector<TileShape> ts;
+  for (int i = 0; i < nm; ++i) {
+    const Symbolic& S = *Ss[i];
+    const std::vector<int32_t>& piv = num[i].piv;
+    std::vector<int32_t> kinv(S.n);
+    std::vector<int64_t> frl(S.nsn);
+    int64_t fr = 0;
+    for (int32_t s = 0; s < S.nsn; ++s) {
+      const int64_t g = sn0[i] + s;
+      const int32_t c0 = S.sn_c0[s], w = S.sn_w[s];
+      const int32_t r = (int32_t)(S.sn_rptr[s + 1] - S.sn_rptr[s]);
+      B.c0[g] = (int32_t)(pos0[i] + c0);
+      B.w[g] = w;
+      B.uoff[g] = (int32_t)(u0[i] + S.sn_rptr[s]);
+      B.roff[g] = u0[i] + S.sn_rptr[s];
+      frl[s] = fr;
+      B.frow0[g] = (int32_t)(fr0[i] + fr);
+      fr += w + r;
+      for (int32_t a = 0; a < r; ++a) B.rows[u0[i] + S.sn_rptr[s] + a] = (int32_t)(pos0[i] + S.rows[S.sn_rptr[s] + a]);
+      for (int32_t k = 0; k < w; ++k) {
+        const int32_t rho = piv[c0 + k];  // new-order row eliminated at pivot position k
+        kinv[rho] = k;
+        B.bidx[pos0[i] + c0 + k] = (int32_t)(*in_idx[i])[S.perm[rho]];
+      }
+      tiles_fwd(w, r, ts);
+      int64_t off = pf0[i] + S.sn_fwd_off[s];
+      for (auto& t : ts) {
+        lf[S.height[s]].push_back({off, (int32_t)g, t.row0, t.nrows, t.col0, t.ncols, 0});
+        off += (int64_t)t.nrows * t.ncols;
+      }
+      tiles_bwd(w, r, ts);
+      off = pb0[i] + S.sn_bwd_off[s];
+      for (auto& t : ts) {
+        lb[S.depth[s]].push_back({off, (int32_t)g, t.row0, t.nrows, t.col0, t.ncols, 0});
+        off += (int64_t)t.nrows * t.ncols;
+      }
+    }
+    // children's updates routed to the parent's front rows
+    auto& fl = fcon_m[i];
+    for (int32_t c = 0; c < S.nsn; ++c) {
+      const int32_t p = S.sn_parent[c];
+      if (p < 0) continue;
+      const int32_t pc0 = S.sn_c0[p], pw = S.sn_w[p];
+      const int32_t* Rp = S.rows.data() + S.sn_rptr[p];
+      const int32_t rp = (int32_t)(S.sn_rptr[p + 1] - S.sn_rptr[p]);
+      for (int64_t a = S.sn_rptr[c]; a < S.sn_rptr[c + 1]; ++a) {
+        const int32_t row = S.rows[a];
+        int64_t f;
+        if (row >= pc0 && row < pc0 + pw) {
+          f = kinv[row];
+        } else {
+          const int32_t* it = std::lower_bound(Rp, Rp + rp, row);
+          if (it == Rp + rp || *it != row) fail(HELM_EINVAL, "internal: child row missing from parent front");
+          f = pw + (it - Rp);
+        }
+        fl.push_back({fr0[i] + frl[p] + f, (int32_t)(u0[i] + a)});
+      }
+    }
+    std::stable_sort(fl.begin(), fl.end(),
+                     [](const std::pair<int64_t, int32_t>& x, const std::pair<int64_t, int32_t>& y) {
+                       return x.first < y.first;
+                     });
+    for (auto& e : fl) fcon_cnt[e.first + 1]++;
+  }
+  B.fcon_ptr.resize(fr0[nm] + 1);
+  B.fcon_ptr[0] = 0;
+  for (int64_t f = 0; f < fr0[nm]; ++f) B.fcon_ptr[f + 1] = B.fcon_ptr[f] + fcon_cnt[f + 1];
+  B.fcon_idx.resize(B.fcon_ptr[fr0[nm]]);
+  {
+    std::vector<int32_t> fill(B.fcon_ptr.begin(), B.fcon_ptr.end() - 1);
+    for (int i = 0; i < nm; ++i)
+      for (auto& e : fcon_m[i]) B.fcon_idx[fill[e.first]++] = e.second;
+  }
+  B.lev_f.assign(1, 0);
+  for (auto& l : lf) {
+    B.tf.insert(B.tf.end(), l.begin(), l.end());
+    B.lev_f.push_back((int64_t)B.tf.size());
+  }
+  B.lev_b.assign(1, 0);
+  for (auto& l : lb) {
+    B.tb.insert(B.tb.end(), l.begin(), l.end());
+    B.lev_b.push_back((int64_t)B.tb.size());
+  }
+}
+
+namespace {
+
+// Factors a batch (one matrix per thread) and uploads the panels; without a
+// device only the layout is built (pivots taken as the identity).
+void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symbolic*>& Ss,
+                 const std::vector<const std::vector<int64_t>*>& in_idx, int device, bool numeric, BatchHost& B,
+                 BatchDev& Dv, int32_t& n_perturbed) {
+  const int nm = (int)As.size();
+  std::vector<int64_t> pf0(nm + 1, 0), pb0(nm + 1, 0);
+  for (int i = 0; i < nm; ++i) {
+    pf0[i + 1] = pf0[i] + Ss[i]->fwd_entries;
+    pb0[i + 1] = pb0[i] + Ss[i]->bwd_entries;
+  }
+  std::vector<NumericOut> num(nm);
+  if (numeric) {
+    Dv.pf.alloc(2 * (size_t)pf0[nm]);
+    Dv.pb.alloc(2 * (size_t)pb0[nm]);
+    std::string errmsg;
+    int errcode = 0;
+    int32_t npert = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : npert)
+    for (int i = 0; i < nm; ++i) {
+      try {
+        const Symbolic& S = *Ss[i];
+        std::vector<cplx> hf(S.fwd_entries), hb(S.bwd_entries);
+        factor_numeric(*As[i], S, hf.data(), hb.data(), num[i]);
+        npert += num[i].n_perturbed;
+        HELM_HIP(hipSetDevice(device));
+        if (S.fwd_entries)
+          HELM_HIP(hipMemcpy(Dv.pf.p + 2 * pf0[i], hf.data(), sizeof(cplx) * S.fwd_entries, hipMemcpyHostToDevice));
+        if (S.bwd_entries)
+          HELM_HIP(hipMemcpy(Dv.pb.p + 2 * pb0[i], hb.data(), sizeof(cplx) * S.bwd_entries, hipMemcpyHostToDevice));
+      } catch (const Error& e) {
+#pragma omp critical
+        {
+          if (!errcode) {
+            errcode = e.code;
+            errmsg = e.what();
+          }
+        }
+      }
+    }
+    if (errcode) fail(errcode, errmsg);
+    n_perturbed = npert;
+  } else {
+    for (int i = 0; i < nm; ++i) {
+      num[i].piv.resize(Ss[i]->n);
+      std::iota(num[i].piv.begin(), num[i].piv.end(), 0);
+    }
+  }
+  layout_batch(Ss, in_idx, num, B);
+  // algorithmic bytes per level: every panel entry once, plus the vector
+  // entries each supernode gathers and writes
+  {
+    const int64_t nsn = (int64_t)B.c0.size();
+    auto r_of = [&](int64_t s) { return (s + 1 < nsn ? B.roff[s + 1] : B.nu) - B.roff[s]; };
+    auto level_bytes = [&](const std::vector<dev::Tile>& T, const std::vector<int64_t>& lev, bool fwd) {
+      std::vector<double> out;
+      for (size_t l = 0; l + 1 < lev.size(); ++l) {
+        double by = 0;
+        int32_t last = -1;
+        for (int64_t q = lev[l]; q < lev[l + 1]; ++q) {
+          by += 16.0 * T[q].nrows * T[q].ncols;
+          const int32_t s = T[q].sn;
+          if (s == last) continue;
+          last = s;
+          const double w = B.w[s], r = (double)r_of(s);
+          if (fwd) {
+            const double nfc = B.fcon_ptr[B.frow0[s] + (int64_t)(w + r)] - B.fcon_ptr[B.frow0[s]];
+            by += 16.0 * (w + nfc + w + r);
+          } else {
+            by += 16.0 * (w + r + w);
+          }
+        }
+        out.push_back(by);
+      }
+      return out;
+    };
+    Dv.bytes_f = level_bytes(B.tf, B.lev_f, true);
+    Dv.bytes_b = level_bytes(B.tb, B.lev_b, false);
+  }
+  if (!numeric) return;
+  Dv.npos = B.npos;
+  Dv.lev_f = B.lev_f;
+  Dv.lev_b = B.lev_b;
+  Dv.tf.upload(B.tf);
+  Dv.tb.upload(B.tb);
+  Dv.c0.upload(B.c0);
+  Dv.w.upload(B.w);
+  Dv.uoff.upload(B.uoff);
+  Dv.frow0.upload(B.frow0);
+  Dv.roff.upload(B.roff);
+  Dv.rows.upload(B.rows);
+  Dv.bidx.upload(B.bidx);
+  Dv.fcon_ptr.upload(B.fcon_ptr);
+  Dv.fcon_idx.upload(B.fcon_idx);
+  Dv.ubuf.alloc(2 * std::max<int64_t>(B.nu, 1));
+  Dv.y.alloc(2 * std::max<int64_t>(B.npos, 1));
+  Dv.x.alloc(2 * std::max<int64_t>(B.npos, 1));
+}
+
+// Forward then backward level sweeps; with profiling on, every level launch
+// of the fine batch is timed (the coarse batch is timed as a whole).
+void batch_solve(const BatchDev& b, const double* in, hipStream_t s, Profiler* prof, bool fine) {
+  dev::Batch v = b.view();
+  const bool each = prof && prof->on && fine;
+  for (size_t l = 0; l + 1 < b.lev_f.size(); ++l) {
+    if (each) prof->begin(s);
+    dev::fwd_level(v, b.lev_f[l], b.lev_f[l + 1] - b.lev_f[l], in, s);
+    if (each) prof->end(HELM_K_TRSV_FWD, b.bytes_f[l], s);
+  }
+  for (size_t l = 0; l + 1 < b.lev_b.size(); ++l) {
+    if (each) prof->begin(s);
+    dev::bwd_level(v, b.lev_b[l], b.lev_b[l + 1] - b.lev_b[l], s);
+    if (each) prof->end(HELM_K_TRSV_BWD, b.bytes_b[l], s);
+  }
+}
+
+double sum(const std::vector<double>& v) { return std::accumulate(v.begin(), v.end(), 0.0); }
+
+}  // namespace
+
+void upload_matrix(Ctx& c) {
+  c.A_ptr.upload(c.D.A.ptr);
+  c.A_col.upload(c.D.A.col);
+  c.A_val.upload(reinterpret_cast<const double*>(c.D.A.val.data()), 2 * c.D.A.val.size());
+}
+
+void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overlap, const helm_mesh* coarse,
+                   const helm_precond_opts* opts) {
+  auto t0 = std::chrono::steady_clock::now();
+  c.free_precond();
+  const bool on_device = c.device >= 0;
+  const int leaf = opts && opts->leaf_size > 0 ? opts->leaf_size : 64;
+  c.n_sub = n_sub;
+  c.overlap = overlap;
+  build_subdomains(c.D, tet_part, n_sub, overlap, c.subs);
+  c.sym.resize(n_sub);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t i = 0; i < n_sub; ++i) nested_dissection(c.subs[i].A, c.subs[i].coords, leaf, c.sym[i]);
+  helm_precond_stats& st = c.stats;
+  st.n_sub = n_sub;
+  for (auto& S : c.subs) st.n_local_total += (int64_t)S.dofs.size();
+  // fine batch
+  std::vector<const Csr*> As;
+  std::vector<const Symbolic*> Ss;
+  std::vector<const std::vector<int64_t>*> in;
+  for (int32_t i = 0; i < n_sub; ++i) {
+    As.push_back(&c.subs[i].A);
+    Ss.push_back(&c.sym[i]);
+    in.push_back(&c.subs[i].dofs);
+  }
+  BatchHost fb;
+  int32_t npert = 0;
+  build_batch(As, Ss, in, c.device, on_device, fb, c.fine, npert);
+  st.factor_entries = fb.nf + fb.nb;
+  st.levels_fwd = (int32_t)fb.lev_f.size() - 1;
+  st.levels_bwd = (int32_t)fb.lev_b.size() - 1;
+  st.max_front = fb.max_front;
+  st.factor_flops = fb.flops;
+  for (auto& S : c.sym) st.n_supernodes += S.nsn;
+  // prolongation map: global dof -> positions with D > 0, in subdomain order
+  {
+    const int64_t n = c.D.n;
+    std::vector<int64_t> ptr(n + 1, 0);
+    for (auto& S : c.subs)
+      for (size_t k = 0; k < S.dofs.size(); ++k)
+        if (S.D[k] > 0) ptr[S.dofs[k] + 1]++;
+    for (int64_t g = 0; g < n; ++g) ptr[g + 1] += ptr[g];
+    std::vector<int32_t> idx(ptr[n]);
+    std::vector<double> wt(ptr[n]);
+    std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+    int64_t pos0 = 0;
+    for (int32_t i = 0; i < n_sub; ++i) {
+      const SubdomainHost& S = c.subs[i];
+      for (size_t k = 0; k < S.dofs.size(); ++k)
+        if (S.D[k] > 0) {
+          int64_t q = fill[S.dofs[k]]++;
+          idx[q] = (int32_t)(pos0 + c.sym[i].iperm[k]);
+          wt[q] = S.D[k];
+        }
+      pos0 += (int64_t)S.dofs.size();
+    }
+    if (on_device) {
+      c.pro_ptr.upload(ptr);
+      c.pro_idx.upload(idx);
+      c.pro_w.upload(wt);
+    }
+  }
+  // coarse level
+  if (coarse) {
+    std::vector<double> ccoords;
+    coarse_interpolation(c.D, *coarse, c.Z, ccoords);
+    transpose_real(c.Z, c.ZT);
+    galerkin(c.D.A, c.Z, c.ZT, c.E);
+    nested_dissection(c.E, ccoords, leaf, c.Esym);
+    std::vector<int64_t> ident(c.E.n);
+    std::iota(ident.begin(), ident.end(), 0);
+    BatchHost cb;
+    int32_t np2 = 0;
+    build_batch({&c.E}, {&c.Esym}, {&ident}, c.device, on_device, cb, c.coarse, np2);
+    npert += np2;
+    c.two_level = true;
+    st.n_coarse = (int32_t)c.E.n;
+    st.coarse_entries = cb.nf + cb.nb;
+    if (on_device) {
+      // Z with columns renumbered to the coarse solve's output positions
+      CsrReal Zp = c.Z;
+      for (auto& col : Zp.col) col = c.Esym.iperm[col];
+      for (int64_t i = 0; i < Zp.n; ++i) {
+        std::vector<std::pair<int32_t, double>> e;
+        for (int64_t p = Zp.ptr[i]; p < Zp.ptr[i + 1]; ++p) e.push_back({Zp.col[p], Zp.val[p]});
+        std::sort(e.begin(), e.end());
+        for (size_t q = 0; q < e.size(); ++q) {
+          Zp.col[Zp.ptr[i] + q] = e[q].first;
+          Zp.val[Zp.ptr[i] + q] = e[q].second;
+        }
+      }
+      c.Zp_ptr.upload(Zp.ptr);
+      c.Zp_col.upload(Zp.col);
+      c.Zp_val.upload(Zp.val);
+      c.ZT_ptr.upload(c.ZT.ptr);
+      c.ZT_col.upload(c.ZT.col);
+      c.ZT_val.upload(c.ZT.val);
+      c.cvec.alloc(2 * c.E.n);
+    }
+  }
+  if (on_device) {
+    c.t.alloc(2 * c.D.n);
+    c.q.alloc(2 * c.D.n);
+    HELM_HIP(hipDeviceSynchronize());
+  }
+  (void)npert;
+  st.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  c.precond_ready = true;
+}
+
+double spmv_bytes(const Ctx& c, bool residual) {
+  const double n = (double)c.D.n, nnz = (double)c.D.A.nnz();
+  return nnz * 20.0 + 8.0 * (n + 1) + 16.0 * n * (residual ? 3 : 2);
+}
+
+void apply_A(Ctx& c, const double* x, double* y, hipStream_t s) {
+  const bool p = c.prof.on;
+  if (p) c.prof.begin(s);
+  dev::spmv(c.D.n, c.A_ptr.p, c.A_col.p, c.A_val.p, x, nullptr, y, s);
+  if (p) c.prof.end(HELM_K_SPMV, spmv_bytes(c, false), s);
+}
+
+void apply_coarse(Ctx& c, const double* r, double* q, hipStream_t s) {
+  const bool p = c.prof.on;
+  if (p) c.prof.begin(s);
+  dev::spmv_real(c.ZT.n, c.ZT_ptr.p, c.ZT_col.p, c.ZT_val.p, r, c.cvec.p, s);
+  batch_solve(c.coarse, c.cvec.p, s, &c.prof, false);
+  dev::spmv_real(c.D.n, c.Zp_ptr.p, c.Zp_col.p, c.Zp_val.p, c.coarse.x.p, q, s);
+  if (p) {
+    const double zb = 2.0 * (12.0 * (double)c.Z.col.size() + 8.0 * c.D.n) + 16.0 * (c.D.n + c.E.n);
+    c.prof.end(HELM_K_COARSE, zb + sum(c.coarse.bytes_f) + sum(c.coarse.bytes_b), s);
+  }
+}
+
+void apply_oras(Ctx& c, const double* r, double* z, const double* q, hipStream_t s) {
+  batch_solve(c.fine, r, s, &c.prof, true);
+  const bool p = c.prof.on;
+  if (p) c.prof.begin(s);
+  dev::prolong(c.D.n, c.pro_ptr.p, c.pro_idx.p, c.pro_w.p, c.fine.x.p, q, z, s);
+  if (p) c.prof.end(HELM_K_PROLONG, 12.0 * c.pro_w.n + 28.0 * c.pro_w.n + 16.0 * c.D.n * (q ? 2 : 1) + 8.0 * c.D.n, s);
+}
+
+void apply_precond(Ctx& c, const double* r, double* z, hipStream_t s) {
+  if (!c.two_level) {
+    apply_oras(c, r, z, nullptr, s);
+    return;
+  }
+  apply_coarse(c, r, c.q.p, s);
+  const bool p = c.prof.on;
+  if (p) c.prof.begin(s);
+  dev::spmv(c.D.n, c.A_ptr.p, c.A_col.p, c.A_val.p, c.q.p, r, c.t.p, s);  // t = r - A q
+  if (p) c.prof.end(HELM_K_SPMV, spmv_bytes(c, true), s);
+  apply_oras(c, c.t.p, z, c.q.p, s);
+}
+
+namespace {
+
+double device_norm(Ctx& c, const double* v, hipStream_t s) {
+  const int nblk = dev::gs_blocks(c.D.n);
+  dev::norm2(c.D.n, v, c.partial.p, nblk, c.nrm.p, s);
+  HELM_HIP(hipMemcpyAsync(c.h_host, c.nrm.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HELM_HIP(hipStreamSynchronize(s));
+  return c.h_host[0];
+}
+
+void ensure_gmres(Ctx& c, int m) {
+  if (c.gm_m == m && c.V.p) return;
+  const int64_t n = c.D.n;
+  c.V.alloc(2 * (size_t)n * (m + 1));
+  c.Zk.alloc(2 * (size_t)n * m);
+  c.w.alloc(2 * (size_t)n);
+  const int nblk = dev::gs_blocks(n);
+  c.partial.alloc(2 * (size_t)nblk * (m + 2));
+  c.hcol.alloc(2 * (size_t)(m + 2));
+  c.htmp.alloc(2 * (size_t)(m + 2));
+  c.nrm.alloc(2);
+  c.ydev.alloc(2 * (size_t)(m + 1));
+  if (c.h_host) (void)hipHostFree(c.h_host);
+  c.h_host = nullptr;
+  HELM_HIP(hipHostMalloc((void**)&c.h_host, 2 * sizeof(double) * (m + 2), hipHostMallocDefault));
+  c.gm_m = m;
+}
+
+}  // namespace
+
+int solve(Ctx& c, int32_t nrhs, const double* B, double tol, const helm_solve_opts* opts, double* U, hipStream_t s,
+          helm_solve_info* info) {
+  const int m = opts && opts->restart > 0 ? opts->restart : 50;
+  const int maxit = opts && opts->maxit > 0 ? opts->maxit : 1000;
+  const bool x0 = opts && (opts->flags & HELM_SOLVE_X0);
+  if (m > 1000) fail(HELM_EINVAL, "restart must be <= 1000");
+  if (!(tol > 0)) fail(HELM_EINVAL, "tol must be positive");
+  ensure_gmres(c, m);
+  const int64_t n = c.D.n;
+  const int nblk = dev::gs_blocks(n);
+  double* V = c.V.p;
+  double* Zk = c.Zk.p;
+  std::vector<cplx> H((size_t)(m + 1) * m), g(m + 1), sn(m);
+  std::vector<double> cs(m);
+  std::vector<cplx> y(m);
+  int status = HELM_OK;
+  for (int32_t j = 0; j < nrhs; ++j) {
+    auto t0 = std::chrono::steady_clock::now();
+    const double* b = B + 2 * (size_t)n * j;
+    double* x = U + 2 * (size_t)n * j;
+    helm_solve_info inf{};
+    const double bnorm = device_norm(c, b, s);
+    if (!std::isfinite(bnorm)) fail(HELM_ENUMERIC, "non-finite right-hand side");
+    if (bnorm == 0) {
+      dev::fill_zero(2 * n, x, s);
+      HELM_HIP(hipStreamSynchronize(s));
+      inf.converged = 1;
+      if (info) info[j] = inf;
+      continue;
+    }
+    if (!x0) dev::fill_zero(2 * n, x, s);
+    int its = 0;
+    bool conv = false;
+    double rel = 0;
+    while (true) {
+      dev::spmv(n, c.A_ptr.p, c.A_col.p, c.A_val.p, x, b, V, s);  // r = b - A x
+      const double beta = device_norm(c, V, s);
+      if (!std::isfinite(beta)) fail(HELM_ENUMERIC, "non-finite residual");
+      rel = beta / bnorm;
+      if (beta <= tol * bnorm) {
+        conv = true;
+        break;
+      }
+      if (its >= maxit) break;
+      dev::scale(n, V, 1.0 / beta, V, s);
+      std::fill(g.begin(), g.end(), cplx(0, 0));
+      g[0] = beta;
+      int k = 0;
+      for (int jj = 0; jj < m; ++jj) {
+        double* vj = V + 2 * (size_t)n * jj;
+        double* zj = Zk + 2 * (size_t)n * jj;
+        apply_precond(c, vj, zj, s);
+        apply_A(c, zj, c.w.p, s);
+        // CGS2
+        const bool prof = c.prof.on;
+        if (prof) c.prof.begin(s);
+        for (int pass = 0; pass < 2; ++pass) {
+          dev::gs_dots_partial(n, V, n, jj + 1, c.w.p, c.partial.p, nblk, s);
+          dev::gs_dots_final(c.partial.p, nblk, jj + 1, c.htmp.p, c.hcol.p, pass, s);
+          dev::gs_update(n, V, n, jj + 1, c.htmp.p, c.w.p, s);
+        }
+        dev::norm2(n, c.w.p, c.partial.p, nblk, c.hcol.p + 2 * (jj + 1), s);
+        dev::scale_by_inv(n, c.w.p, c.hcol.p + 2 * (jj + 1), V + 2 * (size_t)n * (jj + 1), s);
+        if (prof) c.prof.end(HELM_K_GS, 16.0 * n * (3.0 * (jj + 1) + 6.0), s);
+        HELM_HIP(hipMemcpyAsync(c.h_host, c.hcol.p, 2 * sizeof(double) * (jj + 2), hipMemcpyDeviceToHost, s));
+        HELM_HIP(hipStreamSynchronize(s));
+        if (c.prof.on) c.prof.harvest();
+        ++its;
+        cplx* h = H.data() + (size_t)(m + 1) * jj;
+        for (int i = 0; i <= jj + 1; ++i) {
+          h[i] = cplx(c.h_host[2 * i], c.h_host[2 * i + 1]);
+          if (!std::isfinite(h[i].real()) || !std::isfinite(h[i].imag())) fail(HELM_ENUMERIC, "non-finite Hessenberg entry");
+        }
+        const double hn = h[jj + 1].real();
+        for (int i = 0; i < jj; ++i) {
+          cplx a = h[i], bb = h[i + 1];
+          h[i] = cs[i] * a + sn[i] * bb;
+          h[i + 1] = -std::conj(sn[i]) * a + cs[i] * bb;
+        }
+        {
+          cplx a = h[jj], bb = h[jj + 1];
+          if (a == cplx(0, 0)) {
+            cs[jj] = 0;
+            sn[jj] = 1;
+          } else {
+            double r = std::sqrt(std::norm(a) + std::norm(bb));
+            cs[jj] = std::abs(a) / r;
+            sn[jj] = (a / std::abs(a)) * std::conj(bb) / r;
+          }
+          h[jj] = cs[jj] * a + sn[jj] * bb;
+          h[jj + 1] = 0;
+          g[jj + 1] = -std::conj(sn[jj]) * g[jj];
+          g[jj] = cs[jj] * g[jj];
+        }
+        k = jj + 1;
+        if (std::abs(g[jj + 1]) <= tol * bnorm || its >= maxit || hn == 0) break;
+      }
+      // back substitution R y = g
+      for (int i = k - 1; i >= 0; --i) {
+        cplx acc = g[i];
+        for (int l = i + 1; l < k; ++l) acc -= H[(size_t)(m + 1) * l + i] * y[l];
+        y[i] = acc / H[(size_t)(m + 1) * i + i];
+      }
+      HELM_HIP(hipMemcpyAsync(c.ydev.p, y.data(), sizeof(cplx) * k, hipMemcpyHostToDevice, s));
+      dev::gemv_acc(n, Zk, n, k, c.ydev.p, x, s);
+      HELM_HIP(hipStreamSynchronize(s));  // y is reused by the next cycle
+    }
+    HELM_HIP(hipStreamSynchronize(s));
+    if (c.prof.on) c.prof.harvest();
+    inf.iterations = its;
+    inf.converged = conv ? 1 : 0;
+    inf.relres = rel;
+    inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) info[j] = inf;
+    if (!conv) status = HELM_ENOCONV;
+  }
+  return status;
+}
+
+}  // namespace helm

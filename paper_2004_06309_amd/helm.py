@@ -1,0 +1,287 @@
+"""ctypes binding of libhelm (include/helm.h).
+
+Argument marshalling only: every step of the solver runs in the library
+(host C++ setup, HIP kernels on the GPU).  Device vectors are torch tensors
+of dtype complex128 (interleaved re/im doubles); torch only provides device
+memory and streams.  Importing this module fails loudly when the library has
+not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhelm.so")
+
+HELM_OK = 0
+HELM_EINVAL = -1
+HELM_ESINGULAR = -2
+HELM_ENOCONV = -3
+HELM_ENUMERIC = -4
+HELM_ENOMEM = -5
+HELM_ESTATE = -6
+HELM_EDEVICE = -7
+HELM_SOLVE_X0 = 1
+
+_ERRNAMES = {-1: "EINVAL", -2: "ESINGULAR", -3: "ENOCONV", -4: "ENUMERIC", -5: "ENOMEM", -6: "ESTATE",
+             -7: "EDEVICE"}
+
+
+class HelmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"HELM_{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Mesh(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("xyz", C.c_void_p), ("n_tets", C.c_int64), ("tets", C.c_void_p),
+                ("order", C.c_int32)]
+
+
+class PrecondOpts(C.Structure):
+    _fields_ = [("leaf_size", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("maxit", C.c_int32), ("flags", C.c_int32), ("reserved", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("relres", C.c_double),
+                ("seconds", C.c_double)]
+
+
+class PrecondStats(C.Structure):
+    _fields_ = [("n_sub", C.c_int32), ("n_coarse", C.c_int32), ("n_local_total", C.c_int64),
+                ("factor_entries", C.c_int64), ("coarse_entries", C.c_int64), ("levels_fwd", C.c_int32),
+                ("levels_bwd", C.c_int32), ("max_front", C.c_int32), ("n_supernodes", C.c_int32),
+                ("setup_seconds", C.c_double), ("factor_flops", C.c_double)]
+
+
+class KernelProfile(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("milliseconds", C.c_double), ("bytes", C.c_double)]
+
+
+KERNELS = ["trsv_fwd", "trsv_bwd", "spmv", "coarse", "prolong", "gs"]
+
+EXPORTS = {
+    "helm_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int]),
+    "helm_destroy": (None, [C.c_void_p]),
+    "helm_last_error": (C.c_char_p, [C.c_void_p]),
+    "helm_assemble": (C.c_int, [C.c_void_p, C.POINTER(Mesh), C.c_void_p, C.c_double]),
+    "helm_ndof": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "helm_dof_coords": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "helm_point_source": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "helm_matrix_nnz": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "helm_matrix_csr": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "helm_precond_setup": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Mesh),
+                                     C.POINTER(PrecondOpts)]),
+    "helm_precond_stats_get": (C.c_int, [C.c_void_p, C.POINTER(PrecondStats)]),
+    "helm_subdomain_size": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "helm_subdomain_get": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]),
+    "helm_coarse_nnz": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "helm_coarse_get": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "helm_apply_A": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "helm_apply_precond": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "helm_apply_oras": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "helm_apply_coarse": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "helm_solve": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.POINTER(SolveOpts), C.c_void_p,
+                             C.c_void_p, C.POINTER(SolveInfo)]),
+    "helm_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
+    "helm_profile_read": (C.c_int, [C.c_void_p, C.POINTER(KernelProfile)]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libhelm.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is missing: run `python -m paper_2004_06309_amd.build` first")
+        lib = C.CDLL(_LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _mesh(xyz, tets, order):
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    tets = np.ascontiguousarray(tets, dtype=np.int64)
+    m = Mesh(xyz.shape[0], xyz.ctypes.data, tets.shape[0], tets.ctypes.data, int(order))
+    return m, (xyz, tets)
+
+
+def _dev_ptr(t):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.is_contiguous()):
+        raise ValueError("device vectors must be contiguous GPU tensors")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+class Helm:
+    """One solver context (helm_ctx).  device=-1 gives a host-only context."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        h = C.c_void_p()
+        rc = self.lib.helm_create(C.byref(h), device)
+        if rc != HELM_OK:
+            raise HelmError(rc, self.lib.helm_last_error(None).decode())
+        self.h = h
+        self.device = device
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.helm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow=()):
+        if rc != HELM_OK and rc not in allow:
+            raise HelmError(rc, self.lib.helm_last_error(self.h).decode())
+        return rc
+
+    # ---- setup -------------------------------------------------------------
+    def assemble(self, xyz, tets, order, c_tet, omega):
+        m, keep = _mesh(xyz, tets, order)
+        c = np.ascontiguousarray(np.asarray(c_tet, dtype=np.complex128))
+        self._check(self.lib.helm_assemble(self.h, C.byref(m), _ptr(c), float(omega)))
+        n = C.c_int64()
+        self._check(self.lib.helm_ndof(self.h, C.byref(n)))
+        self.n = n.value
+        return self.n
+
+    def dof_coords(self):
+        out = np.empty((self.n, 3))
+        self._check(self.lib.helm_dof_coords(self.h, _ptr(out)))
+        return out
+
+    def point_source(self, xs):
+        xs = np.ascontiguousarray(xs, dtype=np.float64)
+        b = np.empty(self.n, dtype=np.complex128)
+        self._check(self.lib.helm_point_source(self.h, _ptr(xs), _ptr(b)))
+        return b
+
+    def matrix_csr(self):
+        nnz = C.c_int64()
+        self._check(self.lib.helm_matrix_nnz(self.h, C.byref(nnz)))
+        ptr = np.empty(self.n + 1, dtype=np.int64)
+        col = np.empty(nnz.value, dtype=np.int32)
+        val = np.empty(nnz.value, dtype=np.complex128)
+        self._check(self.lib.helm_matrix_csr(self.h, _ptr(ptr), _ptr(col), _ptr(val)))
+        return ptr, col, val
+
+    def precond_setup(self, part, n_sub, overlap, coarse_xyz=None, coarse_tets=None, leaf_size=0):
+        part = np.ascontiguousarray(part, dtype=np.int32)
+        opts = PrecondOpts(int(leaf_size))
+        cm = None
+        if coarse_xyz is not None:
+            cm, keep = _mesh(coarse_xyz, coarse_tets, 1)
+            self._keep = keep
+        self._check(self.lib.helm_precond_setup(self.h, _ptr(part), int(n_sub), int(overlap),
+                                                C.byref(cm) if cm is not None else None, C.byref(opts)))
+        self.two_level = cm is not None
+
+    def stats(self):
+        s = PrecondStats()
+        self._check(self.lib.helm_precond_stats_get(self.h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in PrecondStats._fields_}
+
+    def subdomain(self, i):
+        n_i, nnz = C.c_int64(), C.c_int64()
+        self._check(self.lib.helm_subdomain_size(self.h, int(i), C.byref(n_i), C.byref(nnz)))
+        dofs = np.empty(n_i.value, dtype=np.int64)
+        D = np.empty(n_i.value)
+        ptr = np.empty(n_i.value + 1, dtype=np.int64)
+        col = np.empty(nnz.value, dtype=np.int32)
+        val = np.empty(nnz.value, dtype=np.complex128)
+        self._check(self.lib.helm_subdomain_get(self.h, int(i), _ptr(dofs), _ptr(D), _ptr(ptr), _ptr(col),
+                                                _ptr(val)))
+        return dofs, D, (ptr, col, val)
+
+    def coarse_Z(self):
+        nc, nnz = C.c_int64(), C.c_int64()
+        self._check(self.lib.helm_coarse_nnz(self.h, C.byref(nc), C.byref(nnz)))
+        ptr = np.empty(self.n + 1, dtype=np.int64)
+        col = np.empty(nnz.value, dtype=np.int32)
+        val = np.empty(nnz.value)
+        self._check(self.lib.helm_coarse_get(self.h, _ptr(ptr), _ptr(col), _ptr(val)))
+        return nc.value, (ptr, col, val)
+
+    # ---- device operations (torch complex128 tensors) -----------------------
+    def apply_A(self, x, y, stream=None):
+        self._check(self.lib.helm_apply_A(self.h, _dev_ptr(x), _dev_ptr(y), _stream(stream)))
+
+    def apply_precond(self, r, z, stream=None):
+        self._check(self.lib.helm_apply_precond(self.h, _dev_ptr(r), _dev_ptr(z), _stream(stream)))
+
+    def apply_oras(self, r, z, stream=None):
+        self._check(self.lib.helm_apply_oras(self.h, _dev_ptr(r), _dev_ptr(z), _stream(stream)))
+
+    def apply_coarse(self, r, q, stream=None):
+        self._check(self.lib.helm_apply_coarse(self.h, _dev_ptr(r), _dev_ptr(q), _stream(stream)))
+
+    def solve(self, B, U, tol=1e-6, restart=50, maxit=1000, x0=False, stream=None):
+        """Solve A U = B; B, U are (n,) or (nrhs, n) complex128 GPU tensors
+        (each RHS contiguous).  Returns (status, [info dicts])."""
+        nrhs = 1 if B.dim() == 1 else B.shape[0]
+        info = (SolveInfo * max(nrhs, 1))()
+        opts = SolveOpts(int(restart), int(maxit), HELM_SOLVE_X0 if x0 else 0, 0)
+        rc = self._check(self.lib.helm_solve(self.h, nrhs, _dev_ptr(B), float(tol), C.byref(opts), _dev_ptr(U),
+                                             _stream(stream), info), allow=(HELM_ENOCONV,))
+        return rc, [{f: getattr(info[i], f) for f, _ in SolveInfo._fields_} for i in range(nrhs)]
+
+    # ---- kernel timing -----------------------------------------------------
+    def profile(self, on: bool):
+        """Time every launch of the per-iteration kernels with HIP events."""
+        self._check(self.lib.helm_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self):
+        out = (KernelProfile * len(KERNELS))()
+        self._check(self.lib.helm_profile_read(self.h, out))
+        return {k: {"launches": out[i].launches, "ms": out[i].milliseconds, "bytes": out[i].bytes}
+                for i, k in enumerate(KERNELS)}
+
+
+def from_workload(w, device=0, leaf_size=0):
+    """Helm context assembled and preconditioned for a workloads.Workload."""
+    h = Helm(device)
+    h.assemble(w.xyz, w.tets, w.order, w.c_tet, w.omega)
+    h.precond_setup(w.part, w.n_sub, w.overlap, w.coarse_xyz, w.coarse_tets, leaf_size)
+    return h
+
+
+def load_vector(h: Helm, w):
+    """Right-hand side of a workload (point or nodal source), host complex128."""
+    if w.source_point is not None:
+        return h.point_source(w.source_point)
+    b = np.zeros(h.n, dtype=np.complex128)
+    b[w.source_node] = 1.0
+    return b

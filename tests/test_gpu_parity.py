@@ -1,0 +1,202 @@
+"""GPU parity of libhelm against the CPU oracle, through the C-ABI.
+
+Every step of the per-iteration path (SpMV, one-level ORAS, coarse
+correction, two-level preconditioner) and the full GMRES solve are compared
+with the oracle on the same seeded inputs.  Tolerances:
+
+* SpMV: the two sides assemble the same entries independently (equal to
+  ~1e-15 relative), so products agree to 1e-13 relative (max norm).
+* Preconditioner applications: the library solves with explicit inverses of
+  supernodal LU factors, the oracle with SuperLU; both are backward stable, so
+  they agree to about cond(A_i) * eps.  The local matrices here have
+  condition numbers below ~1e5, hence the bound 1e-9 relative.
+* Solves: true relative residual <= 1e-6 measured with the oracle's A, the
+  same iteration count within +-2 (CGS2 vs MGS), and relative L2 difference
+  <= 1e-5 from the oracle's GMRES solution at the same tolerance.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import dd as odd  # noqa: E402
+from oracle import precond as opre  # noqa: E402
+from paper_2004_06309_amd import helm  # noqa: E402
+from paper_2004_06309_amd import workloads as wl  # noqa: E402
+
+DEV = "cuda"
+
+WORKLOADS = {
+    "tiny": lambda: wl.tiny(),
+    "small_p2_2lvl": lambda: wl.small_box(n=(6, 6, 4), order=2, n_parts=(2, 2, 1), overlap=2),
+    "ragged_p2": lambda: wl.small_box(n=(5, 3, 4), order=2, n_parts=(3, 2, 1), overlap=1, coarse=False),
+    "mid_quarter_2lvl": lambda: wl.mid(scale=4, n_parts=(4, 4, 1)),
+}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dvec(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex128)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+@pytest.fixture(scope="module", params=sorted(WORKLOADS))
+def pair(request):
+    name = request.param
+    say(f"[parity] building {name}")
+    w = WORKLOADS[name]()
+    P, b, M = opre.build(w)
+    h = helm.from_workload(w)
+    return name, w, P, b, M, h
+
+
+def rand_vec(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(n) + 1j * rng.standard_normal(n)
+
+
+def test_spmv_parity(pair):
+    name, w, P, b, M, h = pair
+    x = rand_vec(P.n, 1)
+    y = torch.empty(P.n, dtype=torch.complex128, device=DEV)
+    h.apply_A(dvec(x), y)
+    assert rel(host(y), P.A @ x) <= 1e-13
+
+
+def test_oras_parity(pair):
+    name, w, P, b, M, h = pair
+    r = rand_vec(P.n, 2)
+    z = torch.empty(P.n, dtype=torch.complex128, device=DEV)
+    h.apply_oras(dvec(r), z)
+    assert rel(host(z), M.one_level(r)) <= 1e-9
+
+
+def test_coarse_and_two_level_parity(pair):
+    name, w, P, b, M, h = pair
+    if M.Z is None:
+        pytest.skip("one-level workload")
+    r = rand_vec(P.n, 3)
+    q = torch.empty(P.n, dtype=torch.complex128, device=DEV)
+    h.apply_coarse(dvec(r), q)
+    assert rel(host(q), M.coarse_correction(r)) <= 1e-9
+    z = torch.empty(P.n, dtype=torch.complex128, device=DEV)
+    h.apply_precond(dvec(r), z)
+    assert rel(host(z), M.apply(r)) <= 1e-9
+
+
+def test_solve_parity(pair):
+    name, w, P, b, M, h = pair
+    ro = opre.solve(P, b, M, tol=w.tol, restart=w.restart)
+    U = torch.zeros(P.n, dtype=torch.complex128, device=DEV)
+    B = dvec(b)
+    rc, info = h.solve(B, U, tol=w.tol, restart=w.restart)
+    u = host(U)
+    say(f"[parity] {name}: gpu its={info[0]['iterations']} oracle its={ro.iterations}")
+    assert rc == helm.HELM_OK and info[0]["converged"] == 1
+    res = np.linalg.norm(b - P.A @ u) / np.linalg.norm(b)
+    assert res <= w.tol
+    assert abs(info[0]["iterations"] - ro.iterations) <= 2
+    assert np.linalg.norm(u - ro.x) <= 1e-5 * np.linalg.norm(ro.x)
+    # repeatability: a second solve is bitwise identical
+    U2 = torch.zeros_like(U)
+    h.solve(B, U2, tol=w.tol, restart=w.restart)
+    assert torch.equal(U, U2)
+
+
+def test_edge_cases():
+    w = wl.small_box(n=(4, 3, 3), order=2, n_parts=(2, 1, 1), overlap=1, coarse=False)
+    P, b, M = opre.build(w)
+    h = helm.from_workload(w)
+    n = P.n
+    B = dvec(b)
+    # zero right-hand side -> zero solution, no iteration
+    U = torch.ones(n, dtype=torch.complex128, device=DEV)
+    rc, info = h.solve(torch.zeros(n, dtype=torch.complex128, device=DEV), U)
+    assert rc == helm.HELM_OK and info[0]["iterations"] == 0 and float(U.abs().max()) == 0
+    # maxit reached -> ENOCONV with the last iterate and its residual
+    U = torch.zeros(n, dtype=torch.complex128, device=DEV)
+    rc, info = h.solve(B, U, tol=1e-14, maxit=2)
+    assert rc == helm.HELM_ENOCONV and info[0]["converged"] == 0 and info[0]["iterations"] == 2
+    u = host(U)
+    assert np.isclose(np.linalg.norm(b - P.A @ u) / np.linalg.norm(b), info[0]["relres"], rtol=1e-6)
+    # restart from a converged solution -> 0 iterations
+    rc, info = h.solve(B, U, tol=1e-6)
+    rc, info = h.solve(B, U, tol=1e-6, x0=True)
+    assert rc == helm.HELM_OK and info[0]["iterations"] == 0
+    # NaN in the right-hand side -> ENUMERIC
+    bad = b.copy()
+    bad[3] = np.nan
+    with pytest.raises(helm.HelmError) as e:
+        h.solve(dvec(bad), U)
+    assert e.value.code == helm.HELM_ENUMERIC
+    # several right-hand sides == solo solves; short restart exercises restarts
+    B2 = torch.stack([B, dvec(rand_vec(n, 9))])
+    U2 = torch.zeros_like(B2)
+    rc, info = h.solve(B2, U2, tol=1e-8, restart=5)
+    assert rc == helm.HELM_OK and all(i["converged"] for i in info)
+    U1 = torch.zeros(n, dtype=torch.complex128, device=DEV)
+    h.solve(B2[1].contiguous(), U1, tol=1e-8, restart=5)
+    assert torch.equal(U1, U2[1])
+
+
+@pytest.mark.timeout(900)
+def test_mid_full_size():
+    """Mid workload at full size (1.06M P2 dofs, 64 subdomains, two-level), in
+    the configuration the benchmark times: sampled SpMV rows and sampled local
+    solves against the oracle, and the true residual of the solve measured with
+    the oracle's assembled A."""
+    from oracle import fem
+
+    w = wl.mid()
+    say("[mid] library setup")
+    h = helm.from_workload(w)
+    say("[mid] stats", h.stats())
+    say("[mid] oracle assembly")
+    P = fem.Problem(w.xyz, w.tets, w.order, w.c_tet, w.omega)
+    b = P.point_source(w.source_point)
+    assert np.allclose(h.point_source(w.source_point), b, atol=1e-14)
+    x = rand_vec(P.n, 4)
+    y = torch.empty(P.n, dtype=torch.complex128, device=DEV)
+    h.apply_A(dvec(x), y)
+    y = host(y)
+    rows = np.random.default_rng(5).choice(P.n, 2000, replace=False)
+    assert rel(y[rows], P.A[rows] @ x) <= 1e-13
+    # one-level ORAS at dofs owned by a single subdomain (D_i = 1) equals that
+    # subdomain's local solve
+    r = rand_vec(P.n, 6)
+    z = torch.empty(P.n, dtype=torch.complex128, device=DEV)
+    h.apply_oras(dvec(r), z)
+    z = host(z)
+    subs = odd.decompose(P, w.part, w.n_sub, w.overlap)
+    import scipy.sparse.linalg as spla
+
+    for i in (0, 27):
+        say(f"[mid] oracle local solve {i}")
+        s = subs[i]
+        Ai = odd.local_matrix(P, s).tocsc()
+        zi = spla.splu(Ai).solve(r[s.dofs])
+        own = s.D == 1.0
+        assert rel(z[s.dofs[own]], zi[own]) <= 1e-9
+    say("[mid] solve")
+    U = torch.zeros(P.n, dtype=torch.complex128, device=DEV)
+    rc, info = h.solve(dvec(b), U, tol=w.tol, restart=w.restart)
+    say("[mid] info", info)
+    u = host(U)
+    assert rc == helm.HELM_OK
+    assert np.linalg.norm(b - P.A @ u) / np.linalg.norm(b) <= w.tol
