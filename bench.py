@@ -101,6 +101,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="mid", choices=["mid", "tiny"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the complex64-factor measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -126,45 +127,54 @@ def main():
 
     w = wl.mid() if args.config == "mid" else wl.tiny()
     log(f"[bench] workload {w.name}: {w.tets.shape[0]} tets, P{w.order}")
-    t0 = time.perf_counter()
-    h = helm.Helm(0)
-    h.assemble(w.xyz, w.tets, w.order, w.c_tet, w.omega)
-    t_asm = time.perf_counter() - t0
-    h.precond_setup(w.part, w.n_sub, w.overlap, w.coarse_xyz, w.coarse_tets)
-    st = h.stats()
-    log(f"[bench] setup {time.perf_counter() - t0:.1f} s, stats {st}")
+    stream = torch.cuda.current_stream()
+
+    def setup(c64):
+        t0 = time.perf_counter()
+        h = helm.Helm(0)
+        h.assemble(w.xyz, w.tets, w.order, w.c_tet, w.omega)
+        t_asm = time.perf_counter() - t0
+        h.precond_setup(w.part, w.n_sub, w.overlap, w.coarse_xyz, w.coarse_tets, c64=c64)
+        st = h.stats()
+        log(f"[bench] setup ({'c64' if c64 else 'c128'} factors) {time.perf_counter() - t0:.1f} s, stats {st}")
+        return h, st, t_asm
+
+    def run(h, B, U, steps, warmup, tag):
+        def one_solve():
+            U.zero_()
+            rc, info = h.solve(B, U, tol=w.tol, restart=w.restart, stream=stream)
+            if rc != helm.HELM_OK:
+                raise RuntimeError(f"solve did not converge: {info}")
+            return info[0]
+
+        for i in range(warmup):
+            inf = one_solve()
+            log(f"[bench] {tag} warmup {i}: {inf}")
+        torch.cuda.synchronize()
+        h.profile(True)
+        times, its = [], []
+        for i in range(steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            inf = one_solve()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) / 1e3)
+            its.append(inf["iterations"])
+            log(f"[bench] {tag} step {i}: {inf['iterations']} its, {times[-1] * 1e3:.1f} ms, "
+                f"relres {inf['relres']:.2e}")
+        torch.cuda.synchronize()
+        prof = h.profile_read()
+        h.profile(False)
+        return times, its, prof
+
+    h, st, t_asm = setup(False)
     b = helm.load_vector(h, w)
     B = torch.from_numpy(b).to("cuda")
     U = torch.zeros_like(B)
-    stream = torch.cuda.current_stream()
-
-    def one_solve():
-        U.zero_()
-        rc, info = h.solve(B, U, tol=w.tol, restart=w.restart, stream=stream)
-        if rc != helm.HELM_OK:
-            raise RuntimeError(f"solve did not converge: {info}")
-        return info[0]
-
-    for i in range(args.warmup):
-        inf = one_solve()
-        log(f"[bench] warmup {i}: {inf}")
-    torch.cuda.synchronize()
-    h.profile(True)
-    times, its = [], []
     t_start = time.perf_counter()
-    for i in range(args.steps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        inf = one_solve()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        times.append(e0.elapsed_time(e1) / 1e3)
-        its.append(inf["iterations"])
-        log(f"[bench] step {i}: {inf['iterations']} its, {times[-1] * 1e3:.1f} ms, relres {inf['relres']:.2e}")
-    torch.cuda.synchronize()
+    times, its, prof = run(h, B, U, args.steps, args.warmup, "fp64")
     wall = time.perf_counter() - t_start
-    prof = h.profile_read()
-    h.profile(False)
     total_t = float(np.sum(times))
     total_its = int(np.sum(its))
     its_per_s = total_its / total_t
@@ -209,6 +219,31 @@ def main():
         "kernels": kernels,
         "wall_s_timed": wall,
     }
+    if not args.no_fp32:
+        # the metric's other line: complex64 subdomain factors, FP64 FGMRES,
+        # FP64 coarse solve; error reported against the FP64-factor result
+        u64 = U.clone()
+        del h
+        torch.cuda.empty_cache()
+        h32, st32, _ = setup(True)
+        U32 = torch.zeros_like(B)
+        t32, it32, prof32 = run(h32, B, U32, args.steps, args.warmup, "fp32")
+        tt = float(np.sum(t32))
+        k32 = {k: {"avg_us": 1e3 * v["ms"] / max(v["launches"], 1),
+                   "GBps": (v["bytes"] / 2 / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 and k.startswith("trsv")
+                   else ((v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None)}
+               for k, v in prof32.items()}
+        out["fp32_precond"] = {
+            "iterations_per_s": int(np.sum(it32)) / tt,
+            "solves_per_s": len(t32) / tt,
+            "iterations_per_solve": float(np.mean(it32)),
+            "p50_ms": 1e3 * float(np.percentile(t32, 50)),
+            "p99_ms": 1e3 * float(np.percentile(t32, 99)),
+            "rel_l2_vs_fp64_factors": float(torch.linalg.norm(U32 - u64) / torch.linalg.norm(u64)),
+            "factor_GB": st32["factor_entries"] * 8 / 1e9,
+            "speedup_vs_fp64": (len(t32) / tt) / solves_per_s,
+            "kernels": k32,
+        }
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(w, float(np.mean(its)))

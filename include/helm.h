@@ -63,7 +63,11 @@ typedef struct helm_mesh {
 
 typedef struct helm_precond_opts {
   int32_t leaf_size;       /* nested-dissection leaf size, 0 = default     */
-  int32_t reserved[7];
+  int32_t factor_c64;      /* 1: store the subdomain factors in complex64
+                              (computed in complex128, rounded once); the
+                              panel products still accumulate in FP64 and
+                              the coarse factors stay complex128          */
+  int32_t reserved[6];
 } helm_precond_opts;
 
 enum {
@@ -71,7 +75,7 @@ enum {
 };
 
 typedef struct helm_solve_opts {
-  int32_t restart;         /* GMRES(m) restart length, 0 = 50              */
+  int32_t restart;         /* GMRES(m) restart length, 1..56, 0 = 50       */
   int32_t maxit;           /* total Arnoldi steps per RHS, 0 = 1000        */
   int32_t flags;           /* HELM_SOLVE_*                                 */
   int32_t reserved;
@@ -96,6 +100,8 @@ typedef struct helm_precond_stats {
   int32_t n_supernodes;    /* fine-level supernodes                        */
   double setup_seconds;    /* wall time of the last helm_precond_setup     */
   double factor_flops;     /* complex multiply-adds x 8 in the factorisation */
+  int32_t factor_c64;      /* 1 if the fine factors are stored in complex64 */
+  int32_t reserved;
 } helm_precond_stats;
 
 /* Create a context on HIP device `device_ordinal`; -1 creates a host-only

@@ -53,7 +53,9 @@ struct BatchHost {
   std::vector<int64_t> roff;
   std::vector<int32_t> rows, bidx, fcon_ptr, fcon_idx;
   std::vector<dev::Tile> tf, tb;
-  std::vector<int64_t> lev_f, lev_b;  // tile ranges per level
+  std::vector<dev::Task> kf, kb;      // workgroup tasks
+  std::vector<int64_t> lev_f, lev_b;  // task ranges per level
+  std::vector<double> bytes_f, bytes_b;  // algorithmic bytes per level
   int64_t nf = 0, nb = 0, nu = 0;     // panel entries (fwd, bwd), update entries
   int32_t max_front = 0;
   double flops = 0;
@@ -62,18 +64,26 @@ struct BatchHost {
 // Device copy of a batch.
 struct BatchDev {
   DVec<dev::Tile> tf, tb;
+  DVec<dev::Task> kf, kb;
+  int c64 = 0;
   DVec<int32_t> c0, w, uoff, frow0, rows, bidx, fcon_ptr, fcon_idx;
   DVec<int64_t> roff;
-  DVec<double> pf, pb, ubuf, y, x;
+  DVec<unsigned char> pf, pb;  // panels, complex128 or complex64 entries
+  DVec<double> ubuf, y, x;
   std::vector<int64_t> lev_f, lev_b;
   int64_t npos = 0;
   std::vector<double> bytes_f, bytes_b;  // algorithmic bytes per level
   dev::Batch view() const;
   void reset() {
     for (auto* v : {&c0, &w, &uoff, &frow0, &rows, &bidx, &fcon_ptr, &fcon_idx}) v->reset();
-    for (auto* v : {&pf, &pb, &ubuf, &y, &x}) v->reset();
+    for (auto* v : {&ubuf, &y, &x}) v->reset();
+    pf.reset();
+    pb.reset();
     tf.reset();
     tb.reset();
+    kf.reset();
+    kb.reset();
+    c64 = 0;
     roff.reset();
     lev_f.clear();
     lev_b.clear();

@@ -29,40 +29,79 @@ __device__ __forceinline__ void cfma(double& ar, double& ai, double2 a, double2 
   ai = fma(a.y, v.x, ai);
 }
 
-// Streams columns [k0, k1) of a tile (column-major, ld = nr) against vin.
-__device__ __forceinline__ void tile_dot(const double2* __restrict__ p, int nr, const double2* vin, int k0, int k1,
+__device__ __forceinline__ double2 widen(double2 a) { return a; }
+__device__ __forceinline__ double2 widen(float2 a) { return make_double2((double)a.x, (double)a.y); }
+
+// Streams columns [k0, k1) of a tile (column-major, ld = nr) against vin,
+// eight independent loads in flight per lane.
+template <class PT>
+__device__ __forceinline__ void tile_dot(const PT* __restrict__ p, int nr, const double2* vin, int k0, int k1,
                                         double& ar, double& ai) {
   int k = k0;
   double br = 0, bi = 0;
-  for (; k + 4 <= k1; k += 4) {
-    double2 a0 = p[(int64_t)(k + 0) * nr];
-    double2 a1 = p[(int64_t)(k + 1) * nr];
-    double2 a2 = p[(int64_t)(k + 2) * nr];
-    double2 a3 = p[(int64_t)(k + 3) * nr];
-    cfma(ar, ai, a0, vin[k + 0]);
-    cfma(br, bi, a1, vin[k + 1]);
-    cfma(ar, ai, a2, vin[k + 2]);
-    cfma(br, bi, a3, vin[k + 3]);
+  for (; k + 8 <= k1; k += 8) {
+    PT a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = p[(int64_t)(k + u) * nr];
+#pragma unroll
+    for (int u = 0; u < 8; u += 2) {
+      cfma(ar, ai, widen(a[u]), vin[k + u]);
+      cfma(br, bi, widen(a[u + 1]), vin[k + u + 1]);
+    }
   }
-  for (; k < k1; ++k) cfma(ar, ai, p[(int64_t)k * nr], vin[k]);
+  for (; k < k1; ++k) cfma(ar, ai, widen(p[(int64_t)k * nr]), vin[k]);
   ar += br;
   ai += bi;
 }
 
-__global__ __launch_bounds__(kWG) void fwd_level_kernel(const Tile* __restrict__ tiles, Batch b,
+// Work split of a workgroup (4 waves) over the tiles of its task.
+struct Split {
+  int my;      // tile slot of this wave
+  int part;    // this wave's share of the tile's columns
+  int wpt;     // waves per tile
+  int region;  // LDS entries per tile slot
+  bool has;    // the slot holds a tile
+};
+
+__device__ __forceinline__ Split split_of(const Task& task) {
+  Split sp;
+  const int wv = threadIdx.x >> 6;
+  sp.wpt = task.wpt;
+  sp.my = wv / sp.wpt;
+  sp.part = wv % sp.wpt;
+  sp.region = kChunk / (4 / sp.wpt);
+  sp.has = sp.my < task.ntile;
+  return sp;
+}
+
+template <class PT, int kCoarse>
+__global__ __launch_bounds__(kWG) void fwd_level_kernel(const Task* __restrict__ tasks, Batch b,
                                                         const double2* __restrict__ bin) {
   __shared__ double2 vin[kChunk];
   __shared__ double2 red[4][64];
-  const Tile t = tiles[blockIdx.x];
-  const int s = t.sn;
-  const int c0 = b.sn_c0[s], w = b.sn_w[s], frow0 = b.sn_frow0[s];
+  const Task task = tasks[blockIdx.x];
+  const Split sp = split_of(task);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const double2* __restrict__ P = reinterpret_cast<const double2*>(b.pf) + t.off + lane;
+  Tile t{};
+  int s = 0, c0 = 0, w = 0, frow0 = 0;
+  if (sp.has) {
+    t = b.tf[task.tile0 + sp.my];
+    s = t.sn;
+    c0 = b.sn_c0[s];
+    w = b.sn_w[s];
+    frow0 = b.sn_frow0[s];
+  }
+  double2* vt = vin + sp.my * sp.region;
+  const PT* __restrict__ P = reinterpret_cast<const PT*>(b.pf) + t.off + lane;
   const double2* __restrict__ ub = reinterpret_cast<const double2*>(b.ubuf);
   double ar = 0, ai = 0;
-  for (int cb = 0; cb < t.ncols; cb += kChunk) {
-    const int cn = min(kChunk, t.ncols - cb);
-    for (int k = threadIdx.x; k < cn; k += kWG) {
+  // all waves of a workgroup run the same number of passes: one, unless the
+  // workgroup holds a single wide tile
+  const int npass = sp.wpt == 4 ? (t.ncols + kChunk - 1) / kChunk : 1;
+  for (int pass = 0; pass < npass; ++pass) {
+    const int cb = pass * sp.region;
+    const int cn = sp.has ? min(sp.region, t.ncols - cb) : 0;
+    for (int k = sp.part * 64 + lane; k < cn; k += 64 * sp.wpt) {
       const int kk = cb + k;
       double2 v = bin[b.bidx[c0 + kk]];
       const int fr = frow0 + kk;
@@ -71,19 +110,24 @@ __global__ __launch_bounds__(kWG) void fwd_level_kernel(const Tile* __restrict__
         v.x -= u.x;
         v.y -= u.y;
       }
-      vin[k] = v;
+      vt[k] = v;
     }
     __syncthreads();
-    const int per = (cn + 3) >> 2;
-    const int k0 = wv * per, k1 = min(cn, k0 + per);
-    if (lane < t.nrows) tile_dot(P + (int64_t)cb * t.nrows, t.nrows, vin, k0, k1, ar, ai);
+    if (sp.has && lane < t.nrows) {
+      const int per = (cn + sp.wpt - 1) / sp.wpt;
+      const int k0 = sp.part * per, k1 = min(cn, k0 + per);
+      tile_dot(P + (int64_t)cb * t.nrows, t.nrows, vt, k0, k1, ar, ai);
+    }
     __syncthreads();
   }
   red[wv][lane] = make_double2(ar, ai);
   __syncthreads();
-  if (wv == 0 && lane < t.nrows) {
-    double rr = red[0][lane].x + red[1][lane].x + red[2][lane].x + red[3][lane].x;
-    double ii = red[0][lane].y + red[1][lane].y + red[2][lane].y + red[3][lane].y;
+  if (sp.has && sp.part == 0 && lane < t.nrows) {
+    double rr = 0, ii = 0;
+    for (int q = 0; q < sp.wpt; ++q) {
+      rr += red[wv + q][lane].x;
+      ii += red[wv + q][lane].y;
+    }
     const int row = t.row0 + lane;
     if (row < w) {
       reinterpret_cast<double2*>(b.y)[c0 + row] = make_double2(rr, ii);
@@ -99,35 +143,51 @@ __global__ __launch_bounds__(kWG) void fwd_level_kernel(const Tile* __restrict__
   }
 }
 
-__global__ __launch_bounds__(kWG) void bwd_level_kernel(const Tile* __restrict__ tiles, Batch b) {
+template <class PT, int kCoarse>
+__global__ __launch_bounds__(kWG) void bwd_level_kernel(const Task* __restrict__ tasks, Batch b) {
   __shared__ double2 vin[kChunk];
   __shared__ double2 red[4][64];
-  const Tile t = tiles[blockIdx.x];
-  const int s = t.sn;
-  const int c0 = b.sn_c0[s], w = b.sn_w[s];
-  const int64_t roff = b.sn_roff[s];
+  const Task task = tasks[blockIdx.x];
+  const Split sp = split_of(task);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const double2* __restrict__ P = reinterpret_cast<const double2*>(b.pb) + t.off + lane;
+  Tile t{};
+  int c0 = 0, w = 0;
+  int64_t roff = 0;
+  if (sp.has) {
+    t = b.tb[task.tile0 + sp.my];
+    c0 = b.sn_c0[t.sn];
+    w = b.sn_w[t.sn];
+    roff = b.sn_roff[t.sn];
+  }
+  double2* vt = vin + sp.my * sp.region;
+  const PT* __restrict__ P = reinterpret_cast<const PT*>(b.pb) + t.off + lane;
   const double2* __restrict__ yv = reinterpret_cast<const double2*>(b.y);
   const double2* xv = reinterpret_cast<const double2*>(b.x);
   double ar = 0, ai = 0;
-  for (int cb = 0; cb < t.ncols; cb += kChunk) {
-    const int cn = min(kChunk, t.ncols - cb);
-    for (int k = threadIdx.x; k < cn; k += kWG) {
+  const int npass = sp.wpt == 4 ? (t.ncols + kChunk - 1) / kChunk : 1;
+  for (int pass = 0; pass < npass; ++pass) {
+    const int cb = pass * sp.region;
+    const int cn = sp.has ? min(sp.region, t.ncols - cb) : 0;
+    for (int k = sp.part * 64 + lane; k < cn; k += 64 * sp.wpt) {
       const int c = t.col0 + cb + k;
-      vin[k] = c < w ? yv[c0 + c] : xv[b.rows[roff + (c - w)]];
+      vt[k] = c < w ? yv[c0 + c] : xv[b.rows[roff + (c - w)]];
     }
     __syncthreads();
-    const int per = (cn + 3) >> 2;
-    const int k0 = wv * per, k1 = min(cn, k0 + per);
-    if (lane < t.nrows) tile_dot(P + (int64_t)cb * t.nrows, t.nrows, vin, k0, k1, ar, ai);
+    if (sp.has && lane < t.nrows) {
+      const int per = (cn + sp.wpt - 1) / sp.wpt;
+      const int k0 = sp.part * per, k1 = min(cn, k0 + per);
+      tile_dot(P + (int64_t)cb * t.nrows, t.nrows, vt, k0, k1, ar, ai);
+    }
     __syncthreads();
   }
   red[wv][lane] = make_double2(ar, ai);
   __syncthreads();
-  if (wv == 0 && lane < t.nrows) {
-    double rr = red[0][lane].x + red[1][lane].x + red[2][lane].x + red[3][lane].x;
-    double ii = red[0][lane].y + red[1][lane].y + red[2][lane].y + red[3][lane].y;
+  if (sp.has && sp.part == 0 && lane < t.nrows) {
+    double rr = 0, ii = 0;
+    for (int q = 0; q < sp.wpt; ++q) {
+      rr += red[wv + q][lane].x;
+      ii += red[wv + q][lane].y;
+    }
     reinterpret_cast<double2*>(b.x)[c0 + t.row0 + lane] = make_double2(rr, ii);
   }
 }
@@ -291,6 +351,77 @@ __global__ __launch_bounds__(kWG) void gs_update_kernel(int64_t n, const double2
   }
 }
 
+// One CGS2 pass over a 64-row tile of V (all ncol columns staged in LDS,
+// padded to avoid bank conflicts):
+//   kUpdate: w -= V h                (h: device, ncol entries)
+//   kDots:   partial[blk*ncol + k] = sum_rows conj(V[i,k]) w[i]
+//   kNorm:   partial[blk] = sum_rows |w[i]|^2   (real, stored in .x)
+constexpr int kGsRows = 64;
+constexpr int kGsMaxCols = 64;
+
+template <bool kUpdate, bool kDots, bool kNorm>
+__global__ __launch_bounds__(kWG) void gs_pass_kernel(int64_t n, const double2* __restrict__ V, int64_t ld, int ncol,
+                                                      const double2* __restrict__ h, double2* __restrict__ w,
+                                                      double2* __restrict__ partial) {
+  // dynamic LDS: tile[ncol][kGsRows + 1], then h, the new w and norms
+  extern __shared__ double2 lds[];
+  double2 (*tile)[kGsRows + 1] = reinterpret_cast<double2 (*)[kGsRows + 1]>(lds);
+  double2* hs = lds + (size_t)ncol * (kGsRows + 1);
+  double2* wn = hs + kGsMaxCols;
+  double* red = reinterpret_cast<double*>(wn + kGsRows);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * kGsRows;
+  const int64_t i = i0 + lane;
+  const bool valid = i < n;
+  // stage the tile: wave q loads columns q, q+4, ...
+  for (int k = wv; k < ncol; k += 4) tile[k][lane] = valid ? V[(int64_t)k * ld + i] : make_double2(0.0, 0.0);
+  if (kUpdate && tid < ncol) hs[tid] = h[tid];
+  __syncthreads();
+  if (tid < kGsRows) {
+    double2 wi = valid ? w[i] : make_double2(0.0, 0.0);
+    if (kUpdate) {
+      double ur = 0, ui = 0;
+      for (int k = 0; k < ncol; ++k) cfma(ur, ui, tile[k][tid], hs[k]);
+      wi.x -= ur;
+      wi.y -= ui;
+      if (valid) w[i] = wi;
+    }
+    wn[tid] = wi;
+    if (kNorm) red[tid] = wi.x * wi.x + wi.y * wi.y;
+  }
+  __syncthreads();
+  if (kDots && tid < ncol) {
+    double ar = 0, ai = 0;
+    for (int r = 0; r < kGsRows; ++r) {
+      const double2 v = tile[tid][r], x = wn[r];
+      ar = fma(v.x, x.x, ar);
+      ar = fma(v.y, x.y, ar);
+      ai = fma(v.x, x.y, ai);
+      ai = fma(-v.y, x.x, ai);
+    }
+    partial[(int64_t)blockIdx.x * ncol + tid] = make_double2(ar, ai);
+  }
+  if (kNorm && tid == 0) {
+    double s = 0;
+    for (int r = 0; r < kGsRows; ++r) s += red[r];
+    partial[blockIdx.x] = make_double2(s, 0.0);
+  }
+}
+
+__global__ __launch_bounds__(kWG) void norm_final2_kernel(const double2* __restrict__ partial, int nblk,
+                                                          double2* __restrict__ out) {
+  __shared__ double sm[kWG];
+  double s = 0;
+  for (int b = threadIdx.x; b < nblk; b += kWG) s += partial[b].x;
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = kWG / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sm[threadIdx.x] += sm[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = make_double2(sqrt(sm[0]), 0.0);
+}
+
 __global__ __launch_bounds__(kWG) void norm_partial_kernel(int64_t n, const double2* __restrict__ w,
                                                            double* __restrict__ partial) {
   __shared__ double sm[kWG];
@@ -368,14 +499,29 @@ inline unsigned blocks_for(int64_t n, int per = kWG) { return (unsigned)((n + pe
 
 }  // namespace
 
-void fwd_level(const Batch& b, int64_t tile0, int64_t ntiles, const double* bin, hipStream_t s) {
-  if (ntiles <= 0) return;
-  fwd_level_kernel<<<(unsigned)ntiles, kWG, 0, s>>>(b.tf + tile0, b, reinterpret_cast<const double2*>(bin));
+int waves_per_tile(int ncols) { return ncols <= 96 ? 1 : (ncols <= 384 ? 2 : 4); }
+
+void fwd_level(const Batch& b, int64_t task0, int64_t ntasks, const double* bin, bool coarse, hipStream_t s) {
+  if (ntasks <= 0) return;
+  const Task* k = b.kf + task0;
+  const double2* in = reinterpret_cast<const double2*>(bin);
+  if (coarse)
+    fwd_level_kernel<double2, 1><<<(unsigned)ntasks, kWG, 0, s>>>(k, b, in);
+  else if (b.c64)
+    fwd_level_kernel<float2, 0><<<(unsigned)ntasks, kWG, 0, s>>>(k, b, in);
+  else
+    fwd_level_kernel<double2, 0><<<(unsigned)ntasks, kWG, 0, s>>>(k, b, in);
 }
 
-void bwd_level(const Batch& b, int64_t tile0, int64_t ntiles, hipStream_t s) {
-  if (ntiles <= 0) return;
-  bwd_level_kernel<<<(unsigned)ntiles, kWG, 0, s>>>(b.tb + tile0, b);
+void bwd_level(const Batch& b, int64_t task0, int64_t ntasks, bool coarse, hipStream_t s) {
+  if (ntasks <= 0) return;
+  const Task* k = b.kb + task0;
+  if (coarse)
+    bwd_level_kernel<double2, 1><<<(unsigned)ntasks, kWG, 0, s>>>(k, b);
+  else if (b.c64)
+    bwd_level_kernel<float2, 0><<<(unsigned)ntasks, kWG, 0, s>>>(k, b);
+  else
+    bwd_level_kernel<double2, 0><<<(unsigned)ntasks, kWG, 0, s>>>(k, b);
 }
 
 void spmv(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const double* x, const double* b,
@@ -427,6 +573,29 @@ void gs_update(int64_t n, const double* V, int64_t ld, int ncol, const double* h
   gs_update_kernel<<<(unsigned)gs_blocks(n), kWG, 0, s>>>(n, reinterpret_cast<const double2*>(V), ld, ncol,
                                                            reinterpret_cast<const double2*>(h),
                                                            reinterpret_cast<double2*>(w));
+}
+
+int gs_tiles(int64_t n) { return (int)((n + kGsRows - 1) / kGsRows); }
+
+void gs_pass(int mode, int64_t n, const double* V, int64_t ld, int ncol, const double* h, double* w, double* partial,
+             hipStream_t s) {
+  const unsigned nb = (unsigned)gs_tiles(n);
+  const size_t lds = sizeof(double2) * ((size_t)ncol * (kGsRows + 1) + kGsMaxCols + kGsRows) + sizeof(double) * kGsRows;
+  auto V2 = reinterpret_cast<const double2*>(V);
+  auto h2 = reinterpret_cast<const double2*>(h);
+  auto w2 = reinterpret_cast<double2*>(w);
+  auto p2 = reinterpret_cast<double2*>(partial);
+  if (mode == 0)
+    gs_pass_kernel<false, true, false><<<nb, kWG, lds, s>>>(n, V2, ld, ncol, h2, w2, p2);
+  else if (mode == 1)
+    gs_pass_kernel<true, true, false><<<nb, kWG, lds, s>>>(n, V2, ld, ncol, h2, w2, p2);
+  else
+    gs_pass_kernel<true, false, true><<<nb, kWG, lds, s>>>(n, V2, ld, ncol, h2, w2, p2);
+}
+
+void norm_final(const double* partial, int nblk, double* out, hipStream_t s) {
+  norm_final2_kernel<<<1, kWG, 0, s>>>(reinterpret_cast<const double2*>(partial), nblk,
+                                       reinterpret_cast<double2*>(out));
 }
 
 void norm2(int64_t n, const double* w, double* partial, int nblk, double* out, hipStream_t s) {

@@ -15,11 +15,21 @@ struct Tile {
   int32_t sn, row0, nrows, col0, ncols, pad;
 };
 
+// A workgroup's share of a level: ntile consecutive tiles, each handled by
+// wpt waves (ntile * wpt <= 4).
+struct Task {
+  int32_t tile0;
+  int16_t ntile;
+  int16_t wpt;
+};
+
 // Device arrays of one batch of factored matrices (all fine subdomains, or
 // the coarse matrix), see factor.cpp for the panel layout.
 struct Batch {
   const Tile* tf = nullptr;        // forward tiles, grouped by level
   const Tile* tb = nullptr;        // backward tiles, grouped by level
+  const Task* kf = nullptr;        // forward workgroup tasks, grouped by level
+  const Task* kb = nullptr;        // backward workgroup tasks
   const int32_t* sn_c0 = nullptr;  // first position of the supernode
   const int32_t* sn_w = nullptr;   // columns
   const int32_t* sn_uoff = nullptr;  // offset of its update vector in ubuf
@@ -29,15 +39,20 @@ struct Batch {
   const int32_t* bidx = nullptr;   // pivot position -> input-vector index
   const int32_t* fcon_ptr = nullptr; // front row -> child update entries
   const int32_t* fcon_idx = nullptr;
-  const double* pf = nullptr;      // forward panels
-  const double* pb = nullptr;      // backward panels
+  const void* pf = nullptr;        // forward panels (complex128, or complex64 when c64)
+  const void* pb = nullptr;        // backward panels
+  int c64 = 0;
   double* ubuf = nullptr;          // update vectors
   double* y = nullptr;             // forward result (pivot order)
   double* x = nullptr;             // backward result (column order)
 };
 
-void fwd_level(const Batch& b, int64_t tile0, int64_t ntiles, const double* bin, hipStream_t s);
-void bwd_level(const Batch& b, int64_t tile0, int64_t ntiles, hipStream_t s);
+// One level of the forward / backward sweep: tasks [task0, task0 + ntasks).
+// coarse selects a separate instantiation so profiles tell the two apart.
+void fwd_level(const Batch& b, int64_t task0, int64_t ntasks, const double* bin, bool coarse, hipStream_t s);
+void bwd_level(const Batch& b, int64_t task0, int64_t ntasks, bool coarse, hipStream_t s);
+// Waves per tile chosen for a tile with ncols input columns.
+int waves_per_tile(int ncols);
 
 // y = A x, or y = b - A x when b != nullptr (complex CSR).
 void spmv(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const double* x, const double* b,
@@ -57,6 +72,13 @@ void gs_dots_partial(int64_t n, const double* V, int64_t ld, int ncol, const dou
 // h[k] = sum_b partial[b*ncol + k]; hacc[k] (+)= h[k] (accumulate != 0 adds)
 void gs_dots_final(const double* partial, int nblk, int ncol, double* h, double* hacc, int accumulate,
                    hipStream_t s);
+// Fused CGS2 pass over 64-row tiles (gs_tiles(n) blocks, ncol <= 64):
+// mode 0: partial dots V^H w; mode 1: w -= V h then partial dots of the new
+// w; mode 2: w -= V h then partial squared norms (reduce with norm_final).
+int gs_tiles(int64_t n);
+void gs_pass(int mode, int64_t n, const double* V, int64_t ld, int ncol, const double* h, double* w, double* partial,
+             hipStream_t s);
+void norm_final(const double* partial, int nblk, double* out, hipStream_t s);
 // w -= V h
 void gs_update(int64_t n, const double* V, int64_t ld, int ncol, const double* h, double* w, hipStream_t s);
 // out[0] = ||w||_2 (real, stored as complex with zero imaginary part)

@@ -52,6 +52,9 @@ dev::Batch BatchDev::view() const {
   dev::Batch b;
   b.tf = tf.p;
   b.tb = tb.p;
+  b.kf = kf.p;
+  b.kb = kb.p;
+  b.c64 = c64;
   b.sn_c0 = c0.p;
   b.sn_w = w.p;
   b.sn_uoff = uoff.p;
@@ -227,16 +230,51 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
     for (int i = 0; i < nm; ++i)
       for (auto& e : fcon_m[i]) B.fcon_idx[fill[e.first]++] = e.second;
   }
-  B.lev_f.assign(1, 0);
-  for (auto& l : lf) {
-    B.tf.insert(B.tf.end(), l.begin(), l.end());
-    B.lev_f.push_back((int64_t)B.tf.size());
-  }
-  B.lev_b.assign(1, 0);
-  for (auto& l : lb) {
-    B.tb.insert(B.tb.end(), l.begin(), l.end());
-    B.lev_b.push_back((int64_t)B.tb.size());
-  }
+  // algorithmic bytes per level: every panel entry once, plus the vector
+  // entries each supernode gathers and writes
+  auto r_of = [&](int64_t s) { return (s + 1 < nsn ? B.roff[s + 1] : B.nu) - B.roff[s]; };
+  auto level_bytes = [&](const std::vector<dev::Tile>& T, bool fwd) {
+    double by = 0;
+    int32_t last = -1;
+    for (const auto& t : T) {
+      by += 16.0 * t.nrows * t.ncols;
+      const int32_t s = t.sn;
+      if (s == last) continue;
+      last = s;
+      const double w = B.w[s], r = (double)r_of(s);
+      if (fwd) {
+        const double nfc = B.fcon_ptr[B.frow0[s] + (int64_t)(w + r)] - B.fcon_ptr[B.frow0[s]];
+        by += 16.0 * (w + nfc + w + r);
+      } else {
+        by += 16.0 * (w + r + w);
+      }
+    }
+    return by;
+  };
+  // workgroup tasks: tiles grouped by width class, 4 / wpt tiles per group
+  auto make_tasks = [&](std::vector<std::vector<dev::Tile>>& levels, bool fwd, std::vector<dev::Tile>& tiles,
+                        std::vector<dev::Task>& tasks, std::vector<int64_t>& lev, std::vector<double>& bytes) {
+    lev.assign(1, 0);
+    for (auto& l : levels) {
+      bytes.push_back(level_bytes(l, fwd));
+      std::stable_sort(l.begin(), l.end(), [](const dev::Tile& a, const dev::Tile& b) {
+        return dev::waves_per_tile(a.ncols) < dev::waves_per_tile(b.ncols);
+      });
+      size_t q = 0;
+      while (q < l.size()) {
+        const int wpt = dev::waves_per_tile(l[q].ncols);
+        const int per = 4 / wpt;
+        size_t e = q;
+        while (e < l.size() && (int)(e - q) < per && dev::waves_per_tile(l[e].ncols) == wpt) ++e;
+        tasks.push_back({(int32_t)(tiles.size() + q), (int16_t)(e - q), (int16_t)wpt});
+        q = e;
+      }
+      tiles.insert(tiles.end(), l.begin(), l.end());
+      lev.push_back((int64_t)tasks.size());
+    }
+  };
+  make_tasks(lf, true, B.tf, B.kf, B.lev_f, B.bytes_f);
+  make_tasks(lb, false, B.tb, B.kb, B.lev_b, B.bytes_b);
 }
 
 namespace {
@@ -244,9 +282,11 @@ namespace {
 // Factors a batch (one matrix per thread) and uploads the panels; without a
 // device only the layout is built (pivots taken as the identity).
 void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symbolic*>& Ss,
-                 const std::vector<const std::vector<int64_t>*>& in_idx, int device, bool numeric, BatchHost& B,
-                 BatchDev& Dv, int32_t& n_perturbed) {
+                 const std::vector<const std::vector<int64_t>*>& in_idx, int device, bool numeric, bool c64,
+                 BatchHost& B, BatchDev& Dv, int32_t& n_perturbed) {
   const int nm = (int)As.size();
+  const size_t esz = c64 ? sizeof(std::complex<float>) : sizeof(cplx);
+  Dv.c64 = c64 ? 1 : 0;
   std::vector<int64_t> pf0(nm + 1, 0), pb0(nm + 1, 0);
   for (int i = 0; i < nm; ++i) {
     pf0[i + 1] = pf0[i] + Ss[i]->fwd_entries;
@@ -254,8 +294,8 @@ void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symb
   }
   std::vector<NumericOut> num(nm);
   if (numeric) {
-    Dv.pf.alloc(2 * (size_t)pf0[nm]);
-    Dv.pb.alloc(2 * (size_t)pb0[nm]);
+    Dv.pf.alloc(esz * (size_t)pf0[nm]);
+    Dv.pb.alloc(esz * (size_t)pb0[nm]);
     std::string errmsg;
     int errcode = 0;
     int32_t npert = 0;
@@ -267,10 +307,18 @@ void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symb
         factor_numeric(*As[i], S, hf.data(), hb.data(), num[i]);
         npert += num[i].n_perturbed;
         HELM_HIP(hipSetDevice(device));
-        if (S.fwd_entries)
-          HELM_HIP(hipMemcpy(Dv.pf.p + 2 * pf0[i], hf.data(), sizeof(cplx) * S.fwd_entries, hipMemcpyHostToDevice));
-        if (S.bwd_entries)
-          HELM_HIP(hipMemcpy(Dv.pb.p + 2 * pb0[i], hb.data(), sizeof(cplx) * S.bwd_entries, hipMemcpyHostToDevice));
+        auto put = [&](unsigned char* dst, const std::vector<cplx>& src) {
+          if (src.empty()) return;
+          if (!c64) {
+            HELM_HIP(hipMemcpy(dst, src.data(), sizeof(cplx) * src.size(), hipMemcpyHostToDevice));
+            return;
+          }
+          std::vector<std::complex<float>> lo(src.size());
+          for (size_t q = 0; q < src.size(); ++q) lo[q] = std::complex<float>(src[q]);
+          HELM_HIP(hipMemcpy(dst, lo.data(), sizeof(std::complex<float>) * lo.size(), hipMemcpyHostToDevice));
+        };
+        put(Dv.pf.p + esz * pf0[i], hf);
+        put(Dv.pb.p + esz * pb0[i], hb);
       } catch (const Error& e) {
 #pragma omp critical
         {
@@ -290,42 +338,16 @@ void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symb
     }
   }
   layout_batch(Ss, in_idx, num, B);
-  // algorithmic bytes per level: every panel entry once, plus the vector
-  // entries each supernode gathers and writes
-  {
-    const int64_t nsn = (int64_t)B.c0.size();
-    auto r_of = [&](int64_t s) { return (s + 1 < nsn ? B.roff[s + 1] : B.nu) - B.roff[s]; };
-    auto level_bytes = [&](const std::vector<dev::Tile>& T, const std::vector<int64_t>& lev, bool fwd) {
-      std::vector<double> out;
-      for (size_t l = 0; l + 1 < lev.size(); ++l) {
-        double by = 0;
-        int32_t last = -1;
-        for (int64_t q = lev[l]; q < lev[l + 1]; ++q) {
-          by += 16.0 * T[q].nrows * T[q].ncols;
-          const int32_t s = T[q].sn;
-          if (s == last) continue;
-          last = s;
-          const double w = B.w[s], r = (double)r_of(s);
-          if (fwd) {
-            const double nfc = B.fcon_ptr[B.frow0[s] + (int64_t)(w + r)] - B.fcon_ptr[B.frow0[s]];
-            by += 16.0 * (w + nfc + w + r);
-          } else {
-            by += 16.0 * (w + r + w);
-          }
-        }
-        out.push_back(by);
-      }
-      return out;
-    };
-    Dv.bytes_f = level_bytes(B.tf, B.lev_f, true);
-    Dv.bytes_b = level_bytes(B.tb, B.lev_b, false);
-  }
   if (!numeric) return;
   Dv.npos = B.npos;
   Dv.lev_f = B.lev_f;
   Dv.lev_b = B.lev_b;
+  Dv.bytes_f = B.bytes_f;
+  Dv.bytes_b = B.bytes_b;
   Dv.tf.upload(B.tf);
   Dv.tb.upload(B.tb);
+  Dv.kf.upload(B.kf);
+  Dv.kb.upload(B.kb);
   Dv.c0.upload(B.c0);
   Dv.w.upload(B.w);
   Dv.uoff.upload(B.uoff);
@@ -347,12 +369,12 @@ void batch_solve(const BatchDev& b, const double* in, hipStream_t s, Profiler* p
   const bool each = prof && prof->on && fine;
   for (size_t l = 0; l + 1 < b.lev_f.size(); ++l) {
     if (each) prof->begin(s);
-    dev::fwd_level(v, b.lev_f[l], b.lev_f[l + 1] - b.lev_f[l], in, s);
+    dev::fwd_level(v, b.lev_f[l], b.lev_f[l + 1] - b.lev_f[l], in, !fine, s);
     if (each) prof->end(HELM_K_TRSV_FWD, b.bytes_f[l], s);
   }
   for (size_t l = 0; l + 1 < b.lev_b.size(); ++l) {
     if (each) prof->begin(s);
-    dev::bwd_level(v, b.lev_b[l], b.lev_b[l + 1] - b.lev_b[l], s);
+    dev::bwd_level(v, b.lev_b[l], b.lev_b[l + 1] - b.lev_b[l], !fine, s);
     if (each) prof->end(HELM_K_TRSV_BWD, b.bytes_b[l], s);
   }
 }
@@ -393,8 +415,10 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
   }
   BatchHost fb;
   int32_t npert = 0;
-  build_batch(As, Ss, in, c.device, on_device, fb, c.fine, npert);
+  const bool c64 = opts && opts->factor_c64;
+  build_batch(As, Ss, in, c.device, on_device, c64, fb, c.fine, npert);
   st.factor_entries = fb.nf + fb.nb;
+  st.factor_c64 = c64 ? 1 : 0;
   st.levels_fwd = (int32_t)fb.lev_f.size() - 1;
   st.levels_bwd = (int32_t)fb.lev_b.size() - 1;
   st.max_front = fb.max_front;
@@ -439,7 +463,7 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
     std::iota(ident.begin(), ident.end(), 0);
     BatchHost cb;
     int32_t np2 = 0;
-    build_batch({&c.E}, {&c.Esym}, {&ident}, c.device, on_device, cb, c.coarse, np2);
+    build_batch({&c.E}, {&c.Esym}, {&ident}, c.device, on_device, false, cb, c.coarse, np2);
     npert += np2;
     c.two_level = true;
     st.n_coarse = (int32_t)c.E.n;
@@ -537,7 +561,7 @@ void ensure_gmres(Ctx& c, int m) {
   c.V.alloc(2 * (size_t)n * (m + 1));
   c.Zk.alloc(2 * (size_t)n * m);
   c.w.alloc(2 * (size_t)n);
-  const int nblk = dev::gs_blocks(n);
+  const int nblk = std::max(dev::gs_blocks(n), dev::gs_tiles(n));
   c.partial.alloc(2 * (size_t)nblk * (m + 2));
   c.hcol.alloc(2 * (size_t)(m + 2));
   c.htmp.alloc(2 * (size_t)(m + 2));
@@ -556,7 +580,7 @@ int solve(Ctx& c, int32_t nrhs, const double* B, double tol, const helm_solve_op
   const int m = opts && opts->restart > 0 ? opts->restart : 50;
   const int maxit = opts && opts->maxit > 0 ? opts->maxit : 1000;
   const bool x0 = opts && (opts->flags & HELM_SOLVE_X0);
-  if (m > 1000) fail(HELM_EINVAL, "restart must be <= 1000");
+  if (m > 56) fail(HELM_EINVAL, "restart must be <= 56");
   if (!(tol > 0)) fail(HELM_EINVAL, "tol must be positive");
   ensure_gmres(c, m);
   const int64_t n = c.D.n;
@@ -604,17 +628,18 @@ int solve(Ctx& c, int32_t nrhs, const double* B, double tol, const helm_solve_op
         double* zj = Zk + 2 * (size_t)n * jj;
         apply_precond(c, vj, zj, s);
         apply_A(c, zj, c.w.p, s);
-        // CGS2
+        // CGS2: dots | update + dots | update + norm, each one pass over V
         const bool prof = c.prof.on;
         if (prof) c.prof.begin(s);
-        for (int pass = 0; pass < 2; ++pass) {
-          dev::gs_dots_partial(n, V, n, jj + 1, c.w.p, c.partial.p, nblk, s);
-          dev::gs_dots_final(c.partial.p, nblk, jj + 1, c.htmp.p, c.hcol.p, pass, s);
-          dev::gs_update(n, V, n, jj + 1, c.htmp.p, c.w.p, s);
-        }
-        dev::norm2(n, c.w.p, c.partial.p, nblk, c.hcol.p + 2 * (jj + 1), s);
+        const int nt = dev::gs_tiles(n);
+        dev::gs_pass(0, n, V, n, jj + 1, nullptr, c.w.p, c.partial.p, s);
+        dev::gs_dots_final(c.partial.p, nt, jj + 1, c.htmp.p, c.hcol.p, 0, s);
+        dev::gs_pass(1, n, V, n, jj + 1, c.htmp.p, c.w.p, c.partial.p, s);
+        dev::gs_dots_final(c.partial.p, nt, jj + 1, c.htmp.p, c.hcol.p, 1, s);
+        dev::gs_pass(2, n, V, n, jj + 1, c.htmp.p, c.w.p, c.partial.p, s);
+        dev::norm_final(c.partial.p, nt, c.hcol.p + 2 * (jj + 1), s);
         dev::scale_by_inv(n, c.w.p, c.hcol.p + 2 * (jj + 1), V + 2 * (size_t)n * (jj + 1), s);
-        if (prof) c.prof.end(HELM_K_GS, 16.0 * n * (3.0 * (jj + 1) + 6.0), s);
+        if (prof) c.prof.end(HELM_K_GS, 16.0 * n * (3.0 * (jj + 1) + 7.0), s);
         HELM_HIP(hipMemcpyAsync(c.h_host, c.hcol.p, 2 * sizeof(double) * (jj + 2), hipMemcpyDeviceToHost, s));
         HELM_HIP(hipStreamSynchronize(s));
         if (c.prof.on) c.prof.harvest();

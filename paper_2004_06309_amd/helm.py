@@ -41,7 +41,7 @@ class Mesh(C.Structure):
 
 
 class PrecondOpts(C.Structure):
-    _fields_ = [("leaf_size", C.c_int32), ("reserved", C.c_int32 * 7)]
+    _fields_ = [("leaf_size", C.c_int32), ("factor_c64", C.c_int32), ("reserved", C.c_int32 * 6)]
 
 
 class SolveOpts(C.Structure):
@@ -57,7 +57,8 @@ class PrecondStats(C.Structure):
     _fields_ = [("n_sub", C.c_int32), ("n_coarse", C.c_int32), ("n_local_total", C.c_int64),
                 ("factor_entries", C.c_int64), ("coarse_entries", C.c_int64), ("levels_fwd", C.c_int32),
                 ("levels_bwd", C.c_int32), ("max_front", C.c_int32), ("n_supernodes", C.c_int32),
-                ("setup_seconds", C.c_double), ("factor_flops", C.c_double)]
+                ("setup_seconds", C.c_double), ("factor_flops", C.c_double), ("factor_c64", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class KernelProfile(C.Structure):
@@ -198,9 +199,9 @@ class Helm:
         self._check(self.lib.helm_matrix_csr(self.h, _ptr(ptr), _ptr(col), _ptr(val)))
         return ptr, col, val
 
-    def precond_setup(self, part, n_sub, overlap, coarse_xyz=None, coarse_tets=None, leaf_size=0):
+    def precond_setup(self, part, n_sub, overlap, coarse_xyz=None, coarse_tets=None, leaf_size=0, c64=False):
         part = np.ascontiguousarray(part, dtype=np.int32)
-        opts = PrecondOpts(int(leaf_size))
+        opts = PrecondOpts(int(leaf_size), 1 if c64 else 0)
         cm = None
         if coarse_xyz is not None:
             cm, keep = _mesh(coarse_xyz, coarse_tets, 1)
@@ -212,7 +213,7 @@ class Helm:
     def stats(self):
         s = PrecondStats()
         self._check(self.lib.helm_precond_stats_get(self.h, C.byref(s)))
-        return {f: getattr(s, f) for f, _ in PrecondStats._fields_}
+        return {f: getattr(s, f) for f, _ in PrecondStats._fields_ if f != "reserved"}
 
     def subdomain(self, i):
         n_i, nnz = C.c_int64(), C.c_int64()
@@ -270,11 +271,11 @@ class Helm:
                 for i, k in enumerate(KERNELS)}
 
 
-def from_workload(w, device=0, leaf_size=0):
+def from_workload(w, device=0, leaf_size=0, c64=False):
     """Helm context assembled and preconditioned for a workloads.Workload."""
     h = Helm(device)
     h.assemble(w.xyz, w.tets, w.order, w.c_tet, w.omega)
-    h.precond_setup(w.part, w.n_sub, w.overlap, w.coarse_xyz, w.coarse_tets, leaf_size)
+    h.precond_setup(w.part, w.n_sub, w.overlap, w.coarse_xyz, w.coarse_tets, leaf_size, c64)
     return h
 
 
