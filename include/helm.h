@@ -67,7 +67,8 @@ typedef struct helm_precond_opts {
                               (computed in complex128, rounded once); the
                               panel products still accumulate in FP64 and
                               the coarse factors stay complex128          */
-  int32_t reserved[6];
+  int32_t coarse_leaf_size;  /* leaf size of the coarse ordering, 0 = 256  */
+  int32_t reserved[5];
 } helm_precond_opts;
 
 enum {
@@ -75,7 +76,7 @@ enum {
 };
 
 typedef struct helm_solve_opts {
-  int32_t restart;         /* GMRES(m) restart length, 1..56, 0 = 50       */
+  int32_t restart;         /* GMRES(m) restart length, 1..50, 0 = 50       */
   int32_t maxit;           /* total Arnoldi steps per RHS, 0 = 1000        */
   int32_t flags;           /* HELM_SOLVE_*                                 */
   int32_t reserved;
@@ -170,7 +171,11 @@ int helm_coarse_get(const helm_ctx* ctx, int64_t* rowptr, int32_t* col, double* 
 /* --- Device operations (device pointers to c128[n]; stream = hipStream_t or
  *     NULL for the null stream).  Asynchronous with respect to the host. --- */
 
-/* y = A x  (complex CSR SpMV). */
+/* SpMV storage used by every product with A: 0 = the faster of the two as
+ * timed at helm_assemble (default), 1 = CSR, 2 = sliced ELL (64-row slices). */
+int helm_set_spmv(helm_ctx* ctx, int kind);
+
+/* y = A x  (complex SpMV). */
 int helm_apply_A(helm_ctx* ctx, const void* x, void* y, void* stream);
 
 /* z = M^{-1} r (two-level when a coarse mesh was given, else one-level). */

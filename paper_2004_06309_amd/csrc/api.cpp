@@ -223,6 +223,16 @@ int helm_coarse_get(const helm_ctx* ctx, int64_t* rowptr, int32_t* col, double* 
   });
 }
 
+int helm_set_spmv(helm_ctx* ctx, int kind) {
+  return guarded(ctx, [&](Ctx& c) {
+    need(c.device >= 0, HELM_ESTATE, "host-only context");
+    need(c.assembled, HELM_ESTATE, "call helm_assemble first");
+    need(kind >= 0 && kind <= 2, HELM_EINVAL, "kind must be 0, 1 or 2");
+    c.use_sell = kind == 0 ? c.sell_auto : kind == 2;
+    return HELM_OK;
+  });
+}
+
 int helm_apply_A(helm_ctx* ctx, const void* x, void* y, void* stream) {
   return guarded(ctx, [&](Ctx& c) {
     need(c.device >= 0, HELM_ESTATE, "host-only context");

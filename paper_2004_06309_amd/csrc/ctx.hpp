@@ -122,6 +122,13 @@ struct Ctx {
   Symbolic Esym;
   helm_precond_stats stats{};
   // device operators
+  int g_A = 8, g_ZT = 4, g_Zp = 4;  // lanes per row, picked by timing at setup
+  bool use_sell = false;             // sliced ELL in use
+  bool sell_auto = false;            // what the timing at setup picked
+  int64_t sell_nslices = 0;
+  DVec<int64_t> sell_off;
+  DVec<int32_t> sell_width, sell_perm, sell_col;
+  DVec<double> sell_val;
   DVec<int64_t> A_ptr;
   DVec<int32_t> A_col;
   DVec<double> A_val;

@@ -32,27 +32,31 @@ __device__ __forceinline__ void cfma(double& ar, double& ai, double2 a, double2 
 __device__ __forceinline__ double2 widen(double2 a) { return a; }
 __device__ __forceinline__ double2 widen(float2 a) { return make_double2((double)a.x, (double)a.y); }
 
-// Streams columns [k0, k1) of a tile (column-major, ld = nr) against vin,
-// eight independent loads in flight per lane.
+// Streams columns k0, k0 + ks, ... (< k1) of a tile (column-major, ld = nr)
+// against vin, eight independent loads in flight per lane.
 template <class PT>
-__device__ __forceinline__ void tile_dot(const PT* __restrict__ p, int nr, const double2* vin, int k0, int k1,
+__device__ __forceinline__ void tile_dot(const PT* __restrict__ p, int nr, const double2* vin, int k0, int k1, int ks,
                                         double& ar, double& ai) {
   int k = k0;
   double br = 0, bi = 0;
-  for (; k + 8 <= k1; k += 8) {
+  for (; k + 7 * ks < k1; k += 8 * ks) {
     PT a[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] = p[(int64_t)(k + u) * nr];
+    for (int u = 0; u < 8; ++u) a[u] = p[(int64_t)(k + u * ks) * nr];
 #pragma unroll
     for (int u = 0; u < 8; u += 2) {
-      cfma(ar, ai, widen(a[u]), vin[k + u]);
-      cfma(br, bi, widen(a[u + 1]), vin[k + u + 1]);
+      cfma(ar, ai, widen(a[u]), vin[k + u * ks]);
+      cfma(br, bi, widen(a[u + 1]), vin[k + (u + 1) * ks]);
     }
   }
-  for (; k < k1; ++k) cfma(ar, ai, widen(p[(int64_t)k * nr]), vin[k]);
+  for (; k < k1; k += ks) cfma(ar, ai, widen(p[(int64_t)k * nr]), vin[k]);
   ar += br;
   ai += bi;
 }
+
+// Lanes per tile row group: a tile with few rows spreads its columns over
+// 64 / R lane groups of R lanes (R >= nrows), so no lane idles.
+__device__ __forceinline__ int row_group(int nrows) { return nrows <= 16 ? 16 : (nrows <= 32 ? 32 : 64); }
 
 // Work split of a workgroup (4 waves) over the tiles of its task.
 struct Split {
@@ -92,7 +96,8 @@ __global__ __launch_bounds__(kWG) void fwd_level_kernel(const Task* __restrict__
     frow0 = b.sn_frow0[s];
   }
   double2* vt = vin + sp.my * sp.region;
-  const PT* __restrict__ P = reinterpret_cast<const PT*>(b.pf) + t.off + lane;
+  const int R = row_group(t.nrows), grp = lane / R, row_l = lane % R;
+  const PT* __restrict__ P = reinterpret_cast<const PT*>(b.pf) + t.off + row_l;
   const double2* __restrict__ ub = reinterpret_cast<const double2*>(b.ubuf);
   double ar = 0, ai = 0;
   // all waves of a workgroup run the same number of passes: one, unless the
@@ -113,10 +118,10 @@ __global__ __launch_bounds__(kWG) void fwd_level_kernel(const Task* __restrict__
       vt[k] = v;
     }
     __syncthreads();
-    if (sp.has && lane < t.nrows) {
+    if (sp.has && row_l < t.nrows) {
       const int per = (cn + sp.wpt - 1) / sp.wpt;
       const int k0 = sp.part * per, k1 = min(cn, k0 + per);
-      tile_dot(P + (int64_t)cb * t.nrows, t.nrows, vt, k0, k1, ar, ai);
+      tile_dot(P + (int64_t)cb * t.nrows, t.nrows, vt, k0 + grp, k1, 64 / R, ar, ai);
     }
     __syncthreads();
   }
@@ -124,10 +129,11 @@ __global__ __launch_bounds__(kWG) void fwd_level_kernel(const Task* __restrict__
   __syncthreads();
   if (sp.has && sp.part == 0 && lane < t.nrows) {
     double rr = 0, ii = 0;
-    for (int q = 0; q < sp.wpt; ++q) {
-      rr += red[wv + q][lane].x;
-      ii += red[wv + q][lane].y;
-    }
+    for (int q = 0; q < sp.wpt; ++q)
+      for (int g = lane; g < 64; g += R) {
+        rr += red[wv + q][g].x;
+        ii += red[wv + q][g].y;
+      }
     const int row = t.row0 + lane;
     if (row < w) {
       reinterpret_cast<double2*>(b.y)[c0 + row] = make_double2(rr, ii);
@@ -160,7 +166,8 @@ __global__ __launch_bounds__(kWG) void bwd_level_kernel(const Task* __restrict__
     roff = b.sn_roff[t.sn];
   }
   double2* vt = vin + sp.my * sp.region;
-  const PT* __restrict__ P = reinterpret_cast<const PT*>(b.pb) + t.off + lane;
+  const int R = row_group(t.nrows), grp = lane / R, row_l = lane % R;
+  const PT* __restrict__ P = reinterpret_cast<const PT*>(b.pb) + t.off + row_l;
   const double2* __restrict__ yv = reinterpret_cast<const double2*>(b.y);
   const double2* xv = reinterpret_cast<const double2*>(b.x);
   double ar = 0, ai = 0;
@@ -173,10 +180,10 @@ __global__ __launch_bounds__(kWG) void bwd_level_kernel(const Task* __restrict__
       vt[k] = c < w ? yv[c0 + c] : xv[b.rows[roff + (c - w)]];
     }
     __syncthreads();
-    if (sp.has && lane < t.nrows) {
+    if (sp.has && row_l < t.nrows) {
       const int per = (cn + sp.wpt - 1) / sp.wpt;
       const int k0 = sp.part * per, k1 = min(cn, k0 + per);
-      tile_dot(P + (int64_t)cb * t.nrows, t.nrows, vt, k0, k1, ar, ai);
+      tile_dot(P + (int64_t)cb * t.nrows, t.nrows, vt, k0 + grp, k1, 64 / R, ar, ai);
     }
     __syncthreads();
   }
@@ -184,10 +191,11 @@ __global__ __launch_bounds__(kWG) void bwd_level_kernel(const Task* __restrict__
   __syncthreads();
   if (sp.has && sp.part == 0 && lane < t.nrows) {
     double rr = 0, ii = 0;
-    for (int q = 0; q < sp.wpt; ++q) {
-      rr += red[wv + q][lane].x;
-      ii += red[wv + q][lane].y;
-    }
+    for (int q = 0; q < sp.wpt; ++q)
+      for (int g = lane; g < 64; g += R) {
+        rr += red[wv + q][g].x;
+        ii += red[wv + q][g].y;
+      }
     reinterpret_cast<double2*>(b.x)[c0 + t.row0 + lane] = make_double2(rr, ii);
   }
 }
@@ -216,6 +224,46 @@ __global__ __launch_bounds__(kWG) void spmv_kernel(int64_t n, const int64_t* __r
     } else {
       y[row] = make_double2(ar, ai);
     }
+  }
+}
+
+// Sliced ELL (slices of 64 rows = one wavefront): slice s holds rows
+// perm[64 s .. 64 s + 63], padded to the slice's longest row, stored
+// column-major inside the slice so each lane owns a row and every load of a
+// wave is one contiguous 1 KiB (values) / 256 B (columns) line.
+__global__ __launch_bounds__(kWG) void sell_kernel(int64_t n, int64_t nslices, const int64_t* __restrict__ soff,
+                                                   const int32_t* __restrict__ swidth,
+                                                   const int32_t* __restrict__ perm, const int32_t* __restrict__ col,
+                                                   const double2* __restrict__ val, const double2* __restrict__ x,
+                                                   const double2* __restrict__ bvec, double2* __restrict__ y) {
+  const int64_t s = (int64_t)blockIdx.x * (kWG / 64) + (threadIdx.x >> 6);
+  if (s >= nslices) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t slot = s * 64 + lane;
+  const int64_t off = soff[s] + lane;
+  const int wdt = swidth[s];
+  double ar = 0, ai = 0, br = 0, bi = 0;
+  int j = 0;
+  for (; j + 4 <= wdt; j += 4) {
+    const int c0 = col[off + (int64_t)(j + 0) * 64], c1 = col[off + (int64_t)(j + 1) * 64];
+    const int c2 = col[off + (int64_t)(j + 2) * 64], c3 = col[off + (int64_t)(j + 3) * 64];
+    const double2 v0 = val[off + (int64_t)(j + 0) * 64], v1 = val[off + (int64_t)(j + 1) * 64];
+    const double2 v2 = val[off + (int64_t)(j + 2) * 64], v3 = val[off + (int64_t)(j + 3) * 64];
+    cfma(ar, ai, v0, x[c0]);
+    cfma(br, bi, v1, x[c1]);
+    cfma(ar, ai, v2, x[c2]);
+    cfma(br, bi, v3, x[c3]);
+  }
+  for (; j < wdt; ++j) cfma(ar, ai, val[off + (int64_t)j * 64], x[col[off + (int64_t)j * 64]]);
+  ar += br;
+  ai += bi;
+  if (slot >= n) return;
+  const int row = perm[slot];
+  if (bvec) {
+    const double2 bb = bvec[row];
+    y[row] = make_double2(bb.x - ar, bb.y - ai);
+  } else {
+    y[row] = make_double2(ar, ai);
   }
 }
 
@@ -363,48 +411,87 @@ template <bool kUpdate, bool kDots, bool kNorm>
 __global__ __launch_bounds__(kWG) void gs_pass_kernel(int64_t n, const double2* __restrict__ V, int64_t ld, int ncol,
                                                       const double2* __restrict__ h, double2* __restrict__ w,
                                                       double2* __restrict__ partial) {
-  // dynamic LDS: tile[ncol][kGsRows + 1], then h, the new w and norms
+  // dynamic LDS: tile[ncol][kGsRows + 1], then h, the new w, and the
+  // per-wave partial sums of the update and of the dots
   extern __shared__ double2 lds[];
   double2 (*tile)[kGsRows + 1] = reinterpret_cast<double2 (*)[kGsRows + 1]>(lds);
   double2* hs = lds + (size_t)ncol * (kGsRows + 1);
   double2* wn = hs + kGsMaxCols;
-  double* red = reinterpret_cast<double*>(wn + kGsRows);
+  double2* ured = wn + kGsRows;         // [4][kGsRows]
+  double2* dred = ured + 4 * kGsRows;   // [4][kGsMaxCols]
+  double* red = reinterpret_cast<double*>(dred + 4 * kGsMaxCols);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int64_t i0 = (int64_t)blockIdx.x * kGsRows;
-  const int64_t i = i0 + lane;
-  const bool valid = i < n;
-  // stage the tile: wave q loads columns q, q+4, ...
-  for (int k = wv; k < ncol; k += 4) tile[k][lane] = valid ? V[(int64_t)k * ld + i] : make_double2(0.0, 0.0);
   if (kUpdate && tid < ncol) hs[tid] = h[tid];
-  __syncthreads();
-  if (tid < kGsRows) {
-    double2 wi = valid ? w[i] : make_double2(0.0, 0.0);
+  double dr = 0, di = 0;  // dots: column `lane`, rows [16 wv, 16 wv + 16) of every tile
+  double nrm = 0;         // norm: row `tid` of every tile
+  const int64_t ntiles = (n + kGsRows - 1) / kGsRows;
+  for (int64_t tb = blockIdx.x; tb < ntiles; tb += gridDim.x) {
+    const int64_t i = tb * kGsRows + lane;
+    const bool valid = i < n;
+    // stage the tile: wave q loads columns q, q+4, ..., four loads in flight
+    for (int kb = wv; kb < ncol; kb += 16) {
+      double2 a[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = kb + 4 * u;
+        a[u] = (k < ncol && valid) ? V[(int64_t)k * ld + i] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (kb + 4 * u < ncol) tile[kb + 4 * u][lane] = a[u];
+    }
+    __syncthreads();
     if (kUpdate) {
+      // wave q sums the columns k = q mod 4 of row `lane`
       double ur = 0, ui = 0;
-      for (int k = 0; k < ncol; ++k) cfma(ur, ui, tile[k][tid], hs[k]);
-      wi.x -= ur;
-      wi.y -= ui;
-      if (valid) w[i] = wi;
+      for (int k = wv; k < ncol; k += 4) cfma(ur, ui, tile[k][lane], hs[k]);
+      ured[wv * kGsRows + lane] = make_double2(ur, ui);
+      __syncthreads();
     }
-    wn[tid] = wi;
-    if (kNorm) red[tid] = wi.x * wi.x + wi.y * wi.y;
-  }
-  __syncthreads();
-  if (kDots && tid < ncol) {
-    double ar = 0, ai = 0;
-    for (int r = 0; r < kGsRows; ++r) {
-      const double2 v = tile[tid][r], x = wn[r];
-      ar = fma(v.x, x.x, ar);
-      ar = fma(v.y, x.y, ar);
-      ai = fma(v.x, x.y, ai);
-      ai = fma(-v.y, x.x, ai);
+    if (tid < kGsRows) {
+      double2 wi = valid ? w[i] : make_double2(0.0, 0.0);
+      if (kUpdate) {
+        for (int q = 0; q < 4; ++q) {
+          wi.x -= ured[q * kGsRows + tid].x;
+          wi.y -= ured[q * kGsRows + tid].y;
+        }
+        if (valid) w[i] = wi;
+      }
+      wn[tid] = wi;
+      if (kNorm) nrm = fma(wi.x, wi.x, fma(wi.y, wi.y, nrm));
     }
-    partial[(int64_t)blockIdx.x * ncol + tid] = make_double2(ar, ai);
+    __syncthreads();
+    if (kDots && lane < ncol) {
+      for (int r = wv * 16; r < wv * 16 + 16; ++r) {
+        const double2 v = tile[lane][r], x = wn[r];
+        dr = fma(v.x, x.x, dr);
+        dr = fma(v.y, x.y, dr);
+        di = fma(v.x, x.y, di);
+        di = fma(-v.y, x.x, di);
+      }
+    }
+    __syncthreads();  // the next tile overwrites tile and wn
   }
-  if (kNorm && tid == 0) {
-    double s = 0;
-    for (int r = 0; r < kGsRows; ++r) s += red[r];
-    partial[blockIdx.x] = make_double2(s, 0.0);
+  if (kDots) {
+    if (lane < ncol) dred[wv * kGsMaxCols + lane] = make_double2(dr, di);
+    __syncthreads();
+    if (tid < ncol) {
+      double ar = 0, ai = 0;
+      for (int q = 0; q < 4; ++q) {
+        ar += dred[q * kGsMaxCols + tid].x;
+        ai += dred[q * kGsMaxCols + tid].y;
+      }
+      partial[(int64_t)blockIdx.x * ncol + tid] = make_double2(ar, ai);
+    }
+  }
+  if (kNorm) {
+    if (tid < kGsRows) red[tid] = nrm;
+    __syncthreads();
+    if (tid == 0) {
+      double sum = 0;
+      for (int r = 0; r < kGsRows; ++r) sum += red[r];
+      partial[blockIdx.x] = make_double2(sum, 0.0);
+    }
   }
 }
 
@@ -525,20 +612,41 @@ void bwd_level(const Batch& b, int64_t task0, int64_t ntasks, bool coarse, hipSt
 }
 
 void spmv(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const double* x, const double* b,
-          double* y, hipStream_t s) {
+          double* y, int G, hipStream_t s) {
   if (n <= 0) return;
-  constexpr int G = 8;
-  spmv_kernel<G><<<blocks_for(n * G), kWG, 0, s>>>(n, ptr, col, reinterpret_cast<const double2*>(val),
-                                                    reinterpret_cast<const double2*>(x),
-                                                    reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(y));
+  auto v2 = reinterpret_cast<const double2*>(val);
+  auto x2 = reinterpret_cast<const double2*>(x);
+  auto b2 = reinterpret_cast<const double2*>(b);
+  auto y2 = reinterpret_cast<double2*>(y);
+  switch (G) {
+    case 4: spmv_kernel<4><<<blocks_for(n * 4), kWG, 0, s>>>(n, ptr, col, v2, x2, b2, y2); break;
+    case 16: spmv_kernel<16><<<blocks_for(n * 16), kWG, 0, s>>>(n, ptr, col, v2, x2, b2, y2); break;
+    case 32: spmv_kernel<32><<<blocks_for(n * 32), kWG, 0, s>>>(n, ptr, col, v2, x2, b2, y2); break;
+    case 64: spmv_kernel<64><<<blocks_for(n * 64), kWG, 0, s>>>(n, ptr, col, v2, x2, b2, y2); break;
+    default: spmv_kernel<8><<<blocks_for(n * 8), kWG, 0, s>>>(n, ptr, col, v2, x2, b2, y2); break;
+  }
+}
+
+void sell_spmv(int64_t n, int64_t nslices, const int64_t* soff, const int32_t* swidth, const int32_t* perm,
+               const int32_t* col, const double* val, const double* x, const double* b, double* y, hipStream_t s) {
+  if (n <= 0) return;
+  sell_kernel<<<(unsigned)((nslices + 3) / 4), kWG, 0, s>>>(
+      n, nslices, soff, swidth, perm, col, reinterpret_cast<const double2*>(val), reinterpret_cast<const double2*>(x),
+      reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(y));
 }
 
 void spmv_real(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const double* x, double* y,
-               hipStream_t s) {
+               int G, hipStream_t s) {
   if (n <= 0) return;
-  constexpr int G = 4;
-  spmv_real_kernel<G><<<blocks_for(n * G), kWG, 0, s>>>(n, ptr, col, val, reinterpret_cast<const double2*>(x),
-                                                         reinterpret_cast<double2*>(y));
+  auto x2 = reinterpret_cast<const double2*>(x);
+  auto y2 = reinterpret_cast<double2*>(y);
+  switch (G) {
+    case 8: spmv_real_kernel<8><<<blocks_for(n * 8), kWG, 0, s>>>(n, ptr, col, val, x2, y2); break;
+    case 16: spmv_real_kernel<16><<<blocks_for(n * 16), kWG, 0, s>>>(n, ptr, col, val, x2, y2); break;
+    case 32: spmv_real_kernel<32><<<blocks_for(n * 32), kWG, 0, s>>>(n, ptr, col, val, x2, y2); break;
+    case 64: spmv_real_kernel<64><<<blocks_for(n * 64), kWG, 0, s>>>(n, ptr, col, val, x2, y2); break;
+    default: spmv_real_kernel<4><<<blocks_for(n * 4), kWG, 0, s>>>(n, ptr, col, val, x2, y2); break;
+  }
 }
 
 void prolong(int64_t n, const int64_t* ptr, const int32_t* idx, const double* w, const double* xl, const double* q,
@@ -575,12 +683,17 @@ void gs_update(int64_t n, const double* V, int64_t ld, int ncol, const double* h
                                                            reinterpret_cast<double2*>(w));
 }
 
-int gs_tiles(int64_t n) { return (int)((n + kGsRows - 1) / kGsRows); }
+int gs_tiles(int64_t n) {
+  const int64_t t = (n + kGsRows - 1) / kGsRows;
+  return (int)(t < 2048 ? t : 2048);  // workgroups; each loops over 64-row tiles
+}
 
 void gs_pass(int mode, int64_t n, const double* V, int64_t ld, int ncol, const double* h, double* w, double* partial,
              hipStream_t s) {
   const unsigned nb = (unsigned)gs_tiles(n);
-  const size_t lds = sizeof(double2) * ((size_t)ncol * (kGsRows + 1) + kGsMaxCols + kGsRows) + sizeof(double) * kGsRows;
+  const size_t lds = sizeof(double2) * ((size_t)ncol * (kGsRows + 1) + kGsMaxCols + kGsRows + 4 * kGsRows +
+                                        4 * kGsMaxCols) +
+                     sizeof(double) * kGsRows;
   auto V2 = reinterpret_cast<const double2*>(V);
   auto h2 = reinterpret_cast<const double2*>(h);
   auto w2 = reinterpret_cast<double2*>(w);

@@ -54,12 +54,16 @@ void bwd_level(const Batch& b, int64_t task0, int64_t ntasks, bool coarse, hipSt
 // Waves per tile chosen for a tile with ncols input columns.
 int waves_per_tile(int ncols);
 
-// y = A x, or y = b - A x when b != nullptr (complex CSR).
+// y = A x, or y = b - A x when b != nullptr (complex CSR); G lanes per row
+// (4, 8, 16, 32 or 64).
 void spmv(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const double* x, const double* b,
-          double* y, hipStream_t s);
-// y = A x with a real CSR matrix and complex vectors.
+          double* y, int G, hipStream_t s);
+// Same product from the sliced-ELL copy of A (64-row slices).
+void sell_spmv(int64_t n, int64_t nslices, const int64_t* soff, const int32_t* swidth, const int32_t* perm,
+               const int32_t* col, const double* val, const double* x, const double* b, double* y, hipStream_t s);
+// y = A x with a real CSR matrix and complex vectors; G lanes per row.
 void spmv_real(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const double* x, double* y,
-               hipStream_t s);
+               int G, hipStream_t s);
 // z[g] = sum_p w[p] xl[idx[p]] over p in [ptr[g], ptr[g+1]) (+ q[g] if q).
 void prolong(int64_t n, const int64_t* ptr, const int32_t* idx, const double* w, const double* xl, const double* q,
              double* z, hipStream_t s);

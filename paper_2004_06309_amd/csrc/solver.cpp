@@ -257,8 +257,12 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
     lev.assign(1, 0);
     for (auto& l : levels) {
       bytes.push_back(level_bytes(l, fwd));
+      // widest class first, larger tiles first: the level's tail holds the
+      // shortest workgroups
       std::stable_sort(l.begin(), l.end(), [](const dev::Tile& a, const dev::Tile& b) {
-        return dev::waves_per_tile(a.ncols) < dev::waves_per_tile(b.ncols);
+        const int wa = dev::waves_per_tile(a.ncols), wb = dev::waves_per_tile(b.ncols);
+        if (wa != wb) return wa > wb;
+        return (int64_t)a.nrows * a.ncols > (int64_t)b.nrows * b.ncols;
       });
       size_t q = 0;
       while (q < l.size()) {
@@ -383,18 +387,119 @@ double sum(const std::vector<double>& v) { return std::accumulate(v.begin(), v.e
 
 }  // namespace
 
-void upload_matrix(Ctx& c) {
-  c.A_ptr.upload(c.D.A.ptr);
-  c.A_col.upload(c.D.A.col);
-  c.A_val.upload(reinterpret_cast<const double*>(c.D.A.val.data()), 2 * c.D.A.val.size());
+namespace {
+
+// Times launch(G) for every candidate (one warm-up, then three timed runs on
+// the null stream) and returns the fastest G: the SpMV tile shape is tuned
+// on the device for the matrix at hand.
+template <class F>
+int pick_lanes_per_row(const std::vector<int>& cands, F&& launch) {
+  hipEvent_t e0, e1;
+  HELM_HIP(hipEventCreate(&e0));
+  HELM_HIP(hipEventCreate(&e1));
+  int best = cands[0];
+  float best_ms = 1e30f;
+  for (int G : cands) {
+    launch(G);
+    HELM_HIP(hipEventRecord(e0, nullptr));
+    for (int r = 0; r < 3; ++r) launch(G);
+    HELM_HIP(hipEventRecord(e1, nullptr));
+    HELM_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    HELM_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = G;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return best;
 }
+
+}  // namespace
+
+void upload_matrix(Ctx& c) {
+  const Csr& A = c.D.A;
+  const int64_t n = A.n;
+  c.A_ptr.upload(A.ptr);
+  c.A_col.upload(A.col);
+  c.A_val.upload(reinterpret_cast<const double*>(A.val.data()), 2 * A.val.size());
+  // sliced-ELL copy: rows sorted by length (longest first) inside windows of
+  // 1024 rows, so a slice's rows have similar lengths and stay close in x
+  const int64_t ns = (n + 63) / 64;
+  std::vector<int32_t> perm(ns * 64, 0);
+  for (int64_t w0 = 0; w0 < n; w0 += 1024) {
+    const int64_t w1 = std::min<int64_t>(n, w0 + 1024);
+    std::vector<int32_t> r(w1 - w0);
+    std::iota(r.begin(), r.end(), (int32_t)w0);
+    std::stable_sort(r.begin(), r.end(), [&](int32_t a, int32_t b) {
+      return A.ptr[a + 1] - A.ptr[a] > A.ptr[b + 1] - A.ptr[b];
+    });
+    std::copy(r.begin(), r.end(), perm.begin() + w0);
+  }
+  std::vector<int64_t> soff(ns + 1, 0);
+  std::vector<int32_t> swidth(ns, 0);
+  for (int64_t s = 0; s < ns; ++s) {
+    int32_t wd = 0;
+    for (int64_t q = s * 64; q < std::min<int64_t>(n, s * 64 + 64); ++q)
+      wd = std::max<int32_t>(wd, (int32_t)(A.ptr[perm[q] + 1] - A.ptr[perm[q]]));
+    swidth[s] = wd;
+    soff[s + 1] = soff[s] + 64 * (int64_t)wd;
+  }
+  std::vector<int32_t> scol(soff[ns], 0);
+  std::vector<cplx> sval(soff[ns], cplx(0, 0));
+  for (int64_t s = 0; s < ns; ++s)
+    for (int64_t q = s * 64; q < std::min<int64_t>(n, s * 64 + 64); ++q) {
+      const int64_t row = perm[q], lane = q - s * 64;
+      for (int64_t j = 0; j < swidth[s]; ++j) {
+        const int64_t p = A.ptr[row] + j;
+        const bool real = p < A.ptr[row + 1];
+        scol[soff[s] + j * 64 + lane] = real ? A.col[p] : (int32_t)row;
+        sval[soff[s] + j * 64 + lane] = real ? A.val[p] : cplx(0, 0);
+      }
+    }
+  c.sell_nslices = ns;
+  c.sell_off.upload(soff);
+  c.sell_width.upload(swidth);
+  c.sell_perm.upload(perm);
+  c.sell_col.upload(scol);
+  c.sell_val.upload(reinterpret_cast<const double*>(sval.data()), 2 * sval.size());
+  DVec<double> x, y;
+  x.alloc(2 * n);
+  y.alloc(2 * n);
+  HELM_HIP(hipMemset(x.p, 0, sizeof(double) * 2 * n));
+  // G = 0 stands for the sliced-ELL kernel
+  const int best = pick_lanes_per_row({0, 4, 8, 16, 32}, [&](int G) {
+    if (G == 0)
+      dev::sell_spmv(n, ns, c.sell_off.p, c.sell_width.p, c.sell_perm.p, c.sell_col.p, c.sell_val.p, x.p, nullptr,
+                     y.p, nullptr);
+    else
+      dev::spmv(n, c.A_ptr.p, c.A_col.p, c.A_val.p, x.p, nullptr, y.p, G, nullptr);
+  });
+  c.use_sell = c.sell_auto = best == 0;
+  c.g_A = best == 0 ? 8 : best;
+  HELM_HIP(hipDeviceSynchronize());
+}
+
+namespace {
+
+void spmv_A(Ctx& c, const double* x, const double* b, double* y, hipStream_t s) {
+  if (c.use_sell)
+    dev::sell_spmv(c.D.n, c.sell_nslices, c.sell_off.p, c.sell_width.p, c.sell_perm.p, c.sell_col.p, c.sell_val.p, x,
+                   b, y, s);
+  else
+    dev::spmv(c.D.n, c.A_ptr.p, c.A_col.p, c.A_val.p, x, b, y, c.g_A, s);
+}
+
+}  // namespace
 
 void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overlap, const helm_mesh* coarse,
                    const helm_precond_opts* opts) {
   auto t0 = std::chrono::steady_clock::now();
   c.free_precond();
   const bool on_device = c.device >= 0;
-  const int leaf = opts && opts->leaf_size > 0 ? opts->leaf_size : 64;
+  const int leaf = opts && opts->leaf_size > 0 ? opts->leaf_size : 48;
   c.n_sub = n_sub;
   c.overlap = overlap;
   build_subdomains(c.D, tet_part, n_sub, overlap, c.subs);
@@ -458,7 +563,8 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
     coarse_interpolation(c.D, *coarse, c.Z, ccoords);
     transpose_real(c.Z, c.ZT);
     galerkin(c.D.A, c.Z, c.ZT, c.E);
-    nested_dissection(c.E, ccoords, leaf, c.Esym);
+    const int cleaf = opts && opts->coarse_leaf_size > 0 ? opts->coarse_leaf_size : 256;
+    nested_dissection(c.E, ccoords, cleaf, c.Esym);
     std::vector<int64_t> ident(c.E.n);
     std::iota(ident.begin(), ident.end(), 0);
     BatchHost cb;
@@ -488,6 +594,16 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
       c.ZT_col.upload(c.ZT.col);
       c.ZT_val.upload(c.ZT.val);
       c.cvec.alloc(2 * c.E.n);
+      DVec<double> x, y;
+      x.alloc(2 * c.D.n);
+      y.alloc(2 * c.D.n);
+      HELM_HIP(hipMemset(x.p, 0, sizeof(double) * 2 * c.D.n));
+      c.g_ZT = pick_lanes_per_row({4, 8, 16, 32, 64}, [&](int G) {
+        dev::spmv_real(c.ZT.n, c.ZT_ptr.p, c.ZT_col.p, c.ZT_val.p, x.p, y.p, G, nullptr);
+      });
+      c.g_Zp = pick_lanes_per_row({4, 8}, [&](int G) {
+        dev::spmv_real(c.D.n, c.Zp_ptr.p, c.Zp_col.p, c.Zp_val.p, x.p, y.p, G, nullptr);
+      });
     }
   }
   if (on_device) {
@@ -508,16 +624,16 @@ double spmv_bytes(const Ctx& c, bool residual) {
 void apply_A(Ctx& c, const double* x, double* y, hipStream_t s) {
   const bool p = c.prof.on;
   if (p) c.prof.begin(s);
-  dev::spmv(c.D.n, c.A_ptr.p, c.A_col.p, c.A_val.p, x, nullptr, y, s);
+  spmv_A(c, x, nullptr, y, s);
   if (p) c.prof.end(HELM_K_SPMV, spmv_bytes(c, false), s);
 }
 
 void apply_coarse(Ctx& c, const double* r, double* q, hipStream_t s) {
   const bool p = c.prof.on;
   if (p) c.prof.begin(s);
-  dev::spmv_real(c.ZT.n, c.ZT_ptr.p, c.ZT_col.p, c.ZT_val.p, r, c.cvec.p, s);
+  dev::spmv_real(c.ZT.n, c.ZT_ptr.p, c.ZT_col.p, c.ZT_val.p, r, c.cvec.p, c.g_ZT, s);
   batch_solve(c.coarse, c.cvec.p, s, &c.prof, false);
-  dev::spmv_real(c.D.n, c.Zp_ptr.p, c.Zp_col.p, c.Zp_val.p, c.coarse.x.p, q, s);
+  dev::spmv_real(c.D.n, c.Zp_ptr.p, c.Zp_col.p, c.Zp_val.p, c.coarse.x.p, q, c.g_Zp, s);
   if (p) {
     const double zb = 2.0 * (12.0 * (double)c.Z.col.size() + 8.0 * c.D.n) + 16.0 * (c.D.n + c.E.n);
     c.prof.end(HELM_K_COARSE, zb + sum(c.coarse.bytes_f) + sum(c.coarse.bytes_b), s);
@@ -540,7 +656,7 @@ void apply_precond(Ctx& c, const double* r, double* z, hipStream_t s) {
   apply_coarse(c, r, c.q.p, s);
   const bool p = c.prof.on;
   if (p) c.prof.begin(s);
-  dev::spmv(c.D.n, c.A_ptr.p, c.A_col.p, c.A_val.p, c.q.p, r, c.t.p, s);  // t = r - A q
+  spmv_A(c, c.q.p, r, c.t.p, s);  // t = r - A q
   if (p) c.prof.end(HELM_K_SPMV, spmv_bytes(c, true), s);
   apply_oras(c, c.t.p, z, c.q.p, s);
 }
@@ -580,7 +696,7 @@ int solve(Ctx& c, int32_t nrhs, const double* B, double tol, const helm_solve_op
   const int m = opts && opts->restart > 0 ? opts->restart : 50;
   const int maxit = opts && opts->maxit > 0 ? opts->maxit : 1000;
   const bool x0 = opts && (opts->flags & HELM_SOLVE_X0);
-  if (m > 56) fail(HELM_EINVAL, "restart must be <= 56");
+  if (m > 50) fail(HELM_EINVAL, "restart must be <= 50");
   if (!(tol > 0)) fail(HELM_EINVAL, "tol must be positive");
   ensure_gmres(c, m);
   const int64_t n = c.D.n;
@@ -610,7 +726,7 @@ int solve(Ctx& c, int32_t nrhs, const double* B, double tol, const helm_solve_op
     bool conv = false;
     double rel = 0;
     while (true) {
-      dev::spmv(n, c.A_ptr.p, c.A_col.p, c.A_val.p, x, b, V, s);  // r = b - A x
+      spmv_A(c, x, b, V, s);  // r = b - A x
       const double beta = device_norm(c, V, s);
       if (!std::isfinite(beta)) fail(HELM_ENUMERIC, "non-finite residual");
       rel = beta / bnorm;

@@ -41,7 +41,8 @@ class Mesh(C.Structure):
 
 
 class PrecondOpts(C.Structure):
-    _fields_ = [("leaf_size", C.c_int32), ("factor_c64", C.c_int32), ("reserved", C.c_int32 * 6)]
+    _fields_ = [("leaf_size", C.c_int32), ("factor_c64", C.c_int32), ("coarse_leaf_size", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
 
 
 class SolveOpts(C.Structure):
@@ -85,6 +86,7 @@ EXPORTS = {
                                      C.c_void_p]),
     "helm_coarse_nnz": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "helm_coarse_get": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "helm_set_spmv": (C.c_int, [C.c_void_p, C.c_int]),
     "helm_apply_A": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "helm_apply_precond": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "helm_apply_oras": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -199,9 +201,10 @@ class Helm:
         self._check(self.lib.helm_matrix_csr(self.h, _ptr(ptr), _ptr(col), _ptr(val)))
         return ptr, col, val
 
-    def precond_setup(self, part, n_sub, overlap, coarse_xyz=None, coarse_tets=None, leaf_size=0, c64=False):
+    def precond_setup(self, part, n_sub, overlap, coarse_xyz=None, coarse_tets=None, leaf_size=0, c64=False,
+                      coarse_leaf_size=0):
         part = np.ascontiguousarray(part, dtype=np.int32)
-        opts = PrecondOpts(int(leaf_size), 1 if c64 else 0)
+        opts = PrecondOpts(int(leaf_size), 1 if c64 else 0, int(coarse_leaf_size))
         cm = None
         if coarse_xyz is not None:
             cm, keep = _mesh(coarse_xyz, coarse_tets, 1)
@@ -237,6 +240,10 @@ class Helm:
         return nc.value, (ptr, col, val)
 
     # ---- device operations (torch complex128 tensors) -----------------------
+    def set_spmv(self, kind):
+        """0: faster of CSR / sliced ELL as timed at assembly, 1: CSR, 2: sliced ELL."""
+        self._check(self.lib.helm_set_spmv(self.h, int(kind)))
+
     def apply_A(self, x, y, stream=None):
         self._check(self.lib.helm_apply_A(self.h, _dev_ptr(x), _dev_ptr(y), _stream(stream)))
 

@@ -1,0 +1,90 @@
+"""Summarise rocprofv3 CSV output of a bench run into a short text table.
+
+    python -m paper_2004_06309_amd.rocprof_summary --trace DIR/mid_kernel_trace.csv \
+        [--fetch DIR/mid_counter_collection.csv --write DIR/mid_counter_collection.csv \
+         --copy-fetch ... --copy-write ...] --out profiles/<name>.md --command "<cmd>"
+
+Kernel-trace statistics are grouped by kernel (template arguments kept, so
+fine and coarse level solves are separate rows).  With counter files, the
+per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) are scaled by what the same
+counters read for a device copy of known size, and averaged per dispatch.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import json
+import re
+
+
+def short_name(name: str) -> str:
+    n = name.replace("(anonymous namespace)::", "")
+    n = re.sub(r"HIP_vector_type<(\w+), 2u>", r"\g<1>2", n)
+    m = re.match(r"(?:void )?(?:[\w:]+::)?(\w+(?:<[^()]*>)?)\(", n)
+    return m.group(1) if m else n[:60]
+
+
+def trace_stats(path):
+    d = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        d[short_name(r["Kernel_Name"])].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    return d
+
+
+def counter_means(path, counter):
+    acc = collections.defaultdict(lambda: [0, 0.0])
+    for r in csv.DictReader(open(path)):
+        if r.get("Counter_Name") != counter:
+            continue
+        k = short_name(r["Kernel_Name"])
+        acc[k][0] += 1
+        acc[k][1] += float(r["Counter_Value"])
+    return {k: v[1] / v[0] for k, v in acc.items()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--copy-fetch")
+    ap.add_argument("--copy-write")
+    ap.add_argument("--copy-bytes", type=float, default=2.0 ** 30)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--command", required=True)
+    ap.add_argument("--json-out")
+    args = ap.parse_args()
+    st = trace_stats(args.trace)
+    total = sum(sum(v) for v in st.values())
+    lines = [f"# rocprofv3 kernel summary", "", f"Command: `{args.command}`", "",
+             "| kernel | calls | avg us | total ms | share |", "|---|---|---|---|---|"]
+    for k in sorted(st, key=lambda k: -sum(st[k]))[:24]:
+        v = st[k]
+        lines.append(f"| `{k}` | {len(v)} | {sum(v) / len(v) / 1e3:.1f} | {sum(v) / 1e6:.2f} | "
+                     f"{100 * sum(v) / total:.1f}% |")
+    out = {}
+    if args.fetch and args.write and args.copy_fetch and args.copy_write:
+        cf = max(counter_means(args.copy_fetch, "FETCH_SIZE").values())
+        cw = max(counter_means(args.copy_write, "WRITE_SIZE").values())
+        sf = args.copy_bytes / (cf * 1024.0)
+        sw = args.copy_bytes / (cw * 1024.0)
+        fe = counter_means(args.fetch, "FETCH_SIZE")
+        wr = counter_means(args.write, "WRITE_SIZE")
+        lines += ["", f"HBM traffic per dispatch (FETCH_SIZE x {sf:.3f}, WRITE_SIZE x {sw:.3f}; factors from a "
+                      f"{args.copy_bytes / 2**30:.0f} GiB device copy):", "",
+                  "| kernel | fetch MB | write MB |", "|---|---|---|"]
+        for k in sorted(fe, key=lambda k: -fe[k])[:16]:
+            f = fe[k] * 1024 * sf
+            w = wr.get(k, 0.0) * 1024 * sw
+            out[k] = {"fetch_bytes": f, "write_bytes": w}
+            lines.append(f"| `{k}` | {f / 1e6:.2f} | {w / 1e6:.2f} |")
+        out["_scale"] = {"fetch": sf, "write": sw}
+    open(args.out, "w").write("\n".join(lines) + "\n")
+    if args.json_out:
+        json.dump(out, open(args.json_out, "w"), indent=1)
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main()

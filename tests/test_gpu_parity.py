@@ -72,11 +72,14 @@ def rand_vec(n, seed):
 
 
 def test_spmv_parity(pair):
+    """Both SpMV storages (CSR, sliced ELL) against the oracle's A."""
     name, w, P, b, M, h = pair
     x = rand_vec(P.n, 1)
     y = torch.empty(P.n, dtype=torch.complex128, device=DEV)
-    h.apply_A(dvec(x), y)
-    assert rel(host(y), P.A @ x) <= 1e-13
+    for kind in (1, 2, 0):
+        h.set_spmv(kind)
+        h.apply_A(dvec(x), y)
+        assert rel(host(y), P.A @ x) <= 1e-13, kind
 
 
 def test_oras_parity(pair):
