@@ -79,7 +79,10 @@ typedef struct helm_solve_opts {
   int32_t restart;         /* GMRES(m) restart length, 1..50, 0 = 50       */
   int32_t maxit;           /* total Arnoldi steps per RHS, 0 = 1000        */
   int32_t flags;           /* HELM_SOLVE_*                                 */
-  int32_t reserved;
+  int32_t block;           /* right-hand sides advanced together (pseudo-
+                              block GMRES, one pass over A and the factors
+                              per step for the whole block), 1..16; 0 or 1
+                              = one at a time                             */
 } helm_solve_opts;
 
 typedef struct helm_solve_info {

@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libhelm.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HOST_SOURCES = ["fem.cpp", "decomp.cpp", "order.cpp", "factor.cpp", "coarse.cpp", "solver.cpp", "api.cpp"]
-HIP_SOURCES = ["device.hip"]
+HIP_SOURCES = ["device.hip", "device_block.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result", f"-I{ROCM}/include", f"-I{ROOT}/include"]
 HOST_FLAGS = COMMON + ["-D__HIP_PLATFORM_AMD__", "-fopenmp", "-mavx2", "-mfma", "-ffp-contract=fast"]

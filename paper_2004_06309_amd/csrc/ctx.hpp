@@ -56,6 +56,7 @@ struct BatchHost {
   std::vector<dev::Task> kf, kb;      // workgroup tasks
   std::vector<int64_t> lev_f, lev_b;  // task ranges per level
   std::vector<double> bytes_f, bytes_b;  // algorithmic bytes per level
+  std::vector<double> pbytes_f, pbytes_b;  // of which panel bytes
   int64_t nf = 0, nb = 0, nu = 0;     // panel entries (fwd, bwd), update entries
   int32_t max_front = 0;
   double flops = 0;
@@ -73,6 +74,11 @@ struct BatchDev {
   std::vector<int64_t> lev_f, lev_b;
   int64_t npos = 0;
   std::vector<double> bytes_f, bytes_b;  // algorithmic bytes per level
+  std::vector<double> pbytes_f, pbytes_b;  // of which panel bytes
+  std::vector<int64_t> tiles_f, tiles_b;   // tile range of every level
+  // multi-right-hand-side work vectors (interleaved, widest block so far)
+  int blk_S = 0;
+  DVec<double> ubuf_b, y_b, x_b;
   dev::Batch view() const;
   void reset() {
     for (auto* v : {&c0, &w, &uoff, &frow0, &rows, &bidx, &fcon_ptr, &fcon_idx}) v->reset();
@@ -89,6 +95,14 @@ struct BatchDev {
     lev_b.clear();
     bytes_f.clear();
     bytes_b.clear();
+    pbytes_f.clear();
+    pbytes_b.clear();
+    tiles_f.clear();
+    tiles_b.clear();
+    blk_S = 0;
+    ubuf_b.reset();
+    y_b.reset();
+    x_b.reset();
     npos = 0;
   }
 };
@@ -146,6 +160,11 @@ struct Ctx {
   DVec<double> V, Zk, w, partial, hcol, htmp, nrm, ydev;
   double* h_host = nullptr;  // pinned
   Profiler prof;
+  // pseudo-block GMRES work (per right-hand side of a block)
+  int blk_m = 0, blk_cap = 0;
+  DVec<double> bV[dev::kMaxBlock], bZ[dev::kMaxBlock], bw[dev::kMaxBlock];
+  DVec<double> bhcol, bhtmp, bpartial, by, bX, bZb, bW, bq, bt, bcvec;
+  double* bh_host = nullptr;  // pinned, kMaxBlock x (m + 2) complex
   ~Ctx();
   void free_precond();
 };

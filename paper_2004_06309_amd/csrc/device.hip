@@ -236,7 +236,12 @@ __global__ __launch_bounds__(kWG) void sell_kernel(int64_t n, int64_t nslices, c
                                                    const int32_t* __restrict__ perm, const int32_t* __restrict__ col,
                                                    const double2* __restrict__ val, const double2* __restrict__ x,
                                                    const double2* __restrict__ bvec, double2* __restrict__ y) {
-  const int64_t s = (int64_t)blockIdx.x * (kWG / 64) + (threadIdx.x >> 6);
+  // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so
+  // workgroup b works on block (b % 8) * per + b / 8 and every XCD sweeps a
+  // contiguous eighth of the rows (their x entries stay in its own L2)
+  const unsigned per = gridDim.x / 8;
+  const int64_t vb = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int64_t s = vb * (kWG / 64) + (threadIdx.x >> 6);
   if (s >= nslices) return;
   const int lane = threadIdx.x & 63;
   const int64_t slot = s * 64 + lane;
@@ -314,51 +319,12 @@ __global__ __launch_bounds__(kWG) void prolong_kernel(int64_t n, const int64_t* 
 
 // ---- Gram-Schmidt ----------------------------------------------------------
 
-constexpr int kGsCols = 8;
-
-__global__ __launch_bounds__(kWG) void gs_dots_partial_kernel(int64_t n, const double2* __restrict__ V, int64_t ld,
-                                                              int ncol, const double2* __restrict__ w,
-                                                              double2* __restrict__ partial) {
-  __shared__ double2 sm[kGsCols][kWG];
-  const int tid = threadIdx.x;
-  for (int k0 = 0; k0 < ncol; k0 += kGsCols) {
-    const int kc = min(kGsCols, ncol - k0);
-    double ar[kGsCols], ai[kGsCols];
-#pragma unroll
-    for (int c = 0; c < kGsCols; ++c) ar[c] = ai[c] = 0;
-    for (int64_t i = (int64_t)blockIdx.x * kWG + tid; i < n; i += (int64_t)gridDim.x * kWG) {
-      const double2 wi = w[i];
-#pragma unroll
-      for (int c = 0; c < kGsCols; ++c)
-        if (c < kc) {
-          const double2 v = V[(int64_t)(k0 + c) * ld + i];
-          // conj(v) * wi
-          ar[c] = fma(v.x, wi.x, ar[c]);
-          ar[c] = fma(v.y, wi.y, ar[c]);
-          ai[c] = fma(v.x, wi.y, ai[c]);
-          ai[c] = fma(-v.y, wi.x, ai[c]);
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < kGsCols; ++c) sm[c][tid] = make_double2(ar[c], ai[c]);
-    __syncthreads();
-    for (int st = kWG / 2; st > 0; st >>= 1) {
-      if (tid < st)
-        for (int c = 0; c < kc; ++c) {
-          sm[c][tid].x += sm[c][tid + st].x;
-          sm[c][tid].y += sm[c][tid + st].y;
-        }
-      __syncthreads();
-    }
-    if (tid < kc) partial[(int64_t)blockIdx.x * ncol + k0 + tid] = sm[tid][0];
-    __syncthreads();
-  }
-}
-
-__global__ __launch_bounds__(kWG) void gs_dots_final_kernel(const double2* __restrict__ partial, int nblk, int ncol,
-                                                            double2* __restrict__ h, double2* __restrict__ hacc,
+__global__ __launch_bounds__(kWG) void gs_dots_final_kernel(PtrSetC parts, int nblk, int ncol, PtrSet hs_, PtrSet haccs,
                                                             int accumulate) {
   __shared__ double2 sm[kWG];
+  const double2* __restrict__ partial = reinterpret_cast<const double2*>(parts.p[blockIdx.y]);
+  double2* __restrict__ h = reinterpret_cast<double2*>(hs_.p[blockIdx.y]);
+  double2* __restrict__ hacc = reinterpret_cast<double2*>(haccs.p[blockIdx.y]);
   const int k = blockIdx.x, tid = threadIdx.x;
   double ar = 0, ai = 0;
   for (int b = tid; b < nblk; b += kWG) {
@@ -386,19 +352,6 @@ __global__ __launch_bounds__(kWG) void gs_dots_final_kernel(const double2* __res
   }
 }
 
-__global__ __launch_bounds__(kWG) void gs_update_kernel(int64_t n, const double2* __restrict__ V, int64_t ld, int ncol,
-                                                        const double2* __restrict__ h, double2* __restrict__ w) {
-  __shared__ double2 hs[1024];
-  for (int k = threadIdx.x; k < ncol; k += kWG) hs[k] = h[k];
-  __syncthreads();
-  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWG) {
-    double ar = 0, ai = 0;
-    for (int k = 0; k < ncol; ++k) cfma(ar, ai, V[(int64_t)k * ld + i], hs[k]);
-    double2 wi = w[i];
-    w[i] = make_double2(wi.x - ar, wi.y - ai);
-  }
-}
-
 // One CGS2 pass over a 64-row tile of V (all ncol columns staged in LDS,
 // padded to avoid bank conflicts):
 //   kUpdate: w -= V h                (h: device, ncol entries)
@@ -408,9 +361,13 @@ constexpr int kGsRows = 64;
 constexpr int kGsMaxCols = 64;
 
 template <bool kUpdate, bool kDots, bool kNorm>
-__global__ __launch_bounds__(kWG) void gs_pass_kernel(int64_t n, const double2* __restrict__ V, int64_t ld, int ncol,
-                                                      const double2* __restrict__ h, double2* __restrict__ w,
-                                                      double2* __restrict__ partial) {
+__global__ __launch_bounds__(kWG) void gs_pass_kernel(int64_t n, PtrSetC Vs, int64_t ld, int ncol, PtrSetC hs_,
+                                                      PtrSet ws, PtrSet parts) {
+  // right-hand side blockIdx.y
+  const double2* __restrict__ V = reinterpret_cast<const double2*>(Vs.p[blockIdx.y]);
+  const double2* __restrict__ h = reinterpret_cast<const double2*>(hs_.p[blockIdx.y]);
+  double2* __restrict__ w = reinterpret_cast<double2*>(ws.p[blockIdx.y]);
+  double2* __restrict__ partial = reinterpret_cast<double2*>(parts.p[blockIdx.y]);
   // dynamic LDS: tile[ncol][kGsRows + 1], then h, the new w, and the
   // per-wave partial sums of the update and of the dots
   extern __shared__ double2 lds[];
@@ -495,9 +452,10 @@ __global__ __launch_bounds__(kWG) void gs_pass_kernel(int64_t n, const double2* 
   }
 }
 
-__global__ __launch_bounds__(kWG) void norm_final2_kernel(const double2* __restrict__ partial, int nblk,
-                                                          double2* __restrict__ out) {
+__global__ __launch_bounds__(kWG) void norm_final2_kernel(PtrSetC parts, int nblk, PtrSet outs) {
   __shared__ double sm[kWG];
+  const double2* __restrict__ partial = reinterpret_cast<const double2*>(parts.p[blockIdx.y]);
+  double2* __restrict__ out = reinterpret_cast<double2*>(outs.p[blockIdx.y]);
   double s = 0;
   for (int b = threadIdx.x; b < nblk; b += kWG) s += partial[b].x;
   sm[threadIdx.x] = s;
@@ -541,8 +499,10 @@ __global__ __launch_bounds__(kWG) void norm_final_kernel(const double* __restric
   if (threadIdx.x == 0) out[0] = make_double2(sqrt(sm[0]), 0.0);
 }
 
-__global__ __launch_bounds__(kWG) void scale_by_inv_kernel(int64_t n, const double2* __restrict__ w,
-                                                           const double2* __restrict__ nrm, double2* __restrict__ v) {
+__global__ __launch_bounds__(kWG) void scale_by_inv_kernel(int64_t n, PtrSetC ws, PtrSetC nrms, PtrSet vs) {
+  const double2* __restrict__ w = reinterpret_cast<const double2*>(ws.p[blockIdx.y]);
+  const double2* __restrict__ nrm = reinterpret_cast<const double2*>(nrms.p[blockIdx.y]);
+  double2* __restrict__ v = reinterpret_cast<double2*>(vs.p[blockIdx.y]);
   const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
   if (i >= n) return;
   const double d = nrm[0].x;
@@ -630,7 +590,8 @@ void spmv(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, 
 void sell_spmv(int64_t n, int64_t nslices, const int64_t* soff, const int32_t* swidth, const int32_t* perm,
                const int32_t* col, const double* val, const double* x, const double* b, double* y, hipStream_t s) {
   if (n <= 0) return;
-  sell_kernel<<<(unsigned)((nslices + 3) / 4), kWG, 0, s>>>(
+  const unsigned nb = (unsigned)((nslices + 3) / 4);
+  sell_kernel<<<(nb + 7) / 8 * 8, kWG, 0, s>>>(
       n, nslices, soff, swidth, perm, col, reinterpret_cast<const double2*>(val), reinterpret_cast<const double2*>(x),
       reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(y));
 }
@@ -663,24 +624,9 @@ int gs_blocks(int64_t n) {
   return (int)b;
 }
 
-void gs_dots_partial(int64_t n, const double* V, int64_t ld, int ncol, const double* w, double* partial, int nblk,
-                     hipStream_t s) {
-  gs_dots_partial_kernel<<<(unsigned)nblk, kWG, 0, s>>>(n, reinterpret_cast<const double2*>(V), ld, ncol,
-                                                         reinterpret_cast<const double2*>(w),
-                                                         reinterpret_cast<double2*>(partial));
-}
-
-void gs_dots_final(const double* partial, int nblk, int ncol, double* h, double* hacc, int accumulate,
-                   hipStream_t s) {
-  gs_dots_final_kernel<<<(unsigned)ncol, kWG, 0, s>>>(reinterpret_cast<const double2*>(partial), nblk, ncol,
-                                                       reinterpret_cast<double2*>(h),
-                                                       reinterpret_cast<double2*>(hacc), accumulate);
-}
-
-void gs_update(int64_t n, const double* V, int64_t ld, int ncol, const double* h, double* w, hipStream_t s) {
-  gs_update_kernel<<<(unsigned)gs_blocks(n), kWG, 0, s>>>(n, reinterpret_cast<const double2*>(V), ld, ncol,
-                                                           reinterpret_cast<const double2*>(h),
-                                                           reinterpret_cast<double2*>(w));
+void gs_final(int nr, const PtrSetC& partial, int nblk, int ncol, const PtrSet& h, const PtrSet& hacc,
+              int accumulate, hipStream_t s) {
+  gs_dots_final_kernel<<<dim3((unsigned)ncol, (unsigned)nr), kWG, 0, s>>>(partial, nblk, ncol, h, hacc, accumulate);
 }
 
 int gs_tiles(int64_t n) {
@@ -688,27 +634,22 @@ int gs_tiles(int64_t n) {
   return (int)(t < 2048 ? t : 2048);  // workgroups; each loops over 64-row tiles
 }
 
-void gs_pass(int mode, int64_t n, const double* V, int64_t ld, int ncol, const double* h, double* w, double* partial,
-             hipStream_t s) {
-  const unsigned nb = (unsigned)gs_tiles(n);
+void gs_pass(int mode, int nr, int64_t n, const PtrSetC& V, int64_t ld, int ncol, const PtrSetC& h, const PtrSet& w,
+             const PtrSet& partial, hipStream_t s) {
+  const dim3 grid((unsigned)gs_tiles(n), (unsigned)nr);
   const size_t lds = sizeof(double2) * ((size_t)ncol * (kGsRows + 1) + kGsMaxCols + kGsRows + 4 * kGsRows +
                                         4 * kGsMaxCols) +
                      sizeof(double) * kGsRows;
-  auto V2 = reinterpret_cast<const double2*>(V);
-  auto h2 = reinterpret_cast<const double2*>(h);
-  auto w2 = reinterpret_cast<double2*>(w);
-  auto p2 = reinterpret_cast<double2*>(partial);
   if (mode == 0)
-    gs_pass_kernel<false, true, false><<<nb, kWG, lds, s>>>(n, V2, ld, ncol, h2, w2, p2);
+    gs_pass_kernel<false, true, false><<<grid, kWG, lds, s>>>(n, V, ld, ncol, h, w, partial);
   else if (mode == 1)
-    gs_pass_kernel<true, true, false><<<nb, kWG, lds, s>>>(n, V2, ld, ncol, h2, w2, p2);
+    gs_pass_kernel<true, true, false><<<grid, kWG, lds, s>>>(n, V, ld, ncol, h, w, partial);
   else
-    gs_pass_kernel<true, false, true><<<nb, kWG, lds, s>>>(n, V2, ld, ncol, h2, w2, p2);
+    gs_pass_kernel<true, false, true><<<grid, kWG, lds, s>>>(n, V, ld, ncol, h, w, partial);
 }
 
-void norm_final(const double* partial, int nblk, double* out, hipStream_t s) {
-  norm_final2_kernel<<<1, kWG, 0, s>>>(reinterpret_cast<const double2*>(partial), nblk,
-                                       reinterpret_cast<double2*>(out));
+void norm_final(int nr, const PtrSetC& partial, int nblk, const PtrSet& out, hipStream_t s) {
+  norm_final2_kernel<<<dim3(1, (unsigned)nr), kWG, 0, s>>>(partial, nblk, out);
 }
 
 void norm2(int64_t n, const double* w, double* partial, int nblk, double* out, hipStream_t s) {
@@ -716,11 +657,9 @@ void norm2(int64_t n, const double* w, double* partial, int nblk, double* out, h
   norm_final_kernel<<<1, kWG, 0, s>>>(partial, nblk, reinterpret_cast<double2*>(out));
 }
 
-void scale_by_inv(int64_t n, const double* w, const double* nrm, double* v, hipStream_t s) {
+void scale_by_inv_set(int nr, int64_t n, const PtrSetC& w, const PtrSetC& nrm, const PtrSet& v, hipStream_t s) {
   if (n <= 0) return;
-  scale_by_inv_kernel<<<blocks_for(n), kWG, 0, s>>>(n, reinterpret_cast<const double2*>(w),
-                                                    reinterpret_cast<const double2*>(nrm),
-                                                    reinterpret_cast<double2*>(v));
+  scale_by_inv_kernel<<<dim3(blocks_for(n), (unsigned)nr), kWG, 0, s>>>(n, w, nrm, v);
 }
 
 void scale(int64_t n, const double* w, double alpha, double* v, hipStream_t s) {

@@ -9,6 +9,16 @@
 namespace helm {
 namespace dev {
 
+// Up to kMaxBlock device pointers, one per right-hand side of a block
+// (passed by value as a kernel argument; a null entry is a padding column).
+constexpr int kMaxBlock = 16;
+struct PtrSet {
+  double* p[kMaxBlock];
+};
+struct PtrSetC {
+  const double* p[kMaxBlock];
+};
+
 // Mirrors helm::TileDesc.
 struct Tile {
   int64_t off;
@@ -68,27 +78,44 @@ void spmv_real(int64_t n, const int64_t* ptr, const int32_t* col, const double* 
 void prolong(int64_t n, const int64_t* ptr, const int32_t* idx, const double* w, const double* xl, const double* q,
              double* z, hipStream_t s);
 
-// Gram-Schmidt pieces over V (n x ncol, column-major, leading dim ld).
+// Blocks for norm2's partial sums.
 int gs_blocks(int64_t n);
-// partial[b*ncol + k] = sum over block b's rows of conj(V[i,k]) w[i]
-void gs_dots_partial(int64_t n, const double* V, int64_t ld, int ncol, const double* w, double* partial, int nblk,
-                     hipStream_t s);
-// h[k] = sum_b partial[b*ncol + k]; hacc[k] (+)= h[k] (accumulate != 0 adds)
-void gs_dots_final(const double* partial, int nblk, int ncol, double* h, double* hacc, int accumulate,
-                   hipStream_t s);
-// Fused CGS2 pass over 64-row tiles (gs_tiles(n) blocks, ncol <= 64):
+// Fused CGS2 pass over 64-row tiles (gs_tiles(n) workgroups per
+// right-hand side, ncol <= 64), for nr right-hand sides at once (entry r of
+// each pointer set belongs to right-hand side r):
 // mode 0: partial dots V^H w; mode 1: w -= V h then partial dots of the new
 // w; mode 2: w -= V h then partial squared norms (reduce with norm_final).
 int gs_tiles(int64_t n);
-void gs_pass(int mode, int64_t n, const double* V, int64_t ld, int ncol, const double* h, double* w, double* partial,
-             hipStream_t s);
-void norm_final(const double* partial, int nblk, double* out, hipStream_t s);
-// w -= V h
-void gs_update(int64_t n, const double* V, int64_t ld, int ncol, const double* h, double* w, hipStream_t s);
+void gs_pass(int mode, int nr, int64_t n, const PtrSetC& V, int64_t ld, int ncol, const PtrSetC& h, const PtrSet& w,
+             const PtrSet& partial, hipStream_t s);
+// h[k] = sum_b partial[b*ncol + k]; hacc[k] = (or +=) h[k], per right-hand side
+void gs_final(int nr, const PtrSetC& partial, int nblk, int ncol, const PtrSet& h, const PtrSet& hacc,
+              int accumulate, hipStream_t s);
+void norm_final(int nr, const PtrSetC& partial, int nblk, const PtrSet& out, hipStream_t s);
+// v = w / nrm[0] per right-hand side
+void scale_by_inv_set(int nr, int64_t n, const PtrSetC& w, const PtrSetC& nrm, const PtrSet& v, hipStream_t s);
+
+// ---- block (multi-right-hand-side) operations, S in {2, 4, 8, 16},
+//      interleaved n x S vectors (device_block.hip) ----
+bool block_width_ok(int S);
+// one wavefront per tile: tiles [tile0, tile0 + ntiles) of the level
+void fwd_level_block(const Batch& b, int64_t tile0, int64_t ntiles, int S, const double* bin, double* yb, double* ubb,
+                     bool coarse, hipStream_t s);
+void bwd_level_block(const Batch& b, int64_t tile0, int64_t ntiles, int S, const double* yb, double* xb, bool coarse,
+                     hipStream_t s);
+void sell_spmv_block(int64_t n, int64_t nslices, const int64_t* soff, const int32_t* swidth, const int32_t* perm,
+                     const int32_t* col, const double* val, int S, const double* x, const double* b, double* y,
+                     hipStream_t s);
+void spmv_real_block(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, int S, const double* x,
+                     double* y, hipStream_t s);
+void prolong_block(int64_t n, const int64_t* ptr, const int32_t* idx, const double* w, int S, const double* xl,
+                   const double* q, double* z, hipStream_t s);
+// dst (interleaved) <- the S vectors src.p[r] (zeros for null entries)
+void pack(int64_t n, int S, const PtrSetC& src, double* dst, hipStream_t s);
+// dst.p[r] <- column r of src (skipped for null entries)
+void unpack(int64_t n, int S, const double* src, const PtrSet& dst, hipStream_t s);
 // out[0] = ||w||_2 (real, stored as complex with zero imaginary part)
 void norm2(int64_t n, const double* w, double* partial, int nblk, double* out, hipStream_t s);
-// v = w / out[0]  (zeros when out[0] == 0)
-void scale_by_inv(int64_t n, const double* w, const double* nrm, double* v, hipStream_t s);
 // v = alpha * w
 void scale(int64_t n, const double* w, double alpha, double* v, hipStream_t s);
 // x += Z y  (Z n x k column-major, y device)

@@ -1,0 +1,355 @@
+// Multi-right-hand-side kernels (pseudo-block GMRES: S Krylov spaces advanced
+// together, the operator and the preconditioner applied to all S vectors in
+// one pass over A and over the factor panels).
+//
+// Block vectors are interleaved: entry (i, r) of an n x S block sits at
+// i * S + r, so every gather of a row fetches S contiguous complex values.
+// The level kernels stream each panel tile once for all S columns: one
+// wavefront per tile, a lane per tile row holding S accumulators.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "device.hpp"
+
+namespace helm {
+namespace dev {
+
+namespace {
+
+constexpr int kWG = 256;
+constexpr int kBlkLds = 1024;  // complex entries of the staged input block
+
+__device__ __forceinline__ void cfma(double& ar, double& ai, double2 a, double2 v) {
+  ar = fma(a.x, v.x, ar);
+  ar = fma(-a.y, v.y, ar);
+  ai = fma(a.x, v.y, ai);
+  ai = fma(a.y, v.x, ai);
+}
+__device__ __forceinline__ double2 widen(double2 a) { return a; }
+__device__ __forceinline__ double2 widen(float2 a) { return make_double2((double)a.x, (double)a.y); }
+
+template <class PT, int S, int kCoarse>
+__global__ __launch_bounds__(64) void fwd_block_kernel(const Tile* __restrict__ tiles, Batch b,
+                                                       const double2* __restrict__ bin, double2* __restrict__ yb,
+                                                       double2* __restrict__ ubb) {
+  __shared__ double2 vin[kBlkLds];
+  constexpr int CB = kBlkLds / S;
+  const Tile t = tiles[blockIdx.x];
+  const int lane = threadIdx.x;
+  const int sn = t.sn, c0 = b.sn_c0[sn], w = b.sn_w[sn], frow0 = b.sn_frow0[sn];
+  const PT* __restrict__ P = reinterpret_cast<const PT*>(b.pf) + t.off + lane;
+  double ar[S], ai[S];
+#pragma unroll
+  for (int r = 0; r < S; ++r) ar[r] = ai[r] = 0;
+  for (int cb = 0; cb < t.ncols; cb += CB) {
+    const int cn = min(CB, t.ncols - cb);
+    for (int e = lane; e < cn * S; e += 64) {
+      const int k = e / S, r = e % S, kk = cb + k;
+      double2 v = bin[(int64_t)b.bidx[c0 + kk] * S + r];
+      const int fr = frow0 + kk;
+      for (int q = b.fcon_ptr[fr]; q < b.fcon_ptr[fr + 1]; ++q) {
+        const double2 u = ubb[(int64_t)b.fcon_idx[q] * S + r];
+        v.x -= u.x;
+        v.y -= u.y;
+      }
+      vin[e] = v;
+    }
+    __syncthreads();
+    if (lane < t.nrows) {
+      const PT* p = P + (int64_t)cb * t.nrows;
+      int k = 0;
+      for (; k + 2 <= cn; k += 2) {
+        const double2 a0 = widen(p[(int64_t)k * t.nrows]);
+        const double2 a1 = widen(p[(int64_t)(k + 1) * t.nrows]);
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+          cfma(ar[r], ai[r], a0, vin[k * S + r]);
+          cfma(ar[r], ai[r], a1, vin[(k + 1) * S + r]);
+        }
+      }
+      for (; k < cn; ++k) {
+        const double2 a0 = widen(p[(int64_t)k * t.nrows]);
+#pragma unroll
+        for (int r = 0; r < S; ++r) cfma(ar[r], ai[r], a0, vin[k * S + r]);
+      }
+    }
+    __syncthreads();
+  }
+  if (lane < t.nrows) {
+    const int row = t.row0 + lane;
+    if (row < w) {
+#pragma unroll
+      for (int r = 0; r < S; ++r) yb[(int64_t)(c0 + row) * S + r] = make_double2(ar[r], ai[r]);
+    } else {
+      const int fr = frow0 + row;
+      for (int q = b.fcon_ptr[fr]; q < b.fcon_ptr[fr + 1]; ++q) {
+        const int64_t src = (int64_t)b.fcon_idx[q] * S;
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+          const double2 u = ubb[src + r];
+          ar[r] += u.x;
+          ai[r] += u.y;
+        }
+      }
+      const int64_t dst = (int64_t)(b.sn_uoff[sn] + row - w) * S;
+#pragma unroll
+      for (int r = 0; r < S; ++r) ubb[dst + r] = make_double2(ar[r], ai[r]);
+    }
+  }
+}
+
+template <class PT, int S, int kCoarse>
+__global__ __launch_bounds__(64) void bwd_block_kernel(const Tile* __restrict__ tiles, Batch b,
+                                                       const double2* __restrict__ yb, double2* __restrict__ xb) {
+  __shared__ double2 vin[kBlkLds];
+  constexpr int CB = kBlkLds / S;
+  const Tile t = tiles[blockIdx.x];
+  const int lane = threadIdx.x;
+  const int sn = t.sn, c0 = b.sn_c0[sn], w = b.sn_w[sn];
+  const int64_t roff = b.sn_roff[sn];
+  const PT* __restrict__ P = reinterpret_cast<const PT*>(b.pb) + t.off + lane;
+  double ar[S], ai[S];
+#pragma unroll
+  for (int r = 0; r < S; ++r) ar[r] = ai[r] = 0;
+  for (int cb = 0; cb < t.ncols; cb += CB) {
+    const int cn = min(CB, t.ncols - cb);
+    for (int e = lane; e < cn * S; e += 64) {
+      const int k = e / S, r = e % S, c = t.col0 + cb + k;
+      vin[e] = c < w ? yb[(int64_t)(c0 + c) * S + r] : xb[(int64_t)b.rows[roff + (c - w)] * S + r];
+    }
+    __syncthreads();
+    if (lane < t.nrows) {
+      const PT* p = P + (int64_t)cb * t.nrows;
+      int k = 0;
+      for (; k + 2 <= cn; k += 2) {
+        const double2 a0 = widen(p[(int64_t)k * t.nrows]);
+        const double2 a1 = widen(p[(int64_t)(k + 1) * t.nrows]);
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+          cfma(ar[r], ai[r], a0, vin[k * S + r]);
+          cfma(ar[r], ai[r], a1, vin[(k + 1) * S + r]);
+        }
+      }
+      for (; k < cn; ++k) {
+        const double2 a0 = widen(p[(int64_t)k * t.nrows]);
+#pragma unroll
+        for (int r = 0; r < S; ++r) cfma(ar[r], ai[r], a0, vin[k * S + r]);
+      }
+    }
+    __syncthreads();
+  }
+  if (lane < t.nrows) {
+    const int64_t dst = (int64_t)(c0 + t.row0 + lane) * S;
+#pragma unroll
+    for (int r = 0; r < S; ++r) xb[dst + r] = make_double2(ar[r], ai[r]);
+  }
+}
+
+template <int S>
+__global__ __launch_bounds__(kWG) void sell_block_kernel(int64_t n, int64_t nslices, const int64_t* __restrict__ soff,
+                                                         const int32_t* __restrict__ swidth,
+                                                         const int32_t* __restrict__ perm,
+                                                         const int32_t* __restrict__ col,
+                                                         const double2* __restrict__ val,
+                                                         const double2* __restrict__ x,
+                                                         const double2* __restrict__ bvec, double2* __restrict__ y) {
+  const unsigned per = gridDim.x / 8;
+  const int64_t vb = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int64_t s = vb * (kWG / 64) + (threadIdx.x >> 6);
+  if (s >= nslices) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t slot = s * 64 + lane;
+  const int64_t off = soff[s] + lane;
+  const int wdt = swidth[s];
+  double ar[S], ai[S];
+#pragma unroll
+  for (int r = 0; r < S; ++r) ar[r] = ai[r] = 0;
+  for (int j = 0; j < wdt; ++j) {
+    const int c = col[off + (int64_t)j * 64];
+    const double2 v = val[off + (int64_t)j * 64];
+    const double2* xr = x + (int64_t)c * S;
+#pragma unroll
+    for (int r = 0; r < S; ++r) cfma(ar[r], ai[r], v, xr[r]);
+  }
+  if (slot >= n) return;
+  const int64_t row = perm[slot];
+#pragma unroll
+  for (int r = 0; r < S; ++r) {
+    if (bvec) {
+      const double2 bb = bvec[row * S + r];
+      y[row * S + r] = make_double2(bb.x - ar[r], bb.y - ai[r]);
+    } else {
+      y[row * S + r] = make_double2(ar[r], ai[r]);
+    }
+  }
+}
+
+template <int S>
+__global__ __launch_bounds__(kWG) void spmv_real_block_kernel(int64_t n, const int64_t* __restrict__ ptr,
+                                                              const int32_t* __restrict__ col,
+                                                              const double* __restrict__ val,
+                                                              const double2* __restrict__ x, double2* __restrict__ y) {
+  const int64_t e = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (e >= n * S) return;
+  const int64_t row = e / S;
+  const int r = (int)(e % S);
+  double ar = 0, ai = 0;
+  for (int64_t p = ptr[row]; p < ptr[row + 1]; ++p) {
+    const double a = val[p];
+    const double2 v = x[(int64_t)col[p] * S + r];
+    ar = fma(a, v.x, ar);
+    ai = fma(a, v.y, ai);
+  }
+  y[e] = make_double2(ar, ai);
+}
+
+template <int S>
+__global__ __launch_bounds__(kWG) void prolong_block_kernel(int64_t n, const int64_t* __restrict__ ptr,
+                                                            const int32_t* __restrict__ idx,
+                                                            const double* __restrict__ w,
+                                                            const double2* __restrict__ xl,
+                                                            const double2* __restrict__ q, double2* __restrict__ z) {
+  const int64_t e = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (e >= n * S) return;
+  const int64_t g = e / S;
+  const int r = (int)(e % S);
+  double ar = 0, ai = 0;
+  if (q) {
+    ar = q[e].x;
+    ai = q[e].y;
+  }
+  for (int64_t p = ptr[g]; p < ptr[g + 1]; ++p) {
+    const double2 v = xl[(int64_t)idx[p] * S + r];
+    const double c = w[p];
+    ar = fma(c, v.x, ar);
+    ai = fma(c, v.y, ai);
+  }
+  z[e] = make_double2(ar, ai);
+}
+
+template <int S>
+__global__ __launch_bounds__(kWG) void pack_kernel(int64_t n, PtrSetC src, double2* __restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (e >= n * S) return;
+  const int64_t i = e / S;
+  const int r = (int)(e % S);
+  const double2* p = reinterpret_cast<const double2*>(src.p[r]);
+  dst[e] = p ? p[i] : make_double2(0.0, 0.0);
+}
+
+template <int S>
+__global__ __launch_bounds__(kWG) void unpack_kernel(int64_t n, const double2* __restrict__ src, PtrSet dst) {
+  const int64_t e = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (e >= n * S) return;
+  const int64_t i = e / S;
+  const int r = (int)(e % S);
+  double2* p = reinterpret_cast<double2*>(dst.p[r]);
+  if (p) p[i] = src[e];
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kWG - 1) / kWG); }
+
+// Calls f(std::integral_constant<int, S>) for the supported block widths.
+template <class F>
+void with_width(int S, F&& f) {
+  switch (S) {
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    default: break;
+  }
+}
+
+}  // namespace
+
+bool block_width_ok(int S) { return S == 2 || S == 4 || S == 8 || S == 16; }
+
+void fwd_level_block(const Batch& b, int64_t tile0, int64_t ntiles, int S, const double* bin, double* yb, double* ubb,
+                     bool coarse, hipStream_t s) {
+  if (ntiles <= 0) return;
+  const Tile* t = b.tf + tile0;
+  auto in = reinterpret_cast<const double2*>(bin);
+  auto y = reinterpret_cast<double2*>(yb);
+  auto u = reinterpret_cast<double2*>(ubb);
+  with_width(S, [&](auto w) {
+    constexpr int W = decltype(w)::value;
+    if (coarse)
+      fwd_block_kernel<double2, W, 1><<<(unsigned)ntiles, 64, 0, s>>>(t, b, in, y, u);
+    else if (b.c64)
+      fwd_block_kernel<float2, W, 0><<<(unsigned)ntiles, 64, 0, s>>>(t, b, in, y, u);
+    else
+      fwd_block_kernel<double2, W, 0><<<(unsigned)ntiles, 64, 0, s>>>(t, b, in, y, u);
+  });
+}
+
+void bwd_level_block(const Batch& b, int64_t tile0, int64_t ntiles, int S, const double* yb, double* xb, bool coarse,
+                     hipStream_t s) {
+  if (ntiles <= 0) return;
+  const Tile* t = b.tb + tile0;
+  auto y = reinterpret_cast<const double2*>(yb);
+  auto x = reinterpret_cast<double2*>(xb);
+  with_width(S, [&](auto w) {
+    constexpr int W = decltype(w)::value;
+    if (coarse)
+      bwd_block_kernel<double2, W, 1><<<(unsigned)ntiles, 64, 0, s>>>(t, b, y, x);
+    else if (b.c64)
+      bwd_block_kernel<float2, W, 0><<<(unsigned)ntiles, 64, 0, s>>>(t, b, y, x);
+    else
+      bwd_block_kernel<double2, W, 0><<<(unsigned)ntiles, 64, 0, s>>>(t, b, y, x);
+  });
+}
+
+void sell_spmv_block(int64_t n, int64_t nslices, const int64_t* soff, const int32_t* swidth, const int32_t* perm,
+                     const int32_t* col, const double* val, int S, const double* x, const double* b, double* y,
+                     hipStream_t s) {
+  if (n <= 0) return;
+  const unsigned nb = (unsigned)((nslices + 3) / 4);
+  with_width(S, [&](auto w) {
+    constexpr int W = decltype(w)::value;
+    sell_block_kernel<W><<<(nb + 7) / 8 * 8, kWG, 0, s>>>(
+        n, nslices, soff, swidth, perm, col, reinterpret_cast<const double2*>(val),
+        reinterpret_cast<const double2*>(x), reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(y));
+  });
+}
+
+void spmv_real_block(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, int S, const double* x,
+                     double* y, hipStream_t s) {
+  if (n <= 0) return;
+  with_width(S, [&](auto w) {
+    constexpr int W = decltype(w)::value;
+    spmv_real_block_kernel<W><<<blocks_for(n * W), kWG, 0, s>>>(n, ptr, col, val, reinterpret_cast<const double2*>(x),
+                                                                 reinterpret_cast<double2*>(y));
+  });
+}
+
+void prolong_block(int64_t n, const int64_t* ptr, const int32_t* idx, const double* wt, int S, const double* xl,
+                   const double* q, double* z, hipStream_t s) {
+  if (n <= 0) return;
+  with_width(S, [&](auto w) {
+    constexpr int W = decltype(w)::value;
+    prolong_block_kernel<W><<<blocks_for(n * W), kWG, 0, s>>>(n, ptr, idx, wt, reinterpret_cast<const double2*>(xl),
+                                                               reinterpret_cast<const double2*>(q),
+                                                               reinterpret_cast<double2*>(z));
+  });
+}
+
+void pack(int64_t n, int S, const PtrSetC& src, double* dst, hipStream_t s) {
+  if (n <= 0) return;
+  with_width(S, [&](auto w) {
+    constexpr int W = decltype(w)::value;
+    pack_kernel<W><<<blocks_for(n * W), kWG, 0, s>>>(n, src, reinterpret_cast<double2*>(dst));
+  });
+}
+
+void unpack(int64_t n, int S, const double* src, const PtrSet& dst, hipStream_t s) {
+  if (n <= 0) return;
+  with_width(S, [&](auto w) {
+    constexpr int W = decltype(w)::value;
+    unpack_kernel<W><<<blocks_for(n * W), kWG, 0, s>>>(n, reinterpret_cast<const double2*>(src), dst);
+  });
+}
+
+}  // namespace dev
+}  // namespace helm

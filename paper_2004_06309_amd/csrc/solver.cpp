@@ -23,6 +23,7 @@ namespace helm {
 
 Ctx::~Ctx() {
   if (h_host) (void)hipHostFree(h_host);
+  if (bh_host) (void)hipHostFree(bh_host);
 }
 
 void Ctx::free_precond() {
@@ -233,11 +234,13 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
   // algorithmic bytes per level: every panel entry once, plus the vector
   // entries each supernode gathers and writes
   auto r_of = [&](int64_t s) { return (s + 1 < nsn ? B.roff[s + 1] : B.nu) - B.roff[s]; };
-  auto level_bytes = [&](const std::vector<dev::Tile>& T, bool fwd) {
+  auto level_bytes = [&](const std::vector<dev::Tile>& T, bool fwd, double& panel) {
     double by = 0;
     int32_t last = -1;
+    panel = 0;
     for (const auto& t : T) {
       by += 16.0 * t.nrows * t.ncols;
+      panel += 16.0 * t.nrows * t.ncols;
       const int32_t s = t.sn;
       if (s == last) continue;
       last = s;
@@ -253,10 +256,13 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
   };
   // workgroup tasks: tiles grouped by width class, 4 / wpt tiles per group
   auto make_tasks = [&](std::vector<std::vector<dev::Tile>>& levels, bool fwd, std::vector<dev::Tile>& tiles,
-                        std::vector<dev::Task>& tasks, std::vector<int64_t>& lev, std::vector<double>& bytes) {
+                        std::vector<dev::Task>& tasks, std::vector<int64_t>& lev, std::vector<double>& bytes,
+                        std::vector<double>& pbytes) {
     lev.assign(1, 0);
     for (auto& l : levels) {
-      bytes.push_back(level_bytes(l, fwd));
+      double pb = 0;
+      bytes.push_back(level_bytes(l, fwd, pb));
+      pbytes.push_back(pb);
       // widest class first, larger tiles first: the level's tail holds the
       // shortest workgroups
       std::stable_sort(l.begin(), l.end(), [](const dev::Tile& a, const dev::Tile& b) {
@@ -277,8 +283,8 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
       lev.push_back((int64_t)tasks.size());
     }
   };
-  make_tasks(lf, true, B.tf, B.kf, B.lev_f, B.bytes_f);
-  make_tasks(lb, false, B.tb, B.kb, B.lev_b, B.bytes_b);
+  make_tasks(lf, true, B.tf, B.kf, B.lev_f, B.bytes_f, B.pbytes_f);
+  make_tasks(lb, false, B.tb, B.kb, B.lev_b, B.bytes_b, B.pbytes_b);
 }
 
 namespace {
@@ -348,6 +354,16 @@ void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symb
   Dv.lev_b = B.lev_b;
   Dv.bytes_f = B.bytes_f;
   Dv.bytes_b = B.bytes_b;
+  Dv.pbytes_f = B.pbytes_f;
+  Dv.pbytes_b = B.pbytes_b;
+  auto tile_ranges = [](const std::vector<dev::Task>& K, const std::vector<int64_t>& lev) {
+    std::vector<int64_t> r(1, 0);
+    for (size_t l = 0; l + 1 < lev.size(); ++l)
+      r.push_back(lev[l + 1] > lev[l] ? K[lev[l + 1] - 1].tile0 + K[lev[l + 1] - 1].ntile : r.back());
+    return r;
+  };
+  Dv.tiles_f = tile_ranges(B.kf, B.lev_f);
+  Dv.tiles_b = tile_ranges(B.kb, B.lev_b);
   Dv.tf.upload(B.tf);
   Dv.tb.upload(B.tb);
   Dv.kf.upload(B.kf);
@@ -691,16 +707,13 @@ void ensure_gmres(Ctx& c, int m) {
 
 }  // namespace
 
-int solve(Ctx& c, int32_t nrhs, const double* B, double tol, const helm_solve_opts* opts, double* U, hipStream_t s,
-          helm_solve_info* info) {
-  const int m = opts && opts->restart > 0 ? opts->restart : 50;
-  const int maxit = opts && opts->maxit > 0 ? opts->maxit : 1000;
-  const bool x0 = opts && (opts->flags & HELM_SOLVE_X0);
-  if (m > 50) fail(HELM_EINVAL, "restart must be <= 50");
-  if (!(tol > 0)) fail(HELM_EINVAL, "tol must be positive");
+namespace {
+
+// One right-hand side at a time.
+int solve_single(Ctx& c, int32_t nrhs, const double* B, double tol, int m, int maxit, bool x0, double* U,
+                 hipStream_t s, helm_solve_info* info) {
   ensure_gmres(c, m);
   const int64_t n = c.D.n;
-  const int nblk = dev::gs_blocks(n);
   double* V = c.V.p;
   double* Zk = c.Zk.p;
   std::vector<cplx> H((size_t)(m + 1) * m), g(m + 1), sn(m);
@@ -748,13 +761,27 @@ int solve(Ctx& c, int32_t nrhs, const double* B, double tol, const helm_solve_op
         const bool prof = c.prof.on;
         if (prof) c.prof.begin(s);
         const int nt = dev::gs_tiles(n);
-        dev::gs_pass(0, n, V, n, jj + 1, nullptr, c.w.p, c.partial.p, s);
-        dev::gs_dots_final(c.partial.p, nt, jj + 1, c.htmp.p, c.hcol.p, 0, s);
-        dev::gs_pass(1, n, V, n, jj + 1, c.htmp.p, c.w.p, c.partial.p, s);
-        dev::gs_dots_final(c.partial.p, nt, jj + 1, c.htmp.p, c.hcol.p, 1, s);
-        dev::gs_pass(2, n, V, n, jj + 1, c.htmp.p, c.w.p, c.partial.p, s);
-        dev::norm_final(c.partial.p, nt, c.hcol.p + 2 * (jj + 1), s);
-        dev::scale_by_inv(n, c.w.p, c.hcol.p + 2 * (jj + 1), V + 2 * (size_t)n * (jj + 1), s);
+        dev::PtrSetC Vs{}, hs{}, ps{};
+        dev::PtrSet ws{}, hts{}, hcs{}, pw{}, nrm{}, vn{};
+        Vs.p[0] = V;
+        hs.p[0] = c.htmp.p;
+        ps.p[0] = c.partial.p;
+        ws.p[0] = c.w.p;
+        hts.p[0] = c.htmp.p;
+        hcs.p[0] = c.hcol.p;
+        pw.p[0] = c.partial.p;
+        nrm.p[0] = c.hcol.p + 2 * (jj + 1);
+        vn.p[0] = V + 2 * (size_t)n * (jj + 1);
+        dev::gs_pass(0, 1, n, Vs, n, jj + 1, hs, ws, pw, s);
+        dev::gs_final(1, ps, nt, jj + 1, hts, hcs, 0, s);
+        dev::gs_pass(1, 1, n, Vs, n, jj + 1, hs, ws, pw, s);
+        dev::gs_final(1, ps, nt, jj + 1, hts, hcs, 1, s);
+        dev::gs_pass(2, 1, n, Vs, n, jj + 1, hs, ws, pw, s);
+        dev::norm_final(1, ps, nt, nrm, s);
+        dev::PtrSetC wc{}, nc{};
+        wc.p[0] = c.w.p;
+        nc.p[0] = nrm.p[0];
+        dev::scale_by_inv_set(1, n, wc, nc, vn, s);
         if (prof) c.prof.end(HELM_K_GS, 16.0 * n * (3.0 * (jj + 1) + 7.0), s);
         HELM_HIP(hipMemcpyAsync(c.h_host, c.hcol.p, 2 * sizeof(double) * (jj + 2), hipMemcpyDeviceToHost, s));
         HELM_HIP(hipStreamSynchronize(s));
@@ -807,6 +834,298 @@ int solve(Ctx& c, int32_t nrhs, const double* B, double tol, const helm_solve_op
     inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info) info[j] = inf;
     if (!conv) status = HELM_ENOCONV;
+  }
+  return status;
+}
+
+
+void ensure_batch_block(BatchDev& b, int S) {
+  if (b.blk_S >= S) return;
+  const size_t nu = std::max<size_t>(b.ubuf.n / 2, 1), np = std::max<int64_t>(b.npos, 1);
+  b.ubuf_b.alloc(2 * nu * S);
+  b.y_b.alloc(2 * np * S);
+  b.x_b.alloc(2 * np * S);
+  b.blk_S = S;
+}
+
+void ensure_block(Ctx& c, int m, int S) {
+  const int64_t n = c.D.n;
+  if (c.blk_m != m || c.blk_cap < S) {
+    for (int r = 0; r < dev::kMaxBlock; ++r) {
+      c.bV[r].reset();
+      c.bZ[r].reset();
+      c.bw[r].reset();
+    }
+    for (int r = 0; r < S; ++r) {
+      c.bV[r].alloc(2 * (size_t)n * (m + 1));
+      c.bZ[r].alloc(2 * (size_t)n * m);
+      c.bw[r].alloc(2 * (size_t)n);
+    }
+    c.bhcol.alloc(2 * (size_t)dev::kMaxBlock * (m + 2));
+    c.bhtmp.alloc(2 * (size_t)dev::kMaxBlock * (m + 2));
+    c.bpartial.alloc(2 * (size_t)dev::kMaxBlock * dev::gs_tiles(n) * (m + 2));
+    c.by.alloc(2 * (size_t)(m + 1));
+    c.bX.alloc(2 * (size_t)n * S);
+    c.bZb.alloc(2 * (size_t)n * S);
+    c.bW.alloc(2 * (size_t)n * S);
+    c.bq.alloc(2 * (size_t)n * S);
+    c.bt.alloc(2 * (size_t)n * S);
+    if (c.two_level) c.bcvec.alloc(2 * (size_t)c.E.n * S);
+    if (c.bh_host) (void)hipHostFree(c.bh_host);
+    c.bh_host = nullptr;
+    HELM_HIP(hipHostMalloc((void**)&c.bh_host, 2 * sizeof(double) * dev::kMaxBlock * (m + 2), hipHostMallocDefault));
+    c.blk_m = m;
+    c.blk_cap = S;
+  }
+  ensure_batch_block(c.fine, S);
+  if (c.two_level) ensure_batch_block(c.coarse, S);
+}
+
+// Forward then backward sweeps of a batch for S interleaved right-hand sides.
+void batch_solve_block(BatchDev& b, int S, const double* in, hipStream_t s, Profiler* prof, bool fine) {
+  dev::Batch v = b.view();
+  const bool each = prof && prof->on && fine;
+  for (size_t l = 0; l + 1 < b.tiles_f.size(); ++l) {
+    if (each) prof->begin(s);
+    dev::fwd_level_block(v, b.tiles_f[l], b.tiles_f[l + 1] - b.tiles_f[l], S, in, b.y_b.p, b.ubuf_b.p, !fine, s);
+    if (each) prof->end(HELM_K_TRSV_FWD, b.pbytes_f[l] + S * (b.bytes_f[l] - b.pbytes_f[l]), s);
+  }
+  for (size_t l = 0; l + 1 < b.tiles_b.size(); ++l) {
+    if (each) prof->begin(s);
+    dev::bwd_level_block(v, b.tiles_b[l], b.tiles_b[l + 1] - b.tiles_b[l], S, b.y_b.p, b.x_b.p, !fine, s);
+    if (each) prof->end(HELM_K_TRSV_BWD, b.pbytes_b[l] + S * (b.bytes_b[l] - b.pbytes_b[l]), s);
+  }
+}
+
+void sell_block(Ctx& c, int S, const double* x, const double* b, double* y, hipStream_t s) {
+  dev::sell_spmv_block(c.D.n, c.sell_nslices, c.sell_off.p, c.sell_width.p, c.sell_perm.p, c.sell_col.p,
+                       c.sell_val.p, S, x, b, y, s);
+}
+
+// Z = M^{-1} X for S interleaved vectors (eq. 2lvl, or eq. oras one-level).
+void apply_precond_block(Ctx& c, int S, const double* X, double* Z, hipStream_t s) {
+  const int64_t n = c.D.n;
+  const bool p = c.prof.on;
+  if (c.two_level) {
+    if (p) c.prof.begin(s);
+    dev::spmv_real_block(c.ZT.n, c.ZT_ptr.p, c.ZT_col.p, c.ZT_val.p, S, X, c.bcvec.p, s);
+    batch_solve_block(c.coarse, S, c.bcvec.p, s, &c.prof, false);
+    dev::spmv_real_block(n, c.Zp_ptr.p, c.Zp_col.p, c.Zp_val.p, S, c.coarse.x_b.p, c.bq.p, s);
+    if (p) c.prof.end(HELM_K_COARSE, 0.0, s);
+    if (p) c.prof.begin(s);
+    sell_block(c, S, c.bq.p, X, c.bt.p, s);  // t = x - A q
+    if (p) c.prof.end(HELM_K_SPMV, 0.0, s);
+    batch_solve_block(c.fine, S, c.bt.p, s, &c.prof, true);
+  } else {
+    batch_solve_block(c.fine, S, X, s, &c.prof, true);
+  }
+  if (p) c.prof.begin(s);
+  dev::prolong_block(n, c.pro_ptr.p, c.pro_idx.p, c.pro_w.p, S, c.fine.x_b.p, c.two_level ? c.bq.p : nullptr, Z, s);
+  if (p) c.prof.end(HELM_K_PROLONG, 0.0, s);
+}
+
+// Pseudo-block GMRES: nb <= kMaxBlock right-hand sides, each with its own
+// Krylov space, Hessenberg matrix, Givens rotations and stopping test; every
+// Arnoldi step applies M^{-1} and A to all active vectors at once (one pass
+// over the factor panels and over A for the whole block).
+int solve_block(Ctx& c, int nb, const double* const* Bp, double* const* Up, double tol, int m, int maxit, bool x0,
+                hipStream_t s, helm_solve_info* info) {
+  int S = 2;
+  while (S < nb) S *= 2;
+  ensure_block(c, m, S);
+  const int64_t n = c.D.n;
+  const size_t n2 = 2 * (size_t)n;
+  const int nt = dev::gs_tiles(n);
+  struct St {
+    double bnorm = 0, rel = 0;
+    int its = 0, k = 0;
+    bool conv = false, finished = false, incycle = false, done = false;
+    std::vector<cplx> H, g, sn, y;
+    std::vector<double> cs;
+    std::chrono::steady_clock::time_point t0;
+    double secs = 0;
+  };
+  std::vector<St> st(nb);
+  for (int r = 0; r < nb; ++r) {
+    St& q = st[r];
+    q.t0 = std::chrono::steady_clock::now();
+    q.H.assign((size_t)(m + 1) * m, 0);
+    q.g.assign(m + 1, 0);
+    q.sn.assign(m, 0);
+    q.y.assign(m, 0);
+    q.cs.assign(m, 0);
+    q.bnorm = device_norm(c, Bp[r], s);
+    if (!std::isfinite(q.bnorm)) fail(HELM_ENUMERIC, "non-finite right-hand side");
+    if (q.bnorm == 0 || !x0) dev::fill_zero(n2, Up[r], s);
+    if (q.bnorm == 0) q.conv = q.finished = true;
+  }
+  while (true) {
+    bool any = false;
+    for (int r = 0; r < nb; ++r) {
+      St& q = st[r];
+      if (q.finished) continue;
+      double* v0 = c.bV[r].p;
+      spmv_A(c, Up[r], Bp[r], v0, s);  // r = b - A x
+      const double beta = device_norm(c, v0, s);
+      if (!std::isfinite(beta)) fail(HELM_ENUMERIC, "non-finite residual");
+      q.rel = beta / q.bnorm;
+      if (beta <= tol * q.bnorm) {
+        q.conv = q.finished = true;
+        continue;
+      }
+      if (q.its >= maxit) {
+        q.finished = true;
+        continue;
+      }
+      dev::scale(n, v0, 1.0 / beta, v0, s);
+      std::fill(q.g.begin(), q.g.end(), cplx(0, 0));
+      q.g[0] = beta;
+      q.incycle = true;
+      q.done = false;
+      q.k = 0;
+      any = true;
+    }
+    if (!any) break;
+    for (int jj = 0; jj < m; ++jj) {
+      std::vector<int> act;
+      for (int r = 0; r < nb; ++r)
+        if (st[r].incycle && !st[r].done) act.push_back(r);
+      if (act.empty()) break;
+      const int na = (int)act.size();
+      dev::PtrSetC src{};
+      dev::PtrSet dz{}, dw{};
+      for (int q = 0; q < na; ++q) {
+        src.p[q] = c.bV[act[q]].p + n2 * jj;
+        dz.p[q] = c.bZ[act[q]].p + n2 * jj;
+        dw.p[q] = c.bw[act[q]].p;
+      }
+      dev::pack(n, S, src, c.bX.p, s);
+      apply_precond_block(c, S, c.bX.p, c.bZb.p, s);
+      dev::unpack(n, S, c.bZb.p, dz, s);
+      const bool prof = c.prof.on;
+      if (prof) c.prof.begin(s);
+      sell_block(c, S, c.bZb.p, nullptr, c.bW.p, s);
+      if (prof) c.prof.end(HELM_K_SPMV, 0.0, s);
+      dev::unpack(n, S, c.bW.p, dw, s);
+      // CGS2 over the active right-hand sides (slot q holds act[q])
+      if (prof) c.prof.begin(s);
+      dev::PtrSetC Vs{}, hs{}, ps{}, wc{}, nc{};
+      dev::PtrSet ws{}, hts{}, hcs{}, pw{}, nrm{}, vn{};
+      for (int q = 0; q < na; ++q) {
+        const int r = act[q];
+        Vs.p[q] = c.bV[r].p;
+        hs.p[q] = c.bhtmp.p + 2 * (size_t)q * (m + 2);
+        hts.p[q] = c.bhtmp.p + 2 * (size_t)q * (m + 2);
+        hcs.p[q] = c.bhcol.p + 2 * (size_t)q * (m + 2);
+        ps.p[q] = c.bpartial.p + 2 * (size_t)q * nt * (m + 2);
+        pw.p[q] = c.bpartial.p + 2 * (size_t)q * nt * (m + 2);
+        ws.p[q] = c.bw[r].p;
+        wc.p[q] = c.bw[r].p;
+        nrm.p[q] = hcs.p[q] + 2 * (jj + 1);
+        nc.p[q] = nrm.p[q];
+        vn.p[q] = c.bV[r].p + n2 * (jj + 1);
+      }
+      dev::gs_pass(0, na, n, Vs, n, jj + 1, hs, ws, pw, s);
+      dev::gs_final(na, ps, nt, jj + 1, hts, hcs, 0, s);
+      dev::gs_pass(1, na, n, Vs, n, jj + 1, hs, ws, pw, s);
+      dev::gs_final(na, ps, nt, jj + 1, hts, hcs, 1, s);
+      dev::gs_pass(2, na, n, Vs, n, jj + 1, hs, ws, pw, s);
+      dev::norm_final(na, ps, nt, nrm, s);
+      dev::scale_by_inv_set(na, n, wc, nc, vn, s);
+      if (prof) c.prof.end(HELM_K_GS, na * 16.0 * n * (3.0 * (jj + 1) + 7.0), s);
+      HELM_HIP(hipMemcpyAsync(c.bh_host, c.bhcol.p, 2 * sizeof(double) * na * (m + 2), hipMemcpyDeviceToHost, s));
+      HELM_HIP(hipStreamSynchronize(s));
+      if (c.prof.on) c.prof.harvest();
+      for (int q = 0; q < na; ++q) {
+        St& u = st[act[q]];
+        const double* hh = c.bh_host + 2 * (size_t)q * (m + 2);
+        cplx* h = u.H.data() + (size_t)(m + 1) * jj;
+        for (int i = 0; i <= jj + 1; ++i) {
+          h[i] = cplx(hh[2 * i], hh[2 * i + 1]);
+          if (!std::isfinite(h[i].real()) || !std::isfinite(h[i].imag()))
+            fail(HELM_ENUMERIC, "non-finite Hessenberg entry");
+        }
+        const double hn = h[jj + 1].real();
+        for (int i = 0; i < jj; ++i) {
+          cplx a = h[i], bb = h[i + 1];
+          h[i] = u.cs[i] * a + u.sn[i] * bb;
+          h[i + 1] = -std::conj(u.sn[i]) * a + u.cs[i] * bb;
+        }
+        cplx a = h[jj], bb = h[jj + 1];
+        if (a == cplx(0, 0)) {
+          u.cs[jj] = 0;
+          u.sn[jj] = 1;
+        } else {
+          double rr = std::sqrt(std::norm(a) + std::norm(bb));
+          u.cs[jj] = std::abs(a) / rr;
+          u.sn[jj] = (a / std::abs(a)) * std::conj(bb) / rr;
+        }
+        h[jj] = u.cs[jj] * a + u.sn[jj] * bb;
+        h[jj + 1] = 0;
+        u.g[jj + 1] = -std::conj(u.sn[jj]) * u.g[jj];
+        u.g[jj] = u.cs[jj] * u.g[jj];
+        ++u.its;
+        u.k = jj + 1;
+        if (std::abs(u.g[jj + 1]) <= tol * u.bnorm || u.its >= maxit || hn == 0) u.done = true;
+      }
+    }
+    // cycle end: x += Z_k y for every right-hand side of the cycle
+    for (int r = 0; r < nb; ++r) {
+      St& u = st[r];
+      if (!u.incycle) continue;
+      const int k = u.k;
+      for (int i = k - 1; i >= 0; --i) {
+        cplx acc = u.g[i];
+        for (int l = i + 1; l < k; ++l) acc -= u.H[(size_t)(m + 1) * l + i] * u.y[l];
+        u.y[i] = acc / u.H[(size_t)(m + 1) * i + i];
+      }
+      HELM_HIP(hipMemcpyAsync(c.by.p, u.y.data(), sizeof(cplx) * k, hipMemcpyHostToDevice, s));
+      dev::gemv_acc(n, c.bZ[r].p, n, k, c.by.p, Up[r], s);
+      HELM_HIP(hipStreamSynchronize(s));
+      u.incycle = false;
+    }
+  }
+  HELM_HIP(hipStreamSynchronize(s));
+  if (c.prof.on) c.prof.harvest();
+  int status = HELM_OK;
+  const double total = std::chrono::duration<double>(std::chrono::steady_clock::now() - st[0].t0).count();
+  for (int r = 0; r < nb; ++r) {
+    if (info) {
+      info[r].iterations = st[r].its;
+      info[r].converged = st[r].conv ? 1 : 0;
+      info[r].relres = st[r].rel;
+      info[r].seconds = total;
+    }
+    if (!st[r].conv) status = HELM_ENOCONV;
+  }
+  return status;
+}
+
+}  // namespace
+
+int solve(Ctx& c, int32_t nrhs, const double* B, double tol, const helm_solve_opts* opts, double* U, hipStream_t s,
+          helm_solve_info* info) {
+  const int m = opts && opts->restart > 0 ? opts->restart : 50;
+  const int maxit = opts && opts->maxit > 0 ? opts->maxit : 1000;
+  const bool x0 = opts && (opts->flags & HELM_SOLVE_X0);
+  const int block = opts && opts->block > 0 ? std::min(opts->block, dev::kMaxBlock) : 1;
+  if (m > 50) fail(HELM_EINVAL, "restart must be <= 50");
+  if (!(tol > 0)) fail(HELM_EINVAL, "tol must be positive");
+  if (block <= 1 || nrhs <= 1) return solve_single(c, nrhs, B, tol, m, maxit, x0, U, s, info);
+  ensure_gmres(c, m);  // device_norm's work space
+  const int64_t n = c.D.n;
+  int status = HELM_OK;
+  for (int32_t j0 = 0; j0 < nrhs; j0 += block) {
+    const int nb = std::min<int>(block, nrhs - j0);
+    std::vector<const double*> Bp(nb);
+    std::vector<double*> Up(nb);
+    for (int r = 0; r < nb; ++r) {
+      Bp[r] = B + 2 * (size_t)n * (j0 + r);
+      Up[r] = U + 2 * (size_t)n * (j0 + r);
+    }
+    int st = nb == 1 ? solve_single(c, 1, Bp[0], tol, m, maxit, x0, Up[0], s, info ? info + j0 : nullptr)
+                     : solve_block(c, nb, Bp.data(), Up.data(), tol, m, maxit, x0, s, info ? info + j0 : nullptr);
+    if (st != HELM_OK) status = st;
   }
   return status;
 }

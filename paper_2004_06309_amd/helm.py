@@ -46,7 +46,7 @@ class PrecondOpts(C.Structure):
 
 
 class SolveOpts(C.Structure):
-    _fields_ = [("restart", C.c_int32), ("maxit", C.c_int32), ("flags", C.c_int32), ("reserved", C.c_int32)]
+    _fields_ = [("restart", C.c_int32), ("maxit", C.c_int32), ("flags", C.c_int32), ("block", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -256,12 +256,13 @@ class Helm:
     def apply_coarse(self, r, q, stream=None):
         self._check(self.lib.helm_apply_coarse(self.h, _dev_ptr(r), _dev_ptr(q), _stream(stream)))
 
-    def solve(self, B, U, tol=1e-6, restart=50, maxit=1000, x0=False, stream=None):
+    def solve(self, B, U, tol=1e-6, restart=50, maxit=1000, x0=False, stream=None, block=1):
         """Solve A U = B; B, U are (n,) or (nrhs, n) complex128 GPU tensors
-        (each RHS contiguous).  Returns (status, [info dicts])."""
+        (each RHS contiguous); `block` right-hand sides are advanced together.
+        Returns (status, [info dicts])."""
         nrhs = 1 if B.dim() == 1 else B.shape[0]
         info = (SolveInfo * max(nrhs, 1))()
-        opts = SolveOpts(int(restart), int(maxit), HELM_SOLVE_X0 if x0 else 0, 0)
+        opts = SolveOpts(int(restart), int(maxit), HELM_SOLVE_X0 if x0 else 0, int(block))
         rc = self._check(self.lib.helm_solve(self.h, nrhs, _dev_ptr(B), float(tol), C.byref(opts), _dev_ptr(U),
                                              _stream(stream), info), allow=(HELM_ENOCONV,))
         return rc, [{f: getattr(info[i], f) for f, _ in SolveInfo._fields_} for i in range(nrhs)]

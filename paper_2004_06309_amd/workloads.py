@@ -208,3 +208,12 @@ def small_box(n=(6, 5, 4), size=(600.0, 500.0, 400.0), order=2, freq=3.0, n_part
     src = np.array([size[0] * 0.37, size[1] * 0.61, size[2] * 0.29])
     return Workload("small", xyz, tets, order, c.astype(np.complex128), 2 * np.pi * freq, part,
                     int(np.prod(n_parts)), overlap, cx, cy, src, None)
+
+
+def surface_sources(lx: float, ly: float, n_side: int, depth: float = 10.0) -> np.ndarray:
+    """n_side x n_side point sources on a regular grid at the given depth
+    (cell centres of an n_side x n_side partition of the top face)."""
+    xs = (np.arange(n_side) + 0.5) * lx / n_side
+    ys = (np.arange(n_side) + 0.5) * ly / n_side
+    X, Y = np.meshgrid(xs, ys, indexing="ij")
+    return np.stack([X.ravel(), Y.ravel(), np.full(X.size, depth)], axis=1)
