@@ -106,6 +106,9 @@ void bwd_level_block(const Batch& b, int64_t tile0, int64_t ntiles, int S, const
 void sell_spmv_block(int64_t n, int64_t nslices, const int64_t* soff, const int32_t* swidth, const int32_t* perm,
                      const int32_t* col, const double* val, int S, const double* x, const double* b, double* y,
                      hipStream_t s);
+// y = A x (or b - A x) for S interleaved vectors from the CSR copy of A.
+void csr_spmv_block(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, int S, const double* x,
+                    const double* b, double* y, hipStream_t s);
 void spmv_real_block(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, int S, const double* x,
                      double* y, hipStream_t s);
 void prolong_block(int64_t n, const int64_t* ptr, const int32_t* idx, const double* w, int S, const double* xl,

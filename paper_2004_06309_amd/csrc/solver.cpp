@@ -898,8 +898,7 @@ void batch_solve_block(BatchDev& b, int S, const double* in, hipStream_t s, Prof
 }
 
 void sell_block(Ctx& c, int S, const double* x, const double* b, double* y, hipStream_t s) {
-  dev::sell_spmv_block(c.D.n, c.sell_nslices, c.sell_off.p, c.sell_width.p, c.sell_perm.p, c.sell_col.p,
-                       c.sell_val.p, S, x, b, y, s);
+  dev::csr_spmv_block(c.D.n, c.A_ptr.p, c.A_col.p, c.A_val.p, S, x, b, y, s);
 }
 
 // Z = M^{-1} X for S interleaved vectors (eq. 2lvl, or eq. oras one-level).

@@ -148,7 +148,10 @@ def test_complex64_factors(name):
 
 
 @pytest.mark.parametrize("name,nrhs,block,c64", [("tiny", 3, 4, False), ("mid_quarter_2lvl", 5, 4, False),
-                                                 ("mid_quarter_2lvl", 9, 8, True), ("ragged_p2", 2, 2, False)])
+                                                 ("mid_quarter_2lvl", 9, 8, True), ("ragged_p2", 2, 2, False),
+                                                 ("mid_quarter_2lvl", 16, 16, False),
+                                                 ("mid_quarter_2lvl", 13, 16, True),
+                                                 ("small_p2_2lvl", 16, 16, False)])
 def test_block_solve(name, nrhs, block, c64):
     """Pseudo-block GMRES: several right-hand sides advanced together (ragged
     final block included) give, for every right-hand side, a true residual
