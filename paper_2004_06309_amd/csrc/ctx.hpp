@@ -57,6 +57,11 @@ struct BatchHost {
   std::vector<int64_t> lev_f, lev_b;  // task ranges per level
   std::vector<double> bytes_f, bytes_b;  // algorithmic bytes per level
   std::vector<double> pbytes_f, pbytes_b;  // of which panel bytes
+  // staged 16-right-hand-side inputs: supernodes of every level, their
+  // column offsets in the level's staging block, the largest block
+  std::vector<int32_t> gsn_f, gsn_b, sn_r;
+  std::vector<int64_t> gsn_lev_f, gsn_lev_b, goff_f, goff_b;
+  int64_t stage_cols = 0;
   int64_t nf = 0, nb = 0, nu = 0;     // panel entries (fwd, bwd), update entries
   int32_t max_front = 0;
   double flops = 0;
@@ -79,6 +84,11 @@ struct BatchDev {
   // multi-right-hand-side work vectors (interleaved, widest block so far)
   int blk_S = 0;
   DVec<double> ubuf_b, y_b, x_b;
+  DVec<int32_t> gsn_f, gsn_b, sn_r;
+  DVec<int64_t> goff_f, goff_b;
+  std::vector<int64_t> gsn_lev_f, gsn_lev_b;
+  int64_t stage_cols = 0;
+  DVec<unsigned char> stage;
   dev::Batch view() const;
   void reset() {
     for (auto* v : {&c0, &w, &uoff, &frow0, &rows, &bidx, &fcon_ptr, &fcon_idx}) v->reset();
@@ -103,6 +113,15 @@ struct BatchDev {
     ubuf_b.reset();
     y_b.reset();
     x_b.reset();
+    gsn_f.reset();
+    gsn_b.reset();
+    sn_r.reset();
+    goff_f.reset();
+    goff_b.reset();
+    gsn_lev_f.clear();
+    gsn_lev_b.clear();
+    stage_cols = 0;
+    stage.reset();
     npos = 0;
   }
 };

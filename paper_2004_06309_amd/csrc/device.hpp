@@ -49,6 +49,9 @@ struct Batch {
   const int32_t* bidx = nullptr;   // pivot position -> input-vector index
   const int32_t* fcon_ptr = nullptr; // front row -> child update entries
   const int32_t* fcon_idx = nullptr;
+  const int32_t* sn_r = nullptr;   // |R_s|
+  const int64_t* goff_f = nullptr; // column offset of the supernode's staged block (forward level scratch)
+  const int64_t* goff_b = nullptr; // same for the backward level scratch
   const void* pf = nullptr;        // forward panels (complex128, or complex64 when c64)
   const void* pb = nullptr;        // backward panels
   int c64 = 0;
@@ -103,6 +106,13 @@ void fwd_level_block(const Batch& b, int64_t tile0, int64_t ntiles, int S, const
                      bool coarse, hipStream_t s);
 void bwd_level_block(const Batch& b, int64_t tile0, int64_t ntiles, int S, const double* yb, double* xb, bool coarse,
                      hipStream_t s);
+// 16 right-hand sides on MFMA: stage every supernode's input block of the
+// level once (gather kernels, one workgroup per supernode of `sns`), then
+// one 4-wave workgroup per tile reads its B operands from the staged block.
+void fwd_level_mfma(const Batch& b, const int32_t* sns, int64_t nsn, int64_t tile0, int64_t ntiles,
+                    const double* bin, double* yb, double* ubb, void* stage, bool coarse, hipStream_t s);
+void bwd_level_mfma(const Batch& b, const int32_t* sns, int64_t nsn, int64_t tile0, int64_t ntiles,
+                    const double* yb, double* xb, void* stage, bool coarse, hipStream_t s);
 void sell_spmv_block(int64_t n, int64_t nslices, const int64_t* soff, const int32_t* swidth, const int32_t* perm,
                      const int32_t* col, const double* val, int S, const double* x, const double* b, double* y,
                      hipStream_t s);

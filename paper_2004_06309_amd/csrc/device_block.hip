@@ -309,6 +309,137 @@ __global__ __launch_bounds__(64) void bwd_mfma_kernel(const Tile* __restrict__ t
     }
 }
 
+// ---- staged MFMA form ------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(kWG) void gather_fwd_kernel(const int32_t* __restrict__ sns, Batch b,
+                                                         const double2* __restrict__ bin,
+                                                         const double2* __restrict__ ubb,
+                                                         typename Mf<T>::C2* __restrict__ G) {
+  using C2 = typename Mf<T>::C2;
+  const int sn = sns[blockIdx.x];
+  const int c0 = b.sn_c0[sn], w = b.sn_w[sn], frow0 = b.sn_frow0[sn];
+  C2* g = G + b.goff_f[sn] * 16;
+  for (int e = threadIdx.x; e < w * 16; e += kWG) {
+    const int k = e >> 4, r = e & 15;
+    double2 v = bin[(int64_t)b.bidx[c0 + k] * 16 + r];
+    const int fr = frow0 + k;
+    for (int q = b.fcon_ptr[fr]; q < b.fcon_ptr[fr + 1]; ++q) {
+      const double2 u = ubb[(int64_t)b.fcon_idx[q] * 16 + r];
+      v.x -= u.x;
+      v.y -= u.y;
+    }
+    g[e] = C2{(T)v.x, (T)v.y};
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(kWG) void gather_bwd_kernel(const int32_t* __restrict__ sns, Batch b,
+                                                         const double2* __restrict__ yb,
+                                                         const double2* __restrict__ xb,
+                                                         typename Mf<T>::C2* __restrict__ G) {
+  using C2 = typename Mf<T>::C2;
+  const int sn = sns[blockIdx.x];
+  const int c0 = b.sn_c0[sn], w = b.sn_w[sn], r_ = b.sn_r[sn];
+  const int64_t roff = b.sn_roff[sn];
+  C2* g = G + b.goff_b[sn] * 16;
+  for (int e = threadIdx.x; e < (w + r_) * 16; e += kWG) {
+    const int c = e >> 4, r = e & 15;
+    const double2 v = c < w ? yb[(int64_t)(c0 + c) * 16 + r] : xb[(int64_t)b.rows[roff + (c - w)] * 16 + r];
+    g[e] = C2{(T)v.x, (T)v.y};
+  }
+}
+
+// 4 waves per tile: wave q accumulates the k-steps q, q + 4, ... of the
+// tile, then the partial accumulators are summed through LDS.
+template <class T, int kFwd>
+__device__ __forceinline__ void mfma_tile4(const Tile& t, const typename Mf<T>::C2* __restrict__ P,
+                                           const typename Mf<T>::C2* __restrict__ Bk, typename Mf<T>::V4* dre,
+                                           typename Mf<T>::V4* dim) {
+  using C2 = typename Mf<T>::C2;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
+  const int nr = t.nrows, cn = t.ncols, nrb = (nr + 15) >> 4;
+  for (int k0 = 4 * wv; k0 < cn; k0 += 16) {
+    const int k = k0 + lk;
+    const C2 bv = k < cn ? Bk[(int64_t)k * 16 + lr] : C2{0, 0};
+    C2 a[4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      const int row = 16 * rb + lr;
+      a[rb] = (rb < nrb && row < nr && k < cn) ? P[(int64_t)k * nr + row] : C2{0, 0};
+    }
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      if (rb >= nrb) break;
+      dre[rb] = Mf<T>::mma(a[rb].x, bv.x, dre[rb]);
+      dre[rb] = Mf<T>::mma(-a[rb].y, bv.y, dre[rb]);
+      dim[rb] = Mf<T>::mma(a[rb].x, bv.y, dim[rb]);
+      dim[rb] = Mf<T>::mma(a[rb].y, bv.x, dim[rb]);
+    }
+  }
+}
+
+template <class T, int kFwd, int kCoarse>
+__global__ __launch_bounds__(kWG) void level_mfma_kernel(const Tile* __restrict__ tiles, Batch b,
+                                                         const typename Mf<T>::C2* __restrict__ G,
+                                                         double2* __restrict__ out, double2* __restrict__ ubb) {
+  using C2 = typename Mf<T>::C2;
+  using V4 = typename Mf<T>::V4;
+  // partial sums of the 4 waves, two row blocks at a time: [wave][rb2][j][lane]
+  __shared__ C2 red[4][2][4][64];
+  const Tile t = tiles[blockIdx.x];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int sn = t.sn, c0 = b.sn_c0[sn], w = b.sn_w[sn];
+  const C2* __restrict__ P = reinterpret_cast<const C2*>(kFwd ? b.pf : b.pb) + t.off;
+  const C2* Bk = G + ((kFwd ? b.goff_f[sn] : b.goff_b[sn]) + t.col0) * 16;
+  V4 dre[4], dim[4];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) dre[rb] = dim[rb] = V4{0, 0, 0, 0};
+  mfma_tile4<T, kFwd>(t, P, Bk, dre, dim);
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) red[wv][q][j][lane] = C2{dre[2 * h + q][j], dim[2 * h + q][j]};
+    __syncthreads();
+    // 512 outputs (32 rows x 16 right-hand sides) of this half, 2 per thread
+    for (int o = threadIdx.x; o < 512; o += kWG) {
+      const int rloc = 32 * h + (o >> 4), r = o & 15;
+      if (rloc < t.nrows) {
+        const int q = (rloc >> 4) - 2 * h, rr = rloc & 15;
+        int l, j;
+        if (sizeof(T) == 8) {  // FP64: row = 4 j + l / 16
+          j = rr >> 2;
+          l = (rr & 3) * 16 + r;
+        } else {               // FP32: row = 4 (l / 16) + j
+          j = rr & 3;
+          l = (rr >> 2) * 16 + r;
+        }
+        double ar = 0, ai = 0;
+#pragma unroll
+        for (int wq = 0; wq < 4; ++wq) {
+          ar += (double)red[wq][q][j][l].x;
+          ai += (double)red[wq][q][j][l].y;
+        }
+        const int row = t.row0 + rloc;
+        if (!kFwd) {
+          out[(int64_t)(c0 + row) * 16 + r] = make_double2(ar, ai);
+        } else if (row < w) {
+          out[(int64_t)(c0 + row) * 16 + r] = make_double2(ar, ai);
+        } else {
+          const int fr = b.sn_frow0[sn] + row;
+          for (int e = b.fcon_ptr[fr]; e < b.fcon_ptr[fr + 1]; ++e) {
+            const double2 u = ubb[(int64_t)b.fcon_idx[e] * 16 + r];
+            ar += u.x;
+            ai += u.y;
+          }
+          ubb[(int64_t)(b.sn_uoff[sn] + row - w) * 16 + r] = make_double2(ar, ai);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <int S>
 __global__ __launch_bounds__(kWG) void sell_block_kernel(int64_t n, int64_t nslices, const int64_t* __restrict__ soff,
                                                          const int32_t* __restrict__ swidth,
@@ -519,6 +650,45 @@ void bwd_level_block(const Batch& b, int64_t tile0, int64_t ntiles, int S, const
     else
       bwd_block_kernel<double2, W, 0><<<(unsigned)ntiles, 64, 0, s>>>(t, b, y, x);
   });
+}
+
+void fwd_level_mfma(const Batch& b, const int32_t* sns, int64_t nsn, int64_t tile0, int64_t ntiles,
+                    const double* bin, double* yb, double* ubb, void* stage, bool coarse, hipStream_t s) {
+  if (ntiles <= 0) return;
+  auto in = reinterpret_cast<const double2*>(bin);
+  auto y = reinterpret_cast<double2*>(yb);
+  auto u = reinterpret_cast<double2*>(ubb);
+  if (b.c64 && !coarse) {
+    auto G = reinterpret_cast<float2*>(stage);
+    gather_fwd_kernel<float><<<(unsigned)nsn, kWG, 0, s>>>(sns, b, in, u, G);
+    level_mfma_kernel<float, 1, 0><<<(unsigned)ntiles, kWG, 0, s>>>(b.tf + tile0, b, G, y, u);
+  } else {
+    auto G = reinterpret_cast<double2*>(stage);
+    gather_fwd_kernel<double><<<(unsigned)nsn, kWG, 0, s>>>(sns, b, in, u, G);
+    if (coarse)
+      level_mfma_kernel<double, 1, 1><<<(unsigned)ntiles, kWG, 0, s>>>(b.tf + tile0, b, G, y, u);
+    else
+      level_mfma_kernel<double, 1, 0><<<(unsigned)ntiles, kWG, 0, s>>>(b.tf + tile0, b, G, y, u);
+  }
+}
+
+void bwd_level_mfma(const Batch& b, const int32_t* sns, int64_t nsn, int64_t tile0, int64_t ntiles,
+                    const double* yb, double* xb, void* stage, bool coarse, hipStream_t s) {
+  if (ntiles <= 0) return;
+  auto y = reinterpret_cast<const double2*>(yb);
+  auto x = reinterpret_cast<double2*>(xb);
+  if (b.c64 && !coarse) {
+    auto G = reinterpret_cast<float2*>(stage);
+    gather_bwd_kernel<float><<<(unsigned)nsn, kWG, 0, s>>>(sns, b, y, x, G);
+    level_mfma_kernel<float, 0, 0><<<(unsigned)ntiles, kWG, 0, s>>>(b.tb + tile0, b, G, x, nullptr);
+  } else {
+    auto G = reinterpret_cast<double2*>(stage);
+    gather_bwd_kernel<double><<<(unsigned)nsn, kWG, 0, s>>>(sns, b, y, x, G);
+    if (coarse)
+      level_mfma_kernel<double, 0, 1><<<(unsigned)ntiles, kWG, 0, s>>>(b.tb + tile0, b, G, x, nullptr);
+    else
+      level_mfma_kernel<double, 0, 0><<<(unsigned)ntiles, kWG, 0, s>>>(b.tb + tile0, b, G, x, nullptr);
+  }
 }
 
 void sell_spmv_block(int64_t n, int64_t nslices, const int64_t* soff, const int32_t* swidth, const int32_t* perm,

@@ -56,6 +56,9 @@ dev::Batch BatchDev::view() const {
   b.kf = kf.p;
   b.kb = kb.p;
   b.c64 = c64;
+  b.sn_r = sn_r.p;
+  b.goff_f = goff_f.p;
+  b.goff_b = goff_b.p;
   b.sn_c0 = c0.p;
   b.sn_w = w.p;
   b.sn_uoff = uoff.p;
@@ -283,6 +286,30 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
       lev.push_back((int64_t)tasks.size());
     }
   };
+  // supernodes of every level and their offsets in the level's staging block
+  B.sn_r.resize(nsn);
+  for (int64_t s = 0; s < nsn; ++s) B.sn_r[s] = (int32_t)r_of(s);
+  B.goff_f.assign(nsn, 0);
+  B.goff_b.assign(nsn, 0);
+  auto stage_levels = [&](const std::vector<std::vector<dev::Tile>>& levels, bool fwd, std::vector<int32_t>& gsn,
+                          std::vector<int64_t>& glev, std::vector<int64_t>& goff) {
+    glev.assign(1, 0);
+    for (const auto& l : levels) {
+      int64_t cols = 0;
+      int32_t last = -1;
+      for (const auto& t : l) {
+        if (t.sn == last) continue;
+        last = t.sn;
+        gsn.push_back(t.sn);
+        goff[t.sn] = cols;
+        cols += B.w[t.sn] + (fwd ? 0 : B.sn_r[t.sn]);
+      }
+      glev.push_back((int64_t)gsn.size());
+      B.stage_cols = std::max(B.stage_cols, cols);
+    }
+  };
+  stage_levels(lf, true, B.gsn_f, B.gsn_lev_f, B.goff_f);
+  stage_levels(lb, false, B.gsn_b, B.gsn_lev_b, B.goff_b);
   make_tasks(lf, true, B.tf, B.kf, B.lev_f, B.bytes_f, B.pbytes_f);
   make_tasks(lb, false, B.tb, B.kb, B.lev_b, B.bytes_b, B.pbytes_b);
 }
@@ -364,6 +391,14 @@ void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symb
   };
   Dv.tiles_f = tile_ranges(B.kf, B.lev_f);
   Dv.tiles_b = tile_ranges(B.kb, B.lev_b);
+  Dv.gsn_f.upload(B.gsn_f);
+  Dv.gsn_b.upload(B.gsn_b);
+  Dv.sn_r.upload(B.sn_r);
+  Dv.goff_f.upload(B.goff_f);
+  Dv.goff_b.upload(B.goff_b);
+  Dv.gsn_lev_f = B.gsn_lev_f;
+  Dv.gsn_lev_b = B.gsn_lev_b;
+  Dv.stage_cols = B.stage_cols;
   Dv.tf.upload(B.tf);
   Dv.tb.upload(B.tb);
   Dv.kf.upload(B.kf);
@@ -845,6 +880,7 @@ void ensure_batch_block(BatchDev& b, int S) {
   b.ubuf_b.alloc(2 * nu * S);
   b.y_b.alloc(2 * np * S);
   b.x_b.alloc(2 * np * S);
+  if (S == dev::kMaxBlock) b.stage.alloc(sizeof(double) * 2 * dev::kMaxBlock * std::max<int64_t>(b.stage_cols, 1));
   b.blk_S = S;
 }
 
@@ -885,14 +921,23 @@ void ensure_block(Ctx& c, int m, int S) {
 void batch_solve_block(BatchDev& b, int S, const double* in, hipStream_t s, Profiler* prof, bool fine) {
   dev::Batch v = b.view();
   const bool each = prof && prof->on && fine;
+  const bool mfma = S == dev::kMaxBlock;
   for (size_t l = 0; l + 1 < b.tiles_f.size(); ++l) {
     if (each) prof->begin(s);
-    dev::fwd_level_block(v, b.tiles_f[l], b.tiles_f[l + 1] - b.tiles_f[l], S, in, b.y_b.p, b.ubuf_b.p, !fine, s);
+    if (mfma)
+      dev::fwd_level_mfma(v, b.gsn_f.p + b.gsn_lev_f[l], b.gsn_lev_f[l + 1] - b.gsn_lev_f[l], b.tiles_f[l],
+                          b.tiles_f[l + 1] - b.tiles_f[l], in, b.y_b.p, b.ubuf_b.p, b.stage.p, !fine, s);
+    else
+      dev::fwd_level_block(v, b.tiles_f[l], b.tiles_f[l + 1] - b.tiles_f[l], S, in, b.y_b.p, b.ubuf_b.p, !fine, s);
     if (each) prof->end(HELM_K_TRSV_FWD, b.pbytes_f[l] + S * (b.bytes_f[l] - b.pbytes_f[l]), s);
   }
   for (size_t l = 0; l + 1 < b.tiles_b.size(); ++l) {
     if (each) prof->begin(s);
-    dev::bwd_level_block(v, b.tiles_b[l], b.tiles_b[l + 1] - b.tiles_b[l], S, b.y_b.p, b.x_b.p, !fine, s);
+    if (mfma)
+      dev::bwd_level_mfma(v, b.gsn_b.p + b.gsn_lev_b[l], b.gsn_lev_b[l + 1] - b.gsn_lev_b[l], b.tiles_b[l],
+                          b.tiles_b[l + 1] - b.tiles_b[l], b.y_b.p, b.x_b.p, b.stage.p, !fine, s);
+    else
+      dev::bwd_level_block(v, b.tiles_b[l], b.tiles_b[l + 1] - b.tiles_b[l], S, b.y_b.p, b.x_b.p, !fine, s);
     if (each) prof->end(HELM_K_TRSV_BWD, b.pbytes_b[l] + S * (b.bytes_b[l] - b.pbytes_b[l]), s);
   }
 }
