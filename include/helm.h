@@ -68,7 +68,10 @@ typedef struct helm_precond_opts {
                               panel products still accumulate in FP64 and
                               the coarse factors stay complex128          */
   int32_t coarse_leaf_size;  /* leaf size of the coarse ordering, 0 = 256  */
-  int32_t reserved[5];
+  int32_t tile_rows;       /* rows per solve tile of the subdomain factors:
+                              16, 32 or 64; 0 = 64                         */
+  int32_t coarse_tile_rows;  /* same for the coarse factor; 0 = 16         */
+  int32_t reserved[3];
 } helm_precond_opts;
 
 enum {
@@ -105,7 +108,8 @@ typedef struct helm_precond_stats {
   double setup_seconds;    /* wall time of the last helm_precond_setup     */
   double factor_flops;     /* complex multiply-adds x 8 in the factorisation */
   int32_t factor_c64;      /* 1 if the fine factors are stored in complex64 */
-  int32_t reserved;
+  int32_t coarse_grid;     /* workgroups of the one-launch cooperative coarse
+                              solve; 0 = one launch per level              */
 } helm_precond_stats;
 
 /* Create a context on HIP device `device_ordinal`; -1 creates a host-only
@@ -174,8 +178,13 @@ int helm_coarse_get(const helm_ctx* ctx, int64_t* rowptr, int32_t* col, double* 
 /* --- Device operations (device pointers to c128[n]; stream = hipStream_t or
  *     NULL for the null stream).  Asynchronous with respect to the host. --- */
 
-/* SpMV storage used by every product with A: 0 = the faster of the two as
- * timed at helm_assemble (default), 1 = CSR, 2 = sliced ELL (64-row slices). */
+/* SpMV storage used by every single-vector product with A: 0 = the fastest
+ * as timed at helm_assemble (default), 1 = CSR in dof order, 2 = sliced ELL
+ * (64-row slices of rows taken in Morton order of the dof positions), 3 = CSR
+ * with each XCD sweeping its own contiguous row range (ranges of equal entry
+ * counts).  Kinds 1 and 3 also fix the order of the multi-right-hand-side
+ * products (otherwise the faster one as timed on first use).  HELM_EINVAL for
+ * any other kind. */
 int helm_set_spmv(helm_ctx* ctx, int kind);
 
 /* y = A x  (complex SpMV). */

@@ -89,6 +89,9 @@ struct BatchDev {
   std::vector<int64_t> gsn_lev_f, gsn_lev_b;
   int64_t stage_cols = 0;
   DVec<unsigned char> stage;
+  // > 0: grid of the single cooperative launch that runs the whole solve
+  int coop = 0;
+  dev::LevelRanges ranges{};
   dev::Batch view() const;
   void reset() {
     for (auto* v : {&c0, &w, &uoff, &frow0, &rows, &bidx, &fcon_ptr, &fcon_idx}) v->reset();
@@ -100,6 +103,7 @@ struct BatchDev {
     kf.reset();
     kb.reset();
     c64 = 0;
+    coop = 0;
     roff.reset();
     lev_f.clear();
     lev_b.clear();
@@ -155,9 +159,15 @@ struct Ctx {
   Symbolic Esym;
   helm_precond_stats stats{};
   // device operators
-  int g_A = 8, g_ZT = 4, g_Zp = 4;  // lanes per row, picked by timing at setup
-  bool use_sell = false;             // sliced ELL in use
-  bool sell_auto = false;            // what the timing at setup picked
+  // lanes per row of the CSR SpMV of A (plain order, XCD row ranges) and
+  // of Z^T / Z, picked by timing at setup
+  int g_A = dev::spmv_cfg(8, 1), g_X = dev::spmv_cfg(8, 1), g_ZT = 4, g_Zp = 4;
+  int spmv_kind = 1;   // in use: 1 CSR, 2 sliced ELL, 3 CSR over XCD row ranges
+  int spmv_auto = 1;   // the fastest at assembly
+  bool blk_xcd = false;     // multi-vector SpMV over XCD row ranges (faster on first use)
+  int blk_force = 0;        // 1 / 3: multi-vector SpMV order fixed by helm_set_spmv
+  DVec<int64_t> A_xr;       // 9 row bounds: XCD k sweeps [A_xr[k], A_xr[k+1]), equal entries
+  int64_t A_xrows = 0;      // longest of those ranges
   int64_t sell_nslices = 0;
   DVec<int64_t> sell_off;
   DVec<int32_t> sell_width, sell_perm, sell_col;

@@ -10,6 +10,7 @@
 //  - prolong: partition-of-unity weighted sum of the local solutions.
 //  - Gram-Schmidt reductions: per-block partial sums reduced in a fixed order
 //    (no atomics), so every result is bitwise repeatable.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -32,6 +33,19 @@ __device__ __forceinline__ void cfma(double& ar, double& ai, double2 a, double2 
 __device__ __forceinline__ double2 widen(double2 a) { return a; }
 __device__ __forceinline__ double2 widen(float2 a) { return make_double2((double)a.x, (double)a.y); }
 
+// Panels are streamed once per sweep: non-temporal loads keep them from
+// evicting the reused vectors from the caches.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ldp(const double2* p) {
+  const dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float2 ldp(const float2* p) {
+  const fvec2 v = __builtin_nontemporal_load(reinterpret_cast<const fvec2*>(p));
+  return make_float2(v.x, v.y);
+}
+
 // Streams columns k0, k0 + ks, ... (< k1) of a tile (column-major, ld = nr)
 // against vin, eight independent loads in flight per lane.
 template <class PT>
@@ -42,14 +56,14 @@ __device__ __forceinline__ void tile_dot(const PT* __restrict__ p, int nr, const
   for (; k + 7 * ks < k1; k += 8 * ks) {
     PT a[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) a[u] = p[(int64_t)(k + u * ks) * nr];
+    for (int u = 0; u < 8; ++u) a[u] = ldp(p + (int64_t)(k + u * ks) * nr);
 #pragma unroll
     for (int u = 0; u < 8; u += 2) {
       cfma(ar, ai, widen(a[u]), vin[k + u * ks]);
       cfma(br, bi, widen(a[u + 1]), vin[k + (u + 1) * ks]);
     }
   }
-  for (; k < k1; k += ks) cfma(ar, ai, widen(p[(int64_t)k * nr]), vin[k]);
+  for (; k < k1; k += ks) cfma(ar, ai, widen(ldp(p + (int64_t)k * nr)), vin[k]);
   ar += br;
   ai += bi;
 }
@@ -78,12 +92,11 @@ __device__ __forceinline__ Split split_of(const Task& task) {
   return sp;
 }
 
-template <class PT, int kCoarse>
-__global__ __launch_bounds__(kWG) void fwd_level_kernel(const Task* __restrict__ tasks, Batch b,
-                                                        const double2* __restrict__ bin) {
-  __shared__ double2 vin[kChunk];
-  __shared__ double2 red[4][64];
-  const Task task = tasks[blockIdx.x];
+// One workgroup task of a forward level (vin: kChunk LDS entries, red:
+// 4 x 64 LDS entries).
+template <class PT>
+__device__ __forceinline__ void fwd_task(const Task& task, const Batch& b, const double2* __restrict__ bin,
+                                         double2* vin, double2 (*red)[64]) {
   const Split sp = split_of(task);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   Tile t{};
@@ -149,11 +162,8 @@ __global__ __launch_bounds__(kWG) void fwd_level_kernel(const Task* __restrict__
   }
 }
 
-template <class PT, int kCoarse>
-__global__ __launch_bounds__(kWG) void bwd_level_kernel(const Task* __restrict__ tasks, Batch b) {
-  __shared__ double2 vin[kChunk];
-  __shared__ double2 red[4][64];
-  const Task task = tasks[blockIdx.x];
+template <class PT>
+__device__ __forceinline__ void bwd_task(const Task& task, const Batch& b, double2* vin, double2 (*red)[64]) {
   const Split sp = split_of(task);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   Tile t{};
@@ -200,24 +210,94 @@ __global__ __launch_bounds__(kWG) void bwd_level_kernel(const Task* __restrict__
   }
 }
 
-template <int G>
+template <class PT, int kCoarse>
+__global__ __launch_bounds__(kWG) void fwd_level_kernel(const Task* __restrict__ tasks, Batch b,
+                                                        const double2* __restrict__ bin) {
+  __shared__ double2 vin[kChunk];
+  __shared__ double2 red[4][64];
+  fwd_task<PT>(tasks[blockIdx.x], b, bin, vin, red);
+}
+
+template <class PT, int kCoarse>
+__global__ __launch_bounds__(kWG) void bwd_level_kernel(const Task* __restrict__ tasks, Batch b) {
+  __shared__ double2 vin[kChunk];
+  __shared__ double2 red[4][64];
+  bwd_task<PT>(tasks[blockIdx.x], b, vin, red);
+}
+
+// Whole forward + backward solve of a small batch (the coarse matrix) in one
+// cooperative launch: the workgroups sweep each level's tasks and meet at a
+// grid-wide barrier before the next level, instead of one launch per level.
+__global__ __launch_bounds__(kWG) void batch_solve_coop_kernel(Batch b, const double2* __restrict__ bin,
+                                                               LevelRanges lv) {
+  __shared__ double2 vin[kChunk];
+  __shared__ double2 red[4][64];
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  for (int l = 0; l < lv.nf; ++l) {
+    for (int64_t t = lv.f[l] + blockIdx.x; t < lv.f[l + 1]; t += gridDim.x) {
+      fwd_task<double2>(b.kf[t], b, bin, vin, red);
+      __syncthreads();
+    }
+    grid.sync();
+  }
+  for (int l = 0; l < lv.nb; ++l) {
+    for (int64_t t = lv.b[l] + blockIdx.x; t < lv.b[l + 1]; t += gridDim.x) {
+      bwd_task<double2>(b.kb[t], b, vin, red);
+      __syncthreads();
+    }
+    grid.sync();
+  }
+}
+
+// XCD-aware workgroup order for grids that are a multiple of 8: workgroups
+// are dealt round-robin to the 8 XCDs, so workgroup b takes block
+// (b % 8) * per + b / 8 and every XCD sweeps a contiguous eighth of the
+// blocks, keeping the x entries that block gathers in its own L2.
+__device__ __forceinline__ int64_t xcd_block() {
+  const unsigned per = gridDim.x / 8;
+  return (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+}
+
+// One row of a CSR matrix per G lanes; each lane takes U entries per pass
+// (entries base + u G + lane), loading all U columns, then all U values and
+// x entries before the multiply-adds, so a wave keeps U gathers in flight
+// instead of one dependent col -> x chain per entry.  With kXcd, workgroup b
+// runs on XCD b % 8 (workgroups are dealt round-robin) and takes the
+// (b / 8)-th block of that XCD's row range [xr[b % 8], xr[b % 8 + 1]).
+template <int G, int U, bool kXcd>
 __global__ __launch_bounds__(kWG) void spmv_kernel(int64_t n, const int64_t* __restrict__ ptr,
                                                    const int32_t* __restrict__ col, const double2* __restrict__ val,
-                                                   const double2* __restrict__ x, const double2* __restrict__ bvec,
-                                                   double2* __restrict__ y) {
-  const int64_t row = ((int64_t)blockIdx.x * kWG + threadIdx.x) / G;
+                                                   const int64_t* __restrict__ xr, const double2* __restrict__ x,
+                                                   const double2* __restrict__ bvec, double2* __restrict__ y) {
+  int64_t row, end = n;
+  if (kXcd) {
+    row = xr[blockIdx.x & 7] + ((int64_t)(blockIdx.x >> 3) * kWG + threadIdx.x) / G;
+    end = xr[(blockIdx.x & 7) + 1];
+  } else {
+    row = ((int64_t)blockIdx.x * kWG + threadIdx.x) / G;
+  }
   const int l = threadIdx.x % G;
   double ar = 0, ai = 0;
-  if (row < n) {
+  if (row < end) {
     const int64_t p1 = ptr[row + 1];
-    for (int64_t p = ptr[row] + l; p < p1; p += G) cfma(ar, ai, val[p], x[col[p]]);
+    for (int64_t base = ptr[row] + l; base < p1; base += G * U) {
+      int c[U];
+      double2 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) c[u] = base + u * G < p1 ? col[base + u * G] : -1;
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = base + u * G < p1 ? val[base + u * G] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (c[u] >= 0) cfma(ar, ai, v[u], x[c[u]]);
+    }
   }
 #pragma unroll
   for (int o = G / 2; o > 0; o >>= 1) {
     ar += __shfl_xor(ar, o, G);
     ai += __shfl_xor(ai, o, G);
   }
-  if (row < n && l == 0) {
+  if (row < end && l == 0) {
     if (bvec) {
       double2 bb = bvec[row];
       y[row] = make_double2(bb.x - ar, bb.y - ai);
@@ -543,6 +623,8 @@ __global__ __launch_bounds__(kWG) void copy_kernel(int64_t n, const double* __re
 }
 
 inline unsigned blocks_for(int64_t n, int per = kWG) { return (unsigned)((n + per - 1) / per); }
+// Same, rounded up to a multiple of 8 (grids of kernels that use xcd_block).
+inline unsigned blocks8_for(int64_t n) { return (blocks_for(n) + 7) / 8 * 8; }
 
 }  // namespace
 
@@ -571,20 +653,71 @@ void bwd_level(const Batch& b, int64_t task0, int64_t ntasks, bool coarse, hipSt
     bwd_level_kernel<double2, 0><<<(unsigned)ntasks, kWG, 0, s>>>(k, b);
 }
 
-void spmv(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const double* x, const double* b,
-          double* y, int G, hipStream_t s) {
+int coop_grid() {
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_solve_coop_kernel, kWG, 0) != hipSuccess) return 0;
+  return per * ncu;
+}
+
+hipError_t batch_solve_coop(const Batch& b, const double* bin, const LevelRanges& lv, int grid, hipStream_t s) {
+  Batch bb = b;
+  const double2* in = reinterpret_cast<const double2*>(bin);
+  LevelRanges l = lv;
+  void* args[] = {&bb, &in, &l};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(batch_solve_coop_kernel), dim3(grid), dim3(kWG),
+                                    args, 0, s);
+}
+
+template <int G, int U, bool R>
+void spmv_go(int64_t n, const int64_t* ptr, const int32_t* col, const double2* v2, const int64_t* xr, int64_t xrows,
+             const double2* x2, const double2* b2, double2* y2, hipStream_t s) {
+  // with R, 8 x the block count of the longest XCD range, else one block per kWG / G rows
+  const unsigned grid = R ? 8 * blocks_for(xrows * G) : blocks_for(n * G);
+  spmv_kernel<G, U, R><<<grid, kWG, 0, s>>>(n, ptr, col, v2, xr, x2, b2, y2);
+}
+
+template <bool R>
+void spmv_launch(int64_t n, const int64_t* ptr, const int32_t* col, const double2* v2, const int64_t* xr,
+                 int64_t xrows, const double2* x2, const double2* b2, double2* y2, int cfg, hipStream_t s) {
+  switch (cfg) {
+    case spmv_cfg(4, 4): spmv_go<4, 4, R>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
+    case spmv_cfg(4, 8): spmv_go<4, 8, R>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
+    case spmv_cfg(8, 1): spmv_go<8, 1, R>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
+    case spmv_cfg(8, 2): spmv_go<8, 2, R>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
+    case spmv_cfg(8, 4): spmv_go<8, 4, R>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
+    case spmv_cfg(16, 1): spmv_go<16, 1, R>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
+    case spmv_cfg(16, 2): spmv_go<16, 2, R>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
+    case spmv_cfg(32, 1): spmv_go<32, 1, R>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
+    default: spmv_go<4, 1, R>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
+  }
+}
+
+int64_t xcd_ranges(int64_t n, const int64_t* ptr, int64_t xr[9]) {
+  xr[0] = 0;
+  int64_t r = 0, longest = 0;
+  for (int k = 1; k < 8; ++k) {
+    const int64_t target = (ptr[n] * k) / 8;
+    while (r < n && ptr[r] < target) ++r;
+    xr[k] = r;
+  }
+  xr[8] = n;
+  for (int k = 0; k < 8; ++k) longest = std::max<int64_t>(longest, xr[k + 1] - xr[k]);
+  return longest;
+}
+
+void spmv(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const int64_t* xr, int64_t xrows,
+          const double* x, const double* b, double* y, int cfg, hipStream_t s) {
   if (n <= 0) return;
   auto v2 = reinterpret_cast<const double2*>(val);
   auto x2 = reinterpret_cast<const double2*>(x);
   auto b2 = reinterpret_cast<const double2*>(b);
   auto y2 = reinterpret_cast<double2*>(y);
-  switch (G) {
-    case 4: spmv_kernel<4><<<blocks_for(n * 4), kWG, 0, s>>>(n, ptr, col, v2, x2, b2, y2); break;
-    case 16: spmv_kernel<16><<<blocks_for(n * 16), kWG, 0, s>>>(n, ptr, col, v2, x2, b2, y2); break;
-    case 32: spmv_kernel<32><<<blocks_for(n * 32), kWG, 0, s>>>(n, ptr, col, v2, x2, b2, y2); break;
-    case 64: spmv_kernel<64><<<blocks_for(n * 64), kWG, 0, s>>>(n, ptr, col, v2, x2, b2, y2); break;
-    default: spmv_kernel<8><<<blocks_for(n * 8), kWG, 0, s>>>(n, ptr, col, v2, x2, b2, y2); break;
-  }
+  if (xr)
+    spmv_launch<true>(n, ptr, col, v2, xr, xrows, x2, b2, y2, cfg, s);
+  else
+    spmv_launch<false>(n, ptr, col, v2, nullptr, 0, x2, b2, y2, cfg, s);
 }
 
 void sell_spmv(int64_t n, int64_t nslices, const int64_t* soff, const int32_t* swidth, const int32_t* perm,

@@ -64,13 +64,32 @@ struct Batch {
 // coarse selects a separate instantiation so profiles tell the two apart.
 void fwd_level(const Batch& b, int64_t task0, int64_t ntasks, const double* bin, bool coarse, hipStream_t s);
 void bwd_level(const Batch& b, int64_t task0, int64_t ntasks, bool coarse, hipStream_t s);
+// Task ranges of every level of a batch (a kernel argument).
+constexpr int kMaxLevels = 40;
+struct LevelRanges {
+  int nf, nb;
+  int64_t f[kMaxLevels + 1], b[kMaxLevels + 1];
+};
+// Largest co-resident grid of the cooperative batch solve (0 if unknown).
+int coop_grid();
+// Forward + backward solve of a complex128 batch in one cooperative launch.
+hipError_t batch_solve_coop(const Batch& b, const double* bin, const LevelRanges& lv, int grid, hipStream_t s);
 // Waves per tile chosen for a tile with ncols input columns.
 int waves_per_tile(int ncols);
 
-// y = A x, or y = b - A x when b != nullptr (complex CSR); G lanes per row
-// (4, 8, 16, 32 or 64).
-void spmv(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const double* x, const double* b,
-          double* y, int G, hipStream_t s);
+// Tile shape of the CSR SpMV: G lanes per row, U entries per lane per pass.
+constexpr int spmv_cfg(int G, int U) { return G | (U << 8); }
+// Shapes the CSR SpMV is built for.
+constexpr int kSpmvCfgs[] = {spmv_cfg(4, 1),  spmv_cfg(4, 4),  spmv_cfg(4, 8),  spmv_cfg(8, 1), spmv_cfg(8, 2),
+                             spmv_cfg(8, 4),  spmv_cfg(16, 1), spmv_cfg(16, 2), spmv_cfg(32, 1)};
+// y = A x, or y = b - A x when b != nullptr (complex CSR) with tile shape
+// cfg (one of kSpmvCfgs).  xr (device, 9 entries, or nullptr): row ranges
+// [xr[k], xr[k+1]) swept by XCD k; xrows = the longest range.
+void spmv(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const int64_t* xr, int64_t xrows,
+          const double* x, const double* b, double* y, int cfg, hipStream_t s);
+// Row ranges for the 8 XCDs holding equal numbers of CSR entries (host;
+// xr[0] = 0, xr[8] = n); returns the longest range.
+int64_t xcd_ranges(int64_t n, const int64_t* ptr, int64_t xr[9]);
 // Same product from the sliced-ELL copy of A (64-row slices).
 void sell_spmv(int64_t n, int64_t nslices, const int64_t* soff, const int32_t* swidth, const int32_t* perm,
                const int32_t* col, const double* val, const double* x, const double* b, double* y, hipStream_t s);
@@ -117,8 +136,9 @@ void sell_spmv_block(int64_t n, int64_t nslices, const int64_t* soff, const int3
                      const int32_t* col, const double* val, int S, const double* x, const double* b, double* y,
                      hipStream_t s);
 // y = A x (or b - A x) for S interleaved vectors from the CSR copy of A.
-void csr_spmv_block(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, int S, const double* x,
-                    const double* b, double* y, hipStream_t s);
+// xr / xrows: XCD row ranges as for spmv (nullptr: plain order).
+void csr_spmv_block(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const int64_t* xr,
+                    int64_t xrows, int S, const double* x, const double* b, double* y, hipStream_t s);
 void spmv_real_block(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, int S, const double* x,
                      double* y, hipStream_t s);
 void prolong_block(int64_t n, const int64_t* ptr, const int32_t* idx, const double* w, int S, const double* xl,

@@ -480,23 +480,33 @@ __global__ __launch_bounds__(kWG) void sell_block_kernel(int64_t n, int64_t nsli
 }
 
 // Block SpMV over CSR: S consecutive lanes share a row and take one
-// right-hand side each, so every x gather is one contiguous S x 16 B line;
-// workgroups are dealt to XCDs so each XCD sweeps a contiguous range of rows.
-template <int S>
+// right-hand side each, so every x gather is one contiguous S x 16 B line.
+// With kXcd, XCD k sweeps the rows [xr[k], xr[k+1]) (as in the single-vector
+// kernel).
+template <int S, bool kXcd>
 __global__ __launch_bounds__(kWG) void csr_block_kernel(int64_t n, const int64_t* __restrict__ ptr,
                                                         const int32_t* __restrict__ col,
                                                         const double2* __restrict__ val,
+                                                        const int64_t* __restrict__ xr,
                                                         const double2* __restrict__ x,
                                                         const double2* __restrict__ bvec, double2* __restrict__ y) {
-  const unsigned per = gridDim.x / 8;
-  const int64_t vb = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
-  const int64_t e = vb * kWG + threadIdx.x;
-  const int64_t row = e / S;
-  const int r = (int)(e % S);
-  if (row >= n) return;
+  int64_t i, end = n;
+  int r;
+  if (kXcd) {
+    const int64_t e0 = (int64_t)(blockIdx.x >> 3) * kWG + threadIdx.x;
+    i = xr[blockIdx.x & 7] + e0 / S;
+    r = (int)(e0 % S);
+    end = xr[(blockIdx.x & 7) + 1];
+  } else {
+    const int64_t e0 = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    i = e0 / S;
+    r = (int)(e0 % S);
+  }
+  if (i >= end) return;
+  const int64_t e = i * S + r;
   double ar = 0, ai = 0, br = 0, bi = 0;
-  const int64_t p1 = ptr[row + 1];
-  int64_t p = ptr[row];
+  const int64_t p1 = ptr[i + 1];
+  int64_t p = ptr[i];
   for (; p + 2 <= p1; p += 2) {
     const int c0 = col[p], c1 = col[p + 1];
     const double2 v0 = val[p], v1 = val[p + 1];
@@ -704,15 +714,19 @@ void sell_spmv_block(int64_t n, int64_t nslices, const int64_t* soff, const int3
   });
 }
 
-void csr_spmv_block(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, int S, const double* x,
-                    const double* b, double* y, hipStream_t s) {
+void csr_spmv_block(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const int64_t* xr,
+                    int64_t xrows, int S, const double* x, const double* b, double* y, hipStream_t s) {
   if (n <= 0) return;
   with_width(S, [&](auto w) {
     constexpr int W = decltype(w)::value;
-    const unsigned nb = blocks_for(n * W);
-    csr_block_kernel<W><<<(nb + 7) / 8 * 8, kWG, 0, s>>>(
-        n, ptr, col, reinterpret_cast<const double2*>(val), reinterpret_cast<const double2*>(x),
-        reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(y));
+    auto v2 = reinterpret_cast<const double2*>(val);
+    auto x2 = reinterpret_cast<const double2*>(x);
+    auto b2 = reinterpret_cast<const double2*>(b);
+    auto y2 = reinterpret_cast<double2*>(y);
+    if (xr)
+      csr_block_kernel<W, true><<<8 * blocks_for(xrows * W), kWG, 0, s>>>(n, ptr, col, v2, xr, x2, b2, y2);
+    else
+      csr_block_kernel<W, false><<<blocks_for(n * W), kWG, 0, s>>>(n, ptr, col, v2, nullptr, x2, b2, y2);
   });
 }
 

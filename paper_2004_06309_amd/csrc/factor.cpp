@@ -228,7 +228,7 @@ void factor_numeric(const Csr& A, const Symbolic& S, cplx* fwd, cplx* bwd, Numer
     gemm_acc(w, r, w, cplx(-1, 0), Uinv.data(), w, F.data() + (int64_t)w * m, m, Uoff.data(), w);
     // pack tiles
     cplx* fp = fwd + S.sn_fwd_off[s];
-    tiles_fwd(w, r, ts);
+    tiles_fwd(w, r, S.tile_rows, ts);
     for (auto& t : ts) {
       for (int32_t c = 0; c < t.ncols; ++c)
         for (int32_t i = 0; i < t.nrows; ++i) {
@@ -243,7 +243,7 @@ void factor_numeric(const Csr& A, const Symbolic& S, cplx* fwd, cplx* bwd, Numer
       fp += (int64_t)t.nrows * t.ncols;
     }
     cplx* bp = bwd + S.sn_bwd_off[s];
-    tiles_bwd(w, r, ts);
+    tiles_bwd(w, r, S.tile_rows, ts);
     for (auto& t : ts) {
       for (int32_t c = 0; c < t.ncols; ++c)
         for (int32_t i = 0; i < t.nrows; ++i) {

@@ -106,9 +106,13 @@ struct Symbolic {
   int64_t fwd_entries = 0, bwd_entries = 0;
   double flops = 0;
   int32_t max_front = 0;
+  int32_t tile_rows = 64;  // rows per solve tile (16, 32 or 64)
 };
 
-void nested_dissection(const Csr& A, const std::vector<double>& coords, int leaf, Symbolic& S);
+// tile_rows: rows per solve tile of the panels (16, 32 or 64); shorter tiles
+// give a level more workgroups at the cost of re-reading its input columns.
+void nested_dissection(const Csr& A, const std::vector<double>& coords, int leaf, Symbolic& S,
+                       int tile_rows = 64);
 
 // Numeric factor of one matrix in the solve layout.
 struct TileDesc {
@@ -137,8 +141,8 @@ void factor_numeric(const Csr& A, const Symbolic& S, cplx* fwd, cplx* bwd, Numer
 struct TileShape {
   int32_t row0, nrows, col0, ncols;
 };
-void tiles_fwd(int32_t w, int32_t r, std::vector<TileShape>& out);
-void tiles_bwd(int32_t w, int32_t r, std::vector<TileShape>& out);
+void tiles_fwd(int32_t w, int32_t r, int32_t tile_rows, std::vector<TileShape>& out);
+void tiles_bwd(int32_t w, int32_t r, int32_t tile_rows, std::vector<TileShape>& out);
 
 // Overlapping subdomain (host side).
 struct SubdomainHost {

@@ -20,24 +20,24 @@
 
 namespace helm {
 
-void tiles_fwd(int32_t w, int32_t r, std::vector<TileShape>& out) {
+void tiles_fwd(int32_t w, int32_t r, int32_t tile_rows, std::vector<TileShape>& out) {
   // forward panel [L11^{-1}; L21 L11^{-1}] : (w + r) rows x w columns,
   // the diagonal-block rows only need the columns up to the tile's last row
   out.clear();
   int32_t m = w + r;
-  for (int32_t r0 = 0; r0 < m; r0 += kTileRows) {
-    int32_t nr = std::min(kTileRows, m - r0);
+  for (int32_t r0 = 0; r0 < m; r0 += tile_rows) {
+    int32_t nr = std::min(tile_rows, m - r0);
     int32_t nc = std::min(w, r0 + nr);
     out.push_back({r0, nr, 0, nc});
   }
 }
 
-void tiles_bwd(int32_t w, int32_t r, std::vector<TileShape>& out) {
+void tiles_bwd(int32_t w, int32_t r, int32_t tile_rows, std::vector<TileShape>& out) {
   // backward panel [U11^{-1} | -U11^{-1} U12] : w rows x (w + r) columns,
   // a tile starting at row r0 only needs the columns from r0 on
   out.clear();
-  for (int32_t r0 = 0; r0 < w; r0 += kTileRows) {
-    int32_t nr = std::min(kTileRows, w - r0);
+  for (int32_t r0 = 0; r0 < w; r0 += tile_rows) {
+    int32_t nr = std::min(tile_rows, w - r0);
     out.push_back({r0, nr, r0, w + r - r0});
   }
 }
@@ -152,7 +152,7 @@ struct ND {
 
 }  // namespace
 
-void nested_dissection(const Csr& A, const std::vector<double>& coords, int leaf, Symbolic& S) {
+void nested_dissection(const Csr& A, const std::vector<double>& coords, int leaf, Symbolic& S, int tile_rows) {
   const int64_t n = A.n;
   if (leaf <= 0) leaf = 64;
   // symmetric adjacency without the diagonal
@@ -182,6 +182,8 @@ void nested_dissection(const Csr& A, const std::vector<double>& coords, int leaf
 
   S = Symbolic();
   S.n = n;
+  if (tile_rows != 16 && tile_rows != 32 && tile_rows != 64) fail(HELM_EINVAL, "tile rows must be 16, 32 or 64");
+  S.tile_rows = tile_rows;
   S.perm = nd.order;
   S.iperm.assign(n, -1);
   for (int64_t k = 0; k < n; ++k) S.iperm[S.perm[k]] = (int32_t)k;
@@ -241,9 +243,9 @@ void nested_dissection(const Csr& A, const std::vector<double>& coords, int leaf
     int32_t w = S.sn_w[s], r = (int32_t)(S.sn_rptr[s + 1] - S.sn_rptr[s]);
     S.sn_fwd_off[s] = fo;
     S.sn_bwd_off[s] = bo;
-    tiles_fwd(w, r, ts);
+    tiles_fwd(w, r, S.tile_rows, ts);
     for (auto& t : ts) fo += (int64_t)t.nrows * t.ncols;
-    tiles_bwd(w, r, ts);
+    tiles_bwd(w, r, S.tile_rows, ts);
     for (auto& t : ts) bo += (int64_t)t.nrows * t.ncols;
     double W = w, Rr = r, M = w + r;
     // partial LU of the front + explicit inverses, complex multiply-adds

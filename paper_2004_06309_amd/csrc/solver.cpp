@@ -185,13 +185,13 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
         kinv[rho] = k;
         B.bidx[pos0[i] + c0 + k] = (int32_t)(*in_idx[i])[S.perm[rho]];
       }
-      tiles_fwd(w, r, ts);
+      tiles_fwd(w, r, S.tile_rows, ts);
       int64_t off = pf0[i] + S.sn_fwd_off[s];
       for (auto& t : ts) {
         lf[S.height[s]].push_back({off, (int32_t)g, t.row0, t.nrows, t.col0, t.ncols, 0});
         off += (int64_t)t.nrows * t.ncols;
       }
-      tiles_bwd(w, r, ts);
+      tiles_bwd(w, r, S.tile_rows, ts);
       off = pb0[i] + S.sn_bwd_off[s];
       for (auto& t : ts) {
         lb[S.depth[s]].push_back({off, (int32_t)g, t.row0, t.nrows, t.col0, t.ncols, 0});
@@ -421,6 +421,10 @@ void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symb
 // of the fine batch is timed (the coarse batch is timed as a whole).
 void batch_solve(const BatchDev& b, const double* in, hipStream_t s, Profiler* prof, bool fine) {
   dev::Batch v = b.view();
+  if (!fine && b.coop > 0) {
+    HELM_HIP(dev::batch_solve_coop(v, in, b.ranges, b.coop, s));
+    return;
+  }
   const bool each = prof && prof->on && fine;
   for (size_t l = 0; l + 1 < b.lev_f.size(); ++l) {
     if (each) prof->begin(s);
@@ -470,20 +474,85 @@ int pick_lanes_per_row(const std::vector<int>& cands, F&& launch) {
 
 }  // namespace
 
-void upload_matrix(Ctx& c) {
+namespace {
+
+// Average time (ms) of launch() over three runs on the null stream, after one
+// warm-up run.
+template <class F>
+float time_launch(F&& launch) {
+  hipEvent_t e0, e1;
+  HELM_HIP(hipEventCreate(&e0));
+  HELM_HIP(hipEventCreate(&e1));
+  launch();
+  HELM_HIP(hipEventRecord(e0, nullptr));
+  for (int r = 0; r < 3; ++r) launch();
+  HELM_HIP(hipEventRecord(e1, nullptr));
+  HELM_HIP(hipEventSynchronize(e1));
+  float ms = 0;
+  HELM_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms / 3;
+}
+
+// Spreads the low 21 bits of v to every third bit.
+uint64_t spread3(uint64_t v) {
+  v &= 0x1fffff;
+  v = (v | v << 32) & 0x1f00000000ffffULL;
+  v = (v | v << 16) & 0x1f0000ff0000ffULL;
+  v = (v | v << 8) & 0x100f00f00f00f00fULL;
+  v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+  v = (v | v << 2) & 0x1249249249249249ULL;
+  return v;
+}
+
+// Rows in Morton (Z-curve) order of their dof positions: rows handled close
+// together in time then share the cache lines of x they gather.
+std::vector<int32_t> morton_rows(const Discretization& D) {
+  const int64_t n = D.n;
+  std::vector<double> xyz(3 * n);
+  for (int64_t v = 0; v < D.nv; ++v)
+    for (int d = 0; d < 3; ++d) xyz[3 * v + d] = D.xyz[3 * v + d];
+  for (int64_t e = 0; e < n - D.nv; ++e)
+    for (int d = 0; d < 3; ++d)
+      xyz[3 * (D.nv + e) + d] = 0.5 * (D.xyz[3 * D.edges[2 * e] + d] + D.xyz[3 * D.edges[2 * e + 1] + d]);
+  double lo[3], hi[3];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = 1e300;
+    hi[d] = -1e300;
+  }
+  for (int64_t i = 0; i < n; ++i)
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = std::min(lo[d], xyz[3 * i + d]);
+      hi[d] = std::max(hi[d], xyz[3 * i + d]);
+    }
+  // one scale for all axes keeps the curve's cells cubic
+  double ext = 0;
+  for (int d = 0; d < 3; ++d) ext = std::max(ext, hi[d] - lo[d]);
+  const double sc = ext > 0 ? 2097151.0 / ext : 0.0;
+  std::vector<std::pair<uint64_t, int32_t>> key(n);
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t k = 0;
+    for (int d = 0; d < 3; ++d) k |= spread3((uint64_t)((xyz[3 * i + d] - lo[d]) * sc)) << d;
+    key[i] = {k, (int32_t)i};
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<int32_t> order(n);
+  for (int64_t i = 0; i < n; ++i) order[i] = key[i].second;
+  return order;
+}
+
+// Sliced-ELL copy of A: rows taken in `order`, sorted by length (longest
+// first) inside windows of 1024, so a 64-row slice holds rows of similar
+// length that were close in `order`.
+void build_sell(Ctx& c, const std::vector<int32_t>& order) {
   const Csr& A = c.D.A;
   const int64_t n = A.n;
-  c.A_ptr.upload(A.ptr);
-  c.A_col.upload(A.col);
-  c.A_val.upload(reinterpret_cast<const double*>(A.val.data()), 2 * A.val.size());
-  // sliced-ELL copy: rows sorted by length (longest first) inside windows of
-  // 1024 rows, so a slice's rows have similar lengths and stay close in x
   const int64_t ns = (n + 63) / 64;
   std::vector<int32_t> perm(ns * 64, 0);
   for (int64_t w0 = 0; w0 < n; w0 += 1024) {
     const int64_t w1 = std::min<int64_t>(n, w0 + 1024);
-    std::vector<int32_t> r(w1 - w0);
-    std::iota(r.begin(), r.end(), (int32_t)w0);
+    std::vector<int32_t> r(order.begin() + w0, order.begin() + w1);
     std::stable_sort(r.begin(), r.end(), [&](int32_t a, int32_t b) {
       return A.ptr[a + 1] - A.ptr[a] > A.ptr[b + 1] - A.ptr[b];
     });
@@ -500,6 +569,7 @@ void upload_matrix(Ctx& c) {
   }
   std::vector<int32_t> scol(soff[ns], 0);
   std::vector<cplx> sval(soff[ns], cplx(0, 0));
+#pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < ns; ++s)
     for (int64_t q = s * 64; q < std::min<int64_t>(n, s * 64 + 64); ++q) {
       const int64_t row = perm[q], lane = q - s * 64;
@@ -516,34 +586,100 @@ void upload_matrix(Ctx& c) {
   c.sell_perm.upload(perm);
   c.sell_col.upload(scol);
   c.sell_val.upload(reinterpret_cast<const double*>(sval.data()), 2 * sval.size());
+}
+
+}  // namespace
+
+void upload_matrix(Ctx& c) {
+  const Csr& A = c.D.A;
+  const int64_t n = A.n;
+  c.A_ptr.upload(A.ptr);
+  c.A_col.upload(A.col);
+  c.A_val.upload(reinterpret_cast<const double*>(A.val.data()), 2 * A.val.size());
+  build_sell(c, morton_rows(c.D));
+  {
+    std::vector<int64_t> xr(9);
+    c.A_xrows = dev::xcd_ranges(n, A.ptr.data(), xr.data());
+    c.A_xr.upload(xr);
+  }
   DVec<double> x, y;
   x.alloc(2 * n);
   y.alloc(2 * n);
   HELM_HIP(hipMemset(x.p, 0, sizeof(double) * 2 * n));
-  // G = 0 stands for the sliced-ELL kernel
-  const int best = pick_lanes_per_row({0, 4, 8, 16, 32}, [&](int G) {
-    if (G == 0)
-      dev::sell_spmv(n, ns, c.sell_off.p, c.sell_width.p, c.sell_perm.p, c.sell_col.p, c.sell_val.p, x.p, nullptr,
-                     y.p, nullptr);
-    else
-      dev::spmv(n, c.A_ptr.p, c.A_col.p, c.A_val.p, x.p, nullptr, y.p, G, nullptr);
+  // every storage and lane count is timed; the fastest is the default
+  float best = 1e30f, best_csr = 1e30f, best_x = 1e30f;
+  for (int G : dev::kSpmvCfgs) {
+    const float t = time_launch([&] {
+      dev::spmv(n, c.A_ptr.p, c.A_col.p, c.A_val.p, nullptr, 0, x.p, nullptr, y.p, G, nullptr);
+    });
+    if (t < best_csr) {
+      best_csr = t;
+      c.g_A = G;
+    }
+    const float tx = time_launch([&] {
+      dev::spmv(n, c.A_ptr.p, c.A_col.p, c.A_val.p, c.A_xr.p, c.A_xrows, x.p, nullptr, y.p, G, nullptr);
+    });
+    if (tx < best_x) {
+      best_x = tx;
+      c.g_X = G;
+    }
+  }
+  const float ts = time_launch([&] {
+    dev::sell_spmv(n, c.sell_nslices, c.sell_off.p, c.sell_width.p, c.sell_perm.p, c.sell_col.p, c.sell_val.p, x.p,
+                   nullptr, y.p, nullptr);
   });
-  c.use_sell = c.sell_auto = best == 0;
-  c.g_A = best == 0 ? 8 : best;
+  c.spmv_auto = 1;
+  best = best_csr;
+  if (best_x < best) {
+    best = best_x;
+    c.spmv_auto = 3;
+  }
+  if (ts < best) c.spmv_auto = 2;
+  c.spmv_kind = c.spmv_auto;
   HELM_HIP(hipDeviceSynchronize());
 }
 
 namespace {
 
 void spmv_A(Ctx& c, const double* x, const double* b, double* y, hipStream_t s) {
-  if (c.use_sell)
+  if (c.spmv_kind == 2)
     dev::sell_spmv(c.D.n, c.sell_nslices, c.sell_off.p, c.sell_width.p, c.sell_perm.p, c.sell_col.p, c.sell_val.p, x,
                    b, y, s);
+  else if (c.spmv_kind == 3)
+    dev::spmv(c.D.n, c.A_ptr.p, c.A_col.p, c.A_val.p, c.A_xr.p, c.A_xrows, x, b, y, c.g_X, s);
   else
-    dev::spmv(c.D.n, c.A_ptr.p, c.A_col.p, c.A_val.p, x, b, y, c.g_A, s);
+    dev::spmv(c.D.n, c.A_ptr.p, c.A_col.p, c.A_val.p, nullptr, 0, x, b, y, c.g_A, s);
 }
 
 }  // namespace
+
+// The coarse solve is a chain of small levels whose launch gaps dominate its
+// time.  When the device supports it, one cooperative launch with a grid-wide
+// barrier per level is timed against per-level launches at a few grid sizes,
+// and the fastest is kept.
+void choose_coarse_launch(Ctx& c) {
+  BatchDev& b = c.coarse;
+  b.coop = 0;
+  const int nf = (int)b.lev_f.size() - 1, nb = (int)b.lev_b.size() - 1;
+  int attr = 0;
+  if (b.c64 || nf < 1 || nb < 1 || nf > dev::kMaxLevels || nb > dev::kMaxLevels) return;
+  if (hipDeviceGetAttribute(&attr, hipDeviceAttributeCooperativeLaunch, c.device) != hipSuccess || !attr) return;
+  const int gmax = dev::coop_grid();
+  if (gmax <= 0) return;
+  b.ranges.nf = nf;
+  b.ranges.nb = nb;
+  for (int l = 0; l <= nf; ++l) b.ranges.f[l] = b.lev_f[l];
+  for (int l = 0; l <= nb; ++l) b.ranges.b[l] = b.lev_b[l];
+  HELM_HIP(hipMemset(c.cvec.p, 0, sizeof(double) * 2 * c.E.n));
+  std::vector<int> cands{0};
+  for (int g : {256, 512, 1024})
+    if (g < gmax) cands.push_back(g);
+  cands.push_back(gmax);
+  b.coop = pick_lanes_per_row(cands, [&](int g) {
+    b.coop = g;
+    batch_solve(b, c.cvec.p, nullptr, nullptr, false);
+  });
+}
 
 void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overlap, const helm_mesh* coarse,
                    const helm_precond_opts* opts) {
@@ -555,8 +691,12 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
   c.overlap = overlap;
   build_subdomains(c.D, tet_part, n_sub, overlap, c.subs);
   c.sym.resize(n_sub);
+  const int trows = opts && opts->tile_rows > 0 ? opts->tile_rows : 64;
+  const int ctrows = opts && opts->coarse_tile_rows > 0 ? opts->coarse_tile_rows : 16;
+  if (trows != 16 && trows != 32 && trows != 64) fail(HELM_EINVAL, "tile_rows must be 16, 32 or 64");
+  if (ctrows != 16 && ctrows != 32 && ctrows != 64) fail(HELM_EINVAL, "coarse_tile_rows must be 16, 32 or 64");
 #pragma omp parallel for schedule(dynamic, 1)
-  for (int32_t i = 0; i < n_sub; ++i) nested_dissection(c.subs[i].A, c.subs[i].coords, leaf, c.sym[i]);
+  for (int32_t i = 0; i < n_sub; ++i) nested_dissection(c.subs[i].A, c.subs[i].coords, leaf, c.sym[i], trows);
   helm_precond_stats& st = c.stats;
   st.n_sub = n_sub;
   for (auto& S : c.subs) st.n_local_total += (int64_t)S.dofs.size();
@@ -615,7 +755,7 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
     transpose_real(c.Z, c.ZT);
     galerkin(c.D.A, c.Z, c.ZT, c.E);
     const int cleaf = opts && opts->coarse_leaf_size > 0 ? opts->coarse_leaf_size : 256;
-    nested_dissection(c.E, ccoords, cleaf, c.Esym);
+    nested_dissection(c.E, ccoords, cleaf, c.Esym, ctrows);
     std::vector<int64_t> ident(c.E.n);
     std::iota(ident.begin(), ident.end(), 0);
     BatchHost cb;
@@ -655,6 +795,8 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
       c.g_Zp = pick_lanes_per_row({4, 8}, [&](int G) {
         dev::spmv_real(c.D.n, c.Zp_ptr.p, c.Zp_col.p, c.Zp_val.p, x.p, y.p, G, nullptr);
       });
+      choose_coarse_launch(c);
+      st.coarse_grid = c.coarse.coop;
     }
   }
   if (on_device) {
@@ -912,6 +1054,16 @@ void ensure_block(Ctx& c, int m, int S) {
     HELM_HIP(hipHostMalloc((void**)&c.bh_host, 2 * sizeof(double) * dev::kMaxBlock * (m + 2), hipHostMallocDefault));
     c.blk_m = m;
     c.blk_cap = S;
+    // order of the multi-vector SpMV: plain or over XCD row ranges, the faster
+    HELM_HIP(hipMemset(c.bX.p, 0, sizeof(double) * 2 * n * S));
+    const float td = time_launch([&] {
+      dev::csr_spmv_block(n, c.A_ptr.p, c.A_col.p, c.A_val.p, nullptr, 0, S, c.bX.p, nullptr, c.bW.p, nullptr);
+    });
+    const float tx = time_launch([&] {
+      dev::csr_spmv_block(n, c.A_ptr.p, c.A_col.p, c.A_val.p, c.A_xr.p, c.A_xrows, S, c.bX.p, nullptr, c.bW.p,
+                          nullptr);
+    });
+    c.blk_xcd = tx < td;
   }
   ensure_batch_block(c.fine, S);
   if (c.two_level) ensure_batch_block(c.coarse, S);
@@ -942,8 +1094,11 @@ void batch_solve_block(BatchDev& b, int S, const double* in, hipStream_t s, Prof
   }
 }
 
-void sell_block(Ctx& c, int S, const double* x, const double* b, double* y, hipStream_t s) {
-  dev::csr_spmv_block(c.D.n, c.A_ptr.p, c.A_col.p, c.A_val.p, S, x, b, y, s);
+void spmv_block(Ctx& c, int S, const double* x, const double* b, double* y, hipStream_t s) {
+  if (c.blk_force == 3 || (c.blk_force == 0 && c.blk_xcd))
+    dev::csr_spmv_block(c.D.n, c.A_ptr.p, c.A_col.p, c.A_val.p, c.A_xr.p, c.A_xrows, S, x, b, y, s);
+  else
+    dev::csr_spmv_block(c.D.n, c.A_ptr.p, c.A_col.p, c.A_val.p, nullptr, 0, S, x, b, y, s);
 }
 
 // Z = M^{-1} X for S interleaved vectors (eq. 2lvl, or eq. oras one-level).
@@ -957,7 +1112,7 @@ void apply_precond_block(Ctx& c, int S, const double* X, double* Z, hipStream_t 
     dev::spmv_real_block(n, c.Zp_ptr.p, c.Zp_col.p, c.Zp_val.p, S, c.coarse.x_b.p, c.bq.p, s);
     if (p) c.prof.end(HELM_K_COARSE, 0.0, s);
     if (p) c.prof.begin(s);
-    sell_block(c, S, c.bq.p, X, c.bt.p, s);  // t = x - A q
+    spmv_block(c, S, c.bq.p, X, c.bt.p, s);  // t = x - A q
     if (p) c.prof.end(HELM_K_SPMV, 0.0, s);
     batch_solve_block(c.fine, S, c.bt.p, s, &c.prof, true);
   } else {
@@ -1048,7 +1203,7 @@ int solve_block(Ctx& c, int nb, const double* const* Bp, double* const* Up, doub
       dev::unpack(n, S, c.bZb.p, dz, s);
       const bool prof = c.prof.on;
       if (prof) c.prof.begin(s);
-      sell_block(c, S, c.bZb.p, nullptr, c.bW.p, s);
+      spmv_block(c, S, c.bZb.p, nullptr, c.bW.p, s);
       if (prof) c.prof.end(HELM_K_SPMV, 0.0, s);
       dev::unpack(n, S, c.bW.p, dw, s);
       // CGS2 over the active right-hand sides (slot q holds act[q])

@@ -42,7 +42,7 @@ class Mesh(C.Structure):
 
 class PrecondOpts(C.Structure):
     _fields_ = [("leaf_size", C.c_int32), ("factor_c64", C.c_int32), ("coarse_leaf_size", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("tile_rows", C.c_int32), ("coarse_tile_rows", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class SolveOpts(C.Structure):
@@ -59,7 +59,7 @@ class PrecondStats(C.Structure):
                 ("factor_entries", C.c_int64), ("coarse_entries", C.c_int64), ("levels_fwd", C.c_int32),
                 ("levels_bwd", C.c_int32), ("max_front", C.c_int32), ("n_supernodes", C.c_int32),
                 ("setup_seconds", C.c_double), ("factor_flops", C.c_double), ("factor_c64", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("coarse_grid", C.c_int32)]
 
 
 class KernelProfile(C.Structure):
@@ -202,9 +202,10 @@ class Helm:
         return ptr, col, val
 
     def precond_setup(self, part, n_sub, overlap, coarse_xyz=None, coarse_tets=None, leaf_size=0, c64=False,
-                      coarse_leaf_size=0):
+                      coarse_leaf_size=0, tile_rows=0, coarse_tile_rows=0):
         part = np.ascontiguousarray(part, dtype=np.int32)
-        opts = PrecondOpts(int(leaf_size), 1 if c64 else 0, int(coarse_leaf_size))
+        opts = PrecondOpts(int(leaf_size), 1 if c64 else 0, int(coarse_leaf_size), int(tile_rows),
+                           int(coarse_tile_rows))
         cm = None
         if coarse_xyz is not None:
             cm, keep = _mesh(coarse_xyz, coarse_tets, 1)
@@ -241,7 +242,9 @@ class Helm:
 
     # ---- device operations (torch complex128 tensors) -----------------------
     def set_spmv(self, kind):
-        """0: faster of CSR / sliced ELL as timed at assembly, 1: CSR, 2: sliced ELL."""
+        """0: fastest storage as timed at assembly, 1: CSR, 2: sliced ELL in
+        Morton row order, 3: CSR with XCD row ranges (1 and 3 also fix the
+        multi-vector SpMV's order)."""
         self._check(self.lib.helm_set_spmv(self.h, int(kind)))
 
     def apply_A(self, x, y, stream=None):
@@ -279,11 +282,12 @@ class Helm:
                 for i, k in enumerate(KERNELS)}
 
 
-def from_workload(w, device=0, leaf_size=0, c64=False):
-    """Helm context assembled and preconditioned for a workloads.Workload."""
+def from_workload(w, device=0, leaf_size=0, c64=False, **opts):
+    """Helm context assembled and preconditioned for a workloads.Workload;
+    opts: coarse_leaf_size, tile_rows, coarse_tile_rows (see precond_setup)."""
     h = Helm(device)
     h.assemble(w.xyz, w.tets, w.order, w.c_tet, w.omega)
-    h.precond_setup(w.part, w.n_sub, w.overlap, w.coarse_xyz, w.coarse_tets, leaf_size, c64)
+    h.precond_setup(w.part, w.n_sub, w.overlap, w.coarse_xyz, w.coarse_tets, leaf_size, c64, **opts)
     return h
 
 

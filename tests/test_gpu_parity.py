@@ -72,11 +72,11 @@ def rand_vec(n, seed):
 
 
 def test_spmv_parity(pair):
-    """Both SpMV storages (CSR, sliced ELL) against the oracle's A."""
+    """Every SpMV storage (CSR, sliced ELL, CSR over XCD row ranges) against the oracle's A."""
     name, w, P, b, M, h = pair
     x = rand_vec(P.n, 1)
     y = torch.empty(P.n, dtype=torch.complex128, device=DEV)
-    for kind in (1, 2, 0):
+    for kind in (1, 2, 3, 0):
         h.set_spmv(kind)
         h.apply_A(dvec(x), y)
         assert rel(host(y), P.A @ x) <= 1e-13, kind
@@ -160,6 +160,8 @@ def test_block_solve(name, nrhs, block, c64):
     w = WORKLOADS[name]()
     P, b0, M = opre.build(w)
     h = helm.from_workload(w, c64=c64)
+    # both multi-vector SpMV orders are covered (plain / XCD row ranges)
+    h.set_spmv(1 if nrhs % 2 else 3)
     lo, hi = w.xyz.min(axis=0), w.xyz.max(axis=0)
     rng = np.random.default_rng(11)
     pts = lo + (hi - lo) * rng.uniform(0.1, 0.9, (nrhs, 3))
@@ -181,6 +183,33 @@ def test_block_solve(name, nrhs, block, c64):
         alone = host(U1)
         assert np.linalg.norm(u[r] - alone) <= 1e-5 * np.linalg.norm(alone)
     say(f"[block] {name} nrhs={nrhs} block={block}: its={[i['iterations'] for i in info]}")
+
+
+@pytest.mark.parametrize("tile_rows,coarse_tile_rows", [(16, 64), (32, 32)])
+def test_tile_rows(tile_rows, coarse_tile_rows):
+    """Other solve-tile heights for the subdomain and coarse factors: the
+    two-level preconditioner matches the oracle, and 16 right-hand sides
+    advanced together (MFMA level solves) match the oracle's solves."""
+    w = WORKLOADS["mid_quarter_2lvl"]()
+    P, b, M = opre.build(w)
+    h = helm.from_workload(w, tile_rows=tile_rows, coarse_tile_rows=coarse_tile_rows)
+    r = rand_vec(P.n, 21)
+    z = torch.empty(P.n, dtype=torch.complex128, device=DEV)
+    h.apply_precond(dvec(r), z)
+    assert rel(host(z), M.apply(r)) <= 1e-9
+    lo, hi = w.xyz.min(axis=0), w.xyz.max(axis=0)
+    pts = lo + (hi - lo) * np.random.default_rng(12).uniform(0.1, 0.9, (16, 3))
+    Bs = np.stack([P.point_source(p) for p in pts])
+    U = torch.zeros(16, P.n, dtype=torch.complex128, device=DEV)
+    rc, info = h.solve(dvec(Bs), U, tol=w.tol, restart=w.restart, block=16)
+    assert rc == helm.HELM_OK
+    u = host(U)
+    for k in (0, 7, 15):
+        ro = opre.solve(P, Bs[k], M, tol=w.tol, restart=w.restart)
+        assert np.linalg.norm(Bs[k] - P.A @ u[k]) / np.linalg.norm(Bs[k]) <= w.tol
+        assert abs(info[k]["iterations"] - ro.iterations) <= 2
+        assert np.linalg.norm(u[k] - ro.x) <= 1e-5 * np.linalg.norm(ro.x)
+    say(f"[tiles] {tile_rows}/{coarse_tile_rows}: its={[i['iterations'] for i in info]}")
 
 
 def test_edge_cases():

@@ -148,3 +148,30 @@ def test_call_order_and_host_only_context():
 def test_create_rejects_bad_ordinal():
     with pytest.raises(helm.HelmError):
         helm.Helm(-7)
+
+
+def test_bad_tile_rows_are_rejected():
+    w = wl.small_box(n=(2, 2, 2), order=1, coarse=False)
+    h = helm.Helm(-1)
+    h.assemble(w.xyz, w.tets, 1, w.c_tet, w.omega)
+    for kw in ({"tile_rows": 48}, {"coarse_tile_rows": 8}):
+        with pytest.raises(helm.HelmError) as e:
+            h.precond_setup(w.part, w.n_sub, 1, **kw)
+        assert e.value.code == helm.HELM_EINVAL
+
+
+def test_shorter_tiles_store_fewer_triangle_zeros():
+    """Tiles of the diagonal blocks stop at their last row, so shorter tiles
+    store a subset of the entries of taller ones; the analysis is unchanged."""
+    w = wl.small_box(n=(6, 6, 4), order=2, n_parts=(2, 2, 1), overlap=2)
+    st = {}
+    for tr in (16, 64):
+        h = helm.Helm(-1)
+        h.assemble(w.xyz, w.tets, w.order, w.c_tet, w.omega)
+        h.precond_setup(w.part, w.n_sub, w.overlap, w.coarse_xyz, w.coarse_tets, tile_rows=tr,
+                        coarse_tile_rows=tr)
+        st[tr] = h.stats()
+    assert st[16]["factor_entries"] < st[64]["factor_entries"]
+    assert st[16]["coarse_entries"] <= st[64]["coarse_entries"]
+    for k in ("n_local_total", "levels_fwd", "levels_bwd", "max_front", "n_supernodes"):
+        assert st[16][k] == st[64][k]
