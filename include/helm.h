@@ -71,7 +71,9 @@ typedef struct helm_precond_opts {
   int32_t tile_rows;       /* rows per solve tile of the subdomain factors:
                               16, 32 or 64; 0 = 64                         */
   int32_t coarse_tile_rows;  /* same for the coarse factor; 0 = 16         */
-  int32_t reserved[3];
+  int32_t factor_on_host;  /* 1: numeric factorisation on the host CPU
+                              (reference path); 0 = on the device          */
+  int32_t reserved[2];
 } helm_precond_opts;
 
 enum {
@@ -110,6 +112,9 @@ typedef struct helm_precond_stats {
   int32_t factor_c64;      /* 1 if the fine factors are stored in complex64 */
   int32_t coarse_grid;     /* workgroups of the one-launch cooperative coarse
                               solve; 0 = one launch per level              */
+  int32_t factor_on_host;  /* 1 if the numeric factorisation ran on the host */
+  int32_t n_perturbed;     /* zero pivots replaced by sqrt(eps) max|a_ij|   */
+  double factor_seconds;   /* wall time of the numeric factorisation       */
 } helm_precond_stats;
 
 /* Create a context on HIP device `device_ordinal`; -1 creates a host-only

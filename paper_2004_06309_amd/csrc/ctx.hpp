@@ -198,6 +198,13 @@ struct Ctx {
   void free_precond();
 };
 
+// factor_gpu.cpp: numeric factorisation of a batch on the device, panels
+// written into Dv.pf / Dv.pb (allocated by the caller) at the per-matrix
+// offsets pf0 / pb0; pivots returned in num.
+void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<const Symbolic*>& Ss, bool c64,
+                         BatchDev& Dv, const std::vector<int64_t>& pf0, const std::vector<int64_t>& pb0,
+                         std::vector<NumericOut>& num, int32_t& n_perturbed);
+
 // solver.cpp
 void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<const std::vector<int64_t>*>& in_idx,
                   const std::vector<NumericOut>& num, BatchHost& B);

@@ -64,6 +64,35 @@ struct Batch {
 // coarse selects a separate instantiation so profiles tell the two apart.
 void fwd_level(const Batch& b, int64_t task0, int64_t ntasks, const double* bin, bool coarse, hipStream_t s);
 void bwd_level(const Batch& b, int64_t task0, int64_t ntasks, bool coarse, hipStream_t s);
+// One frontal matrix of the device factorisation (offsets in complex
+// entries).
+struct FrontJob {
+  int64_t F, X, Y;     // front (m x m), forward panel X (m x w), backward panel Y (w x m) in the workspace
+  int64_t upd;         // Schur complement (r x r) in the update buffer
+  int64_t pfo, pbo;    // first forward / backward tile entry in the panel arrays
+  int64_t asm0, asm1;  // range of the front's original entries in the assembly lists
+  int32_t m, w;        // front order, fully-summed columns
+  int32_t c0;          // first column of the supernode in its matrix
+  int32_t piv0;        // batch position of that column (pivot output)
+  int32_t kid0, kid1;  // range of the children in the child list
+  double anorm;        // max |a_ij| of the matrix (zero-pivot replacement scale)
+};
+// A child's Schur complement and the front rows its rows map to.
+struct FrontChild {
+  int64_t upd;  // offset in the update buffer
+  int64_t ep;   // offset of its r front positions in the extend-add map
+  int32_t r, pad;
+};
+// Factors a list of independent fronts (one workgroup each): assembly from
+// the scatter lists (F[asm_pos[q]] = aval[asm_val[q]]) and the children,
+// partial LU, Schur complement into upd, pivots into piv (batch positions),
+// zero-pivot replacements per job into npert, explicit-inverse panels into
+// the solve tiles of pf / pb (complex64 when c64).  ws holds each job's F, X
+// and Y.
+void factor_fronts(const FrontJob* jobs, int njobs, double* ws, double* upd, const int32_t* asm_pos,
+                   const int32_t* asm_val, const double* aval, const FrontChild* kids, const int32_t* ep,
+                   int32_t* piv, int32_t* npert, void* pf, void* pb, bool c64, int tile_rows, hipStream_t s);
+
 // Task ranges of every level of a batch (a kernel argument).
 constexpr int kMaxLevels = 40;
 struct LevelRanges {

@@ -1,0 +1,429 @@
+// Multifrontal numeric LU of a batch of local matrices on the device (the
+// local direct solvers of the ORAS preconditioner, eq. oras, and the coarse
+// matrix E of eq. 2lvl), level by level of the elimination trees.
+//
+// One workgroup owns one frontal matrix F (order m = w + r, column-major in a
+// level workspace) and does, in order:
+//   1. assembly: zero F, scatter the original entries of the supernode's
+//      arrowhead, extend-add the children's Schur complements (children in
+//      ascending order, so the sums are deterministic);
+//   2. blocked right-looking partial LU of the w fully-summed columns, pivot
+//      rows searched among the fully-summed rows only (P F11 = L11 U11,
+//      L21 = F21 U11^{-1}, U12 = L11^{-1} P F12, F22 - L21 U12 left in place);
+//   3. the Schur complement F22 copied out for the parent;
+//   4. the explicit-inverse panels of the partitioned-inverse solve:
+//        X = [I; L21] L11^{-1}   (m x w, right triangular solve by blocks)
+//        Y = U11^{-1} [I | -U12] (w x m, left triangular solve by blocks)
+//   5. X and Y written into the solve tiles (complex128 or complex64).
+// Every rank-32 update of steps 2 and 4 is a complex GEMM on
+// v_mfma_f64_16x16x4f64 (four real MFMAs per complex product); the pivot
+// search, the 32-column panel factorisation and the 32 x 32 triangular
+// solves run on the vector units.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+
+#include "device.hpp"
+
+namespace helm {
+namespace dev {
+
+namespace {
+
+constexpr int kFW = 256;  // threads of a front workgroup
+constexpr int kNB = 32;   // block size of the partial LU and the panel solves
+
+typedef double dv4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void csub_mul(double2& x, double2 a, double2 b) {
+  x.x -= a.x * b.x - a.y * b.y;
+  x.y -= a.x * b.y + a.y * b.x;
+}
+// a / d as (a conj(d)) / |d|^2
+__device__ __forceinline__ double2 cdivd(double2 a, double2 d) {
+  const double q = d.x * d.x + d.y * d.y;
+  return make_double2((a.x * d.x + a.y * d.y) / q, (a.y * d.x - a.x * d.y) / q);
+}
+
+// C[M x N] -= A[M x K] B[K x N] (complex, column-major), by the whole
+// workgroup: each wave computes 32 x 32 output tiles as 2 x 2 MFMA blocks.
+// The MFMA computes the transposed block C^T = B^T A^T, so the 16 lanes that
+// share an accumulator column hold 16 consecutive rows of C (coalesced
+// read-modify-write).  16x16x4 operand layout: lane l holds A[l % 16][l / 16]
+// and B[l / 16][l % 16]; FP64 accumulator register j of lane l is
+// D[4 j + l / 16][l % 16].
+__device__ void wg_gemm_sub(int M, int N, int K, const double2* A, int64_t lda, const double2* B, int64_t ldb,
+                            double2* C, int64_t ldc) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, lo = lane & 15, hi = lane >> 4;
+  const int tm = (M + 31) >> 5, tn = (N + 31) >> 5;
+  for (int t = wv; t < tm * tn; t += kFW / 64) {
+    const int r0 = (t % tm) * 32, c0 = (t / tm) * 32;
+    dv4 dre[2][2], dim[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) dre[a][b] = dim[a][b] = dv4{0, 0, 0, 0};
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int k = k0 + hi;
+      double2 av[2], bv[2];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        const int row = r0 + 16 * rb + lo;
+        av[rb] = (row < M && k < K) ? A[row + (int64_t)k * lda] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) {
+        const int col = c0 + 16 * cb + lo;
+        bv[cb] = (col < N && k < K) ? B[k + (int64_t)col * ldb] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+          dre[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[cb].x, av[rb].x, dre[cb][rb], 0, 0, 0);
+          dre[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-bv[cb].y, av[rb].y, dre[cb][rb], 0, 0, 0);
+          dim[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[cb].x, av[rb].y, dim[cb][rb], 0, 0, 0);
+          dim[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[cb].y, av[rb].x, dim[cb][rb], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int col = c0 + 16 * cb + 4 * j + hi, row = r0 + 16 * rb + lo;
+          if (row < M && col < N) {
+            double2& c = C[row + (int64_t)col * ldc];
+            c.x -= dre[cb][rb][j];
+            c.y -= dim[cb][rb][j];
+          }
+        }
+  }
+  __syncthreads();
+}
+
+// Triangular solves of many short vectors with the kNB x kNB block T (LDS,
+// column-major, identity beyond kb).  The vectors go through LDS 64 at a
+// time; the 4 consecutive lanes that share a vector (always in one wave, so
+// their LDS accesses stay in program order) split its entries mod 4, and the
+// recurrence runs over the block's kNB steps.
+constexpr int kChunkV = kFW / 4;  // vectors per LDS chunk
+
+// Columns of G (kb x ncols, ld): L x = b with L unit lower.
+__device__ void solve_cols_unit_lower(double2* G, int64_t ld, int kb, int ncols, const double2* T, double2* buf) {
+  const int v = threadIdx.x >> 2, q = threadIdx.x & 3;
+  for (int c0 = 0; c0 < ncols; c0 += kChunkV) {
+    const int nc = min(kChunkV, ncols - c0);
+    for (int e = threadIdx.x; e < kNB * kChunkV; e += kFW) {
+      const int i = e % kNB, c = e / kNB;
+      buf[e] = (i < kb && c < nc) ? G[i + (int64_t)(c0 + c) * ld] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    double2* x = buf + v * kNB;
+    for (int k = 0; k < kNB - 1; ++k) {
+      const double2 xk = x[k];
+      for (int i = q; i < kNB; i += 4)
+        if (i > k) csub_mul(x[i], T[i + k * kNB], xk);
+      __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kNB * kChunkV; e += kFW) {
+      const int i = e % kNB, c = e / kNB;
+      if (i < kb && c < nc) G[i + (int64_t)(c0 + c) * ld] = buf[e];
+    }
+    __syncthreads();
+  }
+}
+
+// Rows of G (nrows x kb, ld): x L = b with L unit lower, last entry first.
+__device__ void solve_rows_right_unit_lower(double2* G, int64_t ld, int kb, int nrows, const double2* T,
+                                            double2* buf) {
+  const int v = threadIdx.x >> 2, q = threadIdx.x & 3;
+  for (int r0 = 0; r0 < nrows; r0 += kChunkV) {
+    const int nr = min(kChunkV, nrows - r0);
+    // buf[c + row * kNB]: one row's entries contiguous
+    for (int e = threadIdx.x; e < kNB * kChunkV; e += kFW) {
+      const int row = e % kChunkV, c = e / kChunkV;
+      buf[c + row * kNB] = (c < kb && row < nr) ? G[r0 + row + (int64_t)c * ld] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    double2* x = buf + v * kNB;
+    for (int c2 = kNB - 1; c2 > 0; --c2) {
+      const double2 xc = x[c2];
+      for (int c = q; c < kNB; c += 4)
+        if (c < c2) csub_mul(x[c], xc, T[c2 + c * kNB]);
+      __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kNB * kChunkV; e += kFW) {
+      const int row = e % kChunkV, c = e / kChunkV;
+      if (c < kb && row < nr) G[r0 + row + (int64_t)c * ld] = buf[c + row * kNB];
+    }
+    __syncthreads();
+  }
+}
+
+// Columns of G (kb x ncols, ld): U y = b with U upper (its diagonal
+// included), last entry first.
+__device__ void solve_cols_upper(double2* G, int64_t ld, int kb, int ncols, const double2* T, double2* buf) {
+  const int v = threadIdx.x >> 2, q = threadIdx.x & 3;
+  for (int c0 = 0; c0 < ncols; c0 += kChunkV) {
+    const int nc = min(kChunkV, ncols - c0);
+    for (int e = threadIdx.x; e < kNB * kChunkV; e += kFW) {
+      const int i = e % kNB, c = e / kNB;
+      buf[e] = (i < kb && c < nc) ? G[i + (int64_t)(c0 + c) * ld] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    double2* y = buf + v * kNB;
+    for (int k = kNB - 1; k >= 0; --k) {
+      if (q == (k & 3)) y[k] = cdivd(y[k], T[k + k * kNB]);
+      __builtin_amdgcn_wave_barrier();
+      const double2 yk = y[k];
+      for (int i = q; i < k; i += 4) csub_mul(y[i], T[i + k * kNB], yk);
+      __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kNB * kChunkV; e += kFW) {
+      const int i = e % kNB, c = e / kNB;
+      if (i < kb && c < nc) G[i + (int64_t)(c0 + c) * ld] = buf[e];
+    }
+    __syncthreads();
+  }
+}
+
+// (value, index) maximum over the workgroup; ties go to the lower index.
+__device__ void wg_argmax(double& v, int& idx, double* sv, int* si) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(v, o, 64);
+    const int oi = __shfl_xor(idx, o, 64);
+    if (ov > v || (ov == v && oi < idx)) {
+      v = ov;
+      idx = oi;
+    }
+  }
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sv[wv] = v;
+    si[wv] = idx;
+  }
+  __syncthreads();
+  v = sv[0];
+  idx = si[0];
+  for (int q = 1; q < kFW / 64; ++q)
+    if (sv[q] > v || (sv[q] == v && si[q] < idx)) {
+      v = sv[q];
+      idx = si[q];
+    }
+  __syncthreads();
+}
+
+// Copies the kb x kb diagonal block at F (ld) into T (kNB x kNB), padded
+// with the identity beyond kb.
+__device__ void load_diag_block(const double2* F, int64_t ld, int kb, double2* T) {
+  for (int e = threadIdx.x; e < kNB * kNB; e += kFW) {
+    const int i = e % kNB, j = e / kNB;
+    T[e] = (i < kb && j < kb) ? F[i + (int64_t)j * ld] : make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kFW) void front_kernel(const FrontJob* __restrict__ jobs, double2* __restrict__ ws,
+                                                    double2* __restrict__ upd, const int32_t* __restrict__ asm_pos,
+                                                    const int32_t* __restrict__ asm_val,
+                                                    const double2* __restrict__ aval,
+                                                    const FrontChild* __restrict__ kids,
+                                                    const int32_t* __restrict__ ep, int32_t* __restrict__ piv,
+                                                    int32_t* __restrict__ npert, void* __restrict__ pf,
+                                                    void* __restrict__ pb, int c64, int tile_rows) {
+  __shared__ double2 T[kNB * kNB];
+  __shared__ double2 buf[kNB * kChunkV];
+  __shared__ double sv[kFW / 64];
+  __shared__ int si[kFW / 64];
+  const FrontJob J = jobs[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int m = J.m, w = J.w, r = m - w;
+  const int64_t mm = (int64_t)m * m;
+  double2* F = ws + J.F;
+
+  // 1. assembly
+  for (int64_t e = tid; e < mm; e += kFW) F[e] = make_double2(0.0, 0.0);
+  __syncthreads();
+  for (int64_t q = J.asm0 + tid; q < J.asm1; q += kFW) F[asm_pos[q]] = aval[asm_val[q]];
+  __syncthreads();
+  for (int c = J.kid0; c < J.kid1; ++c) {
+    const FrontChild K = kids[c];
+    const double2* S = upd + K.upd;
+    const int32_t* map = ep + K.ep;
+    const int64_t rc2 = (int64_t)K.r * K.r;
+    for (int64_t e = tid; e < rc2; e += kFW) {
+      const int a = (int)(e % K.r), b = (int)(e / K.r);
+      double2& f = F[map[a] + (int64_t)map[b] * m];
+      const double2 s = S[e];
+      f.x += s.x;
+      f.y += s.y;
+    }
+    __syncthreads();
+  }
+
+  // 2. partial LU of the first w columns, pivots among rows [k, w)
+  int32_t* perm = piv + J.piv0;
+  int n_pert = 0;
+  for (int k = tid; k < w; k += kFW) perm[k] = J.c0 + k;
+  __syncthreads();
+  for (int k0 = 0; k0 < w; k0 += kNB) {
+    const int kb = min(kNB, w - k0);
+    for (int k = k0; k < k0 + kb; ++k) {
+      double2* colk = F + (int64_t)k * m;
+      double best = -1.0;
+      int p = k;
+      for (int i = k + tid; i < w; i += kFW) {
+        const double a = hypot(colk[i].x, colk[i].y);
+        if (a > best) {
+          best = a;
+          p = i;
+        }
+      }
+      wg_argmax(best, p, sv, si);
+      if (p != k) {
+        for (int j = tid; j < m; j += kFW) {
+          const double2 t = F[k + (int64_t)j * m];
+          F[k + (int64_t)j * m] = F[p + (int64_t)j * m];
+          F[p + (int64_t)j * m] = t;
+        }
+        if (tid == 0) {
+          const int32_t t = perm[k];
+          perm[k] = perm[p];
+          perm[p] = t;
+        }
+        __syncthreads();
+      }
+      if (!(best > 1e-300)) {
+        // zero pivot column: replaced by a tiny diagonal (counted)
+        if (tid == 0) colk[k] = make_double2(sqrt(DBL_EPSILON) * J.anorm, 0.0);
+        ++n_pert;
+        __syncthreads();
+      }
+      const double2 d = colk[k];
+      for (int i = k + 1 + tid; i < m; i += kFW) {
+        const double2 l = cdivd(colk[i], d);
+        colk[i] = l;
+        for (int j = k + 1; j < k0 + kb; ++j) csub_mul(F[i + (int64_t)j * m], l, F[k + (int64_t)j * m]);
+      }
+      __syncthreads();
+    }
+    const int j0 = k0 + kb;
+    if (j0 >= m) continue;
+    // U12 rows of this block: unit-lower solve with the block's diagonal
+    load_diag_block(F + k0 + (int64_t)k0 * m, m, kb, T);
+    solve_cols_unit_lower(F + k0 + (int64_t)j0 * m, m, kb, m - j0, T, buf);
+    wg_gemm_sub(m - j0, m - j0, kb, F + j0 + (int64_t)k0 * m, m, F + k0 + (int64_t)j0 * m, m,
+                F + j0 + (int64_t)j0 * m, m);
+  }
+
+  if (tid == 0) npert[blockIdx.x] = n_pert;
+
+  // 3. Schur complement for the parent
+  if (r > 0) {
+    double2* S = upd + J.upd;
+    const int64_t r2 = (int64_t)r * r;
+    for (int64_t e = tid; e < r2; e += kFW) {
+      const int a = (int)(e % r), b = (int)(e / r);
+      S[e] = F[w + a + (int64_t)(w + b) * m];
+    }
+  }
+
+  // 4a. X = [I; L21] L11^{-1}, block columns from the last to the first
+  double2* X = ws + J.X;
+  const int nblk = (w + kNB - 1) / kNB;
+  for (int jb = nblk - 1; jb >= 0; --jb) {
+    const int j0 = jb * kNB, kb = min(kNB, w - j0), jend = j0 + kb;
+    const int64_t cnt = (int64_t)m * kb;
+    for (int64_t e = tid; e < cnt; e += kFW) {
+      const int i = (int)(e % m), c = j0 + (int)(e / m);
+      double2 v;
+      if (i < j0)
+        v = make_double2(0.0, 0.0);
+      else if (i < w)
+        v = make_double2(i == c ? 1.0 : 0.0, 0.0);
+      else
+        v = F[i + (int64_t)c * m];
+      X[i + (int64_t)c * m] = v;
+    }
+    __syncthreads();
+    if (jend < w)
+      wg_gemm_sub(m - j0, kb, w - jend, X + j0 + (int64_t)jend * m, m, F + jend + (int64_t)j0 * m, m,
+                  X + j0 + (int64_t)j0 * m, m);
+    load_diag_block(F + j0 + (int64_t)j0 * m, m, kb, T);
+    solve_rows_right_unit_lower(X + j0 + (int64_t)j0 * m, m, kb, m - j0, T, buf);
+  }
+
+  // 4b. Y = U11^{-1} [I | -U12], block rows from the last to the first
+  double2* Y = ws + J.Y;
+  for (int ib = nblk - 1; ib >= 0; --ib) {
+    const int i0 = ib * kNB, kb = min(kNB, w - i0), iend = i0 + kb;
+    const int64_t cnt = (int64_t)kb * m;
+    for (int64_t e = tid; e < cnt; e += kFW) {
+      const int q = (int)(e % kb), c = (int)(e / kb), row = i0 + q;
+      double2 v;
+      if (c < w) {
+        v = make_double2(row == c ? 1.0 : 0.0, 0.0);
+      } else {
+        const double2 u = F[row + (int64_t)c * m];
+        v = make_double2(-u.x, -u.y);
+      }
+      Y[row + (int64_t)c * w] = v;
+    }
+    __syncthreads();
+    if (iend < w)
+      wg_gemm_sub(kb, m - i0, w - iend, F + i0 + (int64_t)iend * m, m, Y + iend + (int64_t)i0 * w, w,
+                  Y + i0 + (int64_t)i0 * w, w);
+    load_diag_block(F + i0 + (int64_t)i0 * m, m, kb, T);
+    solve_cols_upper(Y + i0 + (int64_t)i0 * w, w, kb, m - i0, T, buf);
+  }
+
+  // 5. solve tiles (column-major inside a tile); diagonal-block entries
+  // outside the triangle are stored as zeros
+  int64_t off = J.pfo;
+  for (int r0 = 0; r0 < m; r0 += tile_rows) {
+    const int nr = min(tile_rows, m - r0), nc = min(w, r0 + nr);
+    const int64_t cnt = (int64_t)nr * nc;
+    for (int64_t e = tid; e < cnt; e += kFW) {
+      const int i = (int)(e % nr), col = (int)(e / nr), row = r0 + i;
+      const double2 v = (row < w && col > row) ? make_double2(0.0, 0.0) : X[row + (int64_t)col * m];
+      if (c64)
+        reinterpret_cast<float2*>(pf)[off + e] = make_float2((float)v.x, (float)v.y);
+      else
+        reinterpret_cast<double2*>(pf)[off + e] = v;
+    }
+    off += cnt;
+  }
+  off = J.pbo;
+  for (int r0 = 0; r0 < w; r0 += tile_rows) {
+    const int nr = min(tile_rows, w - r0), nc = m - r0;
+    const int64_t cnt = (int64_t)nr * nc;
+    for (int64_t e = tid; e < cnt; e += kFW) {
+      const int i = (int)(e % nr), row = r0 + i, col = r0 + (int)(e / nr);
+      const double2 v = (col < w && col < row) ? make_double2(0.0, 0.0) : Y[row + (int64_t)col * w];
+      if (c64)
+        reinterpret_cast<float2*>(pb)[off + e] = make_float2((float)v.x, (float)v.y);
+      else
+        reinterpret_cast<double2*>(pb)[off + e] = v;
+    }
+    off += cnt;
+  }
+}
+
+}  // namespace
+
+void factor_fronts(const FrontJob* jobs, int njobs, double* ws, double* upd, const int32_t* asm_pos,
+                   const int32_t* asm_val, const double* aval, const FrontChild* kids, const int32_t* ep,
+                   int32_t* piv, int32_t* npert, void* pf, void* pb, bool c64, int tile_rows, hipStream_t s) {
+  if (njobs <= 0) return;
+  front_kernel<<<(unsigned)njobs, kFW, 0, s>>>(jobs, reinterpret_cast<double2*>(ws), reinterpret_cast<double2*>(upd),
+                                               asm_pos, asm_val, reinterpret_cast<const double2*>(aval), kids, ep, piv,
+                                               npert, pf, pb, c64 ? 1 : 0, tile_rows);
+}
+
+}  // namespace dev
+}  // namespace helm

@@ -316,11 +316,12 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
 
 namespace {
 
-// Factors a batch (one matrix per thread) and uploads the panels; without a
-// device only the layout is built (pivots taken as the identity).
+// Factors a batch (on the device, or on the host with one matrix per thread)
+// into the device panels; without a device only the layout is built (pivots
+// taken as the identity).
 void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symbolic*>& Ss,
                  const std::vector<const std::vector<int64_t>*>& in_idx, int device, bool numeric, bool c64,
-                 BatchHost& B, BatchDev& Dv, int32_t& n_perturbed) {
+                 bool on_host, BatchHost& B, BatchDev& Dv, int32_t& n_perturbed, double& seconds) {
   const int nm = (int)As.size();
   const size_t esz = c64 ? sizeof(std::complex<float>) : sizeof(cplx);
   Dv.c64 = c64 ? 1 : 0;
@@ -330,7 +331,12 @@ void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symb
     pb0[i + 1] = pb0[i] + Ss[i]->bwd_entries;
   }
   std::vector<NumericOut> num(nm);
-  if (numeric) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (numeric && !on_host) {
+    Dv.pf.alloc(esz * (size_t)pf0[nm]);
+    Dv.pb.alloc(esz * (size_t)pb0[nm]);
+    factor_batch_device(As, Ss, c64, Dv, pf0, pb0, num, n_perturbed);
+  } else if (numeric) {
     Dv.pf.alloc(esz * (size_t)pf0[nm]);
     Dv.pb.alloc(esz * (size_t)pb0[nm]);
     std::string errmsg;
@@ -374,6 +380,7 @@ void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symb
       std::iota(num[i].piv.begin(), num[i].piv.end(), 0);
     }
   }
+  seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   layout_batch(Ss, in_idx, num, B);
   if (!numeric) return;
   Dv.npos = B.npos;
@@ -712,7 +719,9 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
   BatchHost fb;
   int32_t npert = 0;
   const bool c64 = opts && opts->factor_c64;
-  build_batch(As, Ss, in, c.device, on_device, c64, fb, c.fine, npert);
+  const bool on_host = opts && opts->factor_on_host;
+  double fsec = 0, csec = 0;
+  build_batch(As, Ss, in, c.device, on_device, c64, on_host, fb, c.fine, npert, fsec);
   st.factor_entries = fb.nf + fb.nb;
   st.factor_c64 = c64 ? 1 : 0;
   st.levels_fwd = (int32_t)fb.lev_f.size() - 1;
@@ -760,7 +769,7 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
     std::iota(ident.begin(), ident.end(), 0);
     BatchHost cb;
     int32_t np2 = 0;
-    build_batch({&c.E}, {&c.Esym}, {&ident}, c.device, on_device, false, cb, c.coarse, np2);
+    build_batch({&c.E}, {&c.Esym}, {&ident}, c.device, on_device, false, on_host, cb, c.coarse, np2, csec);
     npert += np2;
     c.two_level = true;
     st.n_coarse = (int32_t)c.E.n;
@@ -804,7 +813,9 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
     c.q.alloc(2 * c.D.n);
     HELM_HIP(hipDeviceSynchronize());
   }
-  (void)npert;
+  st.n_perturbed = npert;
+  st.factor_on_host = on_host ? 1 : 0;
+  st.factor_seconds = fsec + csec;
   st.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   c.precond_ready = true;
 }

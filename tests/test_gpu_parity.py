@@ -212,6 +212,37 @@ def test_tile_rows(tile_rows, coarse_tile_rows):
     say(f"[tiles] {tile_rows}/{coarse_tile_rows}: its={[i['iterations'] for i in info]}")
 
 
+@pytest.mark.parametrize("name", ["tiny", "ragged_p2", "mid_quarter_2lvl"])
+def test_device_factorisation_matches_host(name):
+    """The numeric factorisation on the device (multifrontal, MFMA Schur
+    updates) and the host reference factorisation give the same local and
+    coarse solves to rounding (both are backward-stable LU of the same
+    matrices; pivots may differ only in near-ties)."""
+    w = WORKLOADS[name]()
+    P, b, M = opre.build(w)
+    hd = helm.from_workload(w)
+    hh = helm.from_workload(w, factor_on_host=True)
+    sd, sh = hd.stats(), hh.stats()
+    assert sd["factor_on_host"] == 0 and sh["factor_on_host"] == 1
+    assert sd["n_perturbed"] == 0 and sd["factor_entries"] == sh["factor_entries"]
+    r = dvec(rand_vec(P.n, 31))
+    zd = torch.empty_like(r)
+    zh = torch.empty_like(r)
+    hd.apply_oras(r, zd)
+    hh.apply_oras(r, zh)
+    assert rel(host(zd), host(zh)) <= 1e-10
+    assert rel(host(zd), M.one_level(host(r))) <= 1e-9
+    if M.Z is not None:
+        hd.apply_coarse(r, zd)
+        hh.apply_coarse(r, zh)
+        assert rel(host(zd), host(zh)) <= 1e-10
+    # complex64 panels rounded once from either factorisation
+    hd32 = helm.from_workload(w, c64=True)
+    hd32.apply_oras(r, zd)
+    hh.apply_oras(r, zh)
+    assert rel(host(zd), host(zh)) <= 1e-4
+
+
 def test_edge_cases():
     w = wl.small_box(n=(4, 3, 3), order=2, n_parts=(2, 1, 1), overlap=1, coarse=False)
     P, b, M = opre.build(w)
