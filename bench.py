@@ -30,8 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 # rocprofv3 FETCH_SIZE/WRITE_SIZE per dispatch, scaled by a device copy of
 # known size; valid only for the kernel sources they were measured on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mid_c128.json")
-TRAFFIC_KERNEL = {"trsv_fwd": "fwd_level_kernel<double2, 0>", "trsv_bwd": "bwd_level_kernel<double2, 0>",
-                  "spmv": "sell_kernel"}
+TRAFFIC_KERNEL = {"trsv_fwd": ("fwd_level_kernel<double2, 0>",), "trsv_bwd": ("bwd_level_kernel<double2, 0>",),
+                  "spmv": ("spmv_kernel<", "sell_kernel")}
 
 
 def kernel_source_hash():
@@ -50,8 +50,10 @@ def measured_traffic(kernel):
         return None
     if t.get("device_hip_sha256") != kernel_source_hash():
         return None
-    e = t.get(TRAFFIC_KERNEL.get(kernel, ""), None)
-    return None if e is None else e["fetch_bytes"] + e["write_bytes"]
+    for name, e in t.items():
+        if isinstance(e, dict) and "fetch_bytes" in e and name.startswith(TRAFFIC_KERNEL.get(kernel, ("?",))):
+            return e["fetch_bytes"] + e["write_bytes"]
+    return None
 
 
 def log(*a):
@@ -240,6 +242,10 @@ def main():
         "p50_ms": 1e3 * float(np.percentile(times, 50)),
         "p99_ms": 1e3 * float(np.percentile(times, 99)),
         "setup_s": st["setup_seconds"] + t_asm,
+        "factorisation": {"seconds": st["factor_seconds"], "on": "host" if st["factor_on_host"] else "device",
+                          "flops": st["factor_flops"],
+                          "tflops": st["factor_flops"] / max(st["factor_seconds"], 1e-9) / 1e12,
+                          "frac_fp64_mfma_peak": st["factor_flops"] / max(st["factor_seconds"], 1e-9) / 78.6e12},
         "factor_GB": st["factor_entries"] * 16 / 1e9,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),

@@ -80,6 +80,10 @@ def main():
             out[k] = {"fetch_bytes": f, "write_bytes": w}
             lines.append(f"| `{k}` | {f / 1e6:.2f} | {w / 1e6:.2f} |")
         out["_scale"] = {"fetch": sf, "write": sw}
+        import hashlib
+        import os
+        src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "device.hip")
+        out["device_hip_sha256"] = hashlib.sha256(open(src, "rb").read()).hexdigest()
     open(args.out, "w").write("\n".join(lines) + "\n")
     if args.json_out:
         json.dump(out, open(args.json_out, "w"), indent=1)
