@@ -55,6 +55,9 @@ struct BatchHost {
   std::vector<dev::Tile> tf, tb;
   std::vector<dev::Task> kf, kb;      // workgroup tasks
   std::vector<int64_t> lev_f, lev_b;  // task ranges per level
+  std::vector<int32_t> chunk_f, chunk_b;  // LDS input entries per level
+  std::vector<int64_t> nwide_f, nwide_b;  // tiles of each level wider than 96 columns (they come first)
+  std::vector<int32_t> gy_f, gy_b;        // gather workgroups per supernode of each level
   std::vector<double> bytes_f, bytes_b;  // algorithmic bytes per level
   std::vector<double> pbytes_f, pbytes_b;  // of which panel bytes
   // staged 16-right-hand-side inputs: supernodes of every level, their
@@ -77,6 +80,9 @@ struct BatchDev {
   DVec<unsigned char> pf, pb;  // panels, complex128 or complex64 entries
   DVec<double> ubuf, y, x;
   std::vector<int64_t> lev_f, lev_b;
+  std::vector<int32_t> chunk_f, chunk_b;
+  std::vector<int64_t> nwide_f, nwide_b;
+  std::vector<int32_t> gy_f, gy_b;
   int64_t npos = 0;
   std::vector<double> bytes_f, bytes_b;  // algorithmic bytes per level
   std::vector<double> pbytes_f, pbytes_b;  // of which panel bytes

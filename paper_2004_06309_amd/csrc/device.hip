@@ -21,7 +21,7 @@ namespace dev {
 namespace {
 
 constexpr int kWG = 256;
-constexpr int kChunk = 2048;  // input columns staged in LDS per pass
+constexpr int kChunk = kLevelChunkMax;  // input columns staged in LDS per pass (at most)
 
 __device__ __forceinline__ void cfma(double& ar, double& ai, double2 a, double2 v) {
   ar = fma(a.x, v.x, ar);
@@ -81,23 +81,24 @@ struct Split {
   bool has;    // the slot holds a tile
 };
 
-__device__ __forceinline__ Split split_of(const Task& task) {
+__device__ __forceinline__ Split split_of(const Task& task, int chunk) {
   Split sp;
   const int wv = threadIdx.x >> 6;
   sp.wpt = task.wpt;
   sp.my = wv / sp.wpt;
   sp.part = wv % sp.wpt;
-  sp.region = kChunk / (4 / sp.wpt);
+  sp.region = chunk / (4 / sp.wpt);
   sp.has = sp.my < task.ntile;
   return sp;
 }
 
-// One workgroup task of a forward level (vin: kChunk LDS entries, red:
-// 4 x 64 LDS entries).
+// One workgroup task of a forward level (vin: chunk LDS entries, at least
+// 4 / wpt times the widest tile of a task with wpt < 4; red: 4 x 64 LDS
+// entries).
 template <class PT>
 __device__ __forceinline__ void fwd_task(const Task& task, const Batch& b, const double2* __restrict__ bin,
-                                         double2* vin, double2 (*red)[64]) {
-  const Split sp = split_of(task);
+                                         double2* vin, double2 (*red)[64], int chunk) {
+  const Split sp = split_of(task, chunk);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   Tile t{};
   int s = 0, c0 = 0, w = 0, frow0 = 0;
@@ -115,7 +116,7 @@ __device__ __forceinline__ void fwd_task(const Task& task, const Batch& b, const
   double ar = 0, ai = 0;
   // all waves of a workgroup run the same number of passes: one, unless the
   // workgroup holds a single wide tile
-  const int npass = sp.wpt == 4 ? (t.ncols + kChunk - 1) / kChunk : 1;
+  const int npass = sp.wpt == 4 ? (t.ncols + chunk - 1) / chunk : 1;
   for (int pass = 0; pass < npass; ++pass) {
     const int cb = pass * sp.region;
     const int cn = sp.has ? min(sp.region, t.ncols - cb) : 0;
@@ -163,8 +164,9 @@ __device__ __forceinline__ void fwd_task(const Task& task, const Batch& b, const
 }
 
 template <class PT>
-__device__ __forceinline__ void bwd_task(const Task& task, const Batch& b, double2* vin, double2 (*red)[64]) {
-  const Split sp = split_of(task);
+__device__ __forceinline__ void bwd_task(const Task& task, const Batch& b, double2* vin, double2 (*red)[64],
+                                         int chunk) {
+  const Split sp = split_of(task, chunk);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   Tile t{};
   int c0 = 0, w = 0;
@@ -181,7 +183,7 @@ __device__ __forceinline__ void bwd_task(const Task& task, const Batch& b, doubl
   const double2* __restrict__ yv = reinterpret_cast<const double2*>(b.y);
   const double2* xv = reinterpret_cast<const double2*>(b.x);
   double ar = 0, ai = 0;
-  const int npass = sp.wpt == 4 ? (t.ncols + kChunk - 1) / kChunk : 1;
+  const int npass = sp.wpt == 4 ? (t.ncols + chunk - 1) / chunk : 1;
   for (int pass = 0; pass < npass; ++pass) {
     const int cb = pass * sp.region;
     const int cn = sp.has ? min(sp.region, t.ncols - cb) : 0;
@@ -210,19 +212,21 @@ __device__ __forceinline__ void bwd_task(const Task& task, const Batch& b, doubl
   }
 }
 
+// The input-column buffer is dynamic LDS sized per level (chunk entries), so
+// levels of narrow tiles keep more workgroups resident per CU.
 template <class PT, int kCoarse>
 __global__ __launch_bounds__(kWG) void fwd_level_kernel(const Task* __restrict__ tasks, Batch b,
-                                                        const double2* __restrict__ bin) {
-  __shared__ double2 vin[kChunk];
+                                                        const double2* __restrict__ bin, int chunk) {
+  extern __shared__ double2 vin[];
   __shared__ double2 red[4][64];
-  fwd_task<PT>(tasks[blockIdx.x], b, bin, vin, red);
+  fwd_task<PT>(tasks[blockIdx.x], b, bin, vin, red, chunk);
 }
 
 template <class PT, int kCoarse>
-__global__ __launch_bounds__(kWG) void bwd_level_kernel(const Task* __restrict__ tasks, Batch b) {
-  __shared__ double2 vin[kChunk];
+__global__ __launch_bounds__(kWG) void bwd_level_kernel(const Task* __restrict__ tasks, Batch b, int chunk) {
+  extern __shared__ double2 vin[];
   __shared__ double2 red[4][64];
-  bwd_task<PT>(tasks[blockIdx.x], b, vin, red);
+  bwd_task<PT>(tasks[blockIdx.x], b, vin, red, chunk);
 }
 
 // Whole forward + backward solve of a small batch (the coarse matrix) in one
@@ -235,14 +239,14 @@ __global__ __launch_bounds__(kWG) void batch_solve_coop_kernel(Batch b, const do
   cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   for (int l = 0; l < lv.nf; ++l) {
     for (int64_t t = lv.f[l] + blockIdx.x; t < lv.f[l + 1]; t += gridDim.x) {
-      fwd_task<double2>(b.kf[t], b, bin, vin, red);
+      fwd_task<double2>(b.kf[t], b, bin, vin, red, kChunk);
       __syncthreads();
     }
     grid.sync();
   }
   for (int l = 0; l < lv.nb; ++l) {
     for (int64_t t = lv.b[l] + blockIdx.x; t < lv.b[l + 1]; t += gridDim.x) {
-      bwd_task<double2>(b.kb[t], b, vin, red);
+      bwd_task<double2>(b.kb[t], b, vin, red, kChunk);
       __syncthreads();
     }
     grid.sync();
@@ -630,27 +634,30 @@ inline unsigned blocks8_for(int64_t n) { return (blocks_for(n) + 7) / 8 * 8; }
 
 int waves_per_tile(int ncols) { return ncols <= 96 ? 1 : (ncols <= 384 ? 2 : 4); }
 
-void fwd_level(const Batch& b, int64_t task0, int64_t ntasks, const double* bin, bool coarse, hipStream_t s) {
+void fwd_level(const Batch& b, int64_t task0, int64_t ntasks, const double* bin, int chunk, bool coarse,
+               hipStream_t s) {
   if (ntasks <= 0) return;
   const Task* k = b.kf + task0;
   const double2* in = reinterpret_cast<const double2*>(bin);
+  const size_t lds = sizeof(double2) * (size_t)chunk;
   if (coarse)
-    fwd_level_kernel<double2, 1><<<(unsigned)ntasks, kWG, 0, s>>>(k, b, in);
+    fwd_level_kernel<double2, 1><<<(unsigned)ntasks, kWG, lds, s>>>(k, b, in, chunk);
   else if (b.c64)
-    fwd_level_kernel<float2, 0><<<(unsigned)ntasks, kWG, 0, s>>>(k, b, in);
+    fwd_level_kernel<float2, 0><<<(unsigned)ntasks, kWG, lds, s>>>(k, b, in, chunk);
   else
-    fwd_level_kernel<double2, 0><<<(unsigned)ntasks, kWG, 0, s>>>(k, b, in);
+    fwd_level_kernel<double2, 0><<<(unsigned)ntasks, kWG, lds, s>>>(k, b, in, chunk);
 }
 
-void bwd_level(const Batch& b, int64_t task0, int64_t ntasks, bool coarse, hipStream_t s) {
+void bwd_level(const Batch& b, int64_t task0, int64_t ntasks, int chunk, bool coarse, hipStream_t s) {
   if (ntasks <= 0) return;
   const Task* k = b.kb + task0;
+  const size_t lds = sizeof(double2) * (size_t)chunk;
   if (coarse)
-    bwd_level_kernel<double2, 1><<<(unsigned)ntasks, kWG, 0, s>>>(k, b);
+    bwd_level_kernel<double2, 1><<<(unsigned)ntasks, kWG, lds, s>>>(k, b, chunk);
   else if (b.c64)
-    bwd_level_kernel<float2, 0><<<(unsigned)ntasks, kWG, 0, s>>>(k, b);
+    bwd_level_kernel<float2, 0><<<(unsigned)ntasks, kWG, lds, s>>>(k, b, chunk);
   else
-    bwd_level_kernel<double2, 0><<<(unsigned)ntasks, kWG, 0, s>>>(k, b);
+    bwd_level_kernel<double2, 0><<<(unsigned)ntasks, kWG, lds, s>>>(k, b, chunk);
 }
 
 int coop_grid() {

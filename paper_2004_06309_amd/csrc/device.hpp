@@ -62,8 +62,12 @@ struct Batch {
 
 // One level of the forward / backward sweep: tasks [task0, task0 + ntasks).
 // coarse selects a separate instantiation so profiles tell the two apart.
-void fwd_level(const Batch& b, int64_t task0, int64_t ntasks, const double* bin, bool coarse, hipStream_t s);
-void bwd_level(const Batch& b, int64_t task0, int64_t ntasks, bool coarse, hipStream_t s);
+// chunk: LDS entries for the level's input columns (level_chunk).
+void fwd_level(const Batch& b, int64_t task0, int64_t ntasks, const double* bin, int chunk, bool coarse,
+               hipStream_t s);
+void bwd_level(const Batch& b, int64_t task0, int64_t ntasks, int chunk, bool coarse, hipStream_t s);
+// Largest LDS input buffer a level solve uses (entries).
+constexpr int kLevelChunkMax = 2048;
 // One frontal matrix of the device factorisation (offsets in complex
 // entries).
 struct FrontJob {
@@ -157,10 +161,14 @@ void bwd_level_block(const Batch& b, int64_t tile0, int64_t ntiles, int S, const
 // 16 right-hand sides on MFMA: stage every supernode's input block of the
 // level once (gather kernels, one workgroup per supernode of `sns`), then
 // one 4-wave workgroup per tile reads its B operands from the staged block.
-void fwd_level_mfma(const Batch& b, const int32_t* sns, int64_t nsn, int64_t tile0, int64_t ntiles,
-                    const double* bin, double* yb, double* ubb, void* stage, bool coarse, hipStream_t s);
-void bwd_level_mfma(const Batch& b, const int32_t* sns, int64_t nsn, int64_t tile0, int64_t ntiles,
-                    const double* yb, double* xb, void* stage, bool coarse, hipStream_t s);
+// The first nwide tiles of the range are wide (four waves each), the rest
+// narrow (one wave each); gy = workgroups per supernode of the gather (each
+// takes every gy-th run of 256 block entries).
+void fwd_level_mfma(const Batch& b, const int32_t* sns, int64_t nsn, int gy, int64_t tile0, int64_t ntiles,
+                    int64_t nwide, const double* bin, double* yb, double* ubb, void* stage, bool coarse,
+                    hipStream_t s);
+void bwd_level_mfma(const Batch& b, const int32_t* sns, int64_t nsn, int gy, int64_t tile0, int64_t ntiles,
+                    int64_t nwide, const double* yb, double* xb, void* stage, bool coarse, hipStream_t s);
 void sell_spmv_block(int64_t n, int64_t nslices, const int64_t* soff, const int32_t* swidth, const int32_t* perm,
                      const int32_t* col, const double* val, int S, const double* x, const double* b, double* y,
                      hipStream_t s);

@@ -319,7 +319,8 @@ __global__ __launch_bounds__(kWG) void gather_fwd_kernel(const int32_t* __restri
   const int sn = sns[blockIdx.x];
   const int c0 = b.sn_c0[sn], w = b.sn_w[sn], frow0 = b.sn_frow0[sn];
   C2* g = G + b.goff_f[sn] * 16;
-  for (int e = threadIdx.x; e < w * 16; e += kWG) {
+  // workgroup blockIdx.y of gridDim.y takes every gridDim.y-th 256 entries
+  for (int e = blockIdx.y * kWG + threadIdx.x; e < w * 16; e += gridDim.y * kWG) {
     const int k = e >> 4, r = e & 15;
     double2 v = bin[(int64_t)b.bidx[c0 + k] * 16 + r];
     const int fr = frow0 + k;
@@ -342,15 +343,30 @@ __global__ __launch_bounds__(kWG) void gather_bwd_kernel(const int32_t* __restri
   const int c0 = b.sn_c0[sn], w = b.sn_w[sn], r_ = b.sn_r[sn];
   const int64_t roff = b.sn_roff[sn];
   C2* g = G + b.goff_b[sn] * 16;
-  for (int e = threadIdx.x; e < (w + r_) * 16; e += kWG) {
+  for (int e = blockIdx.y * kWG + threadIdx.x; e < (w + r_) * 16; e += gridDim.y * kWG) {
     const int c = e >> 4, r = e & 15;
     const double2 v = c < w ? yb[(int64_t)(c0 + c) * 16 + r] : xb[(int64_t)b.rows[roff + (c - w)] * 16 + r];
     g[e] = C2{(T)v.x, (T)v.y};
   }
 }
 
+// Panel loads are streamed once per sweep: non-temporal, so they do not
+// evict the staged input blocks and vectors from the caches.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ldp(const double2* p) {
+  const dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float2 ldp(const float2* p) {
+  const fvec2 v = __builtin_nontemporal_load(reinterpret_cast<const fvec2*>(p));
+  return make_float2(v.x, v.y);
+}
+
 // 4 waves per tile: wave q accumulates the k-steps q, q + 4, ... of the
-// tile, then the partial accumulators are summed through LDS.
+// tile, then the partial accumulators are summed through LDS.  The loads of
+// the next two k-steps are issued before the MFMAs of the current one, so a
+// wave keeps about three steps of panel in flight while its MFMAs run.
 template <class T, int kFwd>
 __device__ __forceinline__ void mfma_tile4(const Tile& t, const typename Mf<T>::C2* __restrict__ P,
                                            const typename Mf<T>::C2* __restrict__ Bk, typename Mf<T>::V4* dre,
@@ -358,22 +374,36 @@ __device__ __forceinline__ void mfma_tile4(const Tile& t, const typename Mf<T>::
   using C2 = typename Mf<T>::C2;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
   const int nr = t.nrows, cn = t.ncols, nrb = (nr + 15) >> 4;
-  for (int k0 = 4 * wv; k0 < cn; k0 += 16) {
+  auto load = [&](int k0, C2& bv, C2 (&a)[4]) {
     const int k = k0 + lk;
-    const C2 bv = k < cn ? Bk[(int64_t)k * 16 + lr] : C2{0, 0};
-    C2 a[4];
+    bv = k < cn ? Bk[(int64_t)k * 16 + lr] : C2{0, 0};
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
       const int row = 16 * rb + lr;
-      a[rb] = (rb < nrb && row < nr && k < cn) ? P[(int64_t)k * nr + row] : C2{0, 0};
+      a[rb] = (rb < nrb && row < nr && k < cn) ? ldp(P + (int64_t)k * nr + row) : C2{0, 0};
     }
+  };
+  C2 b0, b1, a0[4], a1[4];
+  int k0 = 4 * wv;
+  load(k0, b0, a0);
+  load(k0 + 16, b1, a1);
+  for (; k0 < cn; k0 += 16) {
+    C2 b2, a2[4];
+    load(k0 + 32, b2, a2);
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
       if (rb >= nrb) break;
-      dre[rb] = Mf<T>::mma(a[rb].x, bv.x, dre[rb]);
-      dre[rb] = Mf<T>::mma(-a[rb].y, bv.y, dre[rb]);
-      dim[rb] = Mf<T>::mma(a[rb].x, bv.y, dim[rb]);
-      dim[rb] = Mf<T>::mma(a[rb].y, bv.x, dim[rb]);
+      dre[rb] = Mf<T>::mma(a0[rb].x, b0.x, dre[rb]);
+      dre[rb] = Mf<T>::mma(-a0[rb].y, b0.y, dre[rb]);
+      dim[rb] = Mf<T>::mma(a0[rb].x, b0.y, dim[rb]);
+      dim[rb] = Mf<T>::mma(a0[rb].y, b0.x, dim[rb]);
+    }
+    b0 = b1;
+    b1 = b2;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      a0[rb] = a1[rb];
+      a1[rb] = a2[rb];
     }
   }
 }
@@ -437,6 +467,71 @@ __global__ __launch_bounds__(kWG) void level_mfma_kernel(const Tile* __restrict_
       }
     }
     __syncthreads();
+  }
+}
+
+// Narrow tiles (at most 96 input columns): one wave per tile, all four
+// 16-row blocks of the tile in that wave, so there is no cross-wave
+// reduction; the accumulators go straight to y / the update vectors (FP64
+// accumulator register j of lane l holds row 4 j + l / 16, FP32 row
+// 4 (l / 16) + j, right-hand side l % 16).
+template <class T, int kFwd, int kCoarse>
+__global__ __launch_bounds__(kWG) void level_mfma_narrow_kernel(const Tile* __restrict__ tiles, int64_t ntiles,
+                                                                Batch b, const typename Mf<T>::C2* __restrict__ G,
+                                                                double2* __restrict__ out,
+                                                                double2* __restrict__ ubb) {
+  using C2 = typename Mf<T>::C2;
+  using V4 = typename Mf<T>::V4;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
+  const int64_t ti = (int64_t)blockIdx.x * (kWG / 64) + wv;
+  if (ti >= ntiles) return;  // a whole wave; the kernel has no barrier
+  const Tile t = tiles[ti];
+  const int sn = t.sn, c0 = b.sn_c0[sn], w = b.sn_w[sn];
+  const C2* __restrict__ P = reinterpret_cast<const C2*>(kFwd ? b.pf : b.pb) + t.off;
+  const C2* Bk = G + ((kFwd ? b.goff_f[sn] : b.goff_b[sn]) + t.col0) * 16;
+  const int nr = t.nrows, cn = t.ncols, nrb = (nr + 15) >> 4;
+  V4 dre[4], dim[4];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) dre[rb] = dim[rb] = V4{0, 0, 0, 0};
+  for (int k0 = 0; k0 < cn; k0 += 4) {
+    const int k = k0 + lk;
+    const C2 bv = k < cn ? Bk[(int64_t)k * 16 + lr] : C2{0, 0};
+    C2 a[4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      const int row = 16 * rb + lr;
+      a[rb] = (rb < nrb && row < nr && k < cn) ? ldp(P + (int64_t)k * nr + row) : C2{0, 0};
+    }
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      if (rb >= nrb) break;
+      dre[rb] = Mf<T>::mma(a[rb].x, bv.x, dre[rb]);
+      dre[rb] = Mf<T>::mma(-a[rb].y, bv.y, dre[rb]);
+      dim[rb] = Mf<T>::mma(a[rb].x, bv.y, dim[rb]);
+      dim[rb] = Mf<T>::mma(a[rb].y, bv.x, dim[rb]);
+    }
+  }
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    if (rb >= nrb) break;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int rloc = 16 * rb + Mf<T>::row(lk, j);
+      if (rloc >= nr) continue;
+      double ar = (double)dre[rb][j], ai = (double)dim[rb][j];
+      const int row = t.row0 + rloc;
+      if (!kFwd || row < w) {
+        out[(int64_t)(c0 + row) * 16 + lr] = make_double2(ar, ai);
+      } else {
+        const int fr = b.sn_frow0[sn] + row;
+        for (int e = b.fcon_ptr[fr]; e < b.fcon_ptr[fr + 1]; ++e) {
+          const double2 u = ubb[(int64_t)b.fcon_idx[e] * 16 + lr];
+          ar += u.x;
+          ai += u.y;
+        }
+        ubb[(int64_t)(b.sn_uoff[sn] + row - w) * 16 + lr] = make_double2(ar, ai);
+      }
+    }
   }
 }
 
@@ -662,42 +757,55 @@ void bwd_level_block(const Batch& b, int64_t tile0, int64_t ntiles, int S, const
   });
 }
 
-void fwd_level_mfma(const Batch& b, const int32_t* sns, int64_t nsn, int64_t tile0, int64_t ntiles,
-                    const double* bin, double* yb, double* ubb, void* stage, bool coarse, hipStream_t s) {
+// Tiles [tile0, tile0 + nwide) go to the 4-wave kernel, the rest (narrow,
+// at the end of the level) to the one-wave-per-tile kernel.
+template <class T, int kFwd, int kCoarse>
+void level_mfma_launch(const Batch& b, const Tile* tiles, int64_t ntiles, int64_t nwide,
+                       const typename Mf<T>::C2* G, double2* out, double2* u, hipStream_t s) {
+  if (nwide > 0) level_mfma_kernel<T, kFwd, kCoarse><<<(unsigned)nwide, kWG, 0, s>>>(tiles, b, G, out, u);
+  const int64_t nn = ntiles - nwide;
+  if (nn > 0)
+    level_mfma_narrow_kernel<T, kFwd, kCoarse><<<(unsigned)((nn + 3) / 4), kWG, 0, s>>>(tiles + nwide, nn, b, G, out,
+                                                                                        u);
+}
+
+void fwd_level_mfma(const Batch& b, const int32_t* sns, int64_t nsn, int gy, int64_t tile0, int64_t ntiles,
+                    int64_t nwide, const double* bin, double* yb, double* ubb, void* stage, bool coarse,
+                    hipStream_t s) {
   if (ntiles <= 0) return;
   auto in = reinterpret_cast<const double2*>(bin);
   auto y = reinterpret_cast<double2*>(yb);
   auto u = reinterpret_cast<double2*>(ubb);
   if (b.c64 && !coarse) {
     auto G = reinterpret_cast<float2*>(stage);
-    gather_fwd_kernel<float><<<(unsigned)nsn, kWG, 0, s>>>(sns, b, in, u, G);
-    level_mfma_kernel<float, 1, 0><<<(unsigned)ntiles, kWG, 0, s>>>(b.tf + tile0, b, G, y, u);
+    gather_fwd_kernel<float><<<dim3((unsigned)nsn, (unsigned)gy), kWG, 0, s>>>(sns, b, in, u, G);
+    level_mfma_launch<float, 1, 0>(b, b.tf + tile0, ntiles, nwide, G, y, u, s);
   } else {
     auto G = reinterpret_cast<double2*>(stage);
-    gather_fwd_kernel<double><<<(unsigned)nsn, kWG, 0, s>>>(sns, b, in, u, G);
+    gather_fwd_kernel<double><<<dim3((unsigned)nsn, (unsigned)gy), kWG, 0, s>>>(sns, b, in, u, G);
     if (coarse)
-      level_mfma_kernel<double, 1, 1><<<(unsigned)ntiles, kWG, 0, s>>>(b.tf + tile0, b, G, y, u);
+      level_mfma_launch<double, 1, 1>(b, b.tf + tile0, ntiles, nwide, G, y, u, s);
     else
-      level_mfma_kernel<double, 1, 0><<<(unsigned)ntiles, kWG, 0, s>>>(b.tf + tile0, b, G, y, u);
+      level_mfma_launch<double, 1, 0>(b, b.tf + tile0, ntiles, nwide, G, y, u, s);
   }
 }
 
-void bwd_level_mfma(const Batch& b, const int32_t* sns, int64_t nsn, int64_t tile0, int64_t ntiles,
-                    const double* yb, double* xb, void* stage, bool coarse, hipStream_t s) {
+void bwd_level_mfma(const Batch& b, const int32_t* sns, int64_t nsn, int gy, int64_t tile0, int64_t ntiles,
+                    int64_t nwide, const double* yb, double* xb, void* stage, bool coarse, hipStream_t s) {
   if (ntiles <= 0) return;
   auto y = reinterpret_cast<const double2*>(yb);
   auto x = reinterpret_cast<double2*>(xb);
   if (b.c64 && !coarse) {
     auto G = reinterpret_cast<float2*>(stage);
-    gather_bwd_kernel<float><<<(unsigned)nsn, kWG, 0, s>>>(sns, b, y, x, G);
-    level_mfma_kernel<float, 0, 0><<<(unsigned)ntiles, kWG, 0, s>>>(b.tb + tile0, b, G, x, nullptr);
+    gather_bwd_kernel<float><<<dim3((unsigned)nsn, (unsigned)gy), kWG, 0, s>>>(sns, b, y, x, G);
+    level_mfma_launch<float, 0, 0>(b, b.tb + tile0, ntiles, nwide, G, x, nullptr, s);
   } else {
     auto G = reinterpret_cast<double2*>(stage);
-    gather_bwd_kernel<double><<<(unsigned)nsn, kWG, 0, s>>>(sns, b, y, x, G);
+    gather_bwd_kernel<double><<<dim3((unsigned)nsn, (unsigned)gy), kWG, 0, s>>>(sns, b, y, x, G);
     if (coarse)
-      level_mfma_kernel<double, 0, 1><<<(unsigned)ntiles, kWG, 0, s>>>(b.tb + tile0, b, G, x, nullptr);
+      level_mfma_launch<double, 0, 1>(b, b.tb + tile0, ntiles, nwide, G, x, nullptr, s);
     else
-      level_mfma_kernel<double, 0, 0><<<(unsigned)ntiles, kWG, 0, s>>>(b.tb + tile0, b, G, x, nullptr);
+      level_mfma_launch<double, 0, 0>(b, b.tb + tile0, ntiles, nwide, G, x, nullptr, s);
   }
 }
 

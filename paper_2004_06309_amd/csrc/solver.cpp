@@ -292,26 +292,62 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
   B.goff_f.assign(nsn, 0);
   B.goff_b.assign(nsn, 0);
   auto stage_levels = [&](const std::vector<std::vector<dev::Tile>>& levels, bool fwd, std::vector<int32_t>& gsn,
-                          std::vector<int64_t>& glev, std::vector<int64_t>& goff) {
+                          std::vector<int64_t>& glev, std::vector<int64_t>& goff, std::vector<int32_t>& gy) {
     glev.assign(1, 0);
+    gy.clear();
     for (const auto& l : levels) {
-      int64_t cols = 0;
+      int64_t cols = 0, widest = 1;
       int32_t last = -1;
       for (const auto& t : l) {
         if (t.sn == last) continue;
         last = t.sn;
         gsn.push_back(t.sn);
         goff[t.sn] = cols;
-        cols += B.w[t.sn] + (fwd ? 0 : B.sn_r[t.sn]);
+        const int64_t c = B.w[t.sn] + (fwd ? 0 : B.sn_r[t.sn]);
+        cols += c;
+        widest = std::max(widest, c);
       }
       glev.push_back((int64_t)gsn.size());
+      // a few workgroups per supernode, so the wide blocks of the upper
+      // levels are gathered in parallel without launching idle workgroups
+      gy.push_back((int32_t)std::min<int64_t>(4, (widest * dev::kMaxBlock + 255) / 256));
       B.stage_cols = std::max(B.stage_cols, cols);
     }
   };
-  stage_levels(lf, true, B.gsn_f, B.gsn_lev_f, B.goff_f);
-  stage_levels(lb, false, B.gsn_b, B.gsn_lev_b, B.goff_b);
+  stage_levels(lf, true, B.gsn_f, B.gsn_lev_f, B.goff_f, B.gy_f);
+  stage_levels(lb, false, B.gsn_b, B.gsn_lev_b, B.goff_b, B.gy_b);
   make_tasks(lf, true, B.tf, B.kf, B.lev_f, B.bytes_f, B.pbytes_f);
   make_tasks(lb, false, B.tb, B.kb, B.lev_b, B.bytes_b, B.pbytes_b);
+  // LDS input buffer of every level: each slot of a task with wpt < 4 holds
+  // its whole tile; a single-tile task takes up to kLevelChunkMax per pass
+  auto chunks = [&](const std::vector<dev::Task>& K, const std::vector<dev::Tile>& T, const std::vector<int64_t>& lev,
+                    std::vector<int32_t>& out) {
+    out.clear();
+    for (size_t l = 0; l + 1 < lev.size(); ++l) {
+      int64_t c = 64;
+      for (int64_t q = lev[l]; q < lev[l + 1]; ++q) {
+        int64_t wide = 0;
+        for (int u = 0; u < K[q].ntile; ++u) wide = std::max<int64_t>(wide, T[K[q].tile0 + u].ncols);
+        c = std::max<int64_t>(c, K[q].wpt == 4 ? std::min<int64_t>(wide, dev::kLevelChunkMax) : (4 / K[q].wpt) * wide);
+      }
+      out.push_back((int32_t)std::min<int64_t>((c + 63) / 64 * 64, dev::kLevelChunkMax));
+    }
+  };
+  chunks(B.kf, B.tf, B.lev_f, B.chunk_f);
+  chunks(B.kb, B.tb, B.lev_b, B.chunk_b);
+  // tasks are sorted widest class first, so a level's narrow tiles (one
+  // wave per tile) are its last ones
+  auto wide = [&](const std::vector<dev::Task>& K, const std::vector<int64_t>& lev, std::vector<int64_t>& out) {
+    out.clear();
+    for (size_t l = 0; l + 1 < lev.size(); ++l) {
+      int64_t nw = 0;
+      for (int64_t q = lev[l]; q < lev[l + 1]; ++q)
+        if (K[q].wpt > 1) nw += K[q].ntile;
+      out.push_back(nw);
+    }
+  };
+  wide(B.kf, B.lev_f, B.nwide_f);
+  wide(B.kb, B.lev_b, B.nwide_b);
 }
 
 namespace {
@@ -386,6 +422,12 @@ void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symb
   Dv.npos = B.npos;
   Dv.lev_f = B.lev_f;
   Dv.lev_b = B.lev_b;
+  Dv.chunk_f = B.chunk_f;
+  Dv.chunk_b = B.chunk_b;
+  Dv.nwide_f = B.nwide_f;
+  Dv.nwide_b = B.nwide_b;
+  Dv.gy_f = B.gy_f;
+  Dv.gy_b = B.gy_b;
   Dv.bytes_f = B.bytes_f;
   Dv.bytes_b = B.bytes_b;
   Dv.pbytes_f = B.pbytes_f;
@@ -435,12 +477,12 @@ void batch_solve(const BatchDev& b, const double* in, hipStream_t s, Profiler* p
   const bool each = prof && prof->on && fine;
   for (size_t l = 0; l + 1 < b.lev_f.size(); ++l) {
     if (each) prof->begin(s);
-    dev::fwd_level(v, b.lev_f[l], b.lev_f[l + 1] - b.lev_f[l], in, !fine, s);
+    dev::fwd_level(v, b.lev_f[l], b.lev_f[l + 1] - b.lev_f[l], in, b.chunk_f[l], !fine, s);
     if (each) prof->end(HELM_K_TRSV_FWD, b.bytes_f[l], s);
   }
   for (size_t l = 0; l + 1 < b.lev_b.size(); ++l) {
     if (each) prof->begin(s);
-    dev::bwd_level(v, b.lev_b[l], b.lev_b[l + 1] - b.lev_b[l], !fine, s);
+    dev::bwd_level(v, b.lev_b[l], b.lev_b[l + 1] - b.lev_b[l], b.chunk_b[l], !fine, s);
     if (each) prof->end(HELM_K_TRSV_BWD, b.bytes_b[l], s);
   }
 }
@@ -1088,8 +1130,9 @@ void batch_solve_block(BatchDev& b, int S, const double* in, hipStream_t s, Prof
   for (size_t l = 0; l + 1 < b.tiles_f.size(); ++l) {
     if (each) prof->begin(s);
     if (mfma)
-      dev::fwd_level_mfma(v, b.gsn_f.p + b.gsn_lev_f[l], b.gsn_lev_f[l + 1] - b.gsn_lev_f[l], b.tiles_f[l],
-                          b.tiles_f[l + 1] - b.tiles_f[l], in, b.y_b.p, b.ubuf_b.p, b.stage.p, !fine, s);
+      dev::fwd_level_mfma(v, b.gsn_f.p + b.gsn_lev_f[l], b.gsn_lev_f[l + 1] - b.gsn_lev_f[l], b.gy_f[l], b.tiles_f[l],
+                          b.tiles_f[l + 1] - b.tiles_f[l], b.nwide_f[l], in, b.y_b.p, b.ubuf_b.p, b.stage.p, !fine,
+                          s);
     else
       dev::fwd_level_block(v, b.tiles_f[l], b.tiles_f[l + 1] - b.tiles_f[l], S, in, b.y_b.p, b.ubuf_b.p, !fine, s);
     if (each) prof->end(HELM_K_TRSV_FWD, b.pbytes_f[l] + S * (b.bytes_f[l] - b.pbytes_f[l]), s);
@@ -1097,8 +1140,8 @@ void batch_solve_block(BatchDev& b, int S, const double* in, hipStream_t s, Prof
   for (size_t l = 0; l + 1 < b.tiles_b.size(); ++l) {
     if (each) prof->begin(s);
     if (mfma)
-      dev::bwd_level_mfma(v, b.gsn_b.p + b.gsn_lev_b[l], b.gsn_lev_b[l + 1] - b.gsn_lev_b[l], b.tiles_b[l],
-                          b.tiles_b[l + 1] - b.tiles_b[l], b.y_b.p, b.x_b.p, b.stage.p, !fine, s);
+      dev::bwd_level_mfma(v, b.gsn_b.p + b.gsn_lev_b[l], b.gsn_lev_b[l + 1] - b.gsn_lev_b[l], b.gy_b[l], b.tiles_b[l],
+                          b.tiles_b[l + 1] - b.tiles_b[l], b.nwide_b[l], b.y_b.p, b.x_b.p, b.stage.p, !fine, s);
     else
       dev::bwd_level_block(v, b.tiles_b[l], b.tiles_b[l + 1] - b.tiles_b[l], S, b.y_b.p, b.x_b.p, !fine, s);
     if (each) prof->end(HELM_K_TRSV_BWD, b.pbytes_b[l] + S * (b.bytes_b[l] - b.pbytes_b[l]), s);
