@@ -60,6 +60,74 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def run_serving(n_requests, rate, seed=3):
+    """Continuous batching over two resident operators of the thrust model
+    (5 Hz on the 80 x 80 x 20 P2 mesh, 3 Hz on the 40 x 40 x 10 one), both
+    with complex64 subdomain factors (FP64 FGMRES and coarse solve), one
+    server and stream each, 16 slots.  Requests arrive as a seeded Poisson
+    process; each carries 1-4 point sources at random surface positions
+    (10 m deep) and is done when all its sources are.  Reports solves/s over
+    the makespan and request latency (arrival to last source done)."""
+    import torch
+
+    from paper_2004_06309_amd import helm
+    from paper_2004_06309_amd import workloads as wl
+
+    ops = [wl.mid(), wl.mid(scale=2, freq=3.0)]
+    ctxs, servers, streams = [], [], []
+    for w in ops:
+        h = helm.from_workload(w, c64=True)
+        st = torch.cuda.Stream()
+        ctxs.append(h)
+        streams.append(st)
+        servers.append(helm.Server(h, slots=16, restart=w.restart, tol=w.tol, stream=st))
+    rng = np.random.default_rng(seed)
+    t_arr = np.cumsum(rng.exponential(1.0 / rate, n_requests))
+    op_of = rng.integers(0, len(ops), n_requests)
+    nsrc = rng.integers(1, 5, n_requests)
+    reqs = []  # (arrival, op, [tags])
+    B, U, tag = {}, {}, 0
+    for r in range(n_requests):
+        h = ctxs[op_of[r]]
+        tags = []
+        for _ in range(nsrc[r]):
+            xs = np.array([rng.uniform(100.0, 7900.0), rng.uniform(100.0, 7900.0), 10.0])
+            B[tag] = torch.from_numpy(h.point_source(xs)).to("cuda")
+            U[tag] = torch.zeros_like(B[tag])
+            tags.append(tag)
+            tag += 1
+        reqs.append((float(t_arr[r]), int(op_of[r]), tags))
+    torch.cuda.synchronize()
+    done_at, its, nxt = {}, {}, 0
+    t0 = time.perf_counter()
+    while len(done_at) < tag:
+        now = time.perf_counter() - t0
+        while nxt < n_requests and reqs[nxt][0] <= now:
+            _, op, tags = reqs[nxt]
+            for t in tags:
+                servers[op].submit(B[t], U[t], t)
+            nxt += 1
+        stepped = sum(s_.launch() for s_ in servers)
+        for s_ in servers:
+            for e in s_.finish():
+                if e["status"] != helm.HELM_OK:
+                    raise RuntimeError(f"served solve failed: {e}")
+                done_at[e["tag"]] = time.perf_counter() - t0
+                its[e["tag"]] = e["iterations"]
+        if stepped == 0 and nxt < n_requests:
+            time.sleep(max(0.0, min(0.01, reqs[nxt][0] - (time.perf_counter() - t0))))
+    makespan = max(done_at.values()) - reqs[0][0]
+    lat = np.array([max(done_at[t] for t in tags) - a for a, _, tags in reqs])
+    for s_ in servers:
+        s_.close()
+    return {"requests": n_requests, "solves": tag, "arrival_rate_per_s": rate,
+            "operators": [f"{w.name}: {h.n} dofs, f={w.omega / (2 * np.pi):.0f} Hz" for w, h in zip(ops, ctxs)],
+            "slots_per_operator": 16, "precond_precision": "c64 factors, FP64 FGMRES",
+            "solves_per_s": tag / makespan, "makespan_s": makespan,
+            "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+            "mean_iterations": float(np.mean(list(its.values())))}
+
+
 def cpu_baseline(w, iters_per_solve):
     """Times the CPU oracle (single thread) on a bounded sample of the same
     workload and scales it to GMRES iterations per second: one of the
@@ -132,6 +200,9 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the complex64-factor measurement")
     ap.add_argument("--nrhs", type=int, default=16, help="right-hand sides of the batched measurement (0: skip)")
     ap.add_argument("--block", type=int, default=16, help="right-hand sides advanced together")
+    ap.add_argument("--serve", type=int, default=40,
+                    help="requests of the serving measurement (Poisson arrivals over two operators; 0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=4.0, help="mean request arrivals per second")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -308,6 +379,12 @@ def main():
         if args.nrhs > 0:
             out["batched_fp32"] = run_batched(h32, "fp32")
             out["batched_fp32"]["speedup_vs_single_fp64"] = out["batched_fp32"]["solves_per_s"] / solves_per_s
+        del h32
+    if args.serve > 0 and args.config == "mid":
+        log(f"[bench] serving: {args.serve} requests at {args.serve_rate}/s")
+        torch.cuda.empty_cache()
+        out["serving"] = run_serving(args.serve, args.serve_rate)
+        log(f"[bench] serving: {out['serving']}")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(w, float(np.mean(its)))

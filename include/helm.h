@@ -97,6 +97,32 @@ typedef struct helm_solve_info {
   double seconds;          /* wall time of this RHS (device-synchronised)  */
 } helm_solve_info;
 
+/* Serving: continuous batching of single-right-hand-side requests over one
+ * factored operator (Section "Numerical experiments": many sources per
+ * operator).  Up to 16 requests are in flight as slots of a pseudo-block
+ * GMRES; a request waiting in the queue takes the first slot that frees up,
+ * at the next Arnoldi step, while the others continue their own cycles. */
+typedef struct helm_server helm_server;
+
+typedef struct helm_server_opts {
+  int32_t slots;           /* requests in flight, 1..16; 0 = as many as the
+                              free device memory allows (at most 16)      */
+  int32_t restart;         /* GMRES(m) restart length, 1..50, 0 = 50       */
+  int32_t maxit;           /* Arnoldi steps per request, 0 = 1000          */
+  int32_t reserved;
+  double tol;              /* true relative residual, 0 = 1e-6             */
+} helm_server_opts;
+
+typedef struct helm_server_event {
+  int64_t tag;             /* the caller's tag of the finished request     */
+  int32_t iterations;      /* Arnoldi steps it took                        */
+  int32_t converged;       /* 1 if the true relative residual <= tol       */
+  int32_t status;          /* HELM_OK, HELM_ENOCONV or HELM_ENUMERIC        */
+  int32_t reserved;
+  double relres;           /* true ||b - A u|| / ||b|| at exit            */
+  double seconds;          /* host wall time from submit to completion     */
+} helm_server_event;
+
 typedef struct helm_precond_stats {
   int32_t n_sub;           /* subdomains                                   */
   int32_t n_coarse;        /* coarse unknowns (0 = one-level)              */
@@ -122,7 +148,8 @@ typedef struct helm_precond_stats {
  * setup without a GPU).  *out is NULL on failure. */
 int helm_create(helm_ctx** out, int device_ordinal);
 
-/* Free every host and device resource of the context; NULL is accepted. */
+/* Free every host and device resource of the context; NULL is accepted.
+ * Destroy the context's server (helm_server_destroy) first. */
 void helm_destroy(helm_ctx* ctx);
 
 /* Message of the last failing call on ctx (or of helm_create when ctx is
@@ -228,6 +255,35 @@ enum {
   HELM_K_GS = 5,          /* CGS2 dots, updates, norm, scaling              */
   HELM_K_COUNT = 6
 };
+
+/* Server on a context with a factored preconditioner, running on `stream`
+ * (NULL = the null stream).  Its slots use the context's multi-right-hand-
+ * side work space: while a server exists, helm_solve, helm_assemble and
+ * helm_precond_setup on the same context return HELM_ESTATE.  *out is NULL on failure (HELM_ENOMEM when no slot
+ * fits in device memory). */
+int helm_server_create(helm_ctx* ctx, const helm_server_opts* opts, void* stream, helm_server** out);
+
+/* Queues one request: b (device c128[n], read) and u (device c128[n],
+ * written with the solution); both must stay valid until the request's
+ * completion event.  Never blocks. */
+int helm_server_submit(helm_server* srv, const void* b, void* u, int64_t tag);
+
+/* Enqueues one Arnoldi step for every active slot on the server's stream
+ * and returns without waiting; *active (may be NULL) receives the number of
+ * slots stepped (0: nothing in flight). */
+int helm_server_launch(helm_server* srv, int32_t* active);
+
+/* Waits for the launched step, advances every slot's least-squares problem,
+ * finishes cycles and requests, admits queued requests into free slots, and
+ * writes up to `cap` completion events (host array) with their count in
+ * *count.  Events beyond cap are kept for the next call. */
+int helm_server_finish(helm_server* srv, helm_server_event* events, int32_t cap, int32_t* count);
+
+/* Queued and in-flight requests. */
+int helm_server_status(const helm_server* srv, int32_t* queued, int32_t* active);
+
+/* Frees the server (pending requests are dropped); NULL is accepted. */
+void helm_server_destroy(helm_server* srv);
 
 typedef struct helm_kernel_profile {
   int64_t launches;       /* timed launches since the last reset           */

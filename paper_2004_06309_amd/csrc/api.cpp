@@ -2,6 +2,7 @@
 // call converts internal exceptions into a status code and keeps the message
 // for helm_last_error.
 #include <cstring>
+#include <memory>
 #include <new>
 
 #include "ctx.hpp"
@@ -10,6 +11,13 @@ using namespace helm;
 
 struct helm_ctx {
   Ctx c;
+  int servers = 0;  // live servers on this context
+};
+
+struct helm_server {
+  helm_ctx* ctx;
+  std::unique_ptr<Server> srv;
+  std::vector<helm_server_event> pending;  // completions not yet reported
 };
 
 namespace {
@@ -88,6 +96,7 @@ const char* helm_last_error(const helm_ctx* ctx) {
 
 int helm_assemble(helm_ctx* ctx, const helm_mesh* mesh, const double* c_tet, double omega) {
   return guarded(ctx, [&](Ctx& c) {
+    need(ctx->servers == 0, HELM_ESTATE, "a server is using this context");
     need(mesh && c_tet, HELM_EINVAL, "mesh and c_tet are required");
     need(omega > 0, HELM_EINVAL, "omega must be positive");
     c.free_precond();
@@ -157,6 +166,7 @@ int helm_matrix_csr(const helm_ctx* ctx, int64_t* rowptr, int32_t* col, double* 
 int helm_precond_setup(helm_ctx* ctx, const int32_t* tet_part, int32_t n_sub, int32_t overlap,
                        const helm_mesh* coarse, const helm_precond_opts* opts) {
   return guarded(ctx, [&](Ctx& c) {
+    need(ctx->servers == 0, HELM_ESTATE, "a server is using this context");
     need(c.assembled, HELM_ESTATE, "call helm_assemble first");
     need(tet_part, HELM_EINVAL, "tet_part is required");
     try {
@@ -282,6 +292,7 @@ int helm_solve(helm_ctx* ctx, int32_t nrhs, const void* B, double tol, const hel
                void* stream, helm_solve_info* info) {
   return guarded(ctx, [&](Ctx& c) {
     need(c.device >= 0, HELM_ESTATE, "host-only context");
+    need(ctx->servers == 0, HELM_ESTATE, "a server is using this context");
     need(c.precond_ready, HELM_ESTATE, "call helm_precond_setup first");
     need(nrhs >= 0, HELM_EINVAL, "nrhs must be >= 0");
     need(nrhs == 0 || (B && U), HELM_EINVAL, "null vector");
@@ -305,6 +316,74 @@ int helm_profile_read(helm_ctx* ctx, helm_kernel_profile* out) {
     for (int k = 0; k < HELM_K_COUNT; ++k) out[k] = c.prof.acc[k];
     return HELM_OK;
   });
+}
+
+
+int helm_server_create(helm_ctx* ctx, const helm_server_opts* opts, void* stream, helm_server** out) {
+  if (!out) return HELM_EINVAL;
+  *out = nullptr;
+  return guarded(ctx, [&](Ctx& c) {
+    need(c.device >= 0, HELM_ESTATE, "host-only context");
+    need(c.precond_ready, HELM_ESTATE, "call helm_precond_setup first");
+    need(ctx->servers == 0, HELM_ESTATE, "a server already uses this context");
+    need(!opts || (opts->slots >= 0 && opts->slots <= 16), HELM_EINVAL, "slots must be 0..16");
+    need(!opts || opts->tol >= 0, HELM_EINVAL, "tol must be >= 0");
+    std::unique_ptr<helm_server> h(new helm_server);
+    h->ctx = ctx;
+    h->srv.reset(new Server(c, opts, (hipStream_t)stream));
+    ctx->servers++;
+    *out = h.release();
+    return HELM_OK;
+  });
+}
+
+int helm_server_submit(helm_server* srv, const void* b, void* u, int64_t tag) {
+  if (!srv) return HELM_EINVAL;
+  return guarded(srv->ctx, [&](Ctx&) {
+    need(b && u, HELM_EINVAL, "null vector");
+    srv->srv->submit((const double*)b, (double*)u, tag);
+    return HELM_OK;
+  });
+}
+
+int helm_server_launch(helm_server* srv, int32_t* active) {
+  if (!srv) return HELM_EINVAL;
+  return guarded(srv->ctx, [&](Ctx&) {
+    need(!srv->srv->inflight, HELM_ESTATE, "a step is already launched");
+    const int a = srv->srv->launch();
+    if (active) *active = a;
+    return HELM_OK;
+  });
+}
+
+int helm_server_finish(helm_server* srv, helm_server_event* events, int32_t cap, int32_t* count) {
+  if (!srv) return HELM_EINVAL;
+  return guarded(srv->ctx, [&](Ctx&) {
+    need(cap >= 0 && (cap == 0 || events), HELM_EINVAL, "bad event buffer");
+    srv->srv->finish(srv->pending);
+    const int32_t k = std::min<int32_t>(cap, (int32_t)srv->pending.size());
+    for (int32_t i = 0; i < k; ++i) events[i] = srv->pending[i];
+    srv->pending.erase(srv->pending.begin(), srv->pending.begin() + k);
+    if (count) *count = k;
+    return HELM_OK;
+  });
+}
+
+int helm_server_status(const helm_server* srv, int32_t* queued, int32_t* active) {
+  if (!srv) return HELM_EINVAL;
+  if (queued) *queued = (int32_t)srv->srv->queue.size();
+  if (active) *active = srv->srv->active();
+  return HELM_OK;
+}
+
+void helm_server_destroy(helm_server* srv) {
+  if (!srv) return;
+  if (srv->ctx) {
+    if (srv->ctx->c.device >= 0) (void)hipSetDevice(srv->ctx->c.device);
+    if (srv->srv && srv->srv->inflight) (void)hipEventSynchronize(srv->srv->done_ev);
+    srv->ctx->servers--;
+  }
+  delete srv;
 }
 
 }  // extern "C"

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include <chrono>
+#include <deque>
 #include <string>
 #include <vector>
 
@@ -223,5 +225,47 @@ void apply_coarse(Ctx& c, const double* r, double* q, hipStream_t s);
 void apply_precond(Ctx& c, const double* r, double* z, hipStream_t s);
 int solve(Ctx& c, int32_t nrhs, const double* B, double tol, const helm_solve_opts* opts, double* U, hipStream_t s,
           helm_solve_info* info);
+
+// Continuous-batching server over one context (solver.cpp).
+struct Server {
+  struct Request {
+    const double* b;
+    double* u;
+    int64_t tag;
+    std::chrono::steady_clock::time_point t0;
+  };
+  struct Slot {
+    bool busy = false, conv = false;
+    const double* b = nullptr;
+    double* u = nullptr;
+    int64_t tag = 0;
+    std::chrono::steady_clock::time_point t0;
+    double bnorm = 0, rel = 0;
+    int its = 0, jj = 0;
+    std::vector<cplx> H, g, sn, y;
+    std::vector<double> cs;
+  };
+  Ctx& c;
+  hipStream_t s;
+  int m = 50, maxit = 1000, slots_n = 0;
+  double tol = 1e-6;
+  std::deque<Request> queue;
+  std::vector<Slot> slot;
+  std::vector<int> act;
+  hipEvent_t done_ev = nullptr;
+  bool inflight = false;
+  Server(Ctx& ctx, const helm_server_opts* o, hipStream_t st);
+  ~Server();
+  void submit(const double* b, double* u, int64_t tag);
+  int launch();
+  void finish(std::vector<helm_server_event>& out);
+  void admit(std::vector<helm_server_event>& out);
+  bool start_cycle(int q, std::vector<helm_server_event>& out);
+  int active() const {
+    int a = 0;
+    for (auto& z : slot) a += z.busy;
+    return a;
+  }
+};
 
 }  // namespace helm

@@ -1383,4 +1383,245 @@ int solve(Ctx& c, int32_t nrhs, const double* B, double tol, const helm_solve_op
   return status;
 }
 
+// ---- continuous-batching server -------------------------------------------
+//
+// Requests (one right-hand side each) wait in a FIFO queue and are admitted
+// into free slots of a pseudo-block GMRES whenever a slot frees up, not only
+// between batches: every slot runs its own restart cycles (its own Krylov
+// dimension, Hessenberg matrix, rotations and stopping test), and each
+// Arnoldi step applies M^{-1} and A to all active slots in one pass over the
+// panels and over A.  Gram-Schmidt runs once per group of slots at the same
+// Krylov dimension.  A step is split into launch (kernels and the Hessenberg
+// copy enqueued on the server's stream) and finish (wait, least squares,
+// cycle ends, completions, admissions), so several servers on different
+// streams overlap on the device.
+
+Server::Server(Ctx& ctx, const helm_server_opts* o, hipStream_t st) : c(ctx), s(st) {
+  m = o && o->restart > 0 ? o->restart : 50;
+  maxit = o && o->maxit > 0 ? o->maxit : 1000;
+  tol = o && o->tol > 0 ? o->tol : 1e-6;
+  if (m > 50) fail(HELM_EINVAL, "restart must be <= 50");
+  const int64_t n = c.D.n;
+  int want = o && o->slots > 0 ? o->slots : dev::kMaxBlock;
+  if (want > dev::kMaxBlock) fail(HELM_EINVAL, "at most 16 slots");
+  // admission by memory: each slot holds V (m + 1 columns), Z_m (m columns)
+  // and a work vector; keep a quarter of the free memory in reserve
+  size_t free_b = 0, total_b = 0;
+  HELM_HIP(hipMemGetInfo(&free_b, &total_b));
+  const double per_slot = 16.0 * (double)n * (2 * m + 2);
+  const int fit = (int)std::min<double>(dev::kMaxBlock, 0.75 * (double)free_b / per_slot);
+  if (fit < 1) fail(HELM_ENOMEM, "no device memory for a server slot");
+  slots_n = std::min(want, fit);
+  ensure_gmres(c, m);
+  ensure_block(c, m, dev::kMaxBlock);
+  slot.resize(slots_n);
+  for (auto& q : slot) {
+    q.H.assign((size_t)(m + 1) * m, 0);
+    q.g.assign(m + 1, 0);
+    q.sn.assign(m, 0);
+    q.cs.assign(m, 0);
+    q.y.assign(m, 0);
+  }
+  HELM_HIP(hipEventCreateWithFlags(&done_ev, hipEventDisableTiming));
+}
+
+Server::~Server() { (void)hipEventDestroy(done_ev); }
+
+void Server::submit(const double* b, double* u, int64_t tag) {
+  queue.push_back({b, u, tag, std::chrono::steady_clock::now()});
+}
+
+// Starts (or restarts) a cycle of slot q from its current iterate: r = b - A x.
+// Returns false when the request is finished (converged, maxit, or error).
+bool Server::start_cycle(int q, std::vector<helm_server_event>& out) {
+  Slot& z = slot[q];
+  const int64_t n = c.D.n;
+  double* v0 = c.bV[q].p;
+  spmv_A(c, z.u, z.b, v0, s);
+  const double beta = device_norm(c, v0, s);
+  z.rel = beta / z.bnorm;
+  int status = HELM_OK;
+  if (!std::isfinite(beta)) status = HELM_ENUMERIC;
+  else if (beta <= tol * z.bnorm) z.conv = true;
+  if (status != HELM_OK || z.conv || z.its >= maxit) {
+    helm_server_event e{};
+    e.tag = z.tag;
+    e.iterations = z.its;
+    e.converged = z.conv ? 1 : 0;
+    e.status = status != HELM_OK ? status : (z.conv ? HELM_OK : HELM_ENOCONV);
+    e.relres = z.rel;
+    e.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - z.t0).count();
+    out.push_back(e);
+    z.busy = false;
+    return false;
+  }
+  dev::scale(n, v0, 1.0 / beta, v0, s);
+  std::fill(z.g.begin(), z.g.end(), cplx(0, 0));
+  z.g[0] = beta;
+  z.jj = 0;
+  return true;
+}
+
+void Server::admit(std::vector<helm_server_event>& out) {
+  const int64_t n = c.D.n;
+  for (int q = 0; q < slots_n && !queue.empty(); ++q) {
+    if (slot[q].busy) continue;
+    Request r = queue.front();
+    queue.pop_front();
+    Slot& z = slot[q];
+    z.b = r.b;
+    z.u = r.u;
+    z.tag = r.tag;
+    z.t0 = r.t0;
+    z.its = 0;
+    z.conv = false;
+    z.busy = true;
+    dev::fill_zero(2 * n, z.u, s);
+    z.bnorm = device_norm(c, z.b, s);
+    if (!std::isfinite(z.bnorm) || z.bnorm == 0) {
+      helm_server_event e{};
+      e.tag = z.tag;
+      e.converged = z.bnorm == 0 ? 1 : 0;
+      e.status = z.bnorm == 0 ? HELM_OK : HELM_ENUMERIC;
+      e.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - z.t0).count();
+      out.push_back(e);
+      z.busy = false;
+      --q;  // the slot is free again
+      continue;
+    }
+    start_cycle(q, out);
+  }
+}
+
+int Server::launch() {
+  const int64_t n = c.D.n;
+  const size_t n2 = 2 * (size_t)n;
+  act.clear();
+  for (int q = 0; q < slots_n; ++q)
+    if (slot[q].busy) act.push_back(q);
+  if (act.empty()) return 0;
+  // block width: slot q is column q, so the smallest power of two above the
+  // highest busy slot (free slots in between are zero columns)
+  int S = 2;
+  while (S < act.back() + 1) S *= 2;
+  dev::PtrSetC src{};
+  dev::PtrSet dz{}, dw{};
+  for (int q : act) {
+    src.p[q] = c.bV[q].p + n2 * slot[q].jj;
+    dz.p[q] = c.bZ[q].p + n2 * slot[q].jj;
+    dw.p[q] = c.bw[q].p;
+  }
+  // slots map to their own columns of the block (inactive ones are zero)
+  dev::pack(n, S, src, c.bX.p, s);
+  apply_precond_block(c, S, c.bX.p, c.bZb.p, s);
+  dev::unpack(n, S, c.bZb.p, dz, s);
+  spmv_block(c, S, c.bZb.p, nullptr, c.bW.p, s);
+  dev::unpack(n, S, c.bW.p, dw, s);
+  // CGS2, one call per group of slots at the same Krylov dimension
+  const int nt = dev::gs_tiles(n);
+  std::vector<int> done(act.size(), 0);
+  for (size_t a = 0; a < act.size(); ++a) {
+    if (done[a]) continue;
+    const int jj = slot[act[a]].jj;
+    dev::PtrSetC Vs{}, hs{}, ps{}, wc{}, nc{};
+    dev::PtrSet ws{}, hts{}, hcs{}, pw{}, nrm{}, vn{};
+    int na = 0;
+    for (size_t b2 = a; b2 < act.size(); ++b2) {
+      const int q = act[b2];
+      if (done[b2] || slot[q].jj != jj) continue;
+      done[b2] = 1;
+      Vs.p[na] = c.bV[q].p;
+      hs.p[na] = c.bhtmp.p + 2 * (size_t)q * (m + 2);
+      hts.p[na] = c.bhtmp.p + 2 * (size_t)q * (m + 2);
+      hcs.p[na] = c.bhcol.p + 2 * (size_t)q * (m + 2);
+      ps.p[na] = c.bpartial.p + 2 * (size_t)q * nt * (m + 2);
+      pw.p[na] = c.bpartial.p + 2 * (size_t)q * nt * (m + 2);
+      ws.p[na] = c.bw[q].p;
+      wc.p[na] = c.bw[q].p;
+      nrm.p[na] = hcs.p[na] + 2 * (jj + 1);
+      nc.p[na] = nrm.p[na];
+      vn.p[na] = c.bV[q].p + n2 * (jj + 1);
+      ++na;
+    }
+    dev::gs_pass(0, na, n, Vs, n, jj + 1, hs, ws, pw, s);
+    dev::gs_final(na, ps, nt, jj + 1, hts, hcs, 0, s);
+    dev::gs_pass(1, na, n, Vs, n, jj + 1, hs, ws, pw, s);
+    dev::gs_final(na, ps, nt, jj + 1, hts, hcs, 1, s);
+    dev::gs_pass(2, na, n, Vs, n, jj + 1, hs, ws, pw, s);
+    dev::norm_final(na, ps, nt, nrm, s);
+    dev::scale_by_inv_set(na, n, wc, nc, vn, s);
+  }
+  HELM_HIP(hipMemcpyAsync(c.bh_host, c.bhcol.p, 2 * sizeof(double) * slots_n * (m + 2), hipMemcpyDeviceToHost, s));
+  HELM_HIP(hipEventRecord(done_ev, s));
+  inflight = true;
+  return (int)act.size();
+}
+
+void Server::finish(std::vector<helm_server_event>& out) {
+  const int64_t n = c.D.n;
+  if (inflight) {
+    HELM_HIP(hipEventSynchronize(done_ev));
+    inflight = false;
+    for (int q : act) {
+      Slot& z = slot[q];
+      const int jj = z.jj;
+      const double* hh = c.bh_host + 2 * (size_t)q * (m + 2);
+      cplx* h = z.H.data() + (size_t)(m + 1) * jj;
+      bool bad = false;
+      for (int i = 0; i <= jj + 1; ++i) {
+        h[i] = cplx(hh[2 * i], hh[2 * i + 1]);
+        if (!std::isfinite(h[i].real()) || !std::isfinite(h[i].imag())) bad = true;
+      }
+      ++z.its;
+      if (bad) {
+        helm_server_event e{};
+        e.tag = z.tag;
+        e.iterations = z.its;
+        e.status = HELM_ENUMERIC;
+        e.relres = z.rel;
+        e.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - z.t0).count();
+        out.push_back(e);
+        z.busy = false;
+        continue;
+      }
+      const double hn = h[jj + 1].real();
+      for (int i = 0; i < jj; ++i) {
+        const cplx a = h[i], bb = h[i + 1];
+        h[i] = z.cs[i] * a + z.sn[i] * bb;
+        h[i + 1] = -std::conj(z.sn[i]) * a + z.cs[i] * bb;
+      }
+      const cplx a = h[jj], bb = h[jj + 1];
+      if (a == cplx(0, 0)) {
+        z.cs[jj] = 0;
+        z.sn[jj] = 1;
+      } else {
+        const double rr = std::sqrt(std::norm(a) + std::norm(bb));
+        z.cs[jj] = std::abs(a) / rr;
+        z.sn[jj] = (a / std::abs(a)) * std::conj(bb) / rr;
+      }
+      h[jj] = z.cs[jj] * a + z.sn[jj] * bb;
+      h[jj + 1] = 0;
+      z.g[jj + 1] = -std::conj(z.sn[jj]) * z.g[jj];
+      z.g[jj] = z.cs[jj] * z.g[jj];
+      const bool end = std::abs(z.g[jj + 1]) <= tol * z.bnorm || z.its >= maxit || hn == 0 || jj + 1 == m;
+      if (!end) {
+        z.jj = jj + 1;
+        continue;
+      }
+      // cycle end: x += Z_k y, then the true residual decides
+      const int k = jj + 1;
+      for (int i = k - 1; i >= 0; --i) {
+        cplx acc = z.g[i];
+        for (int l = i + 1; l < k; ++l) acc -= z.H[(size_t)(m + 1) * l + i] * z.y[l];
+        z.y[i] = acc / z.H[(size_t)(m + 1) * i + i];
+      }
+      HELM_HIP(hipMemcpyAsync(c.by.p, z.y.data(), sizeof(cplx) * k, hipMemcpyHostToDevice, s));
+      dev::gemv_acc(n, c.bZ[q].p, n, k, c.by.p, z.u, s);
+      HELM_HIP(hipStreamSynchronize(s));
+      start_cycle(q, out);
+    }
+  }
+  admit(out);
+}
+
 }  // namespace helm

@@ -64,6 +64,16 @@ class PrecondStats(C.Structure):
                 ("factor_seconds", C.c_double)]
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("restart", C.c_int32), ("maxit", C.c_int32), ("reserved", C.c_int32),
+                ("tol", C.c_double)]
+
+
+class ServerEvent(C.Structure):
+    _fields_ = [("tag", C.c_int64), ("iterations", C.c_int32), ("converged", C.c_int32), ("status", C.c_int32),
+                ("reserved", C.c_int32), ("relres", C.c_double), ("seconds", C.c_double)]
+
+
 class KernelProfile(C.Structure):
     _fields_ = [("launches", C.c_int64), ("milliseconds", C.c_double), ("bytes", C.c_double)]
 
@@ -95,6 +105,12 @@ EXPORTS = {
     "helm_apply_coarse": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "helm_solve": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.POINTER(SolveOpts), C.c_void_p,
                              C.c_void_p, C.POINTER(SolveInfo)]),
+    "helm_server_create": (C.c_int, [C.c_void_p, C.POINTER(ServerOpts), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "helm_server_submit": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
+    "helm_server_launch": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "helm_server_finish": (C.c_int, [C.c_void_p, C.POINTER(ServerEvent), C.c_int32, C.POINTER(C.c_int32)]),
+    "helm_server_status": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "helm_server_destroy": (None, [C.c_void_p]),
     "helm_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "helm_profile_read": (C.c_int, [C.c_void_p, C.POINTER(KernelProfile)]),
 }
@@ -282,6 +298,61 @@ class Helm:
         self._check(self.lib.helm_profile_read(self.h, out))
         return {k: {"launches": out[i].launches, "ms": out[i].milliseconds, "bytes": out[i].bytes}
                 for i, k in enumerate(KERNELS)}
+
+
+class Server:
+    """Continuous-batching server over a Helm context (helm_server_*):
+    submit(b, u, tag) queues a request; launch() enqueues one Arnoldi step
+    for every slot in flight; finish() waits for it and returns the
+    completion events as dicts.  Keeps the submitted tensors alive until
+    their completion."""
+
+    def __init__(self, helm, slots=0, restart=50, maxit=1000, tol=1e-6, stream=None):
+        self.helm = helm
+        self.lib = helm.lib
+        opts = ServerOpts(int(slots), int(restart), int(maxit), 0, float(tol))
+        out = C.c_void_p()
+        helm._check(self.lib.helm_server_create(helm.h, C.byref(opts), _stream(stream), C.byref(out)))
+        self.h = out
+        self._alive = {}
+        self._ev = (ServerEvent * 64)()
+
+    def submit(self, b, u, tag):
+        self.helm._check(self.lib.helm_server_submit(self.h, _dev_ptr(b), _dev_ptr(u), int(tag)))
+        self._alive[int(tag)] = (b, u)
+
+    def launch(self):
+        a = C.c_int32()
+        self.helm._check(self.lib.helm_server_launch(self.h, C.byref(a)))
+        return a.value
+
+    def finish(self):
+        out = []
+        while True:
+            k = C.c_int32()
+            self.helm._check(self.lib.helm_server_finish(self.h, self._ev, len(self._ev), C.byref(k)))
+            for i in range(k.value):
+                e = self._ev[i]
+                out.append({f: getattr(e, f) for f, _ in ServerEvent._fields_ if f != "reserved"})
+                self._alive.pop(e.tag, None)
+            if k.value < len(self._ev):
+                return out
+
+    def status(self):
+        q, a = C.c_int32(), C.c_int32()
+        self.lib.helm_server_status(self.h, C.byref(q), C.byref(a))
+        return q.value, a.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.helm_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def from_workload(w, device=0, leaf_size=0, c64=False, **opts):

@@ -324,3 +324,97 @@ def test_mid_full_size():
     u = host(U)
     assert rc == helm.HELM_OK
     assert np.linalg.norm(b - P.A @ u) / np.linalg.norm(b) <= w.tol
+
+
+def _serve(servers, plan):
+    """Drives servers: plan[i] = list of (step, b, u, tag) submissions for
+    server i, submitted when the step counter reaches `step` (requests
+    arrive while others are in flight).  Returns {tag: event}."""
+    events, step = {}, 0
+    total = sum(len(p) for p in plan)
+    while len(events) < total:
+        for srv, p in zip(servers, plan):
+            for (st, b, u, tag) in p:
+                if st == step:
+                    srv.submit(b, u, tag)
+        for srv in servers:  # all servers' steps in flight together
+            srv.launch()
+        for srv in servers:
+            for e in srv.finish():
+                events[e["tag"]] = e
+        step += 1
+        assert step < 5000
+    return events
+
+
+def test_server_continuous_batching():
+    """Requests arriving while others are in flight are admitted into free
+    slots (4 slots, 10 requests); every result equals its solo solve within
+    the solve tolerance (true residual <= tol with the oracle's A, oracle
+    iteration count within +-2, solution within 1e-5)."""
+    w = WORKLOADS["mid_quarter_2lvl"]()
+    P, b0, M = opre.build(w)
+    h = helm.from_workload(w)
+    lo, hi = w.xyz.min(axis=0), w.xyz.max(axis=0)
+    pts = lo + (hi - lo) * np.random.default_rng(17).uniform(0.1, 0.9, (10, 3))
+    Bs = np.stack([P.point_source(p) for p in pts])
+    B = dvec(Bs)
+    solo = torch.zeros_like(B)
+    solo_its = []
+    for r in range(10):
+        rc, info = h.solve(B[r].contiguous(), solo[r], tol=w.tol, restart=w.restart)
+        solo_its.append(info[0]["iterations"])
+    U = torch.zeros_like(B)
+    srv = helm.Server(h, slots=4, restart=w.restart, tol=w.tol)
+    with pytest.raises(helm.HelmError):  # the context is in use by the server
+        h.solve(B[0].contiguous(), solo[0], tol=w.tol)
+    plan = [[(3 * r, B[r], U[r], 100 + r) for r in range(10)]]
+    ev = _serve([srv], plan)
+    srv.close()
+    u, us = host(U), host(solo)
+    for r in range(10):
+        e = ev[100 + r]
+        assert e["converged"] == 1 and e["status"] == helm.HELM_OK
+        assert np.linalg.norm(Bs[r] - P.A @ u[r]) / np.linalg.norm(Bs[r]) <= w.tol
+        assert abs(e["iterations"] - solo_its[r]) <= 2
+        assert np.linalg.norm(u[r] - us[r]) <= 1e-5 * np.linalg.norm(us[r])
+    say(f"[serve] its={[ev[100 + r]['iterations'] for r in range(10)]} solo={solo_its}")
+    # the context is usable again once the server is gone
+    rc, info = h.solve(B[0].contiguous(), solo[0], tol=w.tol)
+    assert rc == helm.HELM_OK
+
+
+def test_servers_on_two_operators_overlap():
+    """Two operators, each with a server on its own stream, stepped together;
+    zero and regular right-hand sides; results match the oracle's solves."""
+    cases = [WORKLOADS["tiny"](), WORKLOADS["small_p2_2lvl"]()]
+    servers, plan, refs = [], [], []
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    keep = []
+    for i, (w, st) in enumerate(zip(cases, streams)):
+        P, b, M = opre.build(w)
+        h = helm.from_workload(w)
+        rng = np.random.default_rng(40 + i)
+        Bs = np.stack([b, np.zeros_like(b), rng.standard_normal(P.n) + 1j * rng.standard_normal(P.n)])
+        B = dvec(Bs)
+        U = torch.zeros_like(B)
+        servers.append(helm.Server(h, slots=2, restart=w.restart, tol=w.tol, stream=st))
+        plan.append([(2 * r, B[r], U[r], 10 * i + r) for r in range(3)])
+        refs.append((P, M, Bs, U, w))
+        keep.append(h)
+    ev = _serve(servers, plan)
+    torch.cuda.synchronize()
+    for s_ in servers:
+        s_.close()
+    for i, (P, M, Bs, U, w) in enumerate(refs):
+        u = host(U)
+        for r in range(3):
+            e = ev[10 * i + r]
+            assert e["status"] == helm.HELM_OK and e["converged"] == 1
+            if r == 1:
+                assert e["iterations"] == 0 and np.abs(u[r]).max() == 0
+                continue
+            ro = opre.solve(P, Bs[r], M, tol=w.tol, restart=w.restart)
+            assert np.linalg.norm(Bs[r] - P.A @ u[r]) / np.linalg.norm(Bs[r]) <= w.tol
+            assert abs(e["iterations"] - ro.iterations) <= 2
+            assert np.linalg.norm(u[r] - ro.x) <= 1e-5 * np.linalg.norm(ro.x)

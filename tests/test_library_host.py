@@ -175,3 +175,13 @@ def test_shorter_tiles_store_fewer_triangle_zeros():
     assert st[16]["coarse_entries"] <= st[64]["coarse_entries"]
     for k in ("n_local_total", "levels_fwd", "levels_bwd", "max_front", "n_supernodes"):
         assert st[16][k] == st[64][k]
+
+
+def test_server_needs_a_device_context():
+    h = helm.Helm(-1)
+    lib = helm.load()
+    out = __import__("ctypes").c_void_p()
+    assert lib.helm_server_create(h.h, None, None, __import__("ctypes").byref(out)) == helm.HELM_ESTATE
+    assert not out.value
+    lib.helm_server_destroy(None)  # NULL-safe
+    assert lib.helm_server_submit(None, None, None, 0) == helm.HELM_EINVAL
