@@ -217,3 +217,115 @@ def surface_sources(lx: float, ly: float, n_side: int, depth: float = 10.0) -> n
     ys = (np.arange(n_side) + 0.5) * ly / n_side
     X, Y = np.meshgrid(xs, ys, indexing="ij")
     return np.stack([X.ravel(), Y.ravel(), np.full(X.size, depth)], axis=1)
+
+
+# ---- h-adapted meshes (conforming bisection of a Kuhn mesh) ----------------
+
+def _kuhn_tagged(nx, ny, nz, lx, ly, lz):
+    """Kuhn mesh with every tet as its monotone lattice path (x0 .. x3, from
+    the cell's lower corner to its upper corner) and bisection tag 3 (its
+    refinement edge is the cell diagonal x0-x3)."""
+    xyz, _ = kuhn_mesh(nx, ny, nz, lx, ly, lz)
+    ci, cj, ck = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    ci, cj, ck = ci.ravel(order="F"), cj.ravel(order="F"), ck.ravel(order="F")
+
+    def nid(a, b, c):
+        return a + (nx + 1) * (b + (ny + 1) * c)
+
+    tets = [np.stack([nid(ci + p[0], cj + p[1], ck + p[2]) for p in path], axis=1) for path in _KUHN_PATHS]
+    tets = np.stack(tets, axis=1).reshape(-1, 4).astype(np.int64)
+    return xyz, tets, np.full(tets.shape[0], 3, dtype=np.int8)
+
+
+def _edge_keys(a, b, n_max):
+    lo, hi = np.minimum(a, b), np.maximum(a, b)
+    return lo * n_max + hi
+
+
+def bisect_to_size(xyz, tets, tags, target, max_passes=200):
+    """Refines a tagged simplicial mesh by newest-vertex bisection (the
+    tagged-simplex rule of Maubach: the refinement edge of (x0..x3; k) is
+    x0-xk; its children are (x0..x_{k-1}, z, x_{k+1}..x3) and
+    (x1..xk, z, x_{k+1}..x3) with tag k-1, or 3 after 1) until every
+    refinement edge is at most target(midpoint) long, bisecting further any
+    tet that holds a hanging vertex on one of its edges (closure), so the
+    result is conforming.  target: callable on an (m, 3) array of points."""
+    xyz = [np.asarray(xyz, dtype=np.float64)]
+    nv = xyz[0].shape[0]
+    tets = np.asarray(tets, dtype=np.int64).copy()
+    tags = np.asarray(tags, dtype=np.int8).copy()
+    mid_of = {}  # edge key -> midpoint vertex id
+    n_max = np.int64(1) << np.int64(31)
+    pairs = [(i, j) for i in range(4) for j in range(i + 1, 4)]
+    for _ in range(max_passes):
+        P = np.concatenate(xyz)
+        k = tags.astype(np.int64)
+        a, b = tets[:, 0], tets[np.arange(tets.shape[0]), k]
+        mid = 0.5 * (P[a] + P[b])
+        mark = np.linalg.norm(P[a] - P[b], axis=1) > target(mid)
+        if mid_of:
+            known = np.fromiter(mid_of.keys(), dtype=np.int64)
+            for (i, j) in pairs:
+                mark |= np.isin(_edge_keys(tets[:, i], tets[:, j], n_max), known)
+        if not mark.any():
+            break
+        idx = np.nonzero(mark)[0]
+        keys = _edge_keys(a[idx], b[idx], n_max)
+        uk, inv = np.unique(keys, return_inverse=True)
+        zid = np.empty(uk.size, dtype=np.int64)
+        for q, key in enumerate(uk.tolist()):
+            v = mid_of.get(key)
+            if v is None:
+                v = nv
+                nv += 1
+                mid_of[key] = v
+            zid[q] = v
+        # coordinates of the new midpoints (in creation order)
+        created = [(key, mid_of[key]) for key in uk.tolist() if mid_of[key] >= P.shape[0]]
+        if created:
+            created.sort(key=lambda t: t[1])
+            lo = np.array([c[0] // n_max for c in created], dtype=np.int64)
+            hi = np.array([c[0] % n_max for c in created], dtype=np.int64)
+            xyz.append(0.5 * (P[lo] + P[hi]))
+        z = zid[inv]
+        T = tets[idx]
+        kk = k[idx]
+        c1 = T.copy()
+        c1[np.arange(idx.size), kk] = z
+        # (x1..xk, z, x_{k+1}..x3), by tag
+        c2 = np.empty_like(T)
+        for kr in (1, 2, 3):
+            s_ = kk == kr
+            c2[s_] = np.concatenate([T[s_][:, 1:kr + 1], z[s_][:, None], T[s_][:, kr + 1:]], axis=1)
+        nt = np.where(kk > 1, kk - 1, 3).astype(np.int8)
+        keep = np.ones(tets.shape[0], dtype=bool)
+        keep[idx] = False
+        tets = np.concatenate([tets[keep], c1, c2])
+        tags = np.concatenate([tags[keep], nt, nt])
+    else:
+        raise RuntimeError("bisection did not finish")
+    P = np.concatenate(xyz)
+    return P, orient_positive(P, tets), tags
+
+
+def adapted_box(lx=8000.0, ly=8000.0, lz=2000.0, n0=(4, 4, 1), freq=2.0, per_wavelength=4.0, coarse_factor=2.0,
+                n_parts=(4, 4, 1), overlap=2, order=2, n_layers=12, seed=0, source=None):
+    """Thrust model meshed to the local wavelength: a Kuhn mesh of n0 cells
+    bisected until every edge is at most c(x) / (per_wavelength f) long
+    (edges in slow layers get short, fast ones long), P2, box subdomains of
+    uneven size, two-level ORAS on the same bisection at coarse_factor x the
+    edge length (not nested in general: the coarse basis is located by
+    point search)."""
+    model = ThrustModel.draw(lx, ly, lz, n_layers, seed)
+
+    def target(scale):
+        return lambda p: scale * model.velocity(p) / (per_wavelength * freq)
+
+    x0, t0, g0 = _kuhn_tagged(*n0, lx, ly, lz)
+    xyz, tets, _ = bisect_to_size(x0, t0, g0, target(1.0))
+    cx, ct, _ = bisect_to_size(x0, t0, g0, target(coarse_factor))
+    c = model.velocity(tet_centroids(xyz, tets)).astype(np.complex128)
+    part = box_partition(xyz, tets, n_parts)
+    src = np.array([lx / 2, ly / 2, 10.0]) if source is None else np.asarray(source, dtype=np.float64)
+    return Workload("adapted", xyz, tets, order, c, 2 * np.pi * freq, part, int(np.prod(n_parts)), overlap,
+                    cx, ct, src, None)

@@ -35,6 +35,9 @@ WORKLOADS = {
     "small_p2_2lvl": lambda: wl.small_box(n=(6, 6, 4), order=2, n_parts=(2, 2, 1), overlap=2),
     "ragged_p2": lambda: wl.small_box(n=(5, 3, 4), order=2, n_parts=(3, 2, 1), overlap=1, coarse=False),
     "mid_quarter_2lvl": lambda: wl.mid(scale=4, n_parts=(4, 4, 1)),
+    # h-adapted (bisection to lambda/4), uneven subdomains, non-nested coarse mesh
+    "adapted_p2_2lvl": lambda: wl.adapted_box(lx=2000.0, ly=2000.0, lz=1000.0, n0=(2, 2, 1), freq=4.0,
+                                              n_parts=(2, 2, 1)),
 }
 
 

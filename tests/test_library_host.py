@@ -37,6 +37,7 @@ CASES = {
     "tiny_p1": lambda: wl.tiny(),
     "small_p2": lambda: wl.small_box(n=(6, 6, 4), order=2, n_parts=(2, 2, 1), overlap=2),
     "small_p2_ragged": lambda: wl.small_box(n=(5, 3, 4), order=2, n_parts=(3, 2, 1), overlap=1, coarse=False),
+    "adapted_p2": lambda: wl.adapted_box(lx=2000.0, ly=2000.0, lz=1000.0, n0=(2, 2, 1), freq=3.0, n_parts=(2, 2, 1)),
 }
 
 
