@@ -466,22 +466,32 @@ __global__ __launch_bounds__(kWG) void gs_pass_kernel(int64_t n, PtrSetC Vs, int
   double dr = 0, di = 0;  // dots: column `lane`, rows [16 wv, 16 wv + 16) of every tile
   double nrm = 0;         // norm: row `tid` of every tile
   const int64_t ntiles = (n + kGsRows - 1) / kGsRows;
+  // Software pipeline: wave q holds columns q, q + 4, ... of the next tile
+  // (and wave 0 the next tile's w) in registers; they are loaded right after
+  // the current tile is staged, so the loads overlap its arithmetic.
+  constexpr int kU = kGsMaxCols / 4;
+  double2 a[kU];
+  double2 wnext = make_double2(0.0, 0.0);
+  auto load_next = [&](int64_t tb) {
+    const int64_t i = tb * kGsRows + lane;
+    const bool valid = tb < ntiles && i < n;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int k = wv + 4 * u;
+      a[u] = (k < ncol && valid) ? V[(int64_t)k * ld + i] : make_double2(0.0, 0.0);
+    }
+    if (tid < kGsRows) wnext = valid ? w[i] : make_double2(0.0, 0.0);
+  };
+  load_next(blockIdx.x);
   for (int64_t tb = blockIdx.x; tb < ntiles; tb += gridDim.x) {
     const int64_t i = tb * kGsRows + lane;
     const bool valid = i < n;
-    // stage the tile: wave q loads columns q, q+4, ..., four loads in flight
-    for (int kb = wv; kb < ncol; kb += 16) {
-      double2 a[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int k = kb + 4 * u;
-        a[u] = (k < ncol && valid) ? V[(int64_t)k * ld + i] : make_double2(0.0, 0.0);
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (kb + 4 * u < ncol) tile[kb + 4 * u][lane] = a[u];
-    }
+    for (int u = 0; u < kU; ++u)
+      if (wv + 4 * u < ncol) tile[wv + 4 * u][lane] = a[u];
+    const double2 wcur = wnext;
     __syncthreads();
+    load_next(tb + gridDim.x);
     if (kUpdate) {
       // wave q sums the columns k = q mod 4 of row `lane`
       double ur = 0, ui = 0;
@@ -490,7 +500,7 @@ __global__ __launch_bounds__(kWG) void gs_pass_kernel(int64_t n, PtrSetC Vs, int
       __syncthreads();
     }
     if (tid < kGsRows) {
-      double2 wi = valid ? w[i] : make_double2(0.0, 0.0);
+      double2 wi = wcur;
       if (kUpdate) {
         for (int q = 0; q < 4; ++q) {
           wi.x -= ured[q * kGsRows + tid].x;
