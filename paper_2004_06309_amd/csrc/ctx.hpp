@@ -194,7 +194,8 @@ struct Ctx {
   DVec<double> t, q, cvec;
   // GMRES work
   int gm_m = 0;
-  DVec<double> V, Zk, w, partial, hcol, htmp, nrm, ydev;
+  DVec<double> V, Zk, w, partial, hcol, htmp, nrm, ydev, coef_w, coef_v;
+  hipEvent_t hev = nullptr;   // marks the Hessenberg column copy of a step
   double* h_host = nullptr;  // pinned
   Profiler prof;
   // pseudo-block GMRES work (per right-hand side of a block)

@@ -546,6 +546,180 @@ __global__ __launch_bounds__(kWG) void gs_pass_kernel(int64_t n, PtrSetC Vs, int
   }
 }
 
+// Delayed CGS2 (two passes over V per Arnoldi step instead of three): the
+// last column v_j of V (ncol = j + 1 columns) was orthogonalised once when it
+// was made; its second pass is folded into the next step.
+//   pass A (kUpdate = false): partial dots V^H w (ncol entries) and V^H v_j
+//     (ncol more, the last being |v_j|^2) of every 64-row tile;
+//   pass B (kUpdate = true): v_j <- (v_j - V_{<j} cv) * cv[j].x and
+//     w <- w - V_{<j} cw - v_j(old) cw[j], written back, plus the partial
+//     squared norms of the new w (partial[blk].x).
+template <bool kUpdate>
+__global__ __launch_bounds__(kWG) void gs_dual_kernel(int64_t n, PtrSetC Vs, PtrSet Vw, int64_t ld, int ncol,
+                                                      PtrSetC cws, PtrSetC cvs, PtrSet ws, PtrSet parts) {
+  const double2* __restrict__ V = reinterpret_cast<const double2*>(Vs.p[blockIdx.y]);
+  double2* __restrict__ w = reinterpret_cast<double2*>(ws.p[blockIdx.y]);
+  double2* __restrict__ partial = reinterpret_cast<double2*>(parts.p[blockIdx.y]);
+  extern __shared__ double2 lds[];
+  double2 (*tile)[kGsRows + 1] = reinterpret_cast<double2 (*)[kGsRows + 1]>(lds);
+  double2* cw = lds + (size_t)ncol * (kGsRows + 1);
+  double2* cv = cw + kGsMaxCols;
+  double2* wn = cv + kGsMaxCols;
+  // the update sums (pass B) and the dot sums (pass A) share their space
+  double2* ured = wn + kGsRows;          // [4][kGsRows]
+  double2* vred = ured + 4 * kGsRows;    // [4][kGsRows]
+  double2* dred = wn + kGsRows;          // [4][kGsMaxCols]
+  double2* ered = dred + 4 * kGsMaxCols; // [4][kGsMaxCols]
+  double* red = reinterpret_cast<double*>(wn + kGsRows + 8 * kGsMaxCols);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, j = ncol - 1;
+  if (kUpdate && tid < ncol) {
+    cw[tid] = reinterpret_cast<const double2*>(cws.p[blockIdx.y])[tid];
+    cv[tid] = reinterpret_cast<const double2*>(cvs.p[blockIdx.y])[tid];
+  }
+  double dr = 0, di = 0, er = 0, ei = 0;  // dots of column `lane` with w and with v_j
+  double nrm = 0;
+  const int64_t ntiles = (n + kGsRows - 1) / kGsRows;
+  constexpr int kU = kGsMaxCols / 4;
+  double2 a[kU];
+  double2 wnext = make_double2(0.0, 0.0);
+  auto load_next = [&](int64_t tb) {
+    const int64_t i = tb * kGsRows + lane;
+    const bool valid = tb < ntiles && i < n;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int k = wv + 4 * u;
+      a[u] = (k < ncol && valid) ? V[(int64_t)k * ld + i] : make_double2(0.0, 0.0);
+    }
+    if (tid < kGsRows) wnext = valid ? w[i] : make_double2(0.0, 0.0);
+  };
+  load_next(blockIdx.x);
+  for (int64_t tb = blockIdx.x; tb < ntiles; tb += gridDim.x) {
+    const int64_t i = tb * kGsRows + lane;
+    const bool valid = i < n;
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (wv + 4 * u < ncol) tile[wv + 4 * u][lane] = a[u];
+    const double2 wcur = wnext;
+    __syncthreads();
+    load_next(tb + gridDim.x);
+    if (kUpdate) {
+      double ur = 0, ui = 0, vr = 0, vi = 0;
+      for (int k = wv; k < j; k += 4) {
+        cfma(ur, ui, tile[k][lane], cw[k]);
+        cfma(vr, vi, tile[k][lane], cv[k]);
+      }
+      ured[wv * kGsRows + lane] = make_double2(ur, ui);
+      vred[wv * kGsRows + lane] = make_double2(vr, vi);
+      __syncthreads();
+      if (tid < kGsRows) {
+        double2 wi = wcur;
+        const double2 vo = tile[j][tid];
+        double2 vn = vo;
+        for (int q = 0; q < 4; ++q) {
+          wi.x -= ured[q * kGsRows + tid].x;
+          wi.y -= ured[q * kGsRows + tid].y;
+          vn.x -= vred[q * kGsRows + tid].x;
+          vn.y -= vred[q * kGsRows + tid].y;
+        }
+        const double ia = cv[j].x, dxr = cw[j].x, dxi = cw[j].y;
+        wi.x -= vo.x * dxr - vo.y * dxi;
+        wi.y -= vo.x * dxi + vo.y * dxr;
+        if (valid) {
+          w[i] = wi;
+          reinterpret_cast<double2*>(Vw.p[blockIdx.y])[(int64_t)j * ld + i] = make_double2(vn.x * ia, vn.y * ia);
+        }
+        nrm = fma(wi.x, wi.x, fma(wi.y, wi.y, nrm));
+      }
+    } else {
+      if (tid < kGsRows) wn[tid] = wcur;
+      __syncthreads();
+      if (lane < ncol) {
+        for (int r = wv * 16; r < wv * 16 + 16; ++r) {
+          const double2 v = tile[lane][r], x = wn[r], y = tile[j][r];
+          dr = fma(v.x, x.x, dr);
+          dr = fma(v.y, x.y, dr);
+          di = fma(v.x, x.y, di);
+          di = fma(-v.y, x.x, di);
+          er = fma(v.x, y.x, er);
+          er = fma(v.y, y.y, er);
+          ei = fma(v.x, y.y, ei);
+          ei = fma(-v.y, y.x, ei);
+        }
+      }
+    }
+    __syncthreads();  // the next tile overwrites tile and wn
+  }
+  if (!kUpdate) {
+    if (lane < ncol) {
+      dred[wv * kGsMaxCols + lane] = make_double2(dr, di);
+      ered[wv * kGsMaxCols + lane] = make_double2(er, ei);
+    }
+    __syncthreads();
+    if (tid < ncol) {
+      double ar = 0, ai = 0, br = 0, bi = 0;
+      for (int q = 0; q < 4; ++q) {
+        ar += dred[q * kGsMaxCols + tid].x;
+        ai += dred[q * kGsMaxCols + tid].y;
+        br += ered[q * kGsMaxCols + tid].x;
+        bi += ered[q * kGsMaxCols + tid].y;
+      }
+      partial[(int64_t)blockIdx.x * 2 * ncol + tid] = make_double2(ar, ai);
+      partial[(int64_t)blockIdx.x * 2 * ncol + ncol + tid] = make_double2(br, bi);
+    }
+  } else {
+    if (tid < kGsRows) red[tid] = nrm;
+    __syncthreads();
+    if (tid == 0) {
+      double sum = 0;
+      for (int r = 0; r < kGsRows; ++r) sum += red[r];
+      partial[blockIdx.x] = make_double2(sum, 0.0);
+    }
+  }
+}
+
+// Coefficients of pass B from the reduced dots of pass A (dots[0, ncol): t =
+// V^H w, dots[ncol, 2 ncol): g = V^H v_j): s = g_{<j}, a = sqrt(g_j - |s|^2),
+// h_j = (t_j - s^H t_{<j}) / a; cw_k = t_k - s_k h_j / a (k < j),
+// cw_j = h_j / a; cv_k = s_k, cv_j = 1 / a.  out (host-bound) gets
+// [t_0 .. t_{j-1}, h_j, (slot for |w|), s_0 .. s_{j-1}, a].  ncol <= 64.
+__global__ __launch_bounds__(64) void dcgs2_coef_kernel(PtrSetC dots_, int ncol, PtrSet cws, PtrSet cvs,
+                                                         PtrSet outs) {
+  const double2* __restrict__ t = reinterpret_cast<const double2*>(dots_.p[blockIdx.y]);
+  const double2* __restrict__ g = t + ncol;
+  double2* __restrict__ cw = reinterpret_cast<double2*>(cws.p[blockIdx.y]);
+  double2* __restrict__ cv = reinterpret_cast<double2*>(cvs.p[blockIdx.y]);
+  double2* __restrict__ out = reinterpret_cast<double2*>(outs.p[blockIdx.y]);
+  const int j = ncol - 1, k = threadIdx.x;  // one wave, lane k < j owns column k
+  const double2 gk = k < j ? g[k] : make_double2(0.0, 0.0);
+  const double2 tk = k < j ? t[k] : make_double2(0.0, 0.0);
+  double ss = gk.x * gk.x + gk.y * gk.y;
+  double str = gk.x * tk.x + gk.y * tk.y;  // conj(s_k) t_k
+  double sti = gk.x * tk.y - gk.y * tk.x;
+  for (int o = 32; o > 0; o >>= 1) {
+    ss += __shfl_xor(ss, o, 64);
+    str += __shfl_xor(str, o, 64);
+    sti += __shfl_xor(sti, o, 64);
+  }
+  const double2 gj = g[j], tj = t[j];
+  double a2 = gj.x - ss;
+  if (!(a2 > 0)) a2 = gj.x;  // no usable correction: keep v_j as it is
+  const double a = sqrt(a2), ia = 1.0 / a;
+  const double hr = (tj.x - str) * ia, hi = (tj.y - sti) * ia;
+  if (k < j) {
+    // s_k h_j / a
+    const double pr = (gk.x * hr - gk.y * hi) * ia, pi = (gk.x * hi + gk.y * hr) * ia;
+    cw[k] = make_double2(tk.x - pr, tk.y - pi);
+    cv[k] = gk;
+    out[k] = tk;
+    out[j + 2 + k] = gk;
+  } else if (k == j) {
+    cw[j] = make_double2(hr * ia, hi * ia);
+    cv[j] = make_double2(ia, 0.0);
+    out[j] = make_double2(hr, hi);
+    out[2 * j + 2] = make_double2(a, 0.0);
+  }
+}
+
 __global__ __launch_bounds__(kWG) void norm_final2_kernel(PtrSetC parts, int nblk, PtrSet outs) {
   __shared__ double sm[kWG];
   const double2* __restrict__ partial = reinterpret_cast<const double2*>(parts.p[blockIdx.y]);
@@ -798,6 +972,21 @@ void gs_pass(int mode, int nr, int64_t n, const PtrSetC& V, int64_t ld, int ncol
     gs_pass_kernel<true, false, true><<<grid, kWG, lds, s>>>(n, V, ld, ncol, h, w, partial);
 }
 
+void gs_dual(bool update, int nr, int64_t n, const PtrSetC& V, const PtrSet& Vw, int64_t ld, int ncol,
+             const PtrSetC& cw, const PtrSetC& cv, const PtrSet& w, const PtrSet& partial, hipStream_t s) {
+  const dim3 grid((unsigned)gs_tiles(n), (unsigned)nr);
+  static_assert(kGsRows == kGsMaxCols, "the shared sum space assumes equal row and column counts");
+  const size_t lds = sizeof(double2) * ((size_t)ncol * (kGsRows + 1) + 2 * kGsMaxCols + kGsRows + 8 * kGsMaxCols) +
+                     sizeof(double) * kGsRows;
+  if (update)
+    gs_dual_kernel<true><<<grid, kWG, lds, s>>>(n, V, Vw, ld, ncol, cw, cv, w, partial);
+  else
+    gs_dual_kernel<false><<<grid, kWG, lds, s>>>(n, V, Vw, ld, ncol, cw, cv, w, partial);
+}
+void dcgs2_coef(int nr, const PtrSetC& dots, int ncol, const PtrSet& cw, const PtrSet& cv, const PtrSet& out,
+                hipStream_t s) {
+  dcgs2_coef_kernel<<<dim3(1, (unsigned)nr), 64, 0, s>>>(dots, ncol, cw, cv, out);
+}
 void norm_final(int nr, const PtrSetC& partial, int nblk, const PtrSet& out, hipStream_t s) {
   norm_final2_kernel<<<dim3(1, (unsigned)nr), kWG, 0, s>>>(partial, nblk, out);
 }

@@ -147,6 +147,16 @@ void gs_pass(int mode, int nr, int64_t n, const PtrSetC& V, int64_t ld, int ncol
 void gs_final(int nr, const PtrSetC& partial, int nblk, int ncol, const PtrSet& h, const PtrSet& hacc,
               int accumulate, hipStream_t s);
 void norm_final(int nr, const PtrSetC& partial, int nblk, const PtrSet& out, hipStream_t s);
+// Delayed CGS2 passes over ncol = j + 1 columns of V (see device.hip):
+// update = false: partial dots V^H w and V^H v_j (2 ncol per tile, reduce
+// with gs_final over 2 ncol); update = true: v_j and w updated with the
+// coefficients cw, cv (written to column j through Vw), partial |w|^2.
+void gs_dual(bool update, int nr, int64_t n, const PtrSetC& V, const PtrSet& Vw, int64_t ld, int ncol,
+             const PtrSetC& cw, const PtrSetC& cv, const PtrSet& w, const PtrSet& partial, hipStream_t s);
+// Pass-B coefficients and the host-bound Hessenberg data from the reduced
+// pass-A dots (2 ncol entries per right-hand side); one wave per RHS.
+void dcgs2_coef(int nr, const PtrSetC& dots, int ncol, const PtrSet& cw, const PtrSet& cv, const PtrSet& out,
+                hipStream_t s);
 // v = w / nrm[0] per right-hand side
 void scale_by_inv_set(int nr, int64_t n, const PtrSetC& w, const PtrSetC& nrm, const PtrSet& v, hipStream_t s);
 

@@ -22,6 +22,7 @@
 namespace helm {
 
 Ctx::~Ctx() {
+  if (hev) (void)hipEventDestroy(hev);
   if (h_host) (void)hipHostFree(h_host);
   if (bh_host) (void)hipHostFree(bh_host);
 }
@@ -894,17 +895,28 @@ void apply_oras(Ctx& c, const double* r, double* z, const double* q, hipStream_t
   if (p) c.prof.end(HELM_K_PROLONG, 12.0 * c.pro_w.n + 28.0 * c.pro_w.n + 16.0 * c.D.n * (q ? 2 : 1) + 8.0 * c.D.n, s);
 }
 
-void apply_precond(Ctx& c, const double* r, double* z, hipStream_t s) {
-  if (!c.two_level) {
-    apply_oras(c, r, z, nullptr, s);
-    return;
-  }
+// Two-level M^{-1} in two stages: the coarse part (q = Z E^{-1} Z^T r,
+// t = r - A q; nothing for one level) and the subdomain part (z = sum R_i^T
+// D_i A_i^{-1} R_i t + q).  The first stage only writes the work vectors q
+// and t, so a solver may enqueue it ahead of a decision it has not taken yet.
+void precond_stage1(Ctx& c, const double* r, hipStream_t s) {
+  if (!c.two_level) return;
   apply_coarse(c, r, c.q.p, s);
   const bool p = c.prof.on;
   if (p) c.prof.begin(s);
   spmv_A(c, c.q.p, r, c.t.p, s);  // t = r - A q
   if (p) c.prof.end(HELM_K_SPMV, spmv_bytes(c, true), s);
-  apply_oras(c, c.t.p, z, c.q.p, s);
+}
+void precond_stage2(Ctx& c, const double* r, double* z, hipStream_t s) {
+  if (!c.two_level)
+    apply_oras(c, r, z, nullptr, s);
+  else
+    apply_oras(c, c.t.p, z, c.q.p, s);
+}
+
+void apply_precond(Ctx& c, const double* r, double* z, hipStream_t s) {
+  precond_stage1(c, r, s);
+  precond_stage2(c, r, z, s);
 }
 
 namespace {
@@ -924,14 +936,17 @@ void ensure_gmres(Ctx& c, int m) {
   c.Zk.alloc(2 * (size_t)n * m);
   c.w.alloc(2 * (size_t)n);
   const int nblk = std::max(dev::gs_blocks(n), dev::gs_tiles(n));
-  c.partial.alloc(2 * (size_t)nblk * (m + 2));
-  c.hcol.alloc(2 * (size_t)(m + 2));
-  c.htmp.alloc(2 * (size_t)(m + 2));
+  c.partial.alloc(2 * (size_t)nblk * (2 * m + 4));
+  c.hcol.alloc(2 * (size_t)(2 * m + 4));
+  c.htmp.alloc(2 * (size_t)(2 * m + 4));
+  c.coef_w.alloc(2 * (size_t)(m + 2));
+  c.coef_v.alloc(2 * (size_t)(m + 2));
   c.nrm.alloc(2);
   c.ydev.alloc(2 * (size_t)(m + 1));
   if (c.h_host) (void)hipHostFree(c.h_host);
   c.h_host = nullptr;
-  HELM_HIP(hipHostMalloc((void**)&c.h_host, 2 * sizeof(double) * (m + 2), hipHostMallocDefault));
+  HELM_HIP(hipHostMalloc((void**)&c.h_host, 2 * sizeof(double) * (2 * m + 4), hipHostMallocDefault));
+  if (!c.hev) HELM_HIP(hipEventCreateWithFlags(&c.hev, hipEventDisableTiming));
   c.gm_m = m;
 }
 
@@ -940,13 +955,68 @@ void ensure_gmres(Ctx& c, int m) {
 namespace {
 
 // One right-hand side at a time.
-int solve_single(Ctx& c, int32_t nrhs, const double* B, double tol, int m, int maxit, bool x0, double* U,
-                 hipStream_t s, helm_solve_info* info) {
+// Givens step on column jj of H (rotations 0..jj-1 applied, new rotation
+// jj, residual vector g updated).
+void givens_step(cplx* h, int jj, std::vector<double>& cs, std::vector<cplx>& sn, std::vector<cplx>& g) {
+  for (int i = 0; i < jj; ++i) {
+    const cplx a = h[i], bb = h[i + 1];
+    h[i] = cs[i] * a + sn[i] * bb;
+    h[i + 1] = -std::conj(sn[i]) * a + cs[i] * bb;
+  }
+  const cplx a = h[jj], bb = h[jj + 1];
+  if (a == cplx(0, 0)) {
+    cs[jj] = 0;
+    sn[jj] = 1;
+  } else {
+    const double r = std::sqrt(std::norm(a) + std::norm(bb));
+    cs[jj] = std::abs(a) / r;
+    sn[jj] = (a / std::abs(a)) * std::conj(bb) / r;
+  }
+  h[jj] = cs[jj] * a + sn[jj] * bb;
+  h[jj + 1] = 0;
+  g[jj + 1] = -std::conj(sn[jj]) * g[jj];
+  g[jj] = cs[jj] * g[jj];
+}
+
+dev::PtrSet pset(double* p) {
+  dev::PtrSet q{};
+  q.p[0] = p;
+  return q;
+}
+dev::PtrSetC csetc(const double* p) {
+  dev::PtrSetC q{};
+  q.p[0] = p;
+  return q;
+}
+
+// Pass A of delayed CGS2 over the first ncol columns of V (the last one
+// orthogonalised once so far) and c.w, then the pass-B coefficients (c.coef_w,
+// c.coef_v) and the host-bound data in c.hcol: [V_{<j}^H w, h_j, |w| slot,
+// s (j entries), alpha] with j = ncol - 1.
+void dual_pass_a(Ctx& c, int ncol, hipStream_t s) {
+  const int64_t n = c.D.n;
+  dev::gs_dual(false, 1, n, csetc(c.V.p), pset(c.V.p), n, ncol, csetc(c.coef_w.p), csetc(c.coef_v.p), pset(c.w.p),
+               pset(c.partial.p), s);
+  dev::gs_final(1, csetc(c.partial.p), dev::gs_tiles(n), 2 * ncol, pset(c.htmp.p), dev::PtrSet{}, 0, s);
+  dev::dcgs2_coef(1, csetc(c.htmp.p), ncol, pset(c.coef_w.p), pset(c.coef_v.p), pset(c.hcol.p), s);
+}
+
+// Column j of H (unrotated) finished with the second-pass data of v_{j+1}:
+// v_{j+1} (once orthogonalised) = alpha v_{j+1} (final) + sum_k s_k v_k, so
+// h_{k,j} += h_{j+1,j} s_k (k <= j) and h_{j+1,j} *= alpha.  s holds j + 1
+// interleaved complex values.
+void finish_column(cplx* h, int j, const double* sv, double alpha) {
+  for (int k = 0; k <= j; ++k) h[k] += h[j + 1] * cplx(sv[2 * k], sv[2 * k + 1]);
+  h[j + 1] *= alpha;
+}
+
+int solve_single(Ctx& c, int32_t nrhs, const double* B, double tol, int m, int maxit, bool x0, bool dcgs2,
+                 double* U, hipStream_t s, helm_solve_info* info) {
   ensure_gmres(c, m);
   const int64_t n = c.D.n;
   double* V = c.V.p;
   double* Zk = c.Zk.p;
-  std::vector<cplx> H((size_t)(m + 1) * m), g(m + 1), sn(m);
+  std::vector<cplx> H((size_t)(m + 1) * m), g(m + 1), sn(m), hc(m + 1);
   std::vector<double> cs(m);
   std::vector<cplx> y(m);
   int status = HELM_OK;
@@ -982,69 +1052,98 @@ int solve_single(Ctx& c, int32_t nrhs, const double* B, double tol, int m, int m
       std::fill(g.begin(), g.end(), cplx(0, 0));
       g[0] = beta;
       int k = 0;
+      precond_stage1(c, V, s);
       for (int jj = 0; jj < m; ++jj) {
         double* vj = V + 2 * (size_t)n * jj;
         double* zj = Zk + 2 * (size_t)n * jj;
-        apply_precond(c, vj, zj, s);
+        precond_stage2(c, vj, zj, s);
         apply_A(c, zj, c.w.p, s);
-        // CGS2: dots | update + dots | update + norm, each one pass over V
         const bool prof = c.prof.on;
         if (prof) c.prof.begin(s);
         const int nt = dev::gs_tiles(n);
-        dev::PtrSetC Vs{}, hs{}, ps{};
-        dev::PtrSet ws{}, hts{}, hcs{}, pw{}, nrm{}, vn{};
+        dev::PtrSetC Vs{}, ps{};
+        dev::PtrSet ws{}, pw{}, nrm{}, vn{};
         Vs.p[0] = V;
-        hs.p[0] = c.htmp.p;
         ps.p[0] = c.partial.p;
         ws.p[0] = c.w.p;
-        hts.p[0] = c.htmp.p;
-        hcs.p[0] = c.hcol.p;
         pw.p[0] = c.partial.p;
         nrm.p[0] = c.hcol.p + 2 * (jj + 1);
         vn.p[0] = V + 2 * (size_t)n * (jj + 1);
-        dev::gs_pass(0, 1, n, Vs, n, jj + 1, hs, ws, pw, s);
-        dev::gs_final(1, ps, nt, jj + 1, hts, hcs, 0, s);
-        dev::gs_pass(1, 1, n, Vs, n, jj + 1, hs, ws, pw, s);
-        dev::gs_final(1, ps, nt, jj + 1, hts, hcs, 1, s);
-        dev::gs_pass(2, 1, n, Vs, n, jj + 1, hs, ws, pw, s);
-        dev::norm_final(1, ps, nt, nrm, s);
-        dev::PtrSetC wc{}, nc{};
-        wc.p[0] = c.w.p;
-        nc.p[0] = nrm.p[0];
-        dev::scale_by_inv_set(1, n, wc, nc, vn, s);
-        if (prof) c.prof.end(HELM_K_GS, 16.0 * n * (3.0 * (jj + 1) + 7.0), s);
-        HELM_HIP(hipMemcpyAsync(c.h_host, c.hcol.p, 2 * sizeof(double) * (jj + 2), hipMemcpyDeviceToHost, s));
-        HELM_HIP(hipStreamSynchronize(s));
-        if (c.prof.on) c.prof.harvest();
+        int nout;  // complex entries of hcol the host reads
+        if (dcgs2) {
+          // pass A: V^H w and V^H v_j | coefficients | pass B: v_j finished,
+          // w orthogonalised, |w|^2
+          dual_pass_a(c, jj + 1, s);
+          dev::gs_dual(true, 1, n, Vs, pset(V), n, jj + 1, csetc(c.coef_w.p), csetc(c.coef_v.p), ws, pw, s);
+          dev::norm_final(1, ps, nt, nrm, s);
+          nout = 2 * jj + 3;
+        } else {
+          // CGS2: dots | update + dots | update + norm, each one pass over V
+          dev::PtrSetC hs{};
+          dev::PtrSet hts{}, hcs{};
+          hs.p[0] = c.htmp.p;
+          hts.p[0] = c.htmp.p;
+          hcs.p[0] = c.hcol.p;
+          dev::gs_pass(0, 1, n, Vs, n, jj + 1, hs, ws, pw, s);
+          dev::gs_final(1, ps, nt, jj + 1, hts, hcs, 0, s);
+          dev::gs_pass(1, 1, n, Vs, n, jj + 1, hs, ws, pw, s);
+          dev::gs_final(1, ps, nt, jj + 1, hts, hcs, 1, s);
+          dev::gs_pass(2, 1, n, Vs, n, jj + 1, hs, ws, pw, s);
+          dev::norm_final(1, ps, nt, nrm, s);
+          nout = jj + 2;
+        }
+        dev::scale_by_inv_set(1, n, csetc(c.w.p), csetc(nrm.p[0]), vn, s);
+        if (prof)
+          c.prof.end(HELM_K_GS, 16.0 * n * (dcgs2 ? 2.0 * (jj + 1) + 6.0 : 3.0 * (jj + 1) + 7.0), s);
+        HELM_HIP(hipMemcpyAsync(c.h_host, c.hcol.p, 2 * sizeof(double) * nout, hipMemcpyDeviceToHost, s));
+        HELM_HIP(hipEventRecord(c.hev, s));
+        // the next step's coarse stage runs while the host updates the
+        // least-squares problem (wasted only when this step ends the cycle)
+        if (jj + 1 < m && its + 1 < maxit) precond_stage1(c, V + 2 * (size_t)n * (jj + 1), s);
+        HELM_HIP(hipEventSynchronize(c.hev));
         ++its;
+        for (int i = 0; i < 2 * nout; ++i)
+          if (!std::isfinite(c.h_host[i])) fail(HELM_ENUMERIC, "non-finite Hessenberg entry");
+        auto hget = [&](int i) { return cplx(c.h_host[2 * i], c.h_host[2 * i + 1]); };
         cplx* h = H.data() + (size_t)(m + 1) * jj;
-        for (int i = 0; i <= jj + 1; ++i) {
-          h[i] = cplx(c.h_host[2 * i], c.h_host[2 * i + 1]);
-          if (!std::isfinite(h[i].real()) || !std::isfinite(h[i].imag())) fail(HELM_ENUMERIC, "non-finite Hessenberg entry");
-        }
+        for (int i = 0; i <= jj + 1; ++i) h[i] = hget(i);
         const double hn = h[jj + 1].real();
-        for (int i = 0; i < jj; ++i) {
-          cplx a = h[i], bb = h[i + 1];
-          h[i] = cs[i] * a + sn[i] * bb;
-          h[i + 1] = -std::conj(sn[i]) * a + cs[i] * bb;
+        if (!dcgs2) {
+          givens_step(h, jj, cs, sn, g);
+          k = jj + 1;
+          if (std::abs(g[jj + 1]) <= tol * bnorm || its >= maxit || hn == 0) break;
+          continue;
         }
+        // delayed CGS2: v_j's second pass finishes column j - 1 of H
+        if (jj >= 1) finish_column(H.data() + (size_t)(m + 1) * (jj - 1), jj - 1, &c.h_host[2 * (jj + 2)], c.h_host[2 * (2 * jj + 2)]);
+        if (jj >= 1) givens_step(H.data() + (size_t)(m + 1) * (jj - 1), jj - 1, cs, sn, g);
+        // residual estimate from column j as it stands (its last correction,
+        // below the orthogonality error of v_{j+1}, comes with the next step)
+        double est;
         {
-          cplx a = h[jj], bb = h[jj + 1];
-          if (a == cplx(0, 0)) {
-            cs[jj] = 0;
-            sn[jj] = 1;
-          } else {
-            double r = std::sqrt(std::norm(a) + std::norm(bb));
-            cs[jj] = std::abs(a) / r;
-            sn[jj] = (a / std::abs(a)) * std::conj(bb) / r;
+          for (int i = 0; i <= jj + 1; ++i) hc[i] = h[i];
+          for (int i = 0; i < jj; ++i) {
+            const cplx a = hc[i], bb = hc[i + 1];
+            hc[i] = cs[i] * a + sn[i] * bb;
+            hc[i + 1] = -std::conj(sn[i]) * a + cs[i] * bb;
           }
-          h[jj] = cs[jj] * a + sn[jj] * bb;
-          h[jj + 1] = 0;
-          g[jj + 1] = -std::conj(sn[jj]) * g[jj];
-          g[jj] = cs[jj] * g[jj];
+          const double r = std::sqrt(std::norm(hc[jj]) + std::norm(hc[jj + 1]));
+          est = hc[jj] == cplx(0, 0) ? std::abs(g[jj]) : std::abs(hc[jj + 1]) / r * std::abs(g[jj]);
         }
-        k = jj + 1;
-        if (std::abs(g[jj + 1]) <= tol * bnorm || its >= maxit || hn == 0) break;
+        if (est <= tol * bnorm || jj + 1 == m || its >= maxit || hn == 0) {
+          if (hn > 0) {
+            // finish column j with the dots of v_{j+1}
+            dual_pass_a(c, jj + 2, s);
+            HELM_HIP(hipMemcpyAsync(c.h_host, c.hcol.p, 2 * sizeof(double) * (2 * jj + 5), hipMemcpyDeviceToHost, s));
+            HELM_HIP(hipStreamSynchronize(s));
+            for (int i = 0; i < 2 * (2 * jj + 5); ++i)
+              if (!std::isfinite(c.h_host[i])) fail(HELM_ENUMERIC, "non-finite Hessenberg entry");
+            finish_column(h, jj, &c.h_host[2 * (jj + 3)], c.h_host[2 * (2 * jj + 4)]);
+          }
+          givens_step(h, jj, cs, sn, g);
+          k = jj + 1;
+          break;
+        }
       }
       // back substitution R y = g
       for (int i = k - 1; i >= 0; --i) {
@@ -1055,6 +1154,7 @@ int solve_single(Ctx& c, int32_t nrhs, const double* B, double tol, int m, int m
       HELM_HIP(hipMemcpyAsync(c.ydev.p, y.data(), sizeof(cplx) * k, hipMemcpyHostToDevice, s));
       dev::gemv_acc(n, Zk, n, k, c.ydev.p, x, s);
       HELM_HIP(hipStreamSynchronize(s));  // y is reused by the next cycle
+      if (c.prof.on) c.prof.harvest();
     }
     HELM_HIP(hipStreamSynchronize(s));
     if (c.prof.on) c.prof.harvest();
@@ -1361,10 +1461,11 @@ int solve(Ctx& c, int32_t nrhs, const double* B, double tol, const helm_solve_op
   const int m = opts && opts->restart > 0 ? opts->restart : 50;
   const int maxit = opts && opts->maxit > 0 ? opts->maxit : 1000;
   const bool x0 = opts && (opts->flags & HELM_SOLVE_X0);
+  const bool dcgs2 = !(opts && (opts->flags & HELM_SOLVE_CGS2));
   const int block = opts && opts->block > 0 ? std::min(opts->block, dev::kMaxBlock) : 1;
   if (m > 50) fail(HELM_EINVAL, "restart must be <= 50");
   if (!(tol > 0)) fail(HELM_EINVAL, "tol must be positive");
-  if (block <= 1 || nrhs <= 1) return solve_single(c, nrhs, B, tol, m, maxit, x0, U, s, info);
+  if (block <= 1 || nrhs <= 1) return solve_single(c, nrhs, B, tol, m, maxit, x0, dcgs2, U, s, info);
   ensure_gmres(c, m);  // device_norm's work space
   const int64_t n = c.D.n;
   int status = HELM_OK;
@@ -1376,7 +1477,7 @@ int solve(Ctx& c, int32_t nrhs, const double* B, double tol, const helm_solve_op
       Bp[r] = B + 2 * (size_t)n * (j0 + r);
       Up[r] = U + 2 * (size_t)n * (j0 + r);
     }
-    int st = nb == 1 ? solve_single(c, 1, Bp[0], tol, m, maxit, x0, Up[0], s, info ? info + j0 : nullptr)
+    int st = nb == 1 ? solve_single(c, 1, Bp[0], tol, m, maxit, x0, dcgs2, Up[0], s, info ? info + j0 : nullptr)
                      : solve_block(c, nb, Bp.data(), Up.data(), tol, m, maxit, x0, s, info ? info + j0 : nullptr);
     if (st != HELM_OK) status = st;
   }

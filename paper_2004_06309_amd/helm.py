@@ -24,6 +24,7 @@ HELM_ENOMEM = -5
 HELM_ESTATE = -6
 HELM_EDEVICE = -7
 HELM_SOLVE_X0 = 1
+HELM_SOLVE_CGS2 = 2
 
 _ERRNAMES = {-1: "EINVAL", -2: "ESINGULAR", -3: "ENOCONV", -4: "ENUMERIC", -5: "ENOMEM", -6: "ESTATE",
              -7: "EDEVICE"}
@@ -277,13 +278,15 @@ class Helm:
     def apply_coarse(self, r, q, stream=None):
         self._check(self.lib.helm_apply_coarse(self.h, _dev_ptr(r), _dev_ptr(q), _stream(stream)))
 
-    def solve(self, B, U, tol=1e-6, restart=50, maxit=1000, x0=False, stream=None, block=1):
+    def solve(self, B, U, tol=1e-6, restart=50, maxit=1000, x0=False, stream=None, block=1, classic_cgs2=False):
         """Solve A U = B; B, U are (n,) or (nrhs, n) complex128 GPU tensors
         (each RHS contiguous); `block` right-hand sides are advanced together.
-        Returns (status, [info dicts])."""
+        `classic_cgs2` selects three-pass CGS2 for one-at-a-time solves
+        (default: delayed CGS2).  Returns (status, [info dicts])."""
         nrhs = 1 if B.dim() == 1 else B.shape[0]
         info = (SolveInfo * max(nrhs, 1))()
-        opts = SolveOpts(int(restart), int(maxit), HELM_SOLVE_X0 if x0 else 0, int(block))
+        flags = (HELM_SOLVE_X0 if x0 else 0) | (HELM_SOLVE_CGS2 if classic_cgs2 else 0)
+        opts = SolveOpts(int(restart), int(maxit), flags, int(block))
         rc = self._check(self.lib.helm_solve(self.h, nrhs, _dev_ptr(B), float(tol), C.byref(opts), _dev_ptr(U),
                                              _stream(stream), info), allow=(HELM_ENOCONV,))
         return rc, [{f: getattr(info[i], f) for f, _ in SolveInfo._fields_} for i in range(nrhs)]

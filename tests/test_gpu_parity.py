@@ -125,6 +125,34 @@ def test_solve_parity(pair):
     assert torch.equal(U, U2)
 
 
+@pytest.mark.parametrize("restart", [1, 2, 7, 50])
+def test_delayed_and_classic_cgs2(restart):
+    """Delayed CGS2 (default; v_j's second pass folded into step j + 1, its
+    correction of H applied one step late and at each cycle end) against
+    classic three-pass CGS2 and the oracle's MGS GMRES, over restart lengths
+    down to GMRES(1), where every cycle ends on its first step."""
+    w = WORKLOADS["small_p2_2lvl"]()
+    P, b, M = opre.build(w)
+    h = helm.from_workload(w)
+    tol = 1e-8
+    ro = opre.solve(P, b, M, tol=tol, restart=restart, maxit=600)
+    B = dvec(b)
+    out = {}
+    for classic in (False, True):
+        U = torch.zeros(P.n, dtype=torch.complex128, device=DEV)
+        rc, info = h.solve(B, U, tol=tol, restart=restart, maxit=600, classic_cgs2=classic)
+        u = host(U)
+        res = np.linalg.norm(b - P.A @ u) / np.linalg.norm(b)
+        say(f"[dcgs2] restart={restart} classic={classic}: its={info[0]['iterations']} oracle={ro.iterations} "
+            f"res={res:.2e} relres={info[0]['relres']:.2e}")
+        assert rc == helm.HELM_OK and info[0]["converged"] == 1
+        assert res <= tol and np.isclose(res, info[0]["relres"], rtol=1e-3)
+        assert abs(info[0]["iterations"] - ro.iterations) <= 2
+        assert np.linalg.norm(u - ro.x) <= 1e-6 * np.linalg.norm(ro.x)
+        out[classic] = info[0]["iterations"]
+    assert abs(out[False] - out[True]) <= 1
+
+
 @pytest.mark.parametrize("name", ["tiny", "mid_quarter_2lvl", "ragged_p2"])
 def test_complex64_factors(name):
     """Subdomain factors stored in complex64 (rounded once from the FP64
@@ -421,3 +449,23 @@ def test_servers_on_two_operators_overlap():
             assert np.linalg.norm(Bs[r] - P.A @ u[r]) / np.linalg.norm(Bs[r]) <= w.tol
             assert abs(e["iterations"] - ro.iterations) <= 2
             assert np.linalg.norm(u[r] - ro.x) <= 1e-5 * np.linalg.norm(ro.x)
+
+
+def test_server_reports_bad_requests_and_keeps_serving():
+    """A request with a NaN right-hand side completes with HELM_ENUMERIC
+    (its slot is freed); the requests around it still converge."""
+    w = WORKLOADS["tiny"]()
+    P, b, M = opre.build(w)
+    h = helm.from_workload(w)
+    bad = b.copy()
+    bad[5] = np.nan
+    B = dvec(np.stack([b, bad, 2.0 * b]))
+    U = torch.zeros_like(B)
+    srv = helm.Server(h, slots=2, tol=w.tol)
+    ev = _serve([srv], [[(0, B[0], U[0], 0), (0, B[1], U[1], 1), (1, B[2], U[2], 2)]])
+    srv.close()
+    assert ev[1]["status"] == helm.HELM_ENUMERIC and ev[1]["converged"] == 0
+    u = host(U)
+    for r, scale in ((0, 1.0), (2, 2.0)):
+        assert ev[r]["status"] == helm.HELM_OK
+        assert np.linalg.norm(scale * b - P.A @ u[r]) / np.linalg.norm(scale * b) <= w.tol
