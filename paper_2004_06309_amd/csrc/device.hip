@@ -13,6 +13,11 @@
 #include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "device.hpp"
 
 namespace helm {
@@ -101,18 +106,27 @@ __device__ __forceinline__ void fwd_task(const Task& task, const Batch& b, const
   const Split sp = split_of(task, chunk);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   Tile t{};
-  int s = 0, c0 = 0, w = 0, frow0 = 0;
-  if (sp.has) {
-    t = b.tf[task.tile0 + sp.my];
-    s = t.sn;
-    c0 = b.sn_c0[s];
-    w = b.sn_w[s];
-    frow0 = b.sn_frow0[s];
-  }
+  if (sp.has) t = b.tf[task.tile0 + sp.my];
+  const int s = t.sn, c0 = t.c0, w = t.w, frow0 = t.aux;
   double2* vt = vin + sp.my * sp.region;
   const int R = row_group(t.nrows), grp = lane / R, row_l = lane % R;
   const PT* __restrict__ P = reinterpret_cast<const PT*>(b.pf) + t.off + row_l;
   const double2* __restrict__ ub = reinterpret_cast<const double2*>(b.ubuf);
+  // the children's updates to this lane's output row (rows past the pivot
+  // block) are fetched before the panel, off the critical path
+  const bool out = sp.has && sp.part == 0 && lane < t.nrows;
+  const int row = t.row0 + lane;
+  double er = 0, ei = 0;
+  int uo = 0;
+  if (out && row >= w) {
+    uo = b.sn_uoff[s] + row - w;
+    const int fr = frow0 + row;
+    for (int e = b.fcon_ptr[fr]; e < b.fcon_ptr[fr + 1]; ++e) {
+      double2 u = ub[b.fcon_idx[e]];
+      er += u.x;
+      ei += u.y;
+    }
+  }
   double ar = 0, ai = 0;
   // all waves of a workgroup run the same number of passes: one, unless the
   // workgroup holds a single wide tile
@@ -141,25 +155,17 @@ __device__ __forceinline__ void fwd_task(const Task& task, const Batch& b, const
   }
   red[wv][lane] = make_double2(ar, ai);
   __syncthreads();
-  if (sp.has && sp.part == 0 && lane < t.nrows) {
+  if (out) {
     double rr = 0, ii = 0;
     for (int q = 0; q < sp.wpt; ++q)
       for (int g = lane; g < 64; g += R) {
         rr += red[wv + q][g].x;
         ii += red[wv + q][g].y;
       }
-    const int row = t.row0 + lane;
-    if (row < w) {
+    if (row < w)
       reinterpret_cast<double2*>(b.y)[c0 + row] = make_double2(rr, ii);
-    } else {
-      const int fr = frow0 + row;
-      for (int e = b.fcon_ptr[fr]; e < b.fcon_ptr[fr + 1]; ++e) {
-        double2 u = ub[b.fcon_idx[e]];
-        rr += u.x;
-        ii += u.y;
-      }
-      reinterpret_cast<double2*>(b.ubuf)[b.sn_uoff[s] + row - w] = make_double2(rr, ii);
-    }
+    else
+      reinterpret_cast<double2*>(b.ubuf)[uo] = make_double2(rr + er, ii + ei);
   }
 }
 
@@ -169,14 +175,9 @@ __device__ __forceinline__ void bwd_task(const Task& task, const Batch& b, doubl
   const Split sp = split_of(task, chunk);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   Tile t{};
-  int c0 = 0, w = 0;
-  int64_t roff = 0;
-  if (sp.has) {
-    t = b.tb[task.tile0 + sp.my];
-    c0 = b.sn_c0[t.sn];
-    w = b.sn_w[t.sn];
-    roff = b.sn_roff[t.sn];
-  }
+  if (sp.has) t = b.tb[task.tile0 + sp.my];
+  const int c0 = t.c0, w = t.w;
+  const int64_t roff = t.aux;
   double2* vt = vin + sp.my * sp.region;
   const int R = row_group(t.nrows), grp = lane / R, row_l = lane % R;
   const PT* __restrict__ P = reinterpret_cast<const PT*>(b.pb) + t.off + row_l;
@@ -214,19 +215,29 @@ __device__ __forceinline__ void bwd_task(const Task& task, const Batch& b, doubl
 
 // The input-column buffer is dynamic LDS sized per level (chunk entries), so
 // levels of narrow tiles keep more workgroups resident per CU.
+// The grid holds at most as many workgroups as fit on the device at once;
+// each sweeps tasks blockIdx.x, blockIdx.x + gridDim.x, ... (widest first),
+// so a level costs no workgroup launches beyond the first wave of them.
 template <class PT, int kCoarse>
-__global__ __launch_bounds__(kWG) void fwd_level_kernel(const Task* __restrict__ tasks, Batch b,
+__global__ __launch_bounds__(kWG) void fwd_level_kernel(const Task* __restrict__ tasks, int ntasks, Batch b,
                                                         const double2* __restrict__ bin, int chunk) {
   extern __shared__ double2 vin[];
   __shared__ double2 red[4][64];
-  fwd_task<PT>(tasks[blockIdx.x], b, bin, vin, red, chunk);
+  for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+    fwd_task<PT>(tasks[t], b, bin, vin, red, chunk);
+    __syncthreads();  // red and vin are rewritten by the next task
+  }
 }
 
 template <class PT, int kCoarse>
-__global__ __launch_bounds__(kWG) void bwd_level_kernel(const Task* __restrict__ tasks, Batch b, int chunk) {
+__global__ __launch_bounds__(kWG) void bwd_level_kernel(const Task* __restrict__ tasks, int ntasks, Batch b,
+                                                        int chunk) {
   extern __shared__ double2 vin[];
   __shared__ double2 red[4][64];
-  bwd_task<PT>(tasks[blockIdx.x], b, vin, red, chunk);
+  for (int t = blockIdx.x; t < ntasks; t += gridDim.x) {
+    bwd_task<PT>(tasks[t], b, vin, red, chunk);
+    __syncthreads();
+  }
 }
 
 // Whole forward + backward solve of a small batch (the coarse matrix) in one
@@ -814,34 +825,82 @@ inline unsigned blocks_for(int64_t n, int per = kWG) { return (unsigned)((n + pe
 // Same, rounded up to a multiple of 8 (grids of kernels that use xcd_block).
 inline unsigned blocks8_for(int64_t n) { return (blocks_for(n) + 7) / 8 * 8; }
 
+__global__ __launch_bounds__(kWG) void copy_tiles_kernel(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst,
+                                                         const int64_t* __restrict__ from,
+                                                         const int64_t* __restrict__ to,
+                                                         const int64_t* __restrict__ words, int64_t ntiles) {
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const uint64_t* a = src + from[t];
+    uint64_t* d = dst + to[t];
+    const int64_t n = words[t];
+    for (int64_t i = threadIdx.x; i < n; i += kWG) d[i] = a[i];
+  }
+}
+
 }  // namespace
 
 int waves_per_tile(int ncols) { return ncols <= 96 ? 1 : (ncols <= 384 ? 2 : 4); }
+
+void copy_tiles(const void* src, void* dst, const int64_t* from, const int64_t* to, const int64_t* words,
+                int64_t ntiles, hipStream_t s) {
+  if (ntiles <= 0) return;
+  const unsigned grid = (unsigned)std::min<int64_t>(ntiles, 1 << 20);
+  copy_tiles_kernel<<<grid, kWG, 0, s>>>(reinterpret_cast<const uint64_t*>(src), reinterpret_cast<uint64_t*>(dst),
+                                         from, to, words, ntiles);
+}
+
+// Workgroups of a level kernel resident on the current device at once
+// (cached per kernel, LDS size and device).
+static int resident_grid(const void* fn, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::tuple<const void*, size_t, int>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1 << 30;
+  const auto key = std::make_tuple(fn, lds, dev);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int ncu = 0, per = 0;
+  int g = 1 << 30;  // unknown: one workgroup per task
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kWG, lds) == hipSuccess && per > 0 && ncu > 0)
+    g = per * ncu;
+  cache.emplace(key, g);
+  return g;
+}
+
+template <class K, class... A>
+static void level_go(K kernel, int64_t ntasks, size_t lds, hipStream_t s, A... args) {
+  const int64_t g = std::min<int64_t>(ntasks, resident_grid(reinterpret_cast<const void*>(kernel), lds));
+  kernel<<<(unsigned)g, kWG, lds, s>>>(args...);
+}
 
 void fwd_level(const Batch& b, int64_t task0, int64_t ntasks, const double* bin, int chunk, bool coarse,
                hipStream_t s) {
   if (ntasks <= 0) return;
   const Task* k = b.kf + task0;
+  const int nt = (int)ntasks;
   const double2* in = reinterpret_cast<const double2*>(bin);
   const size_t lds = sizeof(double2) * (size_t)chunk;
   if (coarse)
-    fwd_level_kernel<double2, 1><<<(unsigned)ntasks, kWG, lds, s>>>(k, b, in, chunk);
+    level_go(fwd_level_kernel<double2, 1>, ntasks, lds, s, k, nt, b, in, chunk);
   else if (b.c64)
-    fwd_level_kernel<float2, 0><<<(unsigned)ntasks, kWG, lds, s>>>(k, b, in, chunk);
+    level_go(fwd_level_kernel<float2, 0>, ntasks, lds, s, k, nt, b, in, chunk);
   else
-    fwd_level_kernel<double2, 0><<<(unsigned)ntasks, kWG, lds, s>>>(k, b, in, chunk);
+    level_go(fwd_level_kernel<double2, 0>, ntasks, lds, s, k, nt, b, in, chunk);
 }
 
 void bwd_level(const Batch& b, int64_t task0, int64_t ntasks, int chunk, bool coarse, hipStream_t s) {
   if (ntasks <= 0) return;
   const Task* k = b.kb + task0;
+  const int nt = (int)ntasks;
   const size_t lds = sizeof(double2) * (size_t)chunk;
   if (coarse)
-    bwd_level_kernel<double2, 1><<<(unsigned)ntasks, kWG, lds, s>>>(k, b, chunk);
+    level_go(bwd_level_kernel<double2, 1>, ntasks, lds, s, k, nt, b, chunk);
   else if (b.c64)
-    bwd_level_kernel<float2, 0><<<(unsigned)ntasks, kWG, lds, s>>>(k, b, chunk);
+    level_go(bwd_level_kernel<float2, 0>, ntasks, lds, s, k, nt, b, chunk);
   else
-    bwd_level_kernel<double2, 0><<<(unsigned)ntasks, kWG, lds, s>>>(k, b, chunk);
+    level_go(bwd_level_kernel<double2, 0>, ntasks, lds, s, k, nt, b, chunk);
 }
 
 int coop_grid() {

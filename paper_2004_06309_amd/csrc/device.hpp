@@ -22,7 +22,10 @@ struct PtrSetC {
 // Mirrors helm::TileDesc.
 struct Tile {
   int64_t off;
-  int32_t sn, row0, nrows, col0, ncols, pad;
+  int32_t sn, row0, nrows, col0, ncols;
+  int32_t c0;   // the supernode's first batch position
+  int32_t w;    // its pivot columns
+  int32_t aux;  // forward: its first front row in fcon_ptr; backward: offset of R_s in rows
 };
 
 // A workgroup's share of a level: ntile consecutive tiles, each handled by
@@ -66,6 +69,10 @@ struct Batch {
 void fwd_level(const Batch& b, int64_t task0, int64_t ntasks, const double* bin, int chunk, bool coarse,
                hipStream_t s);
 void bwd_level(const Batch& b, int64_t task0, int64_t ntasks, int chunk, bool coarse, hipStream_t s);
+// dst[to[t] + i] = src[from[t] + i] for i < words[t], t < ntiles (8-byte
+// words; device pointers): moves panel tiles into their solve order.
+void copy_tiles(const void* src, void* dst, const int64_t* from, const int64_t* to, const int64_t* words,
+                int64_t ntiles, hipStream_t s);
 // Largest LDS input buffer a level solve uses (entries).
 constexpr int kLevelChunkMax = 2048;
 // One frontal matrix of the device factorisation (offsets in complex

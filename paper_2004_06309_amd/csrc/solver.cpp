@@ -189,13 +189,13 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
       tiles_fwd(w, r, S.tile_rows, ts);
       int64_t off = pf0[i] + S.sn_fwd_off[s];
       for (auto& t : ts) {
-        lf[S.height[s]].push_back({off, (int32_t)g, t.row0, t.nrows, t.col0, t.ncols, 0});
+        lf[S.height[s]].push_back({off, (int32_t)g, t.row0, t.nrows, t.col0, t.ncols, B.c0[g], w, B.frow0[g]});
         off += (int64_t)t.nrows * t.ncols;
       }
       tiles_bwd(w, r, S.tile_rows, ts);
       off = pb0[i] + S.sn_bwd_off[s];
       for (auto& t : ts) {
-        lb[S.depth[s]].push_back({off, (int32_t)g, t.row0, t.nrows, t.col0, t.ncols, 0});
+        lb[S.depth[s]].push_back({off, (int32_t)g, t.row0, t.nrows, t.col0, t.ncols, B.c0[g], w, (int32_t)B.roff[g]});
         off += (int64_t)t.nrows * t.ncols;
       }
     }
@@ -420,6 +420,38 @@ void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symb
   seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   layout_batch(Ss, in_idx, num, B);
   if (!numeric) return;
+  // Panels move from factorisation order (per matrix, per supernode) to
+  // solve order: each level's tiles contiguous, in the order its workgroups
+  // take them, so a level streams one region of HBM front to back.
+  auto relayout = [&](DVec<unsigned char>& P, std::vector<dev::Tile>& T) {
+    if (T.empty()) return;
+    const int64_t wpe = (int64_t)(esz / 8);  // 8-byte words per entry
+    std::vector<int64_t> from(T.size()), to(T.size()), words(T.size());
+    int64_t pos = 0;
+    for (size_t i = 0; i < T.size(); ++i) {
+      const int64_t len = (int64_t)T[i].nrows * T[i].ncols;
+      from[i] = T[i].off * wpe;
+      to[i] = pos * wpe;
+      words[i] = len * wpe;
+      T[i].off = pos;
+      pos += len;
+    }
+    bool inside = (size_t)pos * esz == P.n;
+    for (size_t i = 0; i < T.size() && inside; ++i) inside = from[i] >= 0 && (size_t)(from[i] + words[i]) * 8 <= P.n;
+    if (!inside) fail(HELM_EINVAL, "internal: solve tiles do not cover the panel array");
+    DVec<unsigned char> Q;
+    Q.alloc(P.n);
+    DVec<int64_t> f, t, w;
+    f.upload(from);
+    t.upload(to);
+    w.upload(words);
+    dev::copy_tiles(P.p, Q.p, f.p, t.p, w.p, (int64_t)T.size(), nullptr);
+    HELM_HIP(hipDeviceSynchronize());
+    std::swap(P.p, Q.p);
+    std::swap(P.n, Q.n);
+  };
+  relayout(Dv.pf, B.tf);
+  relayout(Dv.pb, B.tb);
   Dv.npos = B.npos;
   Dv.lev_f = B.lev_f;
   Dv.lev_b = B.lev_b;
