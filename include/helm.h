@@ -73,7 +73,12 @@ typedef struct helm_precond_opts {
   int32_t coarse_tile_rows;  /* same for the coarse factor; 0 = 16         */
   int32_t factor_on_host;  /* 1: numeric factorisation on the host CPU
                               (reference path); 0 = on the device          */
-  int32_t reserved[2];
+  int32_t sn_jobs_min;     /* complex128 panels: a forward level with at least
+                              this many supernodes of <= 64 pivots (and
+                              64-row tiles) solves those with one wave per
+                              supernode instead of one per tile; 0 = 6144,
+                              -1 = never                                  */
+  int32_t reserved;
 } helm_precond_opts;
 
 enum {

@@ -59,6 +59,10 @@ struct BatchHost {
   std::vector<int64_t> lev_f, lev_b;  // task ranges per level
   std::vector<int32_t> chunk_f, chunk_b;  // LDS input entries per level
   std::vector<int64_t> nwide_f, nwide_b;  // tiles of each level wider than 96 columns (they come first)
+  // one-wave forward supernodes (their tiles close each level, in job
+  // order); the tile kernel takes the first ktile_f tasks of a level
+  std::vector<dev::SnJob> snj;
+  std::vector<int64_t> snj_lev, ktile_f;
   std::vector<int32_t> gy_f, gy_b;        // gather workgroups per supernode of each level
   std::vector<double> bytes_f, bytes_b;  // algorithmic bytes per level
   std::vector<double> pbytes_f, pbytes_b;  // of which panel bytes
@@ -85,6 +89,8 @@ struct BatchDev {
   std::vector<int32_t> chunk_f, chunk_b;
   std::vector<int64_t> nwide_f, nwide_b;
   std::vector<int32_t> gy_f, gy_b;
+  DVec<dev::SnJob> snj;
+  std::vector<int64_t> snj_lev, ktile_f;
   int64_t npos = 0;
   std::vector<double> bytes_f, bytes_b;  // algorithmic bytes per level
   std::vector<double> pbytes_f, pbytes_b;  // of which panel bytes
@@ -216,7 +222,7 @@ void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<co
 
 // solver.cpp
 void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<const std::vector<int64_t>*>& in_idx,
-                  const std::vector<NumericOut>& num, BatchHost& B);
+                  const std::vector<NumericOut>& num, int64_t sn_jobs_min, BatchHost& B);
 void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overlap, const helm_mesh* coarse,
                    const helm_precond_opts* opts);
 void upload_matrix(Ctx& c);

@@ -240,6 +240,112 @@ __global__ __launch_bounds__(kWG) void bwd_level_kernel(const Task* __restrict__
   }
 }
 
+// Forward solve of narrow supernodes (w <= 64), one wave per supernode.
+// Lane k holds gathered input k; lane l owns row l of every 64-row tile, and
+// the wave streams up to four tiles side by side (column k of each), so a
+// supernode's whole panel is one stream of loads after a single gather.
+__device__ __forceinline__ double bcast(double x, int k) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)v, k);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), k);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// acc[q] += tile q (rows lane, columns 0..w-1) * v, NQ tiles at P + 64 q w
+// (tile q has rows[q] rows, tiles q >= nq are skipped), 8 loads in flight
+// per lane.  Lanes past a tile's last row re-read that row: their sums are
+// never stored, and every load stays inside the tile.
+template <class PT, int NQ>
+__device__ __forceinline__ void sn_stream(const PT* __restrict__ P, int w, int nq, const int* rows, double2 v,
+                                          double2* acc) {
+  constexpr int KU = 8 / NQ;
+  const int lane = threadIdx.x & 63;
+  const PT* base[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) base[q] = P + (int64_t)q * 64 * w + min(lane, max(rows[q], 1) - 1);
+  for (int k = 0; k < w; k += KU) {
+    PT a[KU][NQ];
+#pragma unroll
+    for (int u = 0; u < KU; ++u)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        PT z{};
+        a[u][q] = (k + u < w && q < nq) ? ldp(base[q] + (int64_t)(k + u) * rows[q]) : z;
+      }
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      if (k + u >= w) break;
+      const double2 x = make_double2(bcast(v.x, k + u), bcast(v.y, k + u));
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) cfma(acc[q].x, acc[q].y, widen(a[u][q]), x);
+    }
+  }
+}
+
+template <class PT>
+__global__ __launch_bounds__(kWG) void fwd_sn_kernel(const SnJob* __restrict__ jobs, int njobs, Batch b,
+                                                     const double2* __restrict__ bin) {
+  const int lane = threadIdx.x & 63;
+  const double2* __restrict__ ub = reinterpret_cast<const double2*>(b.ubuf);
+  const int* __restrict__ fptr = b.fcon_ptr;
+  const int* __restrict__ fidx = b.fcon_idx;
+  // the job index is wave-uniform, so the job lives in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int j = blockIdx.x * 4 + wave; j < njobs; j += gridDim.x * 4) {
+    const SnJob jb = jobs[j];
+    const int m = jb.m, w = jb.w;
+    // inputs: restricted right-hand side minus the children's updates
+    double2 v = make_double2(0.0, 0.0);
+    if (lane < w) {
+      v = bin[b.bidx[jb.c0 + lane]];
+      const int fr = jb.frow0 + lane;
+      for (int e = fptr[fr]; e < fptr[fr + 1]; ++e) {
+        const double2 u = ub[fidx[e]];
+        v.x -= u.x;
+        v.y -= u.y;
+      }
+    }
+    const PT* __restrict__ P = reinterpret_cast<const PT*>(b.pf) + jb.off;
+    for (int q0 = 0; q0 * 64 < m; q0 += 4) {
+      const int nq = min(4, (m - q0 * 64 + 63) / 64);
+      int rows[4];
+      double2 acc[4];
+      // rows past the pivot block start from the children's updates
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        rows[q] = q < nq ? min(64, m - (q0 + q) * 64) : 0;
+        acc[q] = make_double2(0.0, 0.0);
+        const int row = (q0 + q) * 64 + lane;
+        if (q < nq && lane < rows[q] && row >= w) {
+          const int fr = jb.frow0 + row;
+          for (int e = fptr[fr]; e < fptr[fr + 1]; ++e) {
+            const double2 u = ub[fidx[e]];
+            acc[q].x += u.x;
+            acc[q].y += u.y;
+          }
+        }
+      }
+      const PT* Pq = P + (int64_t)q0 * 64 * w;
+      if (nq == 1)
+        sn_stream<PT, 1>(Pq, w, nq, rows, v, acc);
+      else if (nq == 2)
+        sn_stream<PT, 2>(Pq, w, nq, rows, v, acc);
+      else
+        sn_stream<PT, 4>(Pq, w, nq, rows, v, acc);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = (q0 + q) * 64 + lane;
+        if (q < nq && lane < rows[q]) {
+          if (row < w)
+            reinterpret_cast<double2*>(b.y)[jb.c0 + row] = acc[q];
+          else
+            reinterpret_cast<double2*>(b.ubuf)[jb.uoff + row - w] = acc[q];
+        }
+      }
+    }
+  }
+}
+
 // Whole forward + backward solve of a small batch (the coarse matrix) in one
 // cooperative launch: the workgroups sweep each level's tasks and meet at a
 // grid-wide barrier before the next level, instead of one launch per level.
@@ -888,6 +994,18 @@ void fwd_level(const Batch& b, int64_t task0, int64_t ntasks, const double* bin,
     level_go(fwd_level_kernel<float2, 0>, ntasks, lds, s, k, nt, b, in, chunk);
   else
     level_go(fwd_level_kernel<double2, 0>, ntasks, lds, s, k, nt, b, in, chunk);
+}
+
+void fwd_sn(const Batch& b, int64_t job0, int64_t njobs, const double* bin, hipStream_t s) {
+  if (njobs <= 0) return;
+  const SnJob* j = b.snj + job0;
+  const int nj = (int)njobs;
+  const double2* in = reinterpret_cast<const double2*>(bin);
+  const int64_t wgs = (njobs + 3) / 4;
+  if (b.c64)
+    level_go(fwd_sn_kernel<float2>, wgs, 0, s, j, nj, b, in);
+  else
+    level_go(fwd_sn_kernel<double2>, wgs, 0, s, j, nj, b, in);
 }
 
 void bwd_level(const Batch& b, int64_t task0, int64_t ntasks, int chunk, bool coarse, hipStream_t s) {

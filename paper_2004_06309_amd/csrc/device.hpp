@@ -28,6 +28,19 @@ struct Tile {
   int32_t aux;  // forward: its first front row in fcon_ptr; backward: offset of R_s in rows
 };
 
+// A supernode of at most 64 pivot columns whose forward panel is solved by
+// one wave: its 64-row tiles lie back to back from off (tile q at
+// off + 64 q w, the last one m - 64 q rows), each w columns wide.
+struct SnJob {
+  int64_t off;
+  int32_t m;      // front rows (w + |R_s|)
+  int32_t w;      // pivot columns (<= 64)
+  int32_t c0;     // first batch position
+  int32_t frow0;  // first front row in fcon_ptr
+  int32_t uoff;   // offset of its update vector in ubuf
+  int32_t tile;   // index of its first tile in the forward tile list
+};
+
 // A workgroup's share of a level: ntile consecutive tiles, each handled by
 // wpt waves (ntile * wpt <= 4).
 struct Task {
@@ -43,6 +56,7 @@ struct Batch {
   const Tile* tb = nullptr;        // backward tiles, grouped by level
   const Task* kf = nullptr;        // forward workgroup tasks, grouped by level
   const Task* kb = nullptr;        // backward workgroup tasks
+  const SnJob* snj = nullptr;      // one-wave forward supernodes, grouped by level
   const int32_t* sn_c0 = nullptr;  // first position of the supernode
   const int32_t* sn_w = nullptr;   // columns
   const int32_t* sn_uoff = nullptr;  // offset of its update vector in ubuf
@@ -69,6 +83,8 @@ struct Batch {
 void fwd_level(const Batch& b, int64_t task0, int64_t ntasks, const double* bin, int chunk, bool coarse,
                hipStream_t s);
 void bwd_level(const Batch& b, int64_t task0, int64_t ntasks, int chunk, bool coarse, hipStream_t s);
+// Forward solve of the one-wave supernodes [job0, job0 + njobs) of a level.
+void fwd_sn(const Batch& b, int64_t job0, int64_t njobs, const double* bin, hipStream_t s);
 // dst[to[t] + i] = src[from[t] + i] for i < words[t], t < ntiles (8-byte
 // words; device pointers): moves panel tiles into their solve order.
 void copy_tiles(const void* src, void* dst, const int64_t* from, const int64_t* to, const int64_t* words,

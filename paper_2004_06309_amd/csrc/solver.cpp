@@ -56,6 +56,7 @@ dev::Batch BatchDev::view() const {
   b.tb = tb.p;
   b.kf = kf.p;
   b.kb = kb.p;
+  b.snj = snj.p;
   b.c64 = c64;
   b.sn_r = sn_r.p;
   b.goff_f = goff_f.p;
@@ -122,7 +123,7 @@ Profiler::~Profiler() {
 // every forward (by height) and backward (by depth) level.  in_idx[i][l] is
 // the index in the solve's input vector of row l (original order) of matrix i.
 void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<const std::vector<int64_t>*>& in_idx,
-                  const std::vector<NumericOut>& num, BatchHost& B) {
+                  const std::vector<NumericOut>& num, int64_t sn_jobs_min, BatchHost& B) {
   const int nm = (int)Ss.size();
   B = BatchHost();
   std::vector<int64_t> pos0(nm + 1, 0), sn0(nm + 1, 0), pf0(nm + 1, 0), pb0(nm + 1, 0), u0(nm + 1, 0),
@@ -160,6 +161,7 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
   B.rows.resize(B.nu);
   B.bidx.assign(B.npos, 0);
   std::vector<std::vector<dev::Tile>> lf(maxlev_f + 1), lb(maxlev_b + 1);
+  std::vector<char> sn_narrow(nsn, 0);
   std::vector<int32_t> fcon_cnt(fr0[nm] + 1, 0);
   std::vector<std::vector<std::pair<int64_t, int32_t>>> fcon_m(nm);
   std::vector<TileShape> ts;
@@ -186,6 +188,7 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
         kinv[rho] = k;
         B.bidx[pos0[i] + c0 + k] = (int32_t)(*in_idx[i])[S.perm[rho]];
       }
+      sn_narrow[g] = sn_jobs_min >= 0 && w <= 64 && S.tile_rows == 64;
       tiles_fwd(w, r, S.tile_rows, ts);
       int64_t off = pf0[i] + S.sn_fwd_off[s];
       for (auto& t : ts) {
@@ -258,30 +261,64 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
     }
     return by;
   };
-  // workgroup tasks: tiles grouped by width class, 4 / wpt tiles per group
+  // workgroup tasks: tiles grouped by width class, 4 / wpt tiles per group.
+  // Forward tiles of narrow supernodes close their level, grouped by
+  // supernode (largest first) in row order, and also form one-wave jobs.
+  auto sn_entries = [&](int32_t s) { return (int64_t)(B.w[s] + r_of(s)) * B.w[s]; };
+  B.snj_lev.assign(1, 0);
   auto make_tasks = [&](std::vector<std::vector<dev::Tile>>& levels, bool fwd, std::vector<dev::Tile>& tiles,
                         std::vector<dev::Task>& tasks, std::vector<int64_t>& lev, std::vector<double>& bytes,
                         std::vector<double>& pbytes) {
     lev.assign(1, 0);
     for (auto& l : levels) {
+      // one-wave jobs only where a level has enough narrow supernodes to
+      // fill the device with waves (fewer, longer waves lose to tiles)
+      int64_t nnar = 0;
+      for (size_t u = 0; u < l.size(); ++u)
+        if (fwd && sn_narrow[l[u].sn] && (u == 0 || l[u - 1].sn != l[u].sn)) ++nnar;
+      const bool use_sn = nnar > 0 && nnar >= sn_jobs_min;
+      auto narrow = [&](const dev::Tile& t) { return use_sn && sn_narrow[t.sn]; };
       double pb = 0;
       bytes.push_back(level_bytes(l, fwd, pb));
       pbytes.push_back(pb);
       // widest class first, larger tiles first: the level's tail holds the
       // shortest workgroups
-      std::stable_sort(l.begin(), l.end(), [](const dev::Tile& a, const dev::Tile& b) {
+      std::stable_sort(l.begin(), l.end(), [&](const dev::Tile& a, const dev::Tile& b) {
+        const bool na = narrow(a), nb = narrow(b);
+        if (na != nb) return nb;
+        if (na) {
+          const int64_t ea = sn_entries(a.sn), eb = sn_entries(b.sn);
+          if (ea != eb) return ea > eb;
+          if (a.sn != b.sn) return a.sn < b.sn;
+          return a.row0 < b.row0;
+        }
         const int wa = dev::waves_per_tile(a.ncols), wb = dev::waves_per_tile(b.ncols);
         if (wa != wb) return wa > wb;
         return (int64_t)a.nrows * a.ncols > (int64_t)b.nrows * b.ncols;
       });
       size_t q = 0;
+      int64_t ktile = -1;
       while (q < l.size()) {
+        if (ktile < 0 && narrow(l[q])) ktile = (int64_t)tasks.size() - lev.back();
         const int wpt = dev::waves_per_tile(l[q].ncols);
         const int per = 4 / wpt;
         size_t e = q;
-        while (e < l.size() && (int)(e - q) < per && dev::waves_per_tile(l[e].ncols) == wpt) ++e;
+        while (e < l.size() && (int)(e - q) < per && dev::waves_per_tile(l[e].ncols) == wpt &&
+               narrow(l[e]) == narrow(l[q]))
+          ++e;
         tasks.push_back({(int32_t)(tiles.size() + q), (int16_t)(e - q), (int16_t)wpt});
         q = e;
+      }
+      if (fwd) {
+        B.ktile_f.push_back(ktile < 0 ? (int64_t)tasks.size() - lev.back() : ktile);
+        for (size_t u = 0; u < l.size(); ++u) {
+          const dev::Tile& t = l[u];
+          if (!narrow(t) || (u > 0 && l[u - 1].sn == t.sn)) continue;
+          const int32_t sn = t.sn;
+          B.snj.push_back({t.off, (int32_t)(B.w[sn] + r_of(sn)), B.w[sn], B.c0[sn], B.frow0[sn], B.uoff[sn],
+                           (int32_t)(tiles.size() + u)});
+        }
+        B.snj_lev.push_back((int64_t)B.snj.size());
       }
       tiles.insert(tiles.end(), l.begin(), l.end());
       lev.push_back((int64_t)tasks.size());
@@ -358,7 +395,8 @@ namespace {
 // taken as the identity).
 void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symbolic*>& Ss,
                  const std::vector<const std::vector<int64_t>*>& in_idx, int device, bool numeric, bool c64,
-                 bool on_host, BatchHost& B, BatchDev& Dv, int32_t& n_perturbed, double& seconds) {
+                 bool on_host, int64_t sn_jobs_min, BatchHost& B, BatchDev& Dv, int32_t& n_perturbed,
+                 double& seconds) {
   const int nm = (int)As.size();
   const size_t esz = c64 ? sizeof(std::complex<float>) : sizeof(cplx);
   Dv.c64 = c64 ? 1 : 0;
@@ -418,7 +456,9 @@ void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symb
     }
   }
   seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  layout_batch(Ss, in_idx, num, B);
+  // one-wave supernode jobs for complex128 panels (with complex64 panels
+  // the narrow tiles stream faster through the tile kernel)
+  layout_batch(Ss, in_idx, num, c64 ? -1 : sn_jobs_min, B);
   if (!numeric) return;
   // Panels move from factorisation order (per matrix, per supernode) to
   // solve order: each level's tiles contiguous, in the order its workgroups
@@ -452,12 +492,16 @@ void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symb
   };
   relayout(Dv.pf, B.tf);
   relayout(Dv.pb, B.tb);
+  for (auto& j : B.snj) j.off = B.tf[j.tile].off;
   Dv.npos = B.npos;
   Dv.lev_f = B.lev_f;
   Dv.lev_b = B.lev_b;
   Dv.chunk_f = B.chunk_f;
   Dv.chunk_b = B.chunk_b;
   Dv.nwide_f = B.nwide_f;
+  Dv.snj.upload(B.snj);
+  Dv.snj_lev = B.snj_lev;
+  Dv.ktile_f = B.ktile_f;
   Dv.nwide_b = B.nwide_b;
   Dv.gy_f = B.gy_f;
   Dv.gy_b = B.gy_b;
@@ -510,7 +554,8 @@ void batch_solve(const BatchDev& b, const double* in, hipStream_t s, Profiler* p
   const bool each = prof && prof->on && fine;
   for (size_t l = 0; l + 1 < b.lev_f.size(); ++l) {
     if (each) prof->begin(s);
-    dev::fwd_level(v, b.lev_f[l], b.lev_f[l + 1] - b.lev_f[l], in, b.chunk_f[l], !fine, s);
+    dev::fwd_level(v, b.lev_f[l], b.ktile_f[l], in, b.chunk_f[l], !fine, s);
+    dev::fwd_sn(v, b.snj_lev[l], b.snj_lev[l + 1] - b.snj_lev[l], in, s);
     if (each) prof->end(HELM_K_TRSV_FWD, b.bytes_f[l], s);
   }
   for (size_t l = 0; l + 1 < b.lev_b.size(); ++l) {
@@ -777,6 +822,7 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
   const int ctrows = opts && opts->coarse_tile_rows > 0 ? opts->coarse_tile_rows : 16;
   if (trows != 16 && trows != 32 && trows != 64) fail(HELM_EINVAL, "tile_rows must be 16, 32 or 64");
   if (ctrows != 16 && ctrows != 32 && ctrows != 64) fail(HELM_EINVAL, "coarse_tile_rows must be 16, 32 or 64");
+  const int64_t snmin = !opts || opts->sn_jobs_min == 0 ? 6144 : (opts->sn_jobs_min < 0 ? -1 : opts->sn_jobs_min);
 #pragma omp parallel for schedule(dynamic, 1)
   for (int32_t i = 0; i < n_sub; ++i) nested_dissection(c.subs[i].A, c.subs[i].coords, leaf, c.sym[i], trows);
   helm_precond_stats& st = c.stats;
@@ -796,7 +842,7 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
   const bool c64 = opts && opts->factor_c64;
   const bool on_host = opts && opts->factor_on_host;
   double fsec = 0, csec = 0;
-  build_batch(As, Ss, in, c.device, on_device, c64, on_host, fb, c.fine, npert, fsec);
+  build_batch(As, Ss, in, c.device, on_device, c64, on_host, snmin, fb, c.fine, npert, fsec);
   st.factor_entries = fb.nf + fb.nb;
   st.factor_c64 = c64 ? 1 : 0;
   st.levels_fwd = (int32_t)fb.lev_f.size() - 1;
@@ -844,7 +890,7 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
     std::iota(ident.begin(), ident.end(), 0);
     BatchHost cb;
     int32_t np2 = 0;
-    build_batch({&c.E}, {&c.Esym}, {&ident}, c.device, on_device, false, on_host, cb, c.coarse, np2, csec);
+    build_batch({&c.E}, {&c.Esym}, {&ident}, c.device, on_device, false, on_host, snmin, cb, c.coarse, np2, csec);
     npert += np2;
     c.two_level = true;
     st.n_coarse = (int32_t)c.E.n;

@@ -243,6 +243,40 @@ def test_tile_rows(tile_rows, coarse_tile_rows):
     say(f"[tiles] {tile_rows}/{coarse_tile_rows}: its={[i['iterations'] for i in info]}")
 
 
+@pytest.mark.parametrize("name", ["small_p2_2lvl", "mid_quarter_2lvl", "adapted_p2_2lvl"])
+def test_one_wave_supernode_jobs(name):
+    """Forward solves of narrow supernodes by one wave each (forced on every
+    level) against the tile kernel alone and against the oracle: local
+    solves, the two-level preconditioner, a single solve and a 16-column
+    block solve (which keeps the tile layout the jobs share)."""
+    w = WORKLOADS[name]()
+    P, b, M = opre.build(w)
+    hj = helm.from_workload(w, sn_jobs_min=1)
+    ht = helm.from_workload(w, sn_jobs_min=-1)
+    r = rand_vec(P.n, 31)
+    zj = torch.empty(P.n, dtype=torch.complex128, device=DEV)
+    zt = torch.empty_like(zj)
+    hj.apply_oras(dvec(r), zj)
+    ht.apply_oras(dvec(r), zt)
+    assert rel(host(zj), host(zt)) <= 1e-12
+    assert rel(host(zj), M.one_level(r)) <= 1e-9
+    hj.apply_precond(dvec(r), zj)
+    assert rel(host(zj), M.apply(r)) <= 1e-9
+    ro = opre.solve(P, b, M, tol=w.tol, restart=w.restart)
+    U = torch.zeros(P.n, dtype=torch.complex128, device=DEV)
+    rc, info = hj.solve(dvec(b), U, tol=w.tol, restart=w.restart)
+    u = host(U)
+    assert rc == helm.HELM_OK and abs(info[0]["iterations"] - ro.iterations) <= 2
+    assert np.linalg.norm(b - P.A @ u) / np.linalg.norm(b) <= w.tol
+    assert np.linalg.norm(u - ro.x) <= 1e-5 * np.linalg.norm(ro.x)
+    Bs = np.stack([b] * 16)
+    U16 = torch.zeros(16, P.n, dtype=torch.complex128, device=DEV)
+    rc, info16 = hj.solve(dvec(Bs), U16, tol=w.tol, restart=w.restart, block=16)
+    assert rc == helm.HELM_OK
+    assert np.linalg.norm(host(U16)[5] - ro.x) <= 1e-5 * np.linalg.norm(ro.x)
+    say(f"[snjobs] {name}: its={info[0]['iterations']} block={info16[5]['iterations']} oracle={ro.iterations}")
+
+
 @pytest.mark.parametrize("name", ["tiny", "ragged_p2", "mid_quarter_2lvl"])
 def test_device_factorisation_matches_host(name):
     """The numeric factorisation on the device (multifrontal, MFMA Schur
