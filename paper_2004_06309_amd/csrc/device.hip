@@ -74,8 +74,8 @@ __device__ __forceinline__ void tile_dot(const PT* __restrict__ p, int nr, const
 }
 
 // Lanes per tile row group: a tile with few rows spreads its columns over
-// 64 / R lane groups of R lanes (R >= nrows), so no lane idles.
-__device__ __forceinline__ int row_group(int nrows) { return nrows <= 16 ? 16 : (nrows <= 32 ? 32 : 64); }
+// 64 / R lane groups of R = nrows lanes (the last 64 mod R lanes idle).
+__device__ __forceinline__ int row_group(int nrows) { return nrows <= 32 ? max(nrows, 1) : 64; }
 
 // Work split of a workgroup (4 waves) over the tiles of its task.
 struct Split {
@@ -109,7 +109,7 @@ __device__ __forceinline__ void fwd_task(const Task& task, const Batch& b, const
   if (sp.has) t = b.tf[task.tile0 + sp.my];
   const int s = t.sn, c0 = t.c0, w = t.w, frow0 = t.aux;
   double2* vt = vin + sp.my * sp.region;
-  const int R = row_group(t.nrows), grp = lane / R, row_l = lane % R;
+  const int R = row_group(t.nrows), G = 64 / R, grp = lane / R, row_l = lane % R;
   const PT* __restrict__ P = reinterpret_cast<const PT*>(b.pf) + t.off + row_l;
   const double2* __restrict__ ub = reinterpret_cast<const double2*>(b.ubuf);
   // the children's updates to this lane's output row (rows past the pivot
@@ -146,10 +146,10 @@ __device__ __forceinline__ void fwd_task(const Task& task, const Batch& b, const
       vt[k] = v;
     }
     __syncthreads();
-    if (sp.has && row_l < t.nrows) {
+    if (sp.has && row_l < t.nrows && grp < G) {
       const int per = (cn + sp.wpt - 1) / sp.wpt;
       const int k0 = sp.part * per, k1 = min(cn, k0 + per);
-      tile_dot(P + (int64_t)cb * t.nrows, t.nrows, vt, k0 + grp, k1, 64 / R, ar, ai);
+      tile_dot(P + (int64_t)cb * t.nrows, t.nrows, vt, k0 + grp, k1, G, ar, ai);
     }
     __syncthreads();
   }
@@ -158,7 +158,7 @@ __device__ __forceinline__ void fwd_task(const Task& task, const Batch& b, const
   if (out) {
     double rr = 0, ii = 0;
     for (int q = 0; q < sp.wpt; ++q)
-      for (int g = lane; g < 64; g += R) {
+      for (int g = lane; g < G * R; g += R) {
         rr += red[wv + q][g].x;
         ii += red[wv + q][g].y;
       }
@@ -179,7 +179,7 @@ __device__ __forceinline__ void bwd_task(const Task& task, const Batch& b, doubl
   const int c0 = t.c0, w = t.w;
   const int64_t roff = t.aux;
   double2* vt = vin + sp.my * sp.region;
-  const int R = row_group(t.nrows), grp = lane / R, row_l = lane % R;
+  const int R = row_group(t.nrows), G = 64 / R, grp = lane / R, row_l = lane % R;
   const PT* __restrict__ P = reinterpret_cast<const PT*>(b.pb) + t.off + row_l;
   const double2* __restrict__ yv = reinterpret_cast<const double2*>(b.y);
   const double2* xv = reinterpret_cast<const double2*>(b.x);
@@ -193,10 +193,10 @@ __device__ __forceinline__ void bwd_task(const Task& task, const Batch& b, doubl
       vt[k] = c < w ? yv[c0 + c] : xv[b.rows[roff + (c - w)]];
     }
     __syncthreads();
-    if (sp.has && row_l < t.nrows) {
+    if (sp.has && row_l < t.nrows && grp < G) {
       const int per = (cn + sp.wpt - 1) / sp.wpt;
       const int k0 = sp.part * per, k1 = min(cn, k0 + per);
-      tile_dot(P + (int64_t)cb * t.nrows, t.nrows, vt, k0 + grp, k1, 64 / R, ar, ai);
+      tile_dot(P + (int64_t)cb * t.nrows, t.nrows, vt, k0 + grp, k1, G, ar, ai);
     }
     __syncthreads();
   }
@@ -205,7 +205,7 @@ __device__ __forceinline__ void bwd_task(const Task& task, const Batch& b, doubl
   if (sp.has && sp.part == 0 && lane < t.nrows) {
     double rr = 0, ii = 0;
     for (int q = 0; q < sp.wpt; ++q)
-      for (int g = lane; g < 64; g += R) {
+      for (int g = lane; g < G * R; g += R) {
         rr += red[wv + q][g].x;
         ii += red[wv + q][g].y;
       }
