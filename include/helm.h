@@ -224,9 +224,12 @@ int helm_coarse_get(const helm_ctx* ctx, int64_t* rowptr, int32_t* col, double* 
  * as timed at helm_assemble (default), 1 = CSR in dof order, 2 = sliced ELL
  * (64-row slices of rows taken in Morton order of the dof positions), 3 = CSR
  * with each XCD sweeping its own contiguous row range (ranges of equal entry
- * counts).  Kinds 1 and 3 also fix the order of the multi-right-hand-side
- * products (otherwise the faster one as timed on first use).  HELM_EINVAL for
- * any other kind. */
+ * counts), 4 = split CSR in dof order (real parts as real entries, nonzero
+ * imaginary parts as extra real entries flagged in the column index; A is
+ * complex only on the absorbing boundary, so 12 B per entry instead of 20).
+ * Kinds 1 and 3 also fix the order of the multi-right-hand-side products
+ * (otherwise the faster one as timed on first use).  HELM_EINVAL for any
+ * other kind. */
 int helm_set_spmv(helm_ctx* ctx, int kind);
 
 /* y = A x  (complex SpMV). */

@@ -237,7 +237,7 @@ int helm_set_spmv(helm_ctx* ctx, int kind) {
   return guarded(ctx, [&](Ctx& c) {
     need(c.device >= 0, HELM_ESTATE, "host-only context");
     need(c.assembled, HELM_ESTATE, "call helm_assemble first");
-    need(kind >= 0 && kind <= 3, HELM_EINVAL, "kind must be 0, 1, 2 or 3");
+    need(kind >= 0 && kind <= 4, HELM_EINVAL, "kind must be 0, 1, 2, 3 or 4");
     c.spmv_kind = kind == 0 ? c.spmv_auto : kind;
     c.blk_force = kind == 1 || kind == 3 ? kind : 0;
     return HELM_OK;

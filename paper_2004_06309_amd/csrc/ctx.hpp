@@ -176,7 +176,7 @@ struct Ctx {
   // lanes per row of the CSR SpMV of A (plain order, XCD row ranges) and
   // of Z^T / Z, picked by timing at setup
   int g_A = dev::spmv_cfg(8, 1), g_X = dev::spmv_cfg(8, 1), g_ZT = 4, g_Zp = 4;
-  int spmv_kind = 1;   // in use: 1 CSR, 2 sliced ELL, 3 CSR over XCD row ranges
+  int spmv_kind = 1;   // in use: 1 CSR, 2 sliced ELL, 3 CSR over XCD row ranges, 4 split CSR
   int spmv_auto = 1;   // the fastest at assembly
   bool blk_xcd = false;     // multi-vector SpMV over XCD row ranges (faster on first use)
   int blk_force = 0;        // 1 / 3: multi-vector SpMV order fixed by helm_set_spmv
@@ -189,6 +189,13 @@ struct Ctx {
   DVec<int64_t> A_ptr;
   DVec<int32_t> A_col;
   DVec<double> A_val;
+  // split storage of A: real parts, plus imaginary parts as extra entries
+  // flagged by bit 31 of the column index (only where they are nonzero)
+  DVec<int64_t> S_ptr;
+  DVec<int32_t> S_col;
+  DVec<double> S_val;
+  int64_t S_nnz = 0;
+  int g_S = 0;  // its tile shape
   BatchDev fine, coarse;
   DVec<int64_t> pro_ptr;   // prolongation: global dof -> (position, weight)
   DVec<int32_t> pro_idx;

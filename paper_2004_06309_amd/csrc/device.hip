@@ -385,9 +385,30 @@ __device__ __forceinline__ int64_t xcd_block() {
 // instead of one dependent col -> x chain per entry.  With kXcd, workgroup b
 // runs on XCD b % 8 (workgroups are dealt round-robin) and takes the
 // (b / 8)-th block of that XCD's row range [xr[b % 8], xr[b % 8 + 1]).
-template <int G, int U, bool kXcd>
+// Entries are complex (VT = double2), or real parts and imaginary parts
+// stored as separate real entries (VT = double): an imaginary entry carries
+// bit 31 in its column index and multiplies i x[col].  A of the Helmholtz
+// problem is complex only on the absorbing boundary, so the split storage
+// moves 12 B per entry instead of 20 B.
+template <class VT>
+__device__ __forceinline__ void spmv_fma(double& ar, double& ai, int c, VT v, const double2* __restrict__ x);
+template <>
+__device__ __forceinline__ void spmv_fma<double2>(double& ar, double& ai, int c, double2 v,
+                                                  const double2* __restrict__ x) {
+  cfma(ar, ai, v, x[c]);
+}
+template <>
+__device__ __forceinline__ void spmv_fma<double>(double& ar, double& ai, int c, double v,
+                                                 const double2* __restrict__ x) {
+  const double2 xv = x[c & 0x7fffffff];
+  const bool im = c < 0;  // i x = (-x.y, x.x)
+  ar = fma(v, im ? -xv.y : xv.x, ar);
+  ai = fma(v, im ? xv.x : xv.y, ai);
+}
+
+template <int G, int U, bool kXcd, class VT>
 __global__ __launch_bounds__(kWG) void spmv_kernel(int64_t n, const int64_t* __restrict__ ptr,
-                                                   const int32_t* __restrict__ col, const double2* __restrict__ val,
+                                                   const int32_t* __restrict__ col, const VT* __restrict__ val,
                                                    const int64_t* __restrict__ xr, const double2* __restrict__ x,
                                                    const double2* __restrict__ bvec, double2* __restrict__ y) {
   int64_t row, end = n;
@@ -403,14 +424,18 @@ __global__ __launch_bounds__(kWG) void spmv_kernel(int64_t n, const int64_t* __r
     const int64_t p1 = ptr[row + 1];
     for (int64_t base = ptr[row] + l; base < p1; base += G * U) {
       int c[U];
-      double2 v[U];
+      VT v[U];
+      bool ok[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) c[u] = base + u * G < p1 ? col[base + u * G] : -1;
+      for (int u = 0; u < U; ++u) {
+        ok[u] = base + u * G < p1;
+        c[u] = ok[u] ? col[base + u * G] : 0;
+      }
 #pragma unroll
-      for (int u = 0; u < U; ++u) v[u] = base + u * G < p1 ? val[base + u * G] : make_double2(0.0, 0.0);
+      for (int u = 0; u < U; ++u) v[u] = ok[u] ? val[base + u * G] : VT{};
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (c[u] >= 0) cfma(ar, ai, v[u], x[c[u]]);
+        if (ok[u]) spmv_fma<VT>(ar, ai, c[u], v[u], x);
     }
   }
 #pragma unroll
@@ -1038,27 +1063,27 @@ hipError_t batch_solve_coop(const Batch& b, const double* bin, const LevelRanges
                                     args, 0, s);
 }
 
-template <int G, int U, bool R>
-void spmv_go(int64_t n, const int64_t* ptr, const int32_t* col, const double2* v2, const int64_t* xr, int64_t xrows,
+template <int G, int U, bool R, class VT>
+void spmv_go(int64_t n, const int64_t* ptr, const int32_t* col, const VT* v2, const int64_t* xr, int64_t xrows,
              const double2* x2, const double2* b2, double2* y2, hipStream_t s) {
   // with R, 8 x the block count of the longest XCD range, else one block per kWG / G rows
   const unsigned grid = R ? 8 * blocks_for(xrows * G) : blocks_for(n * G);
-  spmv_kernel<G, U, R><<<grid, kWG, 0, s>>>(n, ptr, col, v2, xr, x2, b2, y2);
+  spmv_kernel<G, U, R, VT><<<grid, kWG, 0, s>>>(n, ptr, col, v2, xr, x2, b2, y2);
 }
 
-template <bool R>
-void spmv_launch(int64_t n, const int64_t* ptr, const int32_t* col, const double2* v2, const int64_t* xr,
+template <bool R, class VT>
+void spmv_launch(int64_t n, const int64_t* ptr, const int32_t* col, const VT* v2, const int64_t* xr,
                  int64_t xrows, const double2* x2, const double2* b2, double2* y2, int cfg, hipStream_t s) {
   switch (cfg) {
-    case spmv_cfg(4, 4): spmv_go<4, 4, R>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
-    case spmv_cfg(4, 8): spmv_go<4, 8, R>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
-    case spmv_cfg(8, 1): spmv_go<8, 1, R>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
-    case spmv_cfg(8, 2): spmv_go<8, 2, R>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
-    case spmv_cfg(8, 4): spmv_go<8, 4, R>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
-    case spmv_cfg(16, 1): spmv_go<16, 1, R>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
-    case spmv_cfg(16, 2): spmv_go<16, 2, R>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
-    case spmv_cfg(32, 1): spmv_go<32, 1, R>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
-    default: spmv_go<4, 1, R>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
+    case spmv_cfg(4, 4): spmv_go<4, 4, R, VT>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
+    case spmv_cfg(4, 8): spmv_go<4, 8, R, VT>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
+    case spmv_cfg(8, 1): spmv_go<8, 1, R, VT>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
+    case spmv_cfg(8, 2): spmv_go<8, 2, R, VT>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
+    case spmv_cfg(8, 4): spmv_go<8, 4, R, VT>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
+    case spmv_cfg(16, 1): spmv_go<16, 1, R, VT>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
+    case spmv_cfg(16, 2): spmv_go<16, 2, R, VT>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
+    case spmv_cfg(32, 1): spmv_go<32, 1, R, VT>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
+    default: spmv_go<4, 1, R, VT>(n, ptr, col, v2, xr, xrows, x2, b2, y2, s); break;
   }
 }
 
@@ -1083,9 +1108,16 @@ void spmv(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, 
   auto b2 = reinterpret_cast<const double2*>(b);
   auto y2 = reinterpret_cast<double2*>(y);
   if (xr)
-    spmv_launch<true>(n, ptr, col, v2, xr, xrows, x2, b2, y2, cfg, s);
+    spmv_launch<true, double2>(n, ptr, col, v2, xr, xrows, x2, b2, y2, cfg, s);
   else
-    spmv_launch<false>(n, ptr, col, v2, nullptr, 0, x2, b2, y2, cfg, s);
+    spmv_launch<false, double2>(n, ptr, col, v2, nullptr, 0, x2, b2, y2, cfg, s);
+}
+
+void spmv_split(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const double* x,
+                const double* b, double* y, int cfg, hipStream_t s) {
+  if (n <= 0) return;
+  spmv_launch<false, double>(n, ptr, col, val, nullptr, 0, reinterpret_cast<const double2*>(x),
+                             reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(y), cfg, s);
 }
 
 void sell_spmv(int64_t n, int64_t nslices, const int64_t* soff, const int32_t* swidth, const int32_t* perm,

@@ -143,6 +143,11 @@ constexpr int kSpmvCfgs[] = {spmv_cfg(4, 1),  spmv_cfg(4, 4),  spmv_cfg(4, 8),  
 // [xr[k], xr[k+1]) swept by XCD k; xrows = the longest range.
 void spmv(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const int64_t* xr, int64_t xrows,
           const double* x, const double* b, double* y, int cfg, hipStream_t s);
+// Same product from the split storage: real CSR entries, where an entry
+// with bit 31 set in its column index is an imaginary part (multiplies
+// i x[col & 0x7fffffff]).
+void spmv_split(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const double* x,
+                const double* b, double* y, int cfg, hipStream_t s);
 // Row ranges for the 8 XCDs holding equal numbers of CSR entries (host;
 // xr[0] = 0, xr[8] = n); returns the longest range.
 int64_t xcd_ranges(int64_t n, const int64_t* ptr, int64_t xr[9]);

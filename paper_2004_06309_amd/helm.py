@@ -262,8 +262,8 @@ class Helm:
     # ---- device operations (torch complex128 tensors) -----------------------
     def set_spmv(self, kind):
         """0: fastest storage as timed at assembly, 1: CSR, 2: sliced ELL in
-        Morton row order, 3: CSR with XCD row ranges (1 and 3 also fix the
-        multi-vector SpMV's order)."""
+        Morton row order, 3: CSR with XCD row ranges, 4: split real/imaginary
+        CSR (1 and 3 also fix the multi-vector SpMV's order)."""
         self._check(self.lib.helm_set_spmv(self.h, int(kind)))
 
     def apply_A(self, x, y, stream=None):

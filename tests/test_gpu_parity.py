@@ -75,14 +75,22 @@ def rand_vec(n, seed):
 
 
 def test_spmv_parity(pair):
-    """Every SpMV storage (CSR, sliced ELL, CSR over XCD row ranges) against the oracle's A."""
+    """Every SpMV storage (CSR, sliced ELL, CSR over XCD row ranges, split
+    real/imaginary CSR) against the oracle's A."""
     name, w, P, b, M, h = pair
     x = rand_vec(P.n, 1)
     y = torch.empty(P.n, dtype=torch.complex128, device=DEV)
-    for kind in (1, 2, 3, 0):
+    for kind in (1, 2, 3, 4, 0):
         h.set_spmv(kind)
         h.apply_A(dvec(x), y)
         assert rel(host(y), P.A @ x) <= 1e-13, kind
+    # residual form b - A x of the split storage, through a short solve
+    h.set_spmv(4)
+    U = torch.zeros(P.n, dtype=torch.complex128, device=DEV)
+    rc, info = h.solve(dvec(b), U, tol=1e-12, restart=5, maxit=8)
+    u = host(U)
+    h.set_spmv(0)
+    assert np.isclose(np.linalg.norm(b - P.A @ u) / np.linalg.norm(b), info[0]["relres"], rtol=1e-8)
 
 
 def test_oras_parity(pair):
