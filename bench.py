@@ -30,7 +30,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 # rocprofv3 FETCH_SIZE/WRITE_SIZE per dispatch, scaled by a device copy of
 # known size; valid only for the kernel sources they were measured on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mid_c128.json")
-TRAFFIC_KERNEL = {"trsv_fwd": ("fwd_level_kernel<double2, 0>",), "trsv_bwd": ("bwd_level_kernel<double2, 0>",),
+# what one timed launch of each profiled kernel class is
+LAUNCH_UNIT = {"trsv_fwd": "one level of the forward sweep over all 64 subdomains (fwd_level_kernel, plus "
+                           "fwd_sn_kernel on levels with one-wave supernode jobs)",
+               "trsv_bwd": "one level of the backward sweep over all 64 subdomains (bwd_level_kernel)"}
+TRAFFIC_KERNEL = {"trsv_fwd": ("trsv_fwd",), "trsv_bwd": ("bwd_level_kernel<double2, 0>",),
                   "spmv": ("spmv_kernel<", "sell_kernel")}
 
 
@@ -368,7 +372,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 counters, copy-calibrated)",
-                     "avg_launch_us": 1e3 * avg_ms, "avg_bytes_per_launch": avg_bytes},
+                     "avg_launch_us": 1e3 * avg_ms, "avg_bytes_per_launch": avg_bytes,
+                     "launch": LAUNCH_UNIT.get(dom, "one launch")},
         "kernels": kernels,
         "wall_s_timed": wall,
     }

@@ -2,12 +2,17 @@
 
     python -m paper_2004_06309_amd.rocprof_summary --trace DIR/mid_kernel_trace.csv \
         [--fetch DIR/mid_counter_collection.csv --write DIR/mid_counter_collection.csv \
-         --copy-fetch ... --copy-write ...] --out profiles/<name>.md --command "<cmd>"
+         --copy-fetch ... --copy-write ...] [--level-group NAME=K1,K2 --levels L] \
+        --out profiles/<name>.md --command "<cmd>"
 
 Kernel-trace statistics are grouped by kernel (template arguments kept, so
 fine and coarse level solves are separate rows).  With counter files, the
 per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) are scaled by what the same
 counters read for a device copy of known size, and averaged per dispatch.
+A level group sums kernels that share the levels of one sweep (the tile
+kernel and the one-wave supernode kernel of the forward sweep) and reports
+them per level: total time and bytes over (preconditioner applications x
+levels), an application being one launch of --per-apply.
 """
 from __future__ import annotations
 
@@ -32,7 +37,8 @@ def trace_stats(path):
     return d
 
 
-def counter_means(path, counter):
+def counter_sums(path, counter):
+    """kernel -> [dispatches, summed counter value]"""
     acc = collections.defaultdict(lambda: [0, 0.0])
     for r in csv.DictReader(open(path)):
         if r.get("Counter_Name") != counter:
@@ -40,7 +46,11 @@ def counter_means(path, counter):
         k = short_name(r["Kernel_Name"])
         acc[k][0] += 1
         acc[k][1] += float(r["Counter_Value"])
-    return {k: v[1] / v[0] for k, v in acc.items()}
+    return acc
+
+
+def counter_means(path, counter):
+    return {k: v[1] / v[0] for k, v in counter_sums(path, counter).items()}
 
 
 def main():
@@ -54,7 +64,16 @@ def main():
     ap.add_argument("--out", required=True)
     ap.add_argument("--command", required=True)
     ap.add_argument("--json-out")
+    ap.add_argument("--level-group", action="append", default=[],
+                    help="NAME=K1,K2: kernels sharing the levels of one sweep, reported per level")
+    ap.add_argument("--levels", type=int, default=0, help="levels per sweep (for --level-group)")
+    ap.add_argument("--per-apply", default="prolong_kernel",
+                    help="kernel launched once per preconditioner application")
     args = ap.parse_args()
+    groups = {}
+    for g in args.level_group:
+        name, ks = g.split("=", 1)
+        groups[name] = ks.split(",")
     st = trace_stats(args.trace)
     total = sum(sum(v) for v in st.values())
     lines = [f"# rocprofv3 kernel summary", "", f"Command: `{args.command}`", "",
@@ -63,6 +82,15 @@ def main():
         v = st[k]
         lines.append(f"| `{k}` | {len(v)} | {sum(v) / len(v) / 1e3:.1f} | {sum(v) / 1e6:.2f} | "
                      f"{100 * sum(v) / total:.1f}% |")
+    if groups and args.levels > 0:
+        applies = len(st.get(args.per_apply, []))
+        lines += ["", f"Per level of a sweep ({applies} preconditioner applications x {args.levels} levels):", "",
+                  "| group | kernels | level solves | avg us per level |", "|---|---|---|---|"]
+        for name, ks in groups.items():
+            t = sum(sum(st.get(k, [])) for k in ks)
+            n = applies * args.levels
+            lines.append(f"| {name} | {' + '.join('`' + k + '`' for k in ks)} | {n} | "
+                         f"{t / max(n, 1) / 1e3:.1f} |")
     out = {}
     if args.fetch and args.write and args.copy_fetch and args.copy_write:
         cf = max(counter_means(args.copy_fetch, "FETCH_SIZE").values())
@@ -79,6 +107,17 @@ def main():
             w = wr.get(k, 0.0) * 1024 * sw
             out[k] = {"fetch_bytes": f, "write_bytes": w}
             lines.append(f"| `{k}` | {f / 1e6:.2f} | {w / 1e6:.2f} |")
+        if groups and args.levels > 0:
+            fs = counter_sums(args.fetch, "FETCH_SIZE")
+            ws = counter_sums(args.write, "WRITE_SIZE")
+            lines += ["", "Per level of a sweep:", "", "| group | fetch MB | write MB |", "|---|---|---|"]
+            for name, ks in groups.items():
+                na = fs.get(args.per_apply, [0, 0.0])[0] * args.levels
+                nw = ws.get(args.per_apply, [0, 0.0])[0] * args.levels
+                f = sum(fs[k][1] for k in ks if k in fs) * 1024 * sf / max(na, 1)
+                w = sum(ws[k][1] for k in ks if k in ws) * 1024 * sw / max(nw, 1)
+                out[name] = {"fetch_bytes": f, "write_bytes": w}
+                lines.append(f"| {name} | {f / 1e6:.2f} | {w / 1e6:.2f} |")
         out["_scale"] = {"fetch": sf, "write": sw}
         import hashlib
         import os
