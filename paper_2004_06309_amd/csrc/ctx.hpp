@@ -175,7 +175,7 @@ struct Ctx {
   // device operators
   // lanes per row of the CSR SpMV of A (plain order, XCD row ranges) and
   // of Z^T / Z, picked by timing at setup
-  int g_A = dev::spmv_cfg(8, 1), g_X = dev::spmv_cfg(8, 1), g_ZT = 4, g_Zp = 4;
+  int g_A = dev::spmv_cfg(8, 1), g_X = dev::spmv_cfg(8, 1), g_ZT = 4, g_Zp = 4, g_AZ = 4;
   int spmv_kind = 1;   // in use: 1 CSR, 2 sliced ELL, 3 CSR over XCD row ranges, 4 split CSR
   int spmv_auto = 1;   // the fastest at assembly
   bool blk_xcd = false;     // multi-vector SpMV over XCD row ranges (faster on first use)
@@ -201,6 +201,11 @@ struct Ctx {
   DVec<int32_t> pro_idx;
   DVec<double> pro_w;
   DVec<int64_t> Zp_ptr, ZT_ptr;
+  // A Z (fine rows x coarse columns in the coarse solve's output order), split
+  // real/imaginary storage: t = r - A q becomes one pass with q = Z x_c
+  DVec<int64_t> AZ_ptr;
+  DVec<int32_t> AZ_col;
+  DVec<double> AZ_val;
   DVec<int32_t> Zp_col, ZT_col;
   DVec<double> Zp_val, ZT_val;
   // work vectors

@@ -523,6 +523,46 @@ __global__ __launch_bounds__(kWG) void spmv_real_kernel(int64_t n, const int64_t
   if (row < n && l == 0) y[row] = make_double2(ar, ai);
 }
 
+// Both fine-grid products of the coarse solution cx, row by row (G lanes
+// per row): q = Z cx (real Z) and t = r - (A Z) cx, A Z in split storage
+// (real entries; bit 31 of the column marks an imaginary part).
+template <int G>
+__global__ __launch_bounds__(kWG) void coarse_update_kernel(int64_t n, const int64_t* __restrict__ zptr,
+                                                            const int32_t* __restrict__ zcol,
+                                                            const double* __restrict__ zval,
+                                                            const int64_t* __restrict__ aptr,
+                                                            const int32_t* __restrict__ acol,
+                                                            const double* __restrict__ aval,
+                                                            const double2* __restrict__ cx,
+                                                            const double2* __restrict__ r, double2* __restrict__ q,
+                                                            double2* __restrict__ t) {
+  const int64_t row = ((int64_t)blockIdx.x * kWG + threadIdx.x) / G;
+  const int l = threadIdx.x % G;
+  double qr = 0, qi = 0, ar = 0, ai = 0;
+  if (row < n) {
+    const int64_t z1 = zptr[row + 1], a1 = aptr[row + 1];
+    for (int64_t p = zptr[row] + l; p < z1; p += G) {
+      const double z = zval[p];
+      const double2 v = cx[zcol[p]];
+      qr = fma(z, v.x, qr);
+      qi = fma(z, v.y, qi);
+    }
+    for (int64_t p = aptr[row] + l; p < a1; p += G) spmv_fma<double>(ar, ai, acol[p], aval[p], cx);
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    qr += __shfl_xor(qr, o, G);
+    qi += __shfl_xor(qi, o, G);
+    ar += __shfl_xor(ar, o, G);
+    ai += __shfl_xor(ai, o, G);
+  }
+  if (row < n && l == 0) {
+    q[row] = make_double2(qr, qi);
+    const double2 rr = r[row];
+    t[row] = make_double2(rr.x - ar, rr.y - ai);
+  }
+}
+
 __global__ __launch_bounds__(kWG) void prolong_kernel(int64_t n, const int64_t* __restrict__ ptr,
                                                       const int32_t* __restrict__ idx, const double* __restrict__ w,
                                                       const double2* __restrict__ xl, const double2* __restrict__ q,
@@ -1141,6 +1181,20 @@ void spmv_real(int64_t n, const int64_t* ptr, const int32_t* col, const double* 
     case 64: spmv_real_kernel<64><<<blocks_for(n * 64), kWG, 0, s>>>(n, ptr, col, val, x2, y2); break;
     default: spmv_real_kernel<4><<<blocks_for(n * 4), kWG, 0, s>>>(n, ptr, col, val, x2, y2); break;
   }
+}
+
+void coarse_update(int64_t n, const int64_t* zptr, const int32_t* zcol, const double* zval, const int64_t* aptr,
+                   const int32_t* acol, const double* aval, const double* cx, const double* r, double* q, double* t,
+                   int G, hipStream_t s) {
+  if (n <= 0) return;
+  auto c2 = reinterpret_cast<const double2*>(cx);
+  auto r2 = reinterpret_cast<const double2*>(r);
+  auto q2 = reinterpret_cast<double2*>(q);
+  auto t2 = reinterpret_cast<double2*>(t);
+  if (G == 8)
+    coarse_update_kernel<8><<<blocks_for(n * 8), kWG, 0, s>>>(n, zptr, zcol, zval, aptr, acol, aval, c2, r2, q2, t2);
+  else
+    coarse_update_kernel<4><<<blocks_for(n * 4), kWG, 0, s>>>(n, zptr, zcol, zval, aptr, acol, aval, c2, r2, q2, t2);
 }
 
 void prolong(int64_t n, const int64_t* ptr, const int32_t* idx, const double* w, const double* xl, const double* q,

@@ -157,6 +157,12 @@ void sell_spmv(int64_t n, int64_t nslices, const int64_t* soff, const int32_t* s
 // y = A x with a real CSR matrix and complex vectors; G lanes per row.
 void spmv_real(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const double* x, double* y,
                int G, hipStream_t s);
+// q = Z cx and t = r - (A Z) cx for a coarse solution cx (complex vectors):
+// Z real CSR, A Z in the split storage of spmv_split; G = 4 or 8 lanes per
+// row.
+void coarse_update(int64_t n, const int64_t* zptr, const int32_t* zcol, const double* zval, const int64_t* aptr,
+                   const int32_t* acol, const double* aval, const double* cx, const double* r, double* q, double* t,
+                   int G, hipStream_t s);
 // z[g] = sum_p w[p] xl[idx[p]] over p in [ptr[g], ptr[g+1]) (+ q[g] if q).
 void prolong(int64_t n, const int64_t* ptr, const int32_t* idx, const double* w, const double* xl, const double* q,
              double* z, hipStream_t s);

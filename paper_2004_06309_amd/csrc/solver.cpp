@@ -45,6 +45,9 @@ void Ctx::free_precond() {
   Zp_ptr.reset();
   Zp_col.reset();
   Zp_val.reset();
+  AZ_ptr.reset();
+  AZ_col.reset();
+  AZ_val.reset();
   ZT_ptr.reset();
   ZT_col.reset();
   ZT_val.reset();
@@ -947,6 +950,63 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
       c.Zp_ptr.upload(Zp.ptr);
       c.Zp_col.upload(Zp.col);
       c.Zp_val.upload(Zp.val);
+      {
+        // (A Z)_ik = sum_j A_ij Z_jk, row by row; real parts, then the
+        // nonzero imaginary parts flagged in the column index
+        const Csr& A = c.D.A;
+        const int64_t n = A.n, nc = c.E.n, blk = 4096, nblk = (n + blk - 1) / blk;
+        std::vector<std::vector<int64_t>> bp(nblk);
+        std::vector<std::vector<int32_t>> bc(nblk);
+        std::vector<std::vector<double>> bv(nblk);
+#pragma omp parallel
+        {
+          std::vector<cplx> acc(nc);
+          std::vector<char> seen(nc, 0);
+          std::vector<int32_t> touched;
+#pragma omp for schedule(dynamic, 1)
+          for (int64_t b = 0; b < nblk; ++b) {
+            for (int64_t i = b * blk; i < std::min(n, (b + 1) * blk); ++i) {
+              touched.clear();
+              for (int64_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
+                const int64_t j = A.col[p];
+                for (int64_t q = Zp.ptr[j]; q < Zp.ptr[j + 1]; ++q) {
+                  const int32_t k = Zp.col[q];
+                  if (!seen[k]) {
+                    seen[k] = 1;
+                    acc[k] = cplx(0, 0);
+                    touched.push_back(k);
+                  }
+                  acc[k] += A.val[p] * Zp.val[q];
+                }
+              }
+              std::sort(touched.begin(), touched.end());
+              for (int32_t k : touched) {
+                bc[b].push_back(k);
+                bv[b].push_back(acc[k].real());
+              }
+              for (int32_t k : touched)
+                if (acc[k].imag() != 0.0) {
+                  bc[b].push_back((int32_t)((uint32_t)k | 0x80000000u));
+                  bv[b].push_back(acc[k].imag());
+                }
+              for (int32_t k : touched) seen[k] = 0;
+              bp[b].push_back((int64_t)bc[b].size());
+            }
+          }
+        }
+        std::vector<int64_t> ap(1, 0);
+        std::vector<int32_t> acol;
+        std::vector<double> aval;
+        for (int64_t b = 0; b < nblk; ++b) {
+          const int64_t base = (int64_t)acol.size();
+          for (int64_t e : bp[b]) ap.push_back(base + e);
+          acol.insert(acol.end(), bc[b].begin(), bc[b].end());
+          aval.insert(aval.end(), bv[b].begin(), bv[b].end());
+        }
+        c.AZ_ptr.upload(ap);
+        c.AZ_col.upload(acol);
+        c.AZ_val.upload(aval);
+      }
       c.ZT_ptr.upload(c.ZT.ptr);
       c.ZT_col.upload(c.ZT.col);
       c.ZT_val.upload(c.ZT.val);
@@ -960,6 +1020,12 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
       });
       c.g_Zp = pick_lanes_per_row({4, 8}, [&](int G) {
         dev::spmv_real(c.D.n, c.Zp_ptr.p, c.Zp_col.p, c.Zp_val.p, x.p, y.p, G, nullptr);
+      });
+      DVec<double> x2;
+      x2.alloc(2 * c.D.n);
+      c.g_AZ = pick_lanes_per_row({4, 8}, [&](int G) {
+        dev::coarse_update(c.D.n, c.Zp_ptr.p, c.Zp_col.p, c.Zp_val.p, c.AZ_ptr.p, c.AZ_col.p, c.AZ_val.p, x.p, x.p,
+                           y.p, x2.p, G, nullptr);
       });
       choose_coarse_launch(c);
       st.coarse_grid = c.coarse.coop;
@@ -1016,11 +1082,18 @@ void apply_oras(Ctx& c, const double* r, double* z, const double* q, hipStream_t
 // and t, so a solver may enqueue it ahead of a decision it has not taken yet.
 void precond_stage1(Ctx& c, const double* r, hipStream_t s) {
   if (!c.two_level) return;
-  apply_coarse(c, r, c.q.p, s);
+  // q = Z E^{-1} Z^T r and t = r - A q = r - (A Z) E^{-1} Z^T r
   const bool p = c.prof.on;
   if (p) c.prof.begin(s);
-  spmv_A(c, c.q.p, r, c.t.p, s);  // t = r - A q
-  if (p) c.prof.end(HELM_K_SPMV, spmv_bytes(c, true), s);
+  dev::spmv_real(c.ZT.n, c.ZT_ptr.p, c.ZT_col.p, c.ZT_val.p, r, c.cvec.p, c.g_ZT, s);
+  batch_solve(c.coarse, c.cvec.p, s, &c.prof, false);
+  dev::coarse_update(c.D.n, c.Zp_ptr.p, c.Zp_col.p, c.Zp_val.p, c.AZ_ptr.p, c.AZ_col.p, c.AZ_val.p, c.coarse.x.p, r,
+                     c.q.p, c.t.p, c.g_AZ, s);
+  if (p) {
+    const double zb = 12.0 * (double)c.Z.col.size() + 8.0 * c.E.n + 16.0 * (c.D.n + c.E.n);
+    const double ub = 12.0 * (double)(c.Z.col.size() + c.AZ_col.n) + 16.0 * (double)c.D.n + 48.0 * c.D.n;
+    c.prof.end(HELM_K_COARSE, zb + ub + sum(c.coarse.bytes_f) + sum(c.coarse.bytes_b), s);
+  }
 }
 void precond_stage2(Ctx& c, const double* r, double* z, hipStream_t s) {
   if (!c.two_level)

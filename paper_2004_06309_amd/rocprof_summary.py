@@ -2,7 +2,7 @@
 
     python -m paper_2004_06309_amd.rocprof_summary --trace DIR/mid_kernel_trace.csv \
         [--fetch DIR/mid_counter_collection.csv --write DIR/mid_counter_collection.csv \
-         --copy-fetch ... --copy-write ...] [--level-group NAME=K1,K2 --levels L] \
+         --copy-fetch ... --copy-write ...] [--level-group NAME=K1+K2 --levels L] \
         --out profiles/<name>.md --command "<cmd>"
 
 Kernel-trace statistics are grouped by kernel (template arguments kept, so
@@ -27,7 +27,7 @@ def short_name(name: str) -> str:
     n = name.replace("(anonymous namespace)::", "")
     n = re.sub(r"HIP_vector_type<(\w+), 2u>", r"\g<1>2", n)
     m = re.match(r"(?:void )?(?:[\w:]+::)?(\w+(?:<[^()]*>)?)\(", n)
-    return m.group(1) if m else n[:60]
+    return re.sub(r"\s+>", ">", m.group(1)) if m else n[:60]
 
 
 def trace_stats(path):
@@ -65,7 +65,7 @@ def main():
     ap.add_argument("--command", required=True)
     ap.add_argument("--json-out")
     ap.add_argument("--level-group", action="append", default=[],
-                    help="NAME=K1,K2: kernels sharing the levels of one sweep, reported per level")
+                    help="NAME=K1+K2: kernels sharing the levels of one sweep, reported per level")
     ap.add_argument("--levels", type=int, default=0, help="levels per sweep (for --level-group)")
     ap.add_argument("--per-apply", default="prolong_kernel",
                     help="kernel launched once per preconditioner application")
@@ -73,7 +73,7 @@ def main():
     groups = {}
     for g in args.level_group:
         name, ks = g.split("=", 1)
-        groups[name] = ks.split(",")
+        groups[name] = [k.strip() for k in ks.split("+")]
     st = trace_stats(args.trace)
     total = sum(sum(v) for v in st.values())
     lines = [f"# rocprofv3 kernel summary", "", f"Command: `{args.command}`", "",
