@@ -163,6 +163,10 @@ void spmv_real(int64_t n, const int64_t* ptr, const int32_t* col, const double* 
 void coarse_update(int64_t n, const int64_t* zptr, const int32_t* zcol, const double* zval, const int64_t* aptr,
                    const int32_t* acol, const double* aval, const double* cx, const double* r, double* q, double* t,
                    int G, hipStream_t s);
+// coarse_update for S interleaved right-hand sides (device_block.hip).
+void coarse_update_block(int64_t n, const int64_t* zptr, const int32_t* zcol, const double* zval,
+                         const int64_t* aptr, const int32_t* acol, const double* aval, int S, const double* cx,
+                         const double* x, double* q, double* t, hipStream_t s);
 // z[g] = sum_p w[p] xl[idx[p]] over p in [ptr[g], ptr[g+1]) (+ q[g] if q).
 void prolong(int64_t n, const int64_t* ptr, const int32_t* idx, const double* w, const double* xl, const double* q,
              double* z, hipStream_t s);

@@ -638,6 +638,37 @@ __global__ __launch_bounds__(kWG) void spmv_real_block_kernel(int64_t n, const i
   y[e] = make_double2(ar, ai);
 }
 
+// q = Z cx and t = x - (A Z) cx for S interleaved right-hand sides (A Z in
+// split storage: bit 31 of a column marks an imaginary part).
+template <int S>
+__global__ __launch_bounds__(kWG) void coarse_update_block_kernel(
+    int64_t n, const int64_t* __restrict__ zptr, const int32_t* __restrict__ zcol, const double* __restrict__ zval,
+    const int64_t* __restrict__ aptr, const int32_t* __restrict__ acol, const double* __restrict__ aval,
+    const double2* __restrict__ cx, const double2* __restrict__ x, double2* __restrict__ q, double2* __restrict__ t) {
+  const int64_t e = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (e >= n * S) return;
+  const int64_t row = e / S;
+  const int r = (int)(e % S);
+  double qr = 0, qi = 0, ar = 0, ai = 0;
+  for (int64_t p = zptr[row]; p < zptr[row + 1]; ++p) {
+    const double z = zval[p];
+    const double2 v = cx[(int64_t)zcol[p] * S + r];
+    qr = fma(z, v.x, qr);
+    qi = fma(z, v.y, qi);
+  }
+  for (int64_t p = aptr[row]; p < aptr[row + 1]; ++p) {
+    const int c = acol[p];
+    const double a = aval[p];
+    const double2 v = cx[(int64_t)(c & 0x7fffffff) * S + r];
+    const bool im = c < 0;  // i v = (-v.y, v.x)
+    ar = fma(a, im ? -v.y : v.x, ar);
+    ai = fma(a, im ? v.x : v.y, ai);
+  }
+  q[e] = make_double2(qr, qi);
+  const double2 xx = x[e];
+  t[e] = make_double2(xx.x - ar, xx.y - ai);
+}
+
 template <int S>
 __global__ __launch_bounds__(kWG) void prolong_block_kernel(int64_t n, const int64_t* __restrict__ ptr,
                                                             const int32_t* __restrict__ idx,
@@ -845,6 +876,18 @@ void spmv_real_block(int64_t n, const int64_t* ptr, const int32_t* col, const do
     constexpr int W = decltype(w)::value;
     spmv_real_block_kernel<W><<<blocks_for(n * W), kWG, 0, s>>>(n, ptr, col, val, reinterpret_cast<const double2*>(x),
                                                                  reinterpret_cast<double2*>(y));
+  });
+}
+
+void coarse_update_block(int64_t n, const int64_t* zptr, const int32_t* zcol, const double* zval,
+                         const int64_t* aptr, const int32_t* acol, const double* aval, int S, const double* cx,
+                         const double* x, double* q, double* t, hipStream_t s) {
+  if (n <= 0) return;
+  with_width(S, [&](auto w) {
+    constexpr int W = decltype(w)::value;
+    coarse_update_block_kernel<W><<<blocks_for(n * W), kWG, 0, s>>>(
+        n, zptr, zcol, zval, aptr, acol, aval, reinterpret_cast<const double2*>(cx),
+        reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(q), reinterpret_cast<double2*>(t));
   });
 }
 

@@ -1451,11 +1451,10 @@ void apply_precond_block(Ctx& c, int S, const double* X, double* Z, hipStream_t 
     if (p) c.prof.begin(s);
     dev::spmv_real_block(c.ZT.n, c.ZT_ptr.p, c.ZT_col.p, c.ZT_val.p, S, X, c.bcvec.p, s);
     batch_solve_block(c.coarse, S, c.bcvec.p, s, &c.prof, false);
-    dev::spmv_real_block(n, c.Zp_ptr.p, c.Zp_col.p, c.Zp_val.p, S, c.coarse.x_b.p, c.bq.p, s);
+    // q = Z x_c, t = x - (A Z) x_c
+    dev::coarse_update_block(n, c.Zp_ptr.p, c.Zp_col.p, c.Zp_val.p, c.AZ_ptr.p, c.AZ_col.p, c.AZ_val.p, S,
+                             c.coarse.x_b.p, X, c.bq.p, c.bt.p, s);
     if (p) c.prof.end(HELM_K_COARSE, 0.0, s);
-    if (p) c.prof.begin(s);
-    spmv_block(c, S, c.bq.p, X, c.bt.p, s);  // t = x - A q
-    if (p) c.prof.end(HELM_K_SPMV, 0.0, s);
     batch_solve_block(c.fine, S, c.bt.p, s, &c.prof, true);
   } else {
     batch_solve_block(c.fine, S, X, s, &c.prof, true);
