@@ -731,35 +731,22 @@ __global__ __launch_bounds__(kWG) void gs_pass_kernel(int64_t n, PtrSetC Vs, int
 // Delayed CGS2 (two passes over V per Arnoldi step instead of three): the
 // last column v_j of V (ncol = j + 1 columns) was orthogonalised once when it
 // was made; its second pass is folded into the next step.
-//   pass A (kUpdate = false): partial dots V^H w (ncol entries) and V^H v_j
-//     (ncol more, the last being |v_j|^2) of every 64-row tile;
-//   pass B (kUpdate = true): v_j <- (v_j - V_{<j} cv) * cv[j].x and
-//     w <- w - V_{<j} cw - v_j(old) cw[j], written back, plus the partial
-//     squared norms of the new w (partial[blk].x).
-template <bool kUpdate>
-__global__ __launch_bounds__(kWG) void gs_dual_kernel(int64_t n, PtrSetC Vs, PtrSet Vw, int64_t ld, int ncol,
-                                                      PtrSetC cws, PtrSetC cvs, PtrSet ws, PtrSet parts) {
+// Pass A: partial dots V^H w (ncol entries) and V^H v_j (ncol more, the last
+// being |v_j|^2) of every 64-row tile, staged through LDS so lane k of each
+// wave sums column k over a quarter of the tile's rows;
+// partial[blk * 2 ncol + k] and partial[blk * 2 ncol + ncol + k].
+__global__ __launch_bounds__(kWG) void gs_dots_kernel(int64_t n, PtrSetC Vs, int64_t ld, int ncol, PtrSet ws,
+                                                      PtrSet parts) {
   const double2* __restrict__ V = reinterpret_cast<const double2*>(Vs.p[blockIdx.y]);
-  double2* __restrict__ w = reinterpret_cast<double2*>(ws.p[blockIdx.y]);
+  const double2* __restrict__ w = reinterpret_cast<const double2*>(ws.p[blockIdx.y]);
   double2* __restrict__ partial = reinterpret_cast<double2*>(parts.p[blockIdx.y]);
   extern __shared__ double2 lds[];
   double2 (*tile)[kGsRows + 1] = reinterpret_cast<double2 (*)[kGsRows + 1]>(lds);
-  double2* cw = lds + (size_t)ncol * (kGsRows + 1);
-  double2* cv = cw + kGsMaxCols;
-  double2* wn = cv + kGsMaxCols;
-  // the update sums (pass B) and the dot sums (pass A) share their space
-  double2* ured = wn + kGsRows;          // [4][kGsRows]
-  double2* vred = ured + 4 * kGsRows;    // [4][kGsRows]
-  double2* dred = wn + kGsRows;          // [4][kGsMaxCols]
-  double2* ered = dred + 4 * kGsMaxCols; // [4][kGsMaxCols]
-  double* red = reinterpret_cast<double*>(wn + kGsRows + 8 * kGsMaxCols);
+  double2* wn = lds + (size_t)ncol * (kGsRows + 1);
+  double2* dred = wn + kGsRows;           // [4][kGsMaxCols]
+  double2* ered = dred + 4 * kGsMaxCols;  // [4][kGsMaxCols]
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, j = ncol - 1;
-  if (kUpdate && tid < ncol) {
-    cw[tid] = reinterpret_cast<const double2*>(cws.p[blockIdx.y])[tid];
-    cv[tid] = reinterpret_cast<const double2*>(cvs.p[blockIdx.y])[tid];
-  }
   double dr = 0, di = 0, er = 0, ei = 0;  // dots of column `lane` with w and with v_j
-  double nrm = 0;
   const int64_t ntiles = (n + kGsRows - 1) / kGsRows;
   constexpr int kU = kGsMaxCols / 4;
   double2 a[kU];
@@ -776,86 +763,99 @@ __global__ __launch_bounds__(kWG) void gs_dual_kernel(int64_t n, PtrSetC Vs, Ptr
   };
   load_next(blockIdx.x);
   for (int64_t tb = blockIdx.x; tb < ntiles; tb += gridDim.x) {
-    const int64_t i = tb * kGsRows + lane;
-    const bool valid = i < n;
 #pragma unroll
     for (int u = 0; u < kU; ++u)
       if (wv + 4 * u < ncol) tile[wv + 4 * u][lane] = a[u];
-    const double2 wcur = wnext;
+    if (tid < kGsRows) wn[tid] = wnext;
     __syncthreads();
     load_next(tb + gridDim.x);
-    if (kUpdate) {
-      double ur = 0, ui = 0, vr = 0, vi = 0;
-      for (int k = wv; k < j; k += 4) {
-        cfma(ur, ui, tile[k][lane], cw[k]);
-        cfma(vr, vi, tile[k][lane], cv[k]);
-      }
-      ured[wv * kGsRows + lane] = make_double2(ur, ui);
-      vred[wv * kGsRows + lane] = make_double2(vr, vi);
-      __syncthreads();
-      if (tid < kGsRows) {
-        double2 wi = wcur;
-        const double2 vo = tile[j][tid];
-        double2 vn = vo;
-        for (int q = 0; q < 4; ++q) {
-          wi.x -= ured[q * kGsRows + tid].x;
-          wi.y -= ured[q * kGsRows + tid].y;
-          vn.x -= vred[q * kGsRows + tid].x;
-          vn.y -= vred[q * kGsRows + tid].y;
-        }
-        const double ia = cv[j].x, dxr = cw[j].x, dxi = cw[j].y;
-        wi.x -= vo.x * dxr - vo.y * dxi;
-        wi.y -= vo.x * dxi + vo.y * dxr;
-        if (valid) {
-          w[i] = wi;
-          reinterpret_cast<double2*>(Vw.p[blockIdx.y])[(int64_t)j * ld + i] = make_double2(vn.x * ia, vn.y * ia);
-        }
-        nrm = fma(wi.x, wi.x, fma(wi.y, wi.y, nrm));
-      }
-    } else {
-      if (tid < kGsRows) wn[tid] = wcur;
-      __syncthreads();
-      if (lane < ncol) {
-        for (int r = wv * 16; r < wv * 16 + 16; ++r) {
-          const double2 v = tile[lane][r], x = wn[r], y = tile[j][r];
-          dr = fma(v.x, x.x, dr);
-          dr = fma(v.y, x.y, dr);
-          di = fma(v.x, x.y, di);
-          di = fma(-v.y, x.x, di);
-          er = fma(v.x, y.x, er);
-          er = fma(v.y, y.y, er);
-          ei = fma(v.x, y.y, ei);
-          ei = fma(-v.y, y.x, ei);
-        }
+    if (lane < ncol) {
+      for (int r = wv * 16; r < wv * 16 + 16; ++r) {
+        const double2 v = tile[lane][r], x = wn[r], y = tile[j][r];
+        dr = fma(v.x, x.x, dr);
+        dr = fma(v.y, x.y, dr);
+        di = fma(v.x, x.y, di);
+        di = fma(-v.y, x.x, di);
+        er = fma(v.x, y.x, er);
+        er = fma(v.y, y.y, er);
+        ei = fma(v.x, y.y, ei);
+        ei = fma(-v.y, y.x, ei);
       }
     }
     __syncthreads();  // the next tile overwrites tile and wn
   }
-  if (!kUpdate) {
-    if (lane < ncol) {
-      dred[wv * kGsMaxCols + lane] = make_double2(dr, di);
-      ered[wv * kGsMaxCols + lane] = make_double2(er, ei);
+  if (lane < ncol) {
+    dred[wv * kGsMaxCols + lane] = make_double2(dr, di);
+    ered[wv * kGsMaxCols + lane] = make_double2(er, ei);
+  }
+  __syncthreads();
+  if (tid < ncol) {
+    double ar = 0, ai = 0, br = 0, bi = 0;
+    for (int q = 0; q < 4; ++q) {
+      ar += dred[q * kGsMaxCols + tid].x;
+      ai += dred[q * kGsMaxCols + tid].y;
+      br += ered[q * kGsMaxCols + tid].x;
+      bi += ered[q * kGsMaxCols + tid].y;
     }
-    __syncthreads();
-    if (tid < ncol) {
-      double ar = 0, ai = 0, br = 0, bi = 0;
-      for (int q = 0; q < 4; ++q) {
-        ar += dred[q * kGsMaxCols + tid].x;
-        ai += dred[q * kGsMaxCols + tid].y;
-        br += ered[q * kGsMaxCols + tid].x;
-        bi += ered[q * kGsMaxCols + tid].y;
+    partial[(int64_t)blockIdx.x * 2 * ncol + tid] = make_double2(ar, ai);
+    partial[(int64_t)blockIdx.x * 2 * ncol + ncol + tid] = make_double2(br, bi);
+  }
+}
+
+// Pass B of delayed CGS2 with one row per thread (no staging: every row
+// needs all ncol columns, and the coefficients are shared by all rows):
+// v_j <- (v_j - V_{<j} cv) * cv[j].x, w <- w - V_{<j} cw - v_j(old) cw[j],
+// partial squared norms of the new w in partial[blockIdx.x].x.
+__global__ __launch_bounds__(kWG) void gs_update_rows_kernel(int64_t n, PtrSetC Vs, PtrSet Vw, int64_t ld, int ncol,
+                                                             PtrSetC cws, PtrSetC cvs, PtrSet ws, PtrSet parts) {
+  const double2* __restrict__ V = reinterpret_cast<const double2*>(Vs.p[blockIdx.y]);
+  double2* __restrict__ vw = reinterpret_cast<double2*>(Vw.p[blockIdx.y]);
+  double2* __restrict__ w = reinterpret_cast<double2*>(ws.p[blockIdx.y]);
+  double2* __restrict__ partial = reinterpret_cast<double2*>(parts.p[blockIdx.y]);
+  __shared__ double2 cw[kGsMaxCols], cv[kGsMaxCols];
+  __shared__ double red[kWG / 64];
+  const int tid = threadIdx.x, j = ncol - 1;
+  if (tid < ncol) {
+    cw[tid] = reinterpret_cast<const double2*>(cws.p[blockIdx.y])[tid];
+    cv[tid] = reinterpret_cast<const double2*>(cvs.p[blockIdx.y])[tid];
+  }
+  __syncthreads();
+  double nrm = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kWG + tid; i < n; i += (int64_t)gridDim.x * kWG) {
+    double ur = 0, ui = 0, vr = 0, vi = 0;
+    int k = 0;
+    for (; k + 8 <= j; k += 8) {
+      double2 a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = V[(int64_t)(k + u) * ld + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        cfma(ur, ui, a[u], cw[k + u]);
+        cfma(vr, vi, a[u], cv[k + u]);
       }
-      partial[(int64_t)blockIdx.x * 2 * ncol + tid] = make_double2(ar, ai);
-      partial[(int64_t)blockIdx.x * 2 * ncol + ncol + tid] = make_double2(br, bi);
     }
-  } else {
-    if (tid < kGsRows) red[tid] = nrm;
-    __syncthreads();
-    if (tid == 0) {
-      double sum = 0;
-      for (int r = 0; r < kGsRows; ++r) sum += red[r];
-      partial[blockIdx.x] = make_double2(sum, 0.0);
+    for (; k < j; ++k) {
+      const double2 a = V[(int64_t)k * ld + i];
+      cfma(ur, ui, a, cw[k]);
+      cfma(vr, vi, a, cv[k]);
     }
+    const double2 vo = V[(int64_t)j * ld + i];
+    double2 wi = w[i];
+    const double2 dj = cw[j];
+    const double ia = cv[j].x;
+    wi.x -= ur + (vo.x * dj.x - vo.y * dj.y);
+    wi.y -= ui + (vo.x * dj.y + vo.y * dj.x);
+    w[i] = wi;
+    vw[(int64_t)j * ld + i] = make_double2((vo.x - vr) * ia, (vo.y - vi) * ia);
+    nrm = fma(wi.x, wi.x, fma(wi.y, wi.y, nrm));
+  }
+  for (int o = 32; o > 0; o >>= 1) nrm += __shfl_xor(nrm, o, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = nrm;
+  __syncthreads();
+  if (tid == 0) {
+    double sum = 0;
+    for (int q = 0; q < kWG / 64; ++q) sum += red[q];
+    partial[blockIdx.x] = make_double2(sum, 0.0);
   }
 }
 
@@ -1238,13 +1238,11 @@ void gs_pass(int mode, int nr, int64_t n, const PtrSetC& V, int64_t ld, int ncol
 void gs_dual(bool update, int nr, int64_t n, const PtrSetC& V, const PtrSet& Vw, int64_t ld, int ncol,
              const PtrSetC& cw, const PtrSetC& cv, const PtrSet& w, const PtrSet& partial, hipStream_t s) {
   const dim3 grid((unsigned)gs_tiles(n), (unsigned)nr);
-  static_assert(kGsRows == kGsMaxCols, "the shared sum space assumes equal row and column counts");
-  const size_t lds = sizeof(double2) * ((size_t)ncol * (kGsRows + 1) + 2 * kGsMaxCols + kGsRows + 8 * kGsMaxCols) +
-                     sizeof(double) * kGsRows;
+  const size_t lds = sizeof(double2) * ((size_t)ncol * (kGsRows + 1) + kGsRows + 8 * kGsMaxCols);
   if (update)
-    gs_dual_kernel<true><<<grid, kWG, lds, s>>>(n, V, Vw, ld, ncol, cw, cv, w, partial);
+    gs_update_rows_kernel<<<grid, kWG, 0, s>>>(n, V, Vw, ld, ncol, cw, cv, w, partial);
   else
-    gs_dual_kernel<false><<<grid, kWG, lds, s>>>(n, V, Vw, ld, ncol, cw, cv, w, partial);
+    gs_dots_kernel<<<grid, kWG, lds, s>>>(n, V, ld, ncol, w, partial);
 }
 void dcgs2_coef(int nr, const PtrSetC& dots, int ncol, const PtrSet& cw, const PtrSet& cv, const PtrSet& out,
                 hipStream_t s) {
