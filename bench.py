@@ -31,10 +31,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 # known size; valid only for the kernel sources they were measured on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mid_c128.json")
 # what one timed launch of each profiled kernel class is
-LAUNCH_UNIT = {"trsv_fwd": "one level of the forward sweep over all 64 subdomains (fwd_level_kernel, plus "
-                           "fwd_sn_kernel on levels with one-wave supernode jobs)",
-               "trsv_bwd": "one level of the backward sweep over all 64 subdomains (bwd_level_kernel)"}
-TRAFFIC_KERNEL = {"trsv_fwd": ("trsv_fwd",), "trsv_bwd": ("bwd_level_kernel<double2, 0>",),
+LAUNCH_UNIT = {"trsv_fwd": "one level of the forward sweep of one of the two subdomain batches (fwd_level_kernel, or "
+                           "fwd_sn_kernel on levels with one-wave supernode jobs), timed with the batches one after "
+                           "the other",
+               "trsv_bwd": "one level of the backward sweep of one of the two subdomain batches (bwd_level_kernel), "
+                           "timed with the batches one after the other"}
+TRAFFIC_KERNEL = {"trsv_fwd": ("trsv_fwd",), "trsv_bwd": ("trsv_bwd",),
                   "spmv": ("spmv_kernel<", "sell_kernel")}
 
 
@@ -236,8 +238,8 @@ def cpu_baseline(w, iters_per_solve):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="mid", choices=["mid", "tiny"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the complex64-factor measurement")
@@ -313,11 +315,36 @@ def main():
                 f"relres {inf['relres']:.2e}")
         torch.cuda.synchronize()
         h.profile(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
         one_solve()
+        e1.record(stream)
         torch.cuda.synchronize()
         prof = h.profile_read()
+        prof["_solve_s"] = e0.elapsed_time(e1) / 1e3
         h.profile(False)
         return times, its, prof
+
+    def local_solves(h, prof, reps=20, c64=False):
+        """Wall time of one-level ORAS applications (both subdomain batches'
+        forward and backward sweeps, concurrent on two streams, then the
+        prolongation) against their algorithmic bytes from the profile."""
+        applies = max(prof["prolong"]["launches"], 1)
+        panel = 0.5 if c64 else 1.0  # the profile counts complex128 panel bytes
+        by = (panel * (prof["trsv_fwd"]["bytes"] + prof["trsv_bwd"]["bytes"]) + prof["prolong"]["bytes"]) / applies
+        r = torch.randn(h.n, dtype=torch.complex128, device="cuda")
+        z = torch.empty_like(r)
+        for _ in range(2):
+            h.apply_oras(r, z, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            h.apply_oras(r, z, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = 1e3 * e0.elapsed_time(e1) / reps
+        return {"us_per_apply": us, "bytes_per_apply": by, "GBps": by / (us * 1e-6) / 1e9,
+                "frac_of_hbm_peak": by / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}
 
     h, st, t_asm = setup(False)
     b = helm.load_vector(h, w)
@@ -336,11 +363,12 @@ def main():
     avg_ms = pk["ms"] / max(pk["launches"], 1)
     avg_bytes = pk["bytes"] / max(pk["launches"], 1)
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
-    prof_solve_s = total_t / len(times)  # the profiled solve is one more of the same
+    prof_solve_s = prof.pop("_solve_s")  # the profiled solve (batches one after the other)
     kernels = {k: {"launches": v["launches"], "avg_us": 1e3 * v["ms"] / max(v["launches"], 1),
                    "share_of_solve": v["ms"] / 1e3 / prof_solve_s,
                    "GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None}
                for k, v in prof.items()}
+    loc = local_solves(h, prof)
     out = {
         "metric": "GMRES iterations/s and solves/s at 1e-6 rel. residual (fp32 vs fp64 precond); p50/p99",
         "value": its_per_s,
@@ -375,6 +403,7 @@ def main():
                      "avg_launch_us": 1e3 * avg_ms, "avg_bytes_per_launch": avg_bytes,
                      "launch": LAUNCH_UNIT.get(dom, "one launch")},
         "kernels": kernels,
+        "local_solves": loc,
         "wall_s_timed": wall,
     }
     def run_batched(hh, tag):
@@ -412,6 +441,8 @@ def main():
         h32, st32, _ = setup(True)
         U32 = torch.zeros_like(B)
         t32, it32, prof32 = run(h32, B, U32, args.steps, args.warmup, "fp32")
+        prof32.pop("_solve_s")
+        loc32 = local_solves(h32, prof32, c64=True)
         tt = float(np.sum(t32))
         k32 = {k: {"avg_us": 1e3 * v["ms"] / max(v["launches"], 1),
                    "GBps": (v["bytes"] / 2 / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 and k.startswith("trsv")
@@ -427,6 +458,7 @@ def main():
             "factor_GB": st32["factor_entries"] * 8 / 1e9,
             "speedup_vs_fp64": (len(t32) / tt) / solves_per_s,
             "kernels": k32,
+            "local_solves": loc32,
         }
         if args.nrhs > 0:
             out["batched_fp32"] = run_batched(h32, "fp32")

@@ -78,7 +78,10 @@ typedef struct helm_precond_opts {
                               64-row tiles) solves those with one wave per
                               supernode instead of one per tile; 0 = 6144,
                               -1 = never                                  */
-  int32_t reserved;
+  int32_t batches;         /* 0 = the subdomains as two batches of about
+                              equal factor size whose level sweeps run on
+                              two streams (one after the other while
+                              helm_profile is on); 1 = one batch          */
 } helm_precond_opts;
 
 enum {
@@ -151,6 +154,8 @@ typedef struct helm_precond_stats {
   int32_t factor_on_host;  /* 1 if the numeric factorisation ran on the host */
   int32_t n_perturbed;     /* zero pivots replaced by sqrt(eps) max|a_ij|   */
   double factor_seconds;   /* wall time of the numeric factorisation       */
+  int32_t batches;         /* subdomain batches (1 or 2)                   */
+  int32_t reserved;
 } helm_precond_stats;
 
 /* Create a context on HIP device `device_ordinal`; -1 creates a host-only

@@ -105,6 +105,12 @@ struct BatchDev {
   DVec<unsigned char> stage;
   // > 0: grid of the single cooperative launch that runs the whole solve
   int coop = 0;
+  // backward-sweep outputs inside a buffer shared with another batch (the
+  // second subdomain batch writes after the first), else x / x_b
+  double* xo = nullptr;
+  double* xo_b = nullptr;
+  double* xout() const { return xo ? xo : x.p; }
+  double* xout_b() const { return xo_b ? xo_b : x_b.p; }
   dev::LevelRanges ranges{};
   dev::Batch view() const;
   void reset() {
@@ -213,6 +219,14 @@ struct Ctx {
   // GMRES work
   int gm_m = 0;
   DVec<double> V, Zk, w, partial, hcol, htmp, nrm, ydev, coef_w, coef_v;
+  // the subdomains [0, split) and [split, n_sub) as two batches whose
+  // level sweeps run on two streams (0: one batch)
+  BatchDev fine2;
+  int32_t split = 0;
+  DVec<double> xall, xall_b;
+  int xall_b_S = 0;
+  hipStream_t s2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipEvent_t hev = nullptr;   // marks the Hessenberg column copy of a step
   double* h_host = nullptr;  // pinned
   Profiler prof;

@@ -23,6 +23,9 @@ namespace helm {
 
 Ctx::~Ctx() {
   if (hev) (void)hipEventDestroy(hev);
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  if (ev_join) (void)hipEventDestroy(ev_join);
+  if (s2) (void)hipStreamDestroy(s2);
   if (h_host) (void)hipHostFree(h_host);
   if (bh_host) (void)hipHostFree(bh_host);
 }
@@ -38,6 +41,11 @@ void Ctx::free_precond() {
   Esym = Symbolic();
   stats = helm_precond_stats{};
   fine.reset();
+  fine2.reset();
+  split = 0;
+  xall.reset();
+  xall_b.reset();
+  xall_b_S = 0;
   coarse.reset();
   pro_ptr.reset();
   pro_idx.reset();
@@ -77,7 +85,7 @@ dev::Batch BatchDev::view() const {
   b.pb = pb.p;
   b.ubuf = ubuf.p;
   b.y = y.p;
-  b.x = x.p;
+  b.x = xout();
   return b;
 }
 
@@ -876,18 +884,63 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
     Ss.push_back(&c.sym[i]);
     in.push_back(&c.subs[i].dofs);
   }
-  BatchHost fb;
+  BatchHost fb, fb2;
   int32_t npert = 0;
   const bool c64 = opts && opts->factor_c64;
   const bool on_host = opts && opts->factor_on_host;
   double fsec = 0, csec = 0;
-  build_batch(As, Ss, in, c.device, on_device, c64, on_host, snmin, fb, c.fine, npert, fsec);
+  // two batches of about equal panel entries (their level sweeps overlap on
+  // two streams), unless asked for one
+  int32_t h = n_sub;
+  if (on_device && n_sub >= 2 && !(opts && opts->batches == 1)) {
+    double tot = 0, run = 0;
+    for (auto& S : c.sym) tot += (double)(S.fwd_entries + S.bwd_entries);
+    h = 1;
+    for (int32_t i = 0; i + 1 < n_sub; ++i) {
+      run += (double)(c.sym[i].fwd_entries + c.sym[i].bwd_entries);
+      if (run >= 0.5 * tot) break;
+      h = i + 2;
+    }
+    h = std::min(std::max<int32_t>(h, 1), n_sub - 1);
+  }
+  auto part = [&](auto& v, int32_t a, int32_t b) {
+    return std::vector<typename std::decay_t<decltype(v)>::value_type>(v.begin() + a, v.begin() + b);
+  };
+  // two concurrent batches fill the device together: each takes one-wave
+  // jobs at half the threshold
+  const int64_t snb = h < n_sub && snmin > 0 ? std::max<int64_t>(1, snmin / 2) : snmin;
+  build_batch(part(As, 0, h), part(Ss, 0, h), part(in, 0, h), c.device, on_device, c64, on_host, snb, fb, c.fine,
+              npert, fsec);
   st.factor_entries = fb.nf + fb.nb;
-  st.factor_c64 = c64 ? 1 : 0;
   st.levels_fwd = (int32_t)fb.lev_f.size() - 1;
   st.levels_bwd = (int32_t)fb.lev_b.size() - 1;
   st.max_front = fb.max_front;
   st.factor_flops = fb.flops;
+  if (h < n_sub) {
+    int32_t np2 = 0;
+    double f2 = 0;
+    build_batch(part(As, h, n_sub), part(Ss, h, n_sub), part(in, h, n_sub), c.device, on_device, c64, on_host,
+                snb, fb2, c.fine2, np2, f2);
+    npert += np2;
+    fsec += f2;
+    st.factor_entries += fb2.nf + fb2.nb;
+    st.levels_fwd = std::max(st.levels_fwd, (int32_t)fb2.lev_f.size() - 1);
+    st.levels_bwd = std::max(st.levels_bwd, (int32_t)fb2.lev_b.size() - 1);
+    st.max_front = std::max(st.max_front, fb2.max_front);
+    st.factor_flops += fb2.flops;
+    // one output vector in subdomain order, as the prolongation map expects
+    c.split = h;
+    c.xall.alloc(2 * (size_t)(fb.npos + fb2.npos));
+    c.fine.xo = c.xall.p;
+    c.fine2.xo = c.xall.p + 2 * fb.npos;
+    c.fine.x.reset();
+    c.fine2.x.reset();
+    if (!c.s2) HELM_HIP(hipStreamCreateWithFlags(&c.s2, hipStreamNonBlocking));
+    if (!c.ev_fork) HELM_HIP(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming));
+    if (!c.ev_join) HELM_HIP(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming));
+  }
+  st.factor_c64 = c64 ? 1 : 0;
+  st.batches = h < n_sub ? 2 : 1;
   for (auto& S : c.sym) st.n_supernodes += S.nsn;
   // prolongation map: global dof -> positions with D > 0, in subdomain order
   {
@@ -1069,10 +1122,23 @@ void apply_coarse(Ctx& c, const double* r, double* q, hipStream_t s) {
 }
 
 void apply_oras(Ctx& c, const double* r, double* z, const double* q, hipStream_t s) {
-  batch_solve(c.fine, r, s, &c.prof, true);
+  if (!c.split) {
+    batch_solve(c.fine, r, s, &c.prof, true);
+  } else if (c.prof.on) {
+    // timed launch by launch: the two batches one after the other
+    batch_solve(c.fine, r, s, &c.prof, true);
+    batch_solve(c.fine2, r, s, &c.prof, true);
+  } else {
+    HELM_HIP(hipEventRecord(c.ev_fork, s));
+    HELM_HIP(hipStreamWaitEvent(c.s2, c.ev_fork, 0));
+    batch_solve(c.fine2, r, c.s2, nullptr, true);
+    batch_solve(c.fine, r, s, nullptr, true);
+    HELM_HIP(hipEventRecord(c.ev_join, c.s2));
+    HELM_HIP(hipStreamWaitEvent(s, c.ev_join, 0));
+  }
   const bool p = c.prof.on;
   if (p) c.prof.begin(s);
-  dev::prolong(c.D.n, c.pro_ptr.p, c.pro_idx.p, c.pro_w.p, c.fine.x.p, q, z, s);
+  dev::prolong(c.D.n, c.pro_ptr.p, c.pro_idx.p, c.pro_w.p, c.fine.xout(), q, z, s);
   if (p) c.prof.end(HELM_K_PROLONG, 12.0 * c.pro_w.n + 28.0 * c.pro_w.n + 16.0 * c.D.n * (q ? 2 : 1) + 8.0 * c.D.n, s);
 }
 
@@ -1407,6 +1473,13 @@ void ensure_block(Ctx& c, int m, int S) {
     c.blk_xcd = tx < td;
   }
   ensure_batch_block(c.fine, S);
+  if (c.split) {
+    ensure_batch_block(c.fine2, S);
+    if (c.xall_b_S < S) {
+      c.xall_b.alloc(2 * (size_t)(c.fine.npos + c.fine2.npos) * S);
+      c.xall_b_S = S;
+    }
+  }
   if (c.two_level) ensure_batch_block(c.coarse, S);
 }
 
@@ -1429,9 +1502,9 @@ void batch_solve_block(BatchDev& b, int S, const double* in, hipStream_t s, Prof
     if (each) prof->begin(s);
     if (mfma)
       dev::bwd_level_mfma(v, b.gsn_b.p + b.gsn_lev_b[l], b.gsn_lev_b[l + 1] - b.gsn_lev_b[l], b.gy_b[l], b.tiles_b[l],
-                          b.tiles_b[l + 1] - b.tiles_b[l], b.nwide_b[l], b.y_b.p, b.x_b.p, b.stage.p, !fine, s);
+                          b.tiles_b[l + 1] - b.tiles_b[l], b.nwide_b[l], b.y_b.p, b.xout_b(), b.stage.p, !fine, s);
     else
-      dev::bwd_level_block(v, b.tiles_b[l], b.tiles_b[l + 1] - b.tiles_b[l], S, b.y_b.p, b.x_b.p, !fine, s);
+      dev::bwd_level_block(v, b.tiles_b[l], b.tiles_b[l + 1] - b.tiles_b[l], S, b.y_b.p, b.xout_b(), !fine, s);
     if (each) prof->end(HELM_K_TRSV_BWD, b.pbytes_b[l] + S * (b.bytes_b[l] - b.pbytes_b[l]), s);
   }
 }
@@ -1445,6 +1518,11 @@ void spmv_block(Ctx& c, int S, const double* x, const double* b, double* y, hipS
 
 // Z = M^{-1} X for S interleaved vectors (eq. 2lvl, or eq. oras one-level).
 void apply_precond_block(Ctx& c, int S, const double* X, double* Z, hipStream_t s) {
+  if (c.split) {
+    // the second batch's interleaved outputs follow the first batch's
+    c.fine.xo_b = c.xall_b.p;
+    c.fine2.xo_b = c.xall_b.p + 2 * (size_t)c.fine.npos * S;
+  }
   const int64_t n = c.D.n;
   const bool p = c.prof.on;
   if (c.two_level) {
@@ -1456,11 +1534,14 @@ void apply_precond_block(Ctx& c, int S, const double* X, double* Z, hipStream_t 
                              c.coarse.x_b.p, X, c.bq.p, c.bt.p, s);
     if (p) c.prof.end(HELM_K_COARSE, 0.0, s);
     batch_solve_block(c.fine, S, c.bt.p, s, &c.prof, true);
+    if (c.split) batch_solve_block(c.fine2, S, c.bt.p, s, &c.prof, true);
   } else {
     batch_solve_block(c.fine, S, X, s, &c.prof, true);
+    if (c.split) batch_solve_block(c.fine2, S, X, s, &c.prof, true);
   }
   if (p) c.prof.begin(s);
-  dev::prolong_block(n, c.pro_ptr.p, c.pro_idx.p, c.pro_w.p, S, c.fine.x_b.p, c.two_level ? c.bq.p : nullptr, Z, s);
+  dev::prolong_block(n, c.pro_ptr.p, c.pro_idx.p, c.pro_w.p, S, c.fine.xout_b(), c.two_level ? c.bq.p : nullptr, Z,
+                     s);
   if (p) c.prof.end(HELM_K_PROLONG, 0.0, s);
 }
 

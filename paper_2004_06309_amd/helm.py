@@ -44,7 +44,7 @@ class Mesh(C.Structure):
 class PrecondOpts(C.Structure):
     _fields_ = [("leaf_size", C.c_int32), ("factor_c64", C.c_int32), ("coarse_leaf_size", C.c_int32),
                 ("tile_rows", C.c_int32), ("coarse_tile_rows", C.c_int32), ("factor_on_host", C.c_int32),
-                ("sn_jobs_min", C.c_int32), ("reserved", C.c_int32)]
+                ("sn_jobs_min", C.c_int32), ("batches", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -62,7 +62,7 @@ class PrecondStats(C.Structure):
                 ("levels_bwd", C.c_int32), ("max_front", C.c_int32), ("n_supernodes", C.c_int32),
                 ("setup_seconds", C.c_double), ("factor_flops", C.c_double), ("factor_c64", C.c_int32),
                 ("coarse_grid", C.c_int32), ("factor_on_host", C.c_int32), ("n_perturbed", C.c_int32),
-                ("factor_seconds", C.c_double)]
+                ("factor_seconds", C.c_double), ("batches", C.c_int32), ("reserved", C.c_int32)]
 
 
 class ServerOpts(C.Structure):
@@ -221,10 +221,11 @@ class Helm:
         return ptr, col, val
 
     def precond_setup(self, part, n_sub, overlap, coarse_xyz=None, coarse_tets=None, leaf_size=0, c64=False,
-                      coarse_leaf_size=0, tile_rows=0, coarse_tile_rows=0, factor_on_host=False, sn_jobs_min=0):
+                      coarse_leaf_size=0, tile_rows=0, coarse_tile_rows=0, factor_on_host=False, sn_jobs_min=0,
+                      batches=0):
         part = np.ascontiguousarray(part, dtype=np.int32)
         opts = PrecondOpts(int(leaf_size), 1 if c64 else 0, int(coarse_leaf_size), int(tile_rows),
-                           int(coarse_tile_rows), 1 if factor_on_host else 0, int(sn_jobs_min))
+                           int(coarse_tile_rows), 1 if factor_on_host else 0, int(sn_jobs_min), int(batches))
         cm = None
         if coarse_xyz is not None:
             cm, keep = _mesh(coarse_xyz, coarse_tets, 1)
@@ -361,7 +362,7 @@ class Server:
 def from_workload(w, device=0, leaf_size=0, c64=False, **opts):
     """Helm context assembled and preconditioned for a workloads.Workload;
     opts: coarse_leaf_size, tile_rows, coarse_tile_rows, factor_on_host,
-    sn_jobs_min (see precond_setup)."""
+    sn_jobs_min, batches (see precond_setup)."""
     h = Helm(device)
     h.assemble(w.xyz, w.tets, w.order, w.c_tet, w.omega)
     h.precond_setup(w.part, w.n_sub, w.overlap, w.coarse_xyz, w.coarse_tets, leaf_size, c64, **opts)

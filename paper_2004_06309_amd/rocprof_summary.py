@@ -2,17 +2,18 @@
 
     python -m paper_2004_06309_amd.rocprof_summary --trace DIR/mid_kernel_trace.csv \
         [--fetch DIR/mid_counter_collection.csv --write DIR/mid_counter_collection.csv \
-         --copy-fetch ... --copy-write ...] [--level-group NAME=K1+K2 --levels L] \
+         --copy-fetch ... --copy-write ...] [--level-group NAME=K1+K2] \
         --out profiles/<name>.md --command "<cmd>"
 
 Kernel-trace statistics are grouped by kernel (template arguments kept, so
 fine and coarse level solves are separate rows).  With counter files, the
 per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) are scaled by what the same
 counters read for a device copy of known size, and averaged per dispatch.
-A level group sums kernels that share the levels of one sweep (the tile
-kernel and the one-wave supernode kernel of the forward sweep) and reports
-them per level: total time and bytes over (preconditioner applications x
-levels), an application being one launch of --per-apply.
+A level group pools kernels that share the levels of one sweep (the tile
+kernel and the one-wave supernode kernel of the forward sweep), each level
+being one launch of one of them, and reports them per launch: over all
+launches, and over the isolated ones (no other kernel running at the same
+time, as when the subdomain batches are timed one after the other).
 """
 from __future__ import annotations
 
@@ -34,6 +35,21 @@ def trace_stats(path):
     d = collections.defaultdict(list)
     for r in csv.DictReader(open(path)):
         d[short_name(r["Kernel_Name"])].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    return d
+
+
+def isolated_stats(path):
+    """Durations of the launches that overlap no other kernel in time (the
+    ones not sharing the device with a launch on another stream)."""
+    ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short_name(r["Kernel_Name"]))
+                for r in csv.DictReader(open(path)))
+    d = collections.defaultdict(list)
+    reach = -1  # latest end among earlier launches
+    for i, (a, b, k) in enumerate(ev):
+        nxt = ev[i + 1][0] if i + 1 < len(ev) else None
+        if a >= reach and (nxt is None or nxt >= b):
+            d[k].append(b - a)
+        reach = max(reach, b)
     return d
 
 
@@ -66,9 +82,6 @@ def main():
     ap.add_argument("--json-out")
     ap.add_argument("--level-group", action="append", default=[],
                     help="NAME=K1+K2: kernels sharing the levels of one sweep, reported per level")
-    ap.add_argument("--levels", type=int, default=0, help="levels per sweep (for --level-group)")
-    ap.add_argument("--per-apply", default="prolong_kernel",
-                    help="kernel launched once per preconditioner application")
     args = ap.parse_args()
     groups = {}
     for g in args.level_group:
@@ -82,15 +95,20 @@ def main():
         v = st[k]
         lines.append(f"| `{k}` | {len(v)} | {sum(v) / len(v) / 1e3:.1f} | {sum(v) / 1e6:.2f} | "
                      f"{100 * sum(v) / total:.1f}% |")
-    if groups and args.levels > 0:
-        applies = len(st.get(args.per_apply, []))
-        lines += ["", f"Per level of a sweep ({applies} preconditioner applications x {args.levels} levels):", "",
-                  "| group | kernels | level solves | avg us per level |", "|---|---|---|---|"]
+    if groups:
+        iso = isolated_stats(args.trace)
+        lines += ["", "Per level solve (each level of a sweep is one launch of one of the group's kernels; the "
+                      "isolated launches share the device with no other kernel, as in the profiled solve, where "
+                      "the subdomain batches run one after the other):", "",
+                  "| group | kernels | launches | avg us | isolated launches | avg us isolated |",
+                  "|---|---|---|---|---|---|"]
         for name, ks in groups.items():
             t = sum(sum(st.get(k, [])) for k in ks)
-            n = applies * args.levels
-            lines.append(f"| {name} | {' + '.join('`' + k + '`' for k in ks)} | {n} | "
-                         f"{t / max(n, 1) / 1e3:.1f} |")
+            n = sum(len(st.get(k, [])) for k in ks)
+            ti = sum(sum(iso.get(k, [])) for k in ks)
+            ni = sum(len(iso.get(k, [])) for k in ks)
+            lines.append(f"| {name} | {' + '.join('`' + k + '`' for k in ks)} | {n} | {t / max(n, 1) / 1e3:.1f} | "
+                         f"{ni} | {ti / max(ni, 1) / 1e3:.1f} |")
     out = {}
     if args.fetch and args.write and args.copy_fetch and args.copy_write:
         cf = max(counter_means(args.copy_fetch, "FETCH_SIZE").values())
@@ -107,13 +125,13 @@ def main():
             w = wr.get(k, 0.0) * 1024 * sw
             out[k] = {"fetch_bytes": f, "write_bytes": w}
             lines.append(f"| `{k}` | {f / 1e6:.2f} | {w / 1e6:.2f} |")
-        if groups and args.levels > 0:
+        if groups:
             fs = counter_sums(args.fetch, "FETCH_SIZE")
             ws = counter_sums(args.write, "WRITE_SIZE")
-            lines += ["", "Per level of a sweep:", "", "| group | fetch MB | write MB |", "|---|---|---|"]
+            lines += ["", "Per level solve:", "", "| group | fetch MB | write MB |", "|---|---|---|"]
             for name, ks in groups.items():
-                na = fs.get(args.per_apply, [0, 0.0])[0] * args.levels
-                nw = ws.get(args.per_apply, [0, 0.0])[0] * args.levels
+                na = sum(fs[k][0] for k in ks if k in fs)
+                nw = sum(ws[k][0] for k in ks if k in ws)
                 f = sum(fs[k][1] for k in ks if k in fs) * 1024 * sf / max(na, 1)
                 w = sum(ws[k][1] for k in ks if k in ws) * 1024 * sw / max(nw, 1)
                 out[name] = {"fetch_bytes": f, "write_bytes": w}

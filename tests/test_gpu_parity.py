@@ -251,6 +251,45 @@ def test_tile_rows(tile_rows, coarse_tile_rows):
     say(f"[tiles] {tile_rows}/{coarse_tile_rows}: its={[i['iterations'] for i in info]}")
 
 
+@pytest.mark.parametrize("name", ["ragged_p2", "mid_quarter_2lvl", "adapted_p2_2lvl"])
+def test_two_subdomain_batches(name):
+    """The subdomains as two batches whose level sweeps run on two streams
+    (default) against one batch: the same local solves in the same order, so
+    the preconditioner, a solve and a 16-column block solve agree bit for bit;
+    with kernel timing on the two batches run one after the other, same bits."""
+    w = WORKLOADS[name]()
+    P, b, M = opre.build(w)
+    h2 = helm.from_workload(w)
+    h1 = helm.from_workload(w, batches=1)
+    assert h2.stats()["batches"] == 2 and h1.stats()["batches"] == 1
+    assert h2.stats()["factor_entries"] == h1.stats()["factor_entries"]
+    r = dvec(rand_vec(P.n, 41))
+    z1 = torch.empty_like(r)
+    z2 = torch.empty_like(r)
+    h1.apply_precond(r, z1)
+    h2.apply_precond(r, z2)
+    assert torch.equal(z1, z2)
+    h2.profile(True)
+    h2.apply_precond(r, z2)
+    h2.profile(False)
+    assert torch.equal(z1, z2)
+    B = dvec(b)
+    U1 = torch.zeros_like(B)
+    U2 = torch.zeros_like(B)
+    h1.solve(B, U1, tol=w.tol, restart=w.restart)
+    _, info = h2.solve(B, U2, tol=w.tol, restart=w.restart)
+    assert torch.equal(U1, U2)
+    ro = opre.solve(P, b, M, tol=w.tol, restart=w.restart)
+    assert abs(info[0]["iterations"] - ro.iterations) <= 2
+    Bs = torch.stack([B] * 16)
+    V1 = torch.zeros_like(Bs)
+    V2 = torch.zeros_like(Bs)
+    h1.solve(Bs, V1, tol=w.tol, restart=w.restart, block=16)
+    h2.solve(Bs, V2, tol=w.tol, restart=w.restart, block=16)
+    assert torch.equal(V1, V2)
+    say(f"[batches] {name}: its={info[0]['iterations']} oracle={ro.iterations}")
+
+
 @pytest.mark.parametrize("name", ["small_p2_2lvl", "mid_quarter_2lvl", "adapted_p2_2lvl"])
 def test_one_wave_supernode_jobs(name):
     """Forward solves of narrow supernodes by one wave each (forced on every
