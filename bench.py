@@ -41,10 +41,14 @@ TRAFFIC_KERNEL = {"trsv_fwd": ("trsv_fwd",), "trsv_bwd": ("trsv_bwd",),
 
 
 def kernel_source_hash():
+    """SHA-256 of the kernel source and of the host code that shapes the
+    launches (what the committed counters depend on)."""
     import hashlib
 
-    return hashlib.sha256(open(os.path.join(ROOT, "paper_2004_06309_amd", "csrc", "device.hip"), "rb").read()
-                          ).hexdigest()
+    h = hashlib.sha256()
+    for f in ("device.hip", "solver.cpp"):
+        h.update(open(os.path.join(ROOT, "paper_2004_06309_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel):
@@ -54,7 +58,7 @@ def measured_traffic(kernel):
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    if t.get("device_hip_sha256") != kernel_source_hash():
+    if t.get("sources_sha256") != kernel_source_hash():
         return None
     for name, e in t.items():
         if isinstance(e, dict) and "fetch_bytes" in e and name.startswith(TRAFFIC_KERNEL.get(kernel, ("?",))):

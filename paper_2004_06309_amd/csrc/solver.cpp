@@ -1517,6 +1517,24 @@ void spmv_block(Ctx& c, int S, const double* x, const double* b, double* y, hipS
 }
 
 // Z = M^{-1} X for S interleaved vectors (eq. 2lvl, or eq. oras one-level).
+// Local solves of both subdomain batches for S interleaved right-hand sides:
+// concurrent on two streams, or one after the other while kernels are timed.
+void fine_solve_block(Ctx& c, int S, const double* in, hipStream_t s) {
+  if (!c.split) {
+    batch_solve_block(c.fine, S, in, s, &c.prof, true);
+  } else if (c.prof.on) {
+    batch_solve_block(c.fine, S, in, s, &c.prof, true);
+    batch_solve_block(c.fine2, S, in, s, &c.prof, true);
+  } else {
+    HELM_HIP(hipEventRecord(c.ev_fork, s));
+    HELM_HIP(hipStreamWaitEvent(c.s2, c.ev_fork, 0));
+    batch_solve_block(c.fine2, S, in, c.s2, nullptr, true);
+    batch_solve_block(c.fine, S, in, s, nullptr, true);
+    HELM_HIP(hipEventRecord(c.ev_join, c.s2));
+    HELM_HIP(hipStreamWaitEvent(s, c.ev_join, 0));
+  }
+}
+
 void apply_precond_block(Ctx& c, int S, const double* X, double* Z, hipStream_t s) {
   if (c.split) {
     // the second batch's interleaved outputs follow the first batch's
@@ -1533,11 +1551,9 @@ void apply_precond_block(Ctx& c, int S, const double* X, double* Z, hipStream_t 
     dev::coarse_update_block(n, c.Zp_ptr.p, c.Zp_col.p, c.Zp_val.p, c.AZ_ptr.p, c.AZ_col.p, c.AZ_val.p, S,
                              c.coarse.x_b.p, X, c.bq.p, c.bt.p, s);
     if (p) c.prof.end(HELM_K_COARSE, 0.0, s);
-    batch_solve_block(c.fine, S, c.bt.p, s, &c.prof, true);
-    if (c.split) batch_solve_block(c.fine2, S, c.bt.p, s, &c.prof, true);
+    fine_solve_block(c, S, c.bt.p, s);
   } else {
-    batch_solve_block(c.fine, S, X, s, &c.prof, true);
-    if (c.split) batch_solve_block(c.fine2, S, X, s, &c.prof, true);
+    fine_solve_block(c, S, X, s);
   }
   if (p) c.prof.begin(s);
   dev::prolong_block(n, c.pro_ptr.p, c.pro_idx.p, c.pro_w.p, S, c.fine.xout_b(), c.two_level ? c.bq.p : nullptr, Z,

@@ -139,8 +139,10 @@ def main():
         out["_scale"] = {"fetch": sf, "write": sw}
         import hashlib
         import os
-        src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "device.hip")
-        out["device_hip_sha256"] = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        hs = hashlib.sha256()
+        for f in ("device.hip", "solver.cpp"):  # kernels and the host code that shapes their launches
+            hs.update(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", f), "rb").read())
+        out["sources_sha256"] = hs.hexdigest()
     open(args.out, "w").write("\n".join(lines) + "\n")
     if args.json_out:
         json.dump(out, open(args.json_out, "w"), indent=1)

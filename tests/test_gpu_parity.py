@@ -254,9 +254,12 @@ def test_tile_rows(tile_rows, coarse_tile_rows):
 @pytest.mark.parametrize("name", ["ragged_p2", "mid_quarter_2lvl", "adapted_p2_2lvl"])
 def test_two_subdomain_batches(name):
     """The subdomains as two batches whose level sweeps run on two streams
-    (default) against one batch: the same local solves in the same order, so
-    the preconditioner, a solve and a 16-column block solve agree bit for bit;
-    with kernel timing on the two batches run one after the other, same bits."""
+    (default) against one batch: the local solves (one-level ORAS) agree bit
+    for bit, also with kernel timing on (the batches one after the other).
+    Each context times its own SpMV and coarse-update shapes at setup, and a
+    different shape sums a row in a different order, so the two-level
+    preconditioner, a solve and a 16-column block solve are compared to
+    rounding level."""
     w = WORKLOADS[name]()
     P, b, M = opre.build(w)
     h2 = helm.from_workload(w)
@@ -266,19 +269,23 @@ def test_two_subdomain_batches(name):
     r = dvec(rand_vec(P.n, 41))
     z1 = torch.empty_like(r)
     z2 = torch.empty_like(r)
-    h1.apply_precond(r, z1)
-    h2.apply_precond(r, z2)
+    h1.apply_oras(r, z1)
+    h2.apply_oras(r, z2)
     assert torch.equal(z1, z2)
     h2.profile(True)
-    h2.apply_precond(r, z2)
+    h2.apply_oras(r, z2)
     h2.profile(False)
     assert torch.equal(z1, z2)
+    h1.apply_precond(r, z1)
+    h2.apply_precond(r, z2)
+    assert rel(host(z2), host(z1)) <= 1e-13
     B = dvec(b)
     U1 = torch.zeros_like(B)
     U2 = torch.zeros_like(B)
-    h1.solve(B, U1, tol=w.tol, restart=w.restart)
+    _, i1 = h1.solve(B, U1, tol=w.tol, restart=w.restart)
     _, info = h2.solve(B, U2, tol=w.tol, restart=w.restart)
-    assert torch.equal(U1, U2)
+    assert info[0]["iterations"] == i1[0]["iterations"]
+    assert rel(host(U2), host(U1)) <= 1e-10
     ro = opre.solve(P, b, M, tol=w.tol, restart=w.restart)
     assert abs(info[0]["iterations"] - ro.iterations) <= 2
     Bs = torch.stack([B] * 16)
@@ -286,7 +293,7 @@ def test_two_subdomain_batches(name):
     V2 = torch.zeros_like(Bs)
     h1.solve(Bs, V1, tol=w.tol, restart=w.restart, block=16)
     h2.solve(Bs, V2, tol=w.tol, restart=w.restart, block=16)
-    assert torch.equal(V1, V2)
+    assert rel(host(V2), host(V1)) <= 1e-10
     say(f"[batches] {name}: its={info[0]['iterations']} oracle={ro.iterations}")
 
 
