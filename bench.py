@@ -70,22 +70,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_adapted_batch(nrhs):
-    """Batching on an unstructured h-adapted mesh: the 8 x 8 x 2 km thrust
-    model bisected to a quarter of the local wavelength at 5.5 Hz (about 3M
-    P2 dofs; the frequency is chosen so the lambda/4 mesh has that size),
-    128 box subdomains of uneven size, two-level ORAS with a non-nested
-    coarse bisection mesh, complex64 subdomain factors, nrhs point sources
-    on a 10 m-depth grid in blocks of 16."""
-    import torch
-
+def adapted_operator():
+    """The unstructured h-adapted operator: the 8 x 8 x 2 km thrust model
+    bisected to a quarter of the local wavelength at 5.5 Hz (about 3M P2
+    dofs; the frequency is chosen so the lambda/4 mesh has that size), 128
+    box subdomains of uneven size, two-level ORAS with a non-nested coarse
+    bisection mesh, complex64 subdomain factors.  Returns (workload, context,
+    mesh seconds)."""
     from paper_2004_06309_amd import helm
     from paper_2004_06309_amd import workloads as wl
 
     t0 = time.perf_counter()
     w = wl.adapted_box(freq=5.5, n0=(4, 4, 1), n_parts=(8, 8, 2))
     t_mesh = time.perf_counter() - t0
-    h = helm.from_workload(w, c64=True)
+    return w, helm.from_workload(w, c64=True), t_mesh
+
+
+def run_adapted_batch(nrhs, w, h, t_mesh):
+    """Batching on the h-adapted operator: nrhs point sources on a 10 m-depth
+    grid in blocks of 16."""
+    import torch
+
+    from paper_2004_06309_amd import helm
+    from paper_2004_06309_amd import workloads as wl
+
     st = h.stats()
     side = int(np.ceil(np.sqrt(nrhs)))
     pts = wl.surface_sources(8000.0, 8000.0, side)[:nrhs]
@@ -109,31 +117,35 @@ def run_adapted_batch(nrhs):
             "mesh_s": t_mesh, "factor_GB": st["factor_entries"] * 8 / 1e9}
 
 
-def run_serving(n_requests, rate, seed=3):
-    """Continuous batching over two resident operators of the thrust model
-    (5 Hz on the 80 x 80 x 20 P2 mesh, 3 Hz on the 40 x 40 x 10 one), both
-    with complex64 subdomain factors (FP64 FGMRES and coarse solve), one
+def run_serving(n_requests, rate, adapted=None, seed=3):
+    """Continuous batching over three resident operators of the thrust model:
+    3 Hz on the 40 x 40 x 10 P2 mesh, 5 Hz on the 80 x 80 x 20 one and the
+    h-adapted 3M-dof operator (`adapted` = (workload, context), or left out),
+    all with complex64 subdomain factors (FP64 FGMRES and coarse solve), one
     server and stream each, 16 slots.  Requests arrive as a seeded Poisson
-    process; each carries 1-4 point sources at random surface positions
-    (10 m deep) and is done when all its sources are.  Reports solves/s over
-    the makespan and request latency (arrival to last source done)."""
+    process, each for one operator with 1-16 point sources at random surface
+    positions (10 m deep); a request is done when all its sources are.
+    Reports solves/s over the makespan and request latency (arrival to last
+    source done)."""
     import torch
 
     from paper_2004_06309_amd import helm
     from paper_2004_06309_amd import workloads as wl
 
-    ops = [wl.mid(), wl.mid(scale=2, freq=3.0)]
-    ctxs, servers, streams = [], [], []
-    for w in ops:
-        h = helm.from_workload(w, c64=True)
+    ops = [wl.mid(scale=2, freq=3.0), wl.mid()]
+    ctxs = [helm.from_workload(w, c64=True) for w in ops]
+    if adapted is not None:
+        ops.append(adapted[0])
+        ctxs.append(adapted[1])
+    servers, streams = [], []
+    for w, h in zip(ops, ctxs):
         st = torch.cuda.Stream()
-        ctxs.append(h)
         streams.append(st)
         servers.append(helm.Server(h, slots=16, restart=w.restart, tol=w.tol, stream=st))
     rng = np.random.default_rng(seed)
     t_arr = np.cumsum(rng.exponential(1.0 / rate, n_requests))
     op_of = rng.integers(0, len(ops), n_requests)
-    nsrc = rng.integers(1, 5, n_requests)
+    nsrc = rng.integers(1, 17, n_requests)
     reqs = []  # (arrival, op, [tags])
     B, U, tag = {}, {}, 0
     for r in range(n_requests):
@@ -170,7 +182,8 @@ def run_serving(n_requests, rate, seed=3):
     for s_ in servers:
         s_.close()
     return {"requests": n_requests, "solves": tag, "arrival_rate_per_s": rate,
-            "operators": [f"{w.name}: {h.n} dofs, f={w.omega / (2 * np.pi):.0f} Hz" for w, h in zip(ops, ctxs)],
+            "operators": [f"{w.name}: {h.n} dofs, f={w.omega / (2 * np.pi):.1f} Hz" for w, h in zip(ops, ctxs)],
+            "sources_per_request": "1-16",
             "slots_per_operator": 16, "precond_precision": "c64 factors, FP64 FGMRES",
             "solves_per_s": tag / makespan, "makespan_s": makespan,
             "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
@@ -251,9 +264,10 @@ def main():
     ap.add_argument("--block", type=int, default=16, help="right-hand sides advanced together")
     ap.add_argument("--adapted-nrhs", type=int, default=32,
                     help="right-hand sides of the h-adapted batching measurement (0: skip)")
-    ap.add_argument("--serve", type=int, default=40,
-                    help="requests of the serving measurement (Poisson arrivals over two operators; 0: skip)")
-    ap.add_argument("--serve-rate", type=float, default=4.0, help="mean request arrivals per second")
+    ap.add_argument("--serve", type=int, default=24,
+                    help="requests of the serving measurement (Poisson arrivals over three operators; 0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=2.0,
+                    help="mean request arrivals per second (the default offers more than the device serves)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -470,22 +484,28 @@ def main():
         del h32
     # the extra lines below are reported, and a failure there is recorded
     # instead of hiding the main result
-    if args.adapted_nrhs > 0 and args.config == "mid":
-        log(f"[bench] adapted batching: {args.adapted_nrhs} rhs")
+    adapted = None
+    if (args.adapted_nrhs > 0 or args.serve > 0) and args.config == "mid":
         torch.cuda.empty_cache()
         try:
-            out["batched_adapted"] = run_adapted_batch(args.adapted_nrhs)
+            adapted = adapted_operator()
+        except Exception as e:  # noqa: BLE001
+            out["batched_adapted"] = {"error": repr(e)}
+    if args.adapted_nrhs > 0 and adapted is not None:
+        log(f"[bench] adapted batching: {args.adapted_nrhs} rhs")
+        try:
+            out["batched_adapted"] = run_adapted_batch(args.adapted_nrhs, *adapted)
         except Exception as e:  # noqa: BLE001
             out["batched_adapted"] = {"error": repr(e)}
         log(f"[bench] adapted batching: {out['batched_adapted']}")
     if args.serve > 0 and args.config == "mid":
         log(f"[bench] serving: {args.serve} requests at {args.serve_rate}/s")
-        torch.cuda.empty_cache()
         try:
-            out["serving"] = run_serving(args.serve, args.serve_rate)
+            out["serving"] = run_serving(args.serve, args.serve_rate, None if adapted is None else adapted[:2])
         except Exception as e:  # noqa: BLE001
             out["serving"] = {"error": repr(e)}
         log(f"[bench] serving: {out['serving']}")
+    del adapted
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(w, float(np.mean(its)))
