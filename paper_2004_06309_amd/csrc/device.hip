@@ -1193,6 +1193,10 @@ void coarse_update(int64_t n, const int64_t* zptr, const int32_t* zcol, const do
   auto t2 = reinterpret_cast<double2*>(t);
   if (G == 8)
     coarse_update_kernel<8><<<blocks_for(n * 8), kWG, 0, s>>>(n, zptr, zcol, zval, aptr, acol, aval, c2, r2, q2, t2);
+  else if (G == 2)
+    coarse_update_kernel<2><<<blocks_for(n * 2), kWG, 0, s>>>(n, zptr, zcol, zval, aptr, acol, aval, c2, r2, q2, t2);
+  else if (G == 1)
+    coarse_update_kernel<1><<<blocks_for(n), kWG, 0, s>>>(n, zptr, zcol, zval, aptr, acol, aval, c2, r2, q2, t2);
   else
     coarse_update_kernel<4><<<blocks_for(n * 4), kWG, 0, s>>>(n, zptr, zcol, zval, aptr, acol, aval, c2, r2, q2, t2);
 }

@@ -158,8 +158,8 @@ void sell_spmv(int64_t n, int64_t nslices, const int64_t* soff, const int32_t* s
 void spmv_real(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const double* x, double* y,
                int G, hipStream_t s);
 // q = Z cx and t = r - (A Z) cx for a coarse solution cx (complex vectors):
-// Z real CSR, A Z in the split storage of spmv_split; G = 4 or 8 lanes per
-// row.
+// Z real CSR, A Z in the split storage of spmv_split; G = 1, 2, 4 or 8
+// lanes per row.
 void coarse_update(int64_t n, const int64_t* zptr, const int32_t* zcol, const double* zval, const int64_t* aptr,
                    const int32_t* acol, const double* aval, const double* cx, const double* r, double* q, double* t,
                    int G, hipStream_t s);

@@ -1076,7 +1076,7 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
       });
       DVec<double> x2;
       x2.alloc(2 * c.D.n);
-      c.g_AZ = pick_lanes_per_row({4, 8}, [&](int G) {
+      c.g_AZ = pick_lanes_per_row({1, 2, 4, 8}, [&](int G) {
         dev::coarse_update(c.D.n, c.Zp_ptr.p, c.Zp_col.p, c.Zp_val.p, c.AZ_ptr.p, c.AZ_col.p, c.AZ_val.p, x.p, x.p,
                            y.p, x2.p, G, nullptr);
       });
