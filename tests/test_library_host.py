@@ -186,3 +186,15 @@ def test_server_needs_a_device_context():
     assert not out.value
     lib.helm_server_destroy(None)  # NULL-safe
     assert lib.helm_server_submit(None, None, None, 0) == helm.HELM_EINVAL
+
+
+def test_batch_options_on_a_host_context():
+    """The subdomain-batch and one-wave-job options are accepted by a
+    host-only context, which analyses one batch and reports it."""
+    w = wl.small_box(n=(4, 4, 2), order=2, n_parts=(2, 2, 1), overlap=1, coarse=False)
+    for kw in ({}, {"batches": 1}, {"sn_jobs_min": -1}, {"sn_jobs_min": 1}):
+        h = helm.Helm(-1)
+        h.assemble(w.xyz, w.tets, w.order, w.c_tet, w.omega)
+        h.precond_setup(w.part, w.n_sub, w.overlap, **kw)
+        st = h.stats()
+        assert st["batches"] == 1 and st["n_sub"] == 4 and st["factor_entries"] > 0
