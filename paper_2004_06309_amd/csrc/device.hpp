@@ -200,7 +200,6 @@ void scale_by_inv_set(int nr, int64_t n, const PtrSetC& w, const PtrSetC& nrm, c
 
 // ---- block (multi-right-hand-side) operations, S in {2, 4, 8, 16},
 //      interleaved n x S vectors (device_block.hip) ----
-bool block_width_ok(int S);
 // one wavefront per tile: tiles [tile0, tile0 + ntiles) of the level
 void fwd_level_block(const Batch& b, int64_t tile0, int64_t ntiles, int S, const double* bin, double* yb, double* ubb,
                      bool coarse, hipStream_t s);
@@ -217,9 +216,6 @@ void fwd_level_mfma(const Batch& b, const int32_t* sns, int64_t nsn, int gy, int
                     hipStream_t s);
 void bwd_level_mfma(const Batch& b, const int32_t* sns, int64_t nsn, int gy, int64_t tile0, int64_t ntiles,
                     int64_t nwide, const double* yb, double* xb, void* stage, bool coarse, hipStream_t s);
-void sell_spmv_block(int64_t n, int64_t nslices, const int64_t* soff, const int32_t* swidth, const int32_t* perm,
-                     const int32_t* col, const double* val, int S, const double* x, const double* b, double* y,
-                     hipStream_t s);
 // y = A x (or b - A x) for S interleaved vectors from the CSR copy of A.
 // xr / xrows: XCD row ranges as for spmv (nullptr: plain order).
 void csr_spmv_block(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const int64_t* xr,

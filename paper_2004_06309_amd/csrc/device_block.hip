@@ -535,45 +535,6 @@ __global__ __launch_bounds__(kWG) void level_mfma_narrow_kernel(const Tile* __re
   }
 }
 
-template <int S>
-__global__ __launch_bounds__(kWG) void sell_block_kernel(int64_t n, int64_t nslices, const int64_t* __restrict__ soff,
-                                                         const int32_t* __restrict__ swidth,
-                                                         const int32_t* __restrict__ perm,
-                                                         const int32_t* __restrict__ col,
-                                                         const double2* __restrict__ val,
-                                                         const double2* __restrict__ x,
-                                                         const double2* __restrict__ bvec, double2* __restrict__ y) {
-  const unsigned per = gridDim.x / 8;
-  const int64_t vb = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
-  const int64_t s = vb * (kWG / 64) + (threadIdx.x >> 6);
-  if (s >= nslices) return;
-  const int lane = threadIdx.x & 63;
-  const int64_t slot = s * 64 + lane;
-  const int64_t off = soff[s] + lane;
-  const int wdt = swidth[s];
-  double ar[S], ai[S];
-#pragma unroll
-  for (int r = 0; r < S; ++r) ar[r] = ai[r] = 0;
-  for (int j = 0; j < wdt; ++j) {
-    const int c = col[off + (int64_t)j * 64];
-    const double2 v = val[off + (int64_t)j * 64];
-    const double2* xr = x + (int64_t)c * S;
-#pragma unroll
-    for (int r = 0; r < S; ++r) cfma(ar[r], ai[r], v, xr[r]);
-  }
-  if (slot >= n) return;
-  const int64_t row = perm[slot];
-#pragma unroll
-  for (int r = 0; r < S; ++r) {
-    if (bvec) {
-      const double2 bb = bvec[row * S + r];
-      y[row * S + r] = make_double2(bb.x - ar[r], bb.y - ai[r]);
-    } else {
-      y[row * S + r] = make_double2(ar[r], ai[r]);
-    }
-  }
-}
-
 // Block SpMV over CSR: S consecutive lanes share a row and take one
 // right-hand side each, so every x gather is one contiguous S x 16 B line.
 // With kXcd, XCD k sweeps the rows [xr[k], xr[k+1]) (as in the single-vector
@@ -729,8 +690,6 @@ void with_width(int S, F&& f) {
 
 }  // namespace
 
-bool block_width_ok(int S) { return S == 2 || S == 4 || S == 8 || S == 16; }
-
 void fwd_level_block(const Batch& b, int64_t tile0, int64_t ntiles, int S, const double* bin, double* yb, double* ubb,
                      bool coarse, hipStream_t s) {
   if (ntiles <= 0) return;
@@ -838,19 +797,6 @@ void bwd_level_mfma(const Batch& b, const int32_t* sns, int64_t nsn, int gy, int
     else
       level_mfma_launch<double, 0, 0>(b, b.tb + tile0, ntiles, nwide, G, x, nullptr, s);
   }
-}
-
-void sell_spmv_block(int64_t n, int64_t nslices, const int64_t* soff, const int32_t* swidth, const int32_t* perm,
-                     const int32_t* col, const double* val, int S, const double* x, const double* b, double* y,
-                     hipStream_t s) {
-  if (n <= 0) return;
-  const unsigned nb = (unsigned)((nslices + 3) / 4);
-  with_width(S, [&](auto w) {
-    constexpr int W = decltype(w)::value;
-    sell_block_kernel<W><<<(nb + 7) / 8 * 8, kWG, 0, s>>>(
-        n, nslices, soff, swidth, perm, col, reinterpret_cast<const double2*>(val),
-        reinterpret_cast<const double2*>(x), reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(y));
-  });
 }
 
 void csr_spmv_block(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const int64_t* xr,
