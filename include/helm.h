@@ -86,11 +86,11 @@ typedef struct helm_precond_opts {
 
 enum {
   HELM_SOLVE_X0 = 1,       /* read U as the initial guess                  */
-  HELM_SOLVE_CGS2 = 2      /* one-at-a-time solves: classic CGS2 (three
-                              passes over the Krylov basis per step)
-                              instead of the default delayed CGS2 (two
-                              passes; the second orthogonalisation of v_j
-                              is folded into step j + 1)                   */
+  HELM_SOLVE_CGS2 = 2      /* classic CGS2 (three passes over the Krylov
+                              basis per step) instead of the default
+                              delayed CGS2 (two passes; the second
+                              orthogonalisation of v_j is folded into step
+                              j + 1), for single and block solves        */
 };
 
 typedef struct helm_solve_opts {

@@ -233,8 +233,8 @@ struct Ctx {
   // pseudo-block GMRES work (per right-hand side of a block)
   int blk_m = 0, blk_cap = 0;
   DVec<double> bV[dev::kMaxBlock], bZ[dev::kMaxBlock], bw[dev::kMaxBlock];
-  DVec<double> bhcol, bhtmp, bpartial, by, bX, bZb, bW, bq, bt, bcvec;
-  double* bh_host = nullptr;  // pinned, kMaxBlock x (m + 2) complex
+  DVec<double> bhcol, bhtmp, bpartial, by, bX, bZb, bW, bq, bt, bcvec, bcoef_w, bcoef_v;
+  double* bh_host = nullptr;  // pinned, kMaxBlock x (2 m + 4) complex
   ~Ctx();
   void free_precond();
 };

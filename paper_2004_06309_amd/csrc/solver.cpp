@@ -1433,6 +1433,10 @@ void ensure_batch_block(BatchDev& b, int S) {
   b.blk_S = S;
 }
 
+// Complex entries per right-hand side in the block Hessenberg, reduction
+// and host buffers (delayed CGS2 reads up to 2 m + 3 of them per step).
+size_t blk_ld(int m) { return 2 * (size_t)m + 4; }
+
 void ensure_block(Ctx& c, int m, int S) {
   const int64_t n = c.D.n;
   if (c.blk_m != m || c.blk_cap < S) {
@@ -1446,9 +1450,11 @@ void ensure_block(Ctx& c, int m, int S) {
       c.bZ[r].alloc(2 * (size_t)n * m);
       c.bw[r].alloc(2 * (size_t)n);
     }
-    c.bhcol.alloc(2 * (size_t)dev::kMaxBlock * (m + 2));
-    c.bhtmp.alloc(2 * (size_t)dev::kMaxBlock * (m + 2));
-    c.bpartial.alloc(2 * (size_t)dev::kMaxBlock * dev::gs_tiles(n) * (m + 2));
+    c.bhcol.alloc(2 * (size_t)dev::kMaxBlock * blk_ld(m));
+    c.bhtmp.alloc(2 * (size_t)dev::kMaxBlock * blk_ld(m));
+    c.bpartial.alloc(2 * (size_t)dev::kMaxBlock * dev::gs_tiles(n) * blk_ld(m));
+    c.bcoef_w.alloc(2 * (size_t)dev::kMaxBlock * (m + 2));
+    c.bcoef_v.alloc(2 * (size_t)dev::kMaxBlock * (m + 2));
     c.by.alloc(2 * (size_t)(m + 1));
     c.bX.alloc(2 * (size_t)n * S);
     c.bZb.alloc(2 * (size_t)n * S);
@@ -1458,7 +1464,7 @@ void ensure_block(Ctx& c, int m, int S) {
     if (c.two_level) c.bcvec.alloc(2 * (size_t)c.E.n * S);
     if (c.bh_host) (void)hipHostFree(c.bh_host);
     c.bh_host = nullptr;
-    HELM_HIP(hipHostMalloc((void**)&c.bh_host, 2 * sizeof(double) * dev::kMaxBlock * (m + 2), hipHostMallocDefault));
+    HELM_HIP(hipHostMalloc((void**)&c.bh_host, 2 * sizeof(double) * dev::kMaxBlock * blk_ld(m), hipHostMallocDefault));
     c.blk_m = m;
     c.blk_cap = S;
     // order of the multi-vector SpMV: plain or over XCD row ranges, the faster
@@ -1566,7 +1572,7 @@ void apply_precond_block(Ctx& c, int S, const double* X, double* Z, hipStream_t 
 // Arnoldi step applies M^{-1} and A to all active vectors at once (one pass
 // over the factor panels and over A for the whole block).
 int solve_block(Ctx& c, int nb, const double* const* Bp, double* const* Up, double tol, int m, int maxit, bool x0,
-                hipStream_t s, helm_solve_info* info) {
+                bool dcgs2, hipStream_t s, helm_solve_info* info) {
   int S = 2;
   while (S < nb) S *= 2;
   ensure_block(c, m, S);
@@ -1644,66 +1650,126 @@ int solve_block(Ctx& c, int nb, const double* const* Bp, double* const* Up, doub
       spmv_block(c, S, c.bZb.p, nullptr, c.bW.p, s);
       if (prof) c.prof.end(HELM_K_SPMV, 0.0, s);
       dev::unpack(n, S, c.bW.p, dw, s);
-      // CGS2 over the active right-hand sides (slot q holds act[q])
+      // Gram-Schmidt over the active right-hand sides (slot q holds act[q])
       if (prof) c.prof.begin(s);
-      dev::PtrSetC Vs{}, hs{}, ps{}, wc{}, nc{};
-      dev::PtrSet ws{}, hts{}, hcs{}, pw{}, nrm{}, vn{};
+      const size_t ld = blk_ld(m);
+      dev::PtrSetC Vs{}, hs{}, ps{}, wc{}, nc{}, cwc{}, cvc{};
+      dev::PtrSet Vw{}, ws{}, hts{}, hcs{}, pw{}, nrm{}, vn{}, cwp{}, cvp{};
       for (int q = 0; q < na; ++q) {
         const int r = act[q];
         Vs.p[q] = c.bV[r].p;
-        hs.p[q] = c.bhtmp.p + 2 * (size_t)q * (m + 2);
-        hts.p[q] = c.bhtmp.p + 2 * (size_t)q * (m + 2);
-        hcs.p[q] = c.bhcol.p + 2 * (size_t)q * (m + 2);
-        ps.p[q] = c.bpartial.p + 2 * (size_t)q * nt * (m + 2);
-        pw.p[q] = c.bpartial.p + 2 * (size_t)q * nt * (m + 2);
+        Vw.p[q] = c.bV[r].p;
+        hs.p[q] = c.bhtmp.p + 2 * (size_t)q * ld;
+        hts.p[q] = c.bhtmp.p + 2 * (size_t)q * ld;
+        hcs.p[q] = c.bhcol.p + 2 * (size_t)q * ld;
+        ps.p[q] = c.bpartial.p + 2 * (size_t)q * nt * ld;
+        pw.p[q] = c.bpartial.p + 2 * (size_t)q * nt * ld;
         ws.p[q] = c.bw[r].p;
         wc.p[q] = c.bw[r].p;
         nrm.p[q] = hcs.p[q] + 2 * (jj + 1);
         nc.p[q] = nrm.p[q];
         vn.p[q] = c.bV[r].p + n2 * (jj + 1);
+        cwp.p[q] = c.bcoef_w.p + 2 * (size_t)q * (m + 2);
+        cvp.p[q] = c.bcoef_v.p + 2 * (size_t)q * (m + 2);
+        cwc.p[q] = cwp.p[q];
+        cvc.p[q] = cvp.p[q];
       }
-      dev::gs_pass(0, na, n, Vs, n, jj + 1, hs, ws, pw, s);
-      dev::gs_final(na, ps, nt, jj + 1, hts, hcs, 0, s);
-      dev::gs_pass(1, na, n, Vs, n, jj + 1, hs, ws, pw, s);
-      dev::gs_final(na, ps, nt, jj + 1, hts, hcs, 1, s);
-      dev::gs_pass(2, na, n, Vs, n, jj + 1, hs, ws, pw, s);
-      dev::norm_final(na, ps, nt, nrm, s);
+      int nout;
+      if (dcgs2) {
+        // delayed CGS2: dual dots | coefficients | v_j finished, w orthogonalised
+        dev::gs_dual(false, na, n, Vs, Vw, n, jj + 1, cwc, cvc, ws, pw, s);
+        dev::gs_final(na, ps, nt, 2 * (jj + 1), hts, dev::PtrSet{}, 0, s);
+        dev::dcgs2_coef(na, hs, jj + 1, cwp, cvp, hcs, s);
+        dev::gs_dual(true, na, n, Vs, Vw, n, jj + 1, cwc, cvc, ws, pw, s);
+        dev::norm_final(na, ps, nt, nrm, s);
+        nout = 2 * jj + 3;
+      } else {
+        dev::gs_pass(0, na, n, Vs, n, jj + 1, hs, ws, pw, s);
+        dev::gs_final(na, ps, nt, jj + 1, hts, hcs, 0, s);
+        dev::gs_pass(1, na, n, Vs, n, jj + 1, hs, ws, pw, s);
+        dev::gs_final(na, ps, nt, jj + 1, hts, hcs, 1, s);
+        dev::gs_pass(2, na, n, Vs, n, jj + 1, hs, ws, pw, s);
+        dev::norm_final(na, ps, nt, nrm, s);
+        nout = jj + 2;
+      }
       dev::scale_by_inv_set(na, n, wc, nc, vn, s);
-      if (prof) c.prof.end(HELM_K_GS, na * 16.0 * n * (3.0 * (jj + 1) + 7.0), s);
-      HELM_HIP(hipMemcpyAsync(c.bh_host, c.bhcol.p, 2 * sizeof(double) * na * (m + 2), hipMemcpyDeviceToHost, s));
+      if (prof)
+        c.prof.end(HELM_K_GS, na * 16.0 * n * (dcgs2 ? 2.0 * (jj + 1) + 6.0 : 3.0 * (jj + 1) + 7.0), s);
+      HELM_HIP(hipMemcpyAsync(c.bh_host, c.bhcol.p, 2 * sizeof(double) * na * ld, hipMemcpyDeviceToHost, s));
       HELM_HIP(hipStreamSynchronize(s));
       if (c.prof.on) c.prof.harvest();
+      std::vector<int> ending;  // slots whose cycle ends at this step (delayed CGS2)
       for (int q = 0; q < na; ++q) {
         St& u = st[act[q]];
-        const double* hh = c.bh_host + 2 * (size_t)q * (m + 2);
+        const double* hh = c.bh_host + 2 * (size_t)q * ld;
+        for (int i = 0; i < 2 * nout; ++i)
+          if (!std::isfinite(hh[i])) fail(HELM_ENUMERIC, "non-finite Hessenberg entry");
         cplx* h = u.H.data() + (size_t)(m + 1) * jj;
-        for (int i = 0; i <= jj + 1; ++i) {
-          h[i] = cplx(hh[2 * i], hh[2 * i + 1]);
-          if (!std::isfinite(h[i].real()) || !std::isfinite(h[i].imag()))
-            fail(HELM_ENUMERIC, "non-finite Hessenberg entry");
-        }
+        for (int i = 0; i <= jj + 1; ++i) h[i] = cplx(hh[2 * i], hh[2 * i + 1]);
         const double hn = h[jj + 1].real();
-        for (int i = 0; i < jj; ++i) {
-          cplx a = h[i], bb = h[i + 1];
-          h[i] = u.cs[i] * a + u.sn[i] * bb;
-          h[i + 1] = -std::conj(u.sn[i]) * a + u.cs[i] * bb;
-        }
-        cplx a = h[jj], bb = h[jj + 1];
-        if (a == cplx(0, 0)) {
-          u.cs[jj] = 0;
-          u.sn[jj] = 1;
-        } else {
-          double rr = std::sqrt(std::norm(a) + std::norm(bb));
-          u.cs[jj] = std::abs(a) / rr;
-          u.sn[jj] = (a / std::abs(a)) * std::conj(bb) / rr;
-        }
-        h[jj] = u.cs[jj] * a + u.sn[jj] * bb;
-        h[jj + 1] = 0;
-        u.g[jj + 1] = -std::conj(u.sn[jj]) * u.g[jj];
-        u.g[jj] = u.cs[jj] * u.g[jj];
         ++u.its;
         u.k = jj + 1;
-        if (std::abs(u.g[jj + 1]) <= tol * u.bnorm || u.its >= maxit || hn == 0) u.done = true;
+        if (!dcgs2) {
+          givens_step(h, jj, u.cs, u.sn, u.g);
+          if (std::abs(u.g[jj + 1]) <= tol * u.bnorm || u.its >= maxit || hn == 0) u.done = true;
+          continue;
+        }
+        if (jj >= 1) {
+          cplx* hp = u.H.data() + (size_t)(m + 1) * (jj - 1);
+          finish_column(hp, jj - 1, hh + 2 * (jj + 2), hh[2 * (2 * jj + 2)]);
+          givens_step(hp, jj - 1, u.cs, u.sn, u.g);
+        }
+        std::vector<cplx> hc(h, h + jj + 2);
+        for (int i = 0; i < jj; ++i) {
+          const cplx a = hc[i], bb = hc[i + 1];
+          hc[i] = u.cs[i] * a + u.sn[i] * bb;
+          hc[i + 1] = -std::conj(u.sn[i]) * a + u.cs[i] * bb;
+        }
+        const double rr = std::sqrt(std::norm(hc[jj]) + std::norm(hc[jj + 1]));
+        const double est = hc[jj] == cplx(0, 0) ? std::abs(u.g[jj]) : std::abs(hc[jj + 1]) / rr * std::abs(u.g[jj]);
+        if (est <= tol * u.bnorm || u.its >= maxit || hn == 0 || jj + 1 == m) {
+          u.done = true;
+          if (hn > 0)
+            ending.push_back(q);
+          else
+            givens_step(h, jj, u.cs, u.sn, u.g);
+        }
+      }
+      if (!ending.empty()) {
+        // finish column j of the slots that stop here with the dots of v_{j+1}
+        const int ne = (int)ending.size();
+        dev::PtrSetC Ve{}, pe{}, he{}, cwe{}, cve{};
+        dev::PtrSet Vwe{}, we{}, pwe{}, hte{}, hce{}, cwpe{}, cvpe{};
+        for (int e = 0; e < ne; ++e) {
+          const int q = ending[e];
+          Ve.p[e] = Vs.p[q];
+          Vwe.p[e] = Vw.p[q];
+          we.p[e] = ws.p[q];
+          pwe.p[e] = pw.p[q];
+          pe.p[e] = ps.p[q];
+          hte.p[e] = hts.p[q];
+          he.p[e] = hs.p[q];
+          hce.p[e] = hcs.p[q];
+          cwpe.p[e] = cwp.p[q];
+          cvpe.p[e] = cvp.p[q];
+          cwe.p[e] = cwc.p[q];
+          cve.p[e] = cvc.p[q];
+        }
+        dev::gs_dual(false, ne, n, Ve, Vwe, n, jj + 2, cwe, cve, we, pwe, s);
+        dev::gs_final(ne, pe, nt, 2 * (jj + 2), hte, dev::PtrSet{}, 0, s);
+        dev::dcgs2_coef(ne, he, jj + 2, cwpe, cvpe, hce, s);
+        HELM_HIP(hipMemcpyAsync(c.bh_host, c.bhcol.p, 2 * sizeof(double) * na * ld, hipMemcpyDeviceToHost, s));
+        HELM_HIP(hipStreamSynchronize(s));
+        for (int e = 0; e < ne; ++e) {
+          const int q = ending[e];
+          St& u = st[act[q]];
+          const double* hh = c.bh_host + 2 * (size_t)q * ld;
+          for (int i = 0; i < 2 * (2 * jj + 5); ++i)
+            if (!std::isfinite(hh[i])) fail(HELM_ENUMERIC, "non-finite Hessenberg entry");
+          cplx* h = u.H.data() + (size_t)(m + 1) * jj;
+          finish_column(h, jj, hh + 2 * (jj + 3), hh[2 * (2 * jj + 4)]);
+          givens_step(h, jj, u.cs, u.sn, u.g);
+        }
       }
     }
     // cycle end: x += Z_k y for every right-hand side of the cycle
@@ -1762,7 +1828,8 @@ int solve(Ctx& c, int32_t nrhs, const double* B, double tol, const helm_solve_op
       Up[r] = U + 2 * (size_t)n * (j0 + r);
     }
     int st = nb == 1 ? solve_single(c, 1, Bp[0], tol, m, maxit, x0, dcgs2, Up[0], s, info ? info + j0 : nullptr)
-                     : solve_block(c, nb, Bp.data(), Up.data(), tol, m, maxit, x0, s, info ? info + j0 : nullptr);
+                     : solve_block(c, nb, Bp.data(), Up.data(), tol, m, maxit, x0, dcgs2, s,
+                                   info ? info + j0 : nullptr);
     if (st != HELM_OK) status = st;
   }
   return status;
@@ -1916,11 +1983,11 @@ int Server::launch() {
       if (done[b2] || slot[q].jj != jj) continue;
       done[b2] = 1;
       Vs.p[na] = c.bV[q].p;
-      hs.p[na] = c.bhtmp.p + 2 * (size_t)q * (m + 2);
-      hts.p[na] = c.bhtmp.p + 2 * (size_t)q * (m + 2);
-      hcs.p[na] = c.bhcol.p + 2 * (size_t)q * (m + 2);
-      ps.p[na] = c.bpartial.p + 2 * (size_t)q * nt * (m + 2);
-      pw.p[na] = c.bpartial.p + 2 * (size_t)q * nt * (m + 2);
+      hs.p[na] = c.bhtmp.p + 2 * (size_t)q * blk_ld(m);
+      hts.p[na] = c.bhtmp.p + 2 * (size_t)q * blk_ld(m);
+      hcs.p[na] = c.bhcol.p + 2 * (size_t)q * blk_ld(m);
+      ps.p[na] = c.bpartial.p + 2 * (size_t)q * nt * blk_ld(m);
+      pw.p[na] = c.bpartial.p + 2 * (size_t)q * nt * blk_ld(m);
       ws.p[na] = c.bw[q].p;
       wc.p[na] = c.bw[q].p;
       nrm.p[na] = hcs.p[na] + 2 * (jj + 1);
@@ -1936,7 +2003,7 @@ int Server::launch() {
     dev::norm_final(na, ps, nt, nrm, s);
     dev::scale_by_inv_set(na, n, wc, nc, vn, s);
   }
-  HELM_HIP(hipMemcpyAsync(c.bh_host, c.bhcol.p, 2 * sizeof(double) * slots_n * (m + 2), hipMemcpyDeviceToHost, s));
+  HELM_HIP(hipMemcpyAsync(c.bh_host, c.bhcol.p, 2 * sizeof(double) * slots_n * blk_ld(m), hipMemcpyDeviceToHost, s));
   HELM_HIP(hipEventRecord(done_ev, s));
   inflight = true;
   return (int)act.size();
@@ -1950,7 +2017,7 @@ void Server::finish(std::vector<helm_server_event>& out) {
     for (int q : act) {
       Slot& z = slot[q];
       const int jj = z.jj;
-      const double* hh = c.bh_host + 2 * (size_t)q * (m + 2);
+      const double* hh = c.bh_host + 2 * (size_t)q * blk_ld(m);
       cplx* h = z.H.data() + (size_t)(m + 1) * jj;
       bool bad = false;
       for (int i = 0; i <= jj + 1; ++i) {

@@ -282,8 +282,8 @@ class Helm:
     def solve(self, B, U, tol=1e-6, restart=50, maxit=1000, x0=False, stream=None, block=1, classic_cgs2=False):
         """Solve A U = B; B, U are (n,) or (nrhs, n) complex128 GPU tensors
         (each RHS contiguous); `block` right-hand sides are advanced together.
-        `classic_cgs2` selects three-pass CGS2 for one-at-a-time solves
-        (default: delayed CGS2).  Returns (status, [info dicts])."""
+        `classic_cgs2` selects three-pass CGS2 (default: delayed CGS2).
+        Returns (status, [info dicts])."""
         nrhs = 1 if B.dim() == 1 else B.shape[0]
         info = (SolveInfo * max(nrhs, 1))()
         flags = (HELM_SOLVE_X0 if x0 else 0) | (HELM_SOLVE_CGS2 if classic_cgs2 else 0)

@@ -159,6 +159,24 @@ def test_delayed_and_classic_cgs2(restart):
         assert np.linalg.norm(u - ro.x) <= 1e-6 * np.linalg.norm(ro.x)
         out[classic] = info[0]["iterations"]
     assert abs(out[False] - out[True]) <= 1
+    # pseudo-block GMRES, 4 right-hand sides advanced together
+    rng = np.random.default_rng(restart)
+    lo, hi = w.xyz.min(axis=0), w.xyz.max(axis=0)
+    Bs = np.stack([P.point_source(lo + (hi - lo) * rng.uniform(0.2, 0.8, 3)) for _ in range(4)])
+    blk = {}
+    for classic in (False, True):
+        U = torch.zeros(4, P.n, dtype=torch.complex128, device=DEV)
+        rc, info = h.solve(dvec(Bs), U, tol=tol, restart=restart, maxit=600, block=4, classic_cgs2=classic)
+        u = host(U)
+        assert rc == helm.HELM_OK
+        for k in range(4):
+            res = np.linalg.norm(Bs[k] - P.A @ u[k]) / np.linalg.norm(Bs[k])
+            assert res <= tol and np.isclose(res, info[k]["relres"], rtol=1e-3)
+        blk[classic] = (u, [i["iterations"] for i in info])
+    for k in range(4):
+        assert abs(blk[False][1][k] - blk[True][1][k]) <= 1
+        assert np.linalg.norm(blk[False][0][k] - blk[True][0][k]) <= 1e-6 * np.linalg.norm(blk[True][0][k])
+    say(f"[dcgs2] restart={restart} block its delayed={blk[False][1]} classic={blk[True][1]}")
 
 
 @pytest.mark.parametrize("name", ["tiny", "mid_quarter_2lvl", "ragged_p2"])
