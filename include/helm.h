@@ -122,7 +122,8 @@ typedef struct helm_server_opts {
                               free device memory allows (at most 16)      */
   int32_t restart;         /* GMRES(m) restart length, 1..50, 0 = 50       */
   int32_t maxit;           /* Arnoldi steps per request, 0 = 1000          */
-  int32_t reserved;
+  int32_t flags;           /* HELM_SOLVE_CGS2: classic CGS2; other bits
+                              are ignored                                  */
   double tol;              /* true relative residual, 0 = 1e-6             */
 } helm_server_opts;
 

@@ -281,6 +281,7 @@ struct Server {
   Ctx& c;
   hipStream_t s;
   int m = 50, maxit = 1000, slots_n = 0;
+  bool dcgs2 = true;
   double tol = 1e-6;
   std::deque<Request> queue;
   std::vector<Slot> slot;

@@ -1852,6 +1852,7 @@ Server::Server(Ctx& ctx, const helm_server_opts* o, hipStream_t st) : c(ctx), s(
   m = o && o->restart > 0 ? o->restart : 50;
   maxit = o && o->maxit > 0 ? o->maxit : 1000;
   tol = o && o->tol > 0 ? o->tol : 1e-6;
+  dcgs2 = !(o && (o->flags & HELM_SOLVE_CGS2));
   if (m > 50) fail(HELM_EINVAL, "restart must be <= 50");
   const int64_t n = c.D.n;
   int want = o && o->slots > 0 ? o->slots : dev::kMaxBlock;
@@ -1969,20 +1970,25 @@ int Server::launch() {
   dev::unpack(n, S, c.bZb.p, dz, s);
   spmv_block(c, S, c.bZb.p, nullptr, c.bW.p, s);
   dev::unpack(n, S, c.bW.p, dw, s);
-  // CGS2, one call per group of slots at the same Krylov dimension
+  // Gram-Schmidt, one call per group of slots at the same Krylov dimension
   const int nt = dev::gs_tiles(n);
   std::vector<int> done(act.size(), 0);
   for (size_t a = 0; a < act.size(); ++a) {
     if (done[a]) continue;
     const int jj = slot[act[a]].jj;
-    dev::PtrSetC Vs{}, hs{}, ps{}, wc{}, nc{};
-    dev::PtrSet ws{}, hts{}, hcs{}, pw{}, nrm{}, vn{};
+    dev::PtrSetC Vs{}, hs{}, ps{}, wc{}, nc{}, cwc{}, cvc{};
+    dev::PtrSet Vw{}, ws{}, hts{}, hcs{}, pw{}, nrm{}, vn{}, cwp{}, cvp{};
     int na = 0;
     for (size_t b2 = a; b2 < act.size(); ++b2) {
       const int q = act[b2];
       if (done[b2] || slot[q].jj != jj) continue;
       done[b2] = 1;
       Vs.p[na] = c.bV[q].p;
+      Vw.p[na] = c.bV[q].p;
+      cwp.p[na] = c.bcoef_w.p + 2 * (size_t)q * (m + 2);
+      cvp.p[na] = c.bcoef_v.p + 2 * (size_t)q * (m + 2);
+      cwc.p[na] = cwp.p[na];
+      cvc.p[na] = cvp.p[na];
       hs.p[na] = c.bhtmp.p + 2 * (size_t)q * blk_ld(m);
       hts.p[na] = c.bhtmp.p + 2 * (size_t)q * blk_ld(m);
       hcs.p[na] = c.bhcol.p + 2 * (size_t)q * blk_ld(m);
@@ -1995,11 +2001,18 @@ int Server::launch() {
       vn.p[na] = c.bV[q].p + n2 * (jj + 1);
       ++na;
     }
-    dev::gs_pass(0, na, n, Vs, n, jj + 1, hs, ws, pw, s);
-    dev::gs_final(na, ps, nt, jj + 1, hts, hcs, 0, s);
-    dev::gs_pass(1, na, n, Vs, n, jj + 1, hs, ws, pw, s);
-    dev::gs_final(na, ps, nt, jj + 1, hts, hcs, 1, s);
-    dev::gs_pass(2, na, n, Vs, n, jj + 1, hs, ws, pw, s);
+    if (dcgs2) {
+      dev::gs_dual(false, na, n, Vs, Vw, n, jj + 1, cwc, cvc, ws, pw, s);
+      dev::gs_final(na, ps, nt, 2 * (jj + 1), hts, dev::PtrSet{}, 0, s);
+      dev::dcgs2_coef(na, hs, jj + 1, cwp, cvp, hcs, s);
+      dev::gs_dual(true, na, n, Vs, Vw, n, jj + 1, cwc, cvc, ws, pw, s);
+    } else {
+      dev::gs_pass(0, na, n, Vs, n, jj + 1, hs, ws, pw, s);
+      dev::gs_final(na, ps, nt, jj + 1, hts, hcs, 0, s);
+      dev::gs_pass(1, na, n, Vs, n, jj + 1, hs, ws, pw, s);
+      dev::gs_final(na, ps, nt, jj + 1, hts, hcs, 1, s);
+      dev::gs_pass(2, na, n, Vs, n, jj + 1, hs, ws, pw, s);
+    }
     dev::norm_final(na, ps, nt, nrm, s);
     dev::scale_by_inv_set(na, n, wc, nc, vn, s);
   }
@@ -2014,16 +2027,14 @@ void Server::finish(std::vector<helm_server_event>& out) {
   if (inflight) {
     HELM_HIP(hipEventSynchronize(done_ev));
     inflight = false;
+    std::vector<int> ending, close;  // slots finishing their column j / ending their cycle
     for (int q : act) {
       Slot& z = slot[q];
       const int jj = z.jj;
       const double* hh = c.bh_host + 2 * (size_t)q * blk_ld(m);
-      cplx* h = z.H.data() + (size_t)(m + 1) * jj;
+      const int nout = dcgs2 ? 2 * jj + 3 : jj + 2;
       bool bad = false;
-      for (int i = 0; i <= jj + 1; ++i) {
-        h[i] = cplx(hh[2 * i], hh[2 * i + 1]);
-        if (!std::isfinite(h[i].real()) || !std::isfinite(h[i].imag())) bad = true;
-      }
+      for (int i = 0; i < 2 * nout; ++i) bad = bad || !std::isfinite(hh[i]);
       ++z.its;
       if (bad) {
         helm_server_event e{};
@@ -2036,32 +2047,105 @@ void Server::finish(std::vector<helm_server_event>& out) {
         z.busy = false;
         continue;
       }
+      cplx* h = z.H.data() + (size_t)(m + 1) * jj;
+      for (int i = 0; i <= jj + 1; ++i) h[i] = cplx(hh[2 * i], hh[2 * i + 1]);
       const double hn = h[jj + 1].real();
-      for (int i = 0; i < jj; ++i) {
-        const cplx a = h[i], bb = h[i + 1];
-        h[i] = z.cs[i] * a + z.sn[i] * bb;
-        h[i + 1] = -std::conj(z.sn[i]) * a + z.cs[i] * bb;
-      }
-      const cplx a = h[jj], bb = h[jj + 1];
-      if (a == cplx(0, 0)) {
-        z.cs[jj] = 0;
-        z.sn[jj] = 1;
+      bool end;
+      if (!dcgs2) {
+        givens_step(h, jj, z.cs, z.sn, z.g);
+        end = std::abs(z.g[jj + 1]) <= tol * z.bnorm || z.its >= maxit || hn == 0 || jj + 1 == m;
       } else {
-        const double rr = std::sqrt(std::norm(a) + std::norm(bb));
-        z.cs[jj] = std::abs(a) / rr;
-        z.sn[jj] = (a / std::abs(a)) * std::conj(bb) / rr;
+        // v_j's second pass finishes column j - 1; column j is estimated
+        // as it stands and finished at the cycle's end
+        if (jj >= 1) {
+          cplx* hp = z.H.data() + (size_t)(m + 1) * (jj - 1);
+          finish_column(hp, jj - 1, hh + 2 * (jj + 2), hh[2 * (2 * jj + 2)]);
+          givens_step(hp, jj - 1, z.cs, z.sn, z.g);
+        }
+        std::vector<cplx> hc(h, h + jj + 2);
+        for (int i = 0; i < jj; ++i) {
+          const cplx a = hc[i], bb = hc[i + 1];
+          hc[i] = z.cs[i] * a + z.sn[i] * bb;
+          hc[i + 1] = -std::conj(z.sn[i]) * a + z.cs[i] * bb;
+        }
+        const double rr = std::sqrt(std::norm(hc[jj]) + std::norm(hc[jj + 1]));
+        const double est = hc[jj] == cplx(0, 0) ? std::abs(z.g[jj]) : std::abs(hc[jj + 1]) / rr * std::abs(z.g[jj]);
+        end = est <= tol * z.bnorm || z.its >= maxit || hn == 0 || jj + 1 == m;
+        if (end && hn > 0) {
+          ending.push_back(q);
+          continue;
+        }
+        if (end) givens_step(h, jj, z.cs, z.sn, z.g);
       }
-      h[jj] = z.cs[jj] * a + z.sn[jj] * bb;
-      h[jj + 1] = 0;
-      z.g[jj + 1] = -std::conj(z.sn[jj]) * z.g[jj];
-      z.g[jj] = z.cs[jj] * z.g[jj];
-      const bool end = std::abs(z.g[jj + 1]) <= tol * z.bnorm || z.its >= maxit || hn == 0 || jj + 1 == m;
       if (!end) {
         z.jj = jj + 1;
         continue;
       }
+      close.push_back(q);
+    }
+    // delayed CGS2: the slots that stop here finish column j with the dots
+    // of v_{j+1}, one call per group at the same Krylov dimension
+    const int nt = dev::gs_tiles(n);
+    std::vector<int> grouped(ending.size(), 0);
+    for (size_t a = 0; a < ending.size(); ++a) {
+      if (grouped[a]) continue;
+      const int jj = slot[ending[a]].jj;
+      dev::PtrSetC Vs{}, ps{}, hs{}, cwc{}, cvc{};
+      dev::PtrSet Vw{}, ws{}, pw{}, hts{}, hcs{}, cwp{}, cvp{};
+      int na = 0;
+      for (size_t b2 = a; b2 < ending.size(); ++b2) {
+        const int q = ending[b2];
+        if (grouped[b2] || slot[q].jj != jj) continue;
+        grouped[b2] = 1;
+        Vs.p[na] = c.bV[q].p;
+        Vw.p[na] = c.bV[q].p;
+        ws.p[na] = c.bw[q].p;
+        ps.p[na] = c.bpartial.p + 2 * (size_t)q * nt * blk_ld(m);
+        pw.p[na] = c.bpartial.p + 2 * (size_t)q * nt * blk_ld(m);
+        hs.p[na] = c.bhtmp.p + 2 * (size_t)q * blk_ld(m);
+        hts.p[na] = c.bhtmp.p + 2 * (size_t)q * blk_ld(m);
+        hcs.p[na] = c.bhcol.p + 2 * (size_t)q * blk_ld(m);
+        cwp.p[na] = c.bcoef_w.p + 2 * (size_t)q * (m + 2);
+        cvp.p[na] = c.bcoef_v.p + 2 * (size_t)q * (m + 2);
+        cwc.p[na] = cwp.p[na];
+        cvc.p[na] = cvp.p[na];
+        ++na;
+      }
+      dev::gs_dual(false, na, n, Vs, Vw, n, jj + 2, cwc, cvc, ws, pw, s);
+      dev::gs_final(na, ps, nt, 2 * (jj + 2), hts, dev::PtrSet{}, 0, s);
+      dev::dcgs2_coef(na, hs, jj + 2, cwp, cvp, hcs, s);
+    }
+    if (!ending.empty()) {
+      HELM_HIP(hipMemcpyAsync(c.bh_host, c.bhcol.p, 2 * sizeof(double) * slots_n * blk_ld(m), hipMemcpyDeviceToHost,
+                              s));
+      HELM_HIP(hipStreamSynchronize(s));
+    }
+    for (int q : ending) {
+      Slot& z = slot[q];
+      const int jj = z.jj;
+      const double* hh = c.bh_host + 2 * (size_t)q * blk_ld(m);
+      bool bad = false;
+      for (int i = 0; i < 2 * (2 * jj + 5); ++i) bad = bad || !std::isfinite(hh[i]);
+      if (bad) {
+        helm_server_event e{};
+        e.tag = z.tag;
+        e.iterations = z.its;
+        e.status = HELM_ENUMERIC;
+        e.relres = z.rel;
+        e.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - z.t0).count();
+        out.push_back(e);
+        z.busy = false;
+        continue;
+      }
+      cplx* h = z.H.data() + (size_t)(m + 1) * jj;
+      finish_column(h, jj, hh + 2 * (jj + 3), hh[2 * (2 * jj + 4)]);
+      givens_step(h, jj, z.cs, z.sn, z.g);
+      close.push_back(q);
+    }
+    for (int q : close) {
       // cycle end: x += Z_k y, then the true residual decides
-      const int k = jj + 1;
+      Slot& z = slot[q];
+      const int k = z.jj + 1;
       for (int i = k - 1; i >= 0; --i) {
         cplx acc = z.g[i];
         for (int l = i + 1; l < k; ++l) acc -= z.H[(size_t)(m + 1) * l + i] * z.y[l];

@@ -66,7 +66,7 @@ class PrecondStats(C.Structure):
 
 
 class ServerOpts(C.Structure):
-    _fields_ = [("slots", C.c_int32), ("restart", C.c_int32), ("maxit", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("slots", C.c_int32), ("restart", C.c_int32), ("maxit", C.c_int32), ("flags", C.c_int32),
                 ("tol", C.c_double)]
 
 
@@ -311,10 +311,10 @@ class Server:
     completion events as dicts.  Keeps the submitted tensors alive until
     their completion."""
 
-    def __init__(self, helm, slots=0, restart=50, maxit=1000, tol=1e-6, stream=None):
+    def __init__(self, helm, slots=0, restart=50, maxit=1000, tol=1e-6, stream=None, classic_cgs2=False):
         self.helm = helm
         self.lib = helm.lib
-        opts = ServerOpts(int(slots), int(restart), int(maxit), 0, float(tol))
+        opts = ServerOpts(int(slots), int(restart), int(maxit), HELM_SOLVE_CGS2 if classic_cgs2 else 0, float(tol))
         out = C.c_void_p()
         helm._check(self.lib.helm_server_create(helm.h, C.byref(opts), _stream(stream), C.byref(out)))
         self.h = out

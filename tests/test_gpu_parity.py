@@ -519,6 +519,25 @@ def test_server_continuous_batching():
     # the context is usable again once the server is gone
     rc, info = h.solve(B[0].contiguous(), solo[0], tol=w.tol)
     assert rc == helm.HELM_OK
+    # restart cycles inside the server: GMRES(7), delayed and classic CGS2
+    solo7 = torch.zeros_like(B)
+    its7 = []
+    for r in range(6):
+        rc, info = h.solve(B[r].contiguous(), solo7[r], tol=w.tol, restart=7)
+        its7.append(info[0]["iterations"])
+    for classic in (False, True):
+        U = torch.zeros_like(B)
+        srv = helm.Server(h, slots=4, restart=7, tol=w.tol, classic_cgs2=classic)
+        ev = _serve([srv], [[(2 * r, B[r], U[r], 200 + r) for r in range(6)]])
+        srv.close()
+        u, us = host(U), host(solo7)
+        for r in range(6):
+            e = ev[200 + r]
+            assert e["converged"] == 1 and e["status"] == helm.HELM_OK
+            assert np.linalg.norm(Bs[r] - P.A @ u[r]) / np.linalg.norm(Bs[r]) <= w.tol
+            assert abs(e["iterations"] - its7[r]) <= 2
+            assert np.linalg.norm(u[r] - us[r]) <= 1e-5 * np.linalg.norm(us[r])
+        say(f"[serve] GMRES(7) classic={classic}: its={[ev[200 + r]['iterations'] for r in range(6)]} solo={its7}")
 
 
 def test_servers_on_two_operators_overlap():
