@@ -735,6 +735,7 @@ __global__ __launch_bounds__(kWG) void gs_pass_kernel(int64_t n, PtrSetC Vs, int
 // being |v_j|^2) of every 64-row tile, staged through LDS so lane k of each
 // wave sums column k over a quarter of the tile's rows;
 // partial[blk * 2 ncol + k] and partial[blk * 2 ncol + ncol + k].
+template <int kU>  // columns per wave (ncol <= 4 kU): fewer prefetch registers for short bases
 __global__ __launch_bounds__(kWG) void gs_dots_kernel(int64_t n, PtrSetC Vs, int64_t ld, int ncol, PtrSet ws,
                                                       PtrSet parts) {
   const double2* __restrict__ V = reinterpret_cast<const double2*>(Vs.p[blockIdx.y]);
@@ -748,7 +749,6 @@ __global__ __launch_bounds__(kWG) void gs_dots_kernel(int64_t n, PtrSetC Vs, int
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, j = ncol - 1;
   double dr = 0, di = 0, er = 0, ei = 0;  // dots of column `lane` with w and with v_j
   const int64_t ntiles = (n + kGsRows - 1) / kGsRows;
-  constexpr int kU = kGsMaxCols / 4;
   double2 a[kU];
   double2 wnext = make_double2(0.0, 0.0);
   auto load_next = [&](int64_t tb) {
@@ -1245,8 +1245,12 @@ void gs_dual(bool update, int nr, int64_t n, const PtrSetC& V, const PtrSet& Vw,
   const size_t lds = sizeof(double2) * ((size_t)ncol * (kGsRows + 1) + kGsRows + 8 * kGsMaxCols);
   if (update)
     gs_update_rows_kernel<<<grid, kWG, 0, s>>>(n, V, Vw, ld, ncol, cw, cv, w, partial);
+  else if (ncol <= 16)
+    gs_dots_kernel<4><<<grid, kWG, lds, s>>>(n, V, ld, ncol, w, partial);
+  else if (ncol <= 32)
+    gs_dots_kernel<8><<<grid, kWG, lds, s>>>(n, V, ld, ncol, w, partial);
   else
-    gs_dots_kernel<<<grid, kWG, lds, s>>>(n, V, ld, ncol, w, partial);
+    gs_dots_kernel<kGsMaxCols / 4><<<grid, kWG, lds, s>>>(n, V, ld, ncol, w, partial);
 }
 void dcgs2_coef(int nr, const PtrSetC& dots, int ncol, const PtrSet& cw, const PtrSet& cv, const PtrSet& out,
                 hipStream_t s) {
