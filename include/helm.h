@@ -78,10 +78,12 @@ typedef struct helm_precond_opts {
                               64-row tiles) solves those with one wave per
                               supernode instead of one per tile; 0 = 6144,
                               -1 = never                                  */
-  int32_t batches;         /* 0 = the subdomains as two batches of about
-                              equal factor size whose level sweeps run on
-                              two streams (one after the other while
-                              helm_profile is on); 1 = one batch          */
+  int32_t batches;         /* the subdomains as 1 .. 4 consecutive batches
+                              of about equal factor size whose level
+                              sweeps run concurrently, each on a stream of
+                              its own (one after the other while
+                              helm_profile is on); 0 = 2; other values
+                              fail with HELM_EINVAL                       */
 } helm_precond_opts;
 
 enum {
@@ -155,7 +157,7 @@ typedef struct helm_precond_stats {
   int32_t factor_on_host;  /* 1 if the numeric factorisation ran on the host */
   int32_t n_perturbed;     /* zero pivots replaced by sqrt(eps) max|a_ij|   */
   double factor_seconds;   /* wall time of the numeric factorisation       */
-  int32_t batches;         /* subdomain batches (1 or 2)                   */
+  int32_t batches;         /* subdomain batches (1 .. 4)                   */
   int32_t reserved;
 } helm_precond_stats;
 

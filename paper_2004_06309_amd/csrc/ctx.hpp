@@ -164,6 +164,9 @@ struct Profiler {
   ~Profiler();
 };
 
+// Subdomain batches whose local solves run concurrently, at most.
+constexpr int kMaxBatches = 4;
+
 struct Ctx {
   int device = -1;
   std::string err;
@@ -202,7 +205,11 @@ struct Ctx {
   DVec<double> S_val;
   int64_t S_nnz = 0;
   int g_S = 0;  // its tile shape
-  BatchDev fine, coarse;
+  // the subdomains as nbatch consecutive batches of about equal factor size
+  // whose level sweeps run on streams of their own (batch 0 on the caller's)
+  BatchDev fine[kMaxBatches];
+  int32_t nbatch = 1;
+  BatchDev coarse;
   DVec<int64_t> pro_ptr;   // prolongation: global dof -> (position, weight)
   DVec<int32_t> pro_idx;
   DVec<double> pro_w;
@@ -219,14 +226,11 @@ struct Ctx {
   // GMRES work
   int gm_m = 0;
   DVec<double> V, Zk, w, partial, hcol, htmp, nrm, ydev, coef_w, coef_v;
-  // the subdomains [0, split) and [split, n_sub) as two batches whose
-  // level sweeps run on two streams (0: one batch)
-  BatchDev fine2;
-  int32_t split = 0;
+  // backward-sweep outputs of all batches in subdomain order (nbatch > 1)
   DVec<double> xall, xall_b;
   int xall_b_S = 0;
-  hipStream_t s2 = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t sb[kMaxBatches] = {};  // streams of batches 1..nbatch-1
+  hipEvent_t ev_fork = nullptr, ev_join[kMaxBatches] = {};
   hipEvent_t hev = nullptr;   // marks the Hessenberg column copy of a step
   double* h_host = nullptr;  // pinned
   Profiler prof;

@@ -24,8 +24,10 @@ namespace helm {
 Ctx::~Ctx() {
   if (hev) (void)hipEventDestroy(hev);
   if (ev_fork) (void)hipEventDestroy(ev_fork);
-  if (ev_join) (void)hipEventDestroy(ev_join);
-  if (s2) (void)hipStreamDestroy(s2);
+  for (int k = 0; k < kMaxBatches; ++k) {
+    if (ev_join[k]) (void)hipEventDestroy(ev_join[k]);
+    if (sb[k]) (void)hipStreamDestroy(sb[k]);
+  }
   if (h_host) (void)hipHostFree(h_host);
   if (bh_host) (void)hipHostFree(bh_host);
 }
@@ -40,9 +42,8 @@ void Ctx::free_precond() {
   E = Csr();
   Esym = Symbolic();
   stats = helm_precond_stats{};
-  fine.reset();
-  fine2.reset();
-  split = 0;
+  for (auto& b : fine) b.reset();
+  nbatch = 1;
   xall.reset();
   xall_b.reset();
   xall_b_S = 0;
@@ -884,63 +885,68 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
     Ss.push_back(&c.sym[i]);
     in.push_back(&c.subs[i].dofs);
   }
-  BatchHost fb, fb2;
   int32_t npert = 0;
   const bool c64 = opts && opts->factor_c64;
   const bool on_host = opts && opts->factor_on_host;
   double fsec = 0, csec = 0;
-  // two batches of about equal panel entries (their level sweeps overlap on
-  // two streams), unless asked for one
-  int32_t h = n_sub;
-  if (on_device && n_sub >= 2 && !(opts && opts->batches == 1)) {
+  // nb consecutive batches of about equal panel entries (their level sweeps
+  // overlap on nb streams): batch k ends at the first subdomain count whose
+  // running total reaches k / nb of all entries
+  const int32_t want = !opts || opts->batches == 0 ? 2 : opts->batches;
+  if (want < 1 || want > kMaxBatches) fail(HELM_EINVAL, "batches must be 0 .. 4");
+  const int32_t nb = on_device ? std::min(want, n_sub) : 1;
+  std::vector<int32_t> bnd(nb + 1, 0);
+  bnd[nb] = n_sub;
+  {
     double tot = 0, run = 0;
     for (auto& S : c.sym) tot += (double)(S.fwd_entries + S.bwd_entries);
-    h = 1;
-    for (int32_t i = 0; i + 1 < n_sub; ++i) {
-      run += (double)(c.sym[i].fwd_entries + c.sym[i].bwd_entries);
-      if (run >= 0.5 * tot) break;
-      h = i + 2;
+    int32_t i = 0;
+    for (int32_t k = 1; k < nb; ++k) {
+      while (i < n_sub && run < tot * k / nb) run += (double)(c.sym[i].fwd_entries + c.sym[i].bwd_entries), ++i;
+      bnd[k] = std::min(std::max(i, bnd[k - 1] + 1), n_sub - (nb - k));
     }
-    h = std::min(std::max<int32_t>(h, 1), n_sub - 1);
   }
   auto part = [&](auto& v, int32_t a, int32_t b) {
     return std::vector<typename std::decay_t<decltype(v)>::value_type>(v.begin() + a, v.begin() + b);
   };
-  // two concurrent batches fill the device together: each takes one-wave
-  // jobs at half the threshold
-  const int64_t snb = h < n_sub && snmin > 0 ? std::max<int64_t>(1, snmin / 2) : snmin;
-  build_batch(part(As, 0, h), part(Ss, 0, h), part(in, 0, h), c.device, on_device, c64, on_host, snb, fb, c.fine,
-              npert, fsec);
-  st.factor_entries = fb.nf + fb.nb;
-  st.levels_fwd = (int32_t)fb.lev_f.size() - 1;
-  st.levels_bwd = (int32_t)fb.lev_b.size() - 1;
-  st.max_front = fb.max_front;
-  st.factor_flops = fb.flops;
-  if (h < n_sub) {
-    int32_t np2 = 0;
-    double f2 = 0;
-    build_batch(part(As, h, n_sub), part(Ss, h, n_sub), part(in, h, n_sub), c.device, on_device, c64, on_host,
-                snb, fb2, c.fine2, np2, f2);
-    npert += np2;
-    fsec += f2;
-    st.factor_entries += fb2.nf + fb2.nb;
-    st.levels_fwd = std::max(st.levels_fwd, (int32_t)fb2.lev_f.size() - 1);
-    st.levels_bwd = std::max(st.levels_bwd, (int32_t)fb2.lev_b.size() - 1);
-    st.max_front = std::max(st.max_front, fb2.max_front);
-    st.factor_flops += fb2.flops;
+  // concurrent batches fill the device together: each takes one-wave jobs
+  // at 1 / nb of the threshold
+  const int64_t snb = nb > 1 && snmin > 0 ? std::max<int64_t>(1, snmin / nb) : snmin;
+  c.nbatch = nb;
+  st.factor_entries = 0;
+  int64_t npos_all = 0;
+  for (int32_t k = 0; k < nb; ++k) {
+    BatchHost fb;
+    int32_t np = 0;
+    double fs = 0;
+    build_batch(part(As, bnd[k], bnd[k + 1]), part(Ss, bnd[k], bnd[k + 1]), part(in, bnd[k], bnd[k + 1]), c.device,
+                on_device, c64, on_host, snb, fb, c.fine[k], np, fs);
+    npert += np;
+    fsec += fs;
+    st.factor_entries += fb.nf + fb.nb;
+    st.levels_fwd = std::max(st.levels_fwd, (int32_t)fb.lev_f.size() - 1);
+    st.levels_bwd = std::max(st.levels_bwd, (int32_t)fb.lev_b.size() - 1);
+    st.max_front = std::max(st.max_front, fb.max_front);
+    st.factor_flops += fb.flops;
+    npos_all += fb.npos;
+  }
+  if (nb > 1) {
     // one output vector in subdomain order, as the prolongation map expects
-    c.split = h;
-    c.xall.alloc(2 * (size_t)(fb.npos + fb2.npos));
-    c.fine.xo = c.xall.p;
-    c.fine2.xo = c.xall.p + 2 * fb.npos;
-    c.fine.x.reset();
-    c.fine2.x.reset();
-    if (!c.s2) HELM_HIP(hipStreamCreateWithFlags(&c.s2, hipStreamNonBlocking));
+    c.xall.alloc(2 * (size_t)npos_all);
+    int64_t o = 0;
+    for (int32_t k = 0; k < nb; ++k) {
+      c.fine[k].xo = c.xall.p + 2 * o;
+      o += c.fine[k].npos;
+      c.fine[k].x.reset();
+    }
     if (!c.ev_fork) HELM_HIP(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming));
-    if (!c.ev_join) HELM_HIP(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming));
+    for (int32_t k = 1; k < nb; ++k) {
+      if (!c.sb[k]) HELM_HIP(hipStreamCreateWithFlags(&c.sb[k], hipStreamNonBlocking));
+      if (!c.ev_join[k]) HELM_HIP(hipEventCreateWithFlags(&c.ev_join[k], hipEventDisableTiming));
+    }
   }
   st.factor_c64 = c64 ? 1 : 0;
-  st.batches = h < n_sub ? 2 : 1;
+  st.batches = nb;
   for (auto& S : c.sym) st.n_supernodes += S.nsn;
   // prolongation map: global dof -> positions with D > 0, in subdomain order
   {
@@ -1121,24 +1127,33 @@ void apply_coarse(Ctx& c, const double* r, double* q, hipStream_t s) {
   }
 }
 
-void apply_oras(Ctx& c, const double* r, double* z, const double* q, hipStream_t s) {
-  if (!c.split) {
-    batch_solve(c.fine, r, s, &c.prof, true);
-  } else if (c.prof.on) {
-    // timed launch by launch: the two batches one after the other
-    batch_solve(c.fine, r, s, &c.prof, true);
-    batch_solve(c.fine2, r, s, &c.prof, true);
-  } else {
-    HELM_HIP(hipEventRecord(c.ev_fork, s));
-    HELM_HIP(hipStreamWaitEvent(c.s2, c.ev_fork, 0));
-    batch_solve(c.fine2, r, c.s2, nullptr, true);
-    batch_solve(c.fine, r, s, nullptr, true);
-    HELM_HIP(hipEventRecord(c.ev_join, c.s2));
-    HELM_HIP(hipStreamWaitEvent(s, c.ev_join, 0));
+// Runs f(batch, stream) for every subdomain batch: batches 1.. on their own
+// streams, forked from and joined back to s, batch 0 on s; one after the
+// other on s while kernels are timed launch by launch.
+template <class F>
+void for_batches(Ctx& c, hipStream_t s, F&& f) {
+  if (c.nbatch == 1 || c.prof.on) {
+    for (int k = 0; k < c.nbatch; ++k) f(c.fine[k], s);
+    return;
   }
+  HELM_HIP(hipEventRecord(c.ev_fork, s));
+  for (int k = 1; k < c.nbatch; ++k) {
+    HELM_HIP(hipStreamWaitEvent(c.sb[k], c.ev_fork, 0));
+    f(c.fine[k], c.sb[k]);
+  }
+  f(c.fine[0], s);
+  for (int k = 1; k < c.nbatch; ++k) {
+    HELM_HIP(hipEventRecord(c.ev_join[k], c.sb[k]));
+    HELM_HIP(hipStreamWaitEvent(s, c.ev_join[k], 0));
+  }
+}
+
+void apply_oras(Ctx& c, const double* r, double* z, const double* q, hipStream_t s) {
+  Profiler* prof = c.prof.on ? &c.prof : nullptr;
+  for_batches(c, s, [&](BatchDev& b, hipStream_t sk) { batch_solve(b, r, sk, prof, true); });
   const bool p = c.prof.on;
   if (p) c.prof.begin(s);
-  dev::prolong(c.D.n, c.pro_ptr.p, c.pro_idx.p, c.pro_w.p, c.fine.xout(), q, z, s);
+  dev::prolong(c.D.n, c.pro_ptr.p, c.pro_idx.p, c.pro_w.p, c.fine[0].xout(), q, z, s);
   if (p) c.prof.end(HELM_K_PROLONG, 12.0 * c.pro_w.n + 28.0 * c.pro_w.n + 16.0 * c.D.n * (q ? 2 : 1) + 8.0 * c.D.n, s);
 }
 
@@ -1478,13 +1493,14 @@ void ensure_block(Ctx& c, int m, int S) {
     });
     c.blk_xcd = tx < td;
   }
-  ensure_batch_block(c.fine, S);
-  if (c.split) {
-    ensure_batch_block(c.fine2, S);
-    if (c.xall_b_S < S) {
-      c.xall_b.alloc(2 * (size_t)(c.fine.npos + c.fine2.npos) * S);
-      c.xall_b_S = S;
-    }
+  int64_t npos_all = 0;
+  for (int k = 0; k < c.nbatch; ++k) {
+    ensure_batch_block(c.fine[k], S);
+    npos_all += c.fine[k].npos;
+  }
+  if (c.nbatch > 1 && c.xall_b_S < S) {
+    c.xall_b.alloc(2 * (size_t)npos_all * S);
+    c.xall_b_S = S;
   }
   if (c.two_level) ensure_batch_block(c.coarse, S);
 }
@@ -1523,29 +1539,21 @@ void spmv_block(Ctx& c, int S, const double* x, const double* b, double* y, hipS
 }
 
 // Z = M^{-1} X for S interleaved vectors (eq. 2lvl, or eq. oras one-level).
-// Local solves of both subdomain batches for S interleaved right-hand sides:
-// concurrent on two streams, or one after the other while kernels are timed.
+// Local solves of all subdomain batches for S interleaved right-hand sides:
+// concurrent on their streams, or one after the other while kernels are timed.
 void fine_solve_block(Ctx& c, int S, const double* in, hipStream_t s) {
-  if (!c.split) {
-    batch_solve_block(c.fine, S, in, s, &c.prof, true);
-  } else if (c.prof.on) {
-    batch_solve_block(c.fine, S, in, s, &c.prof, true);
-    batch_solve_block(c.fine2, S, in, s, &c.prof, true);
-  } else {
-    HELM_HIP(hipEventRecord(c.ev_fork, s));
-    HELM_HIP(hipStreamWaitEvent(c.s2, c.ev_fork, 0));
-    batch_solve_block(c.fine2, S, in, c.s2, nullptr, true);
-    batch_solve_block(c.fine, S, in, s, nullptr, true);
-    HELM_HIP(hipEventRecord(c.ev_join, c.s2));
-    HELM_HIP(hipStreamWaitEvent(s, c.ev_join, 0));
-  }
+  Profiler* prof = c.prof.on ? &c.prof : nullptr;
+  for_batches(c, s, [&](BatchDev& b, hipStream_t sk) { batch_solve_block(b, S, in, sk, prof, true); });
 }
 
 void apply_precond_block(Ctx& c, int S, const double* X, double* Z, hipStream_t s) {
-  if (c.split) {
-    // the second batch's interleaved outputs follow the first batch's
-    c.fine.xo_b = c.xall_b.p;
-    c.fine2.xo_b = c.xall_b.p + 2 * (size_t)c.fine.npos * S;
+  if (c.nbatch > 1) {
+    // every batch's interleaved outputs follow those of the batches before it
+    size_t o = 0;
+    for (int k = 0; k < c.nbatch; ++k) {
+      c.fine[k].xo_b = c.xall_b.p + 2 * o * S;
+      o += (size_t)c.fine[k].npos;
+    }
   }
   const int64_t n = c.D.n;
   const bool p = c.prof.on;
@@ -1562,7 +1570,7 @@ void apply_precond_block(Ctx& c, int S, const double* X, double* Z, hipStream_t 
     fine_solve_block(c, S, X, s);
   }
   if (p) c.prof.begin(s);
-  dev::prolong_block(n, c.pro_ptr.p, c.pro_idx.p, c.pro_w.p, S, c.fine.xout_b(), c.two_level ? c.bq.p : nullptr, Z,
+  dev::prolong_block(n, c.pro_ptr.p, c.pro_idx.p, c.pro_w.p, S, c.fine[0].xout_b(), c.two_level ? c.bq.p : nullptr, Z,
                      s);
   if (p) c.prof.end(HELM_K_PROLONG, 0.0, s);
 }

@@ -315,6 +315,52 @@ def test_two_subdomain_batches(name):
     say(f"[batches] {name}: its={info[0]['iterations']} oracle={ro.iterations}")
 
 
+@pytest.mark.parametrize("name,nb", [("ragged_p2", 3), ("ragged_p2", 4), ("mid_quarter_2lvl", 3),
+                                     ("mid_quarter_2lvl", 4)])
+def test_more_subdomain_batches(name, nb):
+    """Three and four batches on as many streams against one batch: the local
+    solves agree bit for bit, concurrent and with kernel timing on (one-wave
+    supernode jobs off on both sides, as their threshold scales with the
+    batch count); the preconditioner, a solve and a 16-column block solve
+    (its outputs interleaved batch after batch) to rounding level."""
+    w = WORKLOADS[name]()
+    P, b, M = opre.build(w)
+    h1 = helm.from_workload(w, batches=1, sn_jobs_min=-1)
+    hk = helm.from_workload(w, batches=nb, sn_jobs_min=-1)
+    assert hk.stats()["batches"] == nb and h1.stats()["batches"] == 1
+    assert hk.stats()["factor_entries"] == h1.stats()["factor_entries"]
+    r = dvec(rand_vec(P.n, 43))
+    z1 = torch.empty_like(r)
+    zk = torch.empty_like(r)
+    h1.apply_oras(r, z1)
+    hk.apply_oras(r, zk)
+    assert torch.equal(z1, zk)
+    hk.profile(True)
+    zk.zero_()
+    hk.apply_oras(r, zk)
+    hk.profile(False)
+    assert torch.equal(z1, zk)
+    h1.apply_precond(r, z1)
+    hk.apply_precond(r, zk)
+    assert rel(host(zk), host(z1)) <= 1e-13
+    B = dvec(b)
+    U1 = torch.zeros_like(B)
+    Uk = torch.zeros_like(B)
+    _, i1 = h1.solve(B, U1, tol=w.tol, restart=w.restart)
+    _, ik = hk.solve(B, Uk, tol=w.tol, restart=w.restart)
+    assert ik[0]["iterations"] == i1[0]["iterations"]
+    assert rel(host(Uk), host(U1)) <= 1e-10
+    Bs = torch.stack([B * (1 + 0.25 * j) for j in range(16)])
+    V1 = torch.zeros_like(Bs)
+    Vk = torch.zeros_like(Bs)
+    h1.solve(Bs, V1, tol=w.tol, restart=w.restart, block=16)
+    hk.solve(Bs, Vk, tol=w.tol, restart=w.restart, block=16)
+    assert rel(host(Vk), host(V1)) <= 1e-10
+    ro = opre.solve(P, b, M, tol=w.tol, restart=w.restart)
+    assert np.linalg.norm(host(Uk) - ro.x) <= 1e-5 * np.linalg.norm(ro.x)
+    say(f"[batches] {name} x{nb}: its={ik[0]['iterations']} oracle={ro.iterations}")
+
+
 @pytest.mark.parametrize("name", ["small_p2_2lvl", "mid_quarter_2lvl", "adapted_p2_2lvl"])
 def test_one_wave_supernode_jobs(name):
     """Forward solves of narrow supernodes by one wave each (forced on every

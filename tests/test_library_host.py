@@ -192,9 +192,14 @@ def test_batch_options_on_a_host_context():
     """The subdomain-batch and one-wave-job options are accepted by a
     host-only context, which analyses one batch and reports it."""
     w = wl.small_box(n=(4, 4, 2), order=2, n_parts=(2, 2, 1), overlap=1, coarse=False)
-    for kw in ({}, {"batches": 1}, {"sn_jobs_min": -1}, {"sn_jobs_min": 1}):
+    for kw in ({}, {"batches": 1}, {"batches": 4}, {"sn_jobs_min": -1}, {"sn_jobs_min": 1}):
         h = helm.Helm(-1)
         h.assemble(w.xyz, w.tets, w.order, w.c_tet, w.omega)
         h.precond_setup(w.part, w.n_sub, w.overlap, **kw)
         st = h.stats()
         assert st["batches"] == 1 and st["n_sub"] == 4 and st["factor_entries"] > 0
+    for bad in (-1, 5):
+        h = helm.Helm(-1)
+        h.assemble(w.xyz, w.tets, w.order, w.c_tet, w.omega)
+        with pytest.raises(helm.HelmError, match="batches"):
+            h.precond_setup(w.part, w.n_sub, w.overlap, batches=bad)
