@@ -563,6 +563,24 @@ __global__ __launch_bounds__(kWG) void csr_block_kernel(int64_t n, const int64_t
   double ar = 0, ai = 0, br = 0, bi = 0;
   const int64_t p1 = ptr[i + 1];
   int64_t p = ptr[i];
+  // eight entries per step: all column loads, then the values and the x
+  // gathers, so a lane keeps eight gathers in flight (even entries sum into
+  // a, odd ones into b, in the order of the short loop below)
+  for (; p + 8 <= p1; p += 8) {
+    int c[8];
+    double2 v[8], xv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c[u] = col[p + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = val[p + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) xv[u] = x[(int64_t)c[u] * S + r];
+#pragma unroll
+    for (int u = 0; u < 8; u += 2) {
+      cfma(ar, ai, v[u], xv[u]);
+      cfma(br, bi, v[u + 1], xv[u + 1]);
+    }
+  }
   for (; p + 2 <= p1; p += 2) {
     const int c0 = col[p], c1 = col[p + 1];
     const double2 v0 = val[p], v1 = val[p + 1];
@@ -590,7 +608,26 @@ __global__ __launch_bounds__(kWG) void spmv_real_block_kernel(int64_t n, const i
   const int64_t row = e / S;
   const int r = (int)(e % S);
   double ar = 0, ai = 0;
-  for (int64_t p = ptr[row]; p < ptr[row + 1]; ++p) {
+  const int64_t p1 = ptr[row + 1];
+  int64_t p = ptr[row];
+  // eight entries per step (loads first, then the multiply-adds in order)
+  for (; p + 8 <= p1; p += 8) {
+    int c[8];
+    double a[8];
+    double2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c[u] = col[p + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = val[p + u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = x[(int64_t)c[u] * S + r];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      ar = fma(a[u], v[u].x, ar);
+      ai = fma(a[u], v[u].y, ai);
+    }
+  }
+  for (; p < p1; ++p) {
     const double a = val[p];
     const double2 v = x[(int64_t)col[p] * S + r];
     ar = fma(a, v.x, ar);
@@ -617,13 +654,30 @@ __global__ __launch_bounds__(kWG) void coarse_update_block_kernel(
     qr = fma(z, v.x, qr);
     qi = fma(z, v.y, qi);
   }
-  for (int64_t p = aptr[row]; p < aptr[row + 1]; ++p) {
-    const int c = acol[p];
-    const double a = aval[p];
-    const double2 v = cx[(int64_t)(c & 0x7fffffff) * S + r];
+  auto az = [&](int c, double a, double2 v) {
     const bool im = c < 0;  // i v = (-v.y, v.x)
     ar = fma(a, im ? -v.y : v.x, ar);
     ai = fma(a, im ? v.x : v.y, ai);
+  };
+  const int64_t p1 = aptr[row + 1];
+  int64_t p = aptr[row];
+  // four entries of A Z per step (loads first, then the multiply-adds in order)
+  for (; p + 4 <= p1; p += 4) {
+    int c[4];
+    double a[4];
+    double2 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) c[u] = acol[p + u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = aval[p + u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = cx[(int64_t)(c[u] & 0x7fffffff) * S + r];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) az(c[u], a[u], v[u]);
+  }
+  for (; p < p1; ++p) {
+    const int c = acol[p];
+    az(c, aval[p], cx[(int64_t)(c & 0x7fffffff) * S + r]);
   }
   q[e] = make_double2(qr, qi);
   const double2 xx = x[e];
