@@ -182,133 +182,6 @@ struct Mf<float> {
   static __device__ __forceinline__ int row(int lk, int j) { return 4 * lk + j; }
 };
 
-// Accumulates P (tile, column-major, ld = nr) times vin (k x 16, LDS, rows
-// beyond cn zero) over columns [0, cn) into the four row blocks.
-template <class T>
-__device__ __forceinline__ void mfma_tile(const typename Mf<T>::C2* __restrict__ P, int nr, int cn,
-                                          const typename Mf<T>::C2* vin, typename Mf<T>::V4* dre,
-                                          typename Mf<T>::V4* dim) {
-  using C2 = typename Mf<T>::C2;
-  const int lane = threadIdx.x, lr = lane & 15, lk = lane >> 4;
-  const int nrb = (nr + 15) >> 4;
-  for (int k0 = 0; k0 < cn; k0 += 4) {
-    const int k = k0 + lk;
-    const C2 bv = vin[k0 * 16 + lane];
-    C2 a[4];
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
-      const int row = 16 * rb + lr;
-      a[rb] = (rb < nrb && row < nr && k < cn) ? P[(int64_t)k * nr + row] : C2{0, 0};
-    }
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
-      if (rb >= nrb) break;
-      dre[rb] = Mf<T>::mma(a[rb].x, bv.x, dre[rb]);
-      dre[rb] = Mf<T>::mma(-a[rb].y, bv.y, dre[rb]);
-      dim[rb] = Mf<T>::mma(a[rb].x, bv.y, dim[rb]);
-      dim[rb] = Mf<T>::mma(a[rb].y, bv.x, dim[rb]);
-    }
-  }
-}
-
-template <class T, int kCoarse>
-__global__ __launch_bounds__(64) void fwd_mfma_kernel(const Tile* __restrict__ tiles, Batch b,
-                                                      const double2* __restrict__ bin, double2* __restrict__ yb,
-                                                      double2* __restrict__ ubb) {
-  using C2 = typename Mf<T>::C2;
-  using V4 = typename Mf<T>::V4;
-  constexpr int S = 16, CB = kBlkLds / S;
-  __shared__ C2 vin[kBlkLds];
-  const Tile t = tiles[blockIdx.x];
-  const int lane = threadIdx.x;
-  const int sn = t.sn, c0 = b.sn_c0[sn], w = b.sn_w[sn], frow0 = b.sn_frow0[sn];
-  const C2* __restrict__ P = reinterpret_cast<const C2*>(b.pf) + t.off;
-  V4 dre[4], dim[4];
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb) dre[rb] = dim[rb] = V4{0, 0, 0, 0};
-  for (int cb = 0; cb < t.ncols; cb += CB) {
-    const int cn = min(CB, t.ncols - cb);
-    const int cn4 = (cn + 3) & ~3;
-    for (int e = lane; e < cn4 * S; e += 64) {
-      const int k = e / S, r = e % S, kk = cb + k;
-      double2 v = make_double2(0.0, 0.0);
-      if (k < cn) {
-        v = bin[(int64_t)b.bidx[c0 + kk] * S + r];
-        const int fr = frow0 + kk;
-        for (int q = b.fcon_ptr[fr]; q < b.fcon_ptr[fr + 1]; ++q) {
-          const double2 u = ubb[(int64_t)b.fcon_idx[q] * S + r];
-          v.x -= u.x;
-          v.y -= u.y;
-        }
-      }
-      vin[e] = C2{(T)v.x, (T)v.y};
-    }
-    __syncthreads();
-    mfma_tile<T>(P + (int64_t)cb * t.nrows, t.nrows, cn, vin, dre, dim);
-    __syncthreads();
-  }
-  const int lr = lane & 15, lk = lane >> 4;
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int rloc = 16 * rb + Mf<T>::row(lk, j);
-      if (rloc >= t.nrows) continue;
-      const int row = t.row0 + rloc;
-      double ar = (double)dre[rb][j], ai = (double)dim[rb][j];
-      if (row < w) {
-        yb[(int64_t)(c0 + row) * S + lr] = make_double2(ar, ai);
-      } else {
-        const int fr = frow0 + row;
-        for (int q = b.fcon_ptr[fr]; q < b.fcon_ptr[fr + 1]; ++q) {
-          const double2 u = ubb[(int64_t)b.fcon_idx[q] * S + lr];
-          ar += u.x;
-          ai += u.y;
-        }
-        ubb[(int64_t)(b.sn_uoff[sn] + row - w) * S + lr] = make_double2(ar, ai);
-      }
-    }
-}
-
-template <class T, int kCoarse>
-__global__ __launch_bounds__(64) void bwd_mfma_kernel(const Tile* __restrict__ tiles, Batch b,
-                                                      const double2* __restrict__ yb, double2* __restrict__ xb) {
-  using C2 = typename Mf<T>::C2;
-  using V4 = typename Mf<T>::V4;
-  constexpr int S = 16, CB = kBlkLds / S;
-  __shared__ C2 vin[kBlkLds];
-  const Tile t = tiles[blockIdx.x];
-  const int lane = threadIdx.x;
-  const int sn = t.sn, c0 = b.sn_c0[sn], w = b.sn_w[sn];
-  const int64_t roff = b.sn_roff[sn];
-  const C2* __restrict__ P = reinterpret_cast<const C2*>(b.pb) + t.off;
-  V4 dre[4], dim[4];
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb) dre[rb] = dim[rb] = V4{0, 0, 0, 0};
-  for (int cb = 0; cb < t.ncols; cb += CB) {
-    const int cn = min(CB, t.ncols - cb);
-    const int cn4 = (cn + 3) & ~3;
-    for (int e = lane; e < cn4 * S; e += 64) {
-      const int k = e / S, r = e % S, c = t.col0 + cb + k;
-      double2 v = make_double2(0.0, 0.0);
-      if (k < cn) v = c < w ? yb[(int64_t)(c0 + c) * S + r] : xb[(int64_t)b.rows[roff + (c - w)] * S + r];
-      vin[e] = C2{(T)v.x, (T)v.y};
-    }
-    __syncthreads();
-    mfma_tile<T>(P + (int64_t)cb * t.nrows, t.nrows, cn, vin, dre, dim);
-    __syncthreads();
-  }
-  const int lr = lane & 15, lk = lane >> 4;
-#pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int rloc = 16 * rb + Mf<T>::row(lk, j);
-      if (rloc < t.nrows)
-        xb[(int64_t)(c0 + t.row0 + rloc) * S + lr] = make_double2((double)dre[rb][j], (double)dim[rb][j]);
-    }
-}
-
 // ---- staged MFMA form ------------------------------------------------------
 template <class T>
 __global__ __launch_bounds__(kWG) void gather_fwd_kernel(const int32_t* __restrict__ sns, Batch b,
@@ -751,17 +624,6 @@ void fwd_level_block(const Batch& b, int64_t tile0, int64_t ntiles, int S, const
   auto in = reinterpret_cast<const double2*>(bin);
   auto y = reinterpret_cast<double2*>(yb);
   auto u = reinterpret_cast<double2*>(ubb);
-  if (S == 16 && !coarse) {
-    if (b.c64)
-      fwd_mfma_kernel<float, 0><<<(unsigned)ntiles, 64, 0, s>>>(t, b, in, y, u);
-    else
-      fwd_mfma_kernel<double, 0><<<(unsigned)ntiles, 64, 0, s>>>(t, b, in, y, u);
-    return;
-  }
-  if (S == 16) {
-    fwd_mfma_kernel<double, 1><<<(unsigned)ntiles, 64, 0, s>>>(t, b, in, y, u);
-    return;
-  }
   with_width(S, [&](auto w) {
     constexpr int W = decltype(w)::value;
     if (coarse)
@@ -779,17 +641,6 @@ void bwd_level_block(const Batch& b, int64_t tile0, int64_t ntiles, int S, const
   const Tile* t = b.tb + tile0;
   auto y = reinterpret_cast<const double2*>(yb);
   auto x = reinterpret_cast<double2*>(xb);
-  if (S == 16 && !coarse) {
-    if (b.c64)
-      bwd_mfma_kernel<float, 0><<<(unsigned)ntiles, 64, 0, s>>>(t, b, y, x);
-    else
-      bwd_mfma_kernel<double, 0><<<(unsigned)ntiles, 64, 0, s>>>(t, b, y, x);
-    return;
-  }
-  if (S == 16) {
-    bwd_mfma_kernel<double, 1><<<(unsigned)ntiles, 64, 0, s>>>(t, b, y, x);
-    return;
-  }
   with_width(S, [&](auto w) {
     constexpr int W = decltype(w)::value;
     if (coarse)
