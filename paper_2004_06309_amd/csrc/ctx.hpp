@@ -105,8 +105,8 @@ struct BatchDev {
   DVec<unsigned char> stage;
   // > 0: grid of the single cooperative launch that runs the whole solve
   int coop = 0;
-  // backward-sweep outputs inside a buffer shared with another batch (the
-  // second subdomain batch writes after the first), else x / x_b
+  // backward-sweep outputs inside a buffer shared by all subdomain batches
+  // (each batch writes after the batches before it), else x / x_b
   double* xo = nullptr;
   double* xo_b = nullptr;
   double* xout() const { return xo ? xo : x.p; }
