@@ -252,7 +252,7 @@ void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<co
 
 // solver.cpp
 void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<const std::vector<int64_t>*>& in_idx,
-                  const std::vector<NumericOut>& num, int64_t sn_jobs_min, BatchHost& B);
+                  const std::vector<NumericOut>& num, int64_t sn_jobs_min, bool c64, BatchHost& B);
 void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overlap, const helm_mesh* coarse,
                    const helm_precond_opts* opts);
 void upload_matrix(Ctx& c);

@@ -135,9 +135,12 @@ Profiler::~Profiler() {
 // every forward (by height) and backward (by depth) level.  in_idx[i][l] is
 // the index in the solve's input vector of row l (original order) of matrix i.
 void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<const std::vector<int64_t>*>& in_idx,
-                  const std::vector<NumericOut>& num, int64_t sn_jobs_min, BatchHost& B) {
+                  const std::vector<NumericOut>& num, int64_t sn_jobs_min, bool c64, BatchHost& B) {
   const int nm = (int)Ss.size();
   B = BatchHost();
+  // waves per tile from the tile's bytes per row: a complex64 column is
+  // half a complex128 one, so a wave takes twice the columns
+  auto wpt_of = [c64](int32_t ncols) { return dev::waves_per_tile(c64 ? (ncols + 1) / 2 : ncols); };
   std::vector<int64_t> pos0(nm + 1, 0), sn0(nm + 1, 0), pf0(nm + 1, 0), pb0(nm + 1, 0), u0(nm + 1, 0),
       fr0(nm + 1, 0);
   int32_t maxlev_f = 0, maxlev_b = 0;
@@ -304,7 +307,7 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
           if (a.sn != b.sn) return a.sn < b.sn;
           return a.row0 < b.row0;
         }
-        const int wa = dev::waves_per_tile(a.ncols), wb = dev::waves_per_tile(b.ncols);
+        const int wa = wpt_of(a.ncols), wb = wpt_of(b.ncols);
         if (wa != wb) return wa > wb;
         return (int64_t)a.nrows * a.ncols > (int64_t)b.nrows * b.ncols;
       });
@@ -312,10 +315,10 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
       int64_t ktile = -1;
       while (q < l.size()) {
         if (ktile < 0 && narrow(l[q])) ktile = (int64_t)tasks.size() - lev.back();
-        const int wpt = dev::waves_per_tile(l[q].ncols);
+        const int wpt = wpt_of(l[q].ncols);
         const int per = 4 / wpt;
         size_t e = q;
-        while (e < l.size() && (int)(e - q) < per && dev::waves_per_tile(l[e].ncols) == wpt &&
+        while (e < l.size() && (int)(e - q) < per && wpt_of(l[e].ncols) == wpt &&
                narrow(l[e]) == narrow(l[q]))
           ++e;
         tasks.push_back({(int32_t)(tiles.size() + q), (int16_t)(e - q), (int16_t)wpt});
@@ -470,7 +473,7 @@ void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symb
   seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   // one-wave supernode jobs for complex128 panels (with complex64 panels
   // the narrow tiles stream faster through the tile kernel)
-  layout_batch(Ss, in_idx, num, c64 ? -1 : sn_jobs_min, B);
+  layout_batch(Ss, in_idx, num, c64 ? -1 : sn_jobs_min, c64, B);
   if (!numeric) return;
   // Panels move from factorisation order (per matrix, per supernode) to
   // solve order: each level's tiles contiguous, in the order its workgroups
