@@ -54,6 +54,9 @@ struct BatchHost {
   std::vector<int32_t> c0, w, uoff, frow0;
   std::vector<int64_t> roff;
   std::vector<int32_t> rows, bidx, fcon_ptr, fcon_idx;
+  // per front row its first two child-update indices (-1: none), or
+  // (-2 - list start, 0) for a row with more than two (int2 pairs)
+  std::vector<int32_t> fcon2;
   std::vector<dev::Tile> tf, tb;
   std::vector<dev::Task> kf, kb;      // workgroup tasks
   std::vector<int64_t> lev_f, lev_b;  // task ranges per level
@@ -81,7 +84,7 @@ struct BatchDev {
   DVec<dev::Tile> tf, tb;
   DVec<dev::Task> kf, kb;
   int c64 = 0;
-  DVec<int32_t> c0, w, uoff, frow0, rows, bidx, fcon_ptr, fcon_idx;
+  DVec<int32_t> c0, w, uoff, frow0, rows, bidx, fcon_ptr, fcon_idx, fcon2;
   DVec<int64_t> roff;
   DVec<unsigned char> pf, pb;  // panels, complex128 or complex64 entries
   DVec<double> ubuf, y, x;
@@ -114,7 +117,7 @@ struct BatchDev {
   dev::LevelRanges ranges{};
   dev::Batch view() const;
   void reset() {
-    for (auto* v : {&c0, &w, &uoff, &frow0, &rows, &bidx, &fcon_ptr, &fcon_idx}) v->reset();
+    for (auto* v : {&c0, &w, &uoff, &frow0, &rows, &bidx, &fcon_ptr, &fcon_idx, &fcon2}) v->reset();
     for (auto* v : {&ubuf, &y, &x}) v->reset();
     pf.reset();
     pb.reset();

@@ -73,6 +73,20 @@ __device__ __forceinline__ void tile_dot(const PT* __restrict__ p, int nr, const
   ai += bi;
 }
 
+// Calls f(i) for the child-update entries routed to front row fr, in list
+// order: rows with at most two read them from their index pair (one load),
+// longer lists from fcon_ptr / fcon_idx.
+template <class F>
+__device__ __forceinline__ void for_children(const Batch& b, int fr, F&& f) {
+  const int2 c = b.fcon2[fr];
+  if (c.x >= 0) {
+    f(c.x);
+    if (c.y >= 0) f(c.y);
+  } else if (c.x < -1) {
+    for (int e = -2 - c.x; e < b.fcon_ptr[fr + 1]; ++e) f(b.fcon_idx[e]);
+  }
+}
+
 // Lanes per tile row group: a tile with few rows spreads its columns over
 // 64 / R lane groups of R = nrows lanes (the last 64 mod R lanes idle).
 __device__ __forceinline__ int row_group(int nrows) { return nrows <= 32 ? max(nrows, 1) : 64; }
@@ -120,12 +134,11 @@ __device__ __forceinline__ void fwd_task(const Task& task, const Batch& b, const
   int uo = 0;
   if (out && row >= w) {
     uo = b.sn_uoff[s] + row - w;
-    const int fr = frow0 + row;
-    for (int e = b.fcon_ptr[fr]; e < b.fcon_ptr[fr + 1]; ++e) {
-      double2 u = ub[b.fcon_idx[e]];
+    for_children(b, frow0 + row, [&](int i) {
+      const double2 u = ub[i];
       er += u.x;
       ei += u.y;
-    }
+    });
   }
   double ar = 0, ai = 0;
   // all waves of a workgroup run the same number of passes: one, unless the
@@ -137,12 +150,11 @@ __device__ __forceinline__ void fwd_task(const Task& task, const Batch& b, const
     for (int k = sp.part * 64 + lane; k < cn; k += 64 * sp.wpt) {
       const int kk = cb + k;
       double2 v = bin[b.bidx[c0 + kk]];
-      const int fr = frow0 + kk;
-      for (int e = b.fcon_ptr[fr]; e < b.fcon_ptr[fr + 1]; ++e) {
-        double2 u = ub[b.fcon_idx[e]];
+      for_children(b, frow0 + kk, [&](int i) {
+        const double2 u = ub[i];
         v.x -= u.x;
         v.y -= u.y;
-      }
+      });
       vt[k] = v;
     }
     __syncthreads();
@@ -287,8 +299,6 @@ __global__ __launch_bounds__(kWG) void fwd_sn_kernel(const SnJob* __restrict__ j
                                                      const double2* __restrict__ bin) {
   const int lane = threadIdx.x & 63;
   const double2* __restrict__ ub = reinterpret_cast<const double2*>(b.ubuf);
-  const int* __restrict__ fptr = b.fcon_ptr;
-  const int* __restrict__ fidx = b.fcon_idx;
   // the job index is wave-uniform, so the job lives in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (int j = blockIdx.x * 4 + wave; j < njobs; j += gridDim.x * 4) {
@@ -298,12 +308,11 @@ __global__ __launch_bounds__(kWG) void fwd_sn_kernel(const SnJob* __restrict__ j
     double2 v = make_double2(0.0, 0.0);
     if (lane < w) {
       v = bin[b.bidx[jb.c0 + lane]];
-      const int fr = jb.frow0 + lane;
-      for (int e = fptr[fr]; e < fptr[fr + 1]; ++e) {
-        const double2 u = ub[fidx[e]];
+      for_children(b, jb.frow0 + lane, [&](int i) {
+        const double2 u = ub[i];
         v.x -= u.x;
         v.y -= u.y;
-      }
+      });
     }
     const PT* __restrict__ P = reinterpret_cast<const PT*>(b.pf) + jb.off;
     for (int q0 = 0; q0 * 64 < m; q0 += 4) {
@@ -316,14 +325,12 @@ __global__ __launch_bounds__(kWG) void fwd_sn_kernel(const SnJob* __restrict__ j
         rows[q] = q < nq ? min(64, m - (q0 + q) * 64) : 0;
         acc[q] = make_double2(0.0, 0.0);
         const int row = (q0 + q) * 64 + lane;
-        if (q < nq && lane < rows[q] && row >= w) {
-          const int fr = jb.frow0 + row;
-          for (int e = fptr[fr]; e < fptr[fr + 1]; ++e) {
-            const double2 u = ub[fidx[e]];
+        if (q < nq && lane < rows[q] && row >= w)
+          for_children(b, jb.frow0 + row, [&](int i) {
+            const double2 u = ub[i];
             acc[q].x += u.x;
             acc[q].y += u.y;
-          }
-        }
+          });
       }
       const PT* Pq = P + (int64_t)q0 * 64 * w;
       if (nq == 1)

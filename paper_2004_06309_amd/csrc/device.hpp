@@ -66,6 +66,7 @@ struct Batch {
   const int32_t* bidx = nullptr;   // pivot position -> input-vector index
   const int32_t* fcon_ptr = nullptr; // front row -> child update entries
   const int32_t* fcon_idx = nullptr;
+  const int2* fcon2 = nullptr;     // front row -> first two entries, or (-2 - list start, 0)
   const int32_t* sn_r = nullptr;   // |R_s|
   const int64_t* goff_f = nullptr; // column offset of the supernode's staged block (forward level scratch)
   const int64_t* goff_b = nullptr; // same for the backward level scratch

@@ -82,6 +82,7 @@ dev::Batch BatchDev::view() const {
   b.bidx = bidx.p;
   b.fcon_ptr = fcon_ptr.p;
   b.fcon_idx = fcon_idx.p;
+  b.fcon2 = reinterpret_cast<const int2*>(fcon2.p);
   b.pf = pf.p;
   b.pb = pb.p;
   b.ubuf = ubuf.p;
@@ -252,6 +253,18 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
     std::vector<int32_t> fill(B.fcon_ptr.begin(), B.fcon_ptr.end() - 1);
     for (int i = 0; i < nm; ++i)
       for (auto& e : fcon_m[i]) B.fcon_idx[fill[e.first]++] = e.second;
+  }
+  // the same lists as index pairs (one load for the common rows)
+  B.fcon2.assign(2 * (size_t)std::max<int64_t>(fr0[nm], 1), -1);
+  for (int64_t f = 0; f < fr0[nm]; ++f) {
+    const int32_t e0 = B.fcon_ptr[f], cnt = B.fcon_ptr[f + 1] - e0;
+    if (cnt > 2) {
+      B.fcon2[2 * f] = -2 - e0;
+      B.fcon2[2 * f + 1] = 0;
+    } else {
+      if (cnt >= 1) B.fcon2[2 * f] = B.fcon_idx[e0];
+      if (cnt == 2) B.fcon2[2 * f + 1] = B.fcon_idx[e0 + 1];
+    }
   }
   // algorithmic bytes per level: every panel entry once, plus the vector
   // entries each supernode gathers and writes
@@ -553,6 +566,7 @@ void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symb
   Dv.bidx.upload(B.bidx);
   Dv.fcon_ptr.upload(B.fcon_ptr);
   Dv.fcon_idx.upload(B.fcon_idx);
+  Dv.fcon2.upload(B.fcon2);
   Dv.ubuf.alloc(2 * std::max<int64_t>(B.nu, 1));
   Dv.y.alloc(2 * std::max<int64_t>(B.npos, 1));
   Dv.x.alloc(2 * std::max<int64_t>(B.npos, 1));
