@@ -102,7 +102,9 @@ struct Split {
 
 __device__ __forceinline__ Split split_of(const Task& task, int chunk) {
   Split sp;
-  const int wv = threadIdx.x >> 6;
+  // the wave index is the same on all lanes: scalar, so the wave's tile
+  // descriptor is a scalar load
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   sp.wpt = task.wpt;
   sp.my = wv / sp.wpt;
   sp.part = wv % sp.wpt;
