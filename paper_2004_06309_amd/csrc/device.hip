@@ -120,7 +120,7 @@ template <class PT>
 __device__ __forceinline__ void fwd_task(const Task& task, const Batch& b, const double2* __restrict__ bin,
                                          double2* vin, double2 (*red)[64], int chunk) {
   const Split sp = split_of(task, chunk);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   Tile t{};
   if (sp.has) t = b.tf[task.tile0 + sp.my];
   const int s = t.sn, c0 = t.c0, w = t.w, frow0 = t.aux;
@@ -187,7 +187,7 @@ template <class PT>
 __device__ __forceinline__ void bwd_task(const Task& task, const Batch& b, double2* vin, double2 (*red)[64],
                                          int chunk) {
   const Split sp = split_of(task, chunk);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   Tile t{};
   if (sp.has) t = b.tb[task.tile0 + sp.my];
   const int c0 = t.c0, w = t.w;

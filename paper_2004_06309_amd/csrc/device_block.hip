@@ -245,7 +245,7 @@ __device__ __forceinline__ void mfma_tile4(const Tile& t, const typename Mf<T>::
                                            const typename Mf<T>::C2* __restrict__ Bk, typename Mf<T>::V4* dre,
                                            typename Mf<T>::V4* dim) {
   using C2 = typename Mf<T>::C2;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lr = lane & 15, lk = lane >> 4;
   const int nr = t.nrows, cn = t.ncols, nrb = (nr + 15) >> 4;
   auto load = [&](int k0, C2& bv, C2 (&a)[4]) {
     const int k = k0 + lk;
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(kWG) void level_mfma_kernel(const Tile* __restrict_
   // partial sums of the 4 waves, two row blocks at a time: [wave][rb2][j][lane]
   __shared__ C2 red[4][2][4][64];
   const Tile t = tiles[blockIdx.x];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int sn = t.sn, c0 = b.sn_c0[sn], w = b.sn_w[sn];
   const C2* __restrict__ P = reinterpret_cast<const C2*>(kFwd ? b.pf : b.pb) + t.off;
   const C2* Bk = G + ((kFwd ? b.goff_f[sn] : b.goff_b[sn]) + t.col0) * 16;
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(kWG) void level_mfma_narrow_kernel(const Tile* __re
                                                                 double2* __restrict__ ubb) {
   using C2 = typename Mf<T>::C2;
   using V4 = typename Mf<T>::V4;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, lr = lane & 15, lk = lane >> 4;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lr = lane & 15, lk = lane >> 4;
   const int64_t ti = (int64_t)blockIdx.x * (kWG / 64) + wv;
   if (ti >= ntiles) return;  // a whole wave; the kernel has no barrier
   const Tile t = tiles[ti];
