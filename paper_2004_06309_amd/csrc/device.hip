@@ -652,7 +652,7 @@ __global__ __launch_bounds__(kWG) void gs_pass_kernel(int64_t n, PtrSetC Vs, int
   double2* ured = wn + kGsRows;         // [4][kGsRows]
   double2* dred = ured + 4 * kGsRows;   // [4][kGsMaxCols]
   double* red = reinterpret_cast<double*>(dred + 4 * kGsMaxCols);
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (kUpdate && tid < ncol) hs[tid] = h[tid];
   double dr = 0, di = 0;  // dots: column `lane`, rows [16 wv, 16 wv + 16) of every tile
   double nrm = 0;         // norm: row `tid` of every tile
@@ -755,7 +755,7 @@ __global__ __launch_bounds__(kWG) void gs_dots_kernel(int64_t n, PtrSetC Vs, int
   double2* wn = lds + (size_t)ncol * (kGsRows + 1);
   double2* dred = wn + kGsRows;           // [4][kGsMaxCols]
   double2* ered = dred + 4 * kGsMaxCols;  // [4][kGsMaxCols]
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, j = ncol - 1;
+  const int tid = threadIdx.x, lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6), j = ncol - 1;
   double dr = 0, di = 0, er = 0, ei = 0;  // dots of column `lane` with w and with v_j
   const int64_t ntiles = (n + kGsRows - 1) / kGsRows;
   double2 a[kU];
