@@ -238,8 +238,9 @@ __device__ __forceinline__ float2 ldp(const float2* p) {
 
 // 4 waves per tile: wave q accumulates the k-steps q, q + 4, ... of the
 // tile, then the partial accumulators are summed through LDS.  The loads of
-// the next two k-steps are issued before the MFMAs of the current one, so a
-// wave keeps about three steps of panel in flight while its MFMAs run.
+// the next two k-steps (complex64 panels: the next one) are issued before
+// the MFMAs of the current one, so a wave keeps panel in flight while its
+// MFMAs run.
 template <class T, int kFwd>
 __device__ __forceinline__ void mfma_tile4(const Tile& t, const typename Mf<T>::C2* __restrict__ P,
                                            const typename Mf<T>::C2* __restrict__ Bk, typename Mf<T>::V4* dre,
@@ -256,33 +257,49 @@ __device__ __forceinline__ void mfma_tile4(const Tile& t, const typename Mf<T>::
       a[rb] = (rb < nrb && row < nr && k < cn) ? ldp(P + (int64_t)k * nr + row) : C2{0, 0};
     }
   };
-  C2 b0, b1, a0[4], a1[4];
-  int k0 = 4 * wv;
-  load(k0, b0, a0);
-  load(k0 + 16, b1, a1);
-  for (; k0 < cn; k0 += 16) {
-    C2 b2, a2[4];
-    load(k0 + 32, b2, a2);
+  auto step = [&](const C2& bv, const C2 (&a)[4]) {
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
       if (rb >= nrb) break;
-      dre[rb] = Mf<T>::mma(a0[rb].x, b0.x, dre[rb]);
-      dre[rb] = Mf<T>::mma(-a0[rb].y, b0.y, dre[rb]);
-      dim[rb] = Mf<T>::mma(a0[rb].x, b0.y, dim[rb]);
-      dim[rb] = Mf<T>::mma(a0[rb].y, b0.x, dim[rb]);
+      dre[rb] = Mf<T>::mma(a[rb].x, bv.x, dre[rb]);
+      dre[rb] = Mf<T>::mma(-a[rb].y, bv.y, dre[rb]);
+      dim[rb] = Mf<T>::mma(a[rb].x, bv.y, dim[rb]);
+      dim[rb] = Mf<T>::mma(a[rb].y, bv.x, dim[rb]);
     }
-    b0 = b1;
-    b1 = b2;
+  };
+  C2 b0, a0[4];
+  int k0 = 4 * wv;
+  load(k0, b0, a0);
+  if constexpr (sizeof(T) == 4) {
+    // FP32 MFMA: one step ahead, so seven waves fit per SIMD
+    for (; k0 < cn; k0 += 16) {
+      C2 b1, a1[4];
+      load(k0 + 16, b1, a1);
+      step(b0, a0);
+      b0 = b1;
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
-      a0[rb] = a1[rb];
-      a1[rb] = a2[rb];
+      for (int rb = 0; rb < 4; ++rb) a0[rb] = a1[rb];
+    }
+  } else {
+    C2 b1, a1[4];
+    load(k0 + 16, b1, a1);
+    for (; k0 < cn; k0 += 16) {
+      C2 b2, a2[4];
+      load(k0 + 32, b2, a2);
+      step(b0, a0);
+      b0 = b1;
+      b1 = b2;
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        a0[rb] = a1[rb];
+        a1[rb] = a2[rb];
+      }
     }
   }
 }
 
 template <class T, int kFwd, int kCoarse>
-__global__ __launch_bounds__(kWG) void level_mfma_kernel(const Tile* __restrict__ tiles, Batch b,
+__global__ __launch_bounds__(kWG, sizeof(T) == 4 ? 4 : 1) void level_mfma_kernel(const Tile* __restrict__ tiles, Batch b,
                                                          const typename Mf<T>::C2* __restrict__ G,
                                                          double2* __restrict__ out, double2* __restrict__ ubb) {
   using C2 = typename Mf<T>::C2;
