@@ -366,7 +366,7 @@ __global__ __launch_bounds__(kWG, sizeof(T) == 4 ? 4 : 1) void level_mfma_kernel
 // accumulator register j of lane l holds row 4 j + l / 16, FP32 row
 // 4 (l / 16) + j, right-hand side l % 16).
 template <class T, int kFwd, int kCoarse>
-__global__ __launch_bounds__(kWG) void level_mfma_narrow_kernel(const Tile* __restrict__ tiles, int64_t ntiles,
+__global__ __launch_bounds__(kWG, sizeof(T) == 4 ? 8 : 5) void level_mfma_narrow_kernel(const Tile* __restrict__ tiles, int64_t ntiles,
                                                                 Batch b, const typename Mf<T>::C2* __restrict__ G,
                                                                 double2* __restrict__ out,
                                                                 double2* __restrict__ ubb) {
