@@ -394,6 +394,9 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
       for (int64_t q = lev[l]; q < lev[l + 1]; ++q) {
         int64_t wide = 0;
         for (int u = 0; u < K[q].ntile; ++u) wide = std::max<int64_t>(wide, T[K[q].tile0 + u].ncols);
+        // a task of one or two waves per tile streams each tile in one pass
+        if (K[q].wpt < 4 && (4 / K[q].wpt) * wide > dev::kLevelChunkMax)
+          fail(HELM_EINVAL, "internal: a level tile is wider than its LDS input slot");
         c = std::max<int64_t>(c, K[q].wpt == 4 ? std::min<int64_t>(wide, dev::kLevelChunkMax) : (4 / K[q].wpt) * wide);
       }
       out.push_back((int32_t)std::min<int64_t>((c + 63) / 64 * 64, dev::kLevelChunkMax));
