@@ -361,6 +361,54 @@ def test_more_subdomain_batches(name, nb):
     say(f"[batches] {name} x{nb}: its={ik[0]['iterations']} oracle={ro.iterations}")
 
 
+def test_three_batches_with_complex64_factors_and_the_server():
+    """Three subdomain batches with complex64 factors: local solves bit for
+    bit against one batch (same rounded panels), the 16-column block path;
+    then the continuous-batching server on a three-batch context (its block
+    steps fork the local solves onto the batch streams) against solo solves
+    and the oracle."""
+    w = WORKLOADS["mid_quarter_2lvl"]()
+    P, b, M = opre.build(w)
+    h1 = helm.from_workload(w, c64=True, batches=1)
+    h3 = helm.from_workload(w, c64=True, batches=3)
+    assert h3.stats()["batches"] == 3 and h3.stats()["factor_c64"] == 1
+    r = dvec(rand_vec(P.n, 47))
+    z1 = torch.empty_like(r)
+    z3 = torch.empty_like(r)
+    h1.apply_oras(r, z1)
+    h3.apply_oras(r, z3)
+    assert torch.equal(z1, z3)
+    assert rel(host(z3), M.one_level(host(r))) <= 1e-4
+    B = dvec(b)
+    Bs = torch.stack([B * (1 + 0.25 * j) for j in range(16)])
+    V1 = torch.zeros_like(Bs)
+    V3 = torch.zeros_like(Bs)
+    h1.solve(Bs, V1, tol=w.tol, restart=w.restart, block=16)
+    h3.solve(Bs, V3, tol=w.tol, restart=w.restart, block=16)
+    assert rel(host(V3), host(V1)) <= 1e-10
+    ro = opre.solve(P, b, M, tol=w.tol, restart=w.restart)
+    # server on the three-batch context
+    lo, hi = w.xyz.min(axis=0), w.xyz.max(axis=0)
+    pts = lo + (hi - lo) * np.random.default_rng(29).uniform(0.1, 0.9, (6, 3))
+    Bp = np.stack([P.point_source(p) for p in pts])
+    Bd = dvec(Bp)
+    solo = torch.zeros_like(Bd)
+    for q in range(6):
+        h3.solve(Bd[q].contiguous(), solo[q], tol=w.tol, restart=w.restart)
+    U = torch.zeros_like(Bd)
+    srv = helm.Server(h3, slots=4, restart=w.restart, tol=w.tol)
+    ev = _serve([srv], [[(2 * q, Bd[q], U[q], 300 + q) for q in range(6)]])
+    srv.close()
+    u, us = host(U), host(solo)
+    for q in range(6):
+        e = ev[300 + q]
+        assert e["converged"] == 1 and e["status"] == helm.HELM_OK
+        assert np.linalg.norm(Bp[q] - P.A @ u[q]) / np.linalg.norm(Bp[q]) <= w.tol
+        assert np.linalg.norm(u[q] - us[q]) <= 1e-5 * np.linalg.norm(us[q])
+    assert np.linalg.norm(host(V3)[0] - ro.x) <= 1e-5 * np.linalg.norm(ro.x)
+    say(f"[batches c64] served its={[ev[300 + q]['iterations'] for q in range(6)]}")
+
+
 @pytest.mark.parametrize("name", ["small_p2_2lvl", "mid_quarter_2lvl", "adapted_p2_2lvl"])
 def test_one_wave_supernode_jobs(name):
     """Forward solves of narrow supernodes by one wave each (forced on every
