@@ -223,6 +223,12 @@ class Helm:
     def precond_setup(self, part, n_sub, overlap, coarse_xyz=None, coarse_tets=None, leaf_size=0, c64=False,
                       coarse_leaf_size=0, tile_rows=0, coarse_tile_rows=0, factor_on_host=False, sn_jobs_min=0,
                       batches=0):
+        """helm_precond_setup: subdomains from the tet partition `part` with
+        `overlap` layers, the optional P1 coarse mesh, then the factorisation.
+        c64: complex64 factors; tile_rows / coarse_tile_rows: 16, 32 or 64
+        (0: 64 / 16); sn_jobs_min: one-wave supernode jobs threshold (0:
+        default, -1: never); batches: 1 to 4 subdomain batches whose level
+        sweeps run concurrently (0: 2)."""
         part = np.ascontiguousarray(part, dtype=np.int32)
         opts = PrecondOpts(int(leaf_size), 1 if c64 else 0, int(coarse_leaf_size), int(tile_rows),
                            int(coarse_tile_rows), 1 if factor_on_host else 0, int(sn_jobs_min), int(batches))
