@@ -84,6 +84,22 @@ typedef struct helm_precond_opts {
                               its own (one after the other while
                               helm_profile is on); 0 = 2; other values
                               fail with HELM_EINVAL                       */
+  int32_t perturb_pivots;  /* a pivot with |p| <= 1000 eps max|a_ij| of its
+                              matrix (zero to working precision, after
+                              partial pivoting inside the front) makes
+                              helm_precond_setup fail with HELM_ESINGULAR;
+                              1: replace it by sqrt(eps) max|a_ij| instead,
+                              count it in helm_precond_stats.n_perturbed
+                              and return HELM_OK                          */
+  int32_t coarse_launch;   /* coarse solve: 0 = the faster of the two forms
+                              as timed at setup; 1 = one launch per level;
+                              2 = one cooperative launch with a grid
+                              barrier per level (HELM_EINVAL where the
+                              device cannot co-schedule it).  The
+                              cooperative form is used only after its
+                              result on a fixed right-hand side matched the
+                              per-level launches at setup (to 1e-13; with
+                              2 a mismatch fails with HELM_EDEVICE)        */
 } helm_precond_opts;
 
 enum {
@@ -120,13 +136,22 @@ typedef struct helm_solve_info {
 typedef struct helm_server helm_server;
 
 typedef struct helm_server_opts {
-  int32_t slots;           /* requests in flight, 1..16; 0 = as many as the
-                              free device memory allows (at most 16)      */
+  int32_t slots;           /* requests in flight at most, 1..16; 0 = 16;
+                              each slot opens only when its memory fits
+                              (mem_bytes)                                  */
   int32_t restart;         /* GMRES(m) restart length, 1..50, 0 = 50       */
   int32_t maxit;           /* Arnoldi steps per request, 0 = 1000          */
   int32_t flags;           /* HELM_SOLVE_CGS2: classic CGS2; other bits
                               are ignored                                  */
   double tol;              /* true relative residual, 0 = 1e-6             */
+  double mem_bytes;        /* device memory the server may hold for its
+                              slots (each slot's Krylov basis, 16 (2 m + 2) n
+                              bytes, plus the block buffers of the widest
+                              block in flight); 0 = three quarters of the
+                              free device memory at creation.  A request is
+                              admitted into a slot only when that slot's
+                              memory fits (slots open lowest first and are
+                              kept once opened); otherwise it stays queued */
 } helm_server_opts;
 
 typedef struct helm_server_event {
@@ -155,7 +180,8 @@ typedef struct helm_precond_stats {
   int32_t coarse_grid;     /* workgroups of the one-launch cooperative coarse
                               solve; 0 = one launch per level              */
   int32_t factor_on_host;  /* 1 if the numeric factorisation ran on the host */
-  int32_t n_perturbed;     /* zero pivots replaced by sqrt(eps) max|a_ij|   */
+  int32_t n_perturbed;     /* tiny pivots replaced by sqrt(eps) max|a_ij|
+                              (only with perturb_pivots)                  */
   double factor_seconds;   /* wall time of the numeric factorisation       */
   int32_t batches;         /* subdomain batches (1 .. 4)                   */
   int32_t reserved;
@@ -205,7 +231,9 @@ int helm_matrix_csr(const helm_ctx* ctx, int64_t* rowptr, int32_t* col, double* 
  * chi_i = max(0, 1 - l/overlap) normalised, local solves are LU factors
  * (nested-dissection multifrontal, partial pivoting inside each front) and
  * the coarse matrix E = Z^T A Z is factored the same way.  On a host-only
- * context the numeric factorisation is skipped. */
+ * context the numeric factorisation is skipped, unless factor_on_host is set:
+ * then it runs on the host to check the pivots, and nothing is uploaded.
+ * HELM_ESINGULAR: a zero or tiny pivot (see perturb_pivots). */
 int helm_precond_setup(helm_ctx* ctx, const int32_t* tet_part, int32_t n_sub, int32_t overlap,
                        const helm_mesh* coarse, const helm_precond_opts* opts);
 
@@ -281,12 +309,13 @@ enum {
  * (NULL = the null stream).  Its slots use the context's multi-right-hand-
  * side work space: while a server exists, helm_solve, helm_assemble and
  * helm_precond_setup on the same context return HELM_ESTATE.  *out is NULL on failure (HELM_ENOMEM when no slot
- * fits in device memory). */
+ * fits in opts->mem_bytes or in device memory). */
 int helm_server_create(helm_ctx* ctx, const helm_server_opts* opts, void* stream, helm_server** out);
 
 /* Queues one request: b (device c128[n], read) and u (device c128[n],
  * written with the solution); both must stay valid until the request's
- * completion event.  Never blocks. */
+ * completion event.  The tag names the request in its completion event, so
+ * a tag still queued or in flight is refused (HELM_EINVAL).  Never blocks. */
 int helm_server_submit(helm_server* srv, const void* b, void* u, int64_t tag);
 
 /* Enqueues one Arnoldi step for every active slot on the server's stream
@@ -302,6 +331,10 @@ int helm_server_finish(helm_server* srv, helm_server_event* events, int32_t cap,
 
 /* Queued and in-flight requests. */
 int helm_server_status(const helm_server* srv, int32_t* queued, int32_t* active);
+
+/* Slots opened so far (their memory is held) and the device bytes the server
+ * holds for them (any pointer may be NULL). */
+int helm_server_memory(const helm_server* srv, int32_t* slots_open, double* bytes);
 
 /* Frees the server (pending requests are dropped); NULL is accepted. */
 void helm_server_destroy(helm_server* srv);

@@ -328,6 +328,7 @@ int helm_server_create(helm_ctx* ctx, const helm_server_opts* opts, void* stream
     need(ctx->servers == 0, HELM_ESTATE, "a server already uses this context");
     need(!opts || (opts->slots >= 0 && opts->slots <= 16), HELM_EINVAL, "slots must be 0..16");
     need(!opts || opts->tol >= 0, HELM_EINVAL, "tol must be >= 0");
+    need(!opts || opts->mem_bytes >= 0, HELM_EINVAL, "mem_bytes must be >= 0");
     std::unique_ptr<helm_server> h(new helm_server);
     h->ctx = ctx;
     h->srv.reset(new Server(c, opts, (hipStream_t)stream));
@@ -373,6 +374,13 @@ int helm_server_status(const helm_server* srv, int32_t* queued, int32_t* active)
   if (!srv) return HELM_EINVAL;
   if (queued) *queued = (int32_t)srv->srv->queue.size();
   if (active) *active = srv->srv->active();
+  return HELM_OK;
+}
+
+int helm_server_memory(const helm_server* srv, int32_t* slots_open, double* bytes) {
+  if (!srv) return HELM_EINVAL;
+  if (slots_open) *slots_open = std::min(srv->srv->slots_n, srv->ctx->c.blk_bases);
+  if (bytes) *bytes = srv->srv->held();
   return HELM_OK;
 }
 

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <deque>
 #include <string>
+#include <unordered_set>
 #include <vector>
 
 #include "device.hpp"
@@ -191,6 +192,7 @@ struct Ctx {
   int spmv_kind = 1;   // in use: 1 CSR, 2 sliced ELL, 3 CSR over XCD row ranges, 4 split CSR
   int spmv_auto = 1;   // the fastest at assembly
   bool blk_xcd = false;     // multi-vector SpMV over XCD row ranges (faster on first use)
+  bool blk_timed = false;   // blk_xcd has been timed for this matrix
   int blk_force = 0;        // 1 / 3: multi-vector SpMV order fixed by helm_set_spmv
   DVec<int64_t> A_xr;       // 9 row bounds: XCD k sweeps [A_xr[k], A_xr[k+1]), equal entries
   int64_t A_xrows = 0;      // longest of those ranges
@@ -226,9 +228,14 @@ struct Ctx {
   DVec<double> Zp_val, ZT_val;
   // work vectors
   DVec<double> t, q, cvec;
-  // GMRES work
+  // GMRES work (restart gm_m, order gm_n)
   int gm_m = 0;
+  int64_t gm_n = 0;
   DVec<double> V, Zk, w, partial, hcol, htmp, nrm, ydev, coef_w, coef_v;
+  // 2-norms of single vectors (right-hand sides, residuals): partial sums,
+  // the result and its pinned host copy
+  DVec<double> npart, nval;
+  double* nh_host = nullptr;
   // backward-sweep outputs of all batches in subdomain order (nbatch > 1)
   DVec<double> xall, xall_b;
   int xall_b_S = 0;
@@ -237,14 +244,25 @@ struct Ctx {
   hipEvent_t hev = nullptr;   // marks the Hessenberg column copy of a step
   double* h_host = nullptr;  // pinned
   Profiler prof;
-  // pseudo-block GMRES work (per right-hand side of a block)
-  int blk_m = 0, blk_cap = 0;
+  // pseudo-block GMRES work: Krylov bases bV/bZ/bw of the first blk_bases
+  // right-hand sides (restart blk_m, order blk_n), and the buffers of blocks
+  // up to blk_cap columns wide
+  int blk_m = 0, blk_cap = 0, blk_bases = 0;
+  int64_t blk_n = 0;
   DVec<double> bV[dev::kMaxBlock], bZ[dev::kMaxBlock], bw[dev::kMaxBlock];
   DVec<double> bhcol, bhtmp, bpartial, by, bX, bZb, bW, bq, bt, bcvec, bcoef_w, bcoef_v;
   double* bh_host = nullptr;  // pinned, kMaxBlock x (2 m + 4) complex
   ~Ctx();
   void free_precond();
+  void free_solve_work();
 };
+
+// solver.cpp: block work spaces (Krylov bases of the first `count` right-hand
+// sides; buffers of blocks up to S columns wide) and their device bytes
+size_t basis_bytes(int64_t n, int m);
+size_t width_bytes(const Ctx& c, int m, int S);
+void ensure_bases(Ctx& c, int m, int count);
+void ensure_width(Ctx& c, int m, int S);
 
 // factor_gpu.cpp: numeric factorisation of a batch on the device, panels
 // written into Dv.pf / Dv.pb (allocated by the caller) at the per-matrix
@@ -287,7 +305,8 @@ struct Server {
   };
   Ctx& c;
   hipStream_t s;
-  int m = 50, maxit = 1000, slots_n = 0;
+  int m = 50, maxit = 1000, slots_n = 0;  // slots_n: slots at most (each opened on demand)
+  double budget = 0;  // device bytes the slots' bases and block buffers may hold
   bool dcgs2 = true;
   double tol = 1e-6;
   std::deque<Request> queue;
@@ -301,6 +320,11 @@ struct Server {
   int launch();
   void finish(std::vector<helm_server_event>& out);
   void admit(std::vector<helm_server_event>& out);
+  void emit(std::vector<helm_server_event>& out, const helm_server_event& e);
+  std::unordered_set<int64_t> live;  // tags queued or in flight
+  bool open_slot(int q);
+  double bytes_for(int bases, int width) const;
+  double held() const;
   bool start_cycle(int q, std::vector<helm_server_event>& out);
   int active() const {
     int a = 0;

@@ -9,6 +9,10 @@
 namespace helm {
 namespace dev {
 
+// A pivot is taken as zero when |pivot| <= kTinyPivot max|a_ij| (the
+// factorisations replace it by sqrt(eps) max|a_ij| and count it).
+constexpr double kTinyPivot = 1000.0 * 2.220446049250313e-16;
+
 // Up to kMaxBlock device pointers, one per right-hand side of a block
 // (passed by value as a kernel argument; a null entry is a padding column).
 constexpr int kMaxBlock = 16;

@@ -298,8 +298,9 @@ __global__ __launch_bounds__(kFW) void front_kernel(const FrontJob* __restrict__
         }
         __syncthreads();
       }
-      if (!(best > 1e-300)) {
-        // zero pivot column: replaced by a tiny diagonal (counted)
+      if (!(best > kTinyPivot * J.anorm)) {
+        // zero or tiny pivot column: replaced by a small diagonal (counted;
+        // setup then fails unless replacements were asked for)
         if (tid == 0) colk[k] = make_double2(sqrt(DBL_EPSILON) * J.anorm, 0.0);
         ++n_pert;
         __syncthreads();

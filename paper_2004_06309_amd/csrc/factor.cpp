@@ -19,6 +19,7 @@
 #include <limits>
 #include <memory>
 
+#include "device.hpp"
 #include "internal.hpp"
 
 namespace helm {
@@ -87,7 +88,7 @@ void partial_lu(cplx* F, int m, int w, int32_t* piv, double anorm, int32_t& n_pe
         for (int j = 0; j < m; ++j) std::swap(F[k + (int64_t)j * m], F[p + (int64_t)j * m]);
         std::swap(piv[k], piv[p]);
       }
-      if (!(best > 1e-300)) {
+      if (!(best > dev::kTinyPivot * anorm)) {
         if (!(anorm > 0)) fail(HELM_ESINGULAR, "zero pivot in a frontal matrix");
         colk[k] = cplx(std::sqrt(std::numeric_limits<double>::epsilon()) * anorm, 0.0);
         ++n_pert;

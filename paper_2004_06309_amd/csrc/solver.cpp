@@ -30,10 +30,30 @@ Ctx::~Ctx() {
   }
   if (h_host) (void)hipHostFree(h_host);
   if (bh_host) (void)hipHostFree(bh_host);
+  if (nh_host) (void)hipHostFree(nh_host);
+}
+
+// Work spaces of the solvers: their sizes follow n, the restart, the coarse
+// order and the batches, so they are dropped whenever those can change.
+void Ctx::free_solve_work() {
+  gm_m = 0;
+  gm_n = 0;
+  for (auto* v : {&V, &Zk, &w, &partial, &hcol, &htmp, &nrm, &ydev, &coef_w, &coef_v, &npart, &nval}) v->reset();
+  blk_m = blk_cap = blk_bases = 0;
+  blk_n = 0;
+  blk_timed = false;
+  for (int r = 0; r < dev::kMaxBlock; ++r) {
+    bV[r].reset();
+    bZ[r].reset();
+    bw[r].reset();
+  }
+  for (auto* v : {&bhcol, &bhtmp, &bpartial, &by, &bX, &bZb, &bW, &bq, &bt, &bcvec, &bcoef_w, &bcoef_v}) v->reset();
+  for (auto* v : {&t, &q, &cvec}) v->reset();
 }
 
 void Ctx::free_precond() {
   precond_ready = false;
+  free_solve_work();
   subs.clear();
   sym.clear();
   two_level = false;
@@ -481,6 +501,19 @@ void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symb
     if (errcode) fail(errcode, errmsg);
     n_perturbed = npert;
   } else {
+    // no device: only the layout is built; with on_host the host
+    // factorisation still runs so that its pivots are checked
+    int32_t npert = 0;
+    if (on_host) {
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : npert)
+      for (int i = 0; i < nm; ++i) {
+        std::vector<cplx> hf(Ss[i]->fwd_entries), hb(Ss[i]->bwd_entries);
+        NumericOut o;
+        factor_numeric(*As[i], *Ss[i], hf.data(), hb.data(), o);
+        npert += o.n_perturbed;
+      }
+    }
+    n_perturbed = npert;
     for (int i = 0; i < nm; ++i) {
       num[i].piv.resize(Ss[i]->n);
       std::iota(num[i].piv.begin(), num[i].piv.end(), 0);
@@ -852,21 +885,47 @@ void spmv_A(Ctx& c, const double* x, const double* b, double* y, hipStream_t s) 
 // time.  When the device supports it, one cooperative launch with a grid-wide
 // barrier per level is timed against per-level launches at a few grid sizes,
 // and the fastest is kept.
-void choose_coarse_launch(Ctx& c) {
+void choose_coarse_launch(Ctx& c, int mode) {
   BatchDev& b = c.coarse;
   b.coop = 0;
+  if (mode == 1) return;
   const int nf = (int)b.lev_f.size() - 1, nb = (int)b.lev_b.size() - 1;
   int attr = 0;
-  if (b.c64 || nf < 1 || nb < 1 || nf > dev::kMaxLevels || nb > dev::kMaxLevels) return;
-  if (hipDeviceGetAttribute(&attr, hipDeviceAttributeCooperativeLaunch, c.device) != hipSuccess || !attr) return;
-  const int gmax = dev::coop_grid();
-  if (gmax <= 0) return;
+  const bool fits = !b.c64 && nf >= 1 && nb >= 1 && nf <= dev::kMaxLevels && nb <= dev::kMaxLevels;
+  const bool coop_ok = hipDeviceGetAttribute(&attr, hipDeviceAttributeCooperativeLaunch, c.device) == hipSuccess &&
+                       attr && fits;
+  const int gmax = coop_ok ? dev::coop_grid() : 0;
+  if (gmax <= 0) {
+    if (mode == 2) fail(HELM_EINVAL, "the cooperative coarse solve is not available for this matrix or device");
+    return;
+  }
   b.ranges.nf = nf;
   b.ranges.nb = nb;
   for (int l = 0; l <= nf; ++l) b.ranges.f[l] = b.lev_f[l];
   for (int l = 0; l <= nb; ++l) b.ranges.b[l] = b.lev_b[l];
-  HELM_HIP(hipMemset(c.cvec.p, 0, sizeof(double) * 2 * c.E.n));
-  std::vector<int> cands{0};
+  // both launch forms must give the same solution: compare them on a fixed
+  // right-hand side before the cooperative one may be used
+  const int64_t nc = c.E.n;
+  std::vector<double> in(2 * nc), x1(2 * nc), x2(2 * nc);
+  for (int64_t i = 0; i < 2 * nc; ++i) in[i] = std::sin(0.37 * (double)i + 0.1);
+  HELM_HIP(hipMemcpy(c.cvec.p, in.data(), sizeof(double) * 2 * nc, hipMemcpyHostToDevice));
+  batch_solve(b, c.cvec.p, nullptr, nullptr, false);
+  HELM_HIP(hipMemcpy(x1.data(), b.xout(), sizeof(double) * 2 * nc, hipMemcpyDeviceToHost));
+  b.coop = gmax;
+  batch_solve(b, c.cvec.p, nullptr, nullptr, false);
+  HELM_HIP(hipMemcpy(x2.data(), b.xout(), sizeof(double) * 2 * nc, hipMemcpyDeviceToHost));
+  b.coop = 0;
+  double dmax = 0, xmax = 0;
+  for (int64_t i = 0; i < 2 * nc; ++i) {
+    dmax = std::max(dmax, std::abs(x1[i] - x2[i]));
+    xmax = std::max(xmax, std::abs(x1[i]));
+  }
+  if (!(dmax <= 1e-13 * xmax)) {
+    if (mode == 2) fail(HELM_EDEVICE, "the cooperative coarse solve disagrees with the per-level launches");
+    return;  // keep the per-level launches
+  }
+  std::vector<int> cands;
+  if (mode == 0) cands.push_back(0);
   for (int g : {256, 512, 1024})
     if (g < gmax) cands.push_back(g);
   cands.push_back(gmax);
@@ -891,6 +950,8 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
   if (trows != 16 && trows != 32 && trows != 64) fail(HELM_EINVAL, "tile_rows must be 16, 32 or 64");
   if (ctrows != 16 && ctrows != 32 && ctrows != 64) fail(HELM_EINVAL, "coarse_tile_rows must be 16, 32 or 64");
   const int64_t snmin = !opts || opts->sn_jobs_min == 0 ? 6144 : (opts->sn_jobs_min < 0 ? -1 : opts->sn_jobs_min);
+  const int cmode = opts ? opts->coarse_launch : 0;
+  if (cmode < 0 || cmode > 2) fail(HELM_EINVAL, "coarse_launch must be 0, 1 or 2");
 #pragma omp parallel for schedule(dynamic, 1)
   for (int32_t i = 0; i < n_sub; ++i) nested_dissection(c.subs[i].A, c.subs[i].coords, leaf, c.sym[i], trows);
   helm_precond_stats& st = c.stats;
@@ -1106,7 +1167,7 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
         dev::coarse_update(c.D.n, c.Zp_ptr.p, c.Zp_col.p, c.Zp_val.p, c.AZ_ptr.p, c.AZ_col.p, c.AZ_val.p, x.p, x.p,
                            y.p, x2.p, G, nullptr);
       });
-      choose_coarse_launch(c);
+      choose_coarse_launch(c, cmode);
       st.coarse_grid = c.coarse.coop;
     }
   }
@@ -1116,6 +1177,10 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
     HELM_HIP(hipDeviceSynchronize());
   }
   st.n_perturbed = npert;
+  if (npert > 0 && !(opts && opts->perturb_pivots))
+    fail(HELM_ESINGULAR, std::to_string(npert) +
+                             " zero or tiny pivots (|pivot| <= 1000 eps max|a_ij|) in the local or coarse factors;"
+                             " helm_precond_opts.perturb_pivots replaces them instead");
   st.factor_on_host = on_host ? 1 : 0;
   st.factor_seconds = fsec + csec;
   st.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1210,16 +1275,24 @@ void apply_precond(Ctx& c, const double* r, double* z, hipStream_t s) {
 
 namespace {
 
-double device_norm(Ctx& c, const double* v, hipStream_t s) {
+void ensure_norm(Ctx& c) {
   const int nblk = dev::gs_blocks(c.D.n);
-  dev::norm2(c.D.n, v, c.partial.p, nblk, c.nrm.p, s);
-  HELM_HIP(hipMemcpyAsync(c.h_host, c.nrm.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (c.npart.n < 2 * (size_t)nblk) c.npart.alloc(2 * (size_t)nblk);
+  if (!c.nval.p) c.nval.alloc(2);
+  if (!c.nh_host) HELM_HIP(hipHostMalloc((void**)&c.nh_host, 2 * sizeof(double), hipHostMallocDefault));
+}
+
+double device_norm(Ctx& c, const double* v, hipStream_t s) {
+  ensure_norm(c);
+  const int nblk = dev::gs_blocks(c.D.n);
+  dev::norm2(c.D.n, v, c.npart.p, nblk, c.nval.p, s);
+  HELM_HIP(hipMemcpyAsync(c.nh_host, c.nval.p, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   HELM_HIP(hipStreamSynchronize(s));
-  return c.h_host[0];
+  return c.nh_host[0];
 }
 
 void ensure_gmres(Ctx& c, int m) {
-  if (c.gm_m == m && c.V.p) return;
+  if (c.gm_m == m && c.gm_n == c.D.n && c.V.p) return;
   const int64_t n = c.D.n;
   c.V.alloc(2 * (size_t)n * (m + 1));
   c.Zk.alloc(2 * (size_t)n * m);
@@ -1237,6 +1310,7 @@ void ensure_gmres(Ctx& c, int m) {
   HELM_HIP(hipHostMalloc((void**)&c.h_host, 2 * sizeof(double) * (2 * m + 4), hipHostMallocDefault));
   if (!c.hev) HELM_HIP(hipEventCreateWithFlags(&c.hev, hipEventDisableTiming));
   c.gm_m = m;
+  c.gm_n = n;
 }
 
 }  // namespace
@@ -1472,19 +1546,62 @@ void ensure_batch_block(BatchDev& b, int S) {
 // and host buffers (delayed CGS2 reads up to 2 m + 3 of them per step).
 size_t blk_ld(int m) { return 2 * (size_t)m + 4; }
 
-void ensure_block(Ctx& c, int m, int S) {
+}  // namespace
+
+// Krylov bases (V: m + 1 columns, Z_m: m columns, a work vector) of the
+// first `count` right-hand sides of a block or server slots.
+size_t basis_bytes(int64_t n, int m) { return sizeof(double) * 2 * (size_t)n * (2 * (size_t)m + 2); }
+
+void ensure_bases(Ctx& c, int m, int count) {
   const int64_t n = c.D.n;
-  if (c.blk_m != m || c.blk_cap < S) {
+  if (c.blk_m != m || c.blk_n != n) {
     for (int r = 0; r < dev::kMaxBlock; ++r) {
       c.bV[r].reset();
       c.bZ[r].reset();
       c.bw[r].reset();
     }
-    for (int r = 0; r < S; ++r) {
-      c.bV[r].alloc(2 * (size_t)n * (m + 1));
-      c.bZ[r].alloc(2 * (size_t)n * m);
-      c.bw[r].alloc(2 * (size_t)n);
-    }
+    c.blk_bases = 0;
+    c.blk_cap = 0;  // the per-width buffers depend on m too
+    c.blk_m = m;
+    c.blk_n = n;
+  }
+  for (int r = c.blk_bases; r < count; ++r) {
+    c.bV[r].alloc(2 * (size_t)n * (m + 1));
+    c.bZ[r].alloc(2 * (size_t)n * m);
+    c.bw[r].alloc(2 * (size_t)n);
+    c.blk_bases = r + 1;
+  }
+}
+
+// Device bytes of the buffers of a block S columns wide (apart from the
+// Krylov bases): interleaved block vectors, the subdomain and coarse batch
+// work vectors, the staging block of the 16-column level solves, the
+// Gram-Schmidt reductions.
+size_t width_bytes(const Ctx& c, int m, int S) {
+  const size_t n = (size_t)c.D.n;
+  size_t e = 5 * n * S;  // bX, bZb, bW, bq, bt (complex entries)
+  if (c.two_level) e += (size_t)c.E.n * S;
+  auto batch = [&](const BatchDev& b) {
+    size_t v = (std::max<size_t>(b.ubuf.n / 2, 1) + 2 * std::max<int64_t>(b.npos, 1)) * S;
+    if (S == dev::kMaxBlock) v += dev::kMaxBlock * std::max<int64_t>(b.stage_cols, 1);
+    return v;
+  };
+  int64_t npos_all = 0;
+  for (int k = 0; k < c.nbatch; ++k) {
+    e += batch(c.fine[k]);
+    npos_all += c.fine[k].npos;
+  }
+  if (c.nbatch > 1) e += (size_t)npos_all * S;
+  if (c.two_level) e += batch(c.coarse);
+  e += (size_t)dev::kMaxBlock * ((2 + dev::gs_tiles(c.D.n)) * blk_ld(m) + 2 * (m + 2)) + (m + 1);
+  return 16 * e;
+}
+
+// Buffers of blocks up to S columns wide (bases are separate, ensure_bases).
+void ensure_width(Ctx& c, int m, int S) {
+  const int64_t n = c.D.n;
+  if (c.blk_m != m || c.blk_n != n) ensure_bases(c, m, 0);
+  if (c.blk_cap < S) {
     c.bhcol.alloc(2 * (size_t)dev::kMaxBlock * blk_ld(m));
     c.bhtmp.alloc(2 * (size_t)dev::kMaxBlock * blk_ld(m));
     c.bpartial.alloc(2 * (size_t)dev::kMaxBlock * dev::gs_tiles(n) * blk_ld(m));
@@ -1500,18 +1617,21 @@ void ensure_block(Ctx& c, int m, int S) {
     if (c.bh_host) (void)hipHostFree(c.bh_host);
     c.bh_host = nullptr;
     HELM_HIP(hipHostMalloc((void**)&c.bh_host, 2 * sizeof(double) * dev::kMaxBlock * blk_ld(m), hipHostMallocDefault));
-    c.blk_m = m;
+    const bool first = c.blk_cap == 0 && !c.blk_timed;
     c.blk_cap = S;
-    // order of the multi-vector SpMV: plain or over XCD row ranges, the faster
-    HELM_HIP(hipMemset(c.bX.p, 0, sizeof(double) * 2 * n * S));
-    const float td = time_launch([&] {
-      dev::csr_spmv_block(n, c.A_ptr.p, c.A_col.p, c.A_val.p, nullptr, 0, S, c.bX.p, nullptr, c.bW.p, nullptr);
-    });
-    const float tx = time_launch([&] {
-      dev::csr_spmv_block(n, c.A_ptr.p, c.A_col.p, c.A_val.p, c.A_xr.p, c.A_xrows, S, c.bX.p, nullptr, c.bW.p,
-                          nullptr);
-    });
-    c.blk_xcd = tx < td;
+    if (first) {
+      // order of the multi-vector SpMV: plain or over XCD row ranges, the faster
+      HELM_HIP(hipMemset(c.bX.p, 0, sizeof(double) * 2 * n * S));
+      const float td = time_launch([&] {
+        dev::csr_spmv_block(n, c.A_ptr.p, c.A_col.p, c.A_val.p, nullptr, 0, S, c.bX.p, nullptr, c.bW.p, nullptr);
+      });
+      const float tx = time_launch([&] {
+        dev::csr_spmv_block(n, c.A_ptr.p, c.A_col.p, c.A_val.p, c.A_xr.p, c.A_xrows, S, c.bX.p, nullptr, c.bW.p,
+                            nullptr);
+      });
+      c.blk_xcd = tx < td;
+      c.blk_timed = true;
+    }
   }
   int64_t npos_all = 0;
   for (int k = 0; k < c.nbatch; ++k) {
@@ -1523,6 +1643,13 @@ void ensure_block(Ctx& c, int m, int S) {
     c.xall_b_S = S;
   }
   if (c.two_level) ensure_batch_block(c.coarse, S);
+}
+
+namespace {
+
+void ensure_block(Ctx& c, int m, int S, int bases) {
+  ensure_bases(c, m, bases);
+  ensure_width(c, m, S);
 }
 
 // Forward then backward sweeps of a batch for S interleaved right-hand sides.
@@ -1603,7 +1730,7 @@ int solve_block(Ctx& c, int nb, const double* const* Bp, double* const* Up, doub
                 bool dcgs2, hipStream_t s, helm_solve_info* info) {
   int S = 2;
   while (S < nb) S *= 2;
-  ensure_block(c, m, S);
+  ensure_block(c, m, S, nb);
   const int64_t n = c.D.n;
   const size_t n2 = 2 * (size_t)n;
   const int nt = dev::gs_tiles(n);
@@ -1844,7 +1971,6 @@ int solve(Ctx& c, int32_t nrhs, const double* B, double tol, const helm_solve_op
   if (m > 50) fail(HELM_EINVAL, "restart must be <= 50");
   if (!(tol > 0)) fail(HELM_EINVAL, "tol must be positive");
   if (block <= 1 || nrhs <= 1) return solve_single(c, nrhs, B, tol, m, maxit, x0, dcgs2, U, s, info);
-  ensure_gmres(c, m);  // device_norm's work space
   const int64_t n = c.D.n;
   int status = HELM_OK;
   for (int32_t j0 = 0; j0 < nrhs; j0 += block) {
@@ -1882,19 +2008,14 @@ Server::Server(Ctx& ctx, const helm_server_opts* o, hipStream_t st) : c(ctx), s(
   tol = o && o->tol > 0 ? o->tol : 1e-6;
   dcgs2 = !(o && (o->flags & HELM_SOLVE_CGS2));
   if (m > 50) fail(HELM_EINVAL, "restart must be <= 50");
-  const int64_t n = c.D.n;
   int want = o && o->slots > 0 ? o->slots : dev::kMaxBlock;
   if (want > dev::kMaxBlock) fail(HELM_EINVAL, "at most 16 slots");
-  // admission by memory: each slot holds V (m + 1 columns), Z_m (m columns)
-  // and a work vector; keep a quarter of the free memory in reserve
+  // admission by memory: a slot's Krylov basis and the block width it needs
+  // are allocated when a request is admitted into it, within the budget
   size_t free_b = 0, total_b = 0;
   HELM_HIP(hipMemGetInfo(&free_b, &total_b));
-  const double per_slot = 16.0 * (double)n * (2 * m + 2);
-  const int fit = (int)std::min<double>(dev::kMaxBlock, 0.75 * (double)free_b / per_slot);
-  if (fit < 1) fail(HELM_ENOMEM, "no device memory for a server slot");
-  slots_n = std::min(want, fit);
-  ensure_gmres(c, m);
-  ensure_block(c, m, dev::kMaxBlock);
+  budget = o && o->mem_bytes > 0 ? o->mem_bytes : 0.75 * (double)free_b;
+  slots_n = want;
   slot.resize(slots_n);
   for (auto& q : slot) {
     q.H.assign((size_t)(m + 1) * m, 0);
@@ -1903,13 +2024,48 @@ Server::Server(Ctx& ctx, const helm_server_opts* o, hipStream_t st) : c(ctx), s(
     q.cs.assign(m, 0);
     q.y.assign(m, 0);
   }
+  if (!open_slot(0)) fail(HELM_ENOMEM, "no device memory for a server slot within the budget");
   HELM_HIP(hipEventCreateWithFlags(&done_ev, hipEventDisableTiming));
+}
+
+static int pow2_width(int k) {
+  int S = 2;
+  while (S < k) S *= 2;
+  return S;
+}
+
+double Server::bytes_for(int bases, int width) const {
+  return (double)bases * (double)basis_bytes(c.D.n, m) + (double)width_bytes(c, m, width);
+}
+
+double Server::held() const { return c.blk_m == m ? bytes_for(c.blk_bases, c.blk_cap) : 0.0; }
+
+// Makes slot q usable: its Krylov basis (and those of the slots below it)
+// and the block width q + 1 needs, if the budget allows them.
+bool Server::open_slot(int q) {
+  const int bases = std::max(c.blk_m == m ? c.blk_bases : 0, q + 1);
+  const int width = std::max(c.blk_m == m ? c.blk_cap : 0, pow2_width(q + 1));
+  if (bytes_for(bases, width) > budget) return false;
+  try {
+    ensure_bases(c, m, bases);
+    ensure_width(c, m, width);
+  } catch (const Error& e) {
+    if (e.code != HELM_ENOMEM || active() == 0) throw;
+    return false;  // the device is full: wait for a slot that holds memory
+  }
+  return true;
 }
 
 Server::~Server() { (void)hipEventDestroy(done_ev); }
 
 void Server::submit(const double* b, double* u, int64_t tag) {
+  if (!live.insert(tag).second) fail(HELM_EINVAL, "tag " + std::to_string(tag) + " is already queued or in flight");
   queue.push_back({b, u, tag, std::chrono::steady_clock::now()});
+}
+
+void Server::emit(std::vector<helm_server_event>& out, const helm_server_event& e) {
+  live.erase(e.tag);
+  out.push_back(e);
 }
 
 // Starts (or restarts) a cycle of slot q from its current iterate: r = b - A x.
@@ -1932,7 +2088,7 @@ bool Server::start_cycle(int q, std::vector<helm_server_event>& out) {
     e.status = status != HELM_OK ? status : (z.conv ? HELM_OK : HELM_ENOCONV);
     e.relres = z.rel;
     e.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - z.t0).count();
-    out.push_back(e);
+    emit(out, e);
     z.busy = false;
     return false;
   }
@@ -1947,6 +2103,8 @@ void Server::admit(std::vector<helm_server_event>& out) {
   const int64_t n = c.D.n;
   for (int q = 0; q < slots_n && !queue.empty(); ++q) {
     if (slot[q].busy) continue;
+    // slots open lowest first, so a higher one needs at least as much memory
+    if (q >= c.blk_bases && !open_slot(q)) break;
     Request r = queue.front();
     queue.pop_front();
     Slot& z = slot[q];
@@ -1965,7 +2123,7 @@ void Server::admit(std::vector<helm_server_event>& out) {
       e.converged = z.bnorm == 0 ? 1 : 0;
       e.status = z.bnorm == 0 ? HELM_OK : HELM_ENUMERIC;
       e.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - z.t0).count();
-      out.push_back(e);
+      emit(out, e);
       z.busy = false;
       --q;  // the slot is free again
       continue;
@@ -2071,7 +2229,7 @@ void Server::finish(std::vector<helm_server_event>& out) {
         e.status = HELM_ENUMERIC;
         e.relres = z.rel;
         e.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - z.t0).count();
-        out.push_back(e);
+        emit(out, e);
         z.busy = false;
         continue;
       }
@@ -2161,7 +2319,7 @@ void Server::finish(std::vector<helm_server_event>& out) {
         e.status = HELM_ENUMERIC;
         e.relres = z.rel;
         e.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - z.t0).count();
-        out.push_back(e);
+        emit(out, e);
         z.busy = false;
         continue;
       }

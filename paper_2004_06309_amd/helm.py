@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -44,7 +45,8 @@ class Mesh(C.Structure):
 class PrecondOpts(C.Structure):
     _fields_ = [("leaf_size", C.c_int32), ("factor_c64", C.c_int32), ("coarse_leaf_size", C.c_int32),
                 ("tile_rows", C.c_int32), ("coarse_tile_rows", C.c_int32), ("factor_on_host", C.c_int32),
-                ("sn_jobs_min", C.c_int32), ("batches", C.c_int32)]
+                ("sn_jobs_min", C.c_int32), ("batches", C.c_int32), ("perturb_pivots", C.c_int32),
+                ("coarse_launch", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -67,7 +69,7 @@ class PrecondStats(C.Structure):
 
 class ServerOpts(C.Structure):
     _fields_ = [("slots", C.c_int32), ("restart", C.c_int32), ("maxit", C.c_int32), ("flags", C.c_int32),
-                ("tol", C.c_double)]
+                ("tol", C.c_double), ("mem_bytes", C.c_double)]
 
 
 class ServerEvent(C.Structure):
@@ -111,12 +113,26 @@ EXPORTS = {
     "helm_server_launch": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "helm_server_finish": (C.c_int, [C.c_void_p, C.POINTER(ServerEvent), C.c_int32, C.POINTER(C.c_int32)]),
     "helm_server_status": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "helm_server_memory": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "helm_server_destroy": (None, [C.c_void_p]),
     "helm_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "helm_profile_read": (C.c_int, [C.c_void_p, C.POINTER(KernelProfile)]),
 }
 
 _lib = None
+# every open context and server, so a program can release them (and their
+# device memory) at a point of its choosing rather than at interpreter exit
+_live_ctx = weakref.WeakSet()
+_live_srv = weakref.WeakSet()
+
+
+def close_all():
+    """Destroys every server, then every context, still open (frees their
+    device memory now)."""
+    for s in list(_live_srv):
+        s.close()
+    for h in list(_live_ctx):
+        h.close()
 
 
 def load():
@@ -145,11 +161,27 @@ def _mesh(xyz, tets, order):
     return m, (xyz, tets)
 
 
-def _dev_ptr(t):
+def _dev_ptr(t, numel=None, device=None, name="vector"):
+    """Device pointer of a contiguous complex128 GPU tensor, after checking
+    what the kernels assume: dtype, device, and (when given) its number of
+    entries.  The library reads and writes exactly that many entries, so a
+    short or complex64 tensor would be accessed out of bounds."""
     if t is None:
         return None
-    if not (t.is_cuda and t.is_contiguous()):
-        raise ValueError("device vectors must be contiguous GPU tensors")
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dtype != torch.complex128:
+        raise ValueError(f"{name} must be complex128, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {numel}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if device is not None and device >= 0 and t.device.index != device:
+        raise ValueError(f"{name} is on cuda:{t.device.index}, the context on cuda:{device}")
     return C.c_void_p(t.data_ptr())
 
 
@@ -173,6 +205,7 @@ class Helm:
         self.h = h
         self.device = device
         self._keep = []
+        _live_ctx.add(self)
 
     def close(self):
         if getattr(self, "h", None):
@@ -222,16 +255,20 @@ class Helm:
 
     def precond_setup(self, part, n_sub, overlap, coarse_xyz=None, coarse_tets=None, leaf_size=0, c64=False,
                       coarse_leaf_size=0, tile_rows=0, coarse_tile_rows=0, factor_on_host=False, sn_jobs_min=0,
-                      batches=0):
+                      batches=0, perturb_pivots=False, coarse_launch=0):
         """helm_precond_setup: subdomains from the tet partition `part` with
         `overlap` layers, the optional P1 coarse mesh, then the factorisation.
         c64: complex64 factors; tile_rows / coarse_tile_rows: 16, 32 or 64
         (0: 64 / 16); sn_jobs_min: one-wave supernode jobs threshold (0:
         default, -1: never); batches: 1 to 4 subdomain batches whose level
-        sweeps run concurrently (0: 2)."""
+        sweeps run concurrently (0: 2); perturb_pivots: replace zero or tiny
+        pivots and count them instead of failing with HELM_ESINGULAR;
+        coarse_launch: 0 timed, 1 per-level launches, 2 one cooperative
+        launch for the coarse solve."""
         part = np.ascontiguousarray(part, dtype=np.int32)
         opts = PrecondOpts(int(leaf_size), 1 if c64 else 0, int(coarse_leaf_size), int(tile_rows),
-                           int(coarse_tile_rows), 1 if factor_on_host else 0, int(sn_jobs_min), int(batches))
+                           int(coarse_tile_rows), 1 if factor_on_host else 0, int(sn_jobs_min), int(batches),
+                           1 if perturb_pivots else 0, int(coarse_launch))
         cm = None
         if coarse_xyz is not None:
             cm, keep = _mesh(coarse_xyz, coarse_tets, 1)
@@ -273,29 +310,36 @@ class Helm:
         CSR (1 and 3 also fix the multi-vector SpMV's order)."""
         self._check(self.lib.helm_set_spmv(self.h, int(kind)))
 
+    def _vec(self, t, name, count=1):
+        return _dev_ptr(t, count * self.n, self.device, name)
+
     def apply_A(self, x, y, stream=None):
-        self._check(self.lib.helm_apply_A(self.h, _dev_ptr(x), _dev_ptr(y), _stream(stream)))
+        self._check(self.lib.helm_apply_A(self.h, self._vec(x, "x"), self._vec(y, "y"), _stream(stream)))
 
     def apply_precond(self, r, z, stream=None):
-        self._check(self.lib.helm_apply_precond(self.h, _dev_ptr(r), _dev_ptr(z), _stream(stream)))
+        self._check(self.lib.helm_apply_precond(self.h, self._vec(r, "r"), self._vec(z, "z"), _stream(stream)))
 
     def apply_oras(self, r, z, stream=None):
-        self._check(self.lib.helm_apply_oras(self.h, _dev_ptr(r), _dev_ptr(z), _stream(stream)))
+        self._check(self.lib.helm_apply_oras(self.h, self._vec(r, "r"), self._vec(z, "z"), _stream(stream)))
 
     def apply_coarse(self, r, q, stream=None):
-        self._check(self.lib.helm_apply_coarse(self.h, _dev_ptr(r), _dev_ptr(q), _stream(stream)))
+        self._check(self.lib.helm_apply_coarse(self.h, self._vec(r, "r"), self._vec(q, "q"), _stream(stream)))
 
     def solve(self, B, U, tol=1e-6, restart=50, maxit=1000, x0=False, stream=None, block=1, classic_cgs2=False):
         """Solve A U = B; B, U are (n,) or (nrhs, n) complex128 GPU tensors
         (each RHS contiguous); `block` right-hand sides are advanced together.
         `classic_cgs2` selects three-pass CGS2 (default: delayed CGS2).
         Returns (status, [info dicts])."""
+        if B.dim() not in (1, 2) or tuple(U.shape) != tuple(B.shape):
+            raise ValueError(f"B {tuple(B.shape)} and U {tuple(U.shape)} must both be (n,) or (nrhs, n)")
         nrhs = 1 if B.dim() == 1 else B.shape[0]
+        if B.shape[-1] != self.n:
+            raise ValueError(f"right-hand sides have {B.shape[-1]} entries, the operator {self.n}")
         info = (SolveInfo * max(nrhs, 1))()
         flags = (HELM_SOLVE_X0 if x0 else 0) | (HELM_SOLVE_CGS2 if classic_cgs2 else 0)
         opts = SolveOpts(int(restart), int(maxit), flags, int(block))
-        rc = self._check(self.lib.helm_solve(self.h, nrhs, _dev_ptr(B), float(tol), C.byref(opts), _dev_ptr(U),
-                                             _stream(stream), info), allow=(HELM_ENOCONV,))
+        rc = self._check(self.lib.helm_solve(self.h, nrhs, self._vec(B, "B", nrhs), float(tol), C.byref(opts),
+                                             self._vec(U, "U", nrhs), _stream(stream), info), allow=(HELM_ENOCONV,))
         return rc, [{f: getattr(info[i], f) for f, _ in SolveInfo._fields_} for i in range(nrhs)]
 
     # ---- kernel timing -----------------------------------------------------
@@ -317,18 +361,25 @@ class Server:
     completion events as dicts.  Keeps the submitted tensors alive until
     their completion."""
 
-    def __init__(self, helm, slots=0, restart=50, maxit=1000, tol=1e-6, stream=None, classic_cgs2=False):
+    def __init__(self, helm, slots=0, restart=50, maxit=1000, tol=1e-6, stream=None, classic_cgs2=False,
+                 mem_bytes=0.0):
         self.helm = helm
         self.lib = helm.lib
-        opts = ServerOpts(int(slots), int(restart), int(maxit), HELM_SOLVE_CGS2 if classic_cgs2 else 0, float(tol))
+        opts = ServerOpts(int(slots), int(restart), int(maxit), HELM_SOLVE_CGS2 if classic_cgs2 else 0, float(tol),
+                          float(mem_bytes))
         out = C.c_void_p()
         helm._check(self.lib.helm_server_create(helm.h, C.byref(opts), _stream(stream), C.byref(out)))
         self.h = out
         self._alive = {}
         self._ev = (ServerEvent * 64)()
+        _live_srv.add(self)
 
     def submit(self, b, u, tag):
-        self.helm._check(self.lib.helm_server_submit(self.h, _dev_ptr(b), _dev_ptr(u), int(tag)))
+        """Queues b -> u under `tag`; the library refuses a tag that is still
+        queued or in flight, so the tensors kept alive here are keyed by it."""
+        pb = self.helm._vec(b, "b")
+        pu = self.helm._vec(u, "u")
+        self.helm._check(self.lib.helm_server_submit(self.h, pb, pu, int(tag)))
         self._alive[int(tag)] = (b, u)
 
     def launch(self):
@@ -352,6 +403,12 @@ class Server:
         q, a = C.c_int32(), C.c_int32()
         self.lib.helm_server_status(self.h, C.byref(q), C.byref(a))
         return q.value, a.value
+
+    def memory(self):
+        """(slots opened, device bytes held for them)."""
+        k, b = C.c_int32(), C.c_double()
+        self.helm._check(self.lib.helm_server_memory(self.h, C.byref(k), C.byref(b)))
+        return k.value, b.value
 
     def close(self):
         if getattr(self, "h", None):

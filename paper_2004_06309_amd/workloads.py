@@ -113,11 +113,12 @@ class ThrustModel:
             fold += a * np.sin(2 * np.pi * (x * np.cos(th) + y * np.sin(th)) / lam + ph)
         # Fault plane through fault_point, trace along the strike direction,
         # dipping at fault_dip_deg towards +h.  Points above it are the
-        # hanging wall, whose interfaces are thrown down by fault_throw.
+        # hanging wall; a thrust (reverse) fault raises it, so its interfaces
+        # sit fault_throw shallower than on the footwall.
         h = np.array([-np.sin(self.fault_strike), np.cos(self.fault_strike)])
         dist = (x - self.fault_point[0]) * h[0] + (y - self.fault_point[1]) * h[1]
         hanging = z < np.tan(np.deg2rad(self.fault_dip_deg)) * dist
-        shift = fold + np.where(hanging, self.fault_throw, 0.0)
+        shift = fold - np.where(hanging, self.fault_throw, 0.0)
         nl = self.n_layers
         z0 = self.lz * np.arange(1, nl) / nl  # nl-1 interfaces
         below = (z[:, None] > (z0[None, :] + shift[:, None])).sum(axis=1)
@@ -329,3 +330,15 @@ def adapted_box(lx=8000.0, ly=8000.0, lz=2000.0, n0=(4, 4, 1), freq=2.0, per_wav
     src = np.array([lx / 2, ly / 2, 10.0]) if source is None else np.asarray(source, dtype=np.float64)
     return Workload("adapted", xyz, tets, order, c, 2 * np.pi * freq, part, int(np.prod(n_parts)), overlap,
                     cx, ct, src, None)
+
+
+def random_vector(n: int, seed: int) -> np.ndarray:
+    """Seeded complex test vector (standard normal real and imaginary parts),
+    the input of the preconditioner-application parity checks."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(n) + 1j * rng.standard_normal(n)
+
+
+def sample_dofs(n: int, count: int, seed: int) -> np.ndarray:
+    """Seeded sorted sample of distinct dof indices."""
+    return np.sort(np.random.default_rng(seed).choice(n, count, replace=False))

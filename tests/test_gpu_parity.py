@@ -114,6 +114,31 @@ def test_coarse_and_two_level_parity(pair):
     assert rel(host(z), M.apply(r)) <= 1e-9
 
 
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("name", ["small_p2_2lvl", "mid_quarter_2lvl", "adapted_p2_2lvl"])
+def test_coarse_launch_modes(name, mode):
+    """Both forms of the coarse solve, forced: one launch per level (1) and
+    one cooperative launch with a grid barrier per level (2); the coarse
+    correction and the two-level preconditioner against the oracle."""
+    w = WORKLOADS[name]()
+    P, b, M = opre.build(w)
+    say(f"[coarse] {name} mode {mode}")
+    h = helm.from_workload(w, coarse_launch=mode)
+    st = h.stats()
+    assert (st["coarse_grid"] > 0) == (mode == 2)
+    r = rand_vec(P.n, 13)
+    q = torch.empty(P.n, dtype=torch.complex128, device=DEV)
+    h.apply_coarse(dvec(r), q)
+    assert rel(host(q), M.coarse_correction(r)) <= 1e-9
+    z = torch.empty(P.n, dtype=torch.complex128, device=DEV)
+    h.apply_precond(dvec(r), z)
+    assert rel(host(z), M.apply(r)) <= 1e-9
+    U = torch.zeros(P.n, dtype=torch.complex128, device=DEV)
+    rc, info = h.solve(dvec(b), U, tol=w.tol, restart=w.restart)
+    assert rc == helm.HELM_OK
+    assert np.linalg.norm(b - P.A @ host(U)) / np.linalg.norm(b) <= w.tol
+
+
 def test_solve_parity(pair):
     name, w, P, b, M, h = pair
     ro = opre.solve(P, b, M, tol=w.tol, restart=w.restart)
@@ -632,6 +657,45 @@ def test_server_continuous_batching():
             assert abs(e["iterations"] - its7[r]) <= 2
             assert np.linalg.norm(u[r] - us[r]) <= 1e-5 * np.linalg.norm(us[r])
         say(f"[serve] GMRES(7) classic={classic}: its={[ev[200 + r]['iterations'] for r in range(6)]} solo={its7}")
+
+
+def test_server_admits_by_memory():
+    """A memory budget that holds three slots' Krylov bases (and the block
+    buffers they need) admits three requests at a time; the rest wait in the
+    queue and are admitted as slots free up; every result converges and
+    matches its solo solve."""
+    w = WORKLOADS["small_p2_2lvl"]()
+    P, b0, M = opre.build(w)
+    h = helm.from_workload(w)
+    pts = np.random.default_rng(23).uniform(0.1, 0.9, (7, 3)) * w.xyz.max(axis=0)
+    Bs = np.stack([P.point_source(p) for p in pts])
+    B = dvec(Bs)
+    probe = helm.Server(h, slots=1, restart=w.restart, tol=w.tol)
+    k1, bytes1 = probe.memory()
+    probe.close()
+    assert k1 == 1 and bytes1 > 0
+    # per-slot basis bytes: 16 (2 m + 2) n; block buffers grow with the width
+    basis = 16.0 * (2 * w.restart + 2) * P.n
+    srv = helm.Server(h, slots=16, restart=w.restart, tol=w.tol, mem_bytes=2 * bytes1 + 1.5 * basis)
+    U = torch.zeros_like(B)
+    for r in range(7):
+        srv.submit(B[r], U[r], 300 + r)
+    with pytest.raises(helm.HelmError) as e:  # a tag still queued
+        srv.submit(B[0], U[0], 300)
+    assert e.value.code == helm.HELM_EINVAL
+    peak, events = 0, {}
+    while len(events) < 7:
+        peak = max(peak, srv.launch())
+        for ev in srv.finish():
+            events[ev["tag"]] = ev
+    opened, held = srv.memory()
+    srv.close()
+    say(f"[serve-mem] peak active {peak}, slots opened {opened}, held {held / 1e6:.1f} MB")
+    assert peak == 3 and opened == 3
+    u = host(U)
+    for r in range(7):
+        assert events[300 + r]["converged"] == 1
+        assert np.linalg.norm(Bs[r] - P.A @ u[r]) / np.linalg.norm(Bs[r]) <= w.tol
 
 
 def test_servers_on_two_operators_overlap():

@@ -155,7 +155,7 @@ def test_bad_tile_rows_are_rejected():
     w = wl.small_box(n=(2, 2, 2), order=1, coarse=False)
     h = helm.Helm(-1)
     h.assemble(w.xyz, w.tets, 1, w.c_tet, w.omega)
-    for kw in ({"tile_rows": 48}, {"coarse_tile_rows": 8}):
+    for kw in ({"tile_rows": 48}, {"coarse_tile_rows": 8}, {"coarse_launch": 3}):
         with pytest.raises(helm.HelmError) as e:
             h.precond_setup(w.part, w.n_sub, 1, **kw)
         assert e.value.code == helm.HELM_EINVAL
@@ -203,3 +203,44 @@ def test_batch_options_on_a_host_context():
         h.assemble(w.xyz, w.tets, w.order, w.c_tet, w.omega)
         with pytest.raises(helm.HelmError, match="batches"):
             h.precond_setup(w.part, w.n_sub, w.overlap, batches=bad)
+
+
+def test_binding_rejects_vectors_the_kernels_would_overrun():
+    """Wrong dtype, wrong length, mismatched shapes and host tensors are
+    refused by the binding before any pointer reaches the library."""
+    torch = pytest.importorskip("torch")
+    w = wl.small_box(n=(2, 2, 2), order=1, coarse=False)
+    h = helm.Helm(-1)
+    n = h.assemble(w.xyz, w.tets, 1, w.c_tet, w.omega)
+    good = torch.zeros(n, dtype=torch.complex128)
+    for bad, msg in ((torch.zeros(n, dtype=torch.complex64), "complex128"),
+                     (torch.zeros(n - 1, dtype=torch.complex128), "entries"),
+                     (torch.zeros(2 * n, dtype=torch.complex128)[::2], "contiguous"),
+                     (np.zeros(n, np.complex128), "torch tensor"),
+                     (good, "GPU tensor")):
+        with pytest.raises(ValueError, match=msg):
+            h.apply_A(bad, good)
+    with pytest.raises(ValueError, match="must both be"):
+        h.solve(torch.zeros(2, n, dtype=torch.complex128), torch.zeros(n, dtype=torch.complex128))
+    with pytest.raises(ValueError, match="entries"):
+        h.solve(torch.zeros(2, n + 1, dtype=torch.complex128), torch.zeros(2, n + 1, dtype=torch.complex128))
+
+
+def test_singular_local_matrix_is_reported():
+    """A velocity of 1e300 m/s makes k vanish, so a subdomain away from the
+    Dirichlet top has the local matrix -K_i, singular (constants span its
+    kernel): the host factorisation meets a zero pivot and setup fails with
+    HELM_ESINGULAR, unless pivot replacement is asked for."""
+    w = wl.small_box(n=(4, 4, 4), order=1, n_parts=(2, 2, 2), overlap=1, coarse=False)
+    c = np.full(w.n_tets, 1e300 + 0j)
+    h = helm.Helm(-1)
+    h.assemble(w.xyz, w.tets, 1, c, w.omega)
+    with pytest.raises(helm.HelmError) as e:
+        h.precond_setup(w.part, w.n_sub, w.overlap, factor_on_host=True)
+    assert e.value.code == helm.HELM_ESINGULAR
+    h.precond_setup(w.part, w.n_sub, w.overlap, factor_on_host=True, perturb_pivots=True)
+    assert h.stats()["n_perturbed"] >= 4  # one per subdomain of the lower layer
+    # a regular medium factors without replacements
+    h.assemble(w.xyz, w.tets, 1, w.c_tet, w.omega)
+    h.precond_setup(w.part, w.n_sub, w.overlap, factor_on_host=True)
+    assert h.stats()["n_perturbed"] == 0

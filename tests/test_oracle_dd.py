@@ -181,3 +181,109 @@ def test_attenuation_lowers_iterations():
         P, b, M = precond.build(w)
         its.append(precond.solve(P, b, M).iterations)
     assert its[1] < its[0], its
+
+
+def _box_id(i, n_parts):
+    return i % n_parts[0], (i // n_parts[0]) % n_parts[1], i // (n_parts[0] * n_parts[1])
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_interface_impedance_term_on_box_subdomains(order):
+    """The artificial-face term of the ORAS local matrices (eq. oras; the
+    local problems carry the same absorbing condition as the physical
+    boundary).  The Lagrange basis sums to one and K 1 = 0, so
+        1^T A_i 1 = k_i^2 |Gamma_i| + i k_i |boundary of Gamma_i off the top|,
+    the imaginary part counting every impedance face once.  With overlap 0 and
+    a velocity constant on each box subdomain, Gamma_i is its box and both
+    sides follow from the box extents.  Checked on the six subdomains of the
+    lower layer of a 3x2x2 split (four corners, two edge boxes; none touches
+    the Dirichlet top).  A dropped interface term (Neumann interfaces), a
+    flipped sign, or the neighbour's k on the interface would each miss by far
+    more than the tolerance (asserted below)."""
+    n_parts = (3, 2, 2)
+    size = (600.0, 400.0, 400.0)
+    w = wl.small_box(n=(6, 4, 4), size=size, order=order, n_parts=n_parts, overlap=0, coarse=False)
+    c_sub = (2000.0 + 250.0 * np.arange(w.n_sub)) * (1 - 0.02j)
+    c = c_sub[w.part]
+    P = fem.Problem(w.xyz, w.tets, order, c, w.omega)
+    subs = dd.decompose(P, w.part, w.n_sub, 0)
+    hx, hy, hz = (s / p for s, p in zip(size, n_parts))
+    checked = 0
+    for i, s in enumerate(subs):
+        ix, iy, iz = _box_id(i, n_parts)
+        if iz == 0:
+            continue  # touches the Dirichlet top
+        Ai = dd.local_matrix(P, s)
+        one = np.ones(s.dofs.size)
+        got = one @ (Ai @ one)
+        k = w.omega / c_sub[i]
+        vol = hx * hy * hz
+        faces = [(hy * hz, ix, n_parts[0]), (hx * hz, iy, n_parts[1]), (hx * hy, iz, n_parts[2])]
+        area = 2 * (hx * hy + hy * hz + hx * hz)
+        expect = k * k * vol + 1j * k * area
+        assert abs(got - expect) <= 1e-11 * abs(expect), (i, got, expect)
+        # the same sum under plausible misreadings of the interface term
+        phys = sum(a * ((j == 0) + (j == n - 1)) for a, j, n in faces)
+        art = area - phys
+        wrong = [k * k * vol + 1j * k * phys,  # no interface term
+                 k * k * vol + 1j * k * (phys - art)]  # interface term with the wrong sign
+        for nb in (i - 1, i + 1):  # interface term with a neighbour box's k
+            if 0 <= nb < w.n_sub:
+                wrong.append(k * k * vol + 1j * (k * phys + w.omega / c_sub[nb] * art))
+        for v in wrong:
+            assert abs(got - v) > 1e-3 * abs(expect)
+        checked += 1
+    assert checked == 6
+
+
+def _boundary_area_off_top(xyz, tets):
+    """Area of the faces that belong to exactly one tet, excluding faces on
+    z = min z: plain enumeration with a dictionary."""
+    count = {}
+    for t in tets.tolist():
+        for f in ((t[0], t[1], t[2]), (t[0], t[1], t[3]), (t[0], t[2], t[3]), (t[1], t[2], t[3])):
+            key = tuple(sorted(f))
+            count[key] = count.get(key, 0) + 1
+    ztop = xyz[:, 2].min()
+    area = 0.0
+    for key, cnt in count.items():
+        if cnt != 1:
+            continue
+        p = xyz[list(key)]
+        if np.all(p[:, 2] == ztop):
+            continue
+        area += 0.5 * np.linalg.norm(np.cross(p[1] - p[0], p[2] - p[0]))
+    return area
+
+
+@pytest.mark.parametrize("order,overlap", [(1, 1), (2, 2)])
+def test_interface_impedance_term_with_overlap(order, overlap):
+    """Same identity for overlapping subdomains in a homogeneous medium:
+    1^T A_i 1 = k^2 |Gamma_i| + i k |boundary of Gamma_i off the top|, with
+    the volume summed over Gamma_i's tets and the boundary area found by
+    enumerating the faces of Gamma_i that belong to one of its tets only (the
+    artificial faces of the grown region, jagged at its edges, plus its
+    physical absorbing faces).  Subdomains of the lower layer only (away
+    from the Dirichlet top)."""
+    w = wl.small_box(n=(6, 6, 6), size=(600.0, 600.0, 600.0), order=order, n_parts=(2, 2, 2), overlap=overlap,
+                     coarse=False)
+    c0 = 2400.0 * (1 - 0.03j)
+    P = fem.Problem(w.xyz, w.tets, order, np.full(w.n_tets, c0), w.omega)
+    subs = dd.decompose(P, w.part, w.n_sub, overlap)
+    k = w.omega / c0
+    checked = 0
+    for i, s in enumerate(subs):
+        if _box_id(i, (2, 2, 2))[2] == 0:
+            continue
+        T = w.tets[s.tets]
+        p = w.xyz[T]
+        vol = np.abs(np.einsum("ij,ij->i", np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0]), p[:, 3] - p[:, 0])).sum() / 6
+        assert w.xyz[np.unique(T), 2].min() > 0  # away from the top
+        area = _boundary_area_off_top(w.xyz, T)
+        Ai = dd.local_matrix(P, s)
+        one = np.ones(s.dofs.size)
+        got = one @ (Ai @ one)
+        expect = k * k * vol + 1j * k * area
+        assert abs(got - expect) <= 1e-11 * abs(expect), (i, got, expect)
+        checked += 1
+    assert checked == 4
