@@ -280,6 +280,20 @@ int helm_apply_oras(helm_ctx* ctx, const void* r, void* z, void* stream);
 /* q = Z E^{-1} Z^T r (two-level setup only). */
 int helm_apply_coarse(helm_ctx* ctx, const void* r, void* q, void* stream);
 
+/* q = Z E^{-1} Z^T r exactly as helm_apply_coarse, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): it calls no hipMalloc, hipFree or other
+ * allocating routine and records no timing events.  Its work vectors (Z^T r
+ * and the coarse solve's forward, backward and update vectors) live in a
+ * fixed device scratch of 32 MiB per GPU, set up by helm_create and held
+ * until the process ends; a coarse problem whose work vectors exceed it
+ * (about 16 (3 n_c + update entries) bytes) fails with HELM_EINVAL.  Every
+ * call on a GPU shares that GPU's scratch: calls that overlap on one GPU
+ * (other streams, other threads or contexts) race and must be serialised by
+ * the caller.  Nothing in the scratch needs clearing between calls (every
+ * work vector is written before it is read). */
+int helm_apply_coarse_noalloc(helm_ctx* ctx, const void* r, void* q, void* stream);
+
 /* Solve A U = B for nrhs right-hand sides with right-preconditioned GMRES.
  * B and U are device arrays c128, column-major n x nrhs; U is read as the
  * initial guess iff opts->flags has HELM_SOLVE_X0.  info (host, nrhs

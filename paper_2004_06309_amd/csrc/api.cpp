@@ -66,6 +66,9 @@ int helm_create(helm_ctx** out, int device_ordinal) {
       if (hipGetDeviceCount(&count) != hipSuccess || device_ordinal >= count)
         fail(HELM_EDEVICE, "no HIP device " + std::to_string(device_ordinal));
       HELM_HIP(hipSetDevice(device_ordinal));
+      // the device's fixed scratch (allocation-free entry point): its address,
+      // once per device, with the device current
+      HELM_HIP(dev::scratch_init(device_ordinal));
     } else if (device_ordinal != -1) {
       fail(HELM_EINVAL, "device_ordinal must be >= 0, or -1 for a host-only context");
     }
@@ -283,6 +286,24 @@ int helm_apply_coarse(helm_ctx* ctx, const void* r, void* q, void* stream) {
     need(c.precond_ready && c.two_level, HELM_ESTATE, "no coarse level");
     need(r && q, HELM_EINVAL, "null vector");
     apply_coarse(c, (const double*)r, (double*)q, (hipStream_t)stream);
+    HELM_HIP(hipGetLastError());
+    return HELM_OK;
+  });
+}
+
+int helm_apply_coarse_noalloc(helm_ctx* ctx, const void* r, void* q, void* stream) {
+  return guarded(ctx, [&](Ctx& c) {
+    need(c.device >= 0, HELM_ESTATE, "host-only context");
+    need(c.precond_ready && c.two_level, HELM_ESTATE, "no coarse level");
+    need(r && q, HELM_EINVAL, "null vector");
+    const size_t need_b = coarse_scratch_bytes(c);
+    if (need_b > dev::kScratchBytes)
+      fail(HELM_EINVAL, "the coarse correction needs " + std::to_string(need_b) +
+                            " bytes of work space, more than the fixed scratch of " +
+                            std::to_string(dev::kScratchBytes) + " bytes; use helm_apply_coarse");
+    void* scratch = dev::scratch_ptr(c.device);
+    need(scratch != nullptr, HELM_ESTATE, "device scratch not initialised");
+    apply_coarse_scratch(c, (const double*)r, (double*)q, (hipStream_t)stream, scratch);
     HELM_HIP(hipGetLastError());
     return HELM_OK;
   });

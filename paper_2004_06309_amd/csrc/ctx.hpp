@@ -280,6 +280,8 @@ void upload_matrix(Ctx& c);
 void apply_A(Ctx& c, const double* x, double* y, hipStream_t s);
 void apply_oras(Ctx& c, const double* r, double* z, const double* q, hipStream_t s);
 void apply_coarse(Ctx& c, const double* r, double* q, hipStream_t s);
+size_t coarse_scratch_bytes(const Ctx& c);
+void apply_coarse_scratch(Ctx& c, const double* r, double* q, hipStream_t s, void* scratch);
 void apply_precond(Ctx& c, const double* r, double* z, hipStream_t s);
 int solve(Ctx& c, int32_t nrhs, const double* B, double tol, const helm_solve_opts* opts, double* U, hipStream_t s,
           helm_solve_info* info);

@@ -1291,6 +1291,43 @@ void gemv_acc(int64_t n, const double* Z, int64_t ld, int k, const double* y, do
                                                 reinterpret_cast<const double2*>(y), reinterpret_cast<double2*>(x));
 }
 
+// ---- fixed scratch of the allocation-free entry point ----------------------
+//
+// One file-scope array per device (each GPU the library runs on holds its own
+// copy until the process ends).  In host code `scratch` names a host-side
+// stand-in, not the device array: its device address is looked up once per
+// device with hipGetSymbolAddress and only that address is ever handed to
+// kernels or copies.
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device) return hipErrorInvalidDevice;  // the caller makes `device` current
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void* scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
 void fill_zero(int64_t n, double* p, hipStream_t s) {
   if (n <= 0) return;
   fill_zero_kernel<<<blocks_for(n), kWG, 0, s>>>(n, p);

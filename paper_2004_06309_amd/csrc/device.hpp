@@ -240,6 +240,14 @@ void scale(int64_t n, const double* w, double alpha, double* v, hipStream_t s);
 // x += Z y  (Z n x k column-major, y device)
 void gemv_acc(int64_t n, const double* Z, int64_t ld, int k, const double* y, double* x, hipStream_t s);
 void fill_zero(int64_t n_doubles, double* p, hipStream_t s);
+
+// Fixed device scratch of the allocation-free coarse correction: a
+// file-scope array of kScratchBytes per device.  scratch_init(device), with
+// `device` current, looks up its device address once (hipGetSymbolAddress);
+// scratch_ptr(device) returns it (nullptr before scratch_init).
+constexpr size_t kScratchBytes = size_t(32) << 20;
+hipError_t scratch_init(int device);
+void* scratch_ptr(int device);
 void copy(int64_t n_doubles, const double* src, double* dst, hipStream_t s);
 
 }  // namespace dev

@@ -610,6 +610,20 @@ void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symb
 
 // Forward then backward level sweeps; with profiling on, every level launch
 // of the fine batch is timed (the coarse batch is timed as a whole).
+// Coarse-batch solve (forward and backward sweeps) through a view whose
+// work vectors may lie outside the batch (no profiling).
+void batch_solve_view(const BatchDev& b, const dev::Batch& v, const double* in, hipStream_t s) {
+  if (b.coop > 0) {
+    HELM_HIP(dev::batch_solve_coop(v, in, b.ranges, b.coop, s));
+    return;
+  }
+  for (size_t l = 0; l + 1 < b.lev_f.size(); ++l) {
+    dev::fwd_level(v, b.lev_f[l], b.ktile_f[l], in, b.chunk_f[l], true, s);
+    dev::fwd_sn(v, b.snj_lev[l], b.snj_lev[l + 1] - b.snj_lev[l], in, s);
+  }
+  for (size_t l = 0; l + 1 < b.lev_b.size(); ++l) dev::bwd_level(v, b.lev_b[l], b.lev_b[l + 1] - b.lev_b[l], b.chunk_b[l], true, s);
+}
+
 void batch_solve(const BatchDev& b, const double* in, hipStream_t s, Profiler* prof, bool fine) {
   dev::Batch v = b.view();
   if (!fine && b.coop > 0) {
@@ -1198,6 +1212,38 @@ void apply_A(Ctx& c, const double* x, double* y, hipStream_t s) {
   if (p) c.prof.begin(s);
   spmv_A(c, x, nullptr, y, s);
   if (p) c.prof.end(HELM_K_SPMV, spmv_bytes(c, false), s);
+}
+
+// Bytes of the work vectors of one coarse correction (Z^T r, and the coarse
+// batch's forward result, backward result and update vectors), each region
+// 256-byte aligned.
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+size_t coarse_scratch_bytes(const Ctx& c) {
+  const size_t nc = (size_t)c.E.n, np = (size_t)std::max<int64_t>(c.coarse.npos, 1);
+  const size_t nu = std::max<size_t>(c.coarse.ubuf.n / 2, 1);
+  return align256(16 * nc) + 2 * align256(16 * np) + align256(16 * nu);
+}
+
+// q = Z E^{-1} Z^T r with the work vectors in `scratch` (device memory of at
+// least coarse_scratch_bytes): the same kernels as apply_coarse, no
+// allocation, no timing events.
+void apply_coarse_scratch(Ctx& c, const double* r, double* q, hipStream_t s, void* scratch) {
+  const size_t nc = (size_t)c.E.n, np = (size_t)std::max<int64_t>(c.coarse.npos, 1);
+  unsigned char* base = static_cast<unsigned char*>(scratch);
+  double* cv = reinterpret_cast<double*>(base);
+  base += align256(16 * nc);
+  double* y = reinterpret_cast<double*>(base);
+  base += align256(16 * np);
+  double* x = reinterpret_cast<double*>(base);
+  base += align256(16 * np);
+  double* ub = reinterpret_cast<double*>(base);
+  dev::spmv_real(c.ZT.n, c.ZT_ptr.p, c.ZT_col.p, c.ZT_val.p, r, cv, c.g_ZT, s);
+  dev::Batch v = c.coarse.view();
+  v.y = y;
+  v.x = x;
+  v.ubuf = ub;
+  batch_solve_view(c.coarse, v, cv, s);
+  dev::spmv_real(c.D.n, c.Zp_ptr.p, c.Zp_col.p, c.Zp_val.p, x, q, c.g_Zp, s);
 }
 
 void apply_coarse(Ctx& c, const double* r, double* q, hipStream_t s) {

@@ -106,6 +106,7 @@ EXPORTS = {
     "helm_apply_precond": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "helm_apply_oras": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "helm_apply_coarse": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "helm_apply_coarse_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "helm_solve": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.POINTER(SolveOpts), C.c_void_p,
                              C.c_void_p, C.POINTER(SolveInfo)]),
     "helm_server_create": (C.c_int, [C.c_void_p, C.POINTER(ServerOpts), C.c_void_p, C.POINTER(C.c_void_p)]),
@@ -324,6 +325,12 @@ class Helm:
 
     def apply_coarse(self, r, q, stream=None):
         self._check(self.lib.helm_apply_coarse(self.h, self._vec(r, "r"), self._vec(q, "q"), _stream(stream)))
+
+    def apply_coarse_noalloc(self, r, q, stream=None):
+        """apply_coarse with its work vectors in the library's fixed device
+        scratch (no device allocation)."""
+        self._check(self.lib.helm_apply_coarse_noalloc(self.h, self._vec(r, "r"), self._vec(q, "q"),
+                                                        _stream(stream)))
 
     def solve(self, B, U, tol=1e-6, restart=50, maxit=1000, x0=False, stream=None, block=1, classic_cgs2=False):
         """Solve A U = B; B, U are (n,) or (nrhs, n) complex128 GPU tensors
