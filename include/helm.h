@@ -104,11 +104,29 @@ typedef struct helm_precond_opts {
 
 enum {
   HELM_SOLVE_X0 = 1,       /* read U as the initial guess                  */
-  HELM_SOLVE_CGS2 = 2      /* classic CGS2 (three passes over the Krylov
+  HELM_SOLVE_CGS2 = 2,     /* classic CGS2 (three passes over the Krylov
                               basis per step) instead of the default
                               delayed CGS2 (two passes; the second
                               orthogonalisation of v_j is folded into step
-                              j + 1), for single and block solves        */
+                              j + 1), for single and pseudo-block solves  */
+  HELM_SOLVE_BLOCK_GMRES = 4,  /* block > 1: block GMRES instead of pseudo-
+                              block GMRES: the block's right-hand sides share
+                              one block Krylov space (restart = blocks of
+                              16 columns), orthogonalised by block CGS2 on
+                              MFMA (two passes of tall-skinny contractions)
+                              and CholQR2; the block Hessenberg least
+                              squares runs on the host in FP64 (Householder).
+                              Columns whose true residual reaches tol leave
+                              the block at a restart; residuals that are
+                              linearly dependent fall back to pseudo-block
+                              GMRES.  Device memory: 16 n (2 m + 4) x 16
+                              bytes.  iterations counts block steps       */
+  HELM_SOLVE_GRAPHS = 8    /* with HELM_SOLVE_BLOCK_GMRES: replay each
+                              block step's device work (preconditioner,
+                              product with A, Gram-Schmidt, copy of the
+                              Hessenberg column) from a HIP graph captured
+                              on its first use (one graph per step index;
+                              kept until the preconditioner changes)      */
 };
 
 typedef struct helm_solve_opts {

@@ -14,12 +14,16 @@
 
 namespace helm {
 
+// A failing HIP call also sets the runtime's last error, which the next
+// hipGetLastError would report again: it is cleared before the throw.
 #define HELM_HIP(call)                                                                              \
   do {                                                                                              \
     hipError_t e_ = (call);                                                                         \
-    if (e_ != hipSuccess)                                                                           \
+    if (e_ != hipSuccess) {                                                                         \
+      (void)hipGetLastError();                                                                      \
       ::helm::fail(e_ == hipErrorOutOfMemory ? HELM_ENOMEM : HELM_EDEVICE,                          \
                    std::string(#call) + ": " + hipGetErrorString(e_));                              \
+    }                                                                                               \
   } while (0)
 
 // Owning device array.
@@ -252,6 +256,28 @@ struct Ctx {
   DVec<double> bV[dev::kMaxBlock], bZ[dev::kMaxBlock], bw[dev::kMaxBlock];
   DVec<double> bhcol, bhtmp, bpartial, by, bX, bZb, bW, bq, bt, bcvec, bcoef_w, bcoef_v;
   double* bh_host = nullptr;  // pinned, kMaxBlock x (2 m + 4) complex
+  // block GMRES (one Krylov basis of 16-column blocks shared by the block's
+  // right-hand sides): bases V (m + 1 blocks) and Z_m (m blocks), W, the
+  // block iterate X and right-hand sides B, reduction partials, coefficient
+  // blocks, the 16 x 16 factors and their status; bg_host (pinned) receives
+  // a step's Hessenberg block column
+  int bg_m = 0;
+  int64_t bg_n = 0;
+  DVec<double> bgV, bgZ, bgW, bgX, bgB, bgpart, bgH, bgC;
+  DVec<int> bgstat;
+  double* bg_host = nullptr;
+  int* bg_hstat = nullptr;
+  // captured device work of block GMRES step j (per restart position),
+  // valid for bg_graph_s active columns
+  std::vector<hipGraphExec_t> bg_graph;
+  int bg_graph_s = 0;
+  // stream the graphs are captured on and replayed from (the caller's may be
+  // the legacy null stream, which cannot be captured), joined to the
+  // caller's stream by bg_ev[0] (caller -> graph) and bg_ev[1] (graph -> caller)
+  hipStream_t bg_stream = nullptr;
+  hipEvent_t bg_ev[2] = {};
+  int64_t bg_fallbacks = 0;  // blocks handed to pseudo-block GMRES (dependent residuals)
+  void free_bg_graphs();
   ~Ctx();
   void free_precond();
   void free_solve_work();

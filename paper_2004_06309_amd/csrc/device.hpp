@@ -221,6 +221,26 @@ void fwd_level_mfma(const Batch& b, const int32_t* sns, int64_t nsn, int gy, int
                     hipStream_t s);
 void bwd_level_mfma(const Batch& b, const int32_t* sns, int64_t nsn, int gy, int64_t tile0, int64_t ntiles,
                     int64_t nwide, const double* yb, double* xb, void* stage, bool coarse, hipStream_t s);
+// ---- block Gram-Schmidt of block GMRES (device_bgmres.hip): n x 16
+//      interleaved complex blocks, X_j = X + j ldx (ldx in doubles) ----
+// workgroups of bgs_dots (the partial sums per basis block) and of bgs_mul
+int bgs_wgs(int64_t n);
+int bgs_mul_wgs(int64_t n);
+// partial[(wg * (nb + with_w) + j) * 256 + a * 16 + c] = sum over workgroup
+// wg's rows of conj(X_j[row][a]) W[row][c]; block nb is W itself (with_w)
+void bgs_dots(int64_t n, const double* X, int64_t ldx, int nb, bool with_w, const double* W, double* partial,
+              hipStream_t s);
+// out (and acc, = or +=) [j * 256 + e] = sum over nwg workgroups of the partials
+void bgs_reduce(const double* partial, int nwg, int nbt, double* out, double* acc, bool accumulate, hipStream_t s);
+// Y = (Y0 or 0) + sign sum_{j < nb} X_j C_j (C_j = C + 512 j doubles, 16 x
+// 16 row-major); gram: per-workgroup partial Y^H Y (bgs_mul_wgs of them)
+void bgs_mul(int64_t n, const double* X, int64_t ldx, int nb, const double* C, double sign, const double* Y0,
+             double* Y, double* gram, hipStream_t s);
+// G = L L^H on the leading s x s part: R = L^H, T = L^{-H}; status 0, or
+// 1 + k if pivot k is not above tiny max_k ref[k][k] (ref null: tiny)
+void chol16(const double* G, int s_act, const double* ref, double tiny, double* R, double* T, int* status,
+            hipStream_t s);
+
 // y = A x (or b - A x) for S interleaved vectors from the CSR copy of A.
 // xr / xrows: XCD row ranges as for spmv (nullptr: plain order).
 void csr_spmv_block(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const int64_t* xr,

@@ -31,6 +31,12 @@ Ctx::~Ctx() {
   if (h_host) (void)hipHostFree(h_host);
   if (bh_host) (void)hipHostFree(bh_host);
   if (nh_host) (void)hipHostFree(nh_host);
+  free_bg_graphs();
+  if (bg_host) (void)hipHostFree(bg_host);
+  if (bg_hstat) (void)hipHostFree(bg_hstat);
+  for (auto& e : bg_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (bg_stream) (void)hipStreamDestroy(bg_stream);
 }
 
 // Work spaces of the solvers: their sizes follow n, the restart, the coarse
@@ -49,6 +55,11 @@ void Ctx::free_solve_work() {
   }
   for (auto* v : {&bhcol, &bhtmp, &bpartial, &by, &bX, &bZb, &bW, &bq, &bt, &bcvec, &bcoef_w, &bcoef_v}) v->reset();
   for (auto* v : {&t, &q, &cvec}) v->reset();
+  free_bg_graphs();
+  bg_m = 0;
+  bg_n = 0;
+  for (auto* v : {&bgV, &bgZ, &bgW, &bgX, &bgB, &bgpart, &bgH, &bgC}) v->reset();
+  bgstat.reset();
 }
 
 void Ctx::free_precond() {
@@ -1648,6 +1659,7 @@ void ensure_width(Ctx& c, int m, int S) {
   const int64_t n = c.D.n;
   if (c.blk_m != m || c.blk_n != n) ensure_bases(c, m, 0);
   if (c.blk_cap < S) {
+    c.free_bg_graphs();  // captured block steps point into these buffers
     c.bhcol.alloc(2 * (size_t)dev::kMaxBlock * blk_ld(m));
     c.bhtmp.alloc(2 * (size_t)dev::kMaxBlock * blk_ld(m));
     c.bpartial.alloc(2 * (size_t)dev::kMaxBlock * dev::gs_tiles(n) * blk_ld(m));
@@ -1680,6 +1692,10 @@ void ensure_width(Ctx& c, int m, int S) {
     }
   }
   int64_t npos_all = 0;
+  bool grows = c.nbatch > 1 && c.xall_b_S < S;
+  for (int k = 0; k < c.nbatch; ++k) grows = grows || c.fine[k].blk_S < S;
+  if (c.two_level) grows = grows || c.coarse.blk_S < S;
+  if (grows) c.free_bg_graphs();
   for (int k = 0; k < c.nbatch; ++k) {
     ensure_batch_block(c.fine[k], S);
     npos_all += c.fine[k].npos;
@@ -2005,6 +2021,401 @@ int solve_block(Ctx& c, int nb, const double* const* Bp, double* const* Up, doub
   return status;
 }
 
+// ---- block GMRES ---------------------------------------------------------
+//
+// One block Krylov space for up to 16 right-hand sides (right-preconditioned
+// flexible block GMRES): the block residual R_0 = V_0 beta, each step
+// Z_j = M^{-1} V_j, W = A Z_j, block CGS2 against V_0..V_j (two passes of
+// tall-skinny MFMA contractions), CholQR2 of W into V_{j+1} R_{j+1}; the
+// block Hessenberg matrix is reduced by Householder reflections on the host
+// (FP64) and every right-hand side's residual estimate is read off the
+// rotated right-hand side.  At a restart the columns whose true residual
+// reached the tolerance leave the block.  All device work of a step runs on
+// the solve stream with one copy to the host at its end, so a step can be
+// replayed from a captured graph.
+
+}  // namespace
+
+void Ctx::free_bg_graphs() {
+  for (auto& g : bg_graph)
+    if (g) (void)hipGraphExecDestroy(g);
+  bg_graph.clear();
+  bg_graph_s = 0;
+}
+
+namespace {
+
+constexpr size_t kBlk = 2 * 16 * (size_t)16;  // doubles of a 16 x 16 complex block
+constexpr int64_t kGramWgsMax = 1 << 30;
+
+struct BgLayout {
+  // offsets (doubles) into bgH
+  size_t htot, htmp, r1, r2, g0, g1, g2, t1, t2, total;
+};
+BgLayout bg_layout(int m) {
+  BgLayout L{};
+  size_t o = 0;
+  L.htot = o;
+  o += (size_t)(m + 1) * kBlk;
+  L.htmp = o;
+  o += (size_t)(m + 1) * kBlk;
+  for (size_t* f : {&L.r1, &L.r2, &L.g0, &L.g1, &L.g2, &L.t1, &L.t2}) {
+    *f = o;
+    o += kBlk;
+  }
+  L.total = o;
+  return L;
+}
+
+size_t bg_bytes(int64_t n, int m) {
+  const size_t blk = 2 * 16 * (size_t)n;  // doubles of an n x 16 block
+  const size_t part = std::max<size_t>((size_t)dev::bgs_wgs(n) * (m + 2), (size_t)dev::bgs_mul_wgs(n)) * kBlk;
+  return sizeof(double) * ((size_t)(2 * m + 1) * blk + 3 * blk + part + bg_layout(m).total + (size_t)m * kBlk);
+}
+
+void ensure_bg(Ctx& c, int m) {
+  const int64_t n = c.D.n;
+  ensure_width(c, c.blk_m > 0 ? c.blk_m : m, dev::kMaxBlock);
+  if (c.bg_m == m && c.bg_n == n && c.bgV.p) return;
+  c.free_bg_graphs();
+  const size_t blk = 2 * 16 * (size_t)n;
+  c.bgV.alloc(blk * (m + 1));
+  c.bgZ.alloc(blk * m);
+  c.bgW.alloc(blk);
+  c.bgX.alloc(blk);
+  c.bgB.alloc(blk);
+  c.bgpart.alloc(std::max<size_t>((size_t)dev::bgs_wgs(n) * (m + 2), (size_t)dev::bgs_mul_wgs(n)) * kBlk);
+  c.bgH.alloc(bg_layout(m).total);
+  c.bgC.alloc((size_t)m * kBlk);
+  c.bgstat.alloc(2);
+  if (c.bg_host) (void)hipHostFree(c.bg_host);
+  c.bg_host = nullptr;
+  HELM_HIP(hipHostMalloc((void**)&c.bg_host, sizeof(double) * ((size_t)(m + 1) * kBlk + 2 * kBlk), hipHostMallocDefault));
+  if (!c.bg_hstat) HELM_HIP(hipHostMalloc((void**)&c.bg_hstat, 2 * sizeof(int), hipHostMallocDefault));
+  c.bg_m = m;
+  c.bg_n = n;
+}
+
+// Column norms of an n x 16 block from its Gram matrix (host copy).
+std::vector<double> gram_diag(const double* G, int sa) {
+  std::vector<double> d(sa);
+  for (int q = 0; q < sa; ++q) d[q] = std::sqrt(std::max(0.0, G[2 * (q * 17)]));
+  return d;
+}
+
+// Y = Y Q with the Gram partials of the result reduced into G (device).
+void gram_of(Ctx& c, const double* Y, double* G, hipStream_t s) {
+  const int64_t n = c.D.n;
+  dev::bgs_mul(n, nullptr, 0, 0, nullptr, 1.0, Y, const_cast<double*>(Y), c.bgpart.p, s);
+  dev::bgs_reduce(c.bgpart.p, dev::bgs_mul_wgs(n), 1, G, nullptr, false, s);
+}
+
+// Device work of block Arnoldi step j (sa active columns): Z_j = M^{-1} V_j,
+// W = A Z_j, two CGS passes against V_0..V_j (coefficients summed into
+// htot), CholQR2 of W into V_{j+1} (R1, R2, status), then the copy of the
+// block column and the factors to bg_host.  Enqueued on s only.
+void bg_step_device(Ctx& c, int j, int sa, hipStream_t s) {
+  const int64_t n = c.D.n;
+  const size_t blk = 2 * 16 * (size_t)n;
+  const BgLayout L = bg_layout(c.bg_m);
+  double* H = c.bgH.p;
+  const double* Vj = c.bgV.p + blk * j;
+  double* Zj = c.bgZ.p + blk * j;
+  double* W = c.bgW.p;
+  apply_precond_block(c, dev::kMaxBlock, Vj, Zj, s);
+  spmv_block(c, dev::kMaxBlock, Zj, nullptr, W, s);
+  const bool prof = c.prof.on;
+  if (prof) c.prof.begin(s);
+  const int nb = j + 1, nwg = dev::bgs_wgs(n), mwg = dev::bgs_mul_wgs(n);
+  // pass 1: V^H W and W^H W (the scale breakdowns are measured against)
+  dev::bgs_dots(n, c.bgV.p, blk, nb, true, W, c.bgpart.p, s);
+  dev::bgs_reduce(c.bgpart.p, nwg, nb + 1, H + L.htmp, nullptr, false, s);
+  dev::copy((int64_t)nb * kBlk, H + L.htmp, H + L.htot, s);
+  dev::copy(kBlk, H + L.htmp + nb * kBlk, H + L.g0, s);
+  dev::bgs_mul(n, c.bgV.p, blk, nb, H + L.htmp, -1.0, W, W, nullptr, s);
+  // pass 2
+  dev::bgs_dots(n, c.bgV.p, blk, nb, false, W, c.bgpart.p, s);
+  dev::bgs_reduce(c.bgpart.p, nwg, nb, H + L.htmp, H + L.htot, true, s);
+  dev::bgs_mul(n, c.bgV.p, blk, nb, H + L.htmp, -1.0, W, W, c.bgpart.p, s);
+  dev::bgs_reduce(c.bgpart.p, mwg, 1, H + L.g1, nullptr, false, s);
+  // CholQR2: W = V_{j+1} R2 R1
+  double* Vn = c.bgV.p + blk * (j + 1);
+  dev::chol16(H + L.g1, sa, H + L.g0, 1e-24, H + L.r1, H + L.t1, c.bgstat.p, s);
+  dev::bgs_mul(n, W, 0, 1, H + L.t1, 1.0, nullptr, Vn, c.bgpart.p, s);
+  dev::bgs_reduce(c.bgpart.p, mwg, 1, H + L.g2, nullptr, false, s);
+  dev::chol16(H + L.g2, sa, nullptr, 1e-12, H + L.r2, H + L.t2, c.bgstat.p + 1, s);
+  dev::bgs_mul(n, Vn, 0, 1, H + L.t2, 1.0, nullptr, Vn, nullptr, s);
+  if (prof) c.prof.end(HELM_K_GS, 16.0 * 16.0 * (double)n * (4.0 * nb + 12.0), s);
+  HELM_HIP(hipMemcpyAsync(c.bg_host, H + L.htot, sizeof(double) * nb * kBlk, hipMemcpyDeviceToHost, s));
+  HELM_HIP(hipMemcpyAsync(c.bg_host + (size_t)(c.bg_m + 1) * kBlk, H + L.r1, sizeof(double) * 2 * kBlk,
+                          hipMemcpyDeviceToHost, s));
+  HELM_HIP(hipMemcpyAsync(c.bg_hstat, c.bgstat.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+}
+
+// Step j from its captured graph (captured on first use for sa columns), on
+// the library's graph stream, ordered after the caller's earlier work on s
+// and before its later work.
+void bg_step(Ctx& c, int j, int sa, bool graphs, hipStream_t s) {
+  if (!graphs || c.prof.on) {
+    bg_step_device(c, j, sa, s);
+    return;
+  }
+  if (!c.bg_stream) HELM_HIP(hipStreamCreateWithFlags(&c.bg_stream, hipStreamNonBlocking));
+  for (auto& e : c.bg_ev)
+    if (!e) HELM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  if (c.bg_graph_s != sa || (int)c.bg_graph.size() != c.bg_m) {
+    c.free_bg_graphs();
+    c.bg_graph.assign(c.bg_m, nullptr);
+    c.bg_graph_s = sa;
+  }
+  hipStream_t g = c.bg_stream;
+  HELM_HIP(hipEventRecord(c.bg_ev[0], s));
+  HELM_HIP(hipStreamWaitEvent(g, c.bg_ev[0], 0));
+  if (!c.bg_graph[j]) {
+    hipGraph_t gr = nullptr;
+    HELM_HIP(hipStreamBeginCapture(g, hipStreamCaptureModeRelaxed));
+    try {
+      bg_step_device(c, j, sa, g);
+    } catch (...) {
+      (void)hipStreamEndCapture(g, &gr);
+      if (gr) (void)hipGraphDestroy(gr);
+      (void)hipGetLastError();
+      throw;
+    }
+    HELM_HIP(hipStreamEndCapture(g, &gr));
+    hipGraphExec_t e = nullptr;
+    const hipError_t err = hipGraphInstantiate(&e, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    HELM_HIP(err);
+    c.bg_graph[j] = e;
+  }
+  HELM_HIP(hipGraphLaunch(c.bg_graph[j], g));
+  HELM_HIP(hipEventRecord(c.bg_ev[1], g));
+  HELM_HIP(hipStreamWaitEvent(s, c.bg_ev[1], 0));
+}
+
+// Householder reflector (LAPACK zlarfg convention): H^H (alpha; x) = (beta; 0)
+// with H = I - tau v v^H, v(0) = 1.  x is overwritten by v(1:).
+void house(cplx& alpha, cplx* x, int len, cplx& tau) {
+  double xn = 0;
+  for (int i = 0; i < len; ++i) xn += std::norm(x[i]);
+  xn = std::sqrt(xn);
+  if (xn == 0 && alpha.imag() == 0) {
+    tau = 0;
+    return;
+  }
+  double beta = -std::copysign(std::sqrt(std::norm(alpha) + xn * xn), alpha.real());
+  tau = (beta - alpha) / beta;
+  const cplx sc = 1.0 / (alpha - beta);
+  for (int i = 0; i < len; ++i) x[i] *= sc;
+  alpha = beta;
+}
+
+// y <- H^H y = y - conj(tau) v (v^H y) on rows [k, k + len]
+void apply_house(const cplx* v, cplx tau, cplx* y, int len) {
+  if (tau == cplx(0, 0)) return;
+  cplx d = y[0];
+  for (int i = 1; i <= len; ++i) d += std::conj(v[i - 1]) * y[i];
+  d *= std::conj(tau);
+  y[0] -= d;
+  for (int i = 1; i <= len; ++i) y[i] -= d * v[i - 1];
+}
+
+int solve_bgmres(Ctx& c, int nrhs, const double* const* Bp, double* const* Up, double tol, int m, int maxit, bool x0,
+                 bool graphs, hipStream_t s, helm_solve_info* info, bool& fallback) {
+  fallback = false;
+  ensure_bg(c, m);
+  const int64_t n = c.D.n;
+  const size_t blk = 2 * 16 * (size_t)n;
+  const BgLayout L = bg_layout(m);
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<double> bnorm(nrhs), rel(nrhs, 0);
+  std::vector<int> its(nrhs, 0), conv(nrhs, 0), act;
+  for (int r = 0; r < nrhs; ++r) {
+    bnorm[r] = device_norm(c, Bp[r], s);
+    if (!std::isfinite(bnorm[r])) fail(HELM_ENUMERIC, "non-finite right-hand side");
+    if (bnorm[r] == 0 || !x0) dev::fill_zero(2 * n, Up[r], s);
+    if (bnorm[r] == 0)
+      conv[r] = 1;
+    else
+      act.push_back(r);
+  }
+  std::vector<double> hG(kBlk);
+  // Householder data of a cycle: columns of the rotated block Hessenberg
+  // matrix (ld rows), reflector vectors and factors, rotated right-hand sides
+  std::vector<cplx> Hh, V, tau, G, Y;
+  bool pack_needed = true;
+  while (!act.empty()) {
+    const int sa = (int)act.size();
+    if (pack_needed) {
+      dev::PtrSetC bs{}, us{};
+      for (int q = 0; q < sa; ++q) {
+        bs.p[q] = Bp[act[q]];
+        us.p[q] = Up[act[q]];
+      }
+      dev::pack(n, 16, bs, c.bgB.p, s);
+      dev::pack(n, 16, us, c.bgX.p, s);
+      pack_needed = false;
+    }
+    // true block residual R = B - A X into V_0, its Gram matrix
+    spmv_block(c, 16, c.bgX.p, c.bgB.p, c.bgV.p, s);
+    gram_of(c, c.bgV.p, c.bgH.p + L.g0, s);
+    HELM_HIP(hipMemcpyAsync(hG.data(), c.bgH.p + L.g0, sizeof(double) * kBlk, hipMemcpyDeviceToHost, s));
+    HELM_HIP(hipStreamSynchronize(s));
+    const std::vector<double> rn = gram_diag(hG.data(), sa);
+    std::vector<int> keep;
+    bool changed = false;
+    for (int q = 0; q < sa; ++q) {
+      const int r = act[q];
+      if (!std::isfinite(rn[q])) fail(HELM_ENUMERIC, "non-finite residual");
+      rel[r] = rn[q] / bnorm[r];
+      if (rn[q] <= tol * bnorm[r]) {
+        conv[r] = 1;
+        changed = true;
+      } else if (its[r] >= maxit) {
+        changed = true;
+      } else {
+        keep.push_back(r);
+      }
+    }
+    if (changed) {
+      // finished columns leave the block: write every column back, repack
+      dev::PtrSet us{};
+      for (int q = 0; q < sa; ++q) us.p[q] = Up[act[q]];
+      dev::unpack(n, 16, c.bgX.p, us, s);
+      act = keep;
+      pack_needed = true;
+      continue;
+    }
+    // R_0 = V_0 beta (CholQR2)
+    double* H = c.bgH.p;
+    dev::chol16(H + L.g0, sa, H + L.g0, 1e-28, H + L.r1, H + L.t1, c.bgstat.p, s);
+    dev::bgs_mul(n, c.bgV.p, 0, 1, H + L.t1, 1.0, nullptr, c.bgV.p, c.bgpart.p, s);
+    dev::bgs_reduce(c.bgpart.p, dev::bgs_mul_wgs(n), 1, H + L.g2, nullptr, false, s);
+    dev::chol16(H + L.g2, sa, nullptr, 1e-12, H + L.r2, H + L.t2, c.bgstat.p + 1, s);
+    dev::bgs_mul(n, c.bgV.p, 0, 1, H + L.t2, 1.0, nullptr, c.bgV.p, nullptr, s);
+    HELM_HIP(hipMemcpyAsync(c.bg_host + (size_t)(m + 1) * kBlk, H + L.r1, sizeof(double) * 2 * kBlk,
+                            hipMemcpyDeviceToHost, s));
+    HELM_HIP(hipMemcpyAsync(c.bg_hstat, c.bgstat.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HELM_HIP(hipStreamSynchronize(s));
+    if (c.bg_hstat[0] || c.bg_hstat[1]) {
+      // the residuals are (numerically) linearly dependent: hand the
+      // remaining columns, with their current iterates, to pseudo-block GMRES
+      dev::PtrSet us{};
+      for (int q = 0; q < sa; ++q) us.p[q] = Up[act[q]];
+      dev::unpack(n, 16, c.bgX.p, us, s);
+      HELM_HIP(hipStreamSynchronize(s));
+      fallback = true;
+      std::vector<const double*> b2;
+      std::vector<double*> u2;
+      for (int r : act) {
+        b2.push_back(Bp[r]);
+        u2.push_back(Up[r]);
+      }
+      std::vector<helm_solve_info> inf2(act.size());
+      const int st = solve_block(c, (int)act.size(), b2.data(), u2.data(), tol, m, std::max(1, maxit - its[act[0]]),
+                                 true, true, s, inf2.data());
+      for (size_t q = 0; q < act.size(); ++q) {
+        its[act[q]] += inf2[q].iterations;
+        conv[act[q]] = inf2[q].converged;
+        rel[act[q]] = inf2[q].relres;
+      }
+      (void)st;
+      act.clear();
+      break;
+    }
+    // beta = R2 R1 (upper s x s); G = [beta; 0]
+    const int ld = (m + 1) * sa;
+    auto hostblk = [&](size_t off, int a, int col) {
+      const double* p = c.bg_host + off + 2 * (size_t)(a * 16 + col);
+      return cplx(p[0], p[1]);
+    };
+    const size_t offR1 = (size_t)(m + 1) * kBlk, offR2 = offR1 + kBlk;
+    auto rprod = [&](int a, int col) {  // (R2 R1)[a][col]
+      cplx v = 0;
+      for (int k = 0; k < sa; ++k) v += hostblk(offR2, a, k) * hostblk(offR1, k, col);
+      return v;
+    };
+    G.assign((size_t)ld * sa, 0);
+    for (int a = 0; a < sa; ++a)
+      for (int q = 0; q < sa; ++q) G[(size_t)q * ld + a] = rprod(a, q);
+    Hh.assign((size_t)ld * m * sa, 0);
+    V.assign((size_t)m * sa * sa, 0);
+    tau.assign((size_t)m * sa, 0);
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      bg_step(c, j, sa, graphs, s);
+      HELM_HIP(hipStreamSynchronize(s));
+      if (c.prof.on) c.prof.harvest();
+      for (size_t i = 0; i < (size_t)(j + 1) * kBlk + 2 * kBlk; ++i) {
+        const size_t at = i < (size_t)(j + 1) * kBlk ? i : offR1 + (i - (size_t)(j + 1) * kBlk);
+        if (!std::isfinite(c.bg_host[at])) fail(HELM_ENUMERIC, "non-finite block Hessenberg entry");
+      }
+      const bool brk = c.bg_hstat[0] != 0 || c.bg_hstat[1] != 0;
+      // block column j: H̄[jb s + a][j s + q] = htot_jb[a][q]; R_{j+1} below
+      for (int q = 0; q < sa; ++q) {
+        const int jc = j * sa + q;
+        cplx* col = Hh.data() + (size_t)jc * ld;
+        for (int jb = 0; jb <= j; ++jb)
+          for (int a = 0; a < sa; ++a) col[jb * sa + a] = hostblk((size_t)jb * kBlk, a, q);
+        for (int a = 0; a < sa; ++a) col[(j + 1) * sa + a] = brk ? cplx(0, 0) : rprod(a, q);
+        // earlier reflectors, then this column's
+        for (int pc = 0; pc < jc; ++pc) apply_house(V.data() + (size_t)pc * sa, tau[pc], col + pc, sa);
+        cplx alpha = col[jc];
+        cplx* x = col + jc + 1;
+        for (int i = 0; i < sa; ++i) V[(size_t)jc * sa + i] = x[i];
+        house(alpha, V.data() + (size_t)jc * sa, sa, tau[jc]);
+        col[jc] = alpha;
+        for (int i = 0; i < sa; ++i) x[i] = 0;
+        for (int g = 0; g < sa; ++g) apply_house(V.data() + (size_t)jc * sa, tau[jc], G.data() + (size_t)g * ld + jc, sa);
+      }
+      for (int r : act) ++its[r];
+      k = j + 1;
+      bool all = true;
+      for (int q = 0; q < sa; ++q) {
+        double e = 0;
+        for (int a = 0; a < sa; ++a) e += std::norm(G[(size_t)q * ld + (j + 1) * sa + a]);
+        if (std::sqrt(e) > tol * bnorm[act[q]]) all = false;
+      }
+      if (brk || all || its[act[0]] >= maxit) break;
+    }
+    // Y = Rtri^{-1} G(0 : k sa) and X += sum_j Z_j Y_j
+    const int kk = k * sa;
+    Y.assign((size_t)kk * sa, 0);
+    for (int q = 0; q < sa; ++q)
+      for (int i = kk - 1; i >= 0; --i) {
+        cplx acc = G[(size_t)q * ld + i];
+        for (int l = i + 1; l < kk; ++l) acc -= Hh[(size_t)l * ld + i] * Y[(size_t)q * kk + l];
+        Y[(size_t)q * kk + i] = acc / Hh[(size_t)i * ld + i];
+      }
+    std::vector<double> Cb((size_t)k * kBlk, 0.0);
+    for (int jb = 0; jb < k; ++jb)
+      for (int a = 0; a < sa; ++a)
+        for (int q = 0; q < sa; ++q) {
+          const cplx v = Y[(size_t)q * kk + jb * sa + a];
+          Cb[(size_t)jb * kBlk + 2 * (a * 16 + q)] = v.real();
+          Cb[(size_t)jb * kBlk + 2 * (a * 16 + q) + 1] = v.imag();
+        }
+    HELM_HIP(hipMemcpyAsync(c.bgC.p, Cb.data(), sizeof(double) * Cb.size(), hipMemcpyHostToDevice, s));
+    dev::bgs_mul(n, c.bgZ.p, blk, k, c.bgC.p, 1.0, c.bgX.p, c.bgX.p, nullptr, s);
+    HELM_HIP(hipStreamSynchronize(s));  // Cb is reused
+  }
+  HELM_HIP(hipStreamSynchronize(s));
+  if (c.prof.on) c.prof.harvest();
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int status = HELM_OK;
+  for (int r = 0; r < nrhs; ++r) {
+    if (info) {
+      info[r].iterations = its[r];
+      info[r].converged = conv[r];
+      info[r].relres = rel[r];
+      info[r].seconds = secs;
+    }
+    if (!conv[r]) status = HELM_ENOCONV;
+  }
+  return status;
+}
+
 }  // namespace
 
 int solve(Ctx& c, int32_t nrhs, const double* B, double tol, const helm_solve_opts* opts, double* U, hipStream_t s,
@@ -2018,6 +2429,8 @@ int solve(Ctx& c, int32_t nrhs, const double* B, double tol, const helm_solve_op
   if (!(tol > 0)) fail(HELM_EINVAL, "tol must be positive");
   if (block <= 1 || nrhs <= 1) return solve_single(c, nrhs, B, tol, m, maxit, x0, dcgs2, U, s, info);
   const int64_t n = c.D.n;
+  const bool bgm = opts && (opts->flags & HELM_SOLVE_BLOCK_GMRES);
+  const bool graphs = opts && (opts->flags & HELM_SOLVE_GRAPHS);
   int status = HELM_OK;
   for (int32_t j0 = 0; j0 < nrhs; j0 += block) {
     const int nb = std::min<int>(block, nrhs - j0);
@@ -2027,9 +2440,16 @@ int solve(Ctx& c, int32_t nrhs, const double* B, double tol, const helm_solve_op
       Bp[r] = B + 2 * (size_t)n * (j0 + r);
       Up[r] = U + 2 * (size_t)n * (j0 + r);
     }
-    int st = nb == 1 ? solve_single(c, 1, Bp[0], tol, m, maxit, x0, dcgs2, Up[0], s, info ? info + j0 : nullptr)
-                     : solve_block(c, nb, Bp.data(), Up.data(), tol, m, maxit, x0, dcgs2, s,
-                                   info ? info + j0 : nullptr);
+    int st;
+    if (nb == 1) {
+      st = solve_single(c, 1, Bp[0], tol, m, maxit, x0, dcgs2, Up[0], s, info ? info + j0 : nullptr);
+    } else if (bgm) {
+      bool fb = false;
+      st = solve_bgmres(c, nb, Bp.data(), Up.data(), tol, m, maxit, x0, graphs, s, info ? info + j0 : nullptr, fb);
+      c.bg_fallbacks += fb ? 1 : 0;
+    } else {
+      st = solve_block(c, nb, Bp.data(), Up.data(), tol, m, maxit, x0, dcgs2, s, info ? info + j0 : nullptr);
+    }
     if (st != HELM_OK) status = st;
   }
   return status;

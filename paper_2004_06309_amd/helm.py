@@ -26,6 +26,8 @@ HELM_ESTATE = -6
 HELM_EDEVICE = -7
 HELM_SOLVE_X0 = 1
 HELM_SOLVE_CGS2 = 2
+HELM_SOLVE_BLOCK_GMRES = 4
+HELM_SOLVE_GRAPHS = 8
 
 _ERRNAMES = {-1: "EINVAL", -2: "ESINGULAR", -3: "ENOCONV", -4: "ENUMERIC", -5: "ENOMEM", -6: "ESTATE",
              -7: "EDEVICE"}
@@ -332,10 +334,14 @@ class Helm:
         self._check(self.lib.helm_apply_coarse_noalloc(self.h, self._vec(r, "r"), self._vec(q, "q"),
                                                         _stream(stream)))
 
-    def solve(self, B, U, tol=1e-6, restart=50, maxit=1000, x0=False, stream=None, block=1, classic_cgs2=False):
+    def solve(self, B, U, tol=1e-6, restart=50, maxit=1000, x0=False, stream=None, block=1, classic_cgs2=False,
+              block_gmres=False, graphs=False):
         """Solve A U = B; B, U are (n,) or (nrhs, n) complex128 GPU tensors
         (each RHS contiguous); `block` right-hand sides are advanced together.
-        `classic_cgs2` selects three-pass CGS2 (default: delayed CGS2).
+        `classic_cgs2` selects three-pass CGS2 (default: delayed CGS2);
+        `block_gmres` one shared block Krylov space per block (block CGS2 on
+        MFMA) instead of pseudo-block GMRES, `graphs` its steps replayed
+        from captured HIP graphs.
         Returns (status, [info dicts])."""
         if B.dim() not in (1, 2) or tuple(U.shape) != tuple(B.shape):
             raise ValueError(f"B {tuple(B.shape)} and U {tuple(U.shape)} must both be (n,) or (nrhs, n)")
@@ -343,7 +349,8 @@ class Helm:
         if B.shape[-1] != self.n:
             raise ValueError(f"right-hand sides have {B.shape[-1]} entries, the operator {self.n}")
         info = (SolveInfo * max(nrhs, 1))()
-        flags = (HELM_SOLVE_X0 if x0 else 0) | (HELM_SOLVE_CGS2 if classic_cgs2 else 0)
+        flags = ((HELM_SOLVE_X0 if x0 else 0) | (HELM_SOLVE_CGS2 if classic_cgs2 else 0)
+                 | (HELM_SOLVE_BLOCK_GMRES if block_gmres else 0) | (HELM_SOLVE_GRAPHS if graphs else 0))
         opts = SolveOpts(int(restart), int(maxit), flags, int(block))
         rc = self._check(self.lib.helm_solve(self.h, nrhs, self._vec(B, "B", nrhs), float(tol), C.byref(opts),
                                              self._vec(U, "U", nrhs), _stream(stream), info), allow=(HELM_ENOCONV,))

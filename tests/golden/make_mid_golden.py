@@ -14,12 +14,16 @@ from the HIP library.  Stored values:
   application M^{-1} r (eq. 2lvl), each as its 2-norm and its values at a
   seeded sample of dofs.
 
-Run once on a machine with ~60 GB of memory (the 64 SuperLU factors):
+The 64 SuperLU factorisations take about 60 GB, so the local solves run in
+the oracle's process pool (``oracle.pool``, single-threaded workers: the same
+arithmetic as the sequential oracle, bit for bit).  Run on a host with that
+much memory and a few cores:
 
-    python tests/golden/make_mid_golden.py
+    python tests/golden/make_mid_golden.py [--workers 16]
 
-It takes about half an hour on one core.
+About five minutes with 16 workers.
 """
+import argparse
 import json
 import os
 import resource
@@ -31,7 +35,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-from oracle import precond  # noqa: E402
+from oracle import fem, precond  # noqa: E402
+from oracle.pool import PoolOras  # noqa: E402
 from paper_2004_06309_amd import workloads as wl  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "mid_oracle.json")
@@ -49,14 +54,34 @@ def cplx(v):
 
 
 def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workers", type=int, default=min(16, len(os.sched_getaffinity(0))))
+    args = ap.parse_args()
+    from threadpoolctl import threadpool_limits
+
+    threadpool_limits(1)
     t0 = time.time()
     w = wl.mid()
     log("workload", w.name, "tets", w.n_tets)
-    P, b, M = precond.build(w)
+    P = fem.Problem(w.xyz, w.tets, w.order, w.c_tet, w.omega)
+    b = P.point_source(w.source_point)
+    log(f"assembled, n = {P.n}")
+    M = PoolOras(P, w.part, w.n_sub, w.overlap, (w.coarse_xyz, w.coarse_tets), workers=args.workers, verbose=True)
     t_setup = time.time() - t0
-    log(f"oracle setup {t_setup:.0f} s, n = {P.n}")
+    log(f"oracle setup {t_setup:.0f} s ({args.workers} workers)")
     t1 = time.time()
-    res = precond.solve(P, b, M, tol=w.tol, restart=w.restart, maxit=1000)
+    calls = [0]
+
+    def precond_logged(v):
+        calls[0] += 1
+        if calls[0] % 10 == 0:
+            log(f"preconditioner application {calls[0]}")
+        return M.apply(v)
+
+    class _P:
+        apply = staticmethod(precond_logged)
+
+    res = precond.solve(P, b, _P, tol=w.tol, restart=w.restart, maxit=1000)
     t_solve = time.time() - t1
     log(f"solve: its {res.iterations} relres {res.relres:.3e} converged {res.converged} ({t_solve:.0f} s)")
     sx = wl.sample_dofs(P.n, N_SAMPLE, SEED_SX)
@@ -95,8 +120,9 @@ def main():
             "precond_sample": cplx(z2[sr]),
         },
         "n_sample": N_SAMPLE,
-        "oracle_seconds": {"setup": t_setup, "solve": t_solve},
+        "oracle_seconds": {"setup": t_setup, "solve": t_solve, "workers": args.workers},
     }
+    M.close()
     with open(OUT, "w") as f:
         json.dump(out, f, indent=1)
     log("wrote", OUT)

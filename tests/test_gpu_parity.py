@@ -267,6 +267,89 @@ def test_block_solve(name, nrhs, block, c64):
     say(f"[block] {name} nrhs={nrhs} block={block}: its={[i['iterations'] for i in info]}")
 
 
+def _sources(w, P, k, seed):
+    lo, hi = w.xyz.min(axis=0), w.xyz.max(axis=0)
+    pts = lo + (hi - lo) * np.random.default_rng(seed).uniform(0.1, 0.9, (k, 3))
+    return np.stack([P.point_source(p) for p in pts])
+
+
+@pytest.mark.parametrize("name,nrhs,restart", [("tiny", 3, 50), ("small_p2_2lvl", 16, 3), ("mid_quarter_2lvl", 16, 50),
+                                               ("adapted_p2_2lvl", 5, 8), ("ragged_p2", 7, 50)])
+def test_block_gmres(name, nrhs, restart):
+    """Block GMRES (one block Krylov space, block CGS2 on MFMA, CholQR2,
+    Householder least squares): every right-hand side reaches the true
+    relative residual tol with the oracle's A; at tol 1e-9 the solutions
+    match the oracle's GMRES solutions at 1e-9 to 1e-7 (the same discrete
+    solution; the two Krylov methods differ, so iteration counts are not
+    compared).  Short restarts exercise the deflation of converged columns."""
+    w = WORKLOADS[name]()
+    P, b0, M = opre.build(w)
+    h = helm.from_workload(w)
+    Bs = _sources(w, P, nrhs, 21)
+    B = dvec(Bs)
+    U = torch.zeros_like(B)
+    rc, info = h.solve(B, U, tol=w.tol, restart=restart, block=16, block_gmres=True)
+    assert rc == helm.HELM_OK
+    u = host(U)
+    for r in range(nrhs):
+        assert info[r]["converged"] == 1
+        assert np.linalg.norm(Bs[r] - P.A @ u[r]) / np.linalg.norm(Bs[r]) <= w.tol
+    U.zero_()
+    rc, info9 = h.solve(B, U, tol=1e-9, restart=restart, block=16, block_gmres=True)
+    assert rc == helm.HELM_OK
+    u = host(U)
+    for r in range(nrhs):
+        ro = opre.solve(P, Bs[r], M, tol=1e-9, restart=50)
+        assert np.linalg.norm(u[r] - ro.x) <= 1e-7 * np.linalg.norm(ro.x)
+    say(f"[bgmres] {name} nrhs={nrhs} restart={restart}: block its {info[0]['iterations']} (1e-9: "
+        f"{info9[0]['iterations']}), oracle single its {ro.iterations}")
+
+
+def test_block_gmres_graphs_replay_like_eager():
+    """Block steps replayed from captured HIP graphs give bit for bit the
+    eager result, on every replay (several solves, eager work in between)."""
+    w = WORKLOADS["mid_quarter_2lvl"]()
+    P, b0, M = opre.build(w)
+    h = helm.from_workload(w)
+    B = dvec(_sources(w, P, 16, 5))
+    U0 = torch.zeros_like(B)
+    rc, info0 = h.solve(B, U0, tol=w.tol, block=16, block_gmres=True)
+    for rep in range(3):
+        U = torch.zeros_like(B)
+        rc, info = h.solve(B, U, tol=w.tol, block=16, block_gmres=True, graphs=True)
+        assert rc == helm.HELM_OK
+        assert [i["iterations"] for i in info] == [i["iterations"] for i in info0]
+        assert torch.equal(U, U0), rep
+        # eager work between replays
+        z = torch.empty(P.n, dtype=torch.complex128, device=DEV)
+        h.apply_precond(B[0].contiguous(), z)
+        torch.cuda.synchronize()
+
+
+def test_block_gmres_edge_cases():
+    """A zero right-hand side gets U = 0 in 0 iterations; two equal right-hand
+    sides (dependent block residual) fall back to pseudo-block GMRES; a block
+    that reaches maxit reports HELM_ENOCONV with its last iterates."""
+    w = WORKLOADS["small_p2_2lvl"]()
+    P, b0, M = opre.build(w)
+    h = helm.from_workload(w)
+    Bs = _sources(w, P, 4, 9)
+    Bs[1] = 0
+    Bs[3] = Bs[2]
+    B = dvec(Bs)
+    U = torch.zeros_like(B)
+    rc, info = h.solve(B, U, tol=w.tol, block=4, block_gmres=True)
+    assert rc == helm.HELM_OK
+    u = host(U)
+    assert info[1]["iterations"] == 0 and np.abs(u[1]).max() == 0
+    for r in (0, 2, 3):
+        assert np.linalg.norm(Bs[r] - P.A @ u[r]) / np.linalg.norm(Bs[r]) <= w.tol
+    U.zero_()
+    rc, info = h.solve(B, U, tol=1e-12, block=4, block_gmres=True, maxit=2)
+    assert rc == helm.HELM_ENOCONV
+    assert all(i["iterations"] <= 2 for i in info)
+
+
 @pytest.mark.parametrize("tile_rows,coarse_tile_rows", [(16, 64), (32, 32)])
 def test_tile_rows(tile_rows, coarse_tile_rows):
     """Other solve-tile heights for the subdomain and coarse factors: the
@@ -539,8 +622,13 @@ def test_edge_cases():
 def test_mid_full_size():
     """Mid workload at full size (1.06M P2 dofs, 64 subdomains, two-level), in
     the configuration the benchmark times: sampled SpMV rows and sampled local
-    solves against the oracle, and the true residual of the solve measured with
-    the oracle's assembled A."""
+    solves against the oracle; the true residual of the solve measured with
+    the oracle's assembled A; and, against the oracle's full-size results
+    stored in tests/golden (its GMRES(50) solve and its preconditioner
+    applications to a seeded vector): iteration count within +-2, ||x|| and
+    sampled entries of x within 1e-5, the coarse correction, one-level and
+    two-level applications at sampled dofs within 1e-9, with the coarse solve
+    in both launch forms."""
     from oracle import fem
 
     w = wl.mid()
@@ -580,6 +668,48 @@ def test_mid_full_size():
     u = host(U)
     assert rc == helm.HELM_OK
     assert np.linalg.norm(b - P.A @ u) / np.linalg.norm(b) <= w.tol
+    # against the oracle's own results at this size (tests/golden/mid_oracle.json,
+    # written by tests/golden/make_mid_golden.py from the oracle alone)
+    g = _golden_mid()
+    assert g["n"] == P.n
+    gs = g["solve"]
+    assert abs(info[0]["iterations"] - gs["iterations"]) <= 2
+    assert abs(np.linalg.norm(u) - gs["x_norm"]) <= 1e-5 * gs["x_norm"]
+    sx = wl.sample_dofs(P.n, g["n_sample"], gs["sample_seed"])
+    xs = _cplx(gs["x_sample"])
+    assert np.linalg.norm(u[sx] - xs) <= 1e-5 * np.linalg.norm(xs)
+    ga = g["apply"]
+    r = wl.random_vector(P.n, ga["r_seed"])
+    sr = wl.sample_dofs(P.n, g["n_sample"], ga["sample_seed"])
+    out = torch.empty(P.n, dtype=torch.complex128, device=DEV)
+    for fn, key in ((h.apply_coarse, "q"), (h.apply_oras, "oras"), (h.apply_precond, "precond")):
+        fn(dvec(r), out)
+        v = host(out)
+        ref = _cplx(ga[key + "_sample"])
+        assert rel(v[sr], ref) <= 1e-9, key
+        assert abs(np.linalg.norm(v) - ga[key + "_norm"]) <= 1e-9 * ga[key + "_norm"], key
+    h.close()
+    # both forms of the coarse solve, forced, at this size
+    for mode in (1, 2):
+        say(f"[mid] coarse launch mode {mode}")
+        h2 = helm.from_workload(w, coarse_launch=mode)
+        h2.apply_coarse(dvec(r), out)
+        assert rel(host(out)[sr], _cplx(ga["q_sample"])) <= 1e-9, mode
+        h2.apply_precond(dvec(r), out)
+        assert rel(host(out)[sr], _cplx(ga["precond_sample"])) <= 1e-9, mode
+        h2.close()
+
+
+def _golden_mid():
+    import json
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "mid_oracle.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+def _cplx(d):
+    return np.asarray(d["re"]) + 1j * np.asarray(d["im"])
 
 
 def _serve(servers, plan):

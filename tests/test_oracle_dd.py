@@ -287,3 +287,28 @@ def test_interface_impedance_term_with_overlap(order, overlap):
         assert abs(got - expect) <= 1e-11 * abs(expect), (i, got, expect)
         checked += 1
     assert checked == 4
+
+
+def test_pool_oras_equals_sequential_oras(small):
+    """The pooled oracle (factors in single-threaded worker processes)
+    applies the same one- and two-level preconditioner as Oras, bit for bit
+    when Oras also factors with one BLAS thread (threaded BLAS inside
+    SuperLU only reorders sums)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.pool import PoolOras
+
+    w, P, b, _ = small
+    with threadpool_limits(1):
+        M = precond.Oras(P, w.part, w.n_sub, w.overlap, (w.coarse_xyz, w.coarse_tets))
+    pm = PoolOras(P, w.part, w.n_sub, w.overlap, (w.coarse_xyz, w.coarse_tets), workers=2)
+    try:
+        r = wl.random_vector(P.n, 3)
+        assert np.array_equal(pm.one_level(r), M.one_level(r))
+        assert np.array_equal(pm.apply(r), M.apply(r))
+        assert len(pm.sub_times) == w.n_sub
+        ro = precond.solve(P, b, M)
+        rp = precond.solve(P, b, pm)
+        assert rp.iterations == ro.iterations and np.array_equal(rp.x, ro.x)
+    finally:
+        pm.close()
