@@ -141,6 +141,17 @@ class PoolOras:
             z[s.dofs] += s.D * self._y[self.offs[i]:self.offs[i] + s.dofs.size]
         return z
 
+    def solve_each(self, r):
+        """Local solves of r on one worker at a time (no other solve running):
+        {subdomain: seconds}, the uncontended single-core times."""
+        self._r[:] = r
+        ts = {}
+        for a in self._conns:
+            a.send("solve")
+            tag, t = a.recv()
+            ts.update(t)
+        return ts
+
     def coarse_correction(self, r):
         return self.Z @ self.Elu.solve(self.Z.T @ r)
 

@@ -342,3 +342,20 @@ def random_vector(n: int, seed: int) -> np.ndarray:
 def sample_dofs(n: int, count: int, seed: int) -> np.ndarray:
     """Seeded sorted sample of distinct dof indices."""
     return np.sort(np.random.default_rng(seed).choice(n, count, replace=False))
+
+
+def thrust_box(nxy: int, nz: int, freq: float, n_parts=(8, 8, 1), overlap: int = 2, two_level: bool = True,
+               seed: int = 0, n_layers: int = 12, name: str = "thrust") -> Workload:
+    """The 8 x 8 x 2 km thrust model (as in mid) on an nxy x nxy x nz Kuhn
+    mesh, P2, at frequency freq, source at (4000, 4000, 10) m, box
+    subdomains, and (nxy, nz even) the nested P1 coarse mesh at twice the
+    element size."""
+    xyz, tets = kuhn_mesh(nxy, nxy, nz, 8000.0, 8000.0, 2000.0)
+    model = ThrustModel.draw(8000.0, 8000.0, 2000.0, n_layers, seed)
+    c = model.velocity(tet_centroids(xyz, tets)).astype(np.complex128)
+    part = box_partition(xyz, tets, n_parts)
+    cx = cy = None
+    if two_level:
+        cx, cy = kuhn_mesh(nxy // 2, nxy // 2, nz // 2, 8000.0, 8000.0, 2000.0)
+    return Workload(f"{name} {nxy}x{nxy}x{nz} at {freq:g} Hz", xyz, tets, 2, c, 2 * np.pi * freq, part,
+                    int(np.prod(n_parts)), overlap, cx, cy, np.array([4000.0, 4000.0, 10.0]), None)
