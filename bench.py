@@ -293,8 +293,13 @@ def run_serving(ops, n_solves, rate, seed):
     from paper_2004_06309_amd import helm
 
     servers = []
-    for w, h in ops:
-        servers.append(helm.Server(h, slots=16, restart=w.restart, tol=w.tol, stream=torch.cuda.Stream()))
+    try:
+        for w, h in ops:
+            servers.append(helm.Server(h, slots=16, restart=w.restart, tol=w.tol, stream=torch.cuda.Stream()))
+    except Exception:
+        for s_ in servers:
+            s_.close()
+        raise
     rng = np.random.default_rng(seed)
     reqs, B, U, tag, t_arr = [], {}, {}, 0, 0.0
     while tag < n_solves:

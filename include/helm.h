@@ -166,7 +166,10 @@ typedef struct helm_server_opts {
                               slots (each slot's Krylov basis, 16 (2 m + 2) n
                               bytes, plus the block buffers of the widest
                               block in flight); 0 = three quarters of the
-                              free device memory at creation.  A request is
+                              free device memory at creation plus what the
+                              context already holds for slots of the same
+                              restart (opened by an earlier server).  A
+                              request is
                               admitted into a slot only when that slot's
                               memory fits (slots open lowest first and are
                               kept once opened); otherwise it stays queued */
@@ -211,7 +214,9 @@ typedef struct helm_precond_stats {
 int helm_create(helm_ctx** out, int device_ordinal);
 
 /* Free every host and device resource of the context; NULL is accepted.
- * Destroy the context's server (helm_server_destroy) first. */
+ * A server still open on the context loses its solver state (in-flight work
+ * is waited for); its handle must still be released with
+ * helm_server_destroy, and every other call on it returns HELM_ESTATE. */
 void helm_destroy(helm_ctx* ctx);
 
 /* Message of the last failing call on ctx (or of helm_create when ctx is

@@ -1,6 +1,7 @@
 // extern "C" entry points of libhelm (declared in include/helm.h).  Every
 // call converts internal exceptions into a status code and keeps the message
 // for helm_last_error.
+#include <algorithm>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -9,16 +10,24 @@
 
 using namespace helm;
 
+struct helm_server;
+
 struct helm_ctx {
   Ctx c;
-  int servers = 0;  // live servers on this context
+  int servers = 0;                 // live servers on this context
+  std::vector<helm_server*> srvs;  // them (detached when the context goes first)
 };
 
 struct helm_server {
-  helm_ctx* ctx;
+  helm_ctx* ctx;                   // null once the context was destroyed
   std::unique_ptr<Server> srv;
   std::vector<helm_server_event> pending;  // completions not yet reported
 };
+
+namespace {
+// A server whose context was destroyed: every call but destroy fails.
+int detached(const helm_server* s) { return !s->ctx || !s->srv ? HELM_ESTATE : HELM_OK; }
+}  // namespace
 
 namespace {
 
@@ -89,6 +98,13 @@ int helm_create(helm_ctx** out, int device_ordinal) {
 void helm_destroy(helm_ctx* ctx) {
   if (!ctx) return;
   if (ctx->c.device >= 0) (void)hipSetDevice(ctx->c.device);
+  // servers still open on this context lose their solver state now (their
+  // handles stay valid for helm_server_destroy, every other call fails)
+  for (helm_server* s : ctx->srvs) {
+    if (s->srv && s->srv->inflight) (void)hipEventSynchronize(s->srv->done_ev);
+    s->srv.reset();
+    s->ctx = nullptr;
+  }
   delete ctx;
 }
 
@@ -354,6 +370,7 @@ int helm_server_create(helm_ctx* ctx, const helm_server_opts* opts, void* stream
     h->ctx = ctx;
     h->srv.reset(new Server(c, opts, (hipStream_t)stream));
     ctx->servers++;
+    ctx->srvs.push_back(h.get());
     *out = h.release();
     return HELM_OK;
   });
@@ -361,6 +378,7 @@ int helm_server_create(helm_ctx* ctx, const helm_server_opts* opts, void* stream
 
 int helm_server_submit(helm_server* srv, const void* b, void* u, int64_t tag) {
   if (!srv) return HELM_EINVAL;
+  if (detached(srv)) return HELM_ESTATE;
   return guarded(srv->ctx, [&](Ctx&) {
     need(b && u, HELM_EINVAL, "null vector");
     srv->srv->submit((const double*)b, (double*)u, tag);
@@ -370,6 +388,7 @@ int helm_server_submit(helm_server* srv, const void* b, void* u, int64_t tag) {
 
 int helm_server_launch(helm_server* srv, int32_t* active) {
   if (!srv) return HELM_EINVAL;
+  if (detached(srv)) return HELM_ESTATE;
   return guarded(srv->ctx, [&](Ctx&) {
     need(!srv->srv->inflight, HELM_ESTATE, "a step is already launched");
     const int a = srv->srv->launch();
@@ -380,6 +399,7 @@ int helm_server_launch(helm_server* srv, int32_t* active) {
 
 int helm_server_finish(helm_server* srv, helm_server_event* events, int32_t cap, int32_t* count) {
   if (!srv) return HELM_EINVAL;
+  if (detached(srv)) return HELM_ESTATE;
   return guarded(srv->ctx, [&](Ctx&) {
     need(cap >= 0 && (cap == 0 || events), HELM_EINVAL, "bad event buffer");
     srv->srv->finish(srv->pending);
@@ -393,6 +413,7 @@ int helm_server_finish(helm_server* srv, helm_server_event* events, int32_t cap,
 
 int helm_server_status(const helm_server* srv, int32_t* queued, int32_t* active) {
   if (!srv) return HELM_EINVAL;
+  if (detached(srv)) return HELM_ESTATE;
   if (queued) *queued = (int32_t)srv->srv->queue.size();
   if (active) *active = srv->srv->active();
   return HELM_OK;
@@ -400,6 +421,7 @@ int helm_server_status(const helm_server* srv, int32_t* queued, int32_t* active)
 
 int helm_server_memory(const helm_server* srv, int32_t* slots_open, double* bytes) {
   if (!srv) return HELM_EINVAL;
+  if (detached(srv)) return HELM_ESTATE;
   if (slots_open) *slots_open = std::min(srv->srv->slots_n, srv->ctx->c.blk_bases);
   if (bytes) *bytes = srv->srv->held();
   return HELM_OK;
@@ -411,6 +433,8 @@ void helm_server_destroy(helm_server* srv) {
     if (srv->ctx->c.device >= 0) (void)hipSetDevice(srv->ctx->c.device);
     if (srv->srv && srv->srv->inflight) (void)hipEventSynchronize(srv->srv->done_ev);
     srv->ctx->servers--;
+    auto& v = srv->ctx->srvs;
+    v.erase(std::remove(v.begin(), v.end(), srv), v.end());
   }
   delete srv;
 }

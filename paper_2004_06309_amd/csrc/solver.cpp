@@ -2480,7 +2480,9 @@ Server::Server(Ctx& ctx, const helm_server_opts* o, hipStream_t st) : c(ctx), s(
   // are allocated when a request is admitted into it, within the budget
   size_t free_b = 0, total_b = 0;
   HELM_HIP(hipMemGetInfo(&free_b, &total_b));
-  budget = o && o->mem_bytes > 0 ? o->mem_bytes : 0.75 * (double)free_b;
+  // memory the context already holds for this restart (slots opened by an
+  // earlier server) counts towards the budget, not against the free memory
+  budget = o && o->mem_bytes > 0 ? o->mem_bytes : held() + 0.75 * (double)free_b;
   slots_n = want;
   slot.resize(slots_n);
   for (auto& q : slot) {

@@ -208,9 +208,13 @@ class Helm:
         self.h = h
         self.device = device
         self._keep = []
+        self._servers = weakref.WeakSet()
         _live_ctx.add(self)
 
     def close(self):
+        """Destroys the context, its servers first."""
+        for srv in list(getattr(self, "_servers", ())):
+            srv.close()
         if getattr(self, "h", None):
             self.lib.helm_destroy(self.h)
             self.h = None
@@ -387,6 +391,7 @@ class Server:
         self._alive = {}
         self._ev = (ServerEvent * 64)()
         _live_srv.add(self)
+        helm._servers.add(self)
 
     def submit(self, b, u, tag):
         """Queues b -> u under `tag`; the library refuses a tag that is still

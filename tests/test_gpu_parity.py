@@ -828,6 +828,32 @@ def test_server_admits_by_memory():
         assert np.linalg.norm(Bs[r] - P.A @ u[r]) / np.linalg.norm(Bs[r]) <= w.tol
 
 
+def test_server_reopened_and_context_destroyed_first():
+    """A second server on the same context reuses the slots the first opened
+    (the budget counts the memory the context already holds); destroying the
+    context before its server leaves a handle whose calls fail with
+    HELM_ESTATE and whose destroy is still safe."""
+    w = WORKLOADS["tiny"]()
+    P, b, M = opre.build(w)
+    h = helm.from_workload(w)
+    B = dvec(np.stack([b, 2.0 * b]))
+    for rep in range(2):
+        U = torch.zeros_like(B)
+        srv = helm.Server(h, slots=4, tol=w.tol)
+        ev = _serve([srv], [[(0, B[0], U[0], 1), (0, B[1], U[1], 2)]])
+        assert all(e["converged"] == 1 for e in ev.values())
+        srv.close()
+        u = host(U)
+        assert np.linalg.norm(b - P.A @ u[0]) / np.linalg.norm(b) <= w.tol
+    srv = helm.Server(h, slots=2, tol=w.tol)
+    lib = helm.load()
+    lib.helm_destroy(h.h)  # the context goes first (plain C call)
+    h.h = None
+    assert lib.helm_server_launch(srv.h, None) == helm.HELM_ESTATE
+    assert lib.helm_server_submit(srv.h, B[0].data_ptr(), B[1].data_ptr(), 5) == helm.HELM_ESTATE
+    srv.close()
+
+
 def test_servers_on_two_operators_overlap():
     """Two operators, each with a server on its own stream, stepped together;
     zero and regular right-hand sides; results match the oracle's solves."""
