@@ -71,13 +71,14 @@ struct BatchHost {
   // order); the tile kernel takes the first ktile_f tasks of a level
   std::vector<dev::SnJob> snj;
   std::vector<int64_t> snj_lev, ktile_f;
-  std::vector<int32_t> gy_f, gy_b;        // gather workgroups per supernode of each level
+  std::vector<int32_t> gy_f;              // gather workgroups per supernode of each forward level
   std::vector<double> bytes_f, bytes_b;  // algorithmic bytes per level
   std::vector<double> pbytes_f, pbytes_b;  // of which panel bytes
-  // staged 16-right-hand-side inputs: supernodes of every level, their
-  // column offsets in the level's staging block, the largest block
-  std::vector<int32_t> gsn_f, gsn_b, sn_r;
-  std::vector<int64_t> gsn_lev_f, gsn_lev_b, goff_f, goff_b;
+  // staged 16-right-hand-side inputs of the forward sweep: supernodes of
+  // every level, their column offsets in the level's staging block, the
+  // largest block
+  std::vector<int32_t> gsn_f;
+  std::vector<int64_t> gsn_lev_f, goff_f;
   int64_t stage_cols = 0;
   int64_t nf = 0, nb = 0, nu = 0;     // panel entries (fwd, bwd), update entries
   int32_t max_front = 0;
@@ -96,7 +97,7 @@ struct BatchDev {
   std::vector<int64_t> lev_f, lev_b;
   std::vector<int32_t> chunk_f, chunk_b;
   std::vector<int64_t> nwide_f, nwide_b;
-  std::vector<int32_t> gy_f, gy_b;
+  std::vector<int32_t> gy_f;
   DVec<dev::SnJob> snj;
   std::vector<int64_t> snj_lev, ktile_f;
   int64_t npos = 0;
@@ -106,9 +107,9 @@ struct BatchDev {
   // multi-right-hand-side work vectors (interleaved, widest block so far)
   int blk_S = 0;
   DVec<double> ubuf_b, y_b, x_b;
-  DVec<int32_t> gsn_f, gsn_b, sn_r;
-  DVec<int64_t> goff_f, goff_b;
-  std::vector<int64_t> gsn_lev_f, gsn_lev_b;
+  DVec<int32_t> gsn_f;
+  DVec<int64_t> goff_f;
+  std::vector<int64_t> gsn_lev_f;
   int64_t stage_cols = 0;
   DVec<unsigned char> stage;
   // > 0: grid of the single cooperative launch that runs the whole solve
@@ -146,12 +147,8 @@ struct BatchDev {
     y_b.reset();
     x_b.reset();
     gsn_f.reset();
-    gsn_b.reset();
-    sn_r.reset();
     goff_f.reset();
-    goff_b.reset();
     gsn_lev_f.clear();
-    gsn_lev_b.clear();
     stage_cols = 0;
     stage.reset();
     npos = 0;

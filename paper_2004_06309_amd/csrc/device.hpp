@@ -73,7 +73,6 @@ struct Batch {
   const int2* fcon2 = nullptr;     // front row -> first two entries, or (-2 - list start, 0)
   const int32_t* sn_r = nullptr;   // |R_s|
   const int64_t* goff_f = nullptr; // column offset of the supernode's staged block (forward level scratch)
-  const int64_t* goff_b = nullptr; // same for the backward level scratch
   const void* pf = nullptr;        // forward panels (complex128, or complex64 when c64)
   const void* pb = nullptr;        // backward panels
   int c64 = 0;
@@ -210,17 +209,18 @@ void fwd_level_block(const Batch& b, int64_t tile0, int64_t ntiles, int S, const
                      bool coarse, hipStream_t s);
 void bwd_level_block(const Batch& b, int64_t tile0, int64_t ntiles, int S, const double* yb, double* xb, bool coarse,
                      hipStream_t s);
-// 16 right-hand sides on MFMA: stage every supernode's input block of the
-// level once (gather kernels, one workgroup per supernode of `sns`), then
-// one 4-wave workgroup per tile reads its B operands from the staged block.
-// The first nwide tiles of the range are wide (four waves each), the rest
-// narrow (one wave each); gy = workgroups per supernode of the gather (each
-// takes every gy-th run of 256 block entries).
+// 16 right-hand sides on MFMA.  Forward: stage every supernode's input
+// block of the level once (gather kernel, one workgroup per supernode of
+// `sns`, gy workgroups per supernode each taking every gy-th run of 256
+// block entries), then one 4-wave workgroup per wide tile (the first nwide
+// tiles of the range) or one wave per narrow tile reads its B operands from
+// the staged block.  Backward: one launch, each workgroup gathering its
+// tile's input block into LDS a pass of columns at a time.
 void fwd_level_mfma(const Batch& b, const int32_t* sns, int64_t nsn, int gy, int64_t tile0, int64_t ntiles,
                     int64_t nwide, const double* bin, double* yb, double* ubb, void* stage, bool coarse,
                     hipStream_t s);
-void bwd_level_mfma(const Batch& b, const int32_t* sns, int64_t nsn, int gy, int64_t tile0, int64_t ntiles,
-                    int64_t nwide, const double* yb, double* xb, void* stage, bool coarse, hipStream_t s);
+void bwd_level_mfma(const Batch& b, int64_t tile0, int64_t ntiles, int64_t nwide, const double* yb, double* xb,
+                    bool coarse, hipStream_t s);
 // ---- block Gram-Schmidt of block GMRES (device_bgmres.hip): n x 16
 //      interleaved complex blocks, X_j = X + j ldx (ldx in doubles) ----
 // workgroups of bgs_dots (the partial sums per basis block) and of bgs_mul

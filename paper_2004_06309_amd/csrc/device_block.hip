@@ -206,23 +206,6 @@ __global__ __launch_bounds__(kWG) void gather_fwd_kernel(const int32_t* __restri
   }
 }
 
-template <class T>
-__global__ __launch_bounds__(kWG) void gather_bwd_kernel(const int32_t* __restrict__ sns, Batch b,
-                                                         const double2* __restrict__ yb,
-                                                         const double2* __restrict__ xb,
-                                                         typename Mf<T>::C2* __restrict__ G) {
-  using C2 = typename Mf<T>::C2;
-  const int sn = sns[blockIdx.x];
-  const int c0 = b.sn_c0[sn], w = b.sn_w[sn], r_ = b.sn_r[sn];
-  const int64_t roff = b.sn_roff[sn];
-  C2* g = G + b.goff_b[sn] * 16;
-  for (int e = blockIdx.y * kWG + threadIdx.x; e < (w + r_) * 16; e += gridDim.y * kWG) {
-    const int c = e >> 4, r = e & 15;
-    const double2 v = c < w ? yb[(int64_t)(c0 + c) * 16 + r] : xb[(int64_t)b.rows[roff + (c - w)] * 16 + r];
-    g[e] = C2{(T)v.x, (T)v.y};
-  }
-}
-
 // Panel loads are streamed once per sweep: non-temporal, so they do not
 // evict the staged input blocks and vectors from the caches.
 typedef double dvec2 __attribute__((ext_vector_type(2)));
@@ -310,7 +293,7 @@ __global__ __launch_bounds__(kWG, sizeof(T) == 4 ? 4 : 1) void level_mfma_kernel
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int sn = t.sn, c0 = b.sn_c0[sn], w = b.sn_w[sn];
   const C2* __restrict__ P = reinterpret_cast<const C2*>(kFwd ? b.pf : b.pb) + t.off;
-  const C2* Bk = G + ((kFwd ? b.goff_f[sn] : b.goff_b[sn]) + t.col0) * 16;
+  const C2* Bk = G + (b.goff_f[sn] + t.col0) * 16;  // the staged forward input block
   V4 dre[4], dim[4];
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb) dre[rb] = dim[rb] = V4{0, 0, 0, 0};
@@ -378,7 +361,7 @@ __global__ __launch_bounds__(kWG, sizeof(T) == 4 ? 8 : 5) void level_mfma_narrow
   const Tile t = tiles[ti];
   const int sn = t.sn, c0 = b.sn_c0[sn], w = b.sn_w[sn];
   const C2* __restrict__ P = reinterpret_cast<const C2*>(kFwd ? b.pf : b.pb) + t.off;
-  const C2* Bk = G + ((kFwd ? b.goff_f[sn] : b.goff_b[sn]) + t.col0) * 16;
+  const C2* Bk = G + (b.goff_f[sn] + t.col0) * 16;  // the staged forward input block
   const int nr = t.nrows, cn = t.ncols, nrb = (nr + 15) >> 4;
   V4 dre[4], dim[4];
 #pragma unroll
@@ -421,6 +404,222 @@ __global__ __launch_bounds__(kWG, sizeof(T) == 4 ? 8 : 5) void level_mfma_narrow
         }
         ubb[(int64_t)(b.sn_uoff[sn] + row - w) * 16 + lr] = make_double2(ar, ai);
       }
+    }
+  }
+}
+
+// Stages a pass of a tile's input block into G: entries e = base + q stride
+// (q < 8) of the cn columns from cb, entry e being column col0 + cb + e / 16
+// and right-hand side e % 16.  Forward: the restricted right-hand side,
+// gathered through bidx (restriction, nested-dissection permutation and
+// pivot order in one index), minus the children's updates routed to the
+// column's front row (at most two, read through fcon2; longer lists through
+// fcon_idx).  Backward: the forward result for the pivot columns, the
+// ancestors' backward results (through the supernode's row list) for the
+// others.  All eight entries' index loads are issued first, then all value
+// loads, so a pass costs two memory round trips.
+template <class T, int kFwd>
+__device__ __forceinline__ void stage_pass(const Batch& b, const Tile& t, int cb, int cn, int base, int stride,
+                                           typename Mf<T>::C2* G, const double2* __restrict__ src,
+                                           const double2* aux) {
+  using C2 = typename Mf<T>::C2;
+  constexpr int kQ = 8;
+  int idx[kQ];
+  int2 ch[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const int e = base + q * stride;
+    const bool in = e < cn * 16;
+    const int c = t.col0 + cb + (e >> 4);
+    if (kFwd) {
+      idx[q] = in ? b.bidx[t.c0 + c] : 0;
+      ch[q] = in ? b.fcon2[t.aux + c] : make_int2(-1, -1);
+    } else {
+      // >= 0: position in the forward result; < 0: -1 - position in x
+      idx[q] = !in ? 0 : (c < t.w ? t.c0 + c : -1 - b.rows[(int64_t)t.aux + (c - t.w)]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const int e = base + q * stride;
+    if (e >= cn * 16) continue;
+    const int r = e & 15;
+    double2 v;
+    if (kFwd) {
+      v = src[(int64_t)idx[q] * 16 + r];
+      const int2 c2 = ch[q];
+      if (c2.x >= 0) {
+        const double2 u0 = aux[(int64_t)c2.x * 16 + r];
+        v.x -= u0.x;
+        v.y -= u0.y;
+        if (c2.y >= 0) {
+          const double2 u1 = aux[(int64_t)c2.y * 16 + r];
+          v.x -= u1.x;
+          v.y -= u1.y;
+        }
+      } else if (c2.x < -1) {
+        const int fr = t.aux + t.col0 + cb + (e >> 4);
+        for (int k = -2 - c2.x; k < b.fcon_ptr[fr + 1]; ++k) {
+          const double2 u = aux[(int64_t)b.fcon_idx[k] * 16 + r];
+          v.x -= u.x;
+          v.y -= u.y;
+        }
+      }
+    } else {
+      v = idx[q] >= 0 ? src[(int64_t)idx[q] * 16 + r] : aux[(int64_t)(-1 - idx[q]) * 16 + r];
+    }
+    G[e] = C2{(T)v.x, (T)v.y};
+  }
+}
+
+constexpr int kCB = 128;  // input columns staged per pass of a wide tile (4 waves)
+constexpr int kCBn = 32;  // per pass of a narrow tile (one wave)
+// stage_pass stages eight entries per thread
+static_assert(kCB * 16 == 8 * kWG && kCBn * 16 == 8 * 64, "a pass is eight entries per thread");
+
+// Output row rloc (of the tile) for right-hand side r: forward pivot rows
+// and backward rows go to out; forward update rows add the children's
+// updates routed to that front row and go to the supernode's update vector.
+template <int kFwd>
+__device__ __forceinline__ void put_row(const Batch& b, const Tile& t, int rloc, int r, double ar, double ai,
+                                        double2* out, double2* ubb) {
+  const int row = t.row0 + rloc;
+  if (!kFwd || row < t.w) {
+    out[(int64_t)(t.c0 + row) * 16 + r] = make_double2(ar, ai);
+  } else {
+    const int fr = t.aux + row;
+    for (int e = b.fcon_ptr[fr]; e < b.fcon_ptr[fr + 1]; ++e) {
+      const double2 u = ubb[(int64_t)b.fcon_idx[e] * 16 + r];
+      ar += u.x;
+      ai += u.y;
+    }
+    ubb[(int64_t)(b.sn_uoff[t.sn] + row - t.w) * 16 + r] = make_double2(ar, ai);
+  }
+}
+
+// One level of the 16-right-hand-side backward sweep, the input gather
+// fused in (a backward tile holds all input columns of its rows, so a narrow
+// supernode's input is gathered once; the forward sweep keeps the staged
+// gather, whose supernodes have several row tiles over the same input): a
+// workgroup stages its tile's input block (16 right-hand sides per column)
+// in LDS a pass of columns at a time and multiplies the panel tile into it
+// on MFMA.  Workgroups [0, nwide) take one wide tile each (its k-steps
+// shared by the four waves, wave q taking q, q + 4, ..., partial sums added
+// through LDS); the others take four narrow tiles, a wave each.
+template <class T, int kFwd, int kCoarse>
+__global__ __launch_bounds__(kWG) void level_fused_kernel(const Tile* __restrict__ tiles, int64_t ntiles,
+                                                          int64_t nwide, Batch b, const double2* __restrict__ src,
+                                                          const double2* aux, double2* out, double2* ubb) {
+  using C2 = typename Mf<T>::C2;
+  using V4 = typename Mf<T>::V4;
+  __shared__ C2 G[kCB * 16];
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lr = lane & 15,
+            lk = lane >> 4;
+  V4 dre[4], dim[4];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) dre[rb] = dim[rb] = V4{0, 0, 0, 0};
+  const C2* __restrict__ panels = reinterpret_cast<const C2*>(kFwd ? b.pf : b.pb);
+  if ((int64_t)blockIdx.x < nwide) {
+    const Tile t = tiles[blockIdx.x];
+    for (int cb = 0; cb < t.ncols; cb += kCB) {
+      const int cn = min(kCB, t.ncols - cb);
+      stage_pass<T, kFwd>(b, t, cb, cn, threadIdx.x, kWG, G, src, aux);
+      __syncthreads();
+      Tile tc = t;
+      tc.ncols = cn;
+      mfma_tile4<T, kFwd>(tc, panels + t.off + (int64_t)cb * t.nrows, G, dre, dim);
+      __syncthreads();
+    }
+    // partial sums of the 4 waves, two row blocks at a time, in the staging
+    // buffer: [wave][rb2][j][lane] (4 x 2 x 4 x 64 = kCB x 16 entries)
+    C2 (*red)[2][4][64] = reinterpret_cast<C2 (*)[2][4][64]>(G);
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) red[wv][q][j][lane] = C2{dre[2 * h + q][j], dim[2 * h + q][j]};
+      __syncthreads();
+      // 512 outputs (32 rows x 16 right-hand sides) of this half, 2 per thread
+      for (int o = threadIdx.x; o < 512; o += kWG) {
+        const int rloc = 32 * h + (o >> 4), r = o & 15;
+        if (rloc < t.nrows) {
+          const int q = (rloc >> 4) - 2 * h, rr = rloc & 15;
+          int l, j;
+          if (sizeof(T) == 8) {  // FP64: row = 4 j + l / 16
+            j = rr >> 2;
+            l = (rr & 3) * 16 + r;
+          } else {               // FP32: row = 4 (l / 16) + j
+            j = rr & 3;
+            l = (rr >> 2) * 16 + r;
+          }
+          double ar = 0, ai = 0;
+#pragma unroll
+          for (int wq = 0; wq < 4; ++wq) {
+            ar += (double)red[wq][q][j][l].x;
+            ai += (double)red[wq][q][j][l].y;
+          }
+          put_row<kFwd>(b, t, rloc, r, ar, ai, out, ubb);
+        }
+      }
+      __syncthreads();
+    }
+    return;
+  }
+  // narrow tiles: a wave each, the staging buffer split into four
+  const int64_t g0 = nwide + ((int64_t)blockIdx.x - nwide) * 4;
+  const int64_t ti = g0 + wv;
+  const bool has = ti < ntiles;
+  Tile t{};
+  if (has) t = tiles[ti];
+  int np = 0;  // passes: the most any tile of the workgroup needs (uniform)
+  for (int q = 0; q < 4; ++q)
+    if (g0 + q < ntiles) np = max(np, (tiles[g0 + q].ncols + kCBn - 1) / kCBn);
+  C2* Gw = G + wv * kCBn * 16;
+  const int nr = t.nrows, nrb = (nr + 15) >> 4;
+  const C2* __restrict__ P = panels + t.off;
+  auto loadA = [&](int k, C2 (&a)[4], int cn) {
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      const int row = 16 * rb + lr;
+      a[rb] = (rb < nrb && row < nr && k < cn) ? ldp(P + (int64_t)k * nr + row) : C2{0, 0};
+    }
+  };
+  auto step = [&](const C2& bv, const C2 (&a)[4]) {
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      if (rb >= nrb) break;
+      dre[rb] = Mf<T>::mma(a[rb].x, bv.x, dre[rb]);
+      dre[rb] = Mf<T>::mma(-a[rb].y, bv.y, dre[rb]);
+      dim[rb] = Mf<T>::mma(a[rb].x, bv.y, dim[rb]);
+      dim[rb] = Mf<T>::mma(a[rb].y, bv.x, dim[rb]);
+    }
+  };
+  for (int p = 0; p < np; ++p) {
+    const int cb = p * kCBn;
+    const int cn = has ? max(0, min(kCBn, t.ncols - cb)) : 0;
+    stage_pass<T, kFwd>(b, t, cb, cn, lane, 64, Gw, src, aux);
+    __syncthreads();
+    // two k-steps per iteration, both steps' panel loads issued first
+    for (int k0 = 0; k0 < cn; k0 += 8) {
+      const int k1 = k0 + lk, k2 = k0 + 4 + lk;
+      C2 a0[4], a1[4];
+      loadA(cb + k1, a0, cb + cn);
+      loadA(cb + k2, a1, cb + cn);
+      const C2 b0 = k1 < cn ? Gw[k1 * 16 + lr] : C2{0, 0};
+      const C2 b1 = k2 < cn ? Gw[k2 * 16 + lr] : C2{0, 0};
+      step(b0, a0);
+      step(b1, a1);
+    }
+    __syncthreads();
+  }
+  if (!has) return;
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) {
+    if (rb >= nrb) break;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int rloc = 16 * rb + Mf<T>::row(lk, j);
+      if (rloc < nr) put_row<kFwd>(b, t, rloc, lr, (double)dre[rb][j], (double)dim[rb][j], out, ubb);
     }
   }
 }
@@ -702,23 +901,26 @@ void fwd_level_mfma(const Batch& b, const int32_t* sns, int64_t nsn, int gy, int
   }
 }
 
-void bwd_level_mfma(const Batch& b, const int32_t* sns, int64_t nsn, int gy, int64_t tile0, int64_t ntiles,
-                    int64_t nwide, const double* yb, double* xb, void* stage, bool coarse, hipStream_t s) {
+// One launch per level: nwide wide tiles (the level's first ones) take a
+// workgroup each, the narrow ones four per workgroup.
+template <class T, int kCoarse>
+void bwd_fused_launch(const Batch& b, const Tile* tiles, int64_t ntiles, int64_t nwide, const double2* y, double2* x,
+                      hipStream_t s) {
+  const int64_t grid = nwide + (ntiles - nwide + 3) / 4;
+  level_fused_kernel<T, 0, kCoarse><<<(unsigned)grid, kWG, 0, s>>>(tiles, ntiles, nwide, b, y, x, x, nullptr);
+}
+
+void bwd_level_mfma(const Batch& b, int64_t tile0, int64_t ntiles, int64_t nwide, const double* yb, double* xb,
+                    bool coarse, hipStream_t s) {
   if (ntiles <= 0) return;
   auto y = reinterpret_cast<const double2*>(yb);
   auto x = reinterpret_cast<double2*>(xb);
-  if (b.c64 && !coarse) {
-    auto G = reinterpret_cast<float2*>(stage);
-    gather_bwd_kernel<float><<<dim3((unsigned)nsn, (unsigned)gy), kWG, 0, s>>>(sns, b, y, x, G);
-    level_mfma_launch<float, 0, 0>(b, b.tb + tile0, ntiles, nwide, G, x, nullptr, s);
-  } else {
-    auto G = reinterpret_cast<double2*>(stage);
-    gather_bwd_kernel<double><<<dim3((unsigned)nsn, (unsigned)gy), kWG, 0, s>>>(sns, b, y, x, G);
-    if (coarse)
-      level_mfma_launch<double, 0, 1>(b, b.tb + tile0, ntiles, nwide, G, x, nullptr, s);
-    else
-      level_mfma_launch<double, 0, 0>(b, b.tb + tile0, ntiles, nwide, G, x, nullptr, s);
-  }
+  if (b.c64 && !coarse)
+    bwd_fused_launch<float, 0>(b, b.tb + tile0, ntiles, nwide, y, x, s);
+  else if (coarse)
+    bwd_fused_launch<double, 1>(b, b.tb + tile0, ntiles, nwide, y, x, s);
+  else
+    bwd_fused_launch<double, 0>(b, b.tb + tile0, ntiles, nwide, y, x, s);
 }
 
 void csr_spmv_block(int64_t n, const int64_t* ptr, const int32_t* col, const double* val, const int64_t* xr,

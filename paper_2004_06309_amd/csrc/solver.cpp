@@ -101,9 +101,7 @@ dev::Batch BatchDev::view() const {
   b.kb = kb.p;
   b.snj = snj.p;
   b.c64 = c64;
-  b.sn_r = sn_r.p;
   b.goff_f = goff_f.p;
-  b.goff_b = goff_b.p;
   b.sn_c0 = c0.p;
   b.sn_w = w.p;
   b.sn_uoff = uoff.p;
@@ -383,12 +381,10 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
       lev.push_back((int64_t)tasks.size());
     }
   };
-  // supernodes of every level and their offsets in the level's staging block
-  B.sn_r.resize(nsn);
-  for (int64_t s = 0; s < nsn; ++s) B.sn_r[s] = (int32_t)r_of(s);
+  // supernodes of every forward level and their offsets in the level's
+  // staging block
   B.goff_f.assign(nsn, 0);
-  B.goff_b.assign(nsn, 0);
-  auto stage_levels = [&](const std::vector<std::vector<dev::Tile>>& levels, bool fwd, std::vector<int32_t>& gsn,
+  auto stage_levels = [&](const std::vector<std::vector<dev::Tile>>& levels, std::vector<int32_t>& gsn,
                           std::vector<int64_t>& glev, std::vector<int64_t>& goff, std::vector<int32_t>& gy) {
     glev.assign(1, 0);
     gy.clear();
@@ -400,7 +396,7 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
         last = t.sn;
         gsn.push_back(t.sn);
         goff[t.sn] = cols;
-        const int64_t c = B.w[t.sn] + (fwd ? 0 : B.sn_r[t.sn]);
+        const int64_t c = B.w[t.sn];
         cols += c;
         widest = std::max(widest, c);
       }
@@ -411,8 +407,7 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
       B.stage_cols = std::max(B.stage_cols, cols);
     }
   };
-  stage_levels(lf, true, B.gsn_f, B.gsn_lev_f, B.goff_f, B.gy_f);
-  stage_levels(lb, false, B.gsn_b, B.gsn_lev_b, B.goff_b, B.gy_b);
+  stage_levels(lf, B.gsn_f, B.gsn_lev_f, B.goff_f, B.gy_f);
   make_tasks(lf, true, B.tf, B.kf, B.lev_f, B.bytes_f, B.pbytes_f);
   make_tasks(lb, false, B.tb, B.kb, B.lev_b, B.bytes_b, B.pbytes_b);
   // LDS input buffer of every level: each slot of a task with wpt < 4 holds
@@ -579,7 +574,6 @@ void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symb
   Dv.ktile_f = B.ktile_f;
   Dv.nwide_b = B.nwide_b;
   Dv.gy_f = B.gy_f;
-  Dv.gy_b = B.gy_b;
   Dv.bytes_f = B.bytes_f;
   Dv.bytes_b = B.bytes_b;
   Dv.pbytes_f = B.pbytes_f;
@@ -593,12 +587,8 @@ void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symb
   Dv.tiles_f = tile_ranges(B.kf, B.lev_f);
   Dv.tiles_b = tile_ranges(B.kb, B.lev_b);
   Dv.gsn_f.upload(B.gsn_f);
-  Dv.gsn_b.upload(B.gsn_b);
-  Dv.sn_r.upload(B.sn_r);
   Dv.goff_f.upload(B.goff_f);
-  Dv.goff_b.upload(B.goff_b);
   Dv.gsn_lev_f = B.gsn_lev_f;
-  Dv.gsn_lev_b = B.gsn_lev_b;
   Dv.stage_cols = B.stage_cols;
   Dv.tf.upload(B.tf);
   Dv.tb.upload(B.tb);
@@ -1732,8 +1722,8 @@ void batch_solve_block(BatchDev& b, int S, const double* in, hipStream_t s, Prof
   for (size_t l = 0; l + 1 < b.tiles_b.size(); ++l) {
     if (each) prof->begin(s);
     if (mfma)
-      dev::bwd_level_mfma(v, b.gsn_b.p + b.gsn_lev_b[l], b.gsn_lev_b[l + 1] - b.gsn_lev_b[l], b.gy_b[l], b.tiles_b[l],
-                          b.tiles_b[l + 1] - b.tiles_b[l], b.nwide_b[l], b.y_b.p, b.xout_b(), b.stage.p, !fine, s);
+      dev::bwd_level_mfma(v, b.tiles_b[l], b.tiles_b[l + 1] - b.tiles_b[l], b.nwide_b[l], b.y_b.p, b.xout_b(), !fine,
+                          s);
     else
       dev::bwd_level_block(v, b.tiles_b[l], b.tiles_b[l + 1] - b.tiles_b[l], S, b.y_b.p, b.xout_b(), !fine, s);
     if (each) prof->end(HELM_K_TRSV_BWD, b.pbytes_b[l] + S * (b.bytes_b[l] - b.pbytes_b[l]), s);

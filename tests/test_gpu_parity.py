@@ -273,18 +273,21 @@ def _sources(w, P, k, seed):
     return np.stack([P.point_source(p) for p in pts])
 
 
-@pytest.mark.parametrize("name,nrhs,restart", [("tiny", 3, 50), ("small_p2_2lvl", 16, 3), ("mid_quarter_2lvl", 16, 50),
-                                               ("adapted_p2_2lvl", 5, 8), ("ragged_p2", 7, 50)])
-def test_block_gmres(name, nrhs, restart):
+@pytest.mark.parametrize("name,nrhs,restart,c64", [("tiny", 3, 50, False), ("small_p2_2lvl", 16, 3, False),
+                                                   ("mid_quarter_2lvl", 16, 50, False), ("adapted_p2_2lvl", 5, 8, False),
+                                                   ("ragged_p2", 7, 50, False), ("mid_quarter_2lvl", 16, 50, True)])
+def test_block_gmres(name, nrhs, restart, c64):
     """Block GMRES (one block Krylov space, block CGS2 on MFMA, CholQR2,
     Householder least squares): every right-hand side reaches the true
     relative residual tol with the oracle's A; at tol 1e-9 the solutions
     match the oracle's GMRES solutions at 1e-9 to 1e-7 (the same discrete
     solution; the two Krylov methods differ, so iteration counts are not
-    compared).  Short restarts exercise the deflation of converged columns."""
+    compared).  Short restarts exercise the deflation of converged columns;
+    with complex64 factors the preconditioner differs from the oracle's by
+    about cond(A_i) * 6e-8, which flexible GMRES absorbs."""
     w = WORKLOADS[name]()
     P, b0, M = opre.build(w)
-    h = helm.from_workload(w)
+    h = helm.from_workload(w, c64=c64)
     Bs = _sources(w, P, nrhs, 21)
     B = dvec(Bs)
     U = torch.zeros_like(B)
