@@ -63,10 +63,21 @@ typedef struct helm_mesh {
 
 typedef struct helm_precond_opts {
   int32_t leaf_size;       /* nested-dissection leaf size, 0 = default     */
-  int32_t factor_c64;      /* 1: store the subdomain factors in complex64
-                              (computed in complex128, rounded once); the
-                              panel products still accumulate in FP64 and
-                              the coarse factors stay complex128          */
+  int32_t factor_c64;      /* subdomain factor precision:
+                              0: complex128 factorisation and panels;
+                              1: complex64 factorisation (fronts, Schur
+                                 complements and panels in complex64, the
+                                 frontal updates on FP32 MFMA accumulating
+                                 in FP32), complex64 panels; with
+                                 factor_on_host the host factorisation runs
+                                 in complex128 and its panels are rounded
+                                 (reported as 2);
+                              2: complex128 factorisation, panels rounded
+                                 once to complex64.
+                              With complex64 panels the single-RHS solves
+                              accumulate in FP64 and the 16-RHS block
+                              solves on FP32 MFMA; the coarse factors stay
+                              complex128.  Other values: HELM_EINVAL      */
   int32_t coarse_leaf_size;  /* leaf size of the coarse ordering, 0 = 256  */
   int32_t tile_rows;       /* rows per solve tile of the subdomain factors:
                               16, 32 or 64; 0 = 64                         */
@@ -85,7 +96,8 @@ typedef struct helm_precond_opts {
                               helm_profile is on); 0 = 2; other values
                               fail with HELM_EINVAL                       */
   int32_t perturb_pivots;  /* a pivot with |p| <= 1000 eps max|a_ij| of its
-                              matrix (zero to working precision, after
+                              matrix (16 FP32 eps in a complex64
+                              factorisation; zero to working precision, after
                               partial pivoting inside the front) makes
                               helm_precond_setup fail with HELM_ESINGULAR;
                               1: replace it by sqrt(eps) max|a_ij| instead,
@@ -197,7 +209,8 @@ typedef struct helm_precond_stats {
   int32_t n_supernodes;    /* fine-level supernodes                        */
   double setup_seconds;    /* wall time of the last helm_precond_setup     */
   double factor_flops;     /* complex multiply-adds x 8 in the factorisation */
-  int32_t factor_c64;      /* 1 if the fine factors are stored in complex64 */
+  int32_t factor_c64;      /* fine factor precision as run: 0, 1 or 2 (see
+                              helm_precond_opts.factor_c64)               */
   int32_t coarse_grid;     /* workgroups of the one-launch cooperative coarse
                               solve; 0 = one launch per level              */
   int32_t factor_on_host;  /* 1 if the numeric factorisation ran on the host */

@@ -289,8 +289,10 @@ void ensure_width(Ctx& c, int m, int S);
 
 // factor_gpu.cpp: numeric factorisation of a batch on the device, panels
 // written into Dv.pf / Dv.pb (allocated by the caller) at the per-matrix
-// offsets pf0 / pb0; pivots returned in num.
-void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<const Symbolic*>& Ss, bool c64,
+// offsets pf0 / pb0 (complex64 unless prec is kC128); pivots returned in
+// num.
+void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<const Symbolic*>& Ss,
+                         dev::FactorPrecision prec,
                          BatchDev& Dv, const std::vector<int64_t>& pf0, const std::vector<int64_t>& pb0,
                          std::vector<NumericOut>& num, int32_t& n_perturbed);
 

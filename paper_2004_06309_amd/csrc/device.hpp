@@ -12,6 +12,9 @@ namespace dev {
 // A pivot is taken as zero when |pivot| <= kTinyPivot max|a_ij| (the
 // factorisations replace it by sqrt(eps) max|a_ij| and count it).
 constexpr double kTinyPivot = 1000.0 * 2.220446049250313e-16;
+// The same test for a factorisation in complex64 arithmetic: 16 FP32 eps
+// (a pivot that small carries no correct digit after FP32 elimination).
+constexpr double kTinyPivotF32 = 16.0 * 1.1920928955078125e-07;
 
 // Up to kMaxBlock device pointers, one per right-hand side of a block
 // (passed by value as a kernel argument; a null entry is a padding column).
@@ -118,11 +121,18 @@ struct FrontChild {
 // the scatter lists (F[asm_pos[q]] = aval[asm_val[q]]) and the children,
 // partial LU, Schur complement into upd, pivots into piv (batch positions),
 // zero-pivot replacements per job into npert, explicit-inverse panels into
-// the solve tiles of pf / pb (complex64 when c64).  ws holds each job's F, X
-// and Y.
-void factor_fronts(const FrontJob* jobs, int njobs, double* ws, double* upd, const int32_t* asm_pos,
+// the solve tiles of pf / pb.  ws holds each job's F, X and Y; ws and upd
+// hold complex entries of the working precision (complex64 for kC64,
+// complex128 otherwise); aval is complex128.
+enum class FactorPrecision {
+  kC128,            // complex128 arithmetic, complex128 panels
+  kC128RoundedC64,  // complex128 arithmetic, panels rounded once to complex64
+  kC64,             // complex64 arithmetic (FP32 MFMA), complex64 panels
+};
+void factor_fronts(const FrontJob* jobs, int njobs, void* ws, void* upd, const int32_t* asm_pos,
                    const int32_t* asm_val, const double* aval, const FrontChild* kids, const int32_t* ep,
-                   int32_t* piv, int32_t* npert, void* pf, void* pb, bool c64, int tile_rows, hipStream_t s);
+                   int32_t* piv, int32_t* npert, void* pf, void* pb, FactorPrecision prec, int tile_rows,
+                   hipStream_t s);
 
 // Task ranges of every level of a batch (a kernel argument).
 constexpr int kMaxLevels = 40;

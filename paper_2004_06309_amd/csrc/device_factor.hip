@@ -15,10 +15,17 @@
 //        X = [I; L21] L11^{-1}   (m x w, right triangular solve by blocks)
 //        Y = U11^{-1} [I | -U12] (w x m, left triangular solve by blocks)
 //   5. X and Y written into the solve tiles (complex128 or complex64).
-// Every rank-32 update of steps 2 and 4 is a complex GEMM on
-// v_mfma_f64_16x16x4f64 (four real MFMAs per complex product); the pivot
-// search, the 32-column panel factorisation and the 32 x 32 triangular
-// solves run on the vector units.
+// Every rank-32 update of steps 2 and 4 is a complex GEMM on the 16x16x4
+// MFMA (four real MFMAs per complex product); the pivot search, the
+// 32-column panel factorisation and the 32 x 32 triangular solves run on the
+// vector units.
+//
+// The whole factorisation runs in one of two working precisions: complex128
+// (FP64 MFMA; the panels are stored in complex128, or rounded once to
+// complex64), or complex64 (fronts, Schur complements and panels in
+// complex64, FP32 MFMA accumulating in FP32; the original entries are
+// rounded on assembly).  The complex64 form halves the workspace and runs
+// the updates at the FP32 MFMA rate (twice the FP64 one).
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
@@ -34,15 +41,51 @@ constexpr int kFW = 256;  // threads of a front workgroup
 constexpr int kNB = 32;   // block size of the partial LU and the panel solves
 
 typedef double dv4 __attribute__((ext_vector_type(4)));
+typedef float fv4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ void csub_mul(double2& x, double2 a, double2 b) {
+// Working precision R: its complex type, the 16x16x4 MFMA, the accumulator
+// layout and the pivot tolerances.
+template <class R>
+struct Fp;
+template <>
+struct Fp<double> {
+  using C = double2;
+  using V4 = dv4;
+  static __device__ __forceinline__ C mk(double a, double b) { return make_double2(a, b); }
+  static __device__ __forceinline__ V4 mma(double a, double b, V4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row of D held in accumulator register j of a lane with l / 16 = hi
+  static __device__ __forceinline__ int drow(int hi, int j) { return 4 * j + hi; }
+  static constexpr double kTiny = kTinyPivot;
+  static constexpr double kEps = DBL_EPSILON;
+};
+template <>
+struct Fp<float> {
+  using C = float2;
+  using V4 = fv4;
+  static __device__ __forceinline__ C mk(double a, double b) { return make_float2((float)a, (float)b); }
+  static __device__ __forceinline__ V4 mma(float a, float b, V4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int drow(int hi, int j) { return 4 * hi + j; }
+  static constexpr double kTiny = kTinyPivotF32;
+  static constexpr double kEps = FLT_EPSILON;
+};
+
+template <class C>
+__device__ __forceinline__ void csub_mul(C& x, C a, C b) {
   x.x -= a.x * b.x - a.y * b.y;
   x.y -= a.x * b.y + a.y * b.x;
 }
 // a / d as (a conj(d)) / |d|^2
-__device__ __forceinline__ double2 cdivd(double2 a, double2 d) {
-  const double q = d.x * d.x + d.y * d.y;
-  return make_double2((a.x * d.x + a.y * d.y) / q, (a.y * d.x - a.x * d.y) / q);
+template <class C>
+__device__ __forceinline__ C cdivd(C a, C d) {
+  const auto q = d.x * d.x + d.y * d.y;
+  C r;
+  r.x = (a.x * d.x + a.y * d.y) / q;
+  r.y = (a.y * d.x - a.x * d.y) / q;
+  return r;
 }
 
 // C[M x N] -= A[M x K] B[K x N] (complex, column-major), by the whole
@@ -50,40 +93,44 @@ __device__ __forceinline__ double2 cdivd(double2 a, double2 d) {
 // The MFMA computes the transposed block C^T = B^T A^T, so the 16 lanes that
 // share an accumulator column hold 16 consecutive rows of C (coalesced
 // read-modify-write).  16x16x4 operand layout: lane l holds A[l % 16][l / 16]
-// and B[l / 16][l % 16]; FP64 accumulator register j of lane l is
-// D[4 j + l / 16][l % 16].
-__device__ void wg_gemm_sub(int M, int N, int K, const double2* A, int64_t lda, const double2* B, int64_t ldb,
-                            double2* C, int64_t ldc) {
+// and B[l / 16][l % 16]; accumulator register j of lane l is
+// D[Fp<R>::drow(l / 16, j)][l % 16].
+template <class R>
+__device__ void wg_gemm_sub(int M, int N, int K, const typename Fp<R>::C* A, int64_t lda,
+                            const typename Fp<R>::C* B, int64_t ldb, typename Fp<R>::C* C, int64_t ldc) {
+  using F = Fp<R>;
+  using Cx = typename F::C;
+  using V4 = typename F::V4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, lo = lane & 15, hi = lane >> 4;
   const int tm = (M + 31) >> 5, tn = (N + 31) >> 5;
   for (int t = wv; t < tm * tn; t += kFW / 64) {
     const int r0 = (t % tm) * 32, c0 = (t / tm) * 32;
-    dv4 dre[2][2], dim[2][2];
+    V4 dre[2][2], dim[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) dre[a][b] = dim[a][b] = dv4{0, 0, 0, 0};
+      for (int b = 0; b < 2; ++b) dre[a][b] = dim[a][b] = V4{0, 0, 0, 0};
     for (int k0 = 0; k0 < K; k0 += 4) {
       const int k = k0 + hi;
-      double2 av[2], bv[2];
+      Cx av[2], bv[2];
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb) {
         const int row = r0 + 16 * rb + lo;
-        av[rb] = (row < M && k < K) ? A[row + (int64_t)k * lda] : make_double2(0.0, 0.0);
+        av[rb] = (row < M && k < K) ? A[row + (int64_t)k * lda] : F::mk(0.0, 0.0);
       }
 #pragma unroll
       for (int cb = 0; cb < 2; ++cb) {
         const int col = c0 + 16 * cb + lo;
-        bv[cb] = (col < N && k < K) ? B[k + (int64_t)col * ldb] : make_double2(0.0, 0.0);
+        bv[cb] = (col < N && k < K) ? B[k + (int64_t)col * ldb] : F::mk(0.0, 0.0);
       }
 #pragma unroll
       for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb) {
-          dre[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[cb].x, av[rb].x, dre[cb][rb], 0, 0, 0);
-          dre[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-bv[cb].y, av[rb].y, dre[cb][rb], 0, 0, 0);
-          dim[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[cb].x, av[rb].y, dim[cb][rb], 0, 0, 0);
-          dim[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[cb].y, av[rb].x, dim[cb][rb], 0, 0, 0);
+          dre[cb][rb] = F::mma(bv[cb].x, av[rb].x, dre[cb][rb]);
+          dre[cb][rb] = F::mma(-bv[cb].y, av[rb].y, dre[cb][rb]);
+          dim[cb][rb] = F::mma(bv[cb].x, av[rb].y, dim[cb][rb]);
+          dim[cb][rb] = F::mma(bv[cb].y, av[rb].x, dim[cb][rb]);
         }
     }
 #pragma unroll
@@ -92,9 +139,9 @@ __device__ void wg_gemm_sub(int M, int N, int K, const double2* A, int64_t lda, 
       for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int col = c0 + 16 * cb + 4 * j + hi, row = r0 + 16 * rb + lo;
+          const int col = c0 + 16 * cb + F::drow(hi, j), row = r0 + 16 * rb + lo;
           if (row < M && col < N) {
-            double2& c = C[row + (int64_t)col * ldc];
+            Cx& c = C[row + (int64_t)col * ldc];
             c.x -= dre[cb][rb][j];
             c.y -= dim[cb][rb][j];
           }
@@ -111,18 +158,19 @@ __device__ void wg_gemm_sub(int M, int N, int K, const double2* A, int64_t lda, 
 constexpr int kChunkV = kFW / 4;  // vectors per LDS chunk
 
 // Columns of G (kb x ncols, ld): L x = b with L unit lower.
-__device__ void solve_cols_unit_lower(double2* G, int64_t ld, int kb, int ncols, const double2* T, double2* buf) {
+template <class C>
+__device__ void solve_cols_unit_lower(C* G, int64_t ld, int kb, int ncols, const C* T, C* buf) {
   const int v = threadIdx.x >> 2, q = threadIdx.x & 3;
   for (int c0 = 0; c0 < ncols; c0 += kChunkV) {
     const int nc = min(kChunkV, ncols - c0);
     for (int e = threadIdx.x; e < kNB * kChunkV; e += kFW) {
       const int i = e % kNB, c = e / kNB;
-      buf[e] = (i < kb && c < nc) ? G[i + (int64_t)(c0 + c) * ld] : make_double2(0.0, 0.0);
+      buf[e] = (i < kb && c < nc) ? G[i + (int64_t)(c0 + c) * ld] : C{0, 0};
     }
     __syncthreads();
-    double2* x = buf + v * kNB;
+    C* x = buf + v * kNB;
     for (int k = 0; k < kNB - 1; ++k) {
-      const double2 xk = x[k];
+      const C xk = x[k];
       for (int i = q; i < kNB; i += 4)
         if (i > k) csub_mul(x[i], T[i + k * kNB], xk);
       __builtin_amdgcn_wave_barrier();
@@ -137,20 +185,20 @@ __device__ void solve_cols_unit_lower(double2* G, int64_t ld, int kb, int ncols,
 }
 
 // Rows of G (nrows x kb, ld): x L = b with L unit lower, last entry first.
-__device__ void solve_rows_right_unit_lower(double2* G, int64_t ld, int kb, int nrows, const double2* T,
-                                            double2* buf) {
+template <class C>
+__device__ void solve_rows_right_unit_lower(C* G, int64_t ld, int kb, int nrows, const C* T, C* buf) {
   const int v = threadIdx.x >> 2, q = threadIdx.x & 3;
   for (int r0 = 0; r0 < nrows; r0 += kChunkV) {
     const int nr = min(kChunkV, nrows - r0);
     // buf[c + row * kNB]: one row's entries contiguous
     for (int e = threadIdx.x; e < kNB * kChunkV; e += kFW) {
       const int row = e % kChunkV, c = e / kChunkV;
-      buf[c + row * kNB] = (c < kb && row < nr) ? G[r0 + row + (int64_t)c * ld] : make_double2(0.0, 0.0);
+      buf[c + row * kNB] = (c < kb && row < nr) ? G[r0 + row + (int64_t)c * ld] : C{0, 0};
     }
     __syncthreads();
-    double2* x = buf + v * kNB;
+    C* x = buf + v * kNB;
     for (int c2 = kNB - 1; c2 > 0; --c2) {
-      const double2 xc = x[c2];
+      const C xc = x[c2];
       for (int c = q; c < kNB; c += 4)
         if (c < c2) csub_mul(x[c], xc, T[c2 + c * kNB]);
       __builtin_amdgcn_wave_barrier();
@@ -166,20 +214,21 @@ __device__ void solve_rows_right_unit_lower(double2* G, int64_t ld, int kb, int 
 
 // Columns of G (kb x ncols, ld): U y = b with U upper (its diagonal
 // included), last entry first.
-__device__ void solve_cols_upper(double2* G, int64_t ld, int kb, int ncols, const double2* T, double2* buf) {
+template <class C>
+__device__ void solve_cols_upper(C* G, int64_t ld, int kb, int ncols, const C* T, C* buf) {
   const int v = threadIdx.x >> 2, q = threadIdx.x & 3;
   for (int c0 = 0; c0 < ncols; c0 += kChunkV) {
     const int nc = min(kChunkV, ncols - c0);
     for (int e = threadIdx.x; e < kNB * kChunkV; e += kFW) {
       const int i = e % kNB, c = e / kNB;
-      buf[e] = (i < kb && c < nc) ? G[i + (int64_t)(c0 + c) * ld] : make_double2(0.0, 0.0);
+      buf[e] = (i < kb && c < nc) ? G[i + (int64_t)(c0 + c) * ld] : C{0, 0};
     }
     __syncthreads();
-    double2* y = buf + v * kNB;
+    C* y = buf + v * kNB;
     for (int k = kNB - 1; k >= 0; --k) {
       if (q == (k & 3)) y[k] = cdivd(y[k], T[k + k * kNB]);
       __builtin_amdgcn_wave_barrier();
-      const double2 yk = y[k];
+      const C yk = y[k];
       for (int i = q; i < k; i += 4) csub_mul(y[i], T[i + k * kNB], yk);
       __builtin_amdgcn_wave_barrier();
     }
@@ -220,46 +269,57 @@ __device__ void wg_argmax(double& v, int& idx, double* sv, int* si) {
 
 // Copies the kb x kb diagonal block at F (ld) into T (kNB x kNB), padded
 // with the identity beyond kb.
-__device__ void load_diag_block(const double2* F, int64_t ld, int kb, double2* T) {
+template <class C>
+__device__ void load_diag_block(const C* F, int64_t ld, int kb, C* T) {
   for (int e = threadIdx.x; e < kNB * kNB; e += kFW) {
     const int i = e % kNB, j = e / kNB;
-    T[e] = (i < kb && j < kb) ? F[i + (int64_t)j * ld] : make_double2(i == j ? 1.0 : 0.0, 0.0);
+    T[e] = (i < kb && j < kb) ? F[i + (int64_t)j * ld] : C{i == j ? 1 : 0, 0};
   }
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kFW) void front_kernel(const FrontJob* __restrict__ jobs, double2* __restrict__ ws,
-                                                    double2* __restrict__ upd, const int32_t* __restrict__ asm_pos,
+// One front per workgroup, in working precision R; the panels are written
+// in complex64 when c64 is set (always so for R = float).
+template <class R>
+__global__ __launch_bounds__(kFW) void front_kernel(const FrontJob* __restrict__ jobs,
+                                                    typename Fp<R>::C* __restrict__ ws,
+                                                    typename Fp<R>::C* __restrict__ upd,
+                                                    const int32_t* __restrict__ asm_pos,
                                                     const int32_t* __restrict__ asm_val,
                                                     const double2* __restrict__ aval,
                                                     const FrontChild* __restrict__ kids,
                                                     const int32_t* __restrict__ ep, int32_t* __restrict__ piv,
                                                     int32_t* __restrict__ npert, void* __restrict__ pf,
                                                     void* __restrict__ pb, int c64, int tile_rows) {
-  __shared__ double2 T[kNB * kNB];
-  __shared__ double2 buf[kNB * kChunkV];
+  using F = Fp<R>;
+  using Cx = typename F::C;
+  __shared__ Cx T[kNB * kNB];
+  __shared__ Cx buf[kNB * kChunkV];
   __shared__ double sv[kFW / 64];
   __shared__ int si[kFW / 64];
   const FrontJob J = jobs[blockIdx.x];
   const int tid = threadIdx.x;
   const int m = J.m, w = J.w, r = m - w;
   const int64_t mm = (int64_t)m * m;
-  double2* F = ws + J.F;
+  Cx* Fm = ws + J.F;
 
   // 1. assembly
-  for (int64_t e = tid; e < mm; e += kFW) F[e] = make_double2(0.0, 0.0);
+  for (int64_t e = tid; e < mm; e += kFW) Fm[e] = F::mk(0.0, 0.0);
   __syncthreads();
-  for (int64_t q = J.asm0 + tid; q < J.asm1; q += kFW) F[asm_pos[q]] = aval[asm_val[q]];
+  for (int64_t q = J.asm0 + tid; q < J.asm1; q += kFW) {
+    const double2 a = aval[asm_val[q]];
+    Fm[asm_pos[q]] = F::mk(a.x, a.y);
+  }
   __syncthreads();
   for (int c = J.kid0; c < J.kid1; ++c) {
     const FrontChild K = kids[c];
-    const double2* S = upd + K.upd;
+    const Cx* S = upd + K.upd;
     const int32_t* map = ep + K.ep;
     const int64_t rc2 = (int64_t)K.r * K.r;
     for (int64_t e = tid; e < rc2; e += kFW) {
       const int a = (int)(e % K.r), b = (int)(e / K.r);
-      double2& f = F[map[a] + (int64_t)map[b] * m];
-      const double2 s = S[e];
+      Cx& f = Fm[map[a] + (int64_t)map[b] * m];
+      const Cx s = S[e];
       f.x += s.x;
       f.y += s.y;
     }
@@ -274,11 +334,11 @@ __global__ __launch_bounds__(kFW) void front_kernel(const FrontJob* __restrict__
   for (int k0 = 0; k0 < w; k0 += kNB) {
     const int kb = min(kNB, w - k0);
     for (int k = k0; k < k0 + kb; ++k) {
-      double2* colk = F + (int64_t)k * m;
+      Cx* colk = Fm + (int64_t)k * m;
       double best = -1.0;
       int p = k;
       for (int i = k + tid; i < w; i += kFW) {
-        const double a = hypot(colk[i].x, colk[i].y);
+        const double a = hypot((double)colk[i].x, (double)colk[i].y);
         if (a > best) {
           best = a;
           p = i;
@@ -287,9 +347,9 @@ __global__ __launch_bounds__(kFW) void front_kernel(const FrontJob* __restrict__
       wg_argmax(best, p, sv, si);
       if (p != k) {
         for (int j = tid; j < m; j += kFW) {
-          const double2 t = F[k + (int64_t)j * m];
-          F[k + (int64_t)j * m] = F[p + (int64_t)j * m];
-          F[p + (int64_t)j * m] = t;
+          const Cx t = Fm[k + (int64_t)j * m];
+          Fm[k + (int64_t)j * m] = Fm[p + (int64_t)j * m];
+          Fm[p + (int64_t)j * m] = t;
         }
         if (tid == 0) {
           const int32_t t = perm[k];
@@ -298,104 +358,107 @@ __global__ __launch_bounds__(kFW) void front_kernel(const FrontJob* __restrict__
         }
         __syncthreads();
       }
-      if (!(best > kTinyPivot * J.anorm)) {
+      if (!(best > F::kTiny * J.anorm)) {
         // zero or tiny pivot column: replaced by a small diagonal (counted;
         // setup then fails unless replacements were asked for)
-        if (tid == 0) colk[k] = make_double2(sqrt(DBL_EPSILON) * J.anorm, 0.0);
+        if (tid == 0) colk[k] = F::mk(sqrt(F::kEps) * J.anorm, 0.0);
         ++n_pert;
         __syncthreads();
       }
-      const double2 d = colk[k];
+      const Cx d = colk[k];
       for (int i = k + 1 + tid; i < m; i += kFW) {
-        const double2 l = cdivd(colk[i], d);
+        const Cx l = cdivd(colk[i], d);
         colk[i] = l;
-        for (int j = k + 1; j < k0 + kb; ++j) csub_mul(F[i + (int64_t)j * m], l, F[k + (int64_t)j * m]);
+        for (int j = k + 1; j < k0 + kb; ++j) csub_mul(Fm[i + (int64_t)j * m], l, Fm[k + (int64_t)j * m]);
       }
       __syncthreads();
     }
     const int j0 = k0 + kb;
     if (j0 >= m) continue;
     // U12 rows of this block: unit-lower solve with the block's diagonal
-    load_diag_block(F + k0 + (int64_t)k0 * m, m, kb, T);
-    solve_cols_unit_lower(F + k0 + (int64_t)j0 * m, m, kb, m - j0, T, buf);
-    wg_gemm_sub(m - j0, m - j0, kb, F + j0 + (int64_t)k0 * m, m, F + k0 + (int64_t)j0 * m, m,
-                F + j0 + (int64_t)j0 * m, m);
+    load_diag_block(Fm + k0 + (int64_t)k0 * m, m, kb, T);
+    solve_cols_unit_lower(Fm + k0 + (int64_t)j0 * m, m, kb, m - j0, T, buf);
+    wg_gemm_sub<R>(m - j0, m - j0, kb, Fm + j0 + (int64_t)k0 * m, m, Fm + k0 + (int64_t)j0 * m, m,
+                   Fm + j0 + (int64_t)j0 * m, m);
   }
 
   if (tid == 0) npert[blockIdx.x] = n_pert;
 
   // 3. Schur complement for the parent
   if (r > 0) {
-    double2* S = upd + J.upd;
+    Cx* S = upd + J.upd;
     const int64_t r2 = (int64_t)r * r;
     for (int64_t e = tid; e < r2; e += kFW) {
       const int a = (int)(e % r), b = (int)(e / r);
-      S[e] = F[w + a + (int64_t)(w + b) * m];
+      S[e] = Fm[w + a + (int64_t)(w + b) * m];
     }
   }
 
   // 4a. X = [I; L21] L11^{-1}, block columns from the last to the first
-  double2* X = ws + J.X;
+  Cx* X = ws + J.X;
   const int nblk = (w + kNB - 1) / kNB;
   for (int jb = nblk - 1; jb >= 0; --jb) {
     const int j0 = jb * kNB, kb = min(kNB, w - j0), jend = j0 + kb;
     const int64_t cnt = (int64_t)m * kb;
     for (int64_t e = tid; e < cnt; e += kFW) {
       const int i = (int)(e % m), c = j0 + (int)(e / m);
-      double2 v;
+      Cx v;
       if (i < j0)
-        v = make_double2(0.0, 0.0);
+        v = F::mk(0.0, 0.0);
       else if (i < w)
-        v = make_double2(i == c ? 1.0 : 0.0, 0.0);
+        v = F::mk(i == c ? 1.0 : 0.0, 0.0);
       else
-        v = F[i + (int64_t)c * m];
+        v = Fm[i + (int64_t)c * m];
       X[i + (int64_t)c * m] = v;
     }
     __syncthreads();
     if (jend < w)
-      wg_gemm_sub(m - j0, kb, w - jend, X + j0 + (int64_t)jend * m, m, F + jend + (int64_t)j0 * m, m,
-                  X + j0 + (int64_t)j0 * m, m);
-    load_diag_block(F + j0 + (int64_t)j0 * m, m, kb, T);
+      wg_gemm_sub<R>(m - j0, kb, w - jend, X + j0 + (int64_t)jend * m, m, Fm + jend + (int64_t)j0 * m, m,
+                     X + j0 + (int64_t)j0 * m, m);
+    load_diag_block(Fm + j0 + (int64_t)j0 * m, m, kb, T);
     solve_rows_right_unit_lower(X + j0 + (int64_t)j0 * m, m, kb, m - j0, T, buf);
   }
 
   // 4b. Y = U11^{-1} [I | -U12], block rows from the last to the first
-  double2* Y = ws + J.Y;
+  Cx* Y = ws + J.Y;
   for (int ib = nblk - 1; ib >= 0; --ib) {
     const int i0 = ib * kNB, kb = min(kNB, w - i0), iend = i0 + kb;
     const int64_t cnt = (int64_t)kb * m;
     for (int64_t e = tid; e < cnt; e += kFW) {
       const int q = (int)(e % kb), c = (int)(e / kb), row = i0 + q;
-      double2 v;
+      Cx v;
       if (c < w) {
-        v = make_double2(row == c ? 1.0 : 0.0, 0.0);
+        v = F::mk(row == c ? 1.0 : 0.0, 0.0);
       } else {
-        const double2 u = F[row + (int64_t)c * m];
-        v = make_double2(-u.x, -u.y);
+        const Cx u = Fm[row + (int64_t)c * m];
+        v.x = -u.x;
+        v.y = -u.y;
       }
       Y[row + (int64_t)c * w] = v;
     }
     __syncthreads();
     if (iend < w)
-      wg_gemm_sub(kb, m - i0, w - iend, F + i0 + (int64_t)iend * m, m, Y + iend + (int64_t)i0 * w, w,
-                  Y + i0 + (int64_t)i0 * w, w);
-    load_diag_block(F + i0 + (int64_t)i0 * m, m, kb, T);
+      wg_gemm_sub<R>(kb, m - i0, w - iend, Fm + i0 + (int64_t)iend * m, m, Y + iend + (int64_t)i0 * w, w,
+                     Y + i0 + (int64_t)i0 * w, w);
+    load_diag_block(Fm + i0 + (int64_t)i0 * m, m, kb, T);
     solve_cols_upper(Y + i0 + (int64_t)i0 * w, w, kb, m - i0, T, buf);
   }
 
   // 5. solve tiles (column-major inside a tile); diagonal-block entries
   // outside the triangle are stored as zeros
+  auto put = [&](void* dst, int64_t at, Cx v) {
+    if (c64)
+      reinterpret_cast<float2*>(dst)[at] = make_float2((float)v.x, (float)v.y);
+    else
+      reinterpret_cast<double2*>(dst)[at] = make_double2((double)v.x, (double)v.y);
+  };
   int64_t off = J.pfo;
   for (int r0 = 0; r0 < m; r0 += tile_rows) {
     const int nr = min(tile_rows, m - r0), nc = min(w, r0 + nr);
     const int64_t cnt = (int64_t)nr * nc;
     for (int64_t e = tid; e < cnt; e += kFW) {
       const int i = (int)(e % nr), col = (int)(e / nr), row = r0 + i;
-      const double2 v = (row < w && col > row) ? make_double2(0.0, 0.0) : X[row + (int64_t)col * m];
-      if (c64)
-        reinterpret_cast<float2*>(pf)[off + e] = make_float2((float)v.x, (float)v.y);
-      else
-        reinterpret_cast<double2*>(pf)[off + e] = v;
+      put(pf, off + e, (row < w && col > row) ? F::mk(0.0, 0.0) : X[row + (int64_t)col * m]);
     }
     off += cnt;
   }
@@ -405,11 +468,7 @@ __global__ __launch_bounds__(kFW) void front_kernel(const FrontJob* __restrict__
     const int64_t cnt = (int64_t)nr * nc;
     for (int64_t e = tid; e < cnt; e += kFW) {
       const int i = (int)(e % nr), row = r0 + i, col = r0 + (int)(e / nr);
-      const double2 v = (col < w && col < row) ? make_double2(0.0, 0.0) : Y[row + (int64_t)col * w];
-      if (c64)
-        reinterpret_cast<float2*>(pb)[off + e] = make_float2((float)v.x, (float)v.y);
-      else
-        reinterpret_cast<double2*>(pb)[off + e] = v;
+      put(pb, off + e, (col < w && col < row) ? F::mk(0.0, 0.0) : Y[row + (int64_t)col * w]);
     }
     off += cnt;
   }
@@ -417,13 +476,21 @@ __global__ __launch_bounds__(kFW) void front_kernel(const FrontJob* __restrict__
 
 }  // namespace
 
-void factor_fronts(const FrontJob* jobs, int njobs, double* ws, double* upd, const int32_t* asm_pos,
+void factor_fronts(const FrontJob* jobs, int njobs, void* ws, void* upd, const int32_t* asm_pos,
                    const int32_t* asm_val, const double* aval, const FrontChild* kids, const int32_t* ep,
-                   int32_t* piv, int32_t* npert, void* pf, void* pb, bool c64, int tile_rows, hipStream_t s) {
+                   int32_t* piv, int32_t* npert, void* pf, void* pb, FactorPrecision prec, int tile_rows,
+                   hipStream_t s) {
   if (njobs <= 0) return;
-  front_kernel<<<(unsigned)njobs, kFW, 0, s>>>(jobs, reinterpret_cast<double2*>(ws), reinterpret_cast<double2*>(upd),
-                                               asm_pos, asm_val, reinterpret_cast<const double2*>(aval), kids, ep, piv,
-                                               npert, pf, pb, c64 ? 1 : 0, tile_rows);
+  const double2* a = reinterpret_cast<const double2*>(aval);
+  if (prec == FactorPrecision::kC64) {
+    front_kernel<float><<<(unsigned)njobs, kFW, 0, s>>>(jobs, reinterpret_cast<float2*>(ws),
+                                                        reinterpret_cast<float2*>(upd), asm_pos, asm_val, a, kids, ep,
+                                                        piv, npert, pf, pb, 1, tile_rows);
+  } else {
+    front_kernel<double><<<(unsigned)njobs, kFW, 0, s>>>(
+        jobs, reinterpret_cast<double2*>(ws), reinterpret_cast<double2*>(upd), asm_pos, asm_val, a, kids, ep, piv,
+        npert, pf, pb, prec == FactorPrecision::kC128RoundedC64 ? 1 : 0, tile_rows);
+  }
 }
 
 }  // namespace dev

@@ -90,7 +90,8 @@ void extend_add_map(const Symbolic& S, int32_t* ep) {
 
 }  // namespace
 
-void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<const Symbolic*>& Ss, bool c64,
+void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<const Symbolic*>& Ss,
+                         dev::FactorPrecision prec,
                          BatchDev& Dv, const std::vector<int64_t>& pf0, const std::vector<int64_t>& pb0,
                          std::vector<NumericOut>& num, int32_t& n_perturbed) {
   const int nm = (int)As.size();
@@ -179,8 +180,11 @@ void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<co
   kid0[nsn] = (int32_t)kids.size();
   DVec<dev::FrontChild> kids_d;
   kids_d.upload(kids);
+  // workspace and Schur complements in the working precision: complex64
+  // entries take one double each, complex128 entries two
+  const size_t wpe = prec == dev::FactorPrecision::kC64 ? 1 : 2;
   DVec<double> upd;
-  upd.alloc(2 * std::max<int64_t>(uoff[nsn], 1));
+  upd.alloc(wpe * std::max<int64_t>(uoff[nsn], 1));
 
   // jobs, level by level, in chunks whose workspace fits the budget
   auto job_ws = [&](int i, int32_t s) {
@@ -242,13 +246,13 @@ void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<co
   DVec<dev::FrontJob> jobs_d;
   jobs_d.upload(jobs);
   DVec<double> ws;
-  ws.alloc(2 * (size_t)budget);
+  ws.alloc(wpe * (size_t)budget);
   DVec<int32_t> piv_d, npert_d;
   piv_d.alloc(std::max<int64_t>(pos0[nm], 1));
   npert_d.alloc(std::max<size_t>(jobs.size(), 1));
   for (auto& L : launches)
     dev::factor_fronts(jobs_d.p + L.first, (int)(L.second - L.first), ws.p, upd.p, asm_pos.p, asm_val.p, aval.p,
-                       kids_d.p, ep_d.p, piv_d.p, npert_d.p + L.first, Dv.pf.p, Dv.pb.p, c64, Ss[0]->tile_rows,
+                       kids_d.p, ep_d.p, piv_d.p, npert_d.p + L.first, Dv.pf.p, Dv.pb.p, prec, Ss[0]->tile_rows,
                        nullptr);
   HELM_HIP(hipGetLastError());
   HELM_HIP(hipDeviceSynchronize());

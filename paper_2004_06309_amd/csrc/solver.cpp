@@ -451,10 +451,11 @@ namespace {
 // into the device panels; without a device only the layout is built (pivots
 // taken as the identity).
 void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symbolic*>& Ss,
-                 const std::vector<const std::vector<int64_t>*>& in_idx, int device, bool numeric, bool c64,
-                 bool on_host, int64_t sn_jobs_min, BatchHost& B, BatchDev& Dv, int32_t& n_perturbed,
-                 double& seconds) {
+                 const std::vector<const std::vector<int64_t>*>& in_idx, int device, bool numeric,
+                 dev::FactorPrecision prec, bool on_host, int64_t sn_jobs_min, BatchHost& B, BatchDev& Dv,
+                 int32_t& n_perturbed, double& seconds) {
   const int nm = (int)As.size();
+  const bool c64 = prec != dev::FactorPrecision::kC128;
   const size_t esz = c64 ? sizeof(std::complex<float>) : sizeof(cplx);
   Dv.c64 = c64 ? 1 : 0;
   std::vector<int64_t> pf0(nm + 1, 0), pb0(nm + 1, 0);
@@ -467,7 +468,7 @@ void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symb
   if (numeric && !on_host) {
     Dv.pf.alloc(esz * (size_t)pf0[nm]);
     Dv.pb.alloc(esz * (size_t)pb0[nm]);
-    factor_batch_device(As, Ss, c64, Dv, pf0, pb0, num, n_perturbed);
+    factor_batch_device(As, Ss, prec, Dv, pf0, pb0, num, n_perturbed);
   } else if (numeric) {
     Dv.pf.alloc(esz * (size_t)pf0[nm]);
     Dv.pb.alloc(esz * (size_t)pb0[nm]);
@@ -982,8 +983,15 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
     in.push_back(&c.subs[i].dofs);
   }
   int32_t npert = 0;
-  const bool c64 = opts && opts->factor_c64;
+  const int32_t c64mode = opts ? opts->factor_c64 : 0;
+  if (c64mode < 0 || c64mode > 2) fail(HELM_EINVAL, "factor_c64 must be 0, 1 or 2");
   const bool on_host = opts && opts->factor_on_host;
+  const bool c64 = c64mode != 0;
+  // the host factorisation works in complex128 only (its complex64 panels
+  // are rounded copies)
+  const dev::FactorPrecision prec = !c64                      ? dev::FactorPrecision::kC128
+                                    : c64mode == 1 && !on_host ? dev::FactorPrecision::kC64
+                                                               : dev::FactorPrecision::kC128RoundedC64;
   double fsec = 0, csec = 0;
   // nb consecutive batches of about equal panel entries (their level sweeps
   // overlap on nb streams): batch k ends at the first subdomain count whose
@@ -1016,7 +1024,7 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
     int32_t np = 0;
     double fs = 0;
     build_batch(part(As, bnd[k], bnd[k + 1]), part(Ss, bnd[k], bnd[k + 1]), part(in, bnd[k], bnd[k + 1]), c.device,
-                on_device, c64, on_host, snb, fb, c.fine[k], np, fs);
+                on_device, prec, on_host, snb, fb, c.fine[k], np, fs);
     npert += np;
     fsec += fs;
     st.factor_entries += fb.nf + fb.nb;
@@ -1041,7 +1049,7 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
       if (!c.ev_join[k]) HELM_HIP(hipEventCreateWithFlags(&c.ev_join[k], hipEventDisableTiming));
     }
   }
-  st.factor_c64 = c64 ? 1 : 0;
+  st.factor_c64 = prec == dev::FactorPrecision::kC64 ? 1 : prec == dev::FactorPrecision::kC128RoundedC64 ? 2 : 0;
   st.batches = nb;
   for (auto& S : c.sym) st.n_supernodes += S.nsn;
   // prolongation map: global dof -> positions with D > 0, in subdomain order
@@ -1084,7 +1092,8 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
     std::iota(ident.begin(), ident.end(), 0);
     BatchHost cb;
     int32_t np2 = 0;
-    build_batch({&c.E}, {&c.Esym}, {&ident}, c.device, on_device, false, on_host, snmin, cb, c.coarse, np2, csec);
+    build_batch({&c.E}, {&c.Esym}, {&ident}, c.device, on_device, dev::FactorPrecision::kC128, on_host, snmin, cb,
+                c.coarse, np2, csec);
     npert += np2;
     c.two_level = true;
     st.n_coarse = (int32_t)c.E.n;

@@ -265,7 +265,9 @@ class Helm:
                       batches=0, perturb_pivots=False, coarse_launch=0):
         """helm_precond_setup: subdomains from the tet partition `part` with
         `overlap` layers, the optional P1 coarse mesh, then the factorisation.
-        c64: complex64 factors; tile_rows / coarse_tile_rows: 16, 32 or 64
+        c64: complex64 factors (True or 1: factorised in complex64 on FP32
+        MFMA; 2: factorised in complex128 and rounded once; False or 0:
+        complex128); tile_rows / coarse_tile_rows: 16, 32 or 64
         (0: 64 / 16); sn_jobs_min: one-wave supernode jobs threshold (0:
         default, -1: never); batches: 1 to 4 subdomain batches whose level
         sweeps run concurrently (0: 2); perturb_pivots: replace zero or tiny
@@ -273,7 +275,9 @@ class Helm:
         coarse_launch: 0 timed, 1 per-level launches, 2 one cooperative
         launch for the coarse solve."""
         part = np.ascontiguousarray(part, dtype=np.int32)
-        opts = PrecondOpts(int(leaf_size), 1 if c64 else 0, int(coarse_leaf_size), int(tile_rows),
+        if c64 not in (False, True, 0, 1, 2):
+            raise ValueError("c64 must be False/True or 0, 1, 2")
+        opts = PrecondOpts(int(leaf_size), int(c64), int(coarse_leaf_size), int(tile_rows),
                            int(coarse_tile_rows), 1 if factor_on_host else 0, int(sn_jobs_min), int(batches),
                            1 if perturb_pivots else 0, int(coarse_launch))
         cm = None

@@ -204,25 +204,39 @@ def test_delayed_and_classic_cgs2(restart):
     say(f"[dcgs2] restart={restart} block its delayed={blk[False][1]} classic={blk[True][1]}")
 
 
-@pytest.mark.parametrize("name", ["tiny", "mid_quarter_2lvl", "ragged_p2"])
-def test_complex64_factors(name):
-    """Subdomain factors stored in complex64 (rounded once from the FP64
-    factorisation; FP64 accumulation): the preconditioner differs from the
-    oracle's by about cond(A_i) * 6e-8, and the flexible GMRES solve still
-    meets the FP64 acceptance bar."""
+# One-level ORAS with complex64 subdomain factors against the oracle's
+# complex128 one (relative, max norm), in units of the FP32 unit roundoff
+# u = 6e-8.  Panels rounded once from the FP64 factorisation: one rounding
+# per panel entry, amplified by the conditioning of the partitioned-inverse
+# products (measured 1e-9 .. 3e-8 here): bound 16 u.  Factorisation in
+# complex64 on FP32 MFMA: the backward error of the FP32 elimination times
+# cond(A_i); the impedance conditions on every face keep the local matrices
+# well conditioned (measured 4e-9 .. 1.7e-7 here, 9.5e-7 at the full mid
+# size): bound 160 u.
+C64_APPLY_TOL = {2: 1e-6, 1: 1e-5}
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("name", ["tiny", "mid_quarter_2lvl", "ragged_p2", "adapted_p2_2lvl"])
+def test_complex64_factors(name, mode):
+    """Subdomain factors in complex64, factorised in complex64 on FP32 MFMA
+    (mode 1) or in complex128 and rounded once (mode 2): the preconditioner
+    differs from the oracle's by the bound above, and the GMRES solve (FP64)
+    still meets the FP64 acceptance bar."""
     w = WORKLOADS[name]()
     P, b, M = opre.build(w)
-    h = helm.from_workload(w, c64=True)
-    assert h.stats()["factor_c64"] == 1
+    h = helm.from_workload(w, c64=mode)
+    assert h.stats()["factor_c64"] == mode
     r = rand_vec(P.n, 7)
     z = torch.empty(P.n, dtype=torch.complex128, device=DEV)
     h.apply_oras(dvec(r), z)
-    assert rel(host(z), M.one_level(r)) <= 1e-4
+    err = rel(host(z), M.one_level(r))
     ro = opre.solve(P, b, M, tol=w.tol, restart=w.restart)
     U = torch.zeros(P.n, dtype=torch.complex128, device=DEV)
     rc, info = h.solve(dvec(b), U, tol=w.tol, restart=w.restart)
     u = host(U)
-    say(f"[c64] {name}: gpu its={info[0]['iterations']} oracle its={ro.iterations}")
+    say(f"[c64 mode {mode}] {name}: apply err {err:.2e}, gpu its={info[0]['iterations']} oracle its={ro.iterations}")
+    assert err <= C64_APPLY_TOL[mode]
     assert rc == helm.HELM_OK
     assert np.linalg.norm(b - P.A @ u) / np.linalg.norm(b) <= w.tol
     assert abs(info[0]["iterations"] - ro.iterations) <= 3
@@ -474,7 +488,8 @@ def test_more_subdomain_batches(name, nb):
 
 def test_three_batches_with_complex64_factors_and_the_server():
     """Three subdomain batches with complex64 factors: local solves bit for
-    bit against one batch (same rounded panels), the 16-column block path;
+    bit against one batch (each front is factorised by one workgroup in
+    either layout, so the panels are the same), the 16-column block path;
     then the continuous-batching server on a three-batch context (its block
     steps fork the local solves onto the batch streams) against solo solves
     and the oracle."""
@@ -489,7 +504,7 @@ def test_three_batches_with_complex64_factors_and_the_server():
     h1.apply_oras(r, z1)
     h3.apply_oras(r, z3)
     assert torch.equal(z1, z3)
-    assert rel(host(z3), M.one_level(host(r))) <= 1e-4
+    assert rel(host(z3), M.one_level(host(r))) <= C64_APPLY_TOL[1]
     B = dvec(b)
     Bs = torch.stack([B * (1 + 0.25 * j) for j in range(16)])
     V1 = torch.zeros_like(Bs)
@@ -579,10 +594,15 @@ def test_device_factorisation_matches_host(name):
         hh.apply_coarse(r, zh)
         assert rel(host(zd), host(zh)) <= 1e-10
     # complex64 panels rounded once from either factorisation
-    hd32 = helm.from_workload(w, c64=True)
+    hd32 = helm.from_workload(w, c64=2)
     hd32.apply_oras(r, zd)
     hh.apply_oras(r, zh)
     assert rel(host(zd), host(zh)) <= 1e-4
+    # and factorised in complex64 on the device
+    hd32 = helm.from_workload(w, c64=1)
+    assert hd32.stats()["factor_c64"] == 1
+    hd32.apply_oras(r, zd)
+    assert rel(host(zd), host(zh)) <= C64_APPLY_TOL[1]
 
 
 def test_edge_cases():
