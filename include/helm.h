@@ -112,6 +112,12 @@ typedef struct helm_precond_opts {
                               result on a fixed right-hand side matched the
                               per-level launches at setup (to 1e-13; with
                               2 a mismatch fails with HELM_EDEVICE)        */
+  int32_t split_front_rows;  /* device factorisation: frontal matrices of at
+                              least this many rows are spread over several
+                              workgroups (a sequence of launches per
+                              level), smaller ones take one workgroup each;
+                              0 = 256, -1 = never.  The factors are the
+                              same either way                              */
 } helm_precond_opts;
 
 enum {

@@ -290,9 +290,10 @@ void ensure_width(Ctx& c, int m, int S);
 // factor_gpu.cpp: numeric factorisation of a batch on the device, panels
 // written into Dv.pf / Dv.pb (allocated by the caller) at the per-matrix
 // offsets pf0 / pb0 (complex64 unless prec is kC128); pivots returned in
-// num.
+// num.  Fronts of at least split_min rows (none if negative) are factorised
+// by several workgroups each.
 void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<const Symbolic*>& Ss,
-                         dev::FactorPrecision prec,
+                         dev::FactorPrecision prec, int32_t split_min,
                          BatchDev& Dv, const std::vector<int64_t>& pf0, const std::vector<int64_t>& pb0,
                          std::vector<NumericOut>& num, int32_t& n_perturbed);
 

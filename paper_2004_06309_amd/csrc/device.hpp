@@ -133,6 +133,19 @@ void factor_fronts(const FrontJob* jobs, int njobs, void* ws, void* upd, const i
                    const int32_t* asm_val, const double* aval, const FrontChild* kids, const int32_t* ep,
                    int32_t* piv, int32_t* npert, void* pf, void* pb, FactorPrecision prec, int tile_rows,
                    hipStream_t s);
+// The same for fronts factorised by several workgroups each, in a sequence
+// of launches (assembly by column strips; per 32-column block a one-
+// workgroup panel step and a column-strip update step; the X / Y panels by
+// row / column strips; the backward tiles).  mmax / wmax: largest m / w of
+// the jobs; swp: one int per pivot position (the row interchanges, batch
+// positions as piv).  ep must map every child's rows to increasing front
+// positions.  Same results as factor_fronts.
+void factor_fronts_split(const FrontJob* jobs, int njobs, int mmax, int wmax, void* ws, void* upd,
+                         const int32_t* asm_pos, const int32_t* asm_val, const double* aval, const FrontChild* kids,
+                         const int32_t* ep, int32_t* piv, int32_t* swp, int32_t* npert, void* pf, void* pb,
+                         FactorPrecision prec, int tile_rows, hipStream_t s);
+// Fronts of at least this many rows take factor_fronts_split by default.
+constexpr int kSplitFrontMin = 256;
 
 // Task ranges of every level of a batch (a kernel argument).
 constexpr int kMaxLevels = 40;

@@ -89,44 +89,45 @@ __device__ __forceinline__ C cdivd(C a, C d) {
 }
 
 // C[M x N] -= A[M x K] B[K x N] (complex, column-major), by the whole
-// workgroup: each wave computes 32 x 32 output tiles as 2 x 2 MFMA blocks.
-// The MFMA computes the transposed block C^T = B^T A^T, so the 16 lanes that
-// share an accumulator column hold 16 consecutive rows of C (coalesced
-// read-modify-write).  16x16x4 operand layout: lane l holds A[l % 16][l / 16]
-// and B[l / 16][l % 16]; accumulator register j of lane l is
-// D[Fp<R>::drow(l / 16, j)][l % 16].
-template <class R>
+// workgroup: each wave computes (16 RB) x (16 CB) output tiles as RB x CB
+// MFMA blocks.  The MFMA computes the transposed block C^T = B^T A^T, so the
+// 16 lanes that share an accumulator column hold 16 consecutive rows of C
+// (coalesced read-modify-write).  16x16x4 operand layout: lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator register j of lane l
+// is D[Fp<R>::drow(l / 16, j)][l % 16].
+template <class R, int RB = 2, int CB = 2>
 __device__ void wg_gemm_sub(int M, int N, int K, const typename Fp<R>::C* A, int64_t lda,
                             const typename Fp<R>::C* B, int64_t ldb, typename Fp<R>::C* C, int64_t ldc) {
   using F = Fp<R>;
   using Cx = typename F::C;
   using V4 = typename F::V4;
+  constexpr int TR = 16 * RB, TC = 16 * CB;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, lo = lane & 15, hi = lane >> 4;
-  const int tm = (M + 31) >> 5, tn = (N + 31) >> 5;
+  const int tm = (M + TR - 1) / TR, tn = (N + TC - 1) / TC;
   for (int t = wv; t < tm * tn; t += kFW / 64) {
-    const int r0 = (t % tm) * 32, c0 = (t / tm) * 32;
-    V4 dre[2][2], dim[2][2];
+    const int r0 = (t % tm) * TR, c0 = (t / tm) * TC;
+    V4 dre[CB][RB], dim[CB][RB];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < CB; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) dre[a][b] = dim[a][b] = V4{0, 0, 0, 0};
+      for (int b = 0; b < RB; ++b) dre[a][b] = dim[a][b] = V4{0, 0, 0, 0};
     for (int k0 = 0; k0 < K; k0 += 4) {
       const int k = k0 + hi;
-      Cx av[2], bv[2];
+      Cx av[RB], bv[CB];
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb) {
+      for (int rb = 0; rb < RB; ++rb) {
         const int row = r0 + 16 * rb + lo;
         av[rb] = (row < M && k < K) ? A[row + (int64_t)k * lda] : F::mk(0.0, 0.0);
       }
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb) {
+      for (int cb = 0; cb < CB; ++cb) {
         const int col = c0 + 16 * cb + lo;
         bv[cb] = (col < N && k < K) ? B[k + (int64_t)col * ldb] : F::mk(0.0, 0.0);
       }
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
+      for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb) {
+        for (int rb = 0; rb < RB; ++rb) {
           dre[cb][rb] = F::mma(bv[cb].x, av[rb].x, dre[cb][rb]);
           dre[cb][rb] = F::mma(-bv[cb].y, av[rb].y, dre[cb][rb]);
           dim[cb][rb] = F::mma(bv[cb].x, av[rb].y, dim[cb][rb]);
@@ -134,9 +135,9 @@ __device__ void wg_gemm_sub(int M, int N, int K, const typename Fp<R>::C* A, int
         }
     }
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
+    for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
+      for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int col = c0 + 16 * cb + F::drow(hi, j), row = r0 + 16 * rb + lo;
@@ -474,6 +475,345 @@ __global__ __launch_bounds__(kFW) void front_kernel(const FrontJob* __restrict__
   }
 }
 
+// ---- large fronts: several workgroups per front ---------------------------
+// Near the top of the elimination trees a level has a few dozen fronts of a
+// thousand rows or more, so one workgroup per front leaves most of the device
+// idle for most of the factorisation.  Fronts of at least kSplitFrontMin rows
+// are therefore factorised by a sequence of launches, each spreading every
+// front over many workgroups:
+//   assembly   one workgroup per kStrip-column strip of F;
+//   for each kNB-column block of the partial LU:
+//     panel    one workgroup per front: pivot search and elimination inside
+//              the block's columns (the row interchanges are applied to those
+//              columns only, and recorded);
+//     update   one workgroup per kStrip-column strip: the block's row
+//              interchanges, then, right of the block, the U12 rows and the
+//              rank-kNB update of the strip below the block;
+//   panels     one workgroup per kStrip-row strip of X = [I; L21] L11^{-1}
+//              (its rows are independent right triangular solves; the strip
+//              also copies its rows of the Schur complement and writes its
+//              forward solve tiles), or per kStrip-column strip of
+//              Y = U11^{-1} [I | -U12] (independent columns);
+//   Y tiles    one workgroup per backward solve tile.
+// Every entry goes through the same operations in the same order as in
+// front_kernel, so both forms give the same factors.
+constexpr int kStrip = 64;
+
+template <class R>
+__global__ __launch_bounds__(kFW) void split_assemble_kernel(
+    const FrontJob* __restrict__ jobs, typename Fp<R>::C* __restrict__ ws, const typename Fp<R>::C* __restrict__ upd,
+    const int32_t* __restrict__ asm_pos, const int32_t* __restrict__ asm_val, const double2* __restrict__ aval,
+    const FrontChild* __restrict__ kids, const int32_t* __restrict__ ep, int32_t* __restrict__ piv,
+    int32_t* __restrict__ npert) {
+  using F = Fp<R>;
+  using Cx = typename F::C;
+  const FrontJob J = jobs[blockIdx.x];
+  const int tid = threadIdx.x, m = J.m, c0 = blockIdx.y * kStrip;
+  if (c0 >= m) return;
+  const int c1 = min(m, c0 + kStrip);
+  Cx* Fm = ws + J.F;
+  if (blockIdx.y == 0) {
+    for (int k = tid; k < J.w; k += kFW) piv[J.piv0 + k] = J.c0 + k;
+    if (tid == 0) npert[blockIdx.x] = 0;
+  }
+  Cx* Fs = Fm + (int64_t)c0 * m;
+  const int64_t cnt = (int64_t)m * (c1 - c0);
+  for (int64_t e = tid; e < cnt; e += kFW) Fs[e] = F::mk(0.0, 0.0);
+  __syncthreads();
+  for (int64_t q = J.asm0 + tid; q < J.asm1; q += kFW) {
+    const int32_t pos = asm_pos[q];
+    const int col = pos / m;
+    if (col >= c0 && col < c1) {
+      const double2 a = aval[asm_val[q]];
+      Fm[pos] = F::mk(a.x, a.y);
+    }
+  }
+  __syncthreads();
+  for (int c = J.kid0; c < J.kid1; ++c) {
+    const FrontChild K = kids[c];
+    const Cx* S = upd + K.upd;
+    const int32_t* map = ep + K.ep;
+    // the child's rows map to increasing front positions: the child columns
+    // landing in this strip are one range [b0, b1)
+    int lo = 0, hi = K.r;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (map[mid] < c0) lo = mid + 1; else hi = mid;
+    }
+    const int b0 = lo;
+    hi = K.r;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (map[mid] < c1) lo = mid + 1; else hi = mid;
+    }
+    const int64_t ncnt = (int64_t)(lo - b0) * K.r;
+    for (int64_t e = tid; e < ncnt; e += kFW) {
+      const int a = (int)(e % K.r), b = b0 + (int)(e / K.r);
+      Cx& f = Fm[map[a] + (int64_t)map[b] * m];
+      const Cx sv = S[a + (int64_t)b * K.r];
+      f.x += sv.x;
+      f.y += sv.y;
+    }
+    __syncthreads();
+  }
+}
+
+template <class R>
+__global__ __launch_bounds__(kFW) void split_panel_kernel(const FrontJob* __restrict__ jobs,
+                                                          typename Fp<R>::C* __restrict__ ws,
+                                                          int32_t* __restrict__ piv, int32_t* __restrict__ swp,
+                                                          int32_t* __restrict__ npert, int k0) {
+  using F = Fp<R>;
+  using Cx = typename F::C;
+  __shared__ double sv[kFW / 64];
+  __shared__ int si[kFW / 64];
+  const FrontJob J = jobs[blockIdx.x];
+  const int tid = threadIdx.x, m = J.m, w = J.w;
+  if (k0 >= w) return;
+  const int kb = min(kNB, w - k0);
+  Cx* Fm = ws + J.F;
+  int32_t* perm = piv + J.piv0;
+  int32_t* sw = swp + J.piv0;
+  int n_pert = 0;
+  for (int k = k0; k < k0 + kb; ++k) {
+    Cx* colk = Fm + (int64_t)k * m;
+    double best = -1.0;
+    int p = k;
+    for (int i = k + tid; i < w; i += kFW) {
+      const double a = hypot((double)colk[i].x, (double)colk[i].y);
+      if (a > best) {
+        best = a;
+        p = i;
+      }
+    }
+    wg_argmax(best, p, sv, si);
+    if (p != k) {
+      if (tid < kb) {
+        const int64_t j = k0 + tid;
+        const Cx t = Fm[k + j * m];
+        Fm[k + j * m] = Fm[p + j * m];
+        Fm[p + j * m] = t;
+      }
+      if (tid == 0) {
+        const int32_t t = perm[k];
+        perm[k] = perm[p];
+        perm[p] = t;
+      }
+    }
+    if (tid == 0) sw[k] = p;
+    __syncthreads();
+    if (!(best > F::kTiny * J.anorm)) {
+      if (tid == 0) colk[k] = F::mk(sqrt(F::kEps) * J.anorm, 0.0);
+      ++n_pert;
+      __syncthreads();
+    }
+    const Cx d = colk[k];
+    for (int i = k + 1 + tid; i < m; i += kFW) {
+      const Cx l = cdivd(colk[i], d);
+      colk[i] = l;
+      for (int j = k + 1; j < k0 + kb; ++j) csub_mul(Fm[i + (int64_t)j * m], l, Fm[k + (int64_t)j * m]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) npert[blockIdx.x] += n_pert;
+}
+
+template <class R>
+__global__ __launch_bounds__(kFW) void split_update_kernel(const FrontJob* __restrict__ jobs,
+                                                           typename Fp<R>::C* __restrict__ ws,
+                                                           const int32_t* __restrict__ swp, int k0) {
+  using F = Fp<R>;
+  using Cx = typename F::C;
+  __shared__ Cx T[kNB * kNB];
+  __shared__ Cx buf[kNB * kChunkV];
+  const FrontJob J = jobs[blockIdx.x];
+  const int tid = threadIdx.x, m = J.m, w = J.w;
+  if (k0 >= w) return;
+  const int c0 = blockIdx.y * kStrip;
+  if (c0 >= m) return;
+  const int kb = min(kNB, w - k0), j0 = k0 + kb, c1 = min(m, c0 + kStrip);
+  Cx* Fm = ws + J.F;
+  const int32_t* sw = swp + J.piv0;
+  // the block's row interchanges, in order, one column per thread
+  {
+    const int col = c0 + tid;
+    if (tid < kStrip && col < c1 && (col < k0 || col >= j0)) {
+      Cx* Fc = Fm + (int64_t)col * m;
+      for (int k = k0; k < j0; ++k) {
+        const int p = sw[k];
+        if (p != k) {
+          const Cx t = Fc[k];
+          Fc[k] = Fc[p];
+          Fc[p] = t;
+        }
+      }
+    }
+  }
+  if (c1 <= j0) return;
+  __syncthreads();
+  const int js = max(c0, j0), nc = c1 - js;
+  load_diag_block(Fm + k0 + (int64_t)k0 * m, m, kb, T);
+  solve_cols_unit_lower(Fm + k0 + (int64_t)js * m, m, kb, nc, T, buf);
+  wg_gemm_sub<R>(m - j0, nc, kb, Fm + j0 + (int64_t)k0 * m, m, Fm + k0 + (int64_t)js * m, m,
+                 Fm + j0 + (int64_t)js * m, m);
+}
+
+// Entries of the solve tile starting at row r0 of a panel: forward tiles are
+// min(tile_rows, m - r0) x min(w, r0 + nr), backward ones
+// min(tile_rows, w - r0) x (m - r0); offset of the tile starting at row r0.
+__device__ __forceinline__ int64_t fwd_tile_offset(int m, int w, int tile_rows, int r0) {
+  int64_t off = 0;
+  for (int t0 = 0; t0 < r0; t0 += tile_rows) {
+    const int nr = min(tile_rows, m - t0);
+    off += (int64_t)nr * min(w, t0 + nr);
+  }
+  return off;
+}
+__device__ __forceinline__ int64_t bwd_tile_offset(int m, int w, int tile_rows, int r0) {
+  int64_t off = 0;
+  for (int t0 = 0; t0 < r0; t0 += tile_rows) off += (int64_t)min(tile_rows, w - t0) * (m - t0);
+  return off;
+}
+
+template <class C>
+__device__ __forceinline__ void put_entry(void* dst, int64_t at, C v, int c64) {
+  if (c64)
+    reinterpret_cast<float2*>(dst)[at] = make_float2((float)v.x, (float)v.y);
+  else
+    reinterpret_cast<double2*>(dst)[at] = make_double2((double)v.x, (double)v.y);
+}
+
+// blockIdx.y < sx: row strip of X (and its Schur complement rows and forward
+// tiles); otherwise column strip of Y.
+template <class R>
+__global__ __launch_bounds__(kFW) void split_panels_kernel(const FrontJob* __restrict__ jobs,
+                                                           typename Fp<R>::C* __restrict__ ws,
+                                                           typename Fp<R>::C* __restrict__ upd, void* __restrict__ pf,
+                                                           int c64, int tile_rows, int sx) {
+  using F = Fp<R>;
+  using Cx = typename F::C;
+  __shared__ Cx T[kNB * kNB];
+  __shared__ Cx buf[kNB * kChunkV];
+  const FrontJob J = jobs[blockIdx.x];
+  const int tid = threadIdx.x, m = J.m, w = J.w, r = m - w;
+  const Cx* Fm = ws + J.F;
+  const int nblk = (w + kNB - 1) / kNB;
+  if ((int)blockIdx.y < sx) {
+    const int a0 = blockIdx.y * kStrip;
+    if (a0 >= m) return;
+    const int h = min(kStrip, m - a0);
+    // Schur complement rows of this strip
+    if (r > 0 && a0 + h > w) {
+      Cx* S = upd + J.upd;
+      const int ra = max(a0, w) - w, nra = a0 + h - w - ra;
+      const int64_t cnt = (int64_t)nra * r;
+      for (int64_t e = tid; e < cnt; e += kFW) {
+        const int a = ra + (int)(e % nra), b = (int)(e / nra);
+        S[a + (int64_t)b * r] = Fm[w + a + (int64_t)(w + b) * m];
+      }
+    }
+    Cx* X = ws + J.X;
+    for (int jb = nblk - 1; jb >= 0; --jb) {
+      const int j0 = jb * kNB, kb = min(kNB, w - j0), jend = j0 + kb;
+      const int64_t cnt = (int64_t)h * kb;
+      for (int64_t e = tid; e < cnt; e += kFW) {
+        const int i = a0 + (int)(e % h), c = j0 + (int)(e / h);
+        Cx v;
+        if (i < j0)
+          v = F::mk(0.0, 0.0);
+        else if (i < w)
+          v = F::mk(i == c ? 1.0 : 0.0, 0.0);
+        else
+          v = Fm[i + (int64_t)c * m];
+        X[i + (int64_t)c * m] = v;
+      }
+      __syncthreads();
+      if (a0 + h <= j0) continue;  // rows above the block: zero
+      if (jend < w)
+        wg_gemm_sub<R, 1, 2>(h, kb, w - jend, X + a0 + (int64_t)jend * m, m, Fm + jend + (int64_t)j0 * m, m,
+                             X + a0 + (int64_t)j0 * m, m);
+      load_diag_block(Fm + j0 + (int64_t)j0 * m, m, kb, T);
+      solve_rows_right_unit_lower(X + a0 + (int64_t)j0 * m, m, kb, h, T, buf);
+    }
+    // forward tiles of the strip's rows
+    for (int r0 = a0; r0 < a0 + h; r0 += tile_rows) {
+      const int nr = min(tile_rows, m - r0), nc = min(w, r0 + nr);
+      const int64_t off = J.pfo + fwd_tile_offset(m, w, tile_rows, r0);
+      const int64_t cnt = (int64_t)nr * nc;
+      for (int64_t e = tid; e < cnt; e += kFW) {
+        const int i = (int)(e % nr), col = (int)(e / nr), row = r0 + i;
+        put_entry(pf, off + e, (row < w && col > row) ? F::mk(0.0, 0.0) : X[row + (int64_t)col * m], c64);
+      }
+    }
+  } else {
+    const int cs = (blockIdx.y - sx) * kStrip;
+    if (cs >= m) return;
+    const int nc = min(kStrip, m - cs);
+    Cx* Y = ws + J.Y;
+    for (int ib = nblk - 1; ib >= 0; --ib) {
+      const int i0 = ib * kNB, kb = min(kNB, w - i0), iend = i0 + kb;
+      const int64_t cnt = (int64_t)kb * nc;
+      for (int64_t e = tid; e < cnt; e += kFW) {
+        const int q = (int)(e % kb), c = cs + (int)(e / kb), row = i0 + q;
+        Cx v;
+        if (c < w) {
+          v = F::mk(row == c ? 1.0 : 0.0, 0.0);
+        } else {
+          const Cx u = Fm[row + (int64_t)c * m];
+          v.x = -u.x;
+          v.y = -u.y;
+        }
+        Y[row + (int64_t)c * w] = v;
+      }
+      __syncthreads();
+      if (cs + nc <= i0) continue;  // columns left of the block: zero
+      if (iend < w)
+        wg_gemm_sub<R, 2, 1>(kb, nc, w - iend, Fm + i0 + (int64_t)iend * m, m, Y + iend + (int64_t)cs * w, w,
+                             Y + i0 + (int64_t)cs * w, w);
+      load_diag_block(Fm + i0 + (int64_t)i0 * m, m, kb, T);
+      solve_cols_upper(Y + i0 + (int64_t)cs * w, w, kb, nc, T, buf);
+    }
+  }
+}
+
+template <class R>
+__global__ __launch_bounds__(kFW) void split_ytiles_kernel(const FrontJob* __restrict__ jobs,
+                                                           const typename Fp<R>::C* __restrict__ ws,
+                                                           void* __restrict__ pb, int c64, int tile_rows) {
+  using F = Fp<R>;
+  using Cx = typename F::C;
+  const FrontJob J = jobs[blockIdx.x];
+  const int m = J.m, w = J.w, r0 = blockIdx.y * tile_rows;
+  if (r0 >= w) return;
+  const Cx* Y = ws + J.Y;
+  const int nr = min(tile_rows, w - r0), ncol = m - r0;
+  const int64_t off = J.pbo + bwd_tile_offset(m, w, tile_rows, r0);
+  const int64_t cnt = (int64_t)nr * ncol;
+  for (int64_t e = threadIdx.x; e < cnt; e += kFW) {
+    const int i = (int)(e % nr), row = r0 + i, col = r0 + (int)(e / nr);
+    put_entry(pb, off + e, (col < w && col < row) ? F::mk(0.0, 0.0) : Y[row + (int64_t)col * w], c64);
+  }
+}
+
+template <class R>
+void split_launch(const FrontJob* jobs, int njobs, int mmax, int wmax, void* ws, void* upd, const int32_t* asm_pos,
+                  const int32_t* asm_val, const double2* aval, const FrontChild* kids, const int32_t* ep,
+                  int32_t* piv, int32_t* swp, int32_t* npert, void* pf, void* pb, int c64, int tile_rows,
+                  hipStream_t s) {
+  using Cx = typename Fp<R>::C;
+  Cx* W = reinterpret_cast<Cx*>(ws);
+  Cx* U = reinterpret_cast<Cx*>(upd);
+  const unsigned ns = (unsigned)((mmax + kStrip - 1) / kStrip);
+  split_assemble_kernel<R><<<dim3(njobs, ns), kFW, 0, s>>>(jobs, W, U, asm_pos, asm_val, aval, kids, ep, piv, npert);
+  for (int k0 = 0; k0 < wmax; k0 += kNB) {
+    split_panel_kernel<R><<<njobs, kFW, 0, s>>>(jobs, W, piv, swp, npert, k0);
+    split_update_kernel<R><<<dim3(njobs, ns), kFW, 0, s>>>(jobs, W, swp, k0);
+  }
+  split_panels_kernel<R><<<dim3(njobs, 2 * ns), kFW, 0, s>>>(jobs, W, U, pf, c64, tile_rows, (int)ns);
+  split_ytiles_kernel<R><<<dim3(njobs, (unsigned)((wmax + tile_rows - 1) / tile_rows)), kFW, 0, s>>>(jobs, W, pb, c64,
+                                                                                                     tile_rows);
+}
+
 }  // namespace
 
 void factor_fronts(const FrontJob* jobs, int njobs, void* ws, void* upd, const int32_t* asm_pos,
@@ -491,6 +831,20 @@ void factor_fronts(const FrontJob* jobs, int njobs, void* ws, void* upd, const i
         jobs, reinterpret_cast<double2*>(ws), reinterpret_cast<double2*>(upd), asm_pos, asm_val, a, kids, ep, piv,
         npert, pf, pb, prec == FactorPrecision::kC128RoundedC64 ? 1 : 0, tile_rows);
   }
+}
+
+void factor_fronts_split(const FrontJob* jobs, int njobs, int mmax, int wmax, void* ws, void* upd,
+                         const int32_t* asm_pos, const int32_t* asm_val, const double* aval, const FrontChild* kids,
+                         const int32_t* ep, int32_t* piv, int32_t* swp, int32_t* npert, void* pf, void* pb,
+                         FactorPrecision prec, int tile_rows, hipStream_t s) {
+  if (njobs <= 0) return;
+  const double2* a = reinterpret_cast<const double2*>(aval);
+  if (prec == FactorPrecision::kC64)
+    split_launch<float>(jobs, njobs, mmax, wmax, ws, upd, asm_pos, asm_val, a, kids, ep, piv, swp, npert, pf, pb, 1,
+                        tile_rows, s);
+  else
+    split_launch<double>(jobs, njobs, mmax, wmax, ws, upd, asm_pos, asm_val, a, kids, ep, piv, swp, npert, pf, pb,
+                         prec == FactorPrecision::kC128RoundedC64 ? 1 : 0, tile_rows, s);
 }
 
 }  // namespace dev

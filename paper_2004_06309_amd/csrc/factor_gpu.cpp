@@ -82,6 +82,9 @@ void extend_add_map(const Symbolic& S, int32_t* ep) {
       for (int64_t a = S.sn_rptr[c]; a < S.sn_rptr[c + 1]; ++a) {
         if (fpos[S.rows[a]] < 0) fail(HELM_EINVAL, "internal: child row missing from parent front");
         ep[a] = fpos[S.rows[a]];
+        // sorted row lists map to increasing front positions (the split
+        // assembly relies on it)
+        if (a > S.sn_rptr[c] && ep[a] <= ep[a - 1]) fail(HELM_EINVAL, "internal: unsorted child rows");
       }
     for (int32_t k = 0; k < w; ++k) fpos[c0 + k] = -1;
     for (int32_t a = 0; a < r; ++a) fpos[R[a]] = -1;
@@ -91,7 +94,7 @@ void extend_add_map(const Symbolic& S, int32_t* ep) {
 }  // namespace
 
 void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<const Symbolic*>& Ss,
-                         dev::FactorPrecision prec,
+                         dev::FactorPrecision prec, int32_t split_min,
                          BatchDev& Dv, const std::vector<int64_t>& pf0, const std::vector<int64_t>& pb0,
                          std::vector<NumericOut>& num, int32_t& n_perturbed) {
   const int nm = (int)As.size();
@@ -243,17 +246,36 @@ void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<co
   }
   for (int i = 0; i < nm; ++i)
     if (Ss[i]->tile_rows != Ss[0]->tile_rows) fail(HELM_EINVAL, "internal: mixed tile heights in a batch");
+  // within each launch, the fronts of at least split_min rows first: they
+  // take the several-workgroups form (split_min < 0: none)
+  std::vector<int64_t> nsplit(launches.size(), 0);
+  std::vector<int32_t> mmax(launches.size(), 0), wmax(launches.size(), 0);
+  for (size_t q = 0; q < launches.size(); ++q) {
+    auto first = jobs.begin() + launches[q].first, last = jobs.begin() + launches[q].second;
+    auto mid = std::stable_partition(first, last,
+                                     [&](const dev::FrontJob& J) { return split_min >= 0 && J.m >= split_min; });
+    nsplit[q] = mid - first;
+    for (auto it = first; it != mid; ++it) {
+      mmax[q] = std::max(mmax[q], it->m);
+      wmax[q] = std::max(wmax[q], it->w);
+    }
+  }
   DVec<dev::FrontJob> jobs_d;
   jobs_d.upload(jobs);
   DVec<double> ws;
   ws.alloc(wpe * (size_t)budget);
-  DVec<int32_t> piv_d, npert_d;
+  DVec<int32_t> piv_d, swp_d, npert_d;
   piv_d.alloc(std::max<int64_t>(pos0[nm], 1));
+  swp_d.alloc(std::max<int64_t>(pos0[nm], 1));
   npert_d.alloc(std::max<size_t>(jobs.size(), 1));
-  for (auto& L : launches)
-    dev::factor_fronts(jobs_d.p + L.first, (int)(L.second - L.first), ws.p, upd.p, asm_pos.p, asm_val.p, aval.p,
-                       kids_d.p, ep_d.p, piv_d.p, npert_d.p + L.first, Dv.pf.p, Dv.pb.p, prec, Ss[0]->tile_rows,
-                       nullptr);
+  for (size_t q = 0; q < launches.size(); ++q) {
+    const int64_t f = launches[q].first, ns = nsplit[q], nj = launches[q].second - f;
+    dev::factor_fronts_split(jobs_d.p + f, (int)ns, mmax[q], wmax[q], ws.p, upd.p, asm_pos.p, asm_val.p, aval.p,
+                             kids_d.p, ep_d.p, piv_d.p, swp_d.p, npert_d.p + f, Dv.pf.p, Dv.pb.p, prec,
+                             Ss[0]->tile_rows, nullptr);
+    dev::factor_fronts(jobs_d.p + f + ns, (int)(nj - ns), ws.p, upd.p, asm_pos.p, asm_val.p, aval.p, kids_d.p,
+                       ep_d.p, piv_d.p, npert_d.p + f + ns, Dv.pf.p, Dv.pb.p, prec, Ss[0]->tile_rows, nullptr);
+  }
   HELM_HIP(hipGetLastError());
   HELM_HIP(hipDeviceSynchronize());
   std::vector<int32_t> piv(pos0[nm]), np(jobs.size());

@@ -452,8 +452,8 @@ namespace {
 // taken as the identity).
 void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symbolic*>& Ss,
                  const std::vector<const std::vector<int64_t>*>& in_idx, int device, bool numeric,
-                 dev::FactorPrecision prec, bool on_host, int64_t sn_jobs_min, BatchHost& B, BatchDev& Dv,
-                 int32_t& n_perturbed, double& seconds) {
+                 dev::FactorPrecision prec, int32_t split_min, bool on_host, int64_t sn_jobs_min, BatchHost& B,
+                 BatchDev& Dv, int32_t& n_perturbed, double& seconds) {
   const int nm = (int)As.size();
   const bool c64 = prec != dev::FactorPrecision::kC128;
   const size_t esz = c64 ? sizeof(std::complex<float>) : sizeof(cplx);
@@ -468,7 +468,7 @@ void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symb
   if (numeric && !on_host) {
     Dv.pf.alloc(esz * (size_t)pf0[nm]);
     Dv.pb.alloc(esz * (size_t)pb0[nm]);
-    factor_batch_device(As, Ss, prec, Dv, pf0, pb0, num, n_perturbed);
+    factor_batch_device(As, Ss, prec, split_min, Dv, pf0, pb0, num, n_perturbed);
   } else if (numeric) {
     Dv.pf.alloc(esz * (size_t)pf0[nm]);
     Dv.pb.alloc(esz * (size_t)pb0[nm]);
@@ -987,6 +987,9 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
   if (c64mode < 0 || c64mode > 2) fail(HELM_EINVAL, "factor_c64 must be 0, 1 or 2");
   const bool on_host = opts && opts->factor_on_host;
   const bool c64 = c64mode != 0;
+  const int32_t split_opt = opts ? opts->split_front_rows : 0;
+  if (split_opt < -1) fail(HELM_EINVAL, "split_front_rows must be -1, 0 or positive");
+  const int32_t split_min = split_opt == 0 ? dev::kSplitFrontMin : split_opt;
   // the host factorisation works in complex128 only (its complex64 panels
   // are rounded copies)
   const dev::FactorPrecision prec = !c64                      ? dev::FactorPrecision::kC128
@@ -1024,7 +1027,7 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
     int32_t np = 0;
     double fs = 0;
     build_batch(part(As, bnd[k], bnd[k + 1]), part(Ss, bnd[k], bnd[k + 1]), part(in, bnd[k], bnd[k + 1]), c.device,
-                on_device, prec, on_host, snb, fb, c.fine[k], np, fs);
+                on_device, prec, split_min, on_host, snb, fb, c.fine[k], np, fs);
     npert += np;
     fsec += fs;
     st.factor_entries += fb.nf + fb.nb;
@@ -1092,8 +1095,8 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
     std::iota(ident.begin(), ident.end(), 0);
     BatchHost cb;
     int32_t np2 = 0;
-    build_batch({&c.E}, {&c.Esym}, {&ident}, c.device, on_device, dev::FactorPrecision::kC128, on_host, snmin, cb,
-                c.coarse, np2, csec);
+    build_batch({&c.E}, {&c.Esym}, {&ident}, c.device, on_device, dev::FactorPrecision::kC128, split_min, on_host,
+                snmin, cb, c.coarse, np2, csec);
     npert += np2;
     c.two_level = true;
     st.n_coarse = (int32_t)c.E.n;

@@ -48,7 +48,7 @@ class PrecondOpts(C.Structure):
     _fields_ = [("leaf_size", C.c_int32), ("factor_c64", C.c_int32), ("coarse_leaf_size", C.c_int32),
                 ("tile_rows", C.c_int32), ("coarse_tile_rows", C.c_int32), ("factor_on_host", C.c_int32),
                 ("sn_jobs_min", C.c_int32), ("batches", C.c_int32), ("perturb_pivots", C.c_int32),
-                ("coarse_launch", C.c_int32)]
+                ("coarse_launch", C.c_int32), ("split_front_rows", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -262,7 +262,7 @@ class Helm:
 
     def precond_setup(self, part, n_sub, overlap, coarse_xyz=None, coarse_tets=None, leaf_size=0, c64=False,
                       coarse_leaf_size=0, tile_rows=0, coarse_tile_rows=0, factor_on_host=False, sn_jobs_min=0,
-                      batches=0, perturb_pivots=False, coarse_launch=0):
+                      batches=0, perturb_pivots=False, coarse_launch=0, split_front_rows=0):
         """helm_precond_setup: subdomains from the tet partition `part` with
         `overlap` layers, the optional P1 coarse mesh, then the factorisation.
         c64: complex64 factors (True or 1: factorised in complex64 on FP32
@@ -273,13 +273,15 @@ class Helm:
         sweeps run concurrently (0: 2); perturb_pivots: replace zero or tiny
         pivots and count them instead of failing with HELM_ESINGULAR;
         coarse_launch: 0 timed, 1 per-level launches, 2 one cooperative
-        launch for the coarse solve."""
+        launch for the coarse solve; split_front_rows: fronts of at least
+        this many rows factorised by several workgroups each (0: 256, -1:
+        never)."""
         part = np.ascontiguousarray(part, dtype=np.int32)
         if c64 not in (False, True, 0, 1, 2):
             raise ValueError("c64 must be False/True or 0, 1, 2")
         opts = PrecondOpts(int(leaf_size), int(c64), int(coarse_leaf_size), int(tile_rows),
                            int(coarse_tile_rows), 1 if factor_on_host else 0, int(sn_jobs_min), int(batches),
-                           1 if perturb_pivots else 0, int(coarse_launch))
+                           1 if perturb_pivots else 0, int(coarse_launch), int(split_front_rows))
         cm = None
         if coarse_xyz is not None:
             cm, keep = _mesh(coarse_xyz, coarse_tets, 1)

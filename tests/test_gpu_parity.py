@@ -569,6 +569,32 @@ def test_one_wave_supernode_jobs(name):
     say(f"[snjobs] {name}: its={info[0]['iterations']} block={info16[5]['iterations']} oracle={ro.iterations}")
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("name", ["small_p2_2lvl", "adapted_p2_2lvl", "mid_quarter_2lvl"])
+def test_split_fronts_match_one_workgroup_fronts(name, mode):
+    """Fronts spread over several workgroups (every front, including the
+    coarse ones, with split_front_rows=1) against one workgroup per front
+    (-1): each entry goes through the same operations in the same order, so
+    the local and coarse solves agree bit for bit; the default threshold
+    gives the same; and the result meets the oracle."""
+    w = WORKLOADS[name]()
+    P, b, M = opre.build(w)
+    hs = helm.from_workload(w, c64=mode, split_front_rows=1)
+    h1 = helm.from_workload(w, c64=mode, split_front_rows=-1)
+    hd = helm.from_workload(w, c64=mode)
+    assert hs.stats()["n_perturbed"] == 0 and hs.stats()["factor_c64"] == mode
+    r = dvec(rand_vec(P.n, 37))
+    zs, z1, zd = (torch.empty_like(r) for _ in range(3))
+    for f in ("apply_oras", "apply_coarse") if M.Z is not None else ("apply_oras",):
+        getattr(hs, f)(r, zs)
+        getattr(h1, f)(r, z1)
+        getattr(hd, f)(r, zd)
+        say(f"[split] {name} mode {mode} {f}: max |split - one-wg| {float((zs - z1).abs().max()):.3e}")
+        assert torch.equal(zs, z1) and torch.equal(zd, z1)
+    hs.apply_oras(r, zs)
+    assert rel(host(zs), M.one_level(host(r))) <= (1e-9 if mode == 0 else C64_APPLY_TOL[1])
+
+
 @pytest.mark.parametrize("name", ["tiny", "ragged_p2", "mid_quarter_2lvl"])
 def test_device_factorisation_matches_host(name):
     """The numeric factorisation on the device (multifrontal, MFMA Schur
