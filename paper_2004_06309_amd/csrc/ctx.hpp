@@ -287,15 +287,14 @@ size_t width_bytes(const Ctx& c, int m, int S);
 void ensure_bases(Ctx& c, int m, int count);
 void ensure_width(Ctx& c, int m, int S);
 
-// factor_gpu.cpp: numeric factorisation of a batch on the device, panels
-// written into Dv.pf / Dv.pb (allocated by the caller) at the per-matrix
-// offsets pf0 / pb0 (complex64 unless prec is kC128); pivots returned in
-// num.  Fronts of at least split_min rows (none if negative) are factorised
-// by several workgroups each.
+// factor_gpu.cpp: numeric factorisation of a set of matrices on the device,
+// the panels of matrix i written from pf[i] / pb[i] on (device memory
+// allocated by the caller; complex64 unless prec is kC128); pivots returned
+// in num.  Fronts of at least split_min rows (none if negative) are
+// factorised by several workgroups each.
 void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<const Symbolic*>& Ss,
-                         dev::FactorPrecision prec, int32_t split_min,
-                         BatchDev& Dv, const std::vector<int64_t>& pf0, const std::vector<int64_t>& pb0,
-                         std::vector<NumericOut>& num, int32_t& n_perturbed);
+                         dev::FactorPrecision prec, int32_t split_min, const std::vector<void*>& pf,
+                         const std::vector<void*>& pb, std::vector<NumericOut>& num, int32_t& n_perturbed);
 
 // solver.cpp
 void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<const std::vector<int64_t>*>& in_idx,

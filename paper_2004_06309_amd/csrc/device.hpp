@@ -103,7 +103,9 @@ constexpr int kLevelChunkMax = 2048;
 struct FrontJob {
   int64_t F, X, Y;     // front (m x m), forward panel X (m x w), backward panel Y (w x m) in the workspace
   int64_t upd;         // Schur complement (r x r) in the update buffer
-  int64_t pfo, pbo;    // first forward / backward tile entry in the panel arrays
+  void* pf;            // forward / backward panel arrays of the job's matrix
+  void* pb;            //   (complex128 or complex64 entries)
+  int64_t pfo, pbo;    // first forward / backward tile entry in those arrays
   int64_t asm0, asm1;  // range of the front's original entries in the assembly lists
   int32_t m, w;        // front order, fully-summed columns
   int32_t c0;          // first column of the supernode in its matrix
@@ -121,9 +123,9 @@ struct FrontChild {
 // the scatter lists (F[asm_pos[q]] = aval[asm_val[q]]) and the children,
 // partial LU, Schur complement into upd, pivots into piv (batch positions),
 // zero-pivot replacements per job into npert, explicit-inverse panels into
-// the solve tiles of pf / pb.  ws holds each job's F, X and Y; ws and upd
-// hold complex entries of the working precision (complex64 for kC64,
-// complex128 otherwise); aval is complex128.
+// the solve tiles of each job's pf / pb.  ws holds each job's F, X and Y;
+// ws and upd hold complex entries of the working precision (complex64 for
+// kC64, complex128 otherwise); aval is complex128.
 enum class FactorPrecision {
   kC128,            // complex128 arithmetic, complex128 panels
   kC128RoundedC64,  // complex128 arithmetic, panels rounded once to complex64
@@ -131,8 +133,7 @@ enum class FactorPrecision {
 };
 void factor_fronts(const FrontJob* jobs, int njobs, void* ws, void* upd, const int32_t* asm_pos,
                    const int32_t* asm_val, const double* aval, const FrontChild* kids, const int32_t* ep,
-                   int32_t* piv, int32_t* npert, void* pf, void* pb, FactorPrecision prec, int tile_rows,
-                   hipStream_t s);
+                   int32_t* piv, int32_t* npert, FactorPrecision prec, int tile_rows, hipStream_t s);
 // The same for fronts factorised by several workgroups each, in a sequence
 // of launches (assembly by column strips; per 32-column block a one-
 // workgroup panel step and a column-strip update step; the X / Y panels by
@@ -142,8 +143,8 @@ void factor_fronts(const FrontJob* jobs, int njobs, void* ws, void* upd, const i
 // positions.  Same results as factor_fronts.
 void factor_fronts_split(const FrontJob* jobs, int njobs, int mmax, int wmax, void* ws, void* upd,
                          const int32_t* asm_pos, const int32_t* asm_val, const double* aval, const FrontChild* kids,
-                         const int32_t* ep, int32_t* piv, int32_t* swp, int32_t* npert, void* pf, void* pb,
-                         FactorPrecision prec, int tile_rows, hipStream_t s);
+                         const int32_t* ep, int32_t* piv, int32_t* swp, int32_t* npert, FactorPrecision prec,
+                         int tile_rows, hipStream_t s);
 // Fronts of at least this many rows take factor_fronts_split by default.
 constexpr int kSplitFrontMin = 256;
 

@@ -242,7 +242,9 @@ __device__ void solve_cols_upper(C* G, int64_t ld, int kb, int ncols, const C* T
   }
 }
 
-// (value, index) maximum over the workgroup; ties go to the lower index.
+// (value, index) maximum over the workgroup of NT threads; ties go to the
+// lower index.
+template <int NT = kFW>
 __device__ void wg_argmax(double& v, int& idx, double* sv, int* si) {
   for (int o = 32; o > 0; o >>= 1) {
     const double ov = __shfl_xor(v, o, 64);
@@ -260,7 +262,7 @@ __device__ void wg_argmax(double& v, int& idx, double* sv, int* si) {
   __syncthreads();
   v = sv[0];
   idx = si[0];
-  for (int q = 1; q < kFW / 64; ++q)
+  for (int q = 1; q < NT / 64; ++q)
     if (sv[q] > v || (sv[q] == v && si[q] < idx)) {
       v = sv[q];
       idx = si[q];
@@ -290,8 +292,7 @@ __global__ __launch_bounds__(kFW) void front_kernel(const FrontJob* __restrict__
                                                     const double2* __restrict__ aval,
                                                     const FrontChild* __restrict__ kids,
                                                     const int32_t* __restrict__ ep, int32_t* __restrict__ piv,
-                                                    int32_t* __restrict__ npert, void* __restrict__ pf,
-                                                    void* __restrict__ pb, int c64, int tile_rows) {
+                                                    int32_t* __restrict__ npert, int c64, int tile_rows) {
   using F = Fp<R>;
   using Cx = typename F::C;
   __shared__ Cx T[kNB * kNB];
@@ -302,6 +303,8 @@ __global__ __launch_bounds__(kFW) void front_kernel(const FrontJob* __restrict__
   const int tid = threadIdx.x;
   const int m = J.m, w = J.w, r = m - w;
   const int64_t mm = (int64_t)m * m;
+  void* pf = J.pf;
+  void* pb = J.pb;
   Cx* Fm = ws + J.F;
 
   // 1. assembly
@@ -558,15 +561,18 @@ __global__ __launch_bounds__(kFW) void split_assemble_kernel(
   }
 }
 
+// The panel step runs on kPW threads: its column loops are latency bound.
+constexpr int kPW = 1024;
+
 template <class R>
-__global__ __launch_bounds__(kFW) void split_panel_kernel(const FrontJob* __restrict__ jobs,
+__global__ __launch_bounds__(kPW) void split_panel_kernel(const FrontJob* __restrict__ jobs,
                                                           typename Fp<R>::C* __restrict__ ws,
                                                           int32_t* __restrict__ piv, int32_t* __restrict__ swp,
                                                           int32_t* __restrict__ npert, int k0) {
   using F = Fp<R>;
   using Cx = typename F::C;
-  __shared__ double sv[kFW / 64];
-  __shared__ int si[kFW / 64];
+  __shared__ double sv[kPW / 64];
+  __shared__ int si[kPW / 64];
   const FrontJob J = jobs[blockIdx.x];
   const int tid = threadIdx.x, m = J.m, w = J.w;
   if (k0 >= w) return;
@@ -579,14 +585,14 @@ __global__ __launch_bounds__(kFW) void split_panel_kernel(const FrontJob* __rest
     Cx* colk = Fm + (int64_t)k * m;
     double best = -1.0;
     int p = k;
-    for (int i = k + tid; i < w; i += kFW) {
+    for (int i = k + tid; i < w; i += kPW) {
       const double a = hypot((double)colk[i].x, (double)colk[i].y);
       if (a > best) {
         best = a;
         p = i;
       }
     }
-    wg_argmax(best, p, sv, si);
+    wg_argmax<kPW>(best, p, sv, si);
     if (p != k) {
       if (tid < kb) {
         const int64_t j = k0 + tid;
@@ -608,7 +614,7 @@ __global__ __launch_bounds__(kFW) void split_panel_kernel(const FrontJob* __rest
       __syncthreads();
     }
     const Cx d = colk[k];
-    for (int i = k + 1 + tid; i < m; i += kFW) {
+    for (int i = k + 1 + tid; i < m; i += kPW) {
       const Cx l = cdivd(colk[i], d);
       colk[i] = l;
       for (int j = k + 1; j < k0 + kb; ++j) csub_mul(Fm[i + (int64_t)j * m], l, Fm[k + (int64_t)j * m]);
@@ -688,8 +694,8 @@ __device__ __forceinline__ void put_entry(void* dst, int64_t at, C v, int c64) {
 template <class R>
 __global__ __launch_bounds__(kFW) void split_panels_kernel(const FrontJob* __restrict__ jobs,
                                                            typename Fp<R>::C* __restrict__ ws,
-                                                           typename Fp<R>::C* __restrict__ upd, void* __restrict__ pf,
-                                                           int c64, int tile_rows, int sx) {
+                                                           typename Fp<R>::C* __restrict__ upd, int c64,
+                                                           int tile_rows, int sx) {
   using F = Fp<R>;
   using Cx = typename F::C;
   __shared__ Cx T[kNB * kNB];
@@ -742,7 +748,7 @@ __global__ __launch_bounds__(kFW) void split_panels_kernel(const FrontJob* __res
       const int64_t cnt = (int64_t)nr * nc;
       for (int64_t e = tid; e < cnt; e += kFW) {
         const int i = (int)(e % nr), col = (int)(e / nr), row = r0 + i;
-        put_entry(pf, off + e, (row < w && col > row) ? F::mk(0.0, 0.0) : X[row + (int64_t)col * m], c64);
+        put_entry(J.pf, off + e, (row < w && col > row) ? F::mk(0.0, 0.0) : X[row + (int64_t)col * m], c64);
       }
     }
   } else {
@@ -779,7 +785,7 @@ __global__ __launch_bounds__(kFW) void split_panels_kernel(const FrontJob* __res
 template <class R>
 __global__ __launch_bounds__(kFW) void split_ytiles_kernel(const FrontJob* __restrict__ jobs,
                                                            const typename Fp<R>::C* __restrict__ ws,
-                                                           void* __restrict__ pb, int c64, int tile_rows) {
+                                                           int c64, int tile_rows) {
   using F = Fp<R>;
   using Cx = typename F::C;
   const FrontJob J = jobs[blockIdx.x];
@@ -791,14 +797,14 @@ __global__ __launch_bounds__(kFW) void split_ytiles_kernel(const FrontJob* __res
   const int64_t cnt = (int64_t)nr * ncol;
   for (int64_t e = threadIdx.x; e < cnt; e += kFW) {
     const int i = (int)(e % nr), row = r0 + i, col = r0 + (int)(e / nr);
-    put_entry(pb, off + e, (col < w && col < row) ? F::mk(0.0, 0.0) : Y[row + (int64_t)col * w], c64);
+    put_entry(J.pb, off + e, (col < w && col < row) ? F::mk(0.0, 0.0) : Y[row + (int64_t)col * w], c64);
   }
 }
 
 template <class R>
 void split_launch(const FrontJob* jobs, int njobs, int mmax, int wmax, void* ws, void* upd, const int32_t* asm_pos,
                   const int32_t* asm_val, const double2* aval, const FrontChild* kids, const int32_t* ep,
-                  int32_t* piv, int32_t* swp, int32_t* npert, void* pf, void* pb, int c64, int tile_rows,
+                  int32_t* piv, int32_t* swp, int32_t* npert, int c64, int tile_rows,
                   hipStream_t s) {
   using Cx = typename Fp<R>::C;
   Cx* W = reinterpret_cast<Cx*>(ws);
@@ -806,11 +812,11 @@ void split_launch(const FrontJob* jobs, int njobs, int mmax, int wmax, void* ws,
   const unsigned ns = (unsigned)((mmax + kStrip - 1) / kStrip);
   split_assemble_kernel<R><<<dim3(njobs, ns), kFW, 0, s>>>(jobs, W, U, asm_pos, asm_val, aval, kids, ep, piv, npert);
   for (int k0 = 0; k0 < wmax; k0 += kNB) {
-    split_panel_kernel<R><<<njobs, kFW, 0, s>>>(jobs, W, piv, swp, npert, k0);
+    split_panel_kernel<R><<<njobs, kPW, 0, s>>>(jobs, W, piv, swp, npert, k0);
     split_update_kernel<R><<<dim3(njobs, ns), kFW, 0, s>>>(jobs, W, swp, k0);
   }
-  split_panels_kernel<R><<<dim3(njobs, 2 * ns), kFW, 0, s>>>(jobs, W, U, pf, c64, tile_rows, (int)ns);
-  split_ytiles_kernel<R><<<dim3(njobs, (unsigned)((wmax + tile_rows - 1) / tile_rows)), kFW, 0, s>>>(jobs, W, pb, c64,
+  split_panels_kernel<R><<<dim3(njobs, 2 * ns), kFW, 0, s>>>(jobs, W, U, c64, tile_rows, (int)ns);
+  split_ytiles_kernel<R><<<dim3(njobs, (unsigned)((wmax + tile_rows - 1) / tile_rows)), kFW, 0, s>>>(jobs, W, c64,
                                                                                                      tile_rows);
 }
 
@@ -818,32 +824,32 @@ void split_launch(const FrontJob* jobs, int njobs, int mmax, int wmax, void* ws,
 
 void factor_fronts(const FrontJob* jobs, int njobs, void* ws, void* upd, const int32_t* asm_pos,
                    const int32_t* asm_val, const double* aval, const FrontChild* kids, const int32_t* ep,
-                   int32_t* piv, int32_t* npert, void* pf, void* pb, FactorPrecision prec, int tile_rows,
+                   int32_t* piv, int32_t* npert, FactorPrecision prec, int tile_rows,
                    hipStream_t s) {
   if (njobs <= 0) return;
   const double2* a = reinterpret_cast<const double2*>(aval);
   if (prec == FactorPrecision::kC64) {
     front_kernel<float><<<(unsigned)njobs, kFW, 0, s>>>(jobs, reinterpret_cast<float2*>(ws),
                                                         reinterpret_cast<float2*>(upd), asm_pos, asm_val, a, kids, ep,
-                                                        piv, npert, pf, pb, 1, tile_rows);
+                                                        piv, npert, 1, tile_rows);
   } else {
     front_kernel<double><<<(unsigned)njobs, kFW, 0, s>>>(
         jobs, reinterpret_cast<double2*>(ws), reinterpret_cast<double2*>(upd), asm_pos, asm_val, a, kids, ep, piv,
-        npert, pf, pb, prec == FactorPrecision::kC128RoundedC64 ? 1 : 0, tile_rows);
+        npert, prec == FactorPrecision::kC128RoundedC64 ? 1 : 0, tile_rows);
   }
 }
 
 void factor_fronts_split(const FrontJob* jobs, int njobs, int mmax, int wmax, void* ws, void* upd,
                          const int32_t* asm_pos, const int32_t* asm_val, const double* aval, const FrontChild* kids,
-                         const int32_t* ep, int32_t* piv, int32_t* swp, int32_t* npert, void* pf, void* pb,
+                         const int32_t* ep, int32_t* piv, int32_t* swp, int32_t* npert,
                          FactorPrecision prec, int tile_rows, hipStream_t s) {
   if (njobs <= 0) return;
   const double2* a = reinterpret_cast<const double2*>(aval);
   if (prec == FactorPrecision::kC64)
-    split_launch<float>(jobs, njobs, mmax, wmax, ws, upd, asm_pos, asm_val, a, kids, ep, piv, swp, npert, pf, pb, 1,
+    split_launch<float>(jobs, njobs, mmax, wmax, ws, upd, asm_pos, asm_val, a, kids, ep, piv, swp, npert, 1,
                         tile_rows, s);
   else
-    split_launch<double>(jobs, njobs, mmax, wmax, ws, upd, asm_pos, asm_val, a, kids, ep, piv, swp, npert, pf, pb,
+    split_launch<double>(jobs, njobs, mmax, wmax, ws, upd, asm_pos, asm_val, a, kids, ep, piv, swp, npert,
                          prec == FactorPrecision::kC128RoundedC64 ? 1 : 0, tile_rows, s);
 }
 

@@ -94,9 +94,8 @@ void extend_add_map(const Symbolic& S, int32_t* ep) {
 }  // namespace
 
 void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<const Symbolic*>& Ss,
-                         dev::FactorPrecision prec, int32_t split_min,
-                         BatchDev& Dv, const std::vector<int64_t>& pf0, const std::vector<int64_t>& pb0,
-                         std::vector<NumericOut>& num, int32_t& n_perturbed) {
+                         dev::FactorPrecision prec, int32_t split_min, const std::vector<void*>& pf,
+                         const std::vector<void*>& pb, std::vector<NumericOut>& num, int32_t& n_perturbed) {
   const int nm = (int)As.size();
   std::vector<int64_t> pos0(nm + 1, 0), sn0(nm + 1, 0), rows0(nm + 1, 0), nnz0(nm + 1, 0);
   for (int i = 0; i < nm; ++i) {
@@ -228,8 +227,10 @@ void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<co
       J.X = used + (int64_t)m * m;
       J.Y = J.X + (int64_t)m * w;
       J.upd = uoff[sn0[i] + s];
-      J.pfo = pf0[i] + S.sn_fwd_off[s];
-      J.pbo = pb0[i] + S.sn_bwd_off[s];
+      J.pf = pf[i];
+      J.pb = pb[i];
+      J.pfo = S.sn_fwd_off[s];
+      J.pbo = S.sn_bwd_off[s];
       J.asm0 = asm0[i] + sptr[i][s];
       J.asm1 = asm0[i] + sptr[i][s + 1];
       J.m = m;
@@ -271,10 +272,9 @@ void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<co
   for (size_t q = 0; q < launches.size(); ++q) {
     const int64_t f = launches[q].first, ns = nsplit[q], nj = launches[q].second - f;
     dev::factor_fronts_split(jobs_d.p + f, (int)ns, mmax[q], wmax[q], ws.p, upd.p, asm_pos.p, asm_val.p, aval.p,
-                             kids_d.p, ep_d.p, piv_d.p, swp_d.p, npert_d.p + f, Dv.pf.p, Dv.pb.p, prec,
-                             Ss[0]->tile_rows, nullptr);
+                             kids_d.p, ep_d.p, piv_d.p, swp_d.p, npert_d.p + f, prec, Ss[0]->tile_rows, nullptr);
     dev::factor_fronts(jobs_d.p + f + ns, (int)(nj - ns), ws.p, upd.p, asm_pos.p, asm_val.p, aval.p, kids_d.p,
-                       ep_d.p, piv_d.p, npert_d.p + f + ns, Dv.pf.p, Dv.pb.p, prec, Ss[0]->tile_rows, nullptr);
+                       ep_d.p, piv_d.p, npert_d.p + f + ns, prec, Ss[0]->tile_rows, nullptr);
   }
   HELM_HIP(hipGetLastError());
   HELM_HIP(hipDeviceSynchronize());

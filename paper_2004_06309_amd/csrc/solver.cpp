@@ -447,13 +447,32 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
 
 namespace {
 
+// Panel arrays of a batch (factorisation order: matrix after matrix) and
+// the device pointers of each matrix's first forward / backward entry.
+void alloc_panels(const std::vector<const Symbolic*>& Ss, dev::FactorPrecision prec, BatchDev& Dv,
+                  std::vector<void*>& pf, std::vector<void*>& pb) {
+  const size_t esz = prec != dev::FactorPrecision::kC128 ? sizeof(std::complex<float>) : sizeof(cplx);
+  int64_t nf = 0, nb = 0;
+  for (const Symbolic* S : Ss) nf += S->fwd_entries, nb += S->bwd_entries;
+  Dv.pf.alloc(esz * (size_t)nf);
+  Dv.pb.alloc(esz * (size_t)nb);
+  nf = nb = 0;
+  for (const Symbolic* S : Ss) {
+    pf.push_back(Dv.pf.p + esz * nf);
+    pb.push_back(Dv.pb.p + esz * nb);
+    nf += S->fwd_entries;
+    nb += S->bwd_entries;
+  }
+}
+
 // Factors a batch (on the device, or on the host with one matrix per thread)
 // into the device panels; without a device only the layout is built (pivots
-// taken as the identity).
+// taken as the identity).  With pre, the device panels were allocated by
+// alloc_panels and factorised already, pre holding the pivots.
 void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symbolic*>& Ss,
                  const std::vector<const std::vector<int64_t>*>& in_idx, int device, bool numeric,
                  dev::FactorPrecision prec, int32_t split_min, bool on_host, int64_t sn_jobs_min, BatchHost& B,
-                 BatchDev& Dv, int32_t& n_perturbed, double& seconds) {
+                 BatchDev& Dv, int32_t& n_perturbed, double& seconds, const std::vector<NumericOut>* pre = nullptr) {
   const int nm = (int)As.size();
   const bool c64 = prec != dev::FactorPrecision::kC128;
   const size_t esz = c64 ? sizeof(std::complex<float>) : sizeof(cplx);
@@ -465,10 +484,12 @@ void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symb
   }
   std::vector<NumericOut> num(nm);
   const auto t0 = std::chrono::steady_clock::now();
-  if (numeric && !on_host) {
-    Dv.pf.alloc(esz * (size_t)pf0[nm]);
-    Dv.pb.alloc(esz * (size_t)pb0[nm]);
-    factor_batch_device(As, Ss, prec, split_min, Dv, pf0, pb0, num, n_perturbed);
+  if (pre) {
+    num = *pre;
+  } else if (numeric && !on_host) {
+    std::vector<void*> pf, pb;
+    alloc_panels(Ss, prec, Dv, pf, pb);
+    factor_batch_device(As, Ss, prec, split_min, pf, pb, num, n_perturbed);
   } else if (numeric) {
     Dv.pf.alloc(esz * (size_t)pf0[nm]);
     Dv.pb.alloc(esz * (size_t)pb0[nm]);
@@ -1022,12 +1043,30 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
   c.nbatch = nb;
   st.factor_entries = 0;
   int64_t npos_all = 0;
+  // on the device all subdomains are factorised together (every level's
+  // fronts of every batch in the same launches), each into its batch's
+  // panel arrays
+  std::vector<NumericOut> num_all;
+  if (on_device && !on_host) {
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<void*> pf, pb;
+    for (int32_t k = 0; k < nb; ++k) {
+      c.fine[k].pf.reset();
+      c.fine[k].pb.reset();
+      alloc_panels(part(Ss, bnd[k], bnd[k + 1]), prec, c.fine[k], pf, pb);
+    }
+    num_all.resize(n_sub);
+    factor_batch_device(As, Ss, prec, split_min, pf, pb, num_all, npert);
+    fsec += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
   for (int32_t k = 0; k < nb; ++k) {
     BatchHost fb;
     int32_t np = 0;
     double fs = 0;
+    std::vector<NumericOut> pre;
+    if (!num_all.empty()) pre.assign(num_all.begin() + bnd[k], num_all.begin() + bnd[k + 1]);
     build_batch(part(As, bnd[k], bnd[k + 1]), part(Ss, bnd[k], bnd[k + 1]), part(in, bnd[k], bnd[k + 1]), c.device,
-                on_device, prec, split_min, on_host, snb, fb, c.fine[k], np, fs);
+                on_device, prec, split_min, on_host, snb, fb, c.fine[k], np, fs, num_all.empty() ? nullptr : &pre);
     npert += np;
     fsec += fs;
     st.factor_entries += fb.nf + fb.nb;
