@@ -92,7 +92,10 @@ __device__ __forceinline__ C cdivd(C a, C d) {
 // workgroup: each wave computes (16 RB) x (16 CB) output tiles as RB x CB
 // MFMA blocks.  The MFMA computes the transposed block C^T = B^T A^T, so the
 // 16 lanes that share an accumulator column hold 16 consecutive rows of C
-// (coalesced read-modify-write).  16x16x4 operand layout: lane l holds
+// (coalesced loads and stores).  The accumulators start from C and the
+// products enter negated, so C is read once, before the first product, and
+// written once; the operands of the next 4-wide k step are loaded while the
+// MFMAs of the current one run.  16x16x4 operand layout: lane l holds
 // A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator register j of lane l
 // is D[Fp<R>::drow(l / 16, j)][l % 16].
 template <class R, int RB = 2, int CB = 2>
@@ -108,31 +111,46 @@ __device__ void wg_gemm_sub(int M, int N, int K, const typename Fp<R>::C* A, int
     const int r0 = (t % tm) * TR, c0 = (t / tm) * TC;
     V4 dre[CB][RB], dim[CB][RB];
 #pragma unroll
-    for (int a = 0; a < CB; ++a)
+    for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-      for (int b = 0; b < RB; ++b) dre[a][b] = dim[a][b] = V4{0, 0, 0, 0};
-    for (int k0 = 0; k0 < K; k0 += 4) {
-      const int k = k0 + hi;
-      Cx av[RB], bv[CB];
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int col = c0 + 16 * cb + F::drow(hi, j), row = r0 + 16 * rb + lo;
+          const Cx c = (row < M && col < N) ? C[row + (int64_t)col * ldc] : F::mk(0.0, 0.0);
+          dre[cb][rb][j] = c.x;
+          dim[cb][rb][j] = c.y;
+        }
+    Cx av[RB], bv[CB];
+    auto load = [&](int k, Cx* a, Cx* b) {
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) {
         const int row = r0 + 16 * rb + lo;
-        av[rb] = (row < M && k < K) ? A[row + (int64_t)k * lda] : F::mk(0.0, 0.0);
+        a[rb] = (row < M && k < K) ? A[row + (int64_t)k * lda] : F::mk(0.0, 0.0);
       }
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) {
         const int col = c0 + 16 * cb + lo;
-        bv[cb] = (col < N && k < K) ? B[k + (int64_t)col * ldb] : F::mk(0.0, 0.0);
+        b[cb] = (col < N && k < K) ? B[k + (int64_t)col * ldb] : F::mk(0.0, 0.0);
       }
+    };
+    load(hi, av, bv);
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      Cx an[RB], bn[CB];
+      load(k0 + 4 + hi, an, bn);
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
-          dre[cb][rb] = F::mma(bv[cb].x, av[rb].x, dre[cb][rb]);
-          dre[cb][rb] = F::mma(-bv[cb].y, av[rb].y, dre[cb][rb]);
-          dim[cb][rb] = F::mma(bv[cb].x, av[rb].y, dim[cb][rb]);
-          dim[cb][rb] = F::mma(bv[cb].y, av[rb].x, dim[cb][rb]);
+          dre[cb][rb] = F::mma(-bv[cb].x, av[rb].x, dre[cb][rb]);
+          dre[cb][rb] = F::mma(bv[cb].y, av[rb].y, dre[cb][rb]);
+          dim[cb][rb] = F::mma(-bv[cb].x, av[rb].y, dim[cb][rb]);
+          dim[cb][rb] = F::mma(-bv[cb].y, av[rb].x, dim[cb][rb]);
         }
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) av[rb] = an[rb];
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) bv[cb] = bn[cb];
     }
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb)
@@ -142,9 +160,10 @@ __device__ void wg_gemm_sub(int M, int N, int K, const typename Fp<R>::C* A, int
         for (int j = 0; j < 4; ++j) {
           const int col = c0 + 16 * cb + F::drow(hi, j), row = r0 + 16 * rb + lo;
           if (row < M && col < N) {
-            Cx& c = C[row + (int64_t)col * ldc];
-            c.x -= dre[cb][rb][j];
-            c.y -= dim[cb][rb][j];
+            Cx c;
+            c.x = dre[cb][rb][j];
+            c.y = dim[cb][rb][j];
+            C[row + (int64_t)col * ldc] = c;
           }
         }
   }

@@ -576,12 +576,16 @@ def test_split_fronts_match_one_workgroup_fronts(name, mode):
     coarse ones, with split_front_rows=1) against one workgroup per front
     (-1): each entry goes through the same operations in the same order, so
     the local and coarse solves agree bit for bit; the default threshold
-    gives the same; and the result meets the oracle."""
+    gives the same; and the result meets the oracle.  The coarse correction
+    is compared to rounding only: the lanes per row of its restriction and
+    prolongation products are timed at setup, so two contexts may sum them
+    in different orders (the coarse solve form is fixed for the same
+    reason)."""
     w = WORKLOADS[name]()
     P, b, M = opre.build(w)
-    hs = helm.from_workload(w, c64=mode, split_front_rows=1)
-    h1 = helm.from_workload(w, c64=mode, split_front_rows=-1)
-    hd = helm.from_workload(w, c64=mode)
+    hs = helm.from_workload(w, c64=mode, split_front_rows=1, coarse_launch=1)
+    h1 = helm.from_workload(w, c64=mode, split_front_rows=-1, coarse_launch=1)
+    hd = helm.from_workload(w, c64=mode, coarse_launch=1)
     assert hs.stats()["n_perturbed"] == 0 and hs.stats()["factor_c64"] == mode
     r = dvec(rand_vec(P.n, 37))
     zs, z1, zd = (torch.empty_like(r) for _ in range(3))
@@ -590,7 +594,10 @@ def test_split_fronts_match_one_workgroup_fronts(name, mode):
         getattr(h1, f)(r, z1)
         getattr(hd, f)(r, zd)
         say(f"[split] {name} mode {mode} {f}: max |split - one-wg| {float((zs - z1).abs().max()):.3e}")
-        assert torch.equal(zs, z1) and torch.equal(zd, z1)
+        if f == "apply_oras":
+            assert torch.equal(zs, z1) and torch.equal(zd, z1)
+        else:
+            assert rel(host(zs), host(z1)) <= 1e-14 and rel(host(zd), host(z1)) <= 1e-14
     hs.apply_oras(r, zs)
     assert rel(host(zs), M.one_level(host(r))) <= (1e-9 if mode == 0 else C64_APPLY_TOL[1])
 
