@@ -225,6 +225,11 @@ typedef struct helm_precond_stats {
   double factor_seconds;   /* wall time of the numeric factorisation       */
   int32_t batches;         /* subdomain batches (1 .. 4)                   */
   int32_t reserved;
+  double factor_scratch_bytes;  /* device memory the numeric factorisation
+                              held besides the panels (fronts, Schur
+                              complements, inputs), peak over the fine and
+                              coarse factorisations; freed when setup
+                              returns                                      */
 } helm_precond_stats;
 
 /* Create a context on HIP device `device_ordinal`; -1 creates a host-only

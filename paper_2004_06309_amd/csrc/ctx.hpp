@@ -291,10 +291,12 @@ void ensure_width(Ctx& c, int m, int S);
 // the panels of matrix i written from pf[i] / pb[i] on (device memory
 // allocated by the caller; complex64 unless prec is kC128); pivots returned
 // in num.  Fronts of at least split_min rows (none if negative) are
-// factorised by several workgroups each.
+// factorised by several workgroups each.  scratch_bytes: the device memory
+// it held besides the panels.
 void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<const Symbolic*>& Ss,
                          dev::FactorPrecision prec, int32_t split_min, const std::vector<void*>& pf,
-                         const std::vector<void*>& pb, std::vector<NumericOut>& num, int32_t& n_perturbed);
+                         const std::vector<void*>& pb, std::vector<NumericOut>& num, int32_t& n_perturbed,
+                         double& scratch_bytes);
 
 // solver.cpp
 void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<const std::vector<int64_t>*>& in_idx,

@@ -4,6 +4,7 @@
 #include <omp.h>
 
 #include <algorithm>
+#include <map>
 #include <numeric>
 
 #include "ctx.hpp"
@@ -95,7 +96,8 @@ void extend_add_map(const Symbolic& S, int32_t* ep) {
 
 void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<const Symbolic*>& Ss,
                          dev::FactorPrecision prec, int32_t split_min, const std::vector<void*>& pf,
-                         const std::vector<void*>& pb, std::vector<NumericOut>& num, int32_t& n_perturbed) {
+                         const std::vector<void*>& pb, std::vector<NumericOut>& num, int32_t& n_perturbed,
+                         double& scratch_bytes) {
   const int nm = (int)As.size();
   std::vector<int64_t> pos0(nm + 1, 0), sn0(nm + 1, 0), rows0(nm + 1, 0), nnz0(nm + 1, 0);
   for (int i = 0; i < nm; ++i) {
@@ -151,22 +153,74 @@ void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<co
     ep_d.upload(ep);
   }
 
-  // Schur complement offsets, children lists, levels
+  // Schur complement offsets, children lists, levels.  A supernode's Schur
+  // complement (r x r) is live from its own level (its height in the
+  // elimination tree) until its parent's level has assembled it; offsets
+  // come from a first-fit arena run level by level (a level's new
+  // complements are placed before the ones it consumes are released), so
+  // the buffer holds the largest set live at once instead of all of them.
   const int64_t nsn = sn0[nm];
-  std::vector<int64_t> uoff(nsn + 1, 0);
   int32_t H = 0;
+  for (int i = 0; i < nm; ++i)
+    for (int32_t s = 0; s < Ss[i]->nsn; ++s) H = std::max(H, Ss[i]->height[s]);
+  std::vector<std::vector<std::pair<int, int32_t>>> levels(H + 1);
+  std::vector<std::vector<int64_t>> release(H + 1);  // complements consumed by each level
   for (int i = 0; i < nm; ++i) {
     const Symbolic& S = *Ss[i];
     for (int32_t s = 0; s < S.nsn; ++s) {
-      const int64_t r = S.sn_rptr[s + 1] - S.sn_rptr[s];
-      uoff[sn0[i] + s + 1] = r * r;
-      H = std::max(H, S.height[s]);
+      levels[S.height[s]].push_back({i, s});
+      if (S.sn_parent[s] >= 0) release[S.height[S.sn_parent[s]]].push_back(sn0[i] + s);
     }
   }
-  for (int64_t g = 0; g < nsn; ++g) uoff[g + 1] += uoff[g];
+  auto rsz = [&](int i, int32_t s) { return Ss[i]->sn_rptr[s + 1] - Ss[i]->sn_rptr[s]; };
+  std::vector<int64_t> uoff(nsn, 0), usz(nsn, 0);
+  int64_t upd_entries = 0;
+  {
+    std::map<int64_t, int64_t> holes;  // offset -> entries
+    int64_t top = 0;
+    for (int32_t l = 0; l <= H; ++l) {
+      for (auto& e : levels[l]) {
+        const int64_t g = sn0[e.first] + e.second, r = rsz(e.first, e.second), n = r * r;
+        usz[g] = n;
+        if (n == 0) continue;
+        auto it = holes.begin();
+        while (it != holes.end() && it->second < n) ++it;
+        if (it != holes.end()) {
+          uoff[g] = it->first;
+          const int64_t o = it->first + n, rest = it->second - n;
+          holes.erase(it);
+          if (rest > 0) holes[o] = rest;
+        } else {
+          uoff[g] = top;
+          top += n;
+        }
+      }
+      upd_entries = std::max(upd_entries, top);
+      for (int64_t g : release[l]) {
+        if (usz[g] == 0) continue;
+        int64_t o = uoff[g], n = usz[g];
+        auto nx = holes.lower_bound(o);
+        if (nx != holes.end() && nx->first == o + n) {
+          n += nx->second;
+          nx = holes.erase(nx);
+        }
+        if (nx != holes.begin()) {
+          auto pv = std::prev(nx);
+          if (pv->first + pv->second == o) {
+            o = pv->first;
+            n += pv->second;
+            holes.erase(pv);
+          }
+        }
+        if (o + n == top)
+          top = o;
+        else
+          holes[o] = n;
+      }
+    }
+  }
   std::vector<dev::FrontChild> kids;
   std::vector<int32_t> kid0(nsn + 1, 0);
-  std::vector<std::vector<std::pair<int, int32_t>>> levels(H + 1);
   for (int i = 0; i < nm; ++i) {
     const Symbolic& S = *Ss[i];
     std::vector<std::vector<int32_t>> ch(S.nsn);
@@ -174,9 +228,7 @@ void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<co
       if (S.sn_parent[s] >= 0) ch[S.sn_parent[s]].push_back(s);
     for (int32_t s = 0; s < S.nsn; ++s) {
       kid0[sn0[i] + s] = (int32_t)kids.size();
-      for (int32_t c : ch[s])
-        kids.push_back({uoff[sn0[i] + c], rows0[i] + S.sn_rptr[c], (int32_t)(S.sn_rptr[c + 1] - S.sn_rptr[c]), 0});
-      levels[S.height[s]].push_back({i, s});
+      for (int32_t c : ch[s]) kids.push_back({uoff[sn0[i] + c], rows0[i] + S.sn_rptr[c], (int32_t)rsz(i, c), 0});
     }
   }
   kid0[nsn] = (int32_t)kids.size();
@@ -186,7 +238,7 @@ void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<co
   // entries take one double each, complex128 entries two
   const size_t wpe = prec == dev::FactorPrecision::kC64 ? 1 : 2;
   DVec<double> upd;
-  upd.alloc(wpe * std::max<int64_t>(uoff[nsn], 1));
+  upd.alloc(wpe * std::max<int64_t>(upd_entries, 1));
 
   // jobs, level by level, in chunks whose workspace fits the budget
   auto job_ws = [&](int i, int32_t s) {
@@ -265,10 +317,14 @@ void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<co
   jobs_d.upload(jobs);
   DVec<double> ws;
   ws.alloc(wpe * (size_t)budget);
+  scratch_bytes = 0;
   DVec<int32_t> piv_d, swp_d, npert_d;
   piv_d.alloc(std::max<int64_t>(pos0[nm], 1));
   swp_d.alloc(std::max<int64_t>(pos0[nm], 1));
   npert_d.alloc(std::max<size_t>(jobs.size(), 1));
+  scratch_bytes = 8.0 * (double)(ws.n + upd.n + aval.n) + 4.0 * (double)(asm_pos.n + asm_val.n + ep_d.n + piv_d.n +
+                                                                        swp_d.n + npert_d.n) +
+                  (double)sizeof(dev::FrontChild) * kids_d.n + (double)sizeof(dev::FrontJob) * jobs_d.n;
   for (size_t q = 0; q < launches.size(); ++q) {
     const int64_t f = launches[q].first, ns = nsplit[q], nj = launches[q].second - f;
     dev::factor_fronts_split(jobs_d.p + f, (int)ns, mmax[q], wmax[q], ws.p, upd.p, asm_pos.p, asm_val.p, aval.p,

@@ -472,7 +472,8 @@ void alloc_panels(const std::vector<const Symbolic*>& Ss, dev::FactorPrecision p
 void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symbolic*>& Ss,
                  const std::vector<const std::vector<int64_t>*>& in_idx, int device, bool numeric,
                  dev::FactorPrecision prec, int32_t split_min, bool on_host, int64_t sn_jobs_min, BatchHost& B,
-                 BatchDev& Dv, int32_t& n_perturbed, double& seconds, const std::vector<NumericOut>* pre = nullptr) {
+                 BatchDev& Dv, int32_t& n_perturbed, double& seconds, const std::vector<NumericOut>* pre = nullptr,
+                 double* scratch_bytes = nullptr) {
   const int nm = (int)As.size();
   const bool c64 = prec != dev::FactorPrecision::kC128;
   const size_t esz = c64 ? sizeof(std::complex<float>) : sizeof(cplx);
@@ -489,7 +490,9 @@ void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symb
   } else if (numeric && !on_host) {
     std::vector<void*> pf, pb;
     alloc_panels(Ss, prec, Dv, pf, pb);
-    factor_batch_device(As, Ss, prec, split_min, pf, pb, num, n_perturbed);
+    double sb = 0;
+    factor_batch_device(As, Ss, prec, split_min, pf, pb, num, n_perturbed, sb);
+    if (scratch_bytes) *scratch_bytes = sb;
   } else if (numeric) {
     Dv.pf.alloc(esz * (size_t)pf0[nm]);
     Dv.pb.alloc(esz * (size_t)pb0[nm]);
@@ -1056,7 +1059,9 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
       alloc_panels(part(Ss, bnd[k], bnd[k + 1]), prec, c.fine[k], pf, pb);
     }
     num_all.resize(n_sub);
-    factor_batch_device(As, Ss, prec, split_min, pf, pb, num_all, npert);
+    double sb = 0;
+    factor_batch_device(As, Ss, prec, split_min, pf, pb, num_all, npert, sb);
+    st.factor_scratch_bytes = std::max(st.factor_scratch_bytes, sb);
     fsec += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   for (int32_t k = 0; k < nb; ++k) {
@@ -1134,8 +1139,10 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
     std::iota(ident.begin(), ident.end(), 0);
     BatchHost cb;
     int32_t np2 = 0;
+    double csb = 0;
     build_batch({&c.E}, {&c.Esym}, {&ident}, c.device, on_device, dev::FactorPrecision::kC128, split_min, on_host,
-                snmin, cb, c.coarse, np2, csec);
+                snmin, cb, c.coarse, np2, csec, nullptr, &csb);
+    st.factor_scratch_bytes = std::max(st.factor_scratch_bytes, csb);
     npert += np2;
     c.two_level = true;
     st.n_coarse = (int32_t)c.E.n;

@@ -66,7 +66,8 @@ class PrecondStats(C.Structure):
                 ("levels_bwd", C.c_int32), ("max_front", C.c_int32), ("n_supernodes", C.c_int32),
                 ("setup_seconds", C.c_double), ("factor_flops", C.c_double), ("factor_c64", C.c_int32),
                 ("coarse_grid", C.c_int32), ("factor_on_host", C.c_int32), ("n_perturbed", C.c_int32),
-                ("factor_seconds", C.c_double), ("batches", C.c_int32), ("reserved", C.c_int32)]
+                ("factor_seconds", C.c_double), ("batches", C.c_int32), ("reserved", C.c_int32),
+                ("factor_scratch_bytes", C.c_double)]
 
 
 class ServerOpts(C.Structure):

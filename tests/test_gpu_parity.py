@@ -586,7 +586,10 @@ def test_split_fronts_match_one_workgroup_fronts(name, mode):
     hs = helm.from_workload(w, c64=mode, split_front_rows=1, coarse_launch=1)
     h1 = helm.from_workload(w, c64=mode, split_front_rows=-1, coarse_launch=1)
     hd = helm.from_workload(w, c64=mode, coarse_launch=1)
-    assert hs.stats()["n_perturbed"] == 0 and hs.stats()["factor_c64"] == mode
+    st = hs.stats()
+    assert st["n_perturbed"] == 0 and st["factor_c64"] == mode
+    # the factorisation's device scratch is reported and freed with setup
+    assert 0 < st["factor_scratch_bytes"]
     r = dvec(rand_vec(P.n, 37))
     zs, z1, zd = (torch.empty_like(r) for _ in range(3))
     for f in ("apply_oras", "apply_coarse") if M.Z is not None else ("apply_oras",):
