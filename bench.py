@@ -524,10 +524,7 @@ def main():
         "wall_s_timed": wall,
     }
     log(f"[bench] headline: {its_per_s:.1f} it/s, {solves_per_s:.3f} solves/s")
-    baseline = None
-    if not args.no_cpu_baseline:
-        # the oracle runs on the host's cores while the GPU lines below run
-        baseline = start_cpu_baseline(float(np.mean(its)))
+    mean_its = float(np.mean(its))
     if not args.no_extras:
         # the extra lines are reported, and a failure there is recorded
         # instead of hiding the headline
@@ -593,9 +590,11 @@ def main():
             extra("serving", lambda: serving_line(args.serve_solves))
     else:
         h.close()
-    if baseline is not None:
+    if not args.no_cpu_baseline:
+        # after every GPU line: the oracle's pool takes all host cores, and
+        # the solves above launch their kernels from the host
         try:
-            out["cpu_baseline"] = finish_cpu_baseline(baseline)
+            out["cpu_baseline"] = finish_cpu_baseline(start_cpu_baseline(mean_its))
         except Exception as e:  # noqa: BLE001
             out["cpu_baseline"] = {"error": repr(e)}
         log(f"[bench] cpu baseline: {out['cpu_baseline']}")

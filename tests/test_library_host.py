@@ -205,6 +205,36 @@ def test_batch_options_on_a_host_context():
             h.precond_setup(w.part, w.n_sub, w.overlap, batches=bad)
 
 
+def test_factor_precision_and_split_options_on_a_host_context():
+    """factor_c64 0/1/2 and split_front_rows -1/0/k are accepted (a host-only
+    context runs the complex128 host factorisation, so complex64
+    factorisation is reported as rounded complex128 when factor_on_host is
+    set); other values fail with HELM_EINVAL."""
+    w = wl.small_box(n=(4, 4, 2), order=2, n_parts=(2, 2, 1), overlap=1, coarse=False)
+
+    def setup(**kw):
+        h = helm.Helm(-1)
+        h.assemble(w.xyz, w.tets, w.order, w.c_tet, w.omega)
+        h.precond_setup(w.part, w.n_sub, w.overlap, **kw)
+        return h.stats()
+
+    for mode in (0, 1, 2):
+        assert setup(c64=mode)["factor_c64"] == mode
+    assert setup(c64=1, factor_on_host=True)["factor_c64"] == 2
+    for split in (-1, 0, 1, 300):
+        assert setup(split_front_rows=split)["factor_entries"] > 0
+    with pytest.raises(ValueError, match="c64"):
+        setup(c64=3)
+    h = helm.Helm(-1)
+    h.assemble(w.xyz, w.tets, w.order, w.c_tet, w.omega)
+    opts = helm.PrecondOpts(0, 3, 0, 0, 0, 0, 0, 0, 0, 0, 0)
+    rc = h.lib.helm_precond_setup(h.h, helm._ptr(np.ascontiguousarray(w.part, dtype=np.int32)), w.n_sub, w.overlap,
+                                  None, __import__("ctypes").byref(opts))
+    assert rc == helm.HELM_EINVAL
+    with pytest.raises(helm.HelmError, match="split_front_rows"):
+        setup(split_front_rows=-2)
+
+
 def test_binding_rejects_vectors_the_kernels_would_overrun():
     """Wrong dtype, wrong length, mismatched shapes and host tensors are
     refused by the binding before any pointer reaches the library."""
