@@ -248,11 +248,60 @@ def run_one_level(w, stream):
             "iterations_per_s": float(np.sum(its) / np.sum(times))}
 
 
+def run_coarse_study(w, stream):
+    """Whether the coarse level pays (the paper's two-level claim), on the mid
+    operator at 5 Hz and at 2.5 Hz: one-level ORAS, two-level with the
+    nested coarse mesh at twice the element size (the mid config) and with
+    the coarse mesh on the fine vertices (P1, twice as fine), complex128
+    factors, one right-hand side each."""
+    import dataclasses
+
+    import torch
+
+    from paper_2004_06309_amd import helm
+
+    coarse = {"one-level": (None, None), "two-level, coarse h = 2 x fine h": (w.coarse_xyz, w.coarse_tets),
+              "two-level, coarse h = fine h": (w.xyz, w.tets)}
+    out = {}
+    for f in (5.0, 2.5):
+        for name, (cx, ct) in coarse.items():
+            ww = dataclasses.replace(w, coarse_xyz=cx, coarse_tets=ct, omega=2 * np.pi * f)
+            h = helm.from_workload(ww)
+            try:
+                B = torch.from_numpy(helm.load_vector(h, ww)).to("cuda")
+                U = torch.zeros_like(B)
+                times, its, _ = time_solves(h, ww, B, U, 2, 1, stream, name, maxit=3000)
+                st = h.stats()
+            finally:
+                h.close()
+            out[f"{f:g} Hz, {name}"] = {"coarse_unknowns": st["n_coarse"], "iterations": float(np.mean(its)),
+                                        "seconds_per_solve": float(np.mean(times)),
+                                        "iterations_per_s": float(np.sum(its) / np.sum(times)),
+                                        "coarse_factor_GB": st["coarse_entries"] * 16 / 1e9}
+    return out
+
+
+def run_graph_line(w, stream, nrhs):
+    """Block GMRES on the mid operator (complex64 factors, 16 right-hand
+    sides per block) with every block step replayed from a captured HIP
+    graph, against the same solve launched eagerly."""
+    from paper_2004_06309_amd import helm
+
+    h = helm.from_workload(w, c64=True)
+    try:
+        eager = run_batched(h, w, stream, nrhs, "c64 block eager", True, False)
+        graph = run_batched(h, w, stream, nrhs, "c64 block graphs", True, True)
+    finally:
+        h.close()
+    return {"precond_precision": "c64 factors", "eager": eager, "graphs": graph,
+            "graphs_vs_eager": graph["solves_per_s"] / eager["solves_per_s"]}
+
+
 def run_adapted(nrhs, freq, restart, c64):
     """Config 3: the thrust model on an h-adapted tet mesh (bisection to a
     quarter of the local wavelength at freq), 128 uneven box subdomains,
     two-level ORAS with a non-nested coarse mesh, nrhs point sources on a
-    10 m-depth grid, block GMRES with graph-captured steps."""
+    10 m-depth grid, block GMRES (eager launches)."""
     import torch
 
     from paper_2004_06309_amd import helm
@@ -266,7 +315,7 @@ def run_adapted(nrhs, freq, restart, c64):
     st = h.stats()
     log(f"[bench] adapted setup: {st}")
     stream = torch.cuda.current_stream()
-    out = run_batched(h, w, stream, nrhs, "adapted", True, True, restart=restart)
+    out = run_batched(h, w, stream, nrhs, "adapted", True, False, restart=restart)
     counts = np.bincount(w.part, minlength=w.n_sub)
     n_i = [h.subdomain(i)[0].size for i in (int(np.argmin(counts)), int(np.argmax(counts)))]
     n = h.n
@@ -538,13 +587,14 @@ def main():
         if args.nrhs > 0:
             extra("batched_fp64_pseudo_block", lambda: run_batched(h, w, stream, args.nrhs, "c128 pseudo", False,
                                                                    False))
-            extra("batched_fp64", lambda: run_batched(h, w, stream, args.nrhs, "c128 block", True, True))
+            extra("batched_fp64", lambda: run_batched(h, w, stream, args.nrhs, "c128 block", True, False))
             for k in ("batched_fp64_pseudo_block", "batched_fp64"):
                 if "solves_per_s" in out[k]:
                     out[k]["speedup_vs_single_fp64"] = out[k]["solves_per_s"] / solves_per_s
         h.close()
         torch.cuda.empty_cache()
         extra("one_level", lambda: run_one_level(w, stream))
+        extra("coarse_study", lambda: run_coarse_study(w, stream))
         extra("tiny", lambda: run_tiny(stream, args.tiny_reps))
 
         def fp32_line():
@@ -572,7 +622,7 @@ def main():
                 if args.nrhs > 0:
                     for k, bg in (("batched_fp32_pseudo_block", False), ("batched_fp32", True)):
                         try:
-                            out[k] = run_batched(h32, w, stream, args.nrhs, k, bg, bg)
+                            out[k] = run_batched(h32, w, stream, args.nrhs, k, bg, False)
                             out[k]["speedup_vs_single_fp64"] = out[k]["solves_per_s"] / solves_per_s
                         except Exception as e:  # noqa: BLE001
                             out[k] = {"error": repr(e)}
@@ -588,6 +638,11 @@ def main():
             torch.cuda.empty_cache()
         if args.serve_solves > 0:
             extra("serving", lambda: serving_line(args.serve_solves))
+        if args.nrhs > 0:
+            # last of the GPU lines: once a process has replayed HIP graphs,
+            # its later eager solves run slower (measured 11-17 %), so every
+            # line above runs without them
+            extra("block_gmres_graphs", lambda: run_graph_line(w, stream, args.nrhs))
     else:
         h.close()
     if not args.no_cpu_baseline:

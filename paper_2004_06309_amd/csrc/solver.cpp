@@ -164,6 +164,10 @@ Profiler::~Profiler() {
 // of children's update vectors to the parents' front rows, and the tiles of
 // every forward (by height) and backward (by depth) level.  in_idx[i][l] is
 // the index in the solve's input vector of row l (original order) of matrix i.
+// Supernodes this close to the root of their tree (depth 0: the root
+// separator) are solved with four waves per tile.
+constexpr int32_t kTopDepth = 0;
+
 void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<const std::vector<int64_t>*>& in_idx,
                   const std::vector<NumericOut>& num, int64_t sn_jobs_min, bool c64, BatchHost& B) {
   const int nm = (int)Ss.size();
@@ -206,7 +210,7 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
   B.rows.resize(B.nu);
   B.bidx.assign(B.npos, 0);
   std::vector<std::vector<dev::Tile>> lf(maxlev_f + 1), lb(maxlev_b + 1);
-  std::vector<char> sn_narrow(nsn, 0);
+  std::vector<char> sn_narrow(nsn, 0), sn_top(nsn, 0);
   std::vector<int32_t> fcon_cnt(fr0[nm] + 1, 0);
   std::vector<std::vector<std::pair<int64_t, int32_t>>> fcon_m(nm);
   std::vector<TileShape> ts;
@@ -234,6 +238,7 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
         B.bidx[pos0[i] + c0 + k] = (int32_t)(*in_idx[i])[S.perm[rho]];
       }
       sn_narrow[g] = sn_jobs_min >= 0 && w <= 64 && S.tile_rows == 64;
+      sn_top[g] = S.depth[s] <= kTopDepth;
       tiles_fwd(w, r, S.tile_rows, ts);
       int64_t off = pf0[i] + S.sn_fwd_off[s];
       for (auto& t : ts) {
@@ -322,6 +327,10 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
   // Forward tiles of narrow supernodes close their level, grouped by
   // supernode (largest first) in row order, and also form one-wave jobs.
   auto sn_entries = [&](int32_t s) { return (int64_t)(B.w[s] + r_of(s)) * B.w[s]; };
+  // the top separators of every tree form levels of few tiles: each of
+  // their tiles gets a whole workgroup (four waves over its columns) so the
+  // level still spreads over the device
+  auto wpt_tile = [&](const dev::Tile& t) { return sn_top[t.sn] ? 4 : wpt_of(t.ncols); };
   B.snj_lev.assign(1, 0);
   auto make_tasks = [&](std::vector<std::vector<dev::Tile>>& levels, bool fwd, std::vector<dev::Tile>& tiles,
                         std::vector<dev::Task>& tasks, std::vector<int64_t>& lev, std::vector<double>& bytes,
@@ -349,7 +358,7 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
           if (a.sn != b.sn) return a.sn < b.sn;
           return a.row0 < b.row0;
         }
-        const int wa = wpt_of(a.ncols), wb = wpt_of(b.ncols);
+        const int wa = wpt_tile(a), wb = wpt_tile(b);
         if (wa != wb) return wa > wb;
         return (int64_t)a.nrows * a.ncols > (int64_t)b.nrows * b.ncols;
       });
@@ -357,10 +366,10 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
       int64_t ktile = -1;
       while (q < l.size()) {
         if (ktile < 0 && narrow(l[q])) ktile = (int64_t)tasks.size() - lev.back();
-        const int wpt = wpt_of(l[q].ncols);
+        const int wpt = wpt_tile(l[q]);
         const int per = 4 / wpt;
         size_t e = q;
-        while (e < l.size() && (int)(e - q) < per && wpt_of(l[e].ncols) == wpt &&
+        while (e < l.size() && (int)(e - q) < per && wpt_tile(l[e]) == wpt &&
                narrow(l[e]) == narrow(l[q]))
           ++e;
         tasks.push_back({(int32_t)(tiles.size() + q), (int16_t)(e - q), (int16_t)wpt});
@@ -638,11 +647,18 @@ void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symb
 // of the fine batch is timed (the coarse batch is timed as a whole).
 // Coarse-batch solve (forward and backward sweeps) through a view whose
 // work vectors may lie outside the batch (no profiling).
+// The cooperative coarse solve; false (the launch refused, its error
+// cleared) when the device cannot co-schedule its grid at this moment, for
+// instance while another process holds workgroups: the caller then takes the
+// per-level launches, whose result agreed with it at setup.
+bool coop_solve(const BatchDev& b, const dev::Batch& v, const double* in, hipStream_t s) {
+  if (dev::batch_solve_coop(v, in, b.ranges, b.coop, s) == hipSuccess) return true;
+  (void)hipGetLastError();
+  return false;
+}
+
 void batch_solve_view(const BatchDev& b, const dev::Batch& v, const double* in, hipStream_t s) {
-  if (b.coop > 0) {
-    HELM_HIP(dev::batch_solve_coop(v, in, b.ranges, b.coop, s));
-    return;
-  }
+  if (b.coop > 0 && coop_solve(b, v, in, s)) return;
   for (size_t l = 0; l + 1 < b.lev_f.size(); ++l) {
     dev::fwd_level(v, b.lev_f[l], b.ktile_f[l], in, b.chunk_f[l], true, s);
     dev::fwd_sn(v, b.snj_lev[l], b.snj_lev[l + 1] - b.snj_lev[l], in, s);
@@ -652,10 +668,7 @@ void batch_solve_view(const BatchDev& b, const dev::Batch& v, const double* in, 
 
 void batch_solve(const BatchDev& b, const double* in, hipStream_t s, Profiler* prof, bool fine) {
   dev::Batch v = b.view();
-  if (!fine && b.coop > 0) {
-    HELM_HIP(dev::batch_solve_coop(v, in, b.ranges, b.coop, s));
-    return;
-  }
+  if (!fine && b.coop > 0 && coop_solve(b, v, in, s)) return;
   const bool each = prof && prof->on && fine;
   for (size_t l = 0; l + 1 < b.lev_f.size(); ++l) {
     if (each) prof->begin(s);
@@ -952,9 +965,13 @@ void choose_coarse_launch(Ctx& c, int mode) {
   batch_solve(b, c.cvec.p, nullptr, nullptr, false);
   HELM_HIP(hipMemcpy(x1.data(), b.xout(), sizeof(double) * 2 * nc, hipMemcpyDeviceToHost));
   b.coop = gmax;
-  batch_solve(b, c.cvec.p, nullptr, nullptr, false);
-  HELM_HIP(hipMemcpy(x2.data(), b.xout(), sizeof(double) * 2 * nc, hipMemcpyDeviceToHost));
+  const bool launched = coop_solve(b, b.view(), c.cvec.p, nullptr);
   b.coop = 0;
+  if (!launched) {
+    if (mode == 2) fail(HELM_EDEVICE, "the cooperative coarse solve could not be launched");
+    return;  // keep the per-level launches
+  }
+  HELM_HIP(hipMemcpy(x2.data(), b.xout(), sizeof(double) * 2 * nc, hipMemcpyDeviceToHost));
   double dmax = 0, xmax = 0;
   for (int64_t i = 0; i < 2 * nc; ++i) {
     dmax = std::max(dmax, std::abs(x1[i] - x2[i]));
