@@ -464,6 +464,9 @@ def main():
     ap.add_argument("--adapted-restart", type=int, default=30)
     ap.add_argument("--serve-solves", type=int, default=250,
                     help="solves per serving run (two runs: below and above capacity; 0: skip)")
+    ap.add_argument("--lines", default="all",
+                    help="extra lines to run, comma-separated among batched, one_level, coarse_study, tiny, fp32, "
+                         "adapted, serving, graphs (default: all)")
     ap.add_argument("--serving-only", action="store_true",
                     help="only the serving measurement (--serve-solves solves per load point), one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -577,6 +580,9 @@ def main():
     if not args.no_extras:
         # the extra lines are reported, and a failure there is recorded
         # instead of hiding the headline
+        def want(line):
+            return args.lines == "all" or line in args.lines.split(",")
+
         def extra(key, fn):
             try:
                 out[key] = fn()
@@ -584,7 +590,7 @@ def main():
                 out[key] = {"error": repr(e)}
             log(f"[bench] {key}: {out[key]}")
 
-        if args.nrhs > 0:
+        if args.nrhs > 0 and want("batched"):
             extra("batched_fp64_pseudo_block", lambda: run_batched(h, w, stream, args.nrhs, "c128 pseudo", False,
                                                                    False))
             extra("batched_fp64", lambda: run_batched(h, w, stream, args.nrhs, "c128 block", True, False))
@@ -593,9 +599,12 @@ def main():
                     out[k]["speedup_vs_single_fp64"] = out[k]["solves_per_s"] / solves_per_s
         h.close()
         torch.cuda.empty_cache()
-        extra("one_level", lambda: run_one_level(w, stream))
-        extra("coarse_study", lambda: run_coarse_study(w, stream))
-        extra("tiny", lambda: run_tiny(stream, args.tiny_reps))
+        if want("one_level"):
+            extra("one_level", lambda: run_one_level(w, stream))
+        if want("coarse_study"):
+            extra("coarse_study", lambda: run_coarse_study(w, stream))
+        if want("tiny"):
+            extra("tiny", lambda: run_tiny(stream, args.tiny_reps))
 
         def fp32_line():
             h32, st32, _ = setup(True)
@@ -619,7 +628,7 @@ def main():
                      "factor_GB": st32["factor_entries"] * 8 / 1e9,
                      "speedup_vs_fp64": (len(t32) / tt) / solves_per_s,
                      "local_solves": local_solves(h32, prof32, stream, c64=True)}
-                if args.nrhs > 0:
+                if args.nrhs > 0 and want("batched"):
                     for k, bg in (("batched_fp32_pseudo_block", False), ("batched_fp32", True)):
                         try:
                             out[k] = run_batched(h32, w, stream, args.nrhs, k, bg, False)
@@ -630,15 +639,16 @@ def main():
             finally:
                 h32.close()
 
-        extra("fp32_precond", fp32_line)
-        torch.cuda.empty_cache()
-        if args.adapted_nrhs > 0:
+        if want("fp32"):
+            extra("fp32_precond", fp32_line)
+            torch.cuda.empty_cache()
+        if args.adapted_nrhs > 0 and want("adapted"):
             extra("batched_adapted", lambda: run_adapted(args.adapted_nrhs, args.adapted_freq, args.adapted_restart,
                                                           True))
             torch.cuda.empty_cache()
-        if args.serve_solves > 0:
+        if args.serve_solves > 0 and want("serving"):
             extra("serving", lambda: serving_line(args.serve_solves))
-        if args.nrhs > 0:
+        if args.nrhs > 0 and want("graphs"):
             # last of the GPU lines: once a process has replayed HIP graphs,
             # its later eager solves run slower (measured 11-17 %), so every
             # line above runs without them

@@ -2,7 +2,7 @@
 
     python -m paper_2004_06309_amd.rocprof_summary --trace DIR/mid_kernel_trace.csv \
         [--fetch DIR/mid_counter_collection.csv --write DIR/mid_counter_collection.csv \
-         --copy-fetch ... --copy-write ...] [--level-group NAME=K1+K2] \
+         --copy-fetch ... --copy-write ...] [--level-group NAME=K1+K2] [--row KERNEL] \
         --out profiles/<name>.md --command "<cmd>"
 
 Kernel-trace statistics are grouped by kernel (template arguments kept, so
@@ -69,9 +69,43 @@ def counter_means(path, counter):
     return {k: v[1] / v[0] for k, v in counter_sums(path, counter).items()}
 
 
+def mfma_table(path, simds, xcds, command):
+    """MFMA busy fraction per kernel: SQ_VALU_MFMA_BUSY_CYCLES summed over the
+    kernel's dispatches / (device cycles x SIMDs), the device cycles being
+    GRBM_GUI_ACTIVE / xcds (the counter sums the dies: it advances by about
+    xcds x the shader clock per ns, shown in the last column)."""
+    busy = collections.defaultdict(float)
+    gui = collections.defaultdict(float)
+    ns = collections.defaultdict(float)
+    calls = collections.Counter()
+    for r in csv.DictReader(open(path)):
+        k = short_name(r["Kernel_Name"])
+        if r["Counter_Name"] == "SQ_VALU_MFMA_BUSY_CYCLES":
+            busy[k] += float(r["Counter_Value"])
+        elif r["Counter_Name"] == "GRBM_GUI_ACTIVE":
+            gui[k] += float(r["Counter_Value"])
+            ns[k] += int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+            calls[k] += 1
+    lines = ["# rocprofv3 MFMA counters", "", f"Command: `{command}`", "",
+             f"MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / {xcds} x {simds} SIMDs), summed over each "
+             f"kernel's dispatches (counters serialise the dispatches).  GRBM_GUI_ACTIVE sums the {xcds} XCDs: it "
+             f"advances by about {xcds} x 2.4 cycles per ns (last column).", "",
+             "| kernel | calls | avg us | MFMA busy | GUI cycles / ns |", "|---|---|---|---|---|"]
+    for k in sorted(busy, key=lambda k: -busy[k]):
+        if busy[k] <= 0 or calls[k] == 0:
+            continue
+        lines.append(f"| `{k}` | {calls[k]} | {ns[k] / calls[k] / 1e3:.1f} | {busy[k] * xcds / (gui[k] * simds):.3f} | "
+                     f"{gui[k] / ns[k]:.2f} |")
+    return lines
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--trace", required=True)
+    ap.add_argument("--trace")
+    ap.add_argument("--mfma", help="counter CSV with SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE per dispatch")
+    ap.add_argument("--simds", type=int, default=1024, help="SIMDs of the device (MI355X: 256 CUs x 4)")
+    ap.add_argument("--xcds", type=int, default=8,
+                    help="dies whose GRBM_GUI_ACTIVE counts are summed (MI355X: 8 XCDs)")
     ap.add_argument("--fetch")
     ap.add_argument("--write")
     ap.add_argument("--copy-fetch")
@@ -82,11 +116,18 @@ def main():
     ap.add_argument("--json-out")
     ap.add_argument("--level-group", action="append", default=[],
                     help="NAME=K1+K2: kernels sharing the levels of one sweep, reported per level")
+    ap.add_argument("--row", action="append", default=[],
+                    help="kernel listed in the traffic table even when outside the 16 largest")
     args = ap.parse_args()
     groups = {}
     for g in args.level_group:
         name, ks = g.split("=", 1)
         groups[name] = [k.strip() for k in ks.split("+")]
+    if args.mfma:
+        lines = mfma_table(args.mfma, args.simds, args.xcds, args.command)
+        open(args.out, "w").write("\n".join(lines) + "\n")
+        print("\n".join(lines))
+        return
     st = trace_stats(args.trace)
     total = sum(sum(v) for v in st.values())
     lines = [f"# rocprofv3 kernel summary", "", f"Command: `{args.command}`", "",
@@ -120,11 +161,11 @@ def main():
         lines += ["", f"HBM traffic per dispatch (FETCH_SIZE x {sf:.3f}, WRITE_SIZE x {sw:.3f}; factors from a "
                       f"{args.copy_bytes / 2**30:.0f} GiB device copy):", "",
                   "| kernel | fetch MB | write MB |", "|---|---|---|"]
-        for k in sorted(fe, key=lambda k: -fe[k])[:16]:
-            f = fe[k] * 1024 * sf
-            w = wr.get(k, 0.0) * 1024 * sw
-            out[k] = {"fetch_bytes": f, "write_bytes": w}
-            lines.append(f"| `{k}` | {f / 1e6:.2f} | {w / 1e6:.2f} |")
+        top = sorted(fe, key=lambda k: -fe[k])[:16]
+        for k in top + [k for k in args.row if k in fe and k not in top]:
+            lines.append(f"| `{k}` | {fe[k] * 1024 * sf / 1e6:.2f} | {wr.get(k, 0.0) * 1024 * sw / 1e6:.2f} |")
+        for k in fe:  # every kernel's figures go into the JSON
+            out[k] = {"fetch_bytes": fe[k] * 1024 * sf, "write_bytes": wr.get(k, 0.0) * 1024 * sw}
         if groups:
             fs = counter_sums(args.fetch, "FETCH_SIZE")
             ws = counter_sums(args.write, "WRITE_SIZE")
