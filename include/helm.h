@@ -68,10 +68,7 @@ typedef struct helm_precond_opts {
                               1: complex64 factorisation (fronts, Schur
                                  complements and panels in complex64, the
                                  frontal updates on FP32 MFMA accumulating
-                                 in FP32), complex64 panels; with
-                                 factor_on_host the host factorisation runs
-                                 in complex128 and its panels are rounded
-                                 (reported as 2);
+                                 in FP32), complex64 panels;
                               2: complex128 factorisation, panels rounded
                                  once to complex64.
                               With complex64 panels the single-RHS solves
@@ -82,8 +79,6 @@ typedef struct helm_precond_opts {
   int32_t tile_rows;       /* rows per solve tile of the subdomain factors:
                               16, 32 or 64; 0 = 64                         */
   int32_t coarse_tile_rows;  /* same for the coarse factor; 0 = 16         */
-  int32_t factor_on_host;  /* 1: numeric factorisation on the host CPU
-                              (reference path); 0 = on the device          */
   int32_t sn_jobs_min;     /* complex128 panels: a forward level with at least
                               this many supernodes of <= 64 pivots (and
                               64-row tiles) solves those with one wave per
@@ -224,7 +219,6 @@ typedef struct helm_precond_stats {
                               helm_precond_opts.factor_c64)               */
   int32_t coarse_grid;     /* workgroups of the one-launch cooperative coarse
                               solve; 0 = one launch per level              */
-  int32_t factor_on_host;  /* 1 if the numeric factorisation ran on the host */
   int32_t n_perturbed;     /* tiny pivots replaced by sqrt(eps) max|a_ij|
                               (only with perturb_pivots)                  */
   double factor_seconds;   /* wall time of the numeric factorisation       */
@@ -282,10 +276,10 @@ int helm_matrix_csr(const helm_ctx* ctx, int64_t* rowptr, int32_t* col, double* 
  * the impedance condition on artificial faces, the partition of unity is
  * chi_i = max(0, 1 - l/overlap) normalised, local solves are LU factors
  * (nested-dissection multifrontal, partial pivoting inside each front) and
- * the coarse matrix E = Z^T A Z is factored the same way.  On a host-only
- * context the numeric factorisation is skipped, unless factor_on_host is set:
- * then it runs on the host to check the pivots, and nothing is uploaded.
- * HELM_ESINGULAR: a zero or tiny pivot (see perturb_pivots). */
+ * the coarse matrix E = Z^T A Z is factored the same way, all on the device.
+ * On a host-only context the numeric factorisation is skipped (assembly,
+ * decomposition and symbolic analysis run, and the statistics report their
+ * sizes).  HELM_ESINGULAR: a zero or tiny pivot (see perturb_pivots). */
 int helm_precond_setup(helm_ctx* ctx, const int32_t* tet_part, int32_t n_sub, int32_t overlap,
                        const helm_mesh* coarse, const helm_precond_opts* opts);
 

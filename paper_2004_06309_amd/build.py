@@ -20,8 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libhelm.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HOST_SOURCES = ["fem.cpp", "decomp.cpp", "order.cpp", "factor.cpp", "factor_gpu.cpp", "coarse.cpp", "solver.cpp",
-                "api.cpp"]
+HOST_SOURCES = ["fem.cpp", "decomp.cpp", "order.cpp", "factor_gpu.cpp", "coarse.cpp", "solver.cpp", "api.cpp"]
 HIP_SOURCES = ["device.hip", "device_block.hip", "device_factor.hip", "device_bgmres.hip"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result", f"-I{ROCM}/include", f"-I{ROOT}/include"]

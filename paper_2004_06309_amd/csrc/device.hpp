@@ -57,7 +57,8 @@ struct Task {
 };
 
 // Device arrays of one batch of factored matrices (all fine subdomains, or
-// the coarse matrix), see factor.cpp for the panel layout.
+// the coarse matrix); the panels are the partitioned-inverse tiles written
+// by device_factor.hip.
 struct Batch {
   const Tile* tf = nullptr;        // forward tiles, grouped by level
   const Tile* tb = nullptr;        // backward tiles, grouped by level

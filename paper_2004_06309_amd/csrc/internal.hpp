@@ -127,15 +127,12 @@ struct TileDesc {
 
 constexpr int kTileRows = 64;
 
+// Pivots of a factored matrix (the numeric factorisation runs on the
+// device, device_factor.hip).
 struct NumericOut {
   std::vector<int32_t> piv;  // per new-order row position: pivot permutation within the supernode
   int32_t n_perturbed = 0;
 };
-
-// Factor A (local indices, symbolic S) and write the forward and backward
-// panels in tile layout into fwd/bwd (host arrays sized by S).  Throws
-// HELM_ESINGULAR on a zero pivot.
-void factor_numeric(const Csr& A, const Symbolic& S, cplx* fwd, cplx* bwd, NumericOut& out);
 // Tile shapes of a supernode's panels (rows [row0, row0+nrows), input
 // columns [col0, col0+ncols)), in storage order.
 struct TileShape {

@@ -474,86 +474,31 @@ void alloc_panels(const std::vector<const Symbolic*>& Ss, dev::FactorPrecision p
   }
 }
 
-// Factors a batch (on the device, or on the host with one matrix per thread)
-// into the device panels; without a device only the layout is built (pivots
-// taken as the identity).  With pre, the device panels were allocated by
+// Factors a batch on the device into its panels; without a device only the
+// layout is built (pivots taken as the identity).  With pre, the device panels were allocated by
 // alloc_panels and factorised already, pre holding the pivots.
 void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symbolic*>& Ss,
                  const std::vector<const std::vector<int64_t>*>& in_idx, int device, bool numeric,
-                 dev::FactorPrecision prec, int32_t split_min, bool on_host, int64_t sn_jobs_min, BatchHost& B,
+                 dev::FactorPrecision prec, int32_t split_min, int64_t sn_jobs_min, BatchHost& B,
                  BatchDev& Dv, int32_t& n_perturbed, double& seconds, const std::vector<NumericOut>* pre = nullptr,
                  double* scratch_bytes = nullptr) {
   const int nm = (int)As.size();
   const bool c64 = prec != dev::FactorPrecision::kC128;
   const size_t esz = c64 ? sizeof(std::complex<float>) : sizeof(cplx);
   Dv.c64 = c64 ? 1 : 0;
-  std::vector<int64_t> pf0(nm + 1, 0), pb0(nm + 1, 0);
-  for (int i = 0; i < nm; ++i) {
-    pf0[i + 1] = pf0[i] + Ss[i]->fwd_entries;
-    pb0[i + 1] = pb0[i] + Ss[i]->bwd_entries;
-  }
   std::vector<NumericOut> num(nm);
   const auto t0 = std::chrono::steady_clock::now();
   if (pre) {
     num = *pre;
-  } else if (numeric && !on_host) {
+  } else if (numeric) {
     std::vector<void*> pf, pb;
     alloc_panels(Ss, prec, Dv, pf, pb);
     double sb = 0;
     factor_batch_device(As, Ss, prec, split_min, pf, pb, num, n_perturbed, sb);
     if (scratch_bytes) *scratch_bytes = sb;
-  } else if (numeric) {
-    Dv.pf.alloc(esz * (size_t)pf0[nm]);
-    Dv.pb.alloc(esz * (size_t)pb0[nm]);
-    std::string errmsg;
-    int errcode = 0;
-    int32_t npert = 0;
-#pragma omp parallel for schedule(dynamic, 1) reduction(+ : npert)
-    for (int i = 0; i < nm; ++i) {
-      try {
-        const Symbolic& S = *Ss[i];
-        std::vector<cplx> hf(S.fwd_entries), hb(S.bwd_entries);
-        factor_numeric(*As[i], S, hf.data(), hb.data(), num[i]);
-        npert += num[i].n_perturbed;
-        HELM_HIP(hipSetDevice(device));
-        auto put = [&](unsigned char* dst, const std::vector<cplx>& src) {
-          if (src.empty()) return;
-          if (!c64) {
-            HELM_HIP(hipMemcpy(dst, src.data(), sizeof(cplx) * src.size(), hipMemcpyHostToDevice));
-            return;
-          }
-          std::vector<std::complex<float>> lo(src.size());
-          for (size_t q = 0; q < src.size(); ++q) lo[q] = std::complex<float>(src[q]);
-          HELM_HIP(hipMemcpy(dst, lo.data(), sizeof(std::complex<float>) * lo.size(), hipMemcpyHostToDevice));
-        };
-        put(Dv.pf.p + esz * pf0[i], hf);
-        put(Dv.pb.p + esz * pb0[i], hb);
-      } catch (const Error& e) {
-#pragma omp critical
-        {
-          if (!errcode) {
-            errcode = e.code;
-            errmsg = e.what();
-          }
-        }
-      }
-    }
-    if (errcode) fail(errcode, errmsg);
-    n_perturbed = npert;
   } else {
-    // no device: only the layout is built; with on_host the host
-    // factorisation still runs so that its pivots are checked
-    int32_t npert = 0;
-    if (on_host) {
-#pragma omp parallel for schedule(dynamic, 1) reduction(+ : npert)
-      for (int i = 0; i < nm; ++i) {
-        std::vector<cplx> hf(Ss[i]->fwd_entries), hb(Ss[i]->bwd_entries);
-        NumericOut o;
-        factor_numeric(*As[i], *Ss[i], hf.data(), hb.data(), o);
-        npert += o.n_perturbed;
-      }
-    }
-    n_perturbed = npert;
+    // no device: only the layout is built (identity pivots)
+    n_perturbed = 0;
     for (int i = 0; i < nm; ++i) {
       num[i].piv.resize(Ss[i]->n);
       std::iota(num[i].piv.begin(), num[i].piv.end(), 0);
@@ -1026,16 +971,13 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
   int32_t npert = 0;
   const int32_t c64mode = opts ? opts->factor_c64 : 0;
   if (c64mode < 0 || c64mode > 2) fail(HELM_EINVAL, "factor_c64 must be 0, 1 or 2");
-  const bool on_host = opts && opts->factor_on_host;
   const bool c64 = c64mode != 0;
   const int32_t split_opt = opts ? opts->split_front_rows : 0;
   if (split_opt < -1) fail(HELM_EINVAL, "split_front_rows must be -1, 0 or positive");
   const int32_t split_min = split_opt == 0 ? dev::kSplitFrontMin : split_opt;
-  // the host factorisation works in complex128 only (its complex64 panels
-  // are rounded copies)
-  const dev::FactorPrecision prec = !c64                      ? dev::FactorPrecision::kC128
-                                    : c64mode == 1 && !on_host ? dev::FactorPrecision::kC64
-                                                               : dev::FactorPrecision::kC128RoundedC64;
+  const dev::FactorPrecision prec = !c64           ? dev::FactorPrecision::kC128
+                                    : c64mode == 1 ? dev::FactorPrecision::kC64
+                                                   : dev::FactorPrecision::kC128RoundedC64;
   double fsec = 0, csec = 0;
   // nb consecutive batches of about equal panel entries (their level sweeps
   // overlap on nb streams): batch k ends at the first subdomain count whose
@@ -1067,7 +1009,7 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
   // fronts of every batch in the same launches), each into its batch's
   // panel arrays
   std::vector<NumericOut> num_all;
-  if (on_device && !on_host) {
+  if (on_device) {
     const auto t0 = std::chrono::steady_clock::now();
     std::vector<void*> pf, pb;
     for (int32_t k = 0; k < nb; ++k) {
@@ -1088,7 +1030,7 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
     std::vector<NumericOut> pre;
     if (!num_all.empty()) pre.assign(num_all.begin() + bnd[k], num_all.begin() + bnd[k + 1]);
     build_batch(part(As, bnd[k], bnd[k + 1]), part(Ss, bnd[k], bnd[k + 1]), part(in, bnd[k], bnd[k + 1]), c.device,
-                on_device, prec, split_min, on_host, snb, fb, c.fine[k], np, fs, num_all.empty() ? nullptr : &pre);
+                on_device, prec, split_min, snb, fb, c.fine[k], np, fs, num_all.empty() ? nullptr : &pre);
     npert += np;
     fsec += fs;
     st.factor_entries += fb.nf + fb.nb;
@@ -1157,8 +1099,8 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
     BatchHost cb;
     int32_t np2 = 0;
     double csb = 0;
-    build_batch({&c.E}, {&c.Esym}, {&ident}, c.device, on_device, dev::FactorPrecision::kC128, split_min, on_host,
-                snmin, cb, c.coarse, np2, csec, nullptr, &csb);
+    build_batch({&c.E}, {&c.Esym}, {&ident}, c.device, on_device, dev::FactorPrecision::kC128, split_min, snmin, cb,
+                c.coarse, np2, csec, nullptr, &csb);
     st.factor_scratch_bytes = std::max(st.factor_scratch_bytes, csb);
     npert += np2;
     c.two_level = true;
@@ -1271,7 +1213,6 @@ void precond_setup(Ctx& c, const int32_t* tet_part, int32_t n_sub, int32_t overl
     fail(HELM_ESINGULAR, std::to_string(npert) +
                              " zero or tiny pivots (|pivot| <= 1000 eps max|a_ij|) in the local or coarse factors;"
                              " helm_precond_opts.perturb_pivots replaces them instead");
-  st.factor_on_host = on_host ? 1 : 0;
   st.factor_seconds = fsec + csec;
   st.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   c.precond_ready = true;

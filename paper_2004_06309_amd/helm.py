@@ -46,7 +46,7 @@ class Mesh(C.Structure):
 
 class PrecondOpts(C.Structure):
     _fields_ = [("leaf_size", C.c_int32), ("factor_c64", C.c_int32), ("coarse_leaf_size", C.c_int32),
-                ("tile_rows", C.c_int32), ("coarse_tile_rows", C.c_int32), ("factor_on_host", C.c_int32),
+                ("tile_rows", C.c_int32), ("coarse_tile_rows", C.c_int32),
                 ("sn_jobs_min", C.c_int32), ("batches", C.c_int32), ("perturb_pivots", C.c_int32),
                 ("coarse_launch", C.c_int32), ("split_front_rows", C.c_int32)]
 
@@ -65,7 +65,7 @@ class PrecondStats(C.Structure):
                 ("factor_entries", C.c_int64), ("coarse_entries", C.c_int64), ("levels_fwd", C.c_int32),
                 ("levels_bwd", C.c_int32), ("max_front", C.c_int32), ("n_supernodes", C.c_int32),
                 ("setup_seconds", C.c_double), ("factor_flops", C.c_double), ("factor_c64", C.c_int32),
-                ("coarse_grid", C.c_int32), ("factor_on_host", C.c_int32), ("n_perturbed", C.c_int32),
+                ("coarse_grid", C.c_int32), ("n_perturbed", C.c_int32),
                 ("factor_seconds", C.c_double), ("batches", C.c_int32), ("reserved", C.c_int32),
                 ("factor_scratch_bytes", C.c_double)]
 
@@ -262,7 +262,7 @@ class Helm:
         return ptr, col, val
 
     def precond_setup(self, part, n_sub, overlap, coarse_xyz=None, coarse_tets=None, leaf_size=0, c64=False,
-                      coarse_leaf_size=0, tile_rows=0, coarse_tile_rows=0, factor_on_host=False, sn_jobs_min=0,
+                      coarse_leaf_size=0, tile_rows=0, coarse_tile_rows=0, sn_jobs_min=0,
                       batches=0, perturb_pivots=False, coarse_launch=0, split_front_rows=0):
         """helm_precond_setup: subdomains from the tet partition `part` with
         `overlap` layers, the optional P1 coarse mesh, then the factorisation.
@@ -281,7 +281,7 @@ class Helm:
         if c64 not in (False, True, 0, 1, 2):
             raise ValueError("c64 must be False/True or 0, 1, 2")
         opts = PrecondOpts(int(leaf_size), int(c64), int(coarse_leaf_size), int(tile_rows),
-                           int(coarse_tile_rows), 1 if factor_on_host else 0, int(sn_jobs_min), int(batches),
+                           int(coarse_tile_rows), int(sn_jobs_min), int(batches),
                            1 if perturb_pivots else 0, int(coarse_launch), int(split_front_rows))
         cm = None
         if coarse_xyz is not None:
@@ -450,7 +450,7 @@ class Server:
 
 def from_workload(w, device=0, leaf_size=0, c64=False, **opts):
     """Helm context assembled and preconditioned for a workloads.Workload;
-    opts: coarse_leaf_size, tile_rows, coarse_tile_rows, factor_on_host,
+    opts: coarse_leaf_size, tile_rows, coarse_tile_rows,
     sn_jobs_min, batches (see precond_setup)."""
     h = Helm(device)
     h.assemble(w.xyz, w.tets, w.order, w.c_tet, w.omega)

@@ -605,40 +605,26 @@ def test_split_fronts_match_one_workgroup_fronts(name, mode):
     assert rel(host(zs), M.one_level(host(r))) <= (1e-9 if mode == 0 else C64_APPLY_TOL[1])
 
 
-@pytest.mark.parametrize("name", ["tiny", "ragged_p2", "mid_quarter_2lvl"])
-def test_device_factorisation_matches_host(name):
-    """The numeric factorisation on the device (multifrontal, MFMA Schur
-    updates) and the host reference factorisation give the same local and
-    coarse solves to rounding (both are backward-stable LU of the same
-    matrices; pivots may differ only in near-ties)."""
-    w = WORKLOADS[name]()
-    P, b, M = opre.build(w)
-    hd = helm.from_workload(w)
-    hh = helm.from_workload(w, factor_on_host=True)
-    sd, sh = hd.stats(), hh.stats()
-    assert sd["factor_on_host"] == 0 and sh["factor_on_host"] == 1
-    assert sd["n_perturbed"] == 0 and sd["factor_entries"] == sh["factor_entries"]
-    r = dvec(rand_vec(P.n, 31))
-    zd = torch.empty_like(r)
-    zh = torch.empty_like(r)
-    hd.apply_oras(r, zd)
-    hh.apply_oras(r, zh)
-    assert rel(host(zd), host(zh)) <= 1e-10
-    assert rel(host(zd), M.one_level(host(r))) <= 1e-9
-    if M.Z is not None:
-        hd.apply_coarse(r, zd)
-        hh.apply_coarse(r, zh)
-        assert rel(host(zd), host(zh)) <= 1e-10
-    # complex64 panels rounded once from either factorisation
-    hd32 = helm.from_workload(w, c64=2)
-    hd32.apply_oras(r, zd)
-    hh.apply_oras(r, zh)
-    assert rel(host(zd), host(zh)) <= 1e-4
-    # and factorised in complex64 on the device
-    hd32 = helm.from_workload(w, c64=1)
-    assert hd32.stats()["factor_c64"] == 1
-    hd32.apply_oras(r, zd)
-    assert rel(host(zd), host(zh)) <= C64_APPLY_TOL[1]
+@pytest.mark.parametrize("mode", [0, 1])
+def test_singular_local_matrix_is_reported(mode):
+    """A velocity of 1e300 m/s makes k vanish, so a subdomain away from the
+    Dirichlet top has the local matrix -K_i, singular (constants span its
+    kernel): the device factorisation (complex128 or complex64) meets a zero
+    pivot and setup fails with HELM_ESINGULAR, unless pivot replacement is
+    asked for; a regular medium factors without replacements."""
+    w = wl.small_box(n=(4, 4, 4), order=1, n_parts=(2, 2, 2), overlap=1, coarse=False)
+    c = np.full(w.n_tets, 1e300 + 0j)
+    h = helm.Helm(0)
+    h.assemble(w.xyz, w.tets, 1, c, w.omega)
+    with pytest.raises(helm.HelmError) as e:
+        h.precond_setup(w.part, w.n_sub, w.overlap, c64=mode)
+    assert e.value.code == helm.HELM_ESINGULAR
+    h.precond_setup(w.part, w.n_sub, w.overlap, c64=mode, perturb_pivots=True)
+    assert h.stats()["n_perturbed"] >= 4  # one per subdomain of the lower layer
+    h.assemble(w.xyz, w.tets, 1, w.c_tet, w.omega)
+    h.precond_setup(w.part, w.n_sub, w.overlap, c64=mode)
+    assert h.stats()["n_perturbed"] == 0
+    h.close()
 
 
 def test_edge_cases():

@@ -206,10 +206,9 @@ def test_batch_options_on_a_host_context():
 
 
 def test_factor_precision_and_split_options_on_a_host_context():
-    """factor_c64 0/1/2 and split_front_rows -1/0/k are accepted (a host-only
-    context runs the complex128 host factorisation, so complex64
-    factorisation is reported as rounded complex128 when factor_on_host is
-    set); other values fail with HELM_EINVAL."""
+    """factor_c64 0/1/2 and split_front_rows -1/0/k are accepted by a
+    host-only context (which runs the symbolic analysis only); other values
+    fail with HELM_EINVAL."""
     w = wl.small_box(n=(4, 4, 2), order=2, n_parts=(2, 2, 1), overlap=1, coarse=False)
 
     def setup(**kw):
@@ -220,14 +219,13 @@ def test_factor_precision_and_split_options_on_a_host_context():
 
     for mode in (0, 1, 2):
         assert setup(c64=mode)["factor_c64"] == mode
-    assert setup(c64=1, factor_on_host=True)["factor_c64"] == 2
     for split in (-1, 0, 1, 300):
         assert setup(split_front_rows=split)["factor_entries"] > 0
     with pytest.raises(ValueError, match="c64"):
         setup(c64=3)
     h = helm.Helm(-1)
     h.assemble(w.xyz, w.tets, w.order, w.c_tet, w.omega)
-    opts = helm.PrecondOpts(0, 3, 0, 0, 0, 0, 0, 0, 0, 0, 0)
+    opts = helm.PrecondOpts(0, 3, 0, 0, 0, 0, 0, 0, 0, 0)
     rc = h.lib.helm_precond_setup(h.h, helm._ptr(np.ascontiguousarray(w.part, dtype=np.int32)), w.n_sub, w.overlap,
                                   None, __import__("ctypes").byref(opts))
     assert rc == helm.HELM_EINVAL
@@ -254,23 +252,3 @@ def test_binding_rejects_vectors_the_kernels_would_overrun():
         h.solve(torch.zeros(2, n, dtype=torch.complex128), torch.zeros(n, dtype=torch.complex128))
     with pytest.raises(ValueError, match="entries"):
         h.solve(torch.zeros(2, n + 1, dtype=torch.complex128), torch.zeros(2, n + 1, dtype=torch.complex128))
-
-
-def test_singular_local_matrix_is_reported():
-    """A velocity of 1e300 m/s makes k vanish, so a subdomain away from the
-    Dirichlet top has the local matrix -K_i, singular (constants span its
-    kernel): the host factorisation meets a zero pivot and setup fails with
-    HELM_ESINGULAR, unless pivot replacement is asked for."""
-    w = wl.small_box(n=(4, 4, 4), order=1, n_parts=(2, 2, 2), overlap=1, coarse=False)
-    c = np.full(w.n_tets, 1e300 + 0j)
-    h = helm.Helm(-1)
-    h.assemble(w.xyz, w.tets, 1, c, w.omega)
-    with pytest.raises(helm.HelmError) as e:
-        h.precond_setup(w.part, w.n_sub, w.overlap, factor_on_host=True)
-    assert e.value.code == helm.HELM_ESINGULAR
-    h.precond_setup(w.part, w.n_sub, w.overlap, factor_on_host=True, perturb_pivots=True)
-    assert h.stats()["n_perturbed"] >= 4  # one per subdomain of the lower layer
-    # a regular medium factors without replacements
-    h.assemble(w.xyz, w.tets, 1, w.c_tet, w.omega)
-    h.precond_setup(w.part, w.n_sub, w.overlap, factor_on_host=True)
-    assert h.stats()["n_perturbed"] == 0
