@@ -643,6 +643,64 @@ __global__ __launch_bounds__(kPW) void split_panel_kernel(const FrontJob* __rest
   if (tid == 0) npert[blockIdx.x] += n_pert;
 }
 
+// The row interchanges of pivots [ks, ks + kn) composed into one
+// permutation by the first wave (one map entry per lane) and applied to the
+// columns [c0, c1) outside [skip0, skip1), 32 columns at a time through buf.
+template <class Cx>
+__device__ void apply_interchanges(Cx* Fm, int m, const int32_t* sw, int ks, int kn, int c0, int c1, int skip0,
+                                   int skip1, Cx* buf) {
+  __shared__ int prow[2 * kNB], psrc[2 * kNB];
+  __shared__ int nperm;
+  const int tid = threadIdx.x;
+  if (tid < 64) {
+    int key = -1, val = -1, used = 0;
+    const int myp = tid < kn ? sw[ks + tid] : 0;  // all the block's pivots in one load
+    for (int k = ks; k < ks + kn; ++k) {
+      const int p = __shfl(myp, k - ks, 64);
+      if (p == k) continue;
+      int lk, lp;
+      const unsigned long long mk = __ballot(key == k);
+      if (mk) {
+        lk = __ffsll((long long)mk) - 1;
+      } else {
+        lk = used++;
+        if (tid == lk) key = val = k;
+      }
+      const unsigned long long mp = __ballot(key == p);
+      if (mp) {
+        lp = __ffsll((long long)mp) - 1;
+      } else {
+        lp = used++;
+        if (tid == lp) key = val = p;
+      }
+      const int vk = __shfl(val, lk, 64), vp = __shfl(val, lp, 64);
+      if (tid == lk) val = vp;
+      if (tid == lp) val = vk;
+    }
+    if (tid < used) {
+      prow[tid] = key;
+      psrc[tid] = val;
+    }
+    if (tid == 0) nperm = used;
+  }
+  __syncthreads();
+  constexpr int kCols = kNB * kChunkV / (2 * kNB);
+  const int np = max(nperm, 1);
+  for (int cb = c0; cb < c1; cb += kCols) {
+    const int cnt = (nperm > 0 ? np : 0) * min(kCols, c1 - cb);
+    for (int e = tid; e < cnt; e += kFW) {
+      const int col = cb + e / np;
+      if (col < skip0 || col >= skip1) buf[e] = Fm[psrc[e % np] + (int64_t)col * m];
+    }
+    __syncthreads();
+    for (int e = tid; e < cnt; e += kFW) {
+      const int col = cb + e / np;
+      if (col < skip0 || col >= skip1) Fm[prow[e % np] + (int64_t)col * m] = buf[e];
+    }
+    __syncthreads();
+  }
+}
+
 template <class R>
 __global__ __launch_bounds__(kFW) void split_update_kernel(const FrontJob* __restrict__ jobs,
                                                            typename Fp<R>::C* __restrict__ ws,
@@ -652,35 +710,20 @@ __global__ __launch_bounds__(kFW) void split_update_kernel(const FrontJob* __res
   __shared__ Cx T[kNB * kNB];
   __shared__ Cx buf[kNB * kChunkV];
   const FrontJob J = jobs[blockIdx.x];
-  const int tid = threadIdx.x, m = J.m, w = J.w;
+  const int m = J.m, w = J.w;
   if (k0 >= w) return;
   const int c0 = blockIdx.y * kStrip;
   if (c0 >= m) return;
   const int kb = min(kNB, w - k0), j0 = k0 + kb, c1 = min(m, c0 + kStrip);
   Cx* Fm = ws + J.F;
-  const int32_t* sw = swp + J.piv0;
-  // the block's row interchanges, in order, one column per thread
-  {
-    const int col = c0 + tid;
-    if (tid < kStrip && col < c1 && (col < k0 || col >= j0)) {
-      Cx* Fc = Fm + (int64_t)col * m;
-      for (int k = k0; k < j0; ++k) {
-        const int p = sw[k];
-        if (p != k) {
-          const Cx t = Fc[k];
-          Fc[k] = Fc[p];
-          Fc[p] = t;
-        }
-      }
-    }
-  }
+  apply_interchanges(Fm, m, swp + J.piv0, k0, kb, c0, c1, k0, j0, buf);
   if (c1 <= j0) return;
-  __syncthreads();
   const int js = max(c0, j0), nc = c1 - js;
   load_diag_block(Fm + k0 + (int64_t)k0 * m, m, kb, T);
   solve_cols_unit_lower(Fm + k0 + (int64_t)js * m, m, kb, nc, T, buf);
-  wg_gemm_sub<R>(m - j0, nc, kb, Fm + j0 + (int64_t)k0 * m, m, Fm + k0 + (int64_t)js * m, m,
-                 Fm + j0 + (int64_t)js * m, m);
+  // U12 of the strip is still in buf (one chunk: nc <= kChunkV), zero
+  // beyond kb rows and nc columns
+  wg_gemm_sub<R>(m - j0, nc, kb, Fm + j0 + (int64_t)k0 * m, m, buf, kNB, Fm + j0 + (int64_t)js * m, m);
 }
 
 // Entries of the solve tile starting at row r0 of a panel: forward tiles are
