@@ -4,8 +4,10 @@
 #include <omp.h>
 
 #include <algorithm>
+#include <limits>
 #include <map>
 #include <numeric>
+#include <set>
 
 #include "ctx.hpp"
 
@@ -156,7 +158,7 @@ void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<co
   // Schur complement offsets, children lists, levels.  A supernode's Schur
   // complement (r x r) is live from its own level (its height in the
   // elimination tree) until its parent's level has assembled it; offsets
-  // come from a first-fit arena run level by level (a level's new
+  // come from a best-fit arena run level by level (a level's new
   // complements are placed before the ones it consumes are released), so
   // the buffer holds the largest set live at once instead of all of them.
   const int64_t nsn = sn0[nm];
@@ -176,20 +178,30 @@ void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<co
   std::vector<int64_t> uoff(nsn, 0), usz(nsn, 0);
   int64_t upd_entries = 0;
   {
-    std::map<int64_t, int64_t> holes;  // offset -> entries
+    // free holes below the top, indexed by offset (to merge neighbours) and
+    // by size (best fit, lowest offset among equals)
+    std::map<int64_t, int64_t> by_off;
+    std::set<std::pair<int64_t, int64_t>> by_size;
+    auto add_hole = [&](int64_t o, int64_t n) {
+      by_off[o] = n;
+      by_size.insert({n, o});
+    };
+    auto drop_hole = [&](std::map<int64_t, int64_t>::iterator it) {
+      by_size.erase({it->second, it->first});
+      return by_off.erase(it);
+    };
     int64_t top = 0;
     for (int32_t l = 0; l <= H; ++l) {
       for (auto& e : levels[l]) {
         const int64_t g = sn0[e.first] + e.second, r = rsz(e.first, e.second), n = r * r;
         usz[g] = n;
         if (n == 0) continue;
-        auto it = holes.begin();
-        while (it != holes.end() && it->second < n) ++it;
-        if (it != holes.end()) {
-          uoff[g] = it->first;
-          const int64_t o = it->first + n, rest = it->second - n;
-          holes.erase(it);
-          if (rest > 0) holes[o] = rest;
+        auto fit = by_size.lower_bound({n, std::numeric_limits<int64_t>::min()});
+        if (fit != by_size.end()) {
+          const int64_t o = fit->second, rest = fit->first - n;
+          drop_hole(by_off.find(o));
+          uoff[g] = o;
+          if (rest > 0) add_hole(o + n, rest);
         } else {
           uoff[g] = top;
           top += n;
@@ -199,23 +211,23 @@ void factor_batch_device(const std::vector<const Csr*>& As, const std::vector<co
       for (int64_t g : release[l]) {
         if (usz[g] == 0) continue;
         int64_t o = uoff[g], n = usz[g];
-        auto nx = holes.lower_bound(o);
-        if (nx != holes.end() && nx->first == o + n) {
+        auto nx = by_off.lower_bound(o);
+        if (nx != by_off.end() && nx->first == o + n) {
           n += nx->second;
-          nx = holes.erase(nx);
+          nx = drop_hole(nx);
         }
-        if (nx != holes.begin()) {
+        if (nx != by_off.begin()) {
           auto pv = std::prev(nx);
           if (pv->first + pv->second == o) {
             o = pv->first;
             n += pv->second;
-            holes.erase(pv);
+            drop_hole(pv);
           }
         }
         if (o + n == top)
           top = o;
         else
-          holes[o] = n;
+          add_hole(o, n);
       }
     }
   }
