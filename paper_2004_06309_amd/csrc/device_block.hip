@@ -219,70 +219,71 @@ __device__ __forceinline__ float2 ldp(const float2* p) {
   return make_float2(v.x, v.y);
 }
 
-// 4 waves per tile: wave q accumulates the k-steps q, q + 4, ... of the
-// tile, then the partial accumulators are summed through LDS.  The loads of
-// the next two k-steps (complex64 panels: the next one) are issued before
-// the MFMAs of the current one, so a wave keeps panel in flight while its
-// MFMAs run.
-template <class T, int kFwd>
-__device__ __forceinline__ void mfma_tile4(const Tile& t, const typename Mf<T>::C2* __restrict__ P,
-                                           const typename Mf<T>::C2* __restrict__ Bk, typename Mf<T>::V4* dre,
-                                           typename Mf<T>::V4* dim) {
+// Streams the k-steps k0 = ks0, ks0 + kst, ... < cn (a k-step is four
+// columns) of a panel tile P (nr rows, column-major) against the input block
+// Bk (16 right-hand sides per column) into the accumulators of the row
+// blocks rb < nrb.  The loads of the next k-step are issued before the MFMAs
+// of the current one, into the other of two register sets, so no loaded
+// register is copied (a copy would make the wave wait for the load just
+// issued).  Every load is issued unconditionally, at a clamped address: rows
+// past nr read row nr - 1 (rows whose results are never stored), columns
+// past cn read column cn - 1 and meet a zero B entry, so the waits the
+// compiler places count exactly the other set's loads.
+template <class T>
+__device__ __forceinline__ void mfma_stream(const typename Mf<T>::C2* __restrict__ P, int nr, int cn,
+                                            const typename Mf<T>::C2* __restrict__ Bk, int ks0, int kst,
+                                            typename Mf<T>::V4* dre, typename Mf<T>::V4* dim) {
   using C2 = typename Mf<T>::C2;
-  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lr = lane & 15, lk = lane >> 4;
-  const int nr = t.nrows, cn = t.ncols, nrb = (nr + 15) >> 4;
+  if (ks0 >= cn) return;  // uniform: the wave has no k-step
+  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+  const int nrb = (nr + 15) >> 4;
+  int roff[4];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb) roff[rb] = min(16 * rb + lr, nr - 1);
   auto load = [&](int k0, C2& bv, C2 (&a)[4]) {
-    const int k = k0 + lk;
-    bv = k < cn ? Bk[(int64_t)k * 16 + lr] : C2{0, 0};
+    const int k = min(k0 + lk, cn - 1);
+    bv = Bk[k * 16 + lr];
+    const C2* pc = P + (int64_t)k * nr;
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
-      const int row = 16 * rb + lr;
-      a[rb] = (rb < nrb && row < nr && k < cn) ? ldp(P + (int64_t)k * nr + row) : C2{0, 0};
-    }
+    for (int rb = 0; rb < 4; ++rb) a[rb] = ldp(pc + roff[rb]);
   };
-  auto step = [&](const C2& bv, const C2 (&a)[4]) {
+  auto step = [&](int k0, const C2& b, const C2 (&a)[4]) {
+    const C2 bv = k0 + lk < cn ? b : C2{0, 0};
+    const decltype(bv.y) nby = -bv.y;  // a.y (-b.y) is -(a.y b.y) exactly
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
-      if (rb >= nrb) break;
       dre[rb] = Mf<T>::mma(a[rb].x, bv.x, dre[rb]);
-      dre[rb] = Mf<T>::mma(-a[rb].y, bv.y, dre[rb]);
       dim[rb] = Mf<T>::mma(a[rb].x, bv.y, dim[rb]);
+    }
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      dre[rb] = Mf<T>::mma(a[rb].y, nby, dre[rb]);
       dim[rb] = Mf<T>::mma(a[rb].y, bv.x, dim[rb]);
     }
   };
-  C2 b0, a0[4];
-  int k0 = 4 * wv;
-  load(k0, b0, a0);
-  if constexpr (sizeof(T) == 4) {
-    // FP32 MFMA: one step ahead, so seven waves fit per SIMD
-    for (; k0 < cn; k0 += 16) {
-      C2 b1, a1[4];
-      load(k0 + 16, b1, a1);
-      step(b0, a0);
-      b0 = b1;
-#pragma unroll
-      for (int rb = 0; rb < 4; ++rb) a0[rb] = a1[rb];
-    }
-  } else {
-    C2 b1, a1[4];
-    load(k0 + 16, b1, a1);
-    for (; k0 < cn; k0 += 16) {
-      C2 b2, a2[4];
-      load(k0 + 32, b2, a2);
-      step(b0, a0);
-      b0 = b1;
-      b1 = b2;
-#pragma unroll
-      for (int rb = 0; rb < 4; ++rb) {
-        a0[rb] = a1[rb];
-        a1[rb] = a2[rb];
-      }
-    }
+  C2 b0, a0[4], b1, a1[4];
+  load(ks0, b0, a0);
+  // the k-steps go in pairs (an odd count ends with a step past cn, whose B
+  // entries are all zero); the scheduling barriers keep each k-step's loads
+  // ahead of the MFMAs of the step before it
+  for (int k0 = ks0; k0 < cn; k0 += 2 * kst) {
+    load(k0 + kst, b1, a1);
+    __builtin_amdgcn_sched_barrier(0);
+    step(k0, b0, a0);
+    __builtin_amdgcn_sched_barrier(0);
+    load(k0 + 2 * kst, b0, a0);
+    __builtin_amdgcn_sched_barrier(0);
+    step(k0 + kst, b1, a1);
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
+// The level kernels' launch bounds keep their register budget at or below
+// 256 (at least three waves per SIMD for complex128): with a larger budget
+// the compiler may hold MFMA accumulators in AGPRs and move them through
+// VGPRs around every MFMA.
 template <class T, int kFwd, int kCoarse>
-__global__ __launch_bounds__(kWG, sizeof(T) == 4 ? 4 : 1) void level_mfma_kernel(const Tile* __restrict__ tiles, Batch b,
+__global__ __launch_bounds__(kWG, sizeof(T) == 4 ? 4 : 3) void level_mfma_kernel(const Tile* __restrict__ tiles, Batch b,
                                                          const typename Mf<T>::C2* __restrict__ G,
                                                          double2* __restrict__ out, double2* __restrict__ ubb) {
   using C2 = typename Mf<T>::C2;
@@ -297,7 +298,9 @@ __global__ __launch_bounds__(kWG, sizeof(T) == 4 ? 4 : 1) void level_mfma_kernel
   V4 dre[4], dim[4];
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb) dre[rb] = dim[rb] = V4{0, 0, 0, 0};
-  mfma_tile4<T, kFwd>(t, P, Bk, dre, dim);
+  // 4 waves per tile: wave q takes the k-steps q, q + 4, ... of the tile;
+  // the partial accumulators are summed through LDS
+  mfma_stream<T>(P, t.nrows, t.ncols, Bk, 4 * wv, 16, dre, dim);
   for (int h = 0; h < 2; ++h) {
 #pragma unroll
     for (int q = 0; q < 2; ++q)
@@ -349,7 +352,7 @@ __global__ __launch_bounds__(kWG, sizeof(T) == 4 ? 4 : 1) void level_mfma_kernel
 // accumulator register j of lane l holds row 4 j + l / 16, FP32 row
 // 4 (l / 16) + j, right-hand side l % 16).
 template <class T, int kFwd, int kCoarse>
-__global__ __launch_bounds__(kWG, sizeof(T) == 4 ? 8 : 5) void level_mfma_narrow_kernel(const Tile* __restrict__ tiles, int64_t ntiles,
+__global__ __launch_bounds__(kWG, sizeof(T) == 4 ? 6 : 4) void level_mfma_narrow_kernel(const Tile* __restrict__ tiles, int64_t ntiles,
                                                                 Batch b, const typename Mf<T>::C2* __restrict__ G,
                                                                 double2* __restrict__ out,
                                                                 double2* __restrict__ ubb) {
@@ -362,28 +365,11 @@ __global__ __launch_bounds__(kWG, sizeof(T) == 4 ? 8 : 5) void level_mfma_narrow
   const int sn = t.sn, c0 = b.sn_c0[sn], w = b.sn_w[sn];
   const C2* __restrict__ P = reinterpret_cast<const C2*>(kFwd ? b.pf : b.pb) + t.off;
   const C2* Bk = G + (b.goff_f[sn] + t.col0) * 16;  // the staged forward input block
-  const int nr = t.nrows, cn = t.ncols, nrb = (nr + 15) >> 4;
+  const int nr = t.nrows, nrb = (nr + 15) >> 4;
   V4 dre[4], dim[4];
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb) dre[rb] = dim[rb] = V4{0, 0, 0, 0};
-  for (int k0 = 0; k0 < cn; k0 += 4) {
-    const int k = k0 + lk;
-    const C2 bv = k < cn ? Bk[(int64_t)k * 16 + lr] : C2{0, 0};
-    C2 a[4];
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
-      const int row = 16 * rb + lr;
-      a[rb] = (rb < nrb && row < nr && k < cn) ? ldp(P + (int64_t)k * nr + row) : C2{0, 0};
-    }
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
-      if (rb >= nrb) break;
-      dre[rb] = Mf<T>::mma(a[rb].x, bv.x, dre[rb]);
-      dre[rb] = Mf<T>::mma(-a[rb].y, bv.y, dre[rb]);
-      dim[rb] = Mf<T>::mma(a[rb].x, bv.y, dim[rb]);
-      dim[rb] = Mf<T>::mma(a[rb].y, bv.x, dim[rb]);
-    }
-  }
+  mfma_stream<T>(P, nr, t.ncols, Bk, 0, 4, dre, dim);
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb) {
     if (rb >= nrb) break;
@@ -417,36 +403,56 @@ __global__ __launch_bounds__(kWG, sizeof(T) == 4 ? 8 : 5) void level_mfma_narrow
 // fcon_idx).  Backward: the forward result for the pivot columns, the
 // ancestors' backward results (through the supernode's row list) for the
 // others.  All eight entries' index loads are issued first, then all value
-// loads, so a pass costs two memory round trips.
+// loads, so a pass costs two memory round trips.  The backward loads are
+// unconditional (entries past the pass read a valid dummy address and are
+// not stored), so no load waits behind a branch.
 template <class T, int kFwd>
 __device__ __forceinline__ void stage_pass(const Batch& b, const Tile& t, int cb, int cn, int base, int stride,
                                            typename Mf<T>::C2* G, const double2* __restrict__ src,
                                            const double2* aux) {
   using C2 = typename Mf<T>::C2;
   constexpr int kQ = 8;
-  int idx[kQ];
-  int2 ch[kQ];
+  if constexpr (!kFwd) {
+    int rv[kQ];
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    const int e = base + q * stride;
-    const bool in = e < cn * 16;
-    const int c = t.col0 + cb + (e >> 4);
-    if (kFwd) {
+    for (int q = 0; q < kQ; ++q) {
+      const int e = base + q * stride;
+      const int c = t.col0 + cb + (e >> 4);
+      // an ancestor column reads its position from the row list; the
+      // others read bidx[0] (any valid address) and ignore it
+      const bool up = e < cn * 16 && c >= t.w;
+      rv[q] = *(up ? b.rows + t.aux + (c - t.w) : b.bidx);
+    }
+    double2 v[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const int e = base + q * stride;
+      const int c = t.col0 + cb + (e >> 4), r = e & 15;
+      const bool in = e < cn * 16;
+      v[q] = *(!in ? src + r : (c < t.w ? src + (int64_t)(t.c0 + c) * 16 + r : aux + (int64_t)rv[q] * 16 + r));
+    }
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const int e = base + q * stride;
+      if (e < cn * 16) G[e] = C2{(T)v[q].x, (T)v[q].y};
+    }
+  } else {
+    int idx[kQ];
+    int2 ch[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const int e = base + q * stride;
+      const bool in = e < cn * 16;
+      const int c = t.col0 + cb + (e >> 4);
       idx[q] = in ? b.bidx[t.c0 + c] : 0;
       ch[q] = in ? b.fcon2[t.aux + c] : make_int2(-1, -1);
-    } else {
-      // >= 0: position in the forward result; < 0: -1 - position in x
-      idx[q] = !in ? 0 : (c < t.w ? t.c0 + c : -1 - b.rows[(int64_t)t.aux + (c - t.w)]);
     }
-  }
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    const int e = base + q * stride;
-    if (e >= cn * 16) continue;
-    const int r = e & 15;
-    double2 v;
-    if (kFwd) {
-      v = src[(int64_t)idx[q] * 16 + r];
+    for (int q = 0; q < kQ; ++q) {
+      const int e = base + q * stride;
+      if (e >= cn * 16) continue;
+      const int r = e & 15;
+      double2 v = src[(int64_t)idx[q] * 16 + r];
       const int2 c2 = ch[q];
       if (c2.x >= 0) {
         const double2 u0 = aux[(int64_t)c2.x * 16 + r];
@@ -465,10 +471,8 @@ __device__ __forceinline__ void stage_pass(const Batch& b, const Tile& t, int cb
           v.y -= u.y;
         }
       }
-    } else {
-      v = idx[q] >= 0 ? src[(int64_t)idx[q] * 16 + r] : aux[(int64_t)(-1 - idx[q]) * 16 + r];
+      G[e] = C2{(T)v.x, (T)v.y};
     }
-    G[e] = C2{(T)v.x, (T)v.y};
   }
 }
 
@@ -507,7 +511,7 @@ __device__ __forceinline__ void put_row(const Batch& b, const Tile& t, int rloc,
 // shared by the four waves, wave q taking q, q + 4, ..., partial sums added
 // through LDS); the others take four narrow tiles, a wave each.
 template <class T, int kFwd, int kCoarse>
-__global__ __launch_bounds__(kWG) void level_fused_kernel(const Tile* __restrict__ tiles, int64_t ntiles,
+__global__ __launch_bounds__(kWG, 3) void level_fused_kernel(const Tile* __restrict__ tiles, int64_t ntiles,
                                                           int64_t nwide, Batch b, const double2* __restrict__ src,
                                                           const double2* aux, double2* out, double2* ubb) {
   using C2 = typename Mf<T>::C2;
@@ -525,9 +529,7 @@ __global__ __launch_bounds__(kWG) void level_fused_kernel(const Tile* __restrict
       const int cn = min(kCB, t.ncols - cb);
       stage_pass<T, kFwd>(b, t, cb, cn, threadIdx.x, kWG, G, src, aux);
       __syncthreads();
-      Tile tc = t;
-      tc.ncols = cn;
-      mfma_tile4<T, kFwd>(tc, panels + t.off + (int64_t)cb * t.nrows, G, dre, dim);
+      mfma_stream<T>(panels + t.off + (int64_t)cb * t.nrows, t.nrows, cn, G, 4 * wv, 16, dre, dim);
       __syncthreads();
     }
     // partial sums of the 4 waves, two row blocks at a time, in the staging
@@ -577,39 +579,12 @@ __global__ __launch_bounds__(kWG) void level_fused_kernel(const Tile* __restrict
   C2* Gw = G + wv * kCBn * 16;
   const int nr = t.nrows, nrb = (nr + 15) >> 4;
   const C2* __restrict__ P = panels + t.off;
-  auto loadA = [&](int k, C2 (&a)[4], int cn) {
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
-      const int row = 16 * rb + lr;
-      a[rb] = (rb < nrb && row < nr && k < cn) ? ldp(P + (int64_t)k * nr + row) : C2{0, 0};
-    }
-  };
-  auto step = [&](const C2& bv, const C2 (&a)[4]) {
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
-      if (rb >= nrb) break;
-      dre[rb] = Mf<T>::mma(a[rb].x, bv.x, dre[rb]);
-      dre[rb] = Mf<T>::mma(-a[rb].y, bv.y, dre[rb]);
-      dim[rb] = Mf<T>::mma(a[rb].x, bv.y, dim[rb]);
-      dim[rb] = Mf<T>::mma(a[rb].y, bv.x, dim[rb]);
-    }
-  };
   for (int p = 0; p < np; ++p) {
     const int cb = p * kCBn;
     const int cn = has ? max(0, min(kCBn, t.ncols - cb)) : 0;
     stage_pass<T, kFwd>(b, t, cb, cn, lane, 64, Gw, src, aux);
     __syncthreads();
-    // two k-steps per iteration, both steps' panel loads issued first
-    for (int k0 = 0; k0 < cn; k0 += 8) {
-      const int k1 = k0 + lk, k2 = k0 + 4 + lk;
-      C2 a0[4], a1[4];
-      loadA(cb + k1, a0, cb + cn);
-      loadA(cb + k2, a1, cb + cn);
-      const C2 b0 = k1 < cn ? Gw[k1 * 16 + lr] : C2{0, 0};
-      const C2 b1 = k2 < cn ? Gw[k2 * 16 + lr] : C2{0, 0};
-      step(b0, a0);
-      step(b1, a1);
-    }
+    mfma_stream<T>(P + (int64_t)cb * nr, nr, cn, Gw, 0, 4, dre, dim);
     __syncthreads();
   }
   if (!has) return;
