@@ -248,13 +248,15 @@ void bwd_level_mfma(const Batch& b, int64_t tile0, int64_t ntiles, int64_t nwide
                     bool coarse, hipStream_t s);
 // ---- block Gram-Schmidt of block GMRES (device_bgmres.hip): n x 16
 //      interleaved complex blocks, X_j = X + j ldx (ldx in doubles) ----
-// workgroups of bgs_dots (the partial sums per basis block) and of bgs_mul
+// workgroups of bgs_dots (bgs_dots writes at most 16 blocks of partial sums
+// per workgroup, or nb + 1 when that is more) and of bgs_mul
 int bgs_wgs(int64_t n);
 int bgs_mul_wgs(int64_t n);
-// partial[(wg * (nb + with_w) + j) * 256 + a * 16 + c] = sum over workgroup
-// wg's rows of conj(X_j[row][a]) W[row][c]; block nb is W itself (with_w)
-void bgs_dots(int64_t n, const double* X, int64_t ldx, int nb, bool with_w, const double* W, double* partial,
-              hipStream_t s);
+// partial[(p * (nb + with_w) + j) * 256 + a * 16 + c] = sum over the rows of
+// partial row p of conj(X_j[row][a]) W[row][c]; block nb is W itself
+// (with_w).  Returns the number of partial rows (for bgs_reduce).
+int bgs_dots(int64_t n, const double* X, int64_t ldx, int nb, bool with_w, const double* W, double* partial,
+             hipStream_t s);
 // out (and acc, = or +=) [j * 256 + e] = sum over nwg workgroups of the partials
 void bgs_reduce(const double* partial, int nwg, int nbt, double* out, double* acc, bool accumulate, hipStream_t s);
 // Y = (Y0 or 0) + sign sum_{j < nb} X_j C_j (C_j = C + 512 j doubles, 16 x

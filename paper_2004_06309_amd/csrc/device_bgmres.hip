@@ -36,19 +36,47 @@ constexpr int kWaves = 4;   // waves per workgroup
 constexpr int kBPW = 4;     // basis blocks per wave in bgs_dots
 constexpr int kJG = kWaves * kBPW;  // basis blocks per dots workgroup (grid y splits the rest)
 
-// dots: partial[(wg * nbt + jb) * 256 + a * 16 + c] = sum over the rows of
-// workgroup wg of conj(X_jb[row][a]) W[row][c].  The four waves of a
-// workgroup walk the same 16-row tiles (so W is fetched from HBM once and
-// read from cache by the others), wave q taking the basis blocks
-// jb = 16 blockIdx.y + 4 q + {0..3}; X_jb = X + jb * ldx for jb < nb, and
-// block nb (with_w) is W itself (its Gram matrix).  All operands of a tile
-// are loaded before its MFMAs, which run with the blocks innermost.
-__global__ __launch_bounds__(64 * kWaves) void bgs_dots_kernel(int64_t n, const double2* __restrict__ X, int64_t ldx,
+// Waves per group of kBPW basis blocks in bgs_dots: with fewer than three
+// groups (nbt <= 8) the waves of a workgroup split the group's row tiles
+// (four or two per group) instead of idling.
+__host__ __device__ inline int bgs_wpg(int nbt) {
+  const int g = (nbt + kBPW - 1) / kBPW;
+  return g == 1 ? kWaves : (g == 2 ? kWaves / 2 : 1);
+}
+
+// dots: partial[(p * nbt + jb) * 256 + a * 16 + c] = sum over the rows of
+// partial row p of conj(X_jb[row][a]) W[row][c].  With nbt <= 8, block
+// group g (blocks 4 g .. 4 g + 3) is taken by bgs_wpg(nbt) waves; wave sub
+// of them walks the 16-row tiles blockIdx.x * wpg + sub, stepping by
+// gridDim.x * wpg, and writes partial row p = blockIdx.x * wpg + sub (so
+// gridDim.x * wpg partial rows in all).  Otherwise grid y cuts the blocks
+// into gridDim.y slices of at most 16 consecutive blocks, as equal as
+// possible, dealt in turn to the four waves of a workgroup, which walk the
+// same tiles (W fetched from HBM once, read from cache by the others).
+// X_jb = X + jb * ldx for jb < nb, and block nb (with_w) is W itself (its
+// Gram matrix).  All operands of a tile are loaded before its MFMAs, which
+// run with the blocks innermost.
+__global__ __launch_bounds__(64 * kWaves, 3) void bgs_dots_kernel(int64_t n, const double2* __restrict__ X, int64_t ldx,
                                                                 int nb, int with_w, const double2* __restrict__ W,
                                                                 double2* __restrict__ partial) {
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nbt = nb + with_w;
-  const int jb0 = blockIdx.y * kJG + wv * kBPW, njb = min(kBPW, nbt - jb0);
+  const int wpg = bgs_wpg(nbt), sub = wv % wpg;
+  // blocks of this wave: jb = jb0 + q jst, q < njb
+  int jb0, jst, njb;
+  if (wpg > 1) {
+    jb0 = (wv / wpg) * kBPW;
+    jst = 1;
+    njb = min(kBPW, nbt - jb0);
+  } else {
+    // gridDim.y slices of consecutive blocks, as equal as possible; the
+    // blocks of a slice dealt to its four waves in turn
+    const int y = blockIdx.y, ny = gridDim.y;
+    const int s0 = (int)((int64_t)nbt * y / ny), s1 = (int)((int64_t)nbt * (y + 1) / ny);
+    jb0 = s0 + wv;
+    jst = kWaves;
+    njb = jb0 < s1 ? (s1 - jb0 + kWaves - 1) / kWaves : 0;
+  }
   if (njb <= 0) return;  // whole wave; no barrier in this kernel
   dv4 dre[kBPW], dim[kBPW];
 #pragma unroll
@@ -56,13 +84,14 @@ __global__ __launch_bounds__(64 * kWaves) void bgs_dots_kernel(int64_t n, const 
   const double2* Xq[kBPW];
 #pragma unroll
   for (int q = 0; q < kBPW; ++q) {
-    const int jb = jb0 + q;
+    const int jb = jb0 + q * jst;
     Xq[q] = jb < nb ? X + jb * ldx : W;
   }
   const int64_t ntiles = (n + 15) >> 4;
   // lane l takes row 4 t + l / 16 of the tile at k-step t, column l % 16
   const int rk = lane >> 4, col = lane & 15;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  const int64_t prow = (int64_t)blockIdx.x * wpg + sub;
+  for (int64_t tile = prow; tile < ntiles; tile += (int64_t)gridDim.x * wpg) {
     const int64_t i0 = tile << 4;
     double2 w[4], v[4][kBPW];
 #pragma unroll
@@ -90,7 +119,7 @@ __global__ __launch_bounds__(64 * kWaves) void bgs_dots_kernel(int64_t n, const 
 #pragma unroll
   for (int q = 0; q < kBPW; ++q) {
     if (q >= njb) break;
-    double2* out = partial + ((int64_t)blockIdx.x * nbt + jb0 + q) * 256;
+    double2* out = partial + (prow * nbt + jb0 + q * jst) * 256;
 #pragma unroll
     for (int r = 0; r < 4; ++r) out[(4 * r + rk) * 16 + col] = make_double2(dre[q][r], dim[q][r]);
   }
@@ -152,59 +181,85 @@ __global__ __launch_bounds__(256) void bgs_reduce_kernel(const double2* __restri
   }
 }
 
-constexpr int kMulTiles = 4;  // 16-row tiles per wave in bgs_mul
+constexpr int kMulTiles = 2;  // 16-row tiles per wave in bgs_mul
 
 // Y = (Y0 or 0) + sign * sum_{jb < nb} X_jb C_jb over 16-row tiles, C_jb =
 // C + 256 jb (16 x 16, entry (a, c) at a * 16 + c); with gram, the
 // workgroup's partial sum of Y^H Y goes to gram[blockIdx.x * 256 + ...].
-// Y may alias Y0 and X (each wave reads its own rows before it writes them).
-__global__ __launch_bounds__(64 * kWaves) void bgs_mul_kernel(int64_t n, const double2* X, int64_t ldx,
-                                                               int nb, const double2* __restrict__ C, double sign,
-                                                               const double2* Y0, double2* Y,
-                                                               double2* __restrict__ gram) {
+// Y may alias Y0 and X (each wave reads its own rows before it writes them;
+// rows past n, never stored, read row n - 1).  The operands of block jb + 1
+// are loaded, into the other of two register sets, before the MFMAs of
+// block jb; a step past nb meets zero coefficients.
+__global__ __launch_bounds__(64 * kWaves, 3) void bgs_mul_kernel(int64_t n, const double2* X, int64_t ldx,
+                                                                  int nb, const double2* __restrict__ C, double sign,
+                                                                  const double2* Y0, double2* Y,
+                                                                  double2* __restrict__ gram) {
   __shared__ double2 red[kWaves][256];
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int rk = lane >> 4, col = lane & 15;
   const int64_t base = ((int64_t)blockIdx.x * kWaves + wv) * kMulTiles * 16;
   dv4 dre[kMulTiles], dim[kMulTiles];
-  // accumulators start from Y0: register q of lane l is row 4 q + l / 16
+  // accumulators start from Y0 (all loads issued before the first use):
+  // register q of lane l is row 4 q + l / 16
+  // (without Y0 the loads read Y, any valid rows, and are replaced by zeros)
+  const double2* ysrc = Y0 ? Y0 : Y;
+  const double keep = Y0 ? 1.0 : 0.0;
+  double2 y[kMulTiles][4];
 #pragma unroll
-  for (int tt = 0; tt < kMulTiles; ++tt) {
+  for (int tt = 0; tt < kMulTiles; ++tt)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) y[tt][q] = ysrc[min(base + 16 * tt + 4 * q + rk, n - 1) * 16 + col];
+#pragma unroll
+  for (int tt = 0; tt < kMulTiles; ++tt)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int64_t row = base + 16 * tt + 4 * q + rk;
-      const double2 y = (Y0 && row < n) ? Y0[row * 16 + col] : make_double2(0, 0);
-      dre[tt][q] = y.x;
-      dim[tt][q] = y.y;
+      dre[tt][q] = keep != 0.0 ? y[tt][q].x : 0.0;
+      dim[tt][q] = keep != 0.0 ? y[tt][q].y : 0.0;
     }
-  }
-  for (int jb = 0; jb < nb; ++jb) {
-    const double2* Xj = X + jb * ldx;
-    // B operand at k-step t: C_jb[4 (l / 16) + t][l % 16]
-    double2 cb[4];
+  if (nb > 0) {
+    // A operand at k-step t: X_jb[row l % 16][column 4 t + l / 16] (the four
+    // lanes of a row read 64 contiguous bytes); B operand: C_jb[4 t + l / 16]
+    // [l % 16]
+    int64_t arow[kMulTiles];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) cb[t] = C[jb * 256 + (4 * rk + t) * 16 + col];
-    // A operand at k-step t: X_jb[row l % 16][column 4 (l / 16) + t]; all
-    // tiles' operands first, then the MFMAs with the tiles innermost
-    double2 a[kMulTiles][4];
+    for (int tt = 0; tt < kMulTiles; ++tt) arow[tt] = min(base + 16 * tt + col, n - 1) * 16 + rk;
+    auto load = [&](int jb, double2 (&cb)[4], double2 (&a)[kMulTiles][4]) {
+      const int j = min(jb, nb - 1);
 #pragma unroll
-    for (int tt = 0; tt < kMulTiles; ++tt) {
-      const int64_t row = base + 16 * tt + col;
-      const double2* xr = Xj + row * 16 + 4 * rk;
+      for (int t = 0; t < 4; ++t) cb[t] = C[j * 256 + (4 * t + rk) * 16 + col];
+      const double2* Xj = X + j * ldx;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) a[tt][t] = row < n ? xr[t] : make_double2(0, 0);
-    }
+      for (int tt = 0; tt < kMulTiles; ++tt)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      // (ar + i ai)(cr + i ci), a scaled by sign
+        for (int t = 0; t < 4; ++t) a[tt][t] = Xj[arow[tt] + 4 * t];
+    };
+    auto step = [&](int jb, const double2 (&c)[4], const double2 (&a)[kMulTiles][4]) {
+      const bool on = jb < nb;
 #pragma unroll
-      for (int tt = 0; tt < kMulTiles; ++tt) dre[tt] = mma(sign * a[tt][t].x, cb[t].x, dre[tt]);
+      for (int t = 0; t < 4; ++t) {
+        const double2 cb = on ? c[t] : make_double2(0, 0);
+        // (ar + i ai)(cr + i ci), a scaled by sign
 #pragma unroll
-      for (int tt = 0; tt < kMulTiles; ++tt) dim[tt] = mma(sign * a[tt][t].x, cb[t].y, dim[tt]);
+        for (int tt = 0; tt < kMulTiles; ++tt) dre[tt] = mma(sign * a[tt][t].x, cb.x, dre[tt]);
 #pragma unroll
-      for (int tt = 0; tt < kMulTiles; ++tt) dre[tt] = mma(-sign * a[tt][t].y, cb[t].y, dre[tt]);
+        for (int tt = 0; tt < kMulTiles; ++tt) dim[tt] = mma(sign * a[tt][t].x, cb.y, dim[tt]);
 #pragma unroll
-      for (int tt = 0; tt < kMulTiles; ++tt) dim[tt] = mma(sign * a[tt][t].y, cb[t].x, dim[tt]);
+        for (int tt = 0; tt < kMulTiles; ++tt) dre[tt] = mma(-sign * a[tt][t].y, cb.y, dre[tt]);
+#pragma unroll
+        for (int tt = 0; tt < kMulTiles; ++tt) dim[tt] = mma(sign * a[tt][t].y, cb.x, dim[tt]);
+      }
+    };
+    double2 c0[4], a0[kMulTiles][4], c1[4], a1[kMulTiles][4];
+    load(0, c0, a0);
+    for (int jb = 0; jb < nb; jb += 2) {
+      load(jb + 1, c1, a1);
+      __builtin_amdgcn_sched_barrier(0);
+      step(jb, c0, a0);
+      __builtin_amdgcn_sched_barrier(0);
+      load(jb + 2, c0, a0);
+      __builtin_amdgcn_sched_barrier(0);
+      step(jb + 1, c1, a1);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
   dv4 gre = dv4{0, 0, 0, 0}, gim = dv4{0, 0, 0, 0};
@@ -217,10 +272,11 @@ __global__ __launch_bounds__(64 * kWaves) void bgs_mul_kernel(int64_t n, const d
     }
     if (gram) {
       // register q of lane l holds Y[row 4 q + l / 16][l % 16]: the A and B
-      // operands of Y^H Y at k-step q (rows past n hold zeros)
+      // operands of Y^H Y at k-step q (rows past n taken as zeros)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const double yr = dre[tt][q], yi = dim[tt][q];
+        const bool in = base + 16 * tt + 4 * q + rk < n;
+        const double yr = in ? dre[tt][q] : 0.0, yi = in ? dim[tt][q] : 0.0;
         gre = mma(yr, yr, gre);
         gre = mma(yi, yi, gre);
         gim = mma(yr, yi, gim);
@@ -330,14 +386,16 @@ int bgs_wgs(int64_t n) {
 
 int bgs_mul_wgs(int64_t n) { return (int)((n + 16 * kMulTiles * kWaves - 1) / (16 * kMulTiles * kWaves)); }
 
-void bgs_dots(int64_t n, const double* X, int64_t ldx, int nb, bool with_w, const double* W, double* partial,
-              hipStream_t s) {
+int bgs_dots(int64_t n, const double* X, int64_t ldx, int nb, bool with_w, const double* W, double* partial,
+             hipStream_t s) {
   const int nbt = nb + (with_w ? 1 : 0);
-  if (nbt <= 0) return;
-  dim3 grid(bgs_wgs(n), (nbt + kJG - 1) / kJG);
+  if (nbt <= 0) return 0;
+  const int wpg = bgs_wpg(nbt);
+  dim3 grid(bgs_wgs(n), wpg > 1 ? 1 : (nbt + kJG - 1) / kJG);
   bgs_dots_kernel<<<grid, 64 * kWaves, 0, s>>>(n, reinterpret_cast<const double2*>(X), ldx / 2, nb, with_w ? 1 : 0,
                                                 reinterpret_cast<const double2*>(W),
                                                 reinterpret_cast<double2*>(partial));
+  return (int)grid.x * wpg;
 }
 
 void bgs_reduce(const double* partial, int nwg, int nbt, double* out, double* acc, bool accumulate, hipStream_t s) {

@@ -2073,9 +2073,15 @@ BgLayout bg_layout(int m) {
   return L;
 }
 
+// 16 x 16 blocks of the partial-sum buffer: bgs_dots writes at most
+// max(nb + 2, 16) blocks per workgroup, bgs_mul one per workgroup
+size_t bg_part_blocks(int64_t n, int m) {
+  return std::max<size_t>((size_t)dev::bgs_wgs(n) * std::max(m + 2, 16), (size_t)dev::bgs_mul_wgs(n));
+}
+
 size_t bg_bytes(int64_t n, int m) {
   const size_t blk = 2 * 16 * (size_t)n;  // doubles of an n x 16 block
-  const size_t part = std::max<size_t>((size_t)dev::bgs_wgs(n) * (m + 2), (size_t)dev::bgs_mul_wgs(n)) * kBlk;
+  const size_t part = bg_part_blocks(n, m) * kBlk;
   return sizeof(double) * ((size_t)(2 * m + 1) * blk + 3 * blk + part + bg_layout(m).total + (size_t)m * kBlk);
 }
 
@@ -2090,7 +2096,7 @@ void ensure_bg(Ctx& c, int m) {
   c.bgW.alloc(blk);
   c.bgX.alloc(blk);
   c.bgB.alloc(blk);
-  c.bgpart.alloc(std::max<size_t>((size_t)dev::bgs_wgs(n) * (m + 2), (size_t)dev::bgs_mul_wgs(n)) * kBlk);
+  c.bgpart.alloc(bg_part_blocks(n, m) * kBlk);
   c.bgH.alloc(bg_layout(m).total);
   c.bgC.alloc((size_t)m * kBlk);
   c.bgstat.alloc(2);
@@ -2132,16 +2138,16 @@ void bg_step_device(Ctx& c, int j, int sa, hipStream_t s) {
   spmv_block(c, dev::kMaxBlock, Zj, nullptr, W, s);
   const bool prof = c.prof.on;
   if (prof) c.prof.begin(s);
-  const int nb = j + 1, nwg = dev::bgs_wgs(n), mwg = dev::bgs_mul_wgs(n);
+  const int nb = j + 1, mwg = dev::bgs_mul_wgs(n);
   // pass 1: V^H W and W^H W (the scale breakdowns are measured against)
-  dev::bgs_dots(n, c.bgV.p, blk, nb, true, W, c.bgpart.p, s);
-  dev::bgs_reduce(c.bgpart.p, nwg, nb + 1, H + L.htmp, nullptr, false, s);
+  int prows = dev::bgs_dots(n, c.bgV.p, blk, nb, true, W, c.bgpart.p, s);
+  dev::bgs_reduce(c.bgpart.p, prows, nb + 1, H + L.htmp, nullptr, false, s);
   dev::copy((int64_t)nb * kBlk, H + L.htmp, H + L.htot, s);
   dev::copy(kBlk, H + L.htmp + nb * kBlk, H + L.g0, s);
   dev::bgs_mul(n, c.bgV.p, blk, nb, H + L.htmp, -1.0, W, W, nullptr, s);
   // pass 2
-  dev::bgs_dots(n, c.bgV.p, blk, nb, false, W, c.bgpart.p, s);
-  dev::bgs_reduce(c.bgpart.p, nwg, nb, H + L.htmp, H + L.htot, true, s);
+  prows = dev::bgs_dots(n, c.bgV.p, blk, nb, false, W, c.bgpart.p, s);
+  dev::bgs_reduce(c.bgpart.p, prows, nb, H + L.htmp, H + L.htot, true, s);
   dev::bgs_mul(n, c.bgV.p, blk, nb, H + L.htmp, -1.0, W, W, c.bgpart.p, s);
   dev::bgs_reduce(c.bgpart.p, mwg, 1, H + L.g1, nullptr, false, s);
   // CholQR2: W = V_{j+1} R2 R1
