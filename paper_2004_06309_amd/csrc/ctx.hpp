@@ -67,6 +67,7 @@ struct BatchHost {
   std::vector<int64_t> lev_f, lev_b;  // task ranges per level
   std::vector<int32_t> chunk_f, chunk_b;  // LDS input entries per level
   std::vector<int64_t> nwide_f, nwide_b;  // tiles of each level wider than 96 columns (they come first)
+  std::vector<int64_t> nwide4_f, nwide4_b;  // of which those with four waves (wider than 384 columns, or root separators)
   // one-wave forward supernodes (their tiles close each level, in job
   // order); the tile kernel takes the first ktile_f tasks of a level
   std::vector<dev::SnJob> snj;
@@ -96,7 +97,11 @@ struct BatchDev {
   DVec<double> ubuf, y, x;
   std::vector<int64_t> lev_f, lev_b;
   std::vector<int32_t> chunk_f, chunk_b;
-  std::vector<int64_t> nwide_f, nwide_b;
+  std::vector<int64_t> nwide_f, nwide_b, nwide4_f, nwide4_b;
+  // 16-column level solves: tiles of each level taken four waves each (a
+  // prefix of the level's tiles), chosen by timing at first use
+  std::vector<int64_t> nw16_f, nw16_b;
+  bool blk_tuned = false;
   std::vector<int32_t> gy_f;
   DVec<dev::SnJob> snj;
   std::vector<int64_t> snj_lev, ktile_f;
@@ -143,6 +148,9 @@ struct BatchDev {
     tiles_f.clear();
     tiles_b.clear();
     blk_S = 0;
+    nw16_f.clear();
+    nw16_b.clear();
+    blk_tuned = false;
     ubuf_b.reset();
     y_b.reset();
     x_b.reset();

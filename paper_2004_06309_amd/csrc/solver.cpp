@@ -15,6 +15,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <numeric>
 
 #include "ctx.hpp"
@@ -441,17 +442,20 @@ void layout_batch(const std::vector<const Symbolic*>& Ss, const std::vector<cons
   chunks(B.kb, B.tb, B.lev_b, B.chunk_b);
   // tasks are sorted widest class first, so a level's narrow tiles (one
   // wave per tile) are its last ones
-  auto wide = [&](const std::vector<dev::Task>& K, const std::vector<int64_t>& lev, std::vector<int64_t>& out) {
+  auto wide = [&](const std::vector<dev::Task>& K, const std::vector<int64_t>& lev, int wmin,
+                  std::vector<int64_t>& out) {
     out.clear();
     for (size_t l = 0; l + 1 < lev.size(); ++l) {
       int64_t nw = 0;
       for (int64_t q = lev[l]; q < lev[l + 1]; ++q)
-        if (K[q].wpt > 1) nw += K[q].ntile;
+        if (K[q].wpt >= wmin) nw += K[q].ntile;
       out.push_back(nw);
     }
   };
-  wide(B.kf, B.lev_f, B.nwide_f);
-  wide(B.kb, B.lev_b, B.nwide_b);
+  wide(B.kf, B.lev_f, 2, B.nwide_f);
+  wide(B.kb, B.lev_b, 2, B.nwide_b);
+  wide(B.kf, B.lev_f, 4, B.nwide4_f);
+  wide(B.kb, B.lev_b, 4, B.nwide4_b);
 }
 
 namespace {
@@ -552,6 +556,11 @@ void build_batch(const std::vector<const Csr*>& As, const std::vector<const Symb
   Dv.snj_lev = B.snj_lev;
   Dv.ktile_f = B.ktile_f;
   Dv.nwide_b = B.nwide_b;
+  Dv.nwide4_f = B.nwide4_f;
+  Dv.nwide4_b = B.nwide4_b;
+  Dv.nw16_f = B.nwide_f;
+  Dv.nw16_b = B.nwide_b;
+  Dv.blk_tuned = false;
   Dv.gy_f = B.gy_f;
   Dv.bytes_f = B.bytes_f;
   Dv.bytes_b = B.bytes_b;
@@ -1661,6 +1670,46 @@ size_t width_bytes(const Ctx& c, int m, int S) {
 }
 
 // Buffers of blocks up to S columns wide (bases are separate, ensure_bases).
+// 16-column level solves of a fine batch: the tiles a level gives four
+// waves each (the others one wave each) are a prefix of the level's tiles.
+// The candidates -- the four- and two-wave classes (the default), the
+// four-wave class alone, no tile, every tile -- are timed once per level on
+// the first 16-column use (three launches each after one untimed) and the
+// fastest is kept.  The timed sweeps read whatever the work vectors hold;
+// every solve runs its sweeps afresh.
+void tune_block_levels(BatchDev& b, const double* in) {
+  const dev::Batch v = b.view();
+  auto pick = [](std::initializer_list<int64_t> cand, const std::function<void(int64_t)>& run) {
+    std::vector<int64_t> cs;
+    for (int64_t x : cand)
+      if (std::find(cs.begin(), cs.end(), x) == cs.end()) cs.push_back(x);
+    int64_t best = cs[0];
+    float tb = 0;
+    for (size_t i = 0; i < cs.size(); ++i) {
+      const float t = time_launch([&] { run(cs[i]); });
+      if (i == 0 || t < tb) {
+        tb = t;
+        best = cs[i];
+      }
+    }
+    return best;
+  };
+  for (size_t l = 0; l + 1 < b.tiles_f.size(); ++l) {
+    const int64_t t0 = b.tiles_f[l], nt = b.tiles_f[l + 1] - t0;
+    b.nw16_f[l] = pick({b.nwide_f[l], b.nwide4_f[l], 0, nt}, [&](int64_t nw) {
+      dev::fwd_level_mfma(v, b.gsn_f.p + b.gsn_lev_f[l], b.gsn_lev_f[l + 1] - b.gsn_lev_f[l], b.gy_f[l], t0, nt, nw,
+                          in, b.y_b.p, b.ubuf_b.p, b.stage.p, false, nullptr);
+    });
+  }
+  for (size_t l = 0; l + 1 < b.tiles_b.size(); ++l) {
+    const int64_t t0 = b.tiles_b[l], nt = b.tiles_b[l + 1] - t0;
+    b.nw16_b[l] = pick({b.nwide_b[l], b.nwide4_b[l], 0, nt}, [&](int64_t nw) {
+      dev::bwd_level_mfma(v, t0, nt, nw, b.y_b.p, b.xout_b(), false, nullptr);
+    });
+  }
+  b.blk_tuned = true;
+}
+
 void ensure_width(Ctx& c, int m, int S) {
   const int64_t n = c.D.n;
   if (c.blk_m != m || c.blk_n != n) ensure_bases(c, m, 0);
@@ -1711,6 +1760,18 @@ void ensure_width(Ctx& c, int m, int S) {
     c.xall_b_S = S;
   }
   if (c.two_level) ensure_batch_block(c.coarse, S);
+  if (S == dev::kMaxBlock) {
+    // bX holds n x kMaxBlock entries: any input serves the timed sweeps
+    if (c.nbatch > 1) {
+      size_t o = 0;
+      for (int k = 0; k < c.nbatch; ++k) {
+        c.fine[k].xo_b = c.xall_b.p + 2 * o * S;
+        o += (size_t)c.fine[k].npos;
+      }
+    }
+    for (int k = 0; k < c.nbatch; ++k)
+      if (!c.fine[k].blk_tuned) tune_block_levels(c.fine[k], c.bX.p);
+  }
 }
 
 namespace {
@@ -1729,7 +1790,7 @@ void batch_solve_block(BatchDev& b, int S, const double* in, hipStream_t s, Prof
     if (each) prof->begin(s);
     if (mfma)
       dev::fwd_level_mfma(v, b.gsn_f.p + b.gsn_lev_f[l], b.gsn_lev_f[l + 1] - b.gsn_lev_f[l], b.gy_f[l], b.tiles_f[l],
-                          b.tiles_f[l + 1] - b.tiles_f[l], b.nwide_f[l], in, b.y_b.p, b.ubuf_b.p, b.stage.p, !fine,
+                          b.tiles_f[l + 1] - b.tiles_f[l], b.nw16_f[l], in, b.y_b.p, b.ubuf_b.p, b.stage.p, !fine,
                           s);
     else
       dev::fwd_level_block(v, b.tiles_f[l], b.tiles_f[l + 1] - b.tiles_f[l], S, in, b.y_b.p, b.ubuf_b.p, !fine, s);
@@ -1738,7 +1799,7 @@ void batch_solve_block(BatchDev& b, int S, const double* in, hipStream_t s, Prof
   for (size_t l = 0; l + 1 < b.tiles_b.size(); ++l) {
     if (each) prof->begin(s);
     if (mfma)
-      dev::bwd_level_mfma(v, b.tiles_b[l], b.tiles_b[l + 1] - b.tiles_b[l], b.nwide_b[l], b.y_b.p, b.xout_b(), !fine,
+      dev::bwd_level_mfma(v, b.tiles_b[l], b.tiles_b[l + 1] - b.tiles_b[l], b.nw16_b[l], b.y_b.p, b.xout_b(), !fine,
                           s);
     else
       dev::bwd_level_block(v, b.tiles_b[l], b.tiles_b[l + 1] - b.tiles_b[l], S, b.y_b.p, b.xout_b(), !fine, s);
