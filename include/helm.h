@@ -158,7 +158,11 @@ typedef struct helm_solve_opts {
                               block wider than 8 on a factored operator
                               first times, per level of the local solves,
                               which tiles take four waves each (about
-                              0.1 s at one million unknowns)             */
+                              0.1 s at one million unknowns); the
+                              environment variable HELM_BLOCK_SPLIT = 0, 1,
+                              2 or 3 fixes the choice instead: the tiles
+                              wider than 96 columns; those wider than 384
+                              and the root separators'; none; all         */
 } helm_solve_opts;
 
 typedef struct helm_solve_info {

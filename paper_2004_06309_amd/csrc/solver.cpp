@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <numeric>
@@ -1676,10 +1677,14 @@ size_t width_bytes(const Ctx& c, int m, int S) {
 // four-wave class alone, no tile, every tile -- are timed once per level on
 // the first 16-column use (three launches each after one untimed) and the
 // fastest is kept.  The timed sweeps read whatever the work vectors hold;
-// every solve runs its sweeps afresh.
+// every solve runs its sweeps afresh.  HELM_BLOCK_SPLIT = 0..3 in the
+// environment takes candidate 0..3 on every level without timing.
 void tune_block_levels(BatchDev& b, const double* in) {
   const dev::Batch v = b.view();
-  auto pick = [](std::initializer_list<int64_t> cand, const std::function<void(int64_t)>& run) {
+  const char* force = std::getenv("HELM_BLOCK_SPLIT");
+  const int forced = force && force[0] >= '0' && force[0] <= '3' && !force[1] ? force[0] - '0' : -1;
+  auto pick = [forced](std::initializer_list<int64_t> cand, const std::function<void(int64_t)>& run) {
+    if (forced >= 0) return *(cand.begin() + forced);
     std::vector<int64_t> cs;
     for (int64_t x : cand)
       if (std::find(cs.begin(), cs.end(), x) == cs.end()) cs.push_back(x);

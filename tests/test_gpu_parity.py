@@ -287,6 +287,43 @@ def _sources(w, P, k, seed):
     return np.stack([P.point_source(p) for p in pts])
 
 
+def test_block_level_splits_agree(monkeypatch):
+    """The 16-column local solves split each level's tiles between a
+    four-wave path (k-steps shared out, partial sums added in LDS) and a
+    one-wave path, the split timed on first use.  Forcing each of the four
+    candidate splits (HELM_BLOCK_SPLIT) gives, for every right-hand side, a
+    true residual <= tol with the oracle's A, the same iteration count
+    within 1, and solutions that agree with each other and with the oracle's
+    GMRES solution to 1e-5."""
+    w = WORKLOADS["mid_quarter_2lvl"]()
+    P, b0, M = opre.build(w)
+    Bs = _sources(w, P, 16, 31)
+    sols, its = [], []
+    for k in range(4):
+        monkeypatch.setenv("HELM_BLOCK_SPLIT", str(k))
+        h = helm.from_workload(w)
+        B = dvec(Bs)
+        U = torch.zeros_like(B)
+        rc, info = h.solve(B, U, tol=w.tol, restart=w.restart, block=16)
+        assert rc == helm.HELM_OK
+        u = host(U)
+        for r in range(16):
+            assert info[r]["converged"] == 1
+            assert np.linalg.norm(Bs[r] - P.A @ u[r]) / np.linalg.norm(Bs[r]) <= w.tol
+        sols.append(u)
+        its.append([i["iterations"] for i in info])
+        h.close()
+    for k in range(1, 4):
+        assert max(abs(a - b) for a, b in zip(its[k], its[0])) <= 1
+        for r in range(16):
+            assert np.linalg.norm(sols[k][r] - sols[0][r]) <= 1e-5 * np.linalg.norm(sols[0][r])
+    for r in (0, 7, 15):
+        ro = opre.solve(P, Bs[r], M, tol=w.tol, restart=w.restart)
+        for k in range(4):
+            assert np.linalg.norm(sols[k][r] - ro.x) <= 1e-5 * np.linalg.norm(ro.x)
+    say(f"[block split] iterations per split: {[max(i) for i in its]}")
+
+
 @pytest.mark.parametrize("name,nrhs,restart,c64", [("tiny", 3, 50, False), ("small_p2_2lvl", 16, 3, False),
                                                    ("mid_quarter_2lvl", 16, 50, False), ("adapted_p2_2lvl", 5, 8, False),
                                                    ("ragged_p2", 7, 50, False), ("mid_quarter_2lvl", 16, 50, True)])
