@@ -250,15 +250,16 @@ __device__ __forceinline__ void mfma_stream(const typename Mf<T>::C2* __restrict
   auto step = [&](int k0, const C2& b, const C2 (&a)[4]) {
     const C2 bv = k0 + lk < cn ? b : C2{0, 0};
     const decltype(bv.y) nby = -bv.y;  // a.y (-b.y) is -(a.y b.y) exactly
+    // row blocks past the tile are skipped (uniform branches: nrb is the
+    // same on every lane)
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
-      dre[rb] = Mf<T>::mma(a[rb].x, bv.x, dre[rb]);
-      dim[rb] = Mf<T>::mma(a[rb].x, bv.y, dim[rb]);
-    }
-#pragma unroll
-    for (int rb = 0; rb < 4; ++rb) {
-      dre[rb] = Mf<T>::mma(a[rb].y, nby, dre[rb]);
-      dim[rb] = Mf<T>::mma(a[rb].y, bv.x, dim[rb]);
+      if (rb < nrb) {
+        dre[rb] = Mf<T>::mma(a[rb].x, bv.x, dre[rb]);
+        dim[rb] = Mf<T>::mma(a[rb].x, bv.y, dim[rb]);
+        dre[rb] = Mf<T>::mma(a[rb].y, nby, dre[rb]);
+        dim[rb] = Mf<T>::mma(a[rb].y, bv.x, dim[rb]);
+      }
     }
   };
   C2 b0, a0[4], b1, a1[4];
