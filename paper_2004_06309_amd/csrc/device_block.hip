@@ -264,9 +264,9 @@ __device__ __forceinline__ void mfma_stream(const typename Mf<T>::C2* __restrict
   };
   C2 b0, a0[4], b1, a1[4];
   load(ks0, b0, a0);
-  // the k-steps go in pairs (an odd count ends with a step past cn, whose B
-  // entries are all zero); the scheduling barriers keep each k-step's loads
-  // ahead of the MFMAs of the step before it
+  // the k-steps go in pairs (an odd count loads a step past cn and skips
+  // its MFMAs); the scheduling barriers keep each k-step's loads ahead of
+  // the MFMAs of the step before it
   for (int k0 = ks0; k0 < cn; k0 += 2 * kst) {
     load(k0 + kst, b1, a1);
     __builtin_amdgcn_sched_barrier(0);
@@ -274,8 +274,31 @@ __device__ __forceinline__ void mfma_stream(const typename Mf<T>::C2* __restrict
     __builtin_amdgcn_sched_barrier(0);
     load(k0 + 2 * kst, b0, a0);
     __builtin_amdgcn_sched_barrier(0);
-    step(k0 + kst, b1, a1);
+    if (k0 + kst < cn) step(k0 + kst, b1, a1);  // uniform
     __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Children's updates routed to front row fr, for right-hand side r: the
+// first two entries of the row's list come as one index pair (fcon2), so
+// the values are one load away; a row with more than two walks its list.
+// uu holds the pair's values, loaded beforehand (a missing entry is not
+// used); the sum is taken in list order.
+__device__ __forceinline__ void add_children(const Batch& b, int fr, int2 c2, const double2* uu, const double2* ubb,
+                                             int r, double& ar, double& ai) {
+  if (c2.x >= 0) {
+    ar += uu[0].x;
+    ai += uu[0].y;
+    if (c2.y >= 0) {
+      ar += uu[1].x;
+      ai += uu[1].y;
+    }
+  } else if (c2.x < -1) {
+    for (int e = -2 - c2.x; e < b.fcon_ptr[fr + 1]; ++e) {
+      const double2 u = ubb[(int64_t)b.fcon_idx[e] * 16 + r];
+      ar += u.x;
+      ai += u.y;
+    }
   }
 }
 
@@ -308,8 +331,24 @@ __global__ __launch_bounds__(kWG, sizeof(T) == 4 ? 4 : 3) void level_mfma_kernel
 #pragma unroll
       for (int j = 0; j < 4; ++j) red[wv][q][j][lane] = C2{dre[2 * h + q][j], dim[2 * h + q][j]};
     __syncthreads();
-    // 512 outputs (32 rows x 16 right-hand sides) of this half, 2 per thread
-    for (int o = threadIdx.x; o < 512; o += kWG) {
+    // 512 outputs (32 rows x 16 right-hand sides) of this half, 2 per
+    // thread: the update rows' child-update pairs and values are loaded for
+    // both outputs before either is stored
+    const int frow0 = b.sn_frow0[sn], uoff = b.sn_uoff[sn];
+    int2 c2[2];
+    double2 uu[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int o = threadIdx.x + i * kWG, rloc = 32 * h + (o >> 4), r = o & 15, row = t.row0 + rloc;
+      const bool upd = kFwd && rloc < t.nrows && row >= w;
+      const int2 c = b.fcon2[upd ? frow0 + row : 0];
+      c2[i] = upd ? c : make_int2(-1, -1);
+      uu[i][0] = *(c2[i].x >= 0 ? ubb + (int64_t)c2[i].x * 16 + r : out + r);
+      uu[i][1] = *(c2[i].y >= 0 ? ubb + (int64_t)c2[i].y * 16 + r : out + r);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int o = threadIdx.x + i * kWG;
       const int rloc = 32 * h + (o >> 4), r = o & 15;
       if (rloc < t.nrows) {
         const int q = (rloc >> 4) - 2 * h, rr = rloc & 15;
@@ -328,18 +367,11 @@ __global__ __launch_bounds__(kWG, sizeof(T) == 4 ? 4 : 3) void level_mfma_kernel
           ai += (double)red[wq][q][j][l].y;
         }
         const int row = t.row0 + rloc;
-        if (!kFwd) {
-          out[(int64_t)(c0 + row) * 16 + r] = make_double2(ar, ai);
-        } else if (row < w) {
+        if (!kFwd || row < w) {
           out[(int64_t)(c0 + row) * 16 + r] = make_double2(ar, ai);
         } else {
-          const int fr = b.sn_frow0[sn] + row;
-          for (int e = b.fcon_ptr[fr]; e < b.fcon_ptr[fr + 1]; ++e) {
-            const double2 u = ubb[(int64_t)b.fcon_idx[e] * 16 + r];
-            ar += u.x;
-            ai += u.y;
-          }
-          ubb[(int64_t)(b.sn_uoff[sn] + row - w) * 16 + r] = make_double2(ar, ai);
+          add_children(b, frow0 + row, c2[i], uu[i], ubb, r, ar, ai);
+          ubb[(int64_t)(uoff + row - w) * 16 + r] = make_double2(ar, ai);
         }
       }
     }
@@ -353,7 +385,7 @@ __global__ __launch_bounds__(kWG, sizeof(T) == 4 ? 4 : 3) void level_mfma_kernel
 // accumulator register j of lane l holds row 4 j + l / 16, FP32 row
 // 4 (l / 16) + j, right-hand side l % 16).
 template <class T, int kFwd, int kCoarse>
-__global__ __launch_bounds__(kWG, sizeof(T) == 4 ? 6 : 4) void level_mfma_narrow_kernel(const Tile* __restrict__ tiles, int64_t ntiles,
+__global__ __launch_bounds__(kWG, sizeof(T) == 4 ? 5 : 4) void level_mfma_narrow_kernel(const Tile* __restrict__ tiles, int64_t ntiles,
                                                                 Batch b, const typename Mf<T>::C2* __restrict__ G,
                                                                 double2* __restrict__ out,
                                                                 double2* __restrict__ ubb) {
@@ -371,9 +403,26 @@ __global__ __launch_bounds__(kWG, sizeof(T) == 4 ? 6 : 4) void level_mfma_narrow
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb) dre[rb] = dim[rb] = V4{0, 0, 0, 0};
   mfma_stream<T>(P, nr, t.ncols, Bk, 0, 4, dre, dim);
+  // per row block, the update rows' child-update pairs, then their values,
+  // then the stores (rows without updates read y, any valid address)
+  const int frow0 = b.sn_frow0[sn], uoff = b.sn_uoff[sn];
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb) {
     if (rb >= nrb) break;
+    int2 c2[4];
+    double2 uu[4][2];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int rloc = 16 * rb + Mf<T>::row(lk, j), row = t.row0 + rloc;
+      const bool upd = kFwd && rloc < nr && row >= w;
+      const int2 c = b.fcon2[upd ? frow0 + row : 0];
+      c2[j] = upd ? c : make_int2(-1, -1);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      uu[j][0] = *(c2[j].x >= 0 ? ubb + (int64_t)c2[j].x * 16 + lr : out + lr);
+      uu[j][1] = *(c2[j].y >= 0 ? ubb + (int64_t)c2[j].y * 16 + lr : out + lr);
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int rloc = 16 * rb + Mf<T>::row(lk, j);
@@ -383,13 +432,8 @@ __global__ __launch_bounds__(kWG, sizeof(T) == 4 ? 6 : 4) void level_mfma_narrow
       if (!kFwd || row < w) {
         out[(int64_t)(c0 + row) * 16 + lr] = make_double2(ar, ai);
       } else {
-        const int fr = b.sn_frow0[sn] + row;
-        for (int e = b.fcon_ptr[fr]; e < b.fcon_ptr[fr + 1]; ++e) {
-          const double2 u = ubb[(int64_t)b.fcon_idx[e] * 16 + lr];
-          ar += u.x;
-          ai += u.y;
-        }
-        ubb[(int64_t)(b.sn_uoff[sn] + row - w) * 16 + lr] = make_double2(ar, ai);
+        add_children(b, frow0 + row, c2[j], uu[j], ubb, lr, ar, ai);
+        ubb[(int64_t)(uoff + row - w) * 16 + lr] = make_double2(ar, ai);
       }
     }
   }
