@@ -192,15 +192,31 @@ __global__ __launch_bounds__(kWG) void gather_fwd_kernel(const int32_t* __restri
   const int sn = sns[blockIdx.x];
   const int c0 = b.sn_c0[sn], w = b.sn_w[sn], frow0 = b.sn_frow0[sn];
   C2* g = G + b.goff_f[sn] * 16;
-  // workgroup blockIdx.y of gridDim.y takes every gridDim.y-th 256 entries
+  // workgroup blockIdx.y of gridDim.y takes every gridDim.y-th 256 entries;
+  // an entry's input index and child-update pair are loaded together, then
+  // the input and the (at most two) updates; a row with more children walks
+  // its list
   for (int e = blockIdx.y * kWG + threadIdx.x; e < w * 16; e += gridDim.y * kWG) {
     const int k = e >> 4, r = e & 15;
-    double2 v = bin[(int64_t)b.bidx[c0 + k] * 16 + r];
     const int fr = frow0 + k;
-    for (int q = b.fcon_ptr[fr]; q < b.fcon_ptr[fr + 1]; ++q) {
-      const double2 u = ubb[(int64_t)b.fcon_idx[q] * 16 + r];
-      v.x -= u.x;
-      v.y -= u.y;
+    const int bi = b.bidx[c0 + k];
+    const int2 c2 = b.fcon2[fr];
+    double2 v = bin[(int64_t)bi * 16 + r];
+    const double2 u0 = *(c2.x >= 0 ? ubb + (int64_t)c2.x * 16 + r : bin + r);
+    const double2 u1 = *(c2.y >= 0 ? ubb + (int64_t)c2.y * 16 + r : bin + r);
+    if (c2.x >= 0) {
+      v.x -= u0.x;
+      v.y -= u0.y;
+      if (c2.y >= 0) {
+        v.x -= u1.x;
+        v.y -= u1.y;
+      }
+    } else if (c2.x < -1) {
+      for (int q = -2 - c2.x; q < b.fcon_ptr[fr + 1]; ++q) {
+        const double2 u = ubb[(int64_t)b.fcon_idx[q] * 16 + r];
+        v.x -= u.x;
+        v.y -= u.y;
+      }
     }
     g[e] = C2{(T)v.x, (T)v.y};
   }
